@@ -1,0 +1,1047 @@
+/*
+ * Plain FP64 CPU oracle for the meshless-local Petrov-Galerkin (MLPG)
+ * discrete-ordinates transport method with Voronoi-cell integration
+ * (Bassett & Owen, arXiv 2008.02205).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, calls or
+ * includes this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.  It is written to be read against the paper:
+ * straightforward loops in the order the paper states the method, no blocking
+ * or fusion, FP64 throughout.
+ *
+ * Contents (paper section in brackets):
+ *   - overlap connectivity (Sec. 3.4, Eq. mlpg-connectivity)
+ *   - Voronoi-like cells: kernel-extent box clipped by bisector half-planes
+ *     (Sec. 3.1, Fig. 1), fan subdivision into triangles / tetrahedra (Fig. 2)
+ *   - cubic-spline kernel and its gradient (Sec. 2.1)
+ *   - reproducing-kernel functions U_j and their gradients from the moment
+ *     matrix M, C = M^-1 G, dC = -M^-1 dM C (Sec. 2.2, Eq. rk-matrix)
+ *   - meshless integration with quadrature outermost (Sec. 3.2, Alg. 1,
+ *     App. A maps) into direction-independent sparse blocks
+ *   - operators L, T, MS, D and r of Sec. 4.2 applied per ordinate
+ *   - per-ordinate GMRES for L^-1 and the outer GMRES on
+ *     (I - D L^-1 MS) Phi = b_phi (Eq. krylov-operator), backward Euler
+ *     (Sec. 4.1) and recovery Psi = L^-1 MS Phi + b_psi.
+ *
+ * Readings where the paper is silent (kernel shape, scaled monomials, row
+ * scaling by V_i, fallback order for a singular moment matrix, tau) are the
+ * ones listed in the design notes; each is restated where it is used.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXB 10   /* largest monomial basis: quadratic in 3D */
+#define ORC_MAXD 3
+
+/* ------------------------------------------------------------------------ */
+/* Overlap connectivity (Sec. 3.4): j is a neighbour of i when the supports
+ * of W_i and W_j intersect, |x_i - x_j| <= R_i + R_j.  Brute force over all
+ * pairs; lists exclude i itself and are in increasing index order.         */
+/* ------------------------------------------------------------------------ */
+static int overlaps(int dim, const double *xi, const double *xj, double ri, double rj)
+{
+    double d2 = 0.0;
+    for (int a = 0; a < dim; ++a) {
+        double t = xj[a] - xi[a];
+        d2 = d2 + t * t;
+    }
+    double s = ri + rj;
+    return d2 <= s * s;
+}
+
+int64_t orc_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *off)
+{
+    off[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && overlaps(dim, x + i * dim, x + j * dim, R[i], R[j])) c++;
+        off[i + 1] = off[i] + c;
+    }
+    return off[n];
+}
+
+void orc_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *off,
+                        int32_t *idx)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t p = off[i];
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i && overlaps(dim, x + i * dim, x + j * dim, R[i], R[j])) idx[p++] = (int32_t)j;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Voronoi-like cells in 2D (Sec. 3.1).  The initial polygon is the box
+ * [x_i - R_i, x_i + R_i]^2 (it encloses the kernel extent), intersected with
+ * the domain box; it is then clipped by the half-plane on x_i's side of the
+ * bisector of x_i and every overlap neighbour x_j.  Each edge carries a tag:
+ *   tag >= 0            : edge lies on the bisector with neighbour tag
+ *   tag = -1 - a        : edge lies on domain face a (0:-x 1:+x 2:-y 3:+y)
+ *   tag = ORC_TAG_BOX   : edge of the kernel box not on the domain
+ * Vertices are counter-clockwise; edge k runs from vertex k to k+1.        */
+/* ------------------------------------------------------------------------ */
+#define ORC_TAG_BOX (-100)
+
+static int clip_polygon(int nv, const double *v, const int32_t *tag, double *ov, int32_t *otag,
+                        const double *nrm, double off, int32_t newtag, int cap)
+{
+    /* keep { y : nrm . y - off <= 0 } (points on the line are kept) */
+    int no = 0;
+    for (int k = 0; k < nv; ++k) {
+        const double *P = v + 2 * k;
+        const double *Q = v + 2 * ((k + 1) % nv);
+        double sp = nrm[0] * P[0] + nrm[1] * P[1] - off;
+        double sq = nrm[0] * Q[0] + nrm[1] * Q[1] - off;
+        if (sp <= 0.0) {
+            if (no >= cap) return -1;
+            ov[2 * no] = P[0]; ov[2 * no + 1] = P[1];
+            otag[no++] = tag[k];       /* from P onward along edge k */
+            if (sq > 0.0) {
+                double t = sp / (sp - sq);
+                if (no >= cap) return -1;
+                ov[2 * no] = P[0] + t * (Q[0] - P[0]);
+                ov[2 * no + 1] = P[1] + t * (Q[1] - P[1]);
+                otag[no++] = newtag;   /* ... and from the cut point on along the bisector */
+            }
+        } else if (sq <= 0.0) {
+            double t = sp / (sp - sq);
+            if (no >= cap) return -1;
+            ov[2 * no] = P[0] + t * (Q[0] - P[0]);
+            ov[2 * no + 1] = P[1] + t * (Q[1] - P[1]);
+            otag[no++] = tag[k];       /* from this cut point to Q lies on edge k */
+        }
+    }
+    return no;
+}
+
+int64_t orc_cells2d(int64_t n, const double *x, const double *R, const int64_t *off, const int32_t *idx,
+                    const double *dom_lo, const double *dom_hi, int cap, int32_t *nv_out,
+                    double *verts, int32_t *tags, double *V, double *rho)
+{
+    double *a = (double *)malloc(sizeof(double) * 2 * cap), *b = (double *)malloc(sizeof(double) * 2 * cap);
+    int32_t *ta = (int32_t *)malloc(sizeof(int32_t) * cap), *tb = (int32_t *)malloc(sizeof(int32_t) * cap);
+    int64_t bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double *xi = x + 2 * i;
+        double lo0 = xi[0] - R[i], hi0 = xi[0] + R[i], lo1 = xi[1] - R[i], hi1 = xi[1] + R[i];
+        int32_t t_lo0 = ORC_TAG_BOX, t_hi0 = ORC_TAG_BOX, t_lo1 = ORC_TAG_BOX, t_hi1 = ORC_TAG_BOX;
+        if (lo0 <= dom_lo[0]) { lo0 = dom_lo[0]; t_lo0 = -1; }
+        if (hi0 >= dom_hi[0]) { hi0 = dom_hi[0]; t_hi0 = -2; }
+        if (lo1 <= dom_lo[1]) { lo1 = dom_lo[1]; t_lo1 = -3; }
+        if (hi1 >= dom_hi[1]) { hi1 = dom_hi[1]; t_hi1 = -4; }
+        /* CCW: (lo0,lo1) -> (hi0,lo1) -> (hi0,hi1) -> (lo0,hi1) */
+        a[0] = lo0; a[1] = lo1; ta[0] = t_lo1;
+        a[2] = hi0; a[3] = lo1; ta[1] = t_hi0;
+        a[4] = hi0; a[5] = hi1; ta[2] = t_hi1;
+        a[6] = lo0; a[7] = hi1; ta[3] = t_lo0;
+        int nv = 4;
+        for (int64_t p = off[i]; p < off[i + 1] && nv > 0; ++p) {
+            int32_t j = idx[p];
+            const double *xj = x + 2 * j;
+            double nrm[2] = {xj[0] - xi[0], xj[1] - xi[1]};
+            double mid[2] = {0.5 * (xi[0] + xj[0]), 0.5 * (xi[1] + xj[1])};
+            double o = nrm[0] * mid[0] + nrm[1] * mid[1];
+            int no = clip_polygon(nv, a, ta, b, tb, nrm, o, j, cap);
+            if (no < 0) { nv = -1; break; }
+            nv = no;
+            double *s = a; a = b; b = s;
+            int32_t *st = ta; ta = tb; tb = st;
+        }
+        if (nv < 3) {
+            bad++;
+            nv_out[i] = 0; V[i] = 0.0; rho[i] = 0.0;
+            continue;
+        }
+        nv_out[i] = nv;
+        double area = 0.0, r2 = 0.0;
+        for (int k = 0; k < nv; ++k) {
+            const double *P = a + 2 * k, *Q = a + 2 * ((k + 1) % nv);
+            area += 0.5 * ((P[0] - xi[0]) * (Q[1] - xi[1]) - (P[1] - xi[1]) * (Q[0] - xi[0]));
+            double d0 = P[0] - xi[0], d1 = P[1] - xi[1];
+            if (d0 * d0 + d1 * d1 > r2) r2 = d0 * d0 + d1 * d1;
+            verts[(i * cap + k) * 2] = P[0];
+            verts[(i * cap + k) * 2 + 1] = P[1];
+            tags[i * cap + k] = ta[k];
+        }
+        V[i] = area;
+        rho[i] = sqrt(r2);
+    }
+    free(a); free(b); free(ta); free(tb);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cubic B-spline base kernel (reading of the unnamed W^b of Sec. 2.1),
+ * q = |y - x_j| / h_j with h_j = R_j / 2, support q < 2.  The
+ * normalisation constant cancels in the RK functions and is omitted.
+ * Returns W and fills dW = grad_y W.                                        */
+/* ------------------------------------------------------------------------ */
+static double kernel_w(int dim, const double *y, const double *xj, double Rj, double *dW)
+{
+    double h = 0.5 * Rj;
+    double r[ORC_MAXD], r2 = 0.0;
+    for (int a = 0; a < dim; ++a) { r[a] = y[a] - xj[a]; r2 += r[a] * r[a]; }
+    double q = sqrt(r2) / h;
+    double w, dwq_over_q;  /* W(q) and W'(q)/q */
+    if (q < 1.0) {
+        w = 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+        dwq_over_q = -3.0 + 2.25 * q;
+    } else if (q < 2.0) {
+        double t = 2.0 - q;
+        w = 0.25 * t * t * t;
+        dwq_over_q = -0.75 * t * t / q;
+    } else {
+        w = 0.0;
+        dwq_over_q = 0.0;
+    }
+    /* grad_y W = W'(q) dq/dy = W'(q) (y - x_j) / (q h^2) */
+    for (int a = 0; a < dim; ++a) dW[a] = dwq_over_q * r[a] / (h * h);
+    return w;
+}
+
+/* Monomial basis P(z) = [1, z^a, z^a z^b (a <= b)] of total degree <= order,
+ * and its derivatives dP/dz^g.  Returns the basis size.                    */
+static int basis_size(int dim, int order)
+{
+    if (order == 0) return 1;
+    if (order == 1) return 1 + dim;
+    return (dim + 1) * (dim + 2) / 2;
+}
+
+static void basis_eval(int dim, int order, const double *z, double *P, double dP[][ORC_MAXB])
+{
+    int b = basis_size(dim, order);
+    for (int k = 0; k < b; ++k) {
+        P[k] = 0.0;
+        for (int g = 0; g < dim; ++g) dP[g][k] = 0.0;
+    }
+    P[0] = 1.0;
+    if (order >= 1)
+        for (int a = 0; a < dim; ++a) {
+            P[1 + a] = z[a];
+            dP[a][1 + a] = 1.0;
+        }
+    if (order >= 2) {
+        int k = 1 + dim;
+        for (int a = 0; a < dim; ++a)
+            for (int c = a; c < dim; ++c) {
+                P[k] = z[a] * z[c];
+                dP[a][k] += z[c];
+                dP[c][k] += z[a];
+                k++;
+            }
+    }
+}
+
+/* Cholesky factorisation M = L L^T in place (lower triangle).  Returns 0 on
+ * success, -1 when a pivot falls below rel_tol * max diag(M).               */
+static int cholesky(int b, double M[][ORC_MAXB], double rel_tol)
+{
+    double dmax = 0.0;
+    for (int k = 0; k < b; ++k) if (M[k][k] > dmax) dmax = M[k][k];
+    if (!(dmax > 0.0)) return -1;
+    for (int k = 0; k < b; ++k) {
+        double s = M[k][k];
+        for (int p = 0; p < k; ++p) s -= M[k][p] * M[k][p];
+        if (!(s > rel_tol * dmax)) return -1;
+        M[k][k] = sqrt(s);
+        for (int r = k + 1; r < b; ++r) {
+            double t = M[r][k];
+            for (int p = 0; p < k; ++p) t -= M[r][p] * M[k][p];
+            M[r][k] = t / M[k][k];
+        }
+    }
+    return 0;
+}
+
+static void chol_solve(int b, double L[][ORC_MAXB], const double *rhs, double *out)
+{
+    double t[ORC_MAXB];
+    for (int k = 0; k < b; ++k) {
+        double s = rhs[k];
+        for (int p = 0; p < k; ++p) s -= L[k][p] * t[p];
+        t[k] = s / L[k][k];
+    }
+    for (int k = b - 1; k >= 0; --k) {
+        double s = t[k];
+        for (int p = k + 1; p < b; ++p) s -= L[p][k] * out[p];
+        out[k] = s / L[k][k];
+    }
+}
+
+/* RK functions at point y (Sec. 2.2).  Candidates cand[0..nc) are the points
+ * whose kernel might cover y; those with W_j(y) = 0 get N = dN = 0.  The
+ * monomials are taken in the scaled argument z = (y - x_j) / hs; this
+ * diagonal change of basis leaves U_j unchanged and only improves the
+ * conditioning of M.  Output N_j = V_j U_j and dN_j = V_j grad U_j.  When the
+ * Cholesky pivot test fails the order drops by one and the evaluation is
+ * repeated (reading for the singular case the paper leaves open).  Returns
+ * the order used, or -1 when even order 0 fails (no kernel covers y).      */
+#define ORC_PIVOT_TOL 1e-12
+
+static int rk_eval_act(int dim, int order, const double *y, int nc, const int32_t *cand, const double *x,
+                       const double *R, const double *V, double hs, double *N, double *dN, unsigned char *act)
+{
+    for (int ord = order; ord >= 0; --ord) {
+        int b = basis_size(dim, ord);
+        double M[ORC_MAXB][ORC_MAXB], dM[ORC_MAXD][ORC_MAXB][ORC_MAXB];
+        memset(M, 0, sizeof(M));
+        memset(dM, 0, sizeof(dM));
+        for (int c = 0; c < nc; ++c) {
+            const double *xj = x + (int64_t)cand[c] * dim;
+            double dW[ORC_MAXD];
+            double W = kernel_w(dim, y, xj, R[cand[c]], dW);
+            if (W == 0.0) continue;
+            double z[ORC_MAXD], P[ORC_MAXB], dPz[ORC_MAXD][ORC_MAXB];
+            for (int a = 0; a < dim; ++a) z[a] = (y[a] - xj[a]) / hs;
+            basis_eval(dim, ord, z, P, dPz);
+            double Vj = V[cand[c]];
+            for (int r = 0; r < b; ++r)
+                for (int s = 0; s < b; ++s) {
+                    M[r][s] += Vj * P[r] * P[s] * W;
+                    for (int g = 0; g < dim; ++g)
+                        dM[g][r][s] += Vj * ((dPz[g][r] / hs * P[s] + P[r] * dPz[g][s] / hs) * W +
+                                             P[r] * P[s] * dW[g]);
+                }
+        }
+        double L[ORC_MAXB][ORC_MAXB];
+        memcpy(L, M, sizeof(M));
+        if (cholesky(b, L, ORC_PIVOT_TOL) != 0) continue;
+        double G[ORC_MAXB] = {0}, C[ORC_MAXB], dC[ORC_MAXD][ORC_MAXB];
+        G[0] = 1.0;
+        chol_solve(b, L, G, C);                        /* C = M^-1 G        */
+        for (int g = 0; g < dim; ++g) {                /* dC = -M^-1 dM C   */
+            double t[ORC_MAXB];
+            for (int r = 0; r < b; ++r) {
+                double s = 0.0;
+                for (int q = 0; q < b; ++q) s += dM[g][r][q] * C[q];
+                t[r] = -s;
+            }
+            chol_solve(b, L, t, dC[g]);
+        }
+        for (int c = 0; c < nc; ++c) {
+            const double *xj = x + (int64_t)cand[c] * dim;
+            double dW[ORC_MAXD];
+            double W = kernel_w(dim, y, xj, R[cand[c]], dW);
+            if (W == 0.0) {
+                N[c] = 0.0;
+                for (int g = 0; g < dim; ++g) dN[c * dim + g] = 0.0;
+                if (act) act[c] = 0;
+                continue;
+            }
+            if (act) act[c] = 1;
+            double z[ORC_MAXD], P[ORC_MAXB], dPz[ORC_MAXD][ORC_MAXB];
+            for (int a = 0; a < dim; ++a) z[a] = (y[a] - xj[a]) / hs;
+            basis_eval(dim, ord, z, P, dPz);
+            double PC = 0.0;
+            for (int r = 0; r < b; ++r) PC += P[r] * C[r];
+            double Vj = V[cand[c]];
+            N[c] = Vj * PC * W;                        /* U_j = P_j^T C W_j */
+            for (int g = 0; g < dim; ++g) {
+                double t1 = 0.0, t2 = 0.0;
+                for (int r = 0; r < b; ++r) {
+                    t1 += dPz[g][r] / hs * C[r];
+                    t2 += P[r] * dC[g][r];
+                }
+                dN[c * dim + g] = Vj * ((t1 + t2) * W + PC * dW[g]);
+            }
+        }
+        return ord;
+    }
+    for (int c = 0; c < nc; ++c) {
+        N[c] = 0.0;
+        for (int g = 0; g < dim; ++g) dN[c * dim + g] = 0.0;
+        if (act) act[c] = 0;
+    }
+    return -1;
+}
+
+int orc_rk_eval(int dim, int order, const double *y, int nc, const int32_t *cand, const double *x,
+                const double *R, const double *V, double hs, double *N, double *dN)
+{
+    return rk_eval_act(dim, order, y, nc, cand, x, R, V, hs, N, dN, NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Meshless integration (Sec. 3.2, Alg. 1).  Blocks over the overlap pattern
+ * (rows = test function i, columns = trial function j; row i of the pattern
+ * holds i and its neighbours in increasing order):
+ *   Mass_g[i,j] = <N_i, N_j>        over material-g quadrature points
+ *   D^a_g[i,j]  = <d^a N_i, N_j>    over material-g quadrature points
+ *   K^ab[i,j]   = <d^a N_i, d^b N_j>
+ *   S_f[i,j]    = (N_i, N_j) on domain face f
+ * with N_i = V_i U_i (the test function U_i scaled by V_i, so that Mass is
+ * symmetric).  Block order: for g: Mass_g, D^0_g..D^{d-1}_g; then K^ab with
+ * a-major order; then S_0..S_{2d-1}.                                        */
+/* ------------------------------------------------------------------------ */
+int orc_num_blocks(int dim, int n_mat) { return n_mat * (1 + dim) + dim * dim + 2 * dim; }
+
+static int64_t find_pos(const int64_t *row_off, const int32_t *col, int64_t i, int32_t j)
+{
+    int64_t lo = row_off[i], hi = row_off[i + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (col[mid] == j) return mid;
+        if (col[mid] < j) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+static int material_at(int dim, const double *y, int n_regions, const double *reg_lo,
+                       const double *reg_hi, const int32_t *reg_mat)
+{
+    int m = 0;
+    for (int r = 0; r < n_regions; ++r) {
+        int in = 1;
+        for (int a = 0; a < dim; ++a)
+            if (y[a] < reg_lo[r * dim + a] || y[a] > reg_hi[r * dim + a]) in = 0;
+        if (in) m = reg_mat[r];
+    }
+    return m;
+}
+
+typedef struct {
+    int dim, rk_order, n_mat;
+    int64_t n;
+    const double *x, *R, *V;
+    const int64_t *nb_off;
+    const int32_t *nb_idx;
+    const int64_t *row_off;
+    const int32_t *col;
+    int64_t nnz;
+    int n_regions;
+    const double *reg_lo, *reg_hi;
+    const int32_t *reg_mat;
+    double *blocks;             /* [nblk][nnz] */
+    int64_t fallbacks, missing;
+} integ_ctx;
+
+/* Candidate functions for a cell c: c itself and its overlap neighbours
+ * (the doubled-radius argument of Sec. 3.4). */
+static int cell_candidates(const integ_ctx *ic, int64_t c, int32_t *cand)
+{
+    int nc = 0;
+    cand[nc++] = (int32_t)c;
+    for (int64_t p = ic->nb_off[c]; p < ic->nb_off[c + 1]; ++p) cand[nc++] = ic->nb_idx[p];
+    return nc;
+}
+
+/* Accumulate one volume quadrature point of weight w (already mapped by |J|). */
+static void add_volume_point(integ_ctx *ic, int64_t c, const double *y, double w, int nc,
+                             const int32_t *cand, const int64_t *pos, double *N, double *dN,
+                             unsigned char *act)
+{
+    int dim = ic->dim;
+    int ord = rk_eval_act(dim, ic->rk_order, y, nc, cand, ic->x, ic->R, ic->V, 0.5 * ic->R[c], N, dN, act);
+    if (ord < 0) return;
+    if (ord < ic->rk_order) ic->fallbacks++;
+    int g = material_at(dim, y, ic->n_regions, ic->reg_lo, ic->reg_hi, ic->reg_mat);
+    int64_t nnz = ic->nnz;
+    for (int a = 0; a < nc; ++a) {
+        if (!act[a]) continue;
+        for (int b = 0; b < nc; ++b) {
+            if (!act[b]) continue;
+            int64_t p = pos[a * nc + b];
+            if (p < 0) { ic->missing++; continue; }
+            ic->blocks[(int64_t)(g * (1 + dim)) * nnz + p] += w * N[a] * N[b];
+            for (int al = 0; al < dim; ++al)
+                ic->blocks[(int64_t)(g * (1 + dim) + 1 + al) * nnz + p] += w * dN[a * dim + al] * N[b];
+            int kb = ic->n_mat * (1 + dim);
+            for (int al = 0; al < dim; ++al)
+                for (int be = 0; be < dim; ++be)
+                    ic->blocks[(int64_t)(kb + al * dim + be) * nnz + p] +=
+                        w * dN[a * dim + al] * dN[b * dim + be];
+        }
+    }
+}
+
+typedef struct {
+    int64_t count, cap;
+    double *y;        /* [cap][dim] */
+    int32_t *face;    /* [cap] */
+    double *w;        /* [cap] */
+    int kmax;
+    int32_t *nact;    /* [cap] */
+    int32_t *act;     /* [cap][kmax] */
+    double *Nv;       /* [cap][kmax] */
+} bq_out;
+
+static void add_surface_point(integ_ctx *ic, int64_t c, const double *y, double w, int face, int nc,
+                              const int32_t *cand, const int64_t *pos, double *N, double *dN,
+                              unsigned char *act, bq_out *bo)
+{
+    int dim = ic->dim;
+    int ord = rk_eval_act(dim, ic->rk_order, y, nc, cand, ic->x, ic->R, ic->V, 0.5 * ic->R[c], N, dN, act);
+    if (ord < 0) return;
+    if (ord < ic->rk_order) ic->fallbacks++;
+    int64_t nnz = ic->nnz;
+    int sb = ic->n_mat * (1 + dim) + dim * dim + face;
+    for (int a = 0; a < nc; ++a) {
+        if (!act[a]) continue;
+        for (int b = 0; b < nc; ++b) {
+            if (!act[b]) continue;
+            int64_t p = pos[a * nc + b];
+            if (p < 0) { ic->missing++; continue; }
+            ic->blocks[(int64_t)sb * nnz + p] += w * N[a] * N[b];
+        }
+    }
+    if (bo && bo->y) {
+        int64_t k = bo->count;
+        if (k < bo->cap) {
+            for (int a = 0; a < dim; ++a) bo->y[k * dim + a] = y[a];
+            bo->face[k] = face;
+            bo->w[k] = w;
+            int na = 0;
+            for (int a = 0; a < nc && na < bo->kmax; ++a)
+                if (act[a]) {
+                    bo->act[k * bo->kmax + na] = cand[a];
+                    bo->Nv[k * bo->kmax + na] = N[a];
+                    na++;
+                }
+            bo->nact[k] = na;
+        }
+    }
+    bo->count++;
+}
+
+/* 2D integration: each cell is split into the fan of triangles (x_c, v_k,
+ * v_k+1) (Fig. 2); the reference triangle {xi >= 0, xi0 + xi1 <= 1} is mapped
+ * by x = p0 + (p_a - p0) xi^a with |J| = twice the area (App. A).  Cell edges
+ * on domain face f get the line rule mapped from [-1,1] with K = half the
+ * edge length.  Also returns E[p] = N_j(x_i) on the pattern (the point values
+ * of Eq. flux-expansion), evaluated with the cell of x_i.                   */
+int64_t orc_integrate2d(integ_ctx *ic_in, int cap, const int32_t *nv, const double *verts,
+                        const int32_t *tags, int nq_tri, const double *tri_pts, const double *tri_w,
+                        int nq_seg, const double *seg_pts, const double *seg_w, double *E,
+                        int64_t bq_cap, int kmax, double *bq_y, int32_t *bq_face, double *bq_w,
+                        int32_t *bq_nact, int32_t *bq_act, double *bq_N, int64_t *stats)
+{
+    integ_ctx ic = *ic_in;
+    ic.fallbacks = 0;
+    ic.missing = 0;
+    int64_t n = ic.n;
+    int maxc = 1;
+    for (int64_t c = 0; c < n; ++c) {
+        int k = (int)(ic.nb_off[c + 1] - ic.nb_off[c]) + 1;
+        if (k > maxc) maxc = k;
+    }
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * maxc);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * maxc * maxc);
+    double *N = (double *)malloc(sizeof(double) * maxc);
+    double *dN = (double *)malloc(sizeof(double) * maxc * 2);
+    unsigned char *act = (unsigned char *)malloc(maxc);
+    bq_out bo = {0, bq_cap, bq_y, bq_face, bq_w, kmax, bq_nact, bq_act, bq_N};
+    for (int64_t c = 0; c < n; ++c) {
+        int nc = cell_candidates(&ic, c, cand);
+        for (int a = 0; a < nc; ++a)
+            for (int b = 0; b < nc; ++b) pos[a * nc + b] = find_pos(ic.row_off, ic.col, cand[a], cand[b]);
+        const double *xc = ic.x + 2 * c;
+        int m = nv[c];
+        for (int k = 0; k < m; ++k) {
+            const double *P = verts + (c * cap + k) * 2;
+            const double *Q = verts + (c * cap + (k + 1) % m) * 2;
+            double e1[2] = {P[0] - xc[0], P[1] - xc[1]}, e2[2] = {Q[0] - xc[0], Q[1] - xc[1]};
+            double detJ = e1[0] * e2[1] - e1[1] * e2[0];   /* = 2 * area (CCW) */
+            if (detJ > 0.0) {
+                for (int q = 0; q < nq_tri; ++q) {
+                    double y[2] = {xc[0] + e1[0] * tri_pts[2 * q] + e2[0] * tri_pts[2 * q + 1],
+                                   xc[1] + e1[1] * tri_pts[2 * q] + e2[1] * tri_pts[2 * q + 1]};
+                    add_volume_point(&ic, c, y, tri_w[q] * detJ, nc, cand, pos, N, dN, act);
+                }
+            }
+            int t = tags[c * cap + k];
+            if (t <= -1 && t >= -4) {
+                int face = -1 - t;
+                double len = sqrt((Q[0] - P[0]) * (Q[0] - P[0]) + (Q[1] - P[1]) * (Q[1] - P[1]));
+                for (int q = 0; q < nq_seg; ++q) {
+                    double s = 0.5 * (seg_pts[q] + 1.0);
+                    double y[2] = {P[0] + (Q[0] - P[0]) * s, P[1] + (Q[1] - P[1]) * s};
+                    add_surface_point(&ic, c, y, seg_w[q] * 0.5 * len, face, nc, cand, pos, N, dN, act, &bo);
+                }
+            }
+        }
+        /* point values at the generator x_c */
+        if (E) {
+            int ord = rk_eval_act(2, ic.rk_order, xc, nc, cand, ic.x, ic.R, ic.V, 0.5 * ic.R[c], N, dN, act);
+            if (ord >= 0) {
+                if (ord < ic.rk_order) ic.fallbacks++;
+                for (int a = 0; a < nc; ++a) {
+                    if (!act[a]) continue;
+                    int64_t p = pos[0 * nc + a];
+                    if (p < 0) { ic.missing++; continue; }
+                    E[p] = N[a];
+                }
+            }
+        }
+    }
+    free(cand); free(pos); free(N); free(dN); free(act);
+    stats[0] = ic.fallbacks;
+    stats[1] = ic.missing;
+    stats[2] = bo.count;
+    return bo.count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Operators of Sec. 4.2, applied for one ordinate m from the blocks.
+ *   (L psi)_i  = sum_j [ a0 <N_i,N_j> + a0 tau_i W.<dN_i,N_j>
+ *                       + sum_f max(0, W.n_f) (N_i,N_j)_f - W.<dN_i,N_j>
+ *                       + tau_i W^a W^b <d^a N_i, d^b N_j>
+ *                       + <N_i sigma_t N_j> + tau_i W.<dN_i sigma_t N_j> ] psi_j
+ *   (T psi)_i  = sum_j [ a0 <N_i,N_j> + a0 tau_i W.<dN_i,N_j> ] psi_j
+ *   (MS phi)_i = 1/(4 pi) sum_j [ <N_i sigma_s N_j> + tau_i W.<dN_i sigma_s N_j> ] phi_j
+ *   source     = sum_j [ <N_i,N_j> + tau_i W.<dN_i,N_j> ] q_j   (q expanded in the basis)
+ * with W = Omega_m, a0 = 1/(c dt), and f running over the domain faces whose
+ * outward normal n_f satisfies W.n_f > 0 (outflow).                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int dim, n_mat, n_ord;
+    int64_t n, nnz;
+    const int64_t *row_off;
+    const int32_t *col;
+    const double *blocks;
+    const double *omega;   /* [M][dim] */
+    const double *wq;      /* [M] */
+    const double *sig_t, *sig_s;
+    double a0;
+    const double *tau;     /* [n] */
+    /* boundary quadrature points for the inflow term */
+    int64_t nbq;
+    int kmax;
+    const int32_t *bq_face;
+    const double *bq_w;
+    const int32_t *bq_nact, *bq_act;
+    const double *bq_N;
+    /* solver settings */
+    double tol_in, tol_out;
+    int restart_in, restart_out, max_in, max_out;
+} op_ctx;
+
+static const double face_normal[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+
+static double blk(const op_ctx *o, int b, int64_t p) { return o->blocks[(int64_t)b * o->nnz + p]; }
+
+static double L_entry(const op_ctx *o, int m, int64_t i, int64_t p)
+{
+    int dim = o->dim, G = o->n_mat;
+    const double *W = o->omega + m * dim;
+    double tau = o->tau[i];
+    double mass = 0.0, WD = 0.0, sigmass = 0.0, sigWD = 0.0;
+    for (int g = 0; g < G; ++g) {
+        double mg = blk(o, g * (1 + dim), p);
+        double dg = 0.0;
+        for (int a = 0; a < dim; ++a) dg += W[a] * blk(o, g * (1 + dim) + 1 + a, p);
+        mass += mg;
+        WD += dg;
+        sigmass += o->sig_t[g] * mg;
+        sigWD += o->sig_t[g] * dg;
+    }
+    double WKW = 0.0;
+    int kb = G * (1 + dim);
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) WKW += W[a] * W[b] * blk(o, kb + a * dim + b, p);
+    double surf = 0.0;
+    int sb = kb + dim * dim;
+    for (int f = 0; f < 2 * dim; ++f) {
+        double wn = 0.0;
+        for (int a = 0; a < dim; ++a) wn += W[a] * face_normal[f][a];
+        if (wn > 0.0) surf += wn * blk(o, sb + f, p);
+    }
+    return o->a0 * mass + o->a0 * tau * WD + surf - WD + tau * WKW + sigmass + tau * sigWD;
+}
+
+static void apply_L(const op_ctx *o, int m, const double *x, double *y)
+{
+    for (int64_t i = 0; i < o->n; ++i) {
+        double s = 0.0;
+        for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p) s += L_entry(o, m, i, p) * x[o->col[p]];
+        y[i] = s;
+    }
+}
+
+/* kind 0: (Mass + tau W.D) x ; kind 1: 1/(4 pi) sigma_s-weighted version */
+static void apply_MD(const op_ctx *o, int m, int kind, const double *x, double *y)
+{
+    int dim = o->dim, G = o->n_mat;
+    const double *W = o->omega + m * dim;
+    for (int64_t i = 0; i < o->n; ++i) {
+        double s = 0.0;
+        for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p) {
+            double e = 0.0;
+            for (int g = 0; g < G; ++g) {
+                double coef = kind == 0 ? 1.0 : o->sig_s[g] / (4.0 * M_PI);
+                double dg = 0.0;
+                for (int a = 0; a < dim; ++a) dg += W[a] * blk(o, g * (1 + dim) + 1 + a, p);
+                e += coef * (blk(o, g * (1 + dim), p) + o->tau[i] * dg);
+            }
+            s += e * x[o->col[p]];
+        }
+        y[i] = s;
+    }
+}
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* Restarted GMRES with right point-Jacobi preconditioning for L_m x = f,
+ * x0 = 0, modified Gram-Schmidt Arnoldi and Givens rotations (Saad,
+ * Iterative Methods for Sparse Linear Systems, Alg. 6.9 with right
+ * preconditioning).  Stops when ||f - L x|| <= tol ||f||.  Returns the
+ * number of Arnoldi steps; *res gets the final relative residual.           */
+static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, double *res)
+{
+    int64_t n = o->n;
+    int k = o->restart_in;
+    double *Vb = (double *)malloc(sizeof(double) * n * (k + 1));
+    double *z = (double *)malloc(sizeof(double) * n), *w = (double *)malloc(sizeof(double) * n);
+    double *r = (double *)malloc(sizeof(double) * n), *dinv = (double *)malloc(sizeof(double) * n);
+    double *H = (double *)calloc((size_t)(k + 1) * k, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * k), *sn = (double *)malloc(sizeof(double) * k);
+    double *g = (double *)malloc(sizeof(double) * (k + 1)), *yv = (double *)malloc(sizeof(double) * k);
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p)
+            if (o->col[p] == i) d = L_entry(o, m, i, p);
+        dinv[i] = d != 0.0 ? 1.0 / d : 1.0;
+        x[i] = 0.0;
+    }
+    double fn = sqrt(dot(n, f, f));
+    int64_t its = 0;
+    double rel = 0.0;
+    if (fn == 0.0) goto done;
+    for (;;) {
+        apply_L(o, m, x, r);
+        for (int64_t i = 0; i < n; ++i) r[i] = f[i] - r[i];
+        double beta = sqrt(dot(n, r, r));
+        rel = beta / fn;
+        if (beta <= o->tol_in * fn || its >= o->max_in) break;
+        for (int64_t i = 0; i < n; ++i) Vb[i] = r[i] / beta;
+        for (int j = 0; j <= k; ++j) g[j] = 0.0;
+        g[0] = beta;
+        int jend = 0;
+        for (int j = 0; j < k; ++j) {
+            const double *vj = Vb + (int64_t)j * n;
+            for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * vj[i];
+            apply_L(o, m, z, w);
+            for (int q = 0; q <= j; ++q) {
+                const double *vq = Vb + (int64_t)q * n;
+                double h = dot(n, w, vq);
+                H[q * k + j] = h;
+                for (int64_t i = 0; i < n; ++i) w[i] -= h * vq[i];
+            }
+            double hn = sqrt(dot(n, w, w));
+            H[(j + 1) * k + j] = hn;
+            for (int q = 0; q < j; ++q) {
+                double a = H[q * k + j], b = H[(q + 1) * k + j];
+                H[q * k + j] = cs[q] * a + sn[q] * b;
+                H[(q + 1) * k + j] = -sn[q] * a + cs[q] * b;
+            }
+            double a = H[j * k + j], b = H[(j + 1) * k + j];
+            double den = sqrt(a * a + b * b);
+            cs[j] = den == 0.0 ? 1.0 : a / den;
+            sn[j] = den == 0.0 ? 0.0 : b / den;
+            H[j * k + j] = den;
+            H[(j + 1) * k + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            its++;
+            jend = j + 1;
+            if (fabs(g[j + 1]) <= o->tol_in * fn || hn == 0.0 || its >= o->max_in) break;
+            double *vn = Vb + (int64_t)(j + 1) * n;
+            for (int64_t i = 0; i < n; ++i) vn[i] = w[i] / hn;
+        }
+        for (int q = jend - 1; q >= 0; --q) {
+            double s = g[q];
+            for (int p = q + 1; p < jend; ++p) s -= H[q * k + p] * yv[p];
+            yv[q] = s / H[q * k + q];
+        }
+        for (int q = 0; q < jend; ++q) {
+            const double *vq = Vb + (int64_t)q * n;
+            for (int64_t i = 0; i < n; ++i) x[i] += dinv[i] * yv[q] * vq[i];
+        }
+    }
+done:
+    *res = rel;
+    free(Vb); free(z); free(w); free(r); free(dinv); free(H); free(cs); free(sn); free(g); free(yv);
+    return its;
+}
+
+typedef struct {
+    int64_t inner_its;
+    double inner_res_max;
+    int64_t inner_solves;
+} solve_stats;
+
+/* X = L^-1 F for every ordinate (L is block diagonal in angle).  F, X are
+ * [n][M], ordinate fastest.                                                 */
+static void Linv_all(const op_ctx *o, const double *F, double *X, solve_stats *st)
+{
+    int M = o->n_ord;
+    int64_t n = o->n;
+    int64_t its_sum = 0;
+    double res_max = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : its_sum) reduction(max : res_max)
+    for (int m = 0; m < M; ++m) {
+        double *f = (double *)malloc(sizeof(double) * n), *x = (double *)malloc(sizeof(double) * n);
+        for (int64_t i = 0; i < n; ++i) f[i] = F[i * M + m];
+        double res;
+        its_sum += gmres_L(o, m, f, x, &res);
+        if (res > res_max) res_max = res;
+        for (int64_t i = 0; i < n; ++i) X[i * M + m] = x[i];
+        free(f); free(x);
+    }
+    st->inner_its += its_sum;
+    st->inner_solves += 1;
+    if (res_max > st->inner_res_max) st->inner_res_max = res_max;
+}
+
+/* Y[i][m] = (MS_m phi)_i */
+static void MS_all(const op_ctx *o, const double *phi, double *Y)
+{
+    int M = o->n_ord;
+    int64_t n = o->n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int m = 0; m < M; ++m) {
+        double *y = (double *)malloc(sizeof(double) * n);
+        apply_MD(o, m, 1, phi, y);
+        for (int64_t i = 0; i < n; ++i) Y[i * M + m] = y[i];
+        free(y);
+    }
+}
+
+/* (D Psi)_i = sum_m w_m Psi_{m,i} */
+static void D_op(const op_ctx *o, const double *Psi, double *phi)
+{
+    int M = o->n_ord;
+    for (int64_t i = 0; i < o->n; ++i) {
+        double s = 0.0;
+        for (int m = 0; m < M; ++m) s += o->wq[m] * Psi[i * M + m];
+        phi[i] = s;
+    }
+}
+
+/* Outer operator A phi = phi - D L^-1 MS phi (Eq. krylov-operator). */
+static void apply_outer(const op_ctx *o, const double *phi, double *out, double *tmp1, double *tmp2,
+                        solve_stats *st)
+{
+    MS_all(o, phi, tmp1);
+    Linv_all(o, tmp1, tmp2, st);
+    D_op(o, tmp2, out);
+    for (int64_t i = 0; i < o->n; ++i) out[i] = phi[i] - out[i];
+}
+
+/* Right-hand side of one backward-Euler step (Sec. 4.1-4.2):
+ *   F_m = T_m Psi^{n-1} + r_m,
+ *   r_m = (N_i, |W.n| psi_b)_{W.n<0} + <N_i, q_m> + tau_i W.<dN_i, q_m>.     */
+static void build_rhs(const op_ctx *o, const double *psi_prev, const double *q, const double *psib, double *F)
+{
+    int M = o->n_ord, dim = o->dim;
+    int64_t n = o->n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int m = 0; m < M; ++m) {
+        double *a = (double *)malloc(sizeof(double) * n), *b = (double *)malloc(sizeof(double) * n);
+        double *c = (double *)malloc(sizeof(double) * n), *d = (double *)malloc(sizeof(double) * n);
+        for (int64_t i = 0; i < n; ++i) { a[i] = psi_prev ? psi_prev[i * M + m] : 0.0; c[i] = q[i * M + m]; }
+        apply_MD(o, m, 0, a, b);        /* (Mass + tau W.D) Psi^{n-1} */
+        apply_MD(o, m, 0, c, d);        /* (Mass + tau W.D) q         */
+        for (int64_t i = 0; i < n; ++i) F[i * M + m] = o->a0 * b[i] + d[i];
+        free(a); free(b); free(c); free(d);
+    }
+    if (psib) {
+        for (int64_t k = 0; k < o->nbq; ++k) {
+            const double *nf = face_normal[o->bq_face[k]];
+            for (int m = 0; m < M; ++m) {
+                double wn = 0.0;
+                for (int a = 0; a < dim; ++a) wn += o->omega[m * dim + a] * nf[a];
+                if (wn >= 0.0) continue;
+                double val = psib[k * M + m];
+                if (val == 0.0) continue;
+                for (int t = 0; t < o->bq_nact[k]; ++t) {
+                    int32_t i = o->bq_act[k * o->kmax + t];
+                    F[(int64_t)i * M + m] += o->bq_w[k] * (-wn) * o->bq_N[k * o->kmax + t] * val;
+                }
+            }
+        }
+    }
+}
+
+/* One backward-Euler step, or a steady solve when a0 = 0 (Sec. 4.2):
+ *   b_psi = L^-1 (T Psi^{n-1} + r),  b_phi = D b_psi,
+ *   GMRES on (I - D L^-1 MS) Phi = b_phi from Phi0,
+ *   Psi = L^-1 MS Phi + b_psi.
+ * out_stats: [outer its, inner its total, inner solves], res: [outer rel res, max inner rel res] */
+int orc_step(op_ctx *o, const double *psi_prev, const double *q, const double *psib, const double *phi0,
+             double *psi_out, double *phi_out, int64_t *out_stats, double *out_res)
+{
+    int M = o->n_ord;
+    int64_t n = o->n;
+    solve_stats st = {0, 0.0, 0};
+    double *F = (double *)malloc(sizeof(double) * n * M), *bpsi = (double *)malloc(sizeof(double) * n * M);
+    double *tmp1 = (double *)malloc(sizeof(double) * n * M), *tmp2 = (double *)malloc(sizeof(double) * n * M);
+    build_rhs(o, psi_prev, q, psib, F);
+    Linv_all(o, F, bpsi, &st);
+    double *bphi = (double *)malloc(sizeof(double) * n);
+    D_op(o, bpsi, bphi);
+
+    /* outer GMRES(k), unpreconditioned */
+    int k = o->restart_out;
+    double *Vb = (double *)malloc(sizeof(double) * n * (k + 1));
+    double *w = (double *)malloc(sizeof(double) * n), *r = (double *)malloc(sizeof(double) * n);
+    double *H = (double *)calloc((size_t)(k + 1) * k, sizeof(double));
+    double *cs = (double *)malloc(sizeof(double) * k), *sn = (double *)malloc(sizeof(double) * k);
+    double *g = (double *)malloc(sizeof(double) * (k + 1)), *yv = (double *)malloc(sizeof(double) * k);
+    double *phi = phi_out;
+    for (int64_t i = 0; i < n; ++i) phi[i] = phi0 ? phi0[i] : 0.0;
+    double bn = sqrt(dot(n, bphi, bphi));
+    int64_t outer = 0;
+    double orel = 0.0;
+    if (bn > 0.0) {
+        for (;;) {
+            apply_outer(o, phi, r, tmp1, tmp2, &st);
+            for (int64_t i = 0; i < n; ++i) r[i] = bphi[i] - r[i];
+            double beta = sqrt(dot(n, r, r));
+            orel = beta / bn;
+            if (beta <= o->tol_out * bn || outer >= o->max_out) break;
+            for (int64_t i = 0; i < n; ++i) Vb[i] = r[i] / beta;
+            for (int j = 0; j <= k; ++j) g[j] = 0.0;
+            g[0] = beta;
+            int jend = 0;
+            for (int j = 0; j < k; ++j) {
+                apply_outer(o, Vb + (int64_t)j * n, w, tmp1, tmp2, &st);
+                for (int q2 = 0; q2 <= j; ++q2) {
+                    const double *vq = Vb + (int64_t)q2 * n;
+                    double h = dot(n, w, vq);
+                    H[q2 * k + j] = h;
+                    for (int64_t i = 0; i < n; ++i) w[i] -= h * vq[i];
+                }
+                double hn = sqrt(dot(n, w, w));
+                H[(j + 1) * k + j] = hn;
+                for (int q2 = 0; q2 < j; ++q2) {
+                    double a = H[q2 * k + j], b = H[(q2 + 1) * k + j];
+                    H[q2 * k + j] = cs[q2] * a + sn[q2] * b;
+                    H[(q2 + 1) * k + j] = -sn[q2] * a + cs[q2] * b;
+                }
+                double a = H[j * k + j], b = H[(j + 1) * k + j];
+                double den = sqrt(a * a + b * b);
+                cs[j] = den == 0.0 ? 1.0 : a / den;
+                sn[j] = den == 0.0 ? 0.0 : b / den;
+                H[j * k + j] = den;
+                H[(j + 1) * k + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                outer++;
+                jend = j + 1;
+                if (fabs(g[j + 1]) <= o->tol_out * bn || hn == 0.0 || outer >= o->max_out) break;
+                double *vn = Vb + (int64_t)(j + 1) * n;
+                for (int64_t i = 0; i < n; ++i) vn[i] = w[i] / hn;
+            }
+            for (int q2 = jend - 1; q2 >= 0; --q2) {
+                double s = g[q2];
+                for (int p = q2 + 1; p < jend; ++p) s -= H[q2 * k + p] * yv[p];
+                yv[q2] = s / H[q2 * k + q2];
+            }
+            for (int q2 = 0; q2 < jend; ++q2)
+                for (int64_t i = 0; i < n; ++i) phi[i] += yv[q2] * Vb[(int64_t)q2 * n + i];
+        }
+    } else {
+        for (int64_t i = 0; i < n; ++i) phi[i] = 0.0;
+    }
+    /* recovery: Psi = L^-1 MS Phi + b_psi */
+    MS_all(o, phi, tmp1);
+    Linv_all(o, tmp1, tmp2, &st);
+    for (int64_t t = 0; t < n * M; ++t) psi_out[t] = tmp2[t] + bpsi[t];
+    out_stats[0] = outer;
+    out_stats[1] = st.inner_its;
+    out_stats[2] = st.inner_solves;
+    out_res[0] = orel;
+    out_res[1] = st.inner_res_max;
+    free(F); free(bpsi); free(tmp1); free(tmp2); free(bphi); free(Vb); free(w); free(r); free(H);
+    free(cs); free(sn); free(g); free(yv);
+    return 0;
+}
+
+/* Source iteration Phi <- D L^-1 MS Phi + b_phi, the fixed-point alternative
+ * named in Sec. 4.2; used only as an independent cross-check of the GMRES
+ * outer solve. */
+int orc_step_source_iteration(op_ctx *o, const double *psi_prev, const double *q, const double *psib,
+                              int iters, double *psi_out, double *phi_out)
+{
+    int M = o->n_ord;
+    int64_t n = o->n;
+    solve_stats st = {0, 0.0, 0};
+    double *F = (double *)malloc(sizeof(double) * n * M), *bpsi = (double *)malloc(sizeof(double) * n * M);
+    double *tmp1 = (double *)malloc(sizeof(double) * n * M), *tmp2 = (double *)malloc(sizeof(double) * n * M);
+    double *bphi = (double *)malloc(sizeof(double) * n), *t = (double *)malloc(sizeof(double) * n);
+    build_rhs(o, psi_prev, q, psib, F);
+    Linv_all(o, F, bpsi, &st);
+    D_op(o, bpsi, bphi);
+    for (int64_t i = 0; i < n; ++i) phi_out[i] = bphi[i];
+    for (int it = 0; it < iters; ++it) {
+        MS_all(o, phi_out, tmp1);
+        Linv_all(o, tmp1, tmp2, &st);
+        D_op(o, tmp2, t);
+        for (int64_t i = 0; i < n; ++i) phi_out[i] = t[i] + bphi[i];
+    }
+    MS_all(o, phi_out, tmp1);
+    Linv_all(o, tmp1, tmp2, &st);
+    for (int64_t s = 0; s < n * M; ++s) psi_out[s] = tmp2[s] + bpsi[s];
+    free(F); free(bpsi); free(tmp1); free(tmp2); free(bphi); free(t);
+    return 0;
+}
+
+/* Single operator applications, for parity of one sweep and for assembling
+ * dense systems in tests.  which: 0 = L, 1 = T, 2 = MS, 3 = source operator
+ * (Mass + tau W.D).  X, Y are [n][M].                                        */
+void orc_apply(op_ctx *o, int which, const double *X, double *Y)
+{
+    int M = o->n_ord;
+    int64_t n = o->n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int m = 0; m < M; ++m) {
+        double *x = (double *)malloc(sizeof(double) * n), *y = (double *)malloc(sizeof(double) * n);
+        for (int64_t i = 0; i < n; ++i) x[i] = X[i * M + m];
+        if (which == 0) apply_L(o, m, x, y);
+        else if (which == 1) { apply_MD(o, m, 0, x, y); for (int64_t i = 0; i < n; ++i) y[i] *= o->a0; }
+        else if (which == 2) apply_MD(o, m, 1, x, y);
+        else apply_MD(o, m, 0, x, y);
+        for (int64_t i = 0; i < n; ++i) Y[i * M + m] = y[i];
+        free(x); free(y);
+    }
+}
+
+/* Right-hand side F = T Psi^{n-1} + r alone. */
+void orc_rhs(op_ctx *o, const double *psi_prev, const double *q, const double *psib, double *F)
+{
+    build_rhs(o, psi_prev, q, psib, F);
+}
+
+/* Point values phi(x_i) = sum_j N_j(x_i) Phi_j (Eq. flux-expansion). */
+void orc_point_values(int64_t n, const int64_t *row_off, const int32_t *col, const double *E,
+                      const double *coef, int ncomp, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < ncomp; ++c) {
+            double s = 0.0;
+            for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) s += E[p] * coef[(int64_t)col[p] * ncomp + c];
+            out[i * ncomp + c] = s;
+        }
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,263 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This module holds no arithmetic of the transport method itself: it only
+lays down point clouds (jittered lattices, Poisson-disk samples), support
+radii, material regions and the closed-form problem data (manufactured
+solutions and their sources, beams, Gaussian sources) that define each
+workload.  Both the oracle and the HIP path receive exactly these arrays.
+
+Point placement follows the paper's Results section: a uniform lattice
+whose points are perturbed by up to 0.2 times the spacing in each
+dimension, independently per point and dimension.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+
+SEED_BASE = 20080220
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def jittered_lattice(counts: Sequence[int], lo: Sequence[float], hi: Sequence[float],
+                     jitter: float, seed: int) -> tuple[np.ndarray, float]:
+    """Cell-centred lattice with ``counts[a]`` points along axis ``a``.
+
+    Point ``(i+1/2)*dx`` along each axis, moved by ``gamma*dx`` with
+    ``gamma ~ U[-jitter, jitter]`` drawn per point and per axis.  Returns
+    ``(x[N][d], dx_nominal)`` where ``dx_nominal`` is the spacing of axis 0.
+    Points are ordered with axis 0 fastest.
+    """
+    d = len(counts)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    dxs = (hi - lo) / np.asarray(counts, dtype=np.float64)
+    axes = [lo[a] + (np.arange(counts[a]) + 0.5) * dxs[a] for a in range(d)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    # axis 0 fastest
+    x = np.stack([g.transpose(*reversed(range(d))).reshape(-1) for g in grids], axis=1)
+    if jitter > 0.0:
+        g = rng(seed).uniform(-jitter, jitter, size=x.shape)
+        x = x + g * dxs[None, :]
+    return np.ascontiguousarray(x, dtype=np.float64), float(dxs[0])
+
+
+def poisson_disk(lo: Sequence[float], hi: Sequence[float], r: float, seed: int,
+                 k: int = 30) -> np.ndarray:
+    """Maximal Poisson-disk sample of the 2D box by Bridson's algorithm (2007).
+
+    Every pair of points is at least ``r`` apart; candidates are drawn in the
+    annulus ``[r, 2r]`` around active points, ``k`` tries each.
+    """
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    g = rng(seed)
+    cs = r / math.sqrt(2.0)
+    nx = int(math.ceil((hi[0] - lo[0]) / cs))
+    ny = int(math.ceil((hi[1] - lo[1]) / cs))
+    grid = -np.ones((nx, ny), dtype=np.int64)
+    pts: list[tuple[float, float]] = []
+
+    def cell_of(p):
+        return (min(nx - 1, int((p[0] - lo[0]) / cs)), min(ny - 1, int((p[1] - lo[1]) / cs)))
+
+    def ok(p):
+        if not (lo[0] <= p[0] < hi[0] and lo[1] <= p[1] < hi[1]):
+            return False
+        ci, cj = cell_of(p)
+        for a in range(max(0, ci - 2), min(nx, ci + 3)):
+            for b in range(max(0, cj - 2), min(ny, cj + 3)):
+                q = grid[a, b]
+                if q >= 0:
+                    dx = pts[q][0] - p[0]
+                    dy = pts[q][1] - p[1]
+                    if dx * dx + dy * dy < r * r:
+                        return False
+        return True
+
+    p0 = (lo[0] + g.uniform() * (hi[0] - lo[0]), lo[1] + g.uniform() * (hi[1] - lo[1]))
+    pts.append(p0)
+    grid[cell_of(p0)] = 0
+    active = [0]
+    while active:
+        ai = int(g.integers(len(active)))
+        base = pts[active[ai]]
+        placed = False
+        for _ in range(k):
+            rad = r * (1.0 + g.uniform())
+            th = 2.0 * math.pi * g.uniform()
+            p = (base[0] + rad * math.cos(th), base[1] + rad * math.sin(th))
+            if ok(p):
+                pts.append(p)
+                grid[cell_of(p)] = len(pts) - 1
+                active.append(len(pts) - 1)
+                placed = True
+                break
+        if not placed:
+            active[ai] = active[-1]
+            active.pop()
+    return np.asarray(pts, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Closed-form problem data
+# ---------------------------------------------------------------------------
+
+def mms_sin_psi(x: np.ndarray, omega: np.ndarray, t: float) -> np.ndarray:
+    """Manufactured angular flux psi = sin(pi x) sin(pi y) (1 + mu/2) e^{-t}, mu = Omega_x.
+
+    Returns ``[N][M]``.  Vanishes on the boundary of the unit square, so the
+    inflow data is zero.
+    """
+    s = np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])
+    return (s[:, None] * (1.0 + 0.5 * omega[None, :, 0])) * math.exp(-t)
+
+
+def mms_sin_source(x: np.ndarray, omega: np.ndarray, t: float, sigma_t: float,
+                   sigma_s: float) -> np.ndarray:
+    """Source q that makes ``mms_sin_psi`` solve the continuous transport equation.
+
+    q = d_t psi + Omega . grad psi + sigma_t psi - sigma_s/(4 pi) phi with
+    phi = 4 pi sin(pi x) sin(pi y) e^{-t} (the mu term integrates to zero).
+    """
+    sx, sy = np.sin(np.pi * x[:, 0]), np.sin(np.pi * x[:, 1])
+    cx, cy = np.cos(np.pi * x[:, 0]), np.cos(np.pi * x[:, 1])
+    s = sx * sy
+    gx, gy = np.pi * cx * sy, np.pi * sx * cy
+    mu = omega[None, :, 0]
+    ang = 1.0 + 0.5 * mu
+    odg = omega[None, :, 0] * gx[:, None] + omega[None, :, 1] * gy[:, None]
+    e = math.exp(-t)
+    q = (-s[:, None] * ang + odg * ang + sigma_t * s[:, None] * ang - sigma_s * s[:, None]) * e
+    return q
+
+
+def mms_sin_phi(x: np.ndarray, t: float) -> np.ndarray:
+    return 4.0 * np.pi * np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]) * math.exp(-t)
+
+
+def gaussian_source(x: np.ndarray, center: Sequence[float], s: float) -> np.ndarray:
+    """Isotropic per-steradian source of unit total emission: a Gaussian of std ``s``."""
+    d = x.shape[1]
+    r2 = np.sum((x - np.asarray(center)[None, :]) ** 2, axis=1)
+    norm = (2.0 * np.pi) ** (d / 2.0) * s ** d * 4.0 * np.pi
+    return np.exp(-r2 / (2.0 * s * s)) / norm
+
+
+def absorber_psi(x: np.ndarray, mu: float, sigma_t: float) -> np.ndarray:
+    """Plane-wave solution exp(-sigma_t x / mu) of Omega.grad psi + sigma_t psi = 0 (mu = Omega_x > 0)."""
+    return np.exp(-sigma_t * x[:, 0] / mu)
+
+
+# ---------------------------------------------------------------------------
+# Workload definitions
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    dim: int
+    lo: tuple
+    hi: tuple
+    counts: Optional[tuple]          # lattice counts, or None for Poisson-disk
+    jitter: float
+    radius_factor: float             # support radius R = factor * dx_nominal
+    rk_order: int
+    n_ord: int                       # ordinates
+    ord_kind: str                    # "product" | "beam-dense"
+    sigma_t: tuple                   # per material
+    sigma_s: tuple
+    regions: tuple                   # ((lo), (hi), mat) boxes, last match wins
+    steps: int                       # 0 => steady
+    dt: float
+    c: float
+    source: str                      # "uniform" | "mms-sin" | "gaussian" | "none"
+    inflow: str                      # "vacuum" | "beam"
+    seed: int
+    pd_radius: float = 0.0           # Poisson-disk spacing when counts is None
+
+    @property
+    def inv_c_dt(self) -> float:
+        return 0.0 if self.steps == 0 else 1.0 / (self.c * self.dt)
+
+
+def config(k: int, scale: Optional[int] = None) -> Workload:
+    """The five workloads (k = 1..5).  ``scale`` replaces the lattice count per
+    axis, for the small and mid-size parity variants of the same problem."""
+    if k == 1:
+        n = scale or 32
+        return Workload("2d-lattice-steady-q1", 2, (0.0, 0.0), (1.0, 1.0), (n, n), 0.2, 2.0, 1,
+                        16, "product", (1.0,), (0.5,), (), 0, 0.0, 1.0, "uniform", "vacuum",
+                        SEED_BASE + 1)
+    if k == 2:
+        n = scale or 128
+        return Workload("2d-mms-be20", 2, (0.0, 0.0), (1.0, 1.0), (n, n), 0.2, 2.0, 1,
+                        64, "product", (1.0,), (0.5,), (), 20, 1e-2, 1.0, "mms-sin", "vacuum",
+                        SEED_BASE + 2)
+    if k == 3:
+        n = scale or 40
+        return Workload("3d-gauss-steady", 3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (n, n, n), 0.2, 2.5, 2,
+                        96, "product", (1.0,), (0.9,), (), 0, 0.0, 1.0, "gaussian", "vacuum",
+                        SEED_BASE + 3)
+    if k == 4:
+        return Workload("2d-beam-void-opaque", 2, (0.0, 0.0), (2.0, 1.0), None, 0.0, 2.0, 1,
+                        256, "beam-dense", (1e-4, 100.0), (0.0, 99.0),
+                        (((1.0, 0.0), (2.0, 1.0), 1),), 10, 0.05, 1.0, "none", "beam",
+                        SEED_BASE + 4, pd_radius=0.0046)
+    raise ValueError(k)
+
+
+def points_for(w: Workload) -> tuple[np.ndarray, float]:
+    if w.counts is not None:
+        return jittered_lattice(w.counts, w.lo, w.hi, w.jitter, w.seed)
+    x = poisson_disk(w.lo, w.hi, w.pd_radius, w.seed)
+    area = float(np.prod(np.asarray(w.hi) - np.asarray(w.lo)))
+    return x, math.sqrt(area / x.shape[0])
+
+
+def radii_for(w: Workload, x: np.ndarray, dx: float) -> np.ndarray:
+    return np.full(x.shape[0], w.radius_factor * dx, dtype=np.float64)
+
+
+def source_values(w: Workload, x: np.ndarray, omega: np.ndarray, t: float) -> np.ndarray:
+    """Per-steradian source point values q_m(x_i) as ``[N][M]``."""
+    m = omega.shape[0]
+    if w.source == "uniform":
+        return np.ones((x.shape[0], m))
+    if w.source == "mms-sin":
+        return mms_sin_source(x, omega, t, w.sigma_t[0], w.sigma_s[0])
+    if w.source == "gaussian":
+        g = gaussian_source(x, (0.5,) * w.dim, 0.05)
+        return np.repeat(g[:, None], m, axis=1)
+    if w.source == "none":
+        return np.zeros((x.shape[0], m))
+    raise ValueError(w.source)
+
+
+def initial_psi(w: Workload, x: np.ndarray, omega: np.ndarray) -> np.ndarray:
+    if w.source == "mms-sin":
+        return mms_sin_psi(x, omega, 0.0)
+    return np.zeros((x.shape[0], omega.shape[0]))
+
+
+def inflow_values(w: Workload, y: np.ndarray, omega: np.ndarray) -> np.ndarray:
+    """Incoming angular flux psi_b at boundary points ``y[nb][d]`` for each ordinate: ``[nb][M]``.
+
+    Beam: psi_b = 1 on the face x = 0 where |y - 1/2| < 0.05, for ordinates
+    within 10 degrees of +x; 0 elsewhere.
+    """
+    nb, m = y.shape[0], omega.shape[0]
+    if w.inflow == "vacuum":
+        return np.zeros((nb, m))
+    if w.inflow == "beam":
+        on = (np.abs(y[:, 0] - w.lo[0]) < 1e-12) & (np.abs(y[:, 1] - 0.5) < 0.05)
+        ang = np.arctan2(omega[:, 1], omega[:, 0])
+        win = (np.abs(ang) <= math.radians(10.0) + 1e-12) & (omega[:, 0] > 0)
+        return (on[:, None] & win[None, :]).astype(np.float64)
+    raise ValueError(w.inflow)
