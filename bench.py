@@ -1,0 +1,147 @@
+"""Benchmark of the MLPG transport hot path on one MI355X.
+
+Workload (the 2D manufactured-solution problem): 128 x 128 jittered lattice
+on the unit square, linear RK with support radius 2h, 64 ordinates, sigma_t
+= 1, sigma_s = 0.5, psi = sin(pi x) sin(pi y)(1 + mu/2) e^{-t}, 20
+backward-Euler steps of dt = 0.01 with c = 1, FP64.  One timed step is the
+whole path: neighbour lists, cells, integration, assembly and the 20
+time steps (each: first-flight solve, outer GMRES on Phi with inner
+batched GMRES, recovery solve).  Inputs (points, sources for every time
+level, initial state) are resident in HBM before timing starts.
+
+Metric: DOF x ordinate x Krylov-iteration per second = N * (Arnoldi steps
+summed over ordinates and solves) / time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=None, help="lattice points per axis (default 128)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-ordinates", type=int, default=0, help="ordinates in the CPU sample (0: one per thread)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
+                                   "this build (the angular sharding design is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+
+    torch.cuda.set_device(0)
+    mlpg.lib()
+    w = W.config(2, args.scale)
+    x, dx = W.points_for(w)
+    R = W.radii_for(w, x, dx)
+    n = x.shape[0]
+    om, wq = mlpg.mlpg_angular_quadrature(2, w.n_ord)
+    M = om.shape[0]
+    # resident inputs
+    qs = [torch.from_numpy(np.ascontiguousarray(W.source_values(w, x, om, (s + 1) * w.dt))).cuda()
+          for s in range(w.steps)]
+    psi0 = torch.from_numpy(np.ascontiguousarray(W.initial_psi(w, x, om))).cuda()
+    tau = torch.full((n,), dx, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def one_step():
+        P = GpuProblem(x, R, w.lo, w.hi)
+        P.integrate(w.rk_order)
+        P.assemble(om, wq, list(w.sigma_t), list(w.sigma_s), w.inv_c_dt, tau)
+        P.set_state(psi0)
+        its = 0
+        sweeps = 0
+        outer = 0
+        phi = pv = None
+        for s in range(w.steps):
+            phi, pv, _, info = P.step(qs[s], None, None, want_psi=False)
+            its += info["inner_iters"]
+            sweeps += info["inner_sweeps"]
+            outer += info["outer_iters"]
+        P.close()
+        return its, sweeps, outer, pv
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_its = tot_sw = tot_out = 0
+    pv = None
+    for _ in range(args.steps):
+        its, sw, out, pv = one_step()
+        tot_its += its
+        tot_sw += sw
+        tot_out += out
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el / max(args.steps, 1) * 1e3
+    value = n * tot_its / el
+    ex = W.mms_sin_phi(x, w.steps * w.dt)
+    err = float(np.abs(pv.cpu().numpy() - ex).sum() / ex.sum())
+
+    rec = {
+        "metric": "DOF*ordinate*Krylov-iter/s", "value": value, "unit": "DOF*ord*iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"2d-mms-be20: {int(math.sqrt(n))}^2 jittered lattice, linear RK, R=2h, "
+                               f"{M} ordinates, 20 BE steps dt=0.01", "points": n, "ordinates": M,
+                   "be_steps": w.steps},
+        "detail": {"inner_iters_per_step": tot_its / max(args.steps, 1),
+                   "batched_sweeps_per_step": tot_sw / max(args.steps, 1),
+                   "outer_iters_per_step": tot_out / max(args.steps, 1),
+                   "direction_solves_per_s": None,
+                   "rel_l1_phi_vs_manufactured": err},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(w, x, R, dx, om, wq, k):
+    """The oracle on a bounded sample of the same workload: the first-flight
+    inner solves L_m^-1 F of the first backward-Euler step for the first k
+    ordinates (one per host thread by default)."""
+    import oracle
+    g = oracle.geometry(x, R, w.lo, w.hi)
+    it = oracle.integrate(g, w.rk_order)
+    tr = oracle.Transport(it, om, wq, w.sigma_t[0], w.sigma_s[0], w.inv_c_dt, dx)
+    psi0 = W.initial_psi(w, x, om)
+    F = tr.rhs(psi0, W.source_values(w, x, om, w.dt), None)
+    th = oracle.num_threads()
+    k = k or min(om.shape[0], th)
+    t0 = time.perf_counter()
+    _, its, _ = tr.inner_solve(F, 0, k)
+    el = time.perf_counter() - t0
+    return {"value": x.shape[0] * its / el, "unit": "DOF*ord*iter/s", "cores": th, "kind": "oracle",
+            "sample": f"first-flight inner GMRES solves of BE step 1, ordinates 0..{k - 1} of {om.shape[0]}, "
+                      f"full {x.shape[0]}-point problem ({its} Arnoldi steps in {el:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * mlpg.h - C ABI of libmlpg.so, a gfx950 (MI355X) implementation of the hot
+ * path of the meshless-local Petrov-Galerkin (MLPG) discrete-ordinates
+ * transport method of Bassett & Owen, "Meshless discretization of the
+ * discrete-ordinates transport equation with integration based on Voronoi
+ * cells" (arXiv 2008.02205).
+ *
+ * The four stage calls follow the paper's statement of the problem:
+ *   mlpg_geometry   Sec. 3.1 (Voronoi-like cells) and Sec. 3.4 (connectivity)
+ *   mlpg_integrate  Sec. 2.2 (RK functions), Sec. 3.2 and Alg. 1 (integration)
+ *   mlpg_assemble   Sec. 4.1 (Eq. weak-transport: cross sections, ordinates, dt)
+ *   mlpg_solve      Sec. 4.2 (Eq. krylov-operator: source, inflow; one step)
+ *
+ * Conventions for every call:
+ *   - Pointers named "device" are HIP device pointers on the current device;
+ *     "host" pointers are ordinary host memory.  Inputs are read during the
+ *     call (or, for device inputs, by work enqueued on `stream` before the call
+ *     returns) and are not retained.  Outputs are written by work enqueued on
+ *     `stream`; synchronise the stream before reading them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Arrays of per-point, per-ordinate values are [n][n_ord] with the
+ *     ordinate index fastest.  Points keep the caller's order.
+ *   - The handle owns every device allocation it makes (hipMalloc); they are
+ *     released by mlpg_destroy.  A handle is not thread-safe; separate
+ *     handles may be used concurrently on separate streams.
+ *   - Every call returns MLPG_OK (0) or a negative mlpg_status.  Arguments are
+ *     validated on the host before anything is enqueued; the message of the
+ *     last failure on the calling thread is returned by mlpg_last_error().
+ */
+#ifndef MLPG_H
+#define MLPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mlpg_problem *mlpg_handle;
+
+typedef enum {
+    MLPG_OK = 0,
+    MLPG_ERR_ARG = -1,            /* invalid argument (checked before any launch) */
+    MLPG_ERR_HIP = -2,            /* a HIP runtime call failed */
+    MLPG_ERR_CAPACITY = -3,       /* a fixed per-cell or per-point capacity was exceeded */
+    MLPG_ERR_NOT_CONVERGED = -4,  /* a Krylov solve hit its iteration limit */
+    MLPG_ERR_GEOMETRY = -5,       /* a cell came out empty or a moment matrix stayed singular */
+    MLPG_ERR_STATE = -7           /* stage called out of order */
+} mlpg_status;
+
+enum { MLPG_FP64 = 0, MLPG_MIXED = 1 };
+enum { MLPG_QUAD_PRODUCT = 0, MLPG_QUAD_BEAM_DENSE = 1 };
+enum { MLPG_OP_L = 0, MLPG_OP_T = 1, MLPG_OP_MS = 2, MLPG_OP_SRC = 3 };
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *mlpg_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Angular quadrature (Sec. 4.1: ordinates Omega_m and weights w_m with
+ * sum_m w_m = 4 pi).  Host-only.
+ *   dim = 2, kind = MLPG_QUAD_PRODUCT: two polar levels (the positive roots
+ *     of the 4-point Gauss-Legendre rule, weights doubled for the folded
+ *     lower hemisphere) times n_ord/2 azimuths phi_k = (2k-1) pi / (n_ord/2).
+ *   dim = 3, kind = MLPG_QUAD_PRODUCT: 6-point Gauss-Legendre in Omega_z
+ *     times n_ord/6 azimuths.
+ *   dim = 2, kind = MLPG_QUAD_BEAM_DENSE, n_ord = 256: two polar levels times
+ *     128 azimuthal sectors, 41 uniform sectors in |phi| <= 10 degrees and 87
+ *     over the rest, ordinates at sector midpoints (a fixed stand-in for the
+ *     locally refined rule of Sec. 4.3).
+ * Order: polar level outer (increasing cosine), azimuth inner (increasing).
+ * omega: host [n_ord][dim] out; w: host [n_ord] out.
+ * ---------------------------------------------------------------------- */
+int mlpg_angular_quadrature(int dim, int n_ord, int kind, double *omega, double *w);
+
+/* ------------------------------------------------------------------------
+ * Overlap connectivity (Sec. 3.4, Eq. mlpg-connectivity): j != i is a
+ * neighbour of i when |x_i - x_j| <= R_i + R_j.  Lists are in increasing j.
+ * Two calls: count fills nbr_off (device [n+1], exclusive prefix sums) and
+ * returns the total in *total (host; the call synchronises `stream`); fill
+ * then writes nbr_idx (device [*total]).
+ *   x: device [n][dim]; R: device [n] support radii (> 0).
+ * ---------------------------------------------------------------------- */
+int mlpg_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *nbr_off,
+                         int64_t *total, void *stream);
+int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *nbr_off,
+                        int32_t *nbr_idx, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Stage 1, geometry (Sec. 3.1, Fig. 1; Sec. 3.4).  Creates a handle.  Each
+ * point gets the convex cell obtained by clipping the box
+ * [x_i - R_i, x_i + R_i]^dim intersected with the domain box by the
+ * half-space on x_i's side of the bisector with every overlap neighbour.
+ * The cells tile the domain (a partition of unity in space) as long as every
+ * cell lies inside its own support, which is checked and reported.
+ *   x: device [n][dim] positions; R: device [n] kernel support radii (the
+ *     cubic spline of smoothing length R/2 vanishes beyond R);
+ *   nbr_off, nbr_idx: device overlap lists as produced by mlpg_neighbors_*;
+ *   dom_lo, dom_hi: host [dim] domain box;
+ *   regions: host boxes [n_regions][dim] with material ids; a point of space
+ *     takes the material of the last box containing it, 0 if none.
+ * dim = 2 only in this release (3D returns MLPG_ERR_ARG).  The call
+ * synchronises `stream` (it sizes the boundary quadrature).  On success
+ * *out owns copies of all inputs.
+ * ---------------------------------------------------------------------- */
+int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R,
+                  const int64_t *nbr_off, const int32_t *nbr_idx, const double *dom_lo,
+                  const double *dom_hi, int n_regions, const double *region_lo, const double *region_hi,
+                  const int32_t *region_mat, void *stream);
+
+typedef struct {
+    int64_t n;               /* points */
+    int dim;
+    int n_mat;               /* 1 + largest material id */
+    int64_t nnz;             /* pattern entries: i and its overlap neighbours per row */
+    int64_t n_bq;            /* boundary quadrature points (after mlpg_geometry) */
+    int64_t oversize_cells;  /* cells reaching beyond their own support radius */
+    int64_t failed_cells;    /* cells with no area or over the vertex capacity */
+    int64_t fallback_qps;    /* quadrature points whose moment matrix needed a lower order */
+    int64_t missing_pairs;   /* co-active pairs absent from the pattern (expected 0) */
+    int n_ord;               /* ordinates after mlpg_assemble, else 0 */
+    int n_blocks;            /* integrated blocks: n_mat(1+dim) + dim^2 + 2 dim */
+} mlpg_info;
+
+/* Sizes and counters; synchronises `stream`-independent state (host only). */
+int mlpg_get_info(mlpg_handle h, mlpg_info *info);
+
+/* Cell volumes V_i: device [n] out. */
+int mlpg_get_volumes(mlpg_handle h, double *V, void *stream);
+
+/* Cell polygons (2D): nv device [n], verts device [n][cap][2], tags device
+ * [n][cap] with tag >= 0 the neighbour index of a bisector edge and
+ * tag = -1 - f an edge on domain face f (0:-x 1:+x 2:-y 3:+y).  cap is
+ * returned by mlpg_cell_capacity. */
+int mlpg_cell_capacity(void);
+int mlpg_get_cells(mlpg_handle h, int32_t *nv, double *verts, int32_t *tags, void *stream);
+
+/* Boundary quadrature points of the domain faces (App. A surface map), in
+ * the order the inflow data psi_b of mlpg_solve must follow:
+ *   y: device [n_bq][dim]; face: device [n_bq] (0:-x 1:+x 2:-y 3:+y ...). */
+int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Stage 2, integration (Sec. 2.2; Sec. 3.2 and Alg. 1; App. A).  At every
+ * quadrature point of every cell (fan triangles from the generator, the
+ * 25-point conical-product rule; 5-point Gauss-Legendre on boundary edges)
+ * the RK functions N_j = V_j U_j of order rk_order (0, 1, 2) and their
+ * gradients are formed from the moment matrix (batched Cholesky in FP64,
+ * falling back one order at a time when a pivot is below 1e-6 of the largest
+ * diagonal entry) and accumulated into direction-independent blocks over the
+ * overlap pattern:
+ *   Mass_g = <N_i,N_j>, D^a_g = <d^a N_i, N_j> per material g,
+ *   K^ab = <d^a N_i, d^b N_j>, S_f = (N_i,N_j) on domain face f.
+ * Also forms the point-value matrix E_ij = N_j(x_i) (Eq. flux-expansion).
+ * ---------------------------------------------------------------------- */
+int mlpg_integrate(mlpg_handle h, int rk_order, void *stream);
+
+/* Pattern and blocks for parity checks.  row_off: device [n+1]; col: device
+ * [nnz]; blocks: device [n_blocks][nnz] in the order
+ *   for g: Mass_g, D^0_g .. D^{dim-1}_g;  K^ab (a-major);  S_0 .. S_{2dim-1};
+ * E: device [nnz]. */
+int mlpg_get_pattern(mlpg_handle h, int64_t *row_off, int32_t *col, void *stream);
+int mlpg_get_blocks(mlpg_handle h, double *blocks, double *E, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Stage 3, assembly (Sec. 4.1, Eq. weak-transport; Sec. 4.2 operators).
+ * Combines the blocks with the cross sections, a0 = 1/(c dt) (0 = steady)
+ * and the SUPG lengths tau_i into per-ordinate-combinable value streams:
+ *   L_m = sum_g (a0 + sigma_t,g) Mass_g
+ *       + sum_a W^a [(a0 tau_i - 1) D^a + tau_i sum_g sigma_t,g D^a_g]
+ *       + tau_i sum_ab W^a W^b K^ab + sum_f max(0, W.n_f) S_f,   W = Omega_m
+ *   T_m = a0 (Mass + tau_i W.D),   MS_m = (1/4pi) sum_g sigma_s,g (Mass_g + tau_i W.D_g)
+ * and the point-Jacobi diagonal of every L_m.
+ *   omega: host [n_ord][dim]; w: host [n_ord]; sigma_t, sigma_s: host [n_mat];
+ *   tau: device [n] SUPG lengths (Sec. 4.1: about the point spacing);
+ *   precision: MLPG_FP64 (FP64 values) or MLPG_MIXED (adds FP32 copies used
+ *     by the FP32 inner solver inside FP64 refinement).
+ * May be called again with new cross sections, dt or ordinates.
+ * ---------------------------------------------------------------------- */
+int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w, int n_mat,
+                  const double *sigma_t, const double *sigma_s, double inv_c_dt, const double *tau,
+                  int precision, void *stream);
+
+/* One operator application Y = op X for all ordinates (parity accessor):
+ * which = MLPG_OP_L, MLPG_OP_T, MLPG_OP_MS or MLPG_OP_SRC (Mass + tau W.D);
+ * X, Y: device [n][n_ord]. */
+int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Stage 4, one backward-Euler step (Sec. 4.1) or a steady solve (a0 = 0),
+ * by the Krylov iteration of Sec. 4.2:
+ *   b_psi = L^-1 (T Psi^{n-1} + r),  b_phi = D b_psi,
+ *   (I - D L^-1 MS) Phi = b_phi by GMRES from the previous Phi,
+ *   Psi = L^-1 MS Phi + b_psi,
+ * with r = (N_i, |W.n| psi_b)_{W.n<0} + <N_i, q_m> + tau_i W.<dN_i, q_m>,
+ * q expanded in the RK basis from its point values.  Every L_m^-1 is a
+ * restarted GMRES with right point-Jacobi preconditioning, all ordinates
+ * advanced together.  Psi^{n-1} is the handle's state (zero until
+ * mlpg_set_state); on return the state holds the new Psi and Phi.
+ *   q: device [n][n_ord] source point values (per steradian);
+ *   psi_b: device [n_bq][n_ord] inflow values at mlpg_boundary_points, or NULL (vacuum);
+ *   phi_coef: device [n] out, Phi; phi_point: device [n] out, phi(x_i) (may be NULL);
+ *   psi_out: device [n][n_ord] out, Psi (may be NULL);
+ *   opts: host, NULL for defaults; info: host out, may be NULL.
+ * The call synchronises `stream` at Krylov convergence checks.  Returns
+ * MLPG_ERR_NOT_CONVERGED (with outputs written) when a limit was hit.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double tol_inner;     /* ||f - L_m x|| <= tol ||f|| per ordinate (default 1e-13) */
+    double tol_outer;     /* outer relative residual (default 1e-12) */
+    int restart_inner;    /* GMRES restart length, <= 30 (default 30) */
+    int restart_outer;    /* <= 30 (default 30) */
+    int max_inner;        /* Arnoldi steps per ordinate per solve (default 3000) */
+    int max_outer;        /* (default 500) */
+    int check_every;      /* Arnoldi steps between host convergence checks (default 4) */
+} mlpg_solve_opts;
+
+typedef struct {
+    int outer_iters;
+    int inner_solves;            /* batched L^-1 applications */
+    int64_t inner_iters;         /* Arnoldi steps summed over ordinates and solves */
+    int64_t inner_sweeps;        /* batched Arnoldi steps (one SpMV over all ordinates each) */
+    double outer_res;            /* final outer relative residual */
+    double inner_res_max;        /* largest final inner relative residual */
+    int converged;               /* 1 if every solve met its tolerance */
+} mlpg_solve_info;
+
+void mlpg_default_opts(mlpg_solve_opts *o);
+int mlpg_set_state(mlpg_handle h, const double *psi, void *stream);
+int mlpg_get_state(mlpg_handle h, double *psi, double *phi, void *stream);
+int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_coef, double *phi_point,
+               double *psi_out, const mlpg_solve_opts *opts, mlpg_solve_info *info, void *stream);
+
+/* Point values out[i] = sum_j N_j(x_i) coef[j] (Eq. flux-expansion);
+ * coef, out: device [n]. */
+int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stream);
+
+/* Releases the handle and all its device memory (NULL is ignored). */
+void mlpg_destroy(mlpg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLPG_H */

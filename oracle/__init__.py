@@ -97,6 +97,8 @@ def _declare(L):
     L.orc_rhs.argtypes = [C.POINTER(OpCtx), _dp, _dp, _dp, _dp]
     L.orc_point_values.restype = None
     L.orc_point_values.argtypes = [C.c_int64, _i64p, _i32p, _dp, _dp, C.c_int, _dp]
+    L.orc_Linv_range.restype = C.c_int64
+    L.orc_Linv_range.argtypes = [C.POINTER(OpCtx), _dp, _dp, C.c_int, C.c_int, _dp]
     L.orc_num_threads.restype = C.c_int
     L.orc_num_threads.argtypes = []
 
@@ -456,6 +458,14 @@ class Transport:
         lib().orc_rhs(C.byref(self.ctx), _p(None if psi_prev is None else _f64(psi_prev)), _p(_f64(q)),
                       _p(None if psib is None else _f64(psib)), _p(F))
         return F
+
+    def inner_solve(self, F, m0=0, m1=None):
+        """L_m^-1 F for ordinates m0..m1-1; returns (X, Arnoldi steps summed, max relative residual)."""
+        m1 = self.M if m1 is None else m1
+        X = np.zeros((self.it.geom.n, self.M))
+        rm = np.zeros(1)
+        its = lib().orc_Linv_range(C.byref(self.ctx), _p(_f64(F)), _p(X), m0, m1, _p(rm))
+        return X, int(its), float(rm[0])
 
     def step(self, psi_prev, q, psib=None, phi0=None):
         """One backward-Euler step (or the steady solve when 1/(c dt) = 0)."""

@@ -280,11 +280,13 @@ static void chol_solve(int b, double L[][ORC_MAXB], const double *rhs, double *o
  * whose kernel might cover y; those with W_j(y) = 0 get N = dN = 0.  The
  * monomials are taken in the scaled argument z = (y - x_j) / hs; this
  * diagonal change of basis leaves U_j unchanged and only improves the
- * conditioning of M.  Output N_j = V_j U_j and dN_j = V_j grad U_j.  When the
- * Cholesky pivot test fails the order drops by one and the evaluation is
- * repeated (reading for the singular case the paper leaves open).  Returns
- * the order used, or -1 when even order 0 fails (no kernel covers y).      */
-#define ORC_PIVOT_TOL 1e-12
+ * conditioning of M.  Output N_j = V_j U_j and dN_j = V_j grad U_j.  When a
+ * Cholesky pivot of M falls below 1e-6 of the largest diagonal entry, the
+ * order drops by one and the evaluation is repeated (reading for the singular
+ * case the paper leaves open; the bound keeps the condition number of M near
+ * 1e6 so that the RK functions stay accurate to about 1e-10).  Returns the
+ * order used, or -1 when even order 0 fails (no kernel covers y).          */
+#define ORC_PIVOT_TOL 1e-6
 
 static int rk_eval_act(int dim, int order, const double *y, int nc, const int32_t *cand, const double *x,
                        const double *R, const double *V, double hs, double *N, double *dN, unsigned char *act)
@@ -1017,6 +1019,28 @@ void orc_apply(op_ctx *o, int which, const double *X, double *Y)
         for (int64_t i = 0; i < n; ++i) Y[i * M + m] = y[i];
         free(x); free(y);
     }
+}
+
+/* L_m^-1 for the ordinates m0 <= m < m1 only (used to time a bounded
+ * sample of the inner solves).  Returns the Arnoldi steps summed over them. */
+int64_t orc_Linv_range(op_ctx *o, const double *F, double *X, int m0, int m1, double *res_max)
+{
+    int M = o->n_ord;
+    int64_t n = o->n;
+    int64_t its_sum = 0;
+    double rm = 0.0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : its_sum) reduction(max : rm)
+    for (int m = m0; m < m1; ++m) {
+        double *f = (double *)malloc(sizeof(double) * n), *x = (double *)malloc(sizeof(double) * n);
+        for (int64_t i = 0; i < n; ++i) f[i] = F[i * M + m];
+        double res;
+        its_sum += gmres_L(o, m, f, x, &res);
+        if (res > rm) rm = res;
+        for (int64_t i = 0; i < n; ++i) X[i * M + m] = x[i];
+        free(f); free(x);
+    }
+    *res_max = rm;
+    return its_sum;
 }
 
 /* Right-hand side F = T Psi^{n-1} + r alone. */

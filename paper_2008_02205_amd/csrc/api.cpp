@@ -1,0 +1,568 @@
+// C ABI of libmlpg (declared in include/mlpg.h): argument validation, the
+// problem handle, stage sequencing and the Krylov solve of one step.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mlpg {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+void Problem::release()
+{
+    reg_lo.release(); reg_hi.release(); reg_mat.release(); x.release(); R.release(); nb_off.release();
+    nb_idx.release(); nv.release(); tags.release(); verts.release(); V.release(); rho.release(); bq_off.release();
+    bq_y.release(); bq_w.release(); bq_N.release(); bq_face.release(); bq_nact.release(); bq_act.release();
+    row_off.release(); diag_pos.release(); col.release(); blocks.release(); E.release(); counters.release();
+    wq.release(); omega.release(); sL.release(); sMD.release(); sMS.release(); coefL.release(); coefMD.release();
+    coefF.release(); surf_off.release(); surf_col.release(); surf_val.release(); dinv.release(); psi.release();
+    phi.release(); F.release(); bpsi.release(); t1.release(); t2.release(); bphi.release(); ovec.release();
+    inner.release(); outer.release();
+}
+
+namespace {
+
+hipStream_t S(void *s) { return (hipStream_t)s; }
+
+int op_L(Problem &P, const double *in, const double *dinv, double *out, hipStream_t s, void *)
+{
+    SpmvArgs a;
+    a.vals = P.sL.p; a.ns = P.nsL; a.coef = P.coefL.p; a.x = in; a.dinv = dinv; a.surface = 1; a.y = out;
+    MLPG_HIP(launch_spmv(P, a, s));
+    return MLPG_OK;
+}
+
+struct SolveCounters {
+    const mlpg_solve_opts *o;
+    int64_t its = 0, sweeps = 0;
+    double res_max = 0.0;
+    bool conv = true;
+    int solves = 0;
+};
+
+int inner_solve(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
+{
+    c.solves++;
+    return gmres_batched(P, P.inner, op_L, nullptr, P.dinv.p, f, x, P.n, P.n_ord, c.o->tol_inner, c.o->restart_inner,
+                         c.o->max_inner, c.o->check_every, true, s, &c.its, &c.sweeps, &c.res_max, &c.conv);
+}
+
+// A phi = phi - D L^-1 MS phi  (Eq. krylov-operator)
+int op_outer(Problem &P, const double *in, const double *, double *out, hipStream_t s, void *vctx)
+{
+    SolveCounters &c = *(SolveCounters *)vctx;
+    SpmvArgs a;
+    a.vals = P.sMS.p; a.ns = P.nsMD; a.coef = P.coefMD.p; a.x = in; a.x_bcast = 1; a.y = P.t1.p;
+    MLPG_HIP(launch_spmv(P, a, s));
+    int rc = inner_solve(P, c, P.t1.p, P.t2.p, s);
+    if (rc) return rc;
+    MLPG_HIP(launch_ord_reduce(P, P.t2.p, out, in, -1.0, s));
+    return MLPG_OK;
+}
+
+int check_stage(mlpg_handle h, int need, const char *who)
+{
+    if (!h) {
+        set_error(std::string(who) + ": null handle");
+        return MLPG_ERR_ARG;
+    }
+    Problem *P = (Problem *)h;
+    if (P->stage < need) {
+        set_error(std::string(who) + ": called before the preceding stage");
+        return MLPG_ERR_STATE;
+    }
+    return MLPG_OK;
+}
+
+}  // namespace
+}  // namespace mlpg
+
+using namespace mlpg;
+
+struct mlpg_problem : public Problem {};
+
+extern "C" {
+
+const char *mlpg_last_error(void) { return g_err.c_str(); }
+
+int mlpg_cell_capacity(void) { return kCellCap2D; }
+
+int mlpg_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *nbr_off, int64_t *total,
+                         void *stream)
+{
+    MLPG_CHECK(dim == 2 || dim == 3, MLPG_ERR_ARG, "mlpg_neighbors_count: dim must be 2 or 3");
+    MLPG_CHECK(n > 0 && n < (int64_t)1 << 31, MLPG_ERR_ARG, "mlpg_neighbors_count: n out of range");
+    MLPG_CHECK(x && R && nbr_off && total, MLPG_ERR_ARG, "mlpg_neighbors_count: null pointer");
+    hipStream_t s = S(stream);
+    DevBuf<int64_t> cnt;
+    MLPG_HIP(cnt.alloc(n));
+    MLPG_HIP(launch_neighbors_count(dim, n, x, R, cnt.p, s));
+    MLPG_HIP(launch_exclusive_scan(cnt.p, nbr_off, n, s));
+    MLPG_HIP(hipMemcpyAsync(total, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MLPG_HIP(hipStreamSynchronize(s));
+    cnt.release();
+    return MLPG_OK;
+}
+
+int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *nbr_off,
+                        int32_t *nbr_idx, void *stream)
+{
+    MLPG_CHECK(dim == 2 || dim == 3, MLPG_ERR_ARG, "mlpg_neighbors_fill: dim must be 2 or 3");
+    MLPG_CHECK(n > 0 && x && R && nbr_off && nbr_idx, MLPG_ERR_ARG, "mlpg_neighbors_fill: bad argument");
+    MLPG_HIP(launch_neighbors_fill(dim, n, x, R, nbr_off, nbr_idx, S(stream)));
+    return MLPG_OK;
+}
+
+int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R, const int64_t *nbr_off,
+                  const int32_t *nbr_idx, const double *dom_lo, const double *dom_hi, int n_regions,
+                  const double *region_lo, const double *region_hi, const int32_t *region_mat, void *stream)
+{
+    MLPG_CHECK(out, MLPG_ERR_ARG, "mlpg_geometry: null output handle");
+    *out = nullptr;
+    MLPG_CHECK(dim == 2, MLPG_ERR_ARG, "mlpg_geometry: only dim = 2 is implemented");
+    MLPG_CHECK(n > 0 && n < (int64_t)1 << 31, MLPG_ERR_ARG, "mlpg_geometry: n out of range");
+    MLPG_CHECK(x && R && nbr_off && nbr_idx && dom_lo && dom_hi, MLPG_ERR_ARG, "mlpg_geometry: null pointer");
+    for (int a = 0; a < dim; ++a)
+        MLPG_CHECK(dom_hi[a] > dom_lo[a], MLPG_ERR_ARG, "mlpg_geometry: empty domain box");
+    MLPG_CHECK(n_regions >= 0 && n_regions <= 64, MLPG_ERR_ARG, "mlpg_geometry: n_regions must be in [0, 64]");
+    MLPG_CHECK(n_regions == 0 || (region_lo && region_hi && region_mat), MLPG_ERR_ARG,
+               "mlpg_geometry: null region arrays");
+    int n_mat = 1;
+    for (int r = 0; r < n_regions; ++r) {
+        MLPG_CHECK(region_mat[r] >= 0 && region_mat[r] < 8, MLPG_ERR_ARG, "mlpg_geometry: material id in [0, 8)");
+        n_mat = std::max(n_mat, region_mat[r] + 1);
+    }
+    hipStream_t s = S(stream);
+    mlpg_problem *P = new mlpg_problem();
+    auto fail = [&](int code) {
+        P->release();
+        delete P;
+        return code;
+    };
+    P->dim = dim;
+    P->n = n;
+    P->n_mat = n_mat;
+    for (int a = 0; a < dim; ++a) { P->dom_lo[a] = dom_lo[a]; P->dom_hi[a] = dom_hi[a]; }
+    P->n_regions = n_regions;
+#define TRY(call)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));          \
+            return fail(MLPG_ERR_HIP);                                             \
+        }                                                                          \
+    } while (0)
+    TRY(P->reg_lo.alloc(std::max(1, n_regions) * dim));
+    TRY(P->reg_hi.alloc(std::max(1, n_regions) * dim));
+    TRY(P->reg_mat.alloc(std::max(1, n_regions)));
+    if (n_regions) {
+        TRY(hipMemcpyAsync(P->reg_lo.p, region_lo, sizeof(double) * n_regions * dim, hipMemcpyHostToDevice, s));
+        TRY(hipMemcpyAsync(P->reg_hi.p, region_hi, sizeof(double) * n_regions * dim, hipMemcpyHostToDevice, s));
+        TRY(hipMemcpyAsync(P->reg_mat.p, region_mat, sizeof(int32_t) * n_regions, hipMemcpyHostToDevice, s));
+    }
+    int64_t nnz_nb = 0;
+    TRY(hipMemcpyAsync(&nnz_nb, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    if (nnz_nb < 0 || nnz_nb > ((int64_t)1 << 40)) {
+        set_error("mlpg_geometry: neighbour list size out of range");
+        return fail(MLPG_ERR_ARG);
+    }
+    P->nnz_nb = nnz_nb;
+    TRY(P->x.alloc(n * dim));
+    TRY(P->R.alloc(n));
+    TRY(P->nb_off.alloc(n + 1));
+    TRY(P->nb_idx.alloc(std::max<int64_t>(1, nnz_nb)));
+    TRY(hipMemcpyAsync(P->x.p, x, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
+    TRY(hipMemcpyAsync(P->R.p, R, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    TRY(hipMemcpyAsync(P->nb_off.p, nbr_off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz_nb) TRY(hipMemcpyAsync(P->nb_idx.p, nbr_idx, sizeof(int32_t) * nnz_nb, hipMemcpyDeviceToDevice, s));
+
+    TRY(P->nv.alloc(n));
+    TRY(P->tags.alloc(n * kCellCap2D));
+    TRY(P->verts.alloc(n * kCellCap2D * 2));
+    TRY(P->V.alloc(n));
+    TRY(P->rho.alloc(n));
+    DevBuf<int32_t> flags;
+    DevBuf<int64_t> bqc;
+    TRY(flags.alloc(n));
+    TRY(bqc.alloc(n));
+    TRY(P->bq_off.alloc(n + 1));
+    TRY(launch_clip2d(*P, s, flags.p, bqc.p));
+    TRY(launch_exclusive_scan(bqc.p, P->bq_off.p, n, s));
+    std::vector<int32_t> hf(n);
+    TRY(hipMemcpyAsync(hf.data(), flags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(&P->n_bq, P->bq_off.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    flags.release();
+    bqc.release();
+    for (int64_t i = 0; i < n; ++i) {
+        if (hf[i] == 1) P->failed++;
+        if (hf[i] == 2) P->oversize++;
+    }
+    if (P->failed) {
+        set_error("mlpg_geometry: " + std::to_string(P->failed) + " cells empty or over the vertex capacity");
+        return fail(MLPG_ERR_GEOMETRY);
+    }
+    P->nnz = nnz_nb + n;
+    TRY(P->row_off.alloc(n + 1));
+    TRY(P->col.alloc(P->nnz));
+    TRY(P->diag_pos.alloc(n));
+    TRY(launch_pattern(*P, s));
+    int64_t nbq = std::max<int64_t>(1, P->n_bq);
+    TRY(P->bq_y.alloc(nbq * dim));
+    TRY(P->bq_w.alloc(nbq));
+    TRY(P->bq_face.alloc(nbq));
+    TRY(P->bq_nact.alloc(nbq));
+    TRY(P->bq_act.alloc(nbq * kBqAct));
+    TRY(P->bq_N.alloc(nbq * kBqAct));
+    TRY(P->counters.alloc(kNumCounters));
+    TRY(hipStreamSynchronize(s));
+#undef TRY
+    P->stage = 1;
+    *out = P;
+    return MLPG_OK;
+}
+
+int mlpg_get_info(mlpg_handle h, mlpg_info *info)
+{
+    int rc = check_stage(h, 1, "mlpg_get_info");
+    if (rc) return rc;
+    MLPG_CHECK(info, MLPG_ERR_ARG, "mlpg_get_info: null info");
+    Problem *P = h;
+    info->n = P->n;
+    info->dim = P->dim;
+    info->n_mat = P->n_mat;
+    info->nnz = P->nnz;
+    info->n_bq = P->n_bq;
+    info->oversize_cells = P->oversize;
+    info->failed_cells = P->failed;
+    info->fallback_qps = P->fallbacks;
+    info->missing_pairs = P->missing;
+    info->n_ord = P->stage >= 3 ? P->n_ord : 0;
+    info->n_blocks = P->n_mat * (1 + P->dim) + P->dim * P->dim + 2 * P->dim;
+    return MLPG_OK;
+}
+
+int mlpg_get_volumes(mlpg_handle h, double *V, void *stream)
+{
+    int rc = check_stage(h, 1, "mlpg_get_volumes");
+    if (rc) return rc;
+    MLPG_CHECK(V, MLPG_ERR_ARG, "mlpg_get_volumes: null output");
+    MLPG_HIP(hipMemcpyAsync(V, h->V.p, sizeof(double) * h->n, hipMemcpyDeviceToDevice, S(stream)));
+    return MLPG_OK;
+}
+
+int mlpg_get_cells(mlpg_handle h, int32_t *nv, double *verts, int32_t *tags, void *stream)
+{
+    int rc = check_stage(h, 1, "mlpg_get_cells");
+    if (rc) return rc;
+    MLPG_CHECK(nv && verts && tags, MLPG_ERR_ARG, "mlpg_get_cells: null output");
+    hipStream_t s = S(stream);
+    MLPG_HIP(hipMemcpyAsync(nv, h->nv.p, sizeof(int32_t) * h->n, hipMemcpyDeviceToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(verts, h->verts.p, sizeof(double) * h->n * kCellCap2D * 2, hipMemcpyDeviceToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(tags, h->tags.p, sizeof(int32_t) * h->n * kCellCap2D, hipMemcpyDeviceToDevice, s));
+    return MLPG_OK;
+}
+
+int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream)
+{
+    int rc = check_stage(h, 2, "mlpg_boundary_points");
+    if (rc) return rc;
+    MLPG_CHECK(y && face, MLPG_ERR_ARG, "mlpg_boundary_points: null output");
+    if (h->n_bq == 0) return MLPG_OK;
+    hipStream_t s = S(stream);
+    MLPG_HIP(hipMemcpyAsync(y, h->bq_y.p, sizeof(double) * h->n_bq * h->dim, hipMemcpyDeviceToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(face, h->bq_face.p, sizeof(int32_t) * h->n_bq, hipMemcpyDeviceToDevice, s));
+    return MLPG_OK;
+}
+
+int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
+{
+    int rc = check_stage(h, 1, "mlpg_integrate");
+    if (rc) return rc;
+    MLPG_CHECK(rk_order >= 0 && rk_order <= 2, MLPG_ERR_ARG, "mlpg_integrate: rk_order must be 0, 1 or 2");
+    Problem *P = h;
+    hipStream_t s = S(stream);
+    P->rk_order = rk_order;
+    P->n_blocks = P->n_mat * (1 + P->dim) + P->dim * P->dim + 2 * P->dim;
+    MLPG_HIP(P->blocks.alloc((size_t)P->n_blocks * P->nnz));
+    MLPG_HIP(P->E.alloc(P->nnz));
+    MLPG_HIP(hipMemsetAsync(P->blocks.p, 0, sizeof(double) * P->n_blocks * P->nnz, s));
+    MLPG_HIP(hipMemsetAsync(P->E.p, 0, sizeof(double) * P->nnz, s));
+    MLPG_HIP(hipMemsetAsync(P->counters.p, 0, sizeof(unsigned long long) * kNumCounters, s));
+    MLPG_HIP(hipMemsetAsync(P->bq_nact.p, 0, sizeof(int32_t) * std::max<int64_t>(1, P->n_bq), s));
+    hipError_t e = launch_integrate2d(*P, s);
+    if (e == hipErrorInvalidValue) {
+        set_error("mlpg_integrate: a cell has more candidate functions (" + std::to_string(P->cand_max) +
+                  ") than the per-cell capacity");
+        return MLPG_ERR_CAPACITY;
+    }
+    MLPG_HIP(e);
+    unsigned long long cnt[kNumCounters];
+    MLPG_HIP(hipMemcpyAsync(cnt, P->counters.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    MLPG_HIP(hipStreamSynchronize(s));
+    P->fallbacks = (int64_t)cnt[kFallbacks];
+    P->missing = (int64_t)cnt[kMissing];
+    MLPG_CHECK(cnt[kOverflow] == 0, MLPG_ERR_CAPACITY, "mlpg_integrate: per-cell or per-point capacity exceeded");
+    P->stage = 2;
+    return MLPG_OK;
+}
+
+int mlpg_get_pattern(mlpg_handle h, int64_t *row_off, int32_t *col, void *stream)
+{
+    int rc = check_stage(h, 1, "mlpg_get_pattern");
+    if (rc) return rc;
+    MLPG_CHECK(row_off && col, MLPG_ERR_ARG, "mlpg_get_pattern: null output");
+    hipStream_t s = S(stream);
+    MLPG_HIP(hipMemcpyAsync(row_off, h->row_off.p, sizeof(int64_t) * (h->n + 1), hipMemcpyDeviceToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(col, h->col.p, sizeof(int32_t) * h->nnz, hipMemcpyDeviceToDevice, s));
+    return MLPG_OK;
+}
+
+int mlpg_get_blocks(mlpg_handle h, double *blocks, double *E, void *stream)
+{
+    int rc = check_stage(h, 2, "mlpg_get_blocks");
+    if (rc) return rc;
+    hipStream_t s = S(stream);
+    if (blocks)
+        MLPG_HIP(hipMemcpyAsync(blocks, h->blocks.p, sizeof(double) * h->n_blocks * h->nnz, hipMemcpyDeviceToDevice,
+                                s));
+    if (E) MLPG_HIP(hipMemcpyAsync(E, h->E.p, sizeof(double) * h->nnz, hipMemcpyDeviceToDevice, s));
+    return MLPG_OK;
+}
+
+int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w, int n_mat, const double *sigma_t,
+                  const double *sigma_s, double inv_c_dt, const double *tau, int precision, void *stream)
+{
+    int rc = check_stage(h, 2, "mlpg_assemble");
+    if (rc) return rc;
+    Problem *P = h;
+    MLPG_CHECK(n_ord >= 1 && n_ord <= 1024, MLPG_ERR_ARG, "mlpg_assemble: n_ord must be in [1, 1024]");
+    MLPG_CHECK(omega && w && sigma_t && sigma_s && tau, MLPG_ERR_ARG, "mlpg_assemble: null pointer");
+    MLPG_CHECK(n_mat >= P->n_mat && n_mat <= 8, MLPG_ERR_ARG,
+               "mlpg_assemble: n_mat must cover every material of the regions (and be <= 8)");
+    MLPG_CHECK(inv_c_dt >= 0.0 && std::isfinite(inv_c_dt), MLPG_ERR_ARG, "mlpg_assemble: 1/(c dt) must be >= 0");
+    MLPG_CHECK(precision == MLPG_FP64, MLPG_ERR_ARG, "mlpg_assemble: only MLPG_FP64 is implemented");
+    for (int g = 0; g < n_mat; ++g)
+        MLPG_CHECK(sigma_t[g] >= 0.0 && sigma_s[g] >= 0.0 && sigma_s[g] <= sigma_t[g], MLPG_ERR_ARG,
+                   "mlpg_assemble: need 0 <= sigma_s <= sigma_t");
+    hipStream_t s = S(stream);
+    const int d = P->dim;
+    P->n_ord = n_ord;
+    P->a0 = inv_c_dt;
+    P->precision = precision;
+    P->nsL = 1 + d + d * (d + 1) / 2;
+    P->nsMD = 1 + d;
+    P->nfaces = 2 * d;
+    P->omega_h.assign(omega, omega + (size_t)n_ord * d);
+    P->w_h.assign(w, w + n_ord);
+    MLPG_HIP(P->sL.alloc((size_t)P->nnz * P->nsL));
+    MLPG_HIP(P->sMD.alloc((size_t)P->nnz * P->nsMD));
+    MLPG_HIP(P->sMS.alloc((size_t)P->nnz * P->nsMD));
+    MLPG_HIP(launch_assemble(*P, sigma_t, sigma_s, tau, s));
+    // per-ordinate coefficient tables
+    std::vector<double> cL((size_t)n_ord * P->nsL), cMD((size_t)n_ord * P->nsMD), cF((size_t)n_ord * P->nfaces);
+    for (int m = 0; m < n_ord; ++m) {
+        const double *W = omega + (size_t)m * d;
+        double *l = &cL[(size_t)m * P->nsL];
+        int k = 0;
+        l[k++] = 1.0;
+        for (int a = 0; a < d; ++a) l[k++] = W[a];
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b) l[k++] = W[a] * W[b];
+        cMD[(size_t)m * P->nsMD] = 1.0;
+        for (int a = 0; a < d; ++a) cMD[(size_t)m * P->nsMD + 1 + a] = W[a];
+        for (int f = 0; f < P->nfaces; ++f) {
+            double wn = ((f & 1) ? 1.0 : -1.0) * W[f >> 1];
+            cF[(size_t)m * P->nfaces + f] = wn > 0.0 ? wn : 0.0;
+        }
+    }
+    MLPG_HIP(P->coefL.alloc(cL.size()));
+    MLPG_HIP(P->coefMD.alloc(cMD.size()));
+    MLPG_HIP(P->coefF.alloc(cF.size()));
+    MLPG_HIP(P->omega.alloc((size_t)n_ord * d));
+    MLPG_HIP(P->wq.alloc(n_ord));
+    MLPG_HIP(hipMemcpyAsync(P->coefL.p, cL.data(), sizeof(double) * cL.size(), hipMemcpyHostToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(P->coefMD.p, cMD.data(), sizeof(double) * cMD.size(), hipMemcpyHostToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(P->coefF.p, cF.data(), sizeof(double) * cF.size(), hipMemcpyHostToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(P->omega.p, omega, sizeof(double) * n_ord * d, hipMemcpyHostToDevice, s));
+    MLPG_HIP(hipMemcpyAsync(P->wq.p, w, sizeof(double) * n_ord, hipMemcpyHostToDevice, s));
+    // surface rows
+    DevBuf<int64_t> cnt;
+    MLPG_HIP(cnt.alloc(P->n));
+    MLPG_HIP(P->surf_off.alloc(P->n + 1));
+    MLPG_HIP(launch_surface_count(*P, cnt.p, s));
+    MLPG_HIP(launch_exclusive_scan(cnt.p, P->surf_off.p, P->n, s));
+    MLPG_HIP(hipMemcpyAsync(&P->nnz_s, P->surf_off.p + P->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MLPG_HIP(hipStreamSynchronize(s));
+    cnt.release();
+    MLPG_HIP(P->surf_col.alloc(std::max<int64_t>(1, P->nnz_s)));
+    MLPG_HIP(P->surf_val.alloc(std::max<int64_t>(1, P->nnz_s) * P->nfaces));
+    MLPG_HIP(launch_surface_fill(*P, nullptr, s));
+    MLPG_HIP(P->dinv.alloc((size_t)P->n * n_ord));
+    MLPG_HIP(launch_jacobi(*P, s));
+    // state and scratch
+    size_t nm = (size_t)P->n * n_ord;
+    bool fresh = P->psi.count != nm;
+    MLPG_HIP(P->psi.alloc(nm));
+    MLPG_HIP(P->F.alloc(nm));
+    MLPG_HIP(P->bpsi.alloc(nm));
+    MLPG_HIP(P->t1.alloc(nm));
+    MLPG_HIP(P->t2.alloc(nm));
+    MLPG_HIP(P->phi.alloc(P->n));
+    MLPG_HIP(P->bphi.alloc(P->n));
+    MLPG_HIP(P->ovec.alloc(P->n));
+    if (fresh) {
+        MLPG_HIP(hipMemsetAsync(P->psi.p, 0, sizeof(double) * nm, s));
+        MLPG_HIP(hipMemsetAsync(P->phi.p, 0, sizeof(double) * P->n, s));
+    }
+    MLPG_HIP(hipGetLastError());
+    P->stage = 3;
+    return MLPG_OK;
+}
+
+int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *stream)
+{
+    int rc = check_stage(h, 3, "mlpg_apply");
+    if (rc) return rc;
+    MLPG_CHECK(X && Y, MLPG_ERR_ARG, "mlpg_apply: null pointer");
+    Problem *P = h;
+    SpmvArgs a;
+    a.x = X;
+    a.y = Y;
+    switch (which) {
+    case MLPG_OP_L: a.vals = P->sL.p; a.ns = P->nsL; a.coef = P->coefL.p; a.surface = 1; break;
+    case MLPG_OP_T: a.vals = P->sMD.p; a.ns = P->nsMD; a.coef = P->coefMD.p; a.xs = P->a0; break;
+    case MLPG_OP_MS: a.vals = P->sMS.p; a.ns = P->nsMD; a.coef = P->coefMD.p; break;
+    case MLPG_OP_SRC: a.vals = P->sMD.p; a.ns = P->nsMD; a.coef = P->coefMD.p; break;
+    default: set_error("mlpg_apply: unknown operator"); return MLPG_ERR_ARG;
+    }
+    MLPG_HIP(launch_spmv(*P, a, S(stream)));
+    return MLPG_OK;
+}
+
+void mlpg_default_opts(mlpg_solve_opts *o)
+{
+    if (!o) return;
+    o->tol_inner = 1e-13;
+    o->tol_outer = 1e-12;
+    o->restart_inner = 30;
+    o->restart_outer = 30;
+    o->max_inner = 3000;
+    o->max_outer = 500;
+    o->check_every = 4;
+}
+
+int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)
+{
+    int rc = check_stage(h, 3, "mlpg_set_state");
+    if (rc) return rc;
+    MLPG_CHECK(psi, MLPG_ERR_ARG, "mlpg_set_state: null psi");
+    Problem *P = h;
+    hipStream_t s = S(stream);
+    MLPG_HIP(hipMemcpyAsync(P->psi.p, psi, sizeof(double) * P->n * P->n_ord, hipMemcpyDeviceToDevice, s));
+    MLPG_HIP(launch_ord_reduce(*P, P->psi.p, P->phi.p, nullptr, 1.0, s));
+    return MLPG_OK;
+}
+
+int mlpg_get_state(mlpg_handle h, double *psi, double *phi, void *stream)
+{
+    int rc = check_stage(h, 3, "mlpg_get_state");
+    if (rc) return rc;
+    Problem *P = h;
+    hipStream_t s = S(stream);
+    if (psi) MLPG_HIP(hipMemcpyAsync(psi, P->psi.p, sizeof(double) * P->n * P->n_ord, hipMemcpyDeviceToDevice, s));
+    if (phi) MLPG_HIP(hipMemcpyAsync(phi, P->phi.p, sizeof(double) * P->n, hipMemcpyDeviceToDevice, s));
+    return MLPG_OK;
+}
+
+int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stream)
+{
+    int rc = check_stage(h, 2, "mlpg_point_values");
+    if (rc) return rc;
+    MLPG_CHECK(coef && out, MLPG_ERR_ARG, "mlpg_point_values: null pointer");
+    MLPG_HIP(launch_point_values(*h, coef, out, S(stream)));
+    return MLPG_OK;
+}
+
+int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_coef, double *phi_point,
+               double *psi_out, const mlpg_solve_opts *opts, mlpg_solve_info *info, void *stream)
+{
+    int rc = check_stage(h, 3, "mlpg_solve");
+    if (rc) return rc;
+    MLPG_CHECK(q && phi_coef, MLPG_ERR_ARG, "mlpg_solve: q and phi_coef are required");
+    mlpg_solve_opts o;
+    mlpg_default_opts(&o);
+    if (opts) o = *opts;
+    MLPG_CHECK(o.tol_inner > 0 && o.tol_outer > 0, MLPG_ERR_ARG, "mlpg_solve: tolerances must be positive");
+    MLPG_CHECK(o.restart_inner >= 1 && o.restart_inner <= kMaxRestart && o.restart_outer >= 1 &&
+                   o.restart_outer <= kMaxRestart,
+               MLPG_ERR_ARG, "mlpg_solve: restart lengths must be in [1, 30]");
+    MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1, MLPG_ERR_ARG,
+               "mlpg_solve: iteration limits must be positive");
+    Problem *P = h;
+    hipStream_t s = S(stream);
+    const int64_t n = P->n;
+    const int M = P->n_ord;
+    SolveCounters c;
+    c.o = &o;
+    // F = (Mass + tau W.D)(a0 Psi^{n-1} + q) + inflow term   (T Psi^{n-1} + r)
+    {
+        SpmvArgs a;
+        a.vals = P->sMD.p; a.ns = P->nsMD; a.coef = P->coefMD.p; a.x = P->psi.p; a.xs = P->a0; a.x2 = q;
+        a.y = P->F.p;
+        MLPG_HIP(launch_spmv(*P, a, s));
+        if (psi_b) MLPG_HIP(launch_boundary_rhs(*P, psi_b, P->F.p, s));
+    }
+    // b_psi = L^-1 F, b_phi = D b_psi
+    rc = inner_solve(*P, c, P->F.p, P->bpsi.p, s);
+    if (rc) return rc;
+    MLPG_HIP(launch_ord_reduce(*P, P->bpsi.p, P->bphi.p, nullptr, 1.0, s));
+    // outer GMRES on (I - D L^-1 MS) Phi = b_phi from the previous Phi
+    int64_t oits = 0, osweeps = 0;
+    double ores = 0.0;
+    bool oconv = true;
+    rc = gmres_batched(*P, P->outer, op_outer, &c, nullptr, P->bphi.p, P->phi.p, n, 1, o.tol_outer, o.restart_outer,
+                       std::max(1, o.max_outer), 1, false, s, &oits, &osweeps, &ores, &oconv);
+    if (rc) return rc;
+    // recovery Psi = L^-1 MS Phi + b_psi
+    {
+        SpmvArgs a;
+        a.vals = P->sMS.p; a.ns = P->nsMD; a.coef = P->coefMD.p; a.x = P->phi.p; a.x_bcast = 1; a.y = P->t1.p;
+        MLPG_HIP(launch_spmv(*P, a, s));
+    }
+    rc = inner_solve(*P, c, P->t1.p, P->t2.p, s);
+    if (rc) return rc;
+    MLPG_HIP(launch_add(P->psi.p, P->t2.p, P->bpsi.p, n * M, s));
+    MLPG_HIP(hipMemcpyAsync(phi_coef, P->phi.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (phi_point) MLPG_HIP(launch_point_values(*P, P->phi.p, phi_point, s));
+    if (psi_out) MLPG_HIP(hipMemcpyAsync(psi_out, P->psi.p, sizeof(double) * n * M, hipMemcpyDeviceToDevice, s));
+    if (info) {
+        info->outer_iters = (int)oits;
+        info->inner_solves = c.solves;
+        info->inner_iters = c.its;
+        info->inner_sweeps = c.sweeps;
+        info->outer_res = ores;
+        info->inner_res_max = c.res_max;
+        info->converged = (c.conv && oconv) ? 1 : 0;
+    }
+    if (!(c.conv && oconv)) {
+        set_error("mlpg_solve: a Krylov solve reached its iteration limit");
+        return MLPG_ERR_NOT_CONVERGED;
+    }
+    return MLPG_OK;
+}
+
+void mlpg_destroy(mlpg_handle h)
+{
+    if (!h) return;
+    h->release();
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,570 @@
+// Meshless integration on gfx950 (Sec. 2.2, Sec. 3.2, Alg. 1, App. A).
+//
+// One workgroup per cell.  The functions that can be nonzero on the cell
+// (the cell's generator and the overlap neighbours whose support reaches the
+// cell) are staged in LDS.  Each thread takes quadrature points of the fan
+// triangles, evaluates the moment matrix M = sum_j V_j P P^T W_j and its
+// gradient, factors M by Cholesky in FP64 (dropping one order while a pivot
+// is below 1e-6 of the largest diagonal entry), forms C = M^-1 e0 and
+// dC = -M^-1 dM C, and adds w N_a N_b, w dN_a N_b and w dN_a dN_b for every
+// pair of functions active at the point into an LDS Gram tile with LDS FP64
+// atomics.  The tile is then scattered into the global CSR blocks with one
+// FP64 atomic per pair and block.  When the Gram tile of a cell would not
+// fit in LDS, the pair rows are split into tiles and the points revisited.
+#include "internal.hpp"
+
+namespace mlpg {
+
+__constant__ double c_tri_pts[kTriRule][2];
+__constant__ double c_tri_w[kTriRule];
+__constant__ double c_seg_pts[kSegRule];
+__constant__ double c_seg_w[kSegRule];
+
+hipError_t upload_rules(hipStream_t s)
+{
+    const Rules &r = rules();
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tri_pts), r.tri_pts, sizeof(r.tri_pts), 0,
+                                          hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tri_w), r.tri_w, sizeof(r.tri_w), 0, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_seg_pts), r.seg_pts, sizeof(r.seg_pts), 0, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_seg_w), r.seg_w, sizeof(r.seg_w), 0, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int ORD>
+struct Basis2 {
+    static constexpr int B = ORD == 0 ? 1 : (ORD == 1 ? 3 : 6);
+};
+
+__host__ __device__ constexpr int bsize2(int o) { return o == 0 ? 1 : (o == 1 ? 3 : 6); }
+
+// Cubic B-spline in q = |r| / h, h = R/2: returns W and the factor W'(q)/q
+// so that grad W = (W'(q)/q) r / h^2.  Support q < 2.
+__device__ __forceinline__ double spline(double r2, double h, double *dfac)
+{
+    double q = sqrt(r2) / h;
+    if (q < 1.0) {
+        *dfac = (-3.0 + 2.25 * q) / (h * h);
+        return 1.0 - 1.5 * q * q + 0.75 * q * q * q;
+    }
+    if (q < 2.0) {
+        double t = 2.0 - q;
+        *dfac = (-0.75 * t * t / q) / (h * h);
+        return 0.25 * t * t * t;
+    }
+    *dfac = 0.0;
+    return 0.0;
+}
+
+// Monomials of degree <= ORD in z (2D): [1, z0, z1, z0^2, z0 z1, z1^2] and
+// their z-derivatives.
+template <int ORD>
+__device__ __forceinline__ void basis2(double z0, double z1, double *P, double *D0, double *D1)
+{
+    P[0] = 1.0; D0[0] = 0.0; D1[0] = 0.0;
+    if (ORD >= 1) {
+        P[1] = z0; D0[1] = 1.0; D1[1] = 0.0;
+        P[2] = z1; D0[2] = 0.0; D1[2] = 1.0;
+    }
+    if (ORD >= 2) {
+        P[3] = z0 * z0; D0[3] = 2.0 * z0; D1[3] = 0.0;
+        P[4] = z0 * z1; D0[4] = z1;       D1[4] = z0;
+        P[5] = z1 * z1; D0[5] = 0.0;      D1[5] = 2.0 * z1;
+    }
+}
+
+// Cholesky of the leading b x b block of M (B x B storage) with the pivot
+// test; solves for C = M^-1 e0 and dC_g = -M^-1 dM_g C.  Returns false when a
+// pivot fails.
+template <int B>
+__device__ __forceinline__ bool chol_solve(int b, const double (&M)[B][B], const double (&dM0)[B][B],
+                                           const double (&dM1)[B][B], double (&C)[B], double (&dC0)[B],
+                                           double (&dC1)[B])
+{
+    double L[B][B];
+    double dmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+        if (k < b) dmax = fmax(dmax, M[k][k]);
+    if (!(dmax > 0.0)) return false;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        if (k >= b) break;
+        double s = M[k][k];
+#pragma unroll
+        for (int p = 0; p < B; ++p)
+            if (p < k) s -= L[k][p] * L[k][p];
+        if (!(s > 1e-6 * dmax)) return false;
+        L[k][k] = sqrt(s);
+        double inv = 1.0 / L[k][k];
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            if (r <= k || r >= b) continue;
+            double t = M[r][k];
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+                if (p < k) t -= L[r][p] * L[k][p];
+            L[r][k] = t * inv;
+        }
+    }
+    auto solve = [&](const double (&rhs)[B], double (&out)[B]) {
+        double t[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            if (k >= b) { t[k] = 0.0; continue; }
+            double s = rhs[k];
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+                if (p < k) s -= L[k][p] * t[p];
+            t[k] = s / L[k][k];
+        }
+#pragma unroll
+        for (int k = B - 1; k >= 0; --k) {
+            if (k >= b) { out[k] = 0.0; continue; }
+            double s = t[k];
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+                if (p > k && p < b) s -= L[p][k] * out[p];
+            out[k] = s / L[k][k];
+        }
+    };
+    double e0[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) e0[k] = (k == 0) ? 1.0 : 0.0;
+    solve(e0, C);
+    double r0[B], r1[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+            if (r < b && q < b) {
+                s0 += dM0[r][q] * C[q];
+                s1 += dM1[r][q] * C[q];
+            }
+        r0[r] = -s0;
+        r1[r] = -s1;
+    }
+    solve(r0, dC0);
+    solve(r1, dC1);
+    return true;
+}
+
+// RK correction at point y from the staged candidates.  Returns the order
+// used (-1: no function covers y) and the bitmask of active candidates.
+template <int ORD>
+__device__ int rk_prepare(double y0, double y1, int A, const double *sx, const double *sR, const double *sV, double hs,
+                          double (&C)[Basis2<ORD>::B], double (&dC0)[Basis2<ORD>::B],
+                          double (&dC1)[Basis2<ORD>::B], uint64_t *mask)
+{
+    constexpr int B = Basis2<ORD>::B;
+    double M[B][B], dM0[B][B], dM1[B][B];
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int s = 0; s < B; ++s) { M[r][s] = 0.0; dM0[r][s] = 0.0; dM1[r][s] = 0.0; }
+    uint64_t act = 0;
+    const double ihs = 1.0 / hs;
+    for (int a = 0; a < A; ++a) {
+        double r0 = y0 - sx[2 * a], r1 = y1 - sx[2 * a + 1];
+        double h = 0.5 * sR[a];
+        double r2 = r0 * r0 + r1 * r1;
+        if (!(r2 < 4.0 * h * h)) continue;
+        double dfac;
+        double W = spline(r2, h, &dfac);
+        if (W == 0.0) continue;
+        act |= (1ull << a);
+        double dW0 = dfac * r0, dW1 = dfac * r1;
+        double P[B], D0[B], D1[B];
+        basis2<ORD>(r0 * ihs, r1 * ihs, P, D0, D1);
+        double v = sV[a];
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int s = 0; s < B; ++s) {
+                if (s < r) continue;
+                double pp = P[r] * P[s];
+                M[r][s] += v * pp * W;
+                dM0[r][s] += v * ((D0[r] * P[s] + P[r] * D0[s]) * ihs * W + pp * dW0);
+                dM1[r][s] += v * ((D1[r] * P[s] + P[r] * D1[s]) * ihs * W + pp * dW1);
+            }
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+        for (int s = 0; s < B; ++s)
+            if (s < r) { M[r][s] = M[s][r]; dM0[r][s] = dM0[s][r]; dM1[r][s] = dM1[s][r]; }
+    *mask = act;
+    if (act == 0) return -1;
+#pragma unroll
+    for (int o = ORD; o >= 0; --o) {
+        if (chol_solve<B>(bsize2(o), M, dM0, dM1, C, dC0, dC1)) return o;
+    }
+    return -1;
+}
+
+template <int ORD>
+__device__ __forceinline__ void rk_value(double y0, double y1, int a, const double *sx, const double *sR,
+                                         const double *sV, double hs, const double (&C)[Basis2<ORD>::B],
+                                         const double (&dC0)[Basis2<ORD>::B], const double (&dC1)[Basis2<ORD>::B],
+                                         double *N, double *dN0, double *dN1)
+{
+    constexpr int B = Basis2<ORD>::B;
+    double r0 = y0 - sx[2 * a], r1 = y1 - sx[2 * a + 1];
+    double h = 0.5 * sR[a];
+    double dfac;
+    double W = spline(r0 * r0 + r1 * r1, h, &dfac);
+    double dW0 = dfac * r0, dW1 = dfac * r1;
+    const double ihs = 1.0 / hs;
+    double P[B], D0[B], D1[B];
+    basis2<ORD>(r0 * ihs, r1 * ihs, P, D0, D1);
+    double pc = 0.0, t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        pc += P[r] * C[r];
+        t0 += D0[r] * ihs * C[r] + P[r] * dC0[r];
+        t1 += D1[r] * ihs * C[r] + P[r] * dC1[r];
+    }
+    double v = sV[a];
+    *N = v * pc * W;
+    *dN0 = v * (t0 * W + pc * dW0);
+    *dN1 = v * (t1 * W + pc * dW1);
+}
+
+__device__ __forceinline__ int material_at(double y0, double y1, int nreg, const double *lo, const double *hi,
+                                           const int32_t *mat)
+{
+    int m = 0;
+    for (int r = 0; r < nreg; ++r)
+        if (y0 >= lo[2 * r] && y0 <= hi[2 * r] && y1 >= lo[2 * r + 1] && y1 <= hi[2 * r + 1]) m = mat[r];
+    return m;
+}
+
+__device__ __forceinline__ int64_t find_col(const int64_t *row_off, const int32_t *col, int64_t i, int32_t j)
+{
+    int64_t lo = row_off[i], hi = row_off[i + 1] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) >> 1;
+        int32_t cm = col[mid];
+        if (cm == j) return mid;
+        if (cm < j) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+struct IntegArgs {
+    int64_t n;
+    const double *x, *R, *V, *rho;
+    const int64_t *nb_off;
+    const int32_t *nb_idx;
+    const int32_t *nv;
+    const double *verts;
+    const int32_t *tags;
+    const int64_t *row_off;
+    const int32_t *col;
+    int64_t nnz;
+    int G;
+    int nreg;
+    const double *reg_lo, *reg_hi;
+    const int32_t *reg_mat;
+    double *blocks;
+    double *E;
+    const int64_t *bq_off;
+    double *bq_y, *bq_w, *bq_N;
+    int32_t *bq_face, *bq_nact, *bq_act;
+    unsigned long long *counters;
+    int amax;       // candidate capacity staged in LDS
+    int tile_rows;  // pair rows per Gram tile
+};
+
+// Candidate count per cell (to size LDS).
+__global__ void cand_count_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ R,
+                                  const double *__restrict__ rho, const int64_t *__restrict__ nb_off,
+                                  const int32_t *__restrict__ nb_idx, int32_t *__restrict__ cnt)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double xc0 = x[2 * c], xc1 = x[2 * c + 1], rc = rho[c];
+    int k = 1;
+    for (int64_t p = nb_off[c]; p < nb_off[c + 1]; ++p) {
+        int32_t j = nb_idx[p];
+        double d0 = x[2 * (int64_t)j] - xc0, d1 = x[2 * (int64_t)j + 1] - xc1;
+        double lim = R[j] + rc;
+        if (d0 * d0 + d1 * d1 < lim * lim) k++;
+    }
+    cnt[c] = k;
+}
+
+template <int ORD>
+__global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
+{
+    extern __shared__ double lds[];
+    __shared__ int sA;
+    const int G = g.G;
+    const int NB = 3 * G + 3;
+    const int amax = g.amax;
+    double *sx = lds;
+    double *sR = sx + 2 * amax;
+    double *sV = sR + amax;
+    int32_t *sidx = (int32_t *)(sV + amax);
+    double *gram = sV + amax + (amax + 1) / 2;   // after the int32 indices
+    const int64_t c = blockIdx.x;
+    const double xc0 = g.x[2 * c], xc1 = g.x[2 * c + 1];
+    const double hs = 0.5 * g.R[c];
+    if (threadIdx.x == 0) {
+        int A = 0;
+        double rc = g.rho[c];
+        sidx[A] = (int32_t)c; sx[0] = xc0; sx[1] = xc1; sR[0] = g.R[c]; sV[0] = g.V[c]; A = 1;
+        for (int64_t p = g.nb_off[c]; p < g.nb_off[c + 1]; ++p) {
+            int32_t j = g.nb_idx[p];
+            double d0 = g.x[2 * (int64_t)j] - xc0, d1 = g.x[2 * (int64_t)j + 1] - xc1;
+            double lim = g.R[j] + rc;
+            if (d0 * d0 + d1 * d1 < lim * lim) {
+                if (A >= amax) { A = -1; break; }
+                sidx[A] = j;
+                sx[2 * A] = g.x[2 * (int64_t)j];
+                sx[2 * A + 1] = g.x[2 * (int64_t)j + 1];
+                sR[A] = g.R[j];
+                sV[A] = g.V[j];
+                A++;
+            }
+        }
+        if (A < 0) atomicAdd(&g.counters[kOverflow], 1ull);
+        sA = A;
+    }
+    __syncthreads();
+    const int A = sA;
+    if (A <= 0) return;
+    const int nvc = g.nv[c];
+    const int nq = nvc * kTriRule;
+    const double *cv = g.verts + c * kCellCap2D * 2;
+    constexpr int B = Basis2<ORD>::B;
+
+    for (int a0 = 0; a0 < A; a0 += g.tile_rows) {
+        const int a1 = min(A, a0 + g.tile_rows);
+        const int TR = a1 - a0;
+        const int TT = TR * A;
+        for (int t = threadIdx.x; t < NB * TT; t += kThreads) gram[t] = 0.0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nq; t += kThreads) {
+            int k = t / kTriRule, r = t - k * kTriRule;
+            int kn = (k + 1 == nvc) ? 0 : k + 1;
+            double e10 = cv[2 * k] - xc0, e11 = cv[2 * k + 1] - xc1;
+            double e20 = cv[2 * kn] - xc0, e21 = cv[2 * kn + 1] - xc1;
+            double detJ = e10 * e21 - e11 * e20;
+            if (!(detJ > 0.0)) continue;
+            double y0 = xc0 + e10 * c_tri_pts[r][0] + e20 * c_tri_pts[r][1];
+            double y1 = xc1 + e11 * c_tri_pts[r][0] + e21 * c_tri_pts[r][1];
+            double w = c_tri_w[r] * detJ;
+            double C[B], dC0[B], dC1[B];
+            uint64_t mask;
+            int o = rk_prepare<ORD>(y0, y1, A, sx, sR, sV, hs, C, dC0, dC1, &mask);
+            if (o < 0) continue;
+            if (a0 == 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            int mat = material_at(y0, y1, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
+            uint64_t ma = mask & ((a1 >= 64 ? ~0ull : ((1ull << a1) - 1)) & ~((1ull << a0) - 1));
+            while (ma) {
+                int a = __builtin_ctzll(ma);
+                ma &= ma - 1;
+                double Na, dNa0, dNa1;
+                rk_value<ORD>(y0, y1, a, sx, sR, sV, hs, C, dC0, dC1, &Na, &dNa0, &dNa1);
+                double wa = w * Na, wa0 = w * dNa0, wa1 = w * dNa1;
+                double *gr = gram + (a - a0) * A;
+                uint64_t mb = mask;
+                while (mb) {
+                    int b = __builtin_ctzll(mb);
+                    mb &= mb - 1;
+                    double Nb, dNb0, dNb1;
+                    rk_value<ORD>(y0, y1, b, sx, sR, sV, hs, C, dC0, dC1, &Nb, &dNb0, &dNb1);
+                    atomicAdd(&gr[(3 * mat + 0) * TT + b], wa * Nb);
+                    atomicAdd(&gr[(3 * mat + 1) * TT + b], wa0 * Nb);
+                    atomicAdd(&gr[(3 * mat + 2) * TT + b], wa1 * Nb);
+                    atomicAdd(&gr[(3 * G + 0) * TT + b], wa0 * dNb0);
+                    atomicAdd(&gr[(3 * G + 1) * TT + b], wa0 * dNb1);
+                    atomicAdd(&gr[(3 * G + 2) * TT + b], wa1 * dNb1);
+                }
+            }
+        }
+        __syncthreads();
+        // Scatter the tile.  K^yx[a][b] = K^xy[b][a] is added from the tile
+        // that holds row b of K^xy, i.e. as the transpose of this tile.
+        const int64_t nnz = g.nnz;
+        for (int t = threadIdx.x; t < TT; t += kThreads) {
+            int al = t / A, b = t - al * A;
+            int a = a0 + al;
+            bool nz = false;
+            for (int q = 0; q < NB; ++q) nz |= (gram[q * TT + t] != 0.0);
+            if (!nz) continue;
+            int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+            if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+            for (int m = 0; m < G; ++m)
+                for (int q = 0; q < 3; ++q) {
+                    double v = gram[(3 * m + q) * TT + t];
+                    if (v != 0.0) atomicAdd(&g.blocks[(int64_t)(3 * m + q) * nnz + pos], v);
+                }
+            const int kb = 3 * G;
+            atomicAdd(&g.blocks[(int64_t)(kb + 0) * nnz + pos], gram[(3 * G + 0) * TT + t]);
+            atomicAdd(&g.blocks[(int64_t)(kb + 1) * nnz + pos], gram[(3 * G + 1) * TT + t]);
+            atomicAdd(&g.blocks[(int64_t)(kb + 3) * nnz + pos], gram[(3 * G + 2) * TT + t]);
+            // transpose part: K^yx[b][a] += K^xy[a][b]
+            int64_t pos_t = find_col(g.row_off, g.col, sidx[b], sidx[a]);
+            if (pos_t < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+            atomicAdd(&g.blocks[(int64_t)(kb + 2) * nnz + pos_t], gram[(3 * G + 1) * TT + t]);
+        }
+        __syncthreads();
+    }
+
+    // Boundary edges on domain faces: line rule mapped from [-1, 1] with
+    // K = half the edge length (App. A); surface blocks and the boundary
+    // point table used for the inflow term.
+    int nbe = 0;
+    for (int k = 0; k < nvc; ++k) {
+        int tg = g.tags[c * kCellCap2D + k];
+        if (tg <= -1 && tg >= -4) nbe++;
+    }
+    const int64_t nnz = g.nnz;
+    for (int t = threadIdx.x; t < nbe * kSegRule; t += kThreads) {
+        int e = t / kSegRule, q = t - e * kSegRule;
+        int k = 0, seen = -1;
+        for (k = 0; k < nvc; ++k) {
+            int tg = g.tags[c * kCellCap2D + k];
+            if (tg <= -1 && tg >= -4) {
+                seen++;
+                if (seen == e) break;
+            }
+        }
+        int face = -1 - g.tags[c * kCellCap2D + k];
+        int kn = (k + 1 == nvc) ? 0 : k + 1;
+        double p0 = cv[2 * k], p1 = cv[2 * k + 1], q0 = cv[2 * kn], q1 = cv[2 * kn + 1];
+        double s = 0.5 * (c_seg_pts[q] + 1.0);
+        double y0 = p0 + (q0 - p0) * s, y1 = p1 + (q1 - p1) * s;
+        double len = sqrt((q0 - p0) * (q0 - p0) + (q1 - p1) * (q1 - p1));
+        double w = c_seg_w[q] * 0.5 * len;
+        int64_t bq = g.bq_off[c] + t;
+        g.bq_y[2 * bq] = y0;
+        g.bq_y[2 * bq + 1] = y1;
+        g.bq_face[bq] = face;
+        g.bq_w[bq] = w;
+        double C[B], dC0[B], dC1[B];
+        uint64_t mask;
+        int o = rk_prepare<ORD>(y0, y1, A, sx, sR, sV, hs, C, dC0, dC1, &mask);
+        int na = 0;
+        if (o >= 0) {
+            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            uint64_t ma = mask;
+            while (ma) {
+                int a = __builtin_ctzll(ma);
+                ma &= ma - 1;
+                double Na, d0, d1;
+                rk_value<ORD>(y0, y1, a, sx, sR, sV, hs, C, dC0, dC1, &Na, &d0, &d1);
+                if (na < kBqAct) {
+                    g.bq_act[bq * kBqAct + na] = sidx[a];
+                    g.bq_N[bq * kBqAct + na] = Na;
+                } else {
+                    atomicAdd(&g.counters[kOverflow], 1ull);
+                }
+                na++;
+                uint64_t mb = mask;
+                while (mb) {
+                    int b = __builtin_ctzll(mb);
+                    mb &= mb - 1;
+                    double Nb, e0, e1;
+                    rk_value<ORD>(y0, y1, b, sx, sR, sV, hs, C, dC0, dC1, &Nb, &e0, &e1);
+                    int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+                    if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+                    atomicAdd(&g.blocks[(int64_t)(3 * G + 4 + face) * nnz + pos], w * Na * Nb);
+                }
+            }
+        }
+        g.bq_nact[bq] = na < kBqAct ? na : kBqAct;
+    }
+
+    // Point values at the generator: E[c, j] = N_j(x_c).
+    if (threadIdx.x == 0) {
+        double C[B], dC0[B], dC1[B];
+        uint64_t mask;
+        int o = rk_prepare<ORD>(xc0, xc1, A, sx, sR, sV, hs, C, dC0, dC1, &mask);
+        if (o >= 0) {
+            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            uint64_t ma = mask;
+            while (ma) {
+                int a = __builtin_ctzll(ma);
+                ma &= ma - 1;
+                double Na, d0, d1;
+                rk_value<ORD>(xc0, xc1, a, sx, sR, sV, hs, C, dC0, dC1, &Na, &d0, &d1);
+                int64_t pos = find_col(g.row_off, g.col, (int32_t)c, sidx[a]);
+                if (pos >= 0) g.E[pos] = Na;
+                else atomicAdd(&g.counters[kMissing], 1ull);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_integrate2d(Problem &P, hipStream_t s)
+{
+    // Candidate capacity from the largest candidate set.
+    DevBuf<int32_t> cnt;
+    hipError_t e = cnt.alloc(P.n);
+    if (e != hipSuccess) return e;
+    cand_count_kernel<<<(int)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.x.p, P.R.p, P.rho.p, P.nb_off.p, P.nb_idx.p,
+                                                                 cnt.p);
+    std::vector<int32_t> h(P.n);
+    e = hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cnt.release();
+    if (e != hipSuccess) return e;
+    int amax = 1;
+    for (int32_t v : h) amax = v > amax ? v : amax;
+    P.cand_max = amax;
+    if (amax > kCandMax2D) return hipErrorInvalidValue;   // reported as capacity by the caller
+
+    int dev = 0;
+    int lds_max = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+    const int NB = 3 * P.n_mat + 3;
+    size_t fixed = sizeof(double) * (4 * amax + (amax + 1) / 2) + 64;
+    size_t budget = (lds_max > 0 ? (size_t)lds_max : 65536) - fixed;
+    int tile_rows = (int)(budget / (sizeof(double) * NB * amax));
+    if (tile_rows > amax) tile_rows = amax;
+    if (tile_rows < 1) return hipErrorInvalidValue;
+    size_t shmem = fixed + sizeof(double) * (size_t)NB * tile_rows * amax;
+
+    IntegArgs g;
+    g.n = P.n; g.x = P.x.p; g.R = P.R.p; g.V = P.V.p; g.rho = P.rho.p;
+    g.nb_off = P.nb_off.p; g.nb_idx = P.nb_idx.p; g.nv = P.nv.p; g.verts = P.verts.p; g.tags = P.tags.p;
+    g.row_off = P.row_off.p; g.col = P.col.p; g.nnz = P.nnz; g.G = P.n_mat; g.nreg = P.n_regions;
+    g.reg_lo = P.reg_lo.p; g.reg_hi = P.reg_hi.p; g.reg_mat = P.reg_mat.p; g.blocks = P.blocks.p; g.E = P.E.p;
+    g.bq_off = P.bq_off.p; g.bq_y = P.bq_y.p; g.bq_w = P.bq_w.p; g.bq_N = P.bq_N.p; g.bq_face = P.bq_face.p;
+    g.bq_nact = P.bq_nact.p; g.bq_act = P.bq_act.p; g.counters = P.counters.p; g.amax = amax;
+    g.tile_rows = tile_rows;
+    if ((e = upload_rules(s)) != hipSuccess) return e;
+    dim3 grid((unsigned)P.n);
+    switch (P.rk_order) {
+    case 0:
+        if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
+        integrate2d_kernel<0><<<grid, kThreads, shmem, s>>>(g);
+        break;
+    case 1:
+        if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
+        integrate2d_kernel<1><<<grid, kThreads, shmem, s>>>(g);
+        break;
+    default:
+        if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
+        integrate2d_kernel<2><<<grid, kThreads, shmem, s>>>(g);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mlpg

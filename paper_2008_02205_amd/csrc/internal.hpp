@@ -1,0 +1,223 @@
+// Internal declarations of libmlpg: the problem handle, device buffers and
+// the kernel launchers shared between translation units.  Nothing here is
+// part of the C ABI (include/mlpg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mlpg.h"
+
+namespace mlpg {
+
+constexpr int kCellCap2D = 32;     // polygon vertex capacity of a 2D cell
+constexpr int kSegRule = 5;        // Gauss-Legendre points on a boundary edge
+constexpr int kTriN = 5;           // conical-product order on a triangle (25 points)
+constexpr int kTriRule = kTriN * kTriN;
+constexpr int kBqAct = 32;         // active functions stored per boundary point
+constexpr int kCandMax2D = 64;     // functions possibly active on one 2D cell
+constexpr int kMaxRestart = 30;
+constexpr int kTagBox = -100;      // edge of the kernel box not on the domain
+
+// Thread-local error message for mlpg_last_error.
+void set_error(const std::string &msg);
+
+#define MLPG_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            ::mlpg::set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+            return MLPG_ERR_HIP;                                                          \
+        }                                                                                 \
+    } while (0)
+
+#define MLPG_CHECK(cond, code, msg)                                                       \
+    do {                                                                                  \
+        if (!(cond)) {                                                                    \
+            ::mlpg::set_error(msg);                                                       \
+            return code;                                                                  \
+        }                                                                                 \
+    } while (0)
+
+// Device buffer owned by the handle.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t count = 0;
+    hipError_t alloc(size_t n) {
+        if (n <= count && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+        hipError_t e = hipMalloc(&p, (n ? n : 1) * sizeof(T));
+        if (e == hipSuccess) count = n;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+    }
+};
+
+// Host-side quadrature tables (computed once, uploaded as kernel arguments
+// or constant memory).
+struct Rules {
+    double tri_pts[kTriRule][2];
+    double tri_w[kTriRule];
+    double seg_pts[kSegRule];
+    double seg_w[kSegRule];
+};
+const Rules &rules();
+hipError_t upload_rules(hipStream_t s);   // copies the tables to __constant__ memory
+
+// Gauss-Legendre on [-1,1] and Gauss-Jacobi (weight (1-x)^alpha) on [-1,1].
+void gauss_legendre(int n, double *x, double *w);
+void gauss_jacobi(int n, double alpha, double *x, double *w);
+
+// Counters written by kernels (device, zeroed at each stage that uses them).
+enum Counter { kFallbacks = 0, kMissing = 1, kOverflow = 2, kNumCounters = 4 };
+
+// Batched GMRES workspace for `nb` simultaneous systems of `n` unknowns
+// (ordinates as the fastest index).
+struct Krylov {
+    int64_t n = 0;
+    int nb = 0;
+    int k = 0;
+    DevBuf<double> V;        // [(k+1)][n][nb]
+    DevBuf<double> w;        // [n][nb]
+    DevBuf<double> r;        // [n][nb]
+    DevBuf<double> part;     // [nblk][k+2][nb] block partial sums
+    DevBuf<double> h1, h2;   // [k+1][nb]
+    DevBuf<double> H;        // [nb][k+1][k]
+    DevBuf<double> cs, sn;   // [nb][k]
+    DevBuf<double> g;        // [nb][k+1]
+    DevBuf<double> y;        // [k][nb]
+    DevBuf<double> fnorm;    // [nb]
+    DevBuf<double> beta;     // [nb]
+    DevBuf<double> resid;    // [nb] relative residual of the last cycle
+    DevBuf<int> active;      // [nb] 1 while the system iterates in this cycle
+    DevBuf<int> done;        // [nb] 1 once converged (or out of steps)
+    DevBuf<int> its;         // [nb] Arnoldi steps so far in this solve
+    DevBuf<int> jend;        // [nb] columns built in this cycle
+    DevBuf<int> nactive;     // [1]
+    int *nactive_host = nullptr;   // pinned mirror
+    int part_blocks = 0;
+    hipError_t ensure(int64_t n_, int nb_, int k_);
+    void release();
+};
+
+struct Problem {
+    int dim = 0;
+    int64_t n = 0;
+    int n_mat = 1;
+    double dom_lo[3] = {0, 0, 0}, dom_hi[3] = {0, 0, 0};
+    int n_regions = 0;
+    DevBuf<double> reg_lo, reg_hi;
+    DevBuf<int32_t> reg_mat;
+
+    DevBuf<double> x, R;
+    DevBuf<int64_t> nb_off;
+    DevBuf<int32_t> nb_idx;
+    int64_t nnz_nb = 0;
+
+    // cells
+    DevBuf<int32_t> nv, tags;
+    DevBuf<double> verts, V, rho;
+    int64_t oversize = 0, failed = 0;
+
+    // boundary quadrature
+    int64_t n_bq = 0;
+    DevBuf<int64_t> bq_off;   // [n+1] first boundary point of each cell
+    DevBuf<double> bq_y, bq_w, bq_N;
+    DevBuf<int32_t> bq_face, bq_nact, bq_act;
+
+    // pattern and blocks
+    int64_t nnz = 0;
+    DevBuf<int64_t> row_off, diag_pos;
+    DevBuf<int32_t> col;
+    int n_blocks = 0;
+    int rk_order = -1;
+    DevBuf<double> blocks, E;
+    DevBuf<unsigned long long> counters;
+    int64_t fallbacks = 0, missing = 0;
+    int cand_max = 0;
+
+    // assembled operators
+    int n_ord = 0;
+    int precision = MLPG_FP64;
+    double a0 = 0.0;
+    std::vector<double> omega_h, w_h;
+    DevBuf<double> wq;                    // [M]
+    DevBuf<double> omega;                 // [M][dim]
+    int nsL = 0, nsMD = 0, nfaces = 0;
+    DevBuf<double> sL, sMD, sMS;          // [nnz][nsL], [nnz][1+d], [nnz][1+d]
+    DevBuf<double> coefL, coefMD, coefF;  // [M][nsL], [M][1+d], [M][2d]
+    DevBuf<int64_t> surf_off;             // [n+1]
+    DevBuf<int32_t> surf_col;
+    DevBuf<double> surf_val;              // [nnz_s][2d]
+    int64_t nnz_s = 0;
+    DevBuf<double> dinv;                  // [n][M]
+
+    // state and solver scratch
+    DevBuf<double> psi, phi;              // [n][M], [n]
+    DevBuf<double> F, bpsi, t1, t2;       // [n][M]
+    DevBuf<double> bphi, ovec;            // [n]
+    Krylov inner, outer;
+    int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
+
+    void release();
+};
+
+// ---- kernel launchers -----------------------------------------------------
+hipError_t launch_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *counts,
+                                  hipStream_t s);
+hipError_t launch_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *off,
+                                 int32_t *idx, hipStream_t s);
+hipError_t launch_exclusive_scan(const int64_t *counts, int64_t *off, int64_t n, hipStream_t s);
+
+hipError_t launch_clip2d(Problem &P, hipStream_t s, int32_t *flags, int64_t *bq_count);
+hipError_t launch_pattern(Problem &P, hipStream_t s);
+hipError_t launch_integrate2d(Problem &P, hipStream_t s);
+
+hipError_t launch_assemble(Problem &P, const double *sig_t, const double *sig_s, const double *tau,
+                           hipStream_t s);
+hipError_t launch_surface_count(Problem &P, int64_t *counts, hipStream_t s);
+hipError_t launch_surface_fill(Problem &P, const double *omega_unused, hipStream_t s);
+hipError_t launch_jacobi(Problem &P, hipStream_t s);
+
+// y[i][m] = sum_p (sum_b coef[m][b] vals[p][b]) * xin[col[p]][m]  (+ surface part)
+// with xin = xa*(a_scale) + xb  and optional right preconditioner dinv.
+struct SpmvArgs {
+    const double *vals = nullptr;
+    int ns = 0;
+    const double *coef = nullptr;     // [M][ns]
+    const double *x = nullptr;        // [n][M] or [n] when x_bcast
+    int x_bcast = 0;
+    const double *x2 = nullptr;       // optional second input added: x_eff = xs*x + x2
+    double xs = 1.0;
+    const double *dinv = nullptr;     // optional [n][M] right preconditioner
+    const double *colscale = nullptr; // optional [M] per-ordinate scale of x
+    int surface = 0;                  // add sum_f max(0, W.n_f) S_f
+    double *y = nullptr;
+    const double *yadd = nullptr;     // optional: y = yadd - (A x) when set with ysign=-1
+    int ysign = 1;
+};
+hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s);
+hipError_t launch_point_values(Problem &P, const double *coef, double *out, hipStream_t s);
+hipError_t launch_boundary_rhs(Problem &P, const double *psib, double *F, hipStream_t s);
+hipError_t launch_ord_reduce(Problem &P, const double *X, double *out, const double *base, double sign,
+                             hipStream_t s);
+hipError_t launch_add(double *y, const double *a, const double *b, int64_t count, hipStream_t s);
+
+// Batched GMRES driver.  The operator callback computes out = A(in) for all
+// systems; `precond` (may be null) is the right point-Jacobi scaling.
+using OpFn = int (*)(Problem &P, const double *in, const double *dinv, double *out, hipStream_t s, void *ctx);
+int gmres_batched(Problem &P, Krylov &K, OpFn op, void *ctx, const double *dinv, const double *f, double *x,
+                  int64_t n, int nb, double tol, int restart, int max_its, int check_every, bool x_zero,
+                  hipStream_t s, int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged);
+
+}  // namespace mlpg

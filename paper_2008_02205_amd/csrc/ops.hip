@@ -1,0 +1,340 @@
+// Assembly of the per-ordinate operators of Sec. 4.2 into
+// direction-independent value streams, and the operator applications used
+// by the solver: the ordinate-batched SpMV, the all-ordinate reduction D,
+// the point values of Eq. flux-expansion and the inflow term of r.
+//
+// Streams are stored row-major interleaved ([nnz][ns]) so that one nonzero's
+// values are read together; every lane of a row owns one ordinate and
+// combines the streams with its own coefficients (products of Omega_m
+// components) in registers, so L_m is never stored per ordinate.
+#include "internal.hpp"
+
+namespace mlpg {
+
+namespace {
+
+__device__ __forceinline__ int64_t row_of(const int64_t *row_off, int64_t n, int64_t p)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (row_off[mid] <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct AsmArgs {
+    int64_t n, nnz;
+    int dim, G;
+    const int64_t *row_off;
+    const double *blocks;
+    const double *tau;
+    double a0;
+    double sig_t[8], sig_s[8];
+    double *sL, *sMD, *sMS;
+    int nsL;
+};
+
+// One thread per nonzero: combine the material blocks with sigma_t, sigma_s,
+// a0 = 1/(c dt) and tau_i (Eq. weak-transport, operator forms of Sec. 4.2).
+__global__ void assemble_kernel(AsmArgs a)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.nnz) return;
+    const int d = a.dim, G = a.G;
+    const int64_t nnz = a.nnz;
+    const int64_t i = row_of(a.row_off, a.n, p);
+    const double tau = a.tau[i];
+    double mass = 0.0, smass_t = 0.0, smass_s = 0.0;
+    double D[3] = {0, 0, 0}, Dt[3] = {0, 0, 0}, Ds[3] = {0, 0, 0};
+    for (int g = 0; g < G; ++g) {
+        double mg = a.blocks[(int64_t)(g * (1 + d)) * nnz + p];
+        mass += mg;
+        smass_t += a.sig_t[g] * mg;
+        smass_s += a.sig_s[g] * mg;
+        for (int al = 0; al < d; ++al) {
+            double dg = a.blocks[(int64_t)(g * (1 + d) + 1 + al) * nnz + p];
+            D[al] += dg;
+            Dt[al] += a.sig_t[g] * dg;
+            Ds[al] += a.sig_s[g] * dg;
+        }
+    }
+    const int kb = G * (1 + d);
+    double *L = a.sL + p * a.nsL;
+    L[0] = a.a0 * mass + smass_t;
+    for (int al = 0; al < d; ++al) L[1 + al] = (a.a0 * tau - 1.0) * D[al] + tau * Dt[al];
+    // SUPG second-order term: tau_i sum_ab W^a W^b K^ab, with the symmetric
+    // pair K^ab + K^ba folded into one stream for a < b.
+    int s = 1 + d;
+    for (int al = 0; al < d; ++al)
+        for (int be = al; be < d; ++be) {
+            double k = a.blocks[(int64_t)(kb + al * d + be) * nnz + p];
+            if (be != al) k += a.blocks[(int64_t)(kb + be * d + al) * nnz + p];
+            L[s++] = tau * k;
+        }
+    double *MD = a.sMD + p * (1 + d);
+    double *MS = a.sMS + p * (1 + d);
+    const double f4pi = 1.0 / (4.0 * M_PI);
+    MD[0] = mass;
+    MS[0] = f4pi * smass_s;
+    for (int al = 0; al < d; ++al) {
+        MD[1 + al] = tau * D[al];
+        MS[1 + al] = f4pi * tau * Ds[al];
+    }
+}
+
+// Surface rows: count entries of row i with any nonzero face block.
+__global__ void surface_count_kernel(int64_t n, int64_t nnz, int nf, int sb, const int64_t *row_off,
+                                     const double *blocks, int64_t *counts)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t c = 0;
+    for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) {
+        bool nz = false;
+        for (int f = 0; f < nf; ++f) nz |= blocks[(int64_t)(sb + f) * nnz + p] != 0.0;
+        c += nz;
+    }
+    counts[i] = c;
+}
+
+__global__ void surface_fill_kernel(int64_t n, int64_t nnz, int nf, int sb, const int64_t *row_off,
+                                    const int32_t *col, const double *blocks, const int64_t *soff, int32_t *scol,
+                                    double *sval)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t o = soff[i];
+    for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) {
+        bool nz = false;
+        for (int f = 0; f < nf; ++f) nz |= blocks[(int64_t)(sb + f) * nnz + p] != 0.0;
+        if (!nz) continue;
+        scol[o] = col[p];
+        for (int f = 0; f < nf; ++f) sval[o * nf + f] = blocks[(int64_t)(sb + f) * nnz + p];
+        o++;
+    }
+}
+
+// dinv[i][m] = 1 / L_m[i,i]
+__global__ void jacobi_kernel(int64_t n, int M, int nsL, int nf, const int64_t *diag_pos, const double *sL,
+                              const double *coefL, const int64_t *soff, const int32_t *scol, const double *sval,
+                              const double *coefF, double *dinv)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * M) return;
+    int64_t i = t / M;
+    int m = (int)(t - i * M);
+    const double *v = sL + diag_pos[i] * nsL;
+    double d = 0.0;
+    for (int b = 0; b < nsL; ++b) d += coefL[m * nsL + b] * v[b];
+    for (int64_t p = soff[i]; p < soff[i + 1]; ++p)
+        if (scol[p] == i)
+            for (int f = 0; f < nf; ++f) d += coefF[m * nf + f] * sval[p * nf + f];
+    dinv[t] = d != 0.0 ? 1.0 / d : 1.0;
+}
+
+// Ordinate-batched SpMV.  Thread (row group, m): lanes of one row share the
+// row's stream values (broadcast loads) and each combines them with its own
+// ordinate coefficients held in registers.
+template <int NS>
+__global__ __launch_bounds__(256) void spmv_kernel(int64_t n, int M, const int64_t *__restrict__ row_off,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ vals,
+                                                   const double *__restrict__ coef, const double *__restrict__ x,
+                                                   int x_bcast, const double *__restrict__ x2, double xs,
+                                                   const double *__restrict__ dinv,
+                                                   const double *__restrict__ colscale,
+                                                   const int64_t *__restrict__ soff, const int32_t *__restrict__ scol,
+                                                   const double *__restrict__ sval, const double *__restrict__ coefF,
+                                                   int nf, double *__restrict__ y, const double *__restrict__ yadd,
+                                                   int ysign)
+{
+    const int rpb = blockDim.x / M;
+    const int rl = threadIdx.x / M;
+    const int m = threadIdx.x - rl * M;
+    if (rl >= rpb) return;
+    double c[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) c[b] = coef[m * NS + b];
+    double cf[6] = {0, 0, 0, 0, 0, 0};
+    if (soff)
+        for (int f = 0; f < nf; ++f) cf[f] = coefF[m * nf + f];
+    const double sc = colscale ? colscale[m] : 1.0;
+    for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
+        double acc = 0.0;
+        const int64_t p0 = row_off[i], p1 = row_off[i + 1];
+        for (int64_t p = p0; p < p1; ++p) {
+            const int64_t j = col[p];
+            const double *v = vals + p * NS;
+            double a = 0.0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) a += c[b] * v[b];
+            double xv = xs * (x_bcast ? x[j] : x[j * M + m]);
+            if (x2) xv += x2[j * M + m];
+            if (dinv) xv *= dinv[j * M + m];
+            acc += a * xv;
+        }
+        if (soff) {
+            for (int64_t p = soff[i]; p < soff[i + 1]; ++p) {
+                const int64_t j = scol[p];
+                double a = 0.0;
+                for (int f = 0; f < nf; ++f) a += cf[f] * sval[p * nf + f];
+                double xv = xs * (x_bcast ? x[j] : x[j * M + m]);
+                if (x2) xv += x2[j * M + m];
+                if (dinv) xv *= dinv[j * M + m];
+                acc += a * xv;
+            }
+        }
+        acc *= sc;
+        y[i * M + m] = yadd ? yadd[i * M + m] + ysign * acc : acc;
+    }
+}
+
+__global__ void point_values_kernel(int64_t n, const int64_t *row_off, const int32_t *col, const double *E,
+                                    const double *coef, double *out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) s += E[p] * coef[col[p]];
+    out[i] = s;
+}
+
+// Inflow term (N_i, |W.n| psi_b)_{W.n<0}: one thread per (boundary point, m).
+__global__ void boundary_rhs_kernel(int64_t nbq, int M, int dim, const int32_t *face, const double *bw,
+                                    const int32_t *nact, const int32_t *act, const double *bN, const double *omega,
+                                    const double *psib, double *F)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbq * M) return;
+    int64_t k = t / M;
+    int m = (int)(t - k * M);
+    int f = face[k];
+    int ax = f >> 1;
+    double sgn = (f & 1) ? 1.0 : -1.0;
+    double wn = sgn * omega[m * dim + ax];
+    if (wn >= 0.0) return;
+    double val = psib[t];
+    if (val == 0.0) return;
+    double s = bw[k] * (-wn) * val;
+    for (int a = 0; a < nact[k]; ++a) atomicAdd(&F[(int64_t)act[k * kBqAct + a] * M + m], s * bN[k * kBqAct + a]);
+}
+
+// out[i] = base[i] + sign * sum_m w_m X[i][m]; one wave per row.
+__global__ __launch_bounds__(256) void ord_reduce_kernel(int64_t n, int M, const double *wq, const double *X,
+                                                         const double *base, double sign, double *out)
+{
+    int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int m = lane; m < M; m += 64) s += wq[m] * X[i * M + m];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (lane == 0) out[i] = (base ? base[i] : 0.0) + sign * s;
+}
+
+__global__ void add_kernel(double *y, const double *a, const double *b, int64_t count)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) y[t] = a[t] + b[t];
+}
+
+inline int rows_per_block(int M) { return M >= 256 ? 1 : 256 / M; }
+
+}  // namespace
+
+hipError_t launch_assemble(Problem &P, const double *sig_t, const double *sig_s, const double *tau, hipStream_t s)
+{
+    AsmArgs a;
+    a.n = P.n; a.nnz = P.nnz; a.dim = P.dim; a.G = P.n_mat; a.row_off = P.row_off.p; a.blocks = P.blocks.p;
+    a.tau = tau; a.a0 = P.a0;
+    for (int g = 0; g < 8; ++g) {
+        a.sig_t[g] = g < P.n_mat ? sig_t[g] : 0.0;
+        a.sig_s[g] = g < P.n_mat ? sig_s[g] : 0.0;
+    }
+    a.sL = P.sL.p; a.sMD = P.sMD.p; a.sMS = P.sMS.p; a.nsL = P.nsL;
+    assemble_kernel<<<(unsigned)((P.nnz + 255) / 256), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_count(Problem &P, int64_t *counts, hipStream_t s)
+{
+    int sb = P.n_mat * (1 + P.dim) + P.dim * P.dim;
+    surface_count_kernel<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.nnz, 2 * P.dim, sb, P.row_off.p,
+                                                                         P.blocks.p, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_fill(Problem &P, const double *, hipStream_t s)
+{
+    int sb = P.n_mat * (1 + P.dim) + P.dim * P.dim;
+    surface_fill_kernel<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.nnz, 2 * P.dim, sb, P.row_off.p,
+                                                                        P.col.p, P.blocks.p, P.surf_off.p,
+                                                                        P.surf_col.p, P.surf_val.p);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi(Problem &P, hipStream_t s)
+{
+    int64_t tot = P.n * P.n_ord;
+    jacobi_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(P.n, P.n_ord, P.nsL, P.nfaces, P.diag_pos.p, P.sL.p,
+                                                                   P.coefL.p, P.surf_off.p, P.surf_col.p,
+                                                                   P.surf_val.p, P.coefF.p, P.dinv.p);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s)
+{
+    const int M = P.n_ord;
+    const int rpb = rows_per_block(M);
+    const int threads = rpb * M;
+    if (threads > 1024) return hipErrorInvalidValue;
+    int64_t blocks = (P.n + rpb - 1) / rpb;
+    if (blocks > 65536) blocks = 65536;
+    const int64_t *soff = a.surface ? P.surf_off.p : nullptr;
+#define MLPG_SPMV(NSV)                                                                                         \
+    spmv_kernel<NSV><<<(unsigned)blocks, threads, 0, s>>>(P.n, M, P.row_off.p, P.col.p, a.vals, a.coef, a.x,   \
+                                                          a.x_bcast, a.x2, a.xs, a.dinv, a.colscale, soff,      \
+                                                          P.surf_col.p, P.surf_val.p, P.coefF.p, P.nfaces, a.y, \
+                                                          a.yadd, a.ysign)
+    switch (a.ns) {
+    case 3: MLPG_SPMV(3); break;
+    case 4: MLPG_SPMV(4); break;
+    case 6: MLPG_SPMV(6); break;
+    case 10: MLPG_SPMV(10); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MLPG_SPMV
+    return hipGetLastError();
+}
+
+hipError_t launch_point_values(Problem &P, const double *coef, double *out, hipStream_t s)
+{
+    point_values_kernel<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.row_off.p, P.col.p, P.E.p, coef, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_boundary_rhs(Problem &P, const double *psib, double *F, hipStream_t s)
+{
+    int64_t tot = P.n_bq * P.n_ord;
+    if (tot == 0) return hipSuccess;
+    boundary_rhs_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(P.n_bq, P.n_ord, P.dim, P.bq_face.p, P.bq_w.p,
+                                                                        P.bq_nact.p, P.bq_act.p, P.bq_N.p,
+                                                                        P.omega.p, psib, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_ord_reduce(Problem &P, const double *X, double *out, const double *base, double sign, hipStream_t s)
+{
+    int64_t blocks = (P.n + 3) / 4;
+    ord_reduce_kernel<<<(unsigned)blocks, 256, 0, s>>>(P.n, P.n_ord, P.wq.p, X, base, sign, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(double *y, const double *a, const double *b, int64_t count, hipStream_t s)
+{
+    add_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(y, a, b, count);
+    return hipGetLastError();
+}
+
+}  // namespace mlpg

@@ -1,0 +1,284 @@
+"""Thin ctypes binding of libmlpg.so (include/mlpg.h), one function per C entry point.
+
+Argument marshalling only: device arrays are torch tensors on the GPU (their
+data pointers are passed straight through), host arrays are numpy arrays,
+and every call runs on torch's current HIP stream.  All computation happens
+in the HIP library; when the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlpg.so")
+
+MLPG_FP64, MLPG_MIXED = 0, 1
+MLPG_QUAD_PRODUCT, MLPG_QUAD_BEAM_DENSE = 0, 1
+MLPG_OP_L, MLPG_OP_T, MLPG_OP_MS, MLPG_OP_SRC = 0, 1, 2, 3
+STATUS = {0: "MLPG_OK", -1: "MLPG_ERR_ARG", -2: "MLPG_ERR_HIP", -3: "MLPG_ERR_CAPACITY",
+          -4: "MLPG_ERR_NOT_CONVERGED", -5: "MLPG_ERR_GEOMETRY", -7: "MLPG_ERR_STATE"}
+
+EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count", "mlpg_neighbors_fill",
+           "mlpg_geometry", "mlpg_get_info", "mlpg_get_volumes", "mlpg_cell_capacity", "mlpg_get_cells",
+           "mlpg_boundary_points", "mlpg_integrate", "mlpg_get_pattern", "mlpg_get_blocks", "mlpg_assemble",
+           "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
+           "mlpg_point_values", "mlpg_destroy"]
+
+
+class MlpgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int), ("n_mat", C.c_int), ("nnz", C.c_int64), ("n_bq", C.c_int64),
+                ("oversize_cells", C.c_int64), ("failed_cells", C.c_int64), ("fallback_qps", C.c_int64),
+                ("missing_pairs", C.c_int64), ("n_ord", C.c_int), ("n_blocks", C.c_int)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol_inner", C.c_double), ("tol_outer", C.c_double), ("restart_inner", C.c_int),
+                ("restart_outer", C.c_int), ("max_inner", C.c_int), ("max_outer", C.c_int),
+                ("check_every", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("inner_solves", C.c_int), ("inner_iters", C.c_int64),
+                ("inner_sweeps", C.c_int64), ("outer_res", C.c_double), ("inner_res_max", C.c_double),
+                ("converged", C.c_int)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libmlpg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2008_02205_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
+        L.mlpg_last_error.restype = C.c_char_p
+        L.mlpg_last_error.argtypes = []
+        L.mlpg_angular_quadrature.argtypes = [i32, i32, i32, vp, vp]
+        L.mlpg_neighbors_count.argtypes = [i32, i64, vp, vp, vp, C.POINTER(C.c_int64), vp]
+        L.mlpg_neighbors_fill.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+        L.mlpg_geometry.argtypes = [C.POINTER(vp), i32, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.mlpg_get_info.argtypes = [vp, C.POINTER(Info)]
+        L.mlpg_get_volumes.argtypes = [vp, vp, vp]
+        L.mlpg_cell_capacity.argtypes = []
+        L.mlpg_get_cells.argtypes = [vp, vp, vp, vp, vp]
+        L.mlpg_boundary_points.argtypes = [vp, vp, vp, vp]
+        L.mlpg_integrate.argtypes = [vp, i32, vp]
+        L.mlpg_get_pattern.argtypes = [vp, vp, vp, vp]
+        L.mlpg_get_blocks.argtypes = [vp, vp, vp, vp]
+        L.mlpg_assemble.argtypes = [vp, i32, vp, vp, i32, vp, vp, dbl, vp, i32, vp]
+        L.mlpg_apply.argtypes = [vp, i32, vp, vp, vp]
+        L.mlpg_default_opts.restype = None
+        L.mlpg_default_opts.argtypes = [C.POINTER(SolveOpts)]
+        L.mlpg_set_state.argtypes = [vp, vp, vp]
+        L.mlpg_get_state.argtypes = [vp, vp, vp, vp]
+        L.mlpg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.mlpg_point_values.argtypes = [vp, vp, vp, vp]
+        L.mlpg_destroy.restype = None
+        L.mlpg_destroy.argtypes = [vp]
+        for name in EXPORTS:
+            if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise MlpgError(rc, lib().mlpg_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t) -> Optional[int]:
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensor expected (contiguous, on the GPU)"
+    return t.data_ptr()
+
+
+def _host(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data
+
+
+def _stream() -> int:
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _empty(shape, dtype=None):
+    torch = _torch()
+    return torch.empty(shape, dtype=dtype or torch.float64, device="cuda")
+
+
+# ---------------------------------------------------------------------------
+
+def mlpg_angular_quadrature(dim: int, n_ord: int, kind: int = MLPG_QUAD_PRODUCT):
+    om = np.zeros((n_ord, dim))
+    w = np.zeros(n_ord)
+    _check(lib().mlpg_angular_quadrature(dim, n_ord, kind, _host(om), _host(w)))
+    return om, w
+
+
+def mlpg_neighbors_count(x, R):
+    torch = _torch()
+    n, dim = x.shape
+    off = _empty(n + 1, torch.int64)
+    total = C.c_int64(0)
+    _check(lib().mlpg_neighbors_count(dim, n, _dev(x), _dev(R), _dev(off), C.byref(total), _stream()))
+    return off, int(total.value)
+
+
+def mlpg_neighbors_fill(x, R, off, total):
+    torch = _torch()
+    n, dim = x.shape
+    idx = _empty(max(total, 1), torch.int32)
+    _check(lib().mlpg_neighbors_fill(dim, n, _dev(x), _dev(R), _dev(off), _dev(idx), _stream()))
+    return idx[:total]
+
+
+def mlpg_geometry(x, R, nbr_off, nbr_idx, dom_lo, dom_hi, regions=()):
+    n, dim = x.shape
+    lo = np.ascontiguousarray(dom_lo, dtype=np.float64)
+    hi = np.ascontiguousarray(dom_hi, dtype=np.float64)
+    if regions:
+        rlo = np.ascontiguousarray([r[0] for r in regions], dtype=np.float64)
+        rhi = np.ascontiguousarray([r[1] for r in regions], dtype=np.float64)
+        rmat = np.ascontiguousarray([r[2] for r in regions], dtype=np.int32)
+    else:
+        rlo = rhi = rmat = None
+    h = C.c_void_p(None)
+    idx = nbr_idx if nbr_idx.numel() > 0 else _empty(1, _torch().int32)
+    _check(lib().mlpg_geometry(C.byref(h), dim, n, _dev(x), _dev(R), _dev(nbr_off), _dev(idx), _host(lo), _host(hi),
+                               len(regions), _host(rlo), _host(rhi), _host(rmat), _stream()))
+    return h
+
+
+def mlpg_get_info(h) -> dict:
+    info = Info()
+    _check(lib().mlpg_get_info(h, C.byref(info)))
+    return {k: getattr(info, k) for k, _ in Info._fields_}
+
+
+def mlpg_get_volumes(h, n):
+    V = _empty(n)
+    _check(lib().mlpg_get_volumes(h, _dev(V), _stream()))
+    return V
+
+
+def mlpg_cell_capacity() -> int:
+    return lib().mlpg_cell_capacity()
+
+
+def mlpg_get_cells(h, n):
+    torch = _torch()
+    cap = mlpg_cell_capacity()
+    nv = _empty(n, torch.int32)
+    verts = _empty((n, cap, 2))
+    tags = _empty((n, cap), torch.int32)
+    _check(lib().mlpg_get_cells(h, _dev(nv), _dev(verts), _dev(tags), _stream()))
+    return nv, verts, tags
+
+
+def mlpg_boundary_points(h, n_bq, dim):
+    torch = _torch()
+    y = _empty((max(n_bq, 1), dim))
+    face = _empty(max(n_bq, 1), torch.int32)
+    _check(lib().mlpg_boundary_points(h, _dev(y), _dev(face), _stream()))
+    return y[:n_bq], face[:n_bq]
+
+
+def mlpg_integrate(h, rk_order: int):
+    _check(lib().mlpg_integrate(h, rk_order, _stream()))
+
+
+def mlpg_get_pattern(h, n, nnz):
+    torch = _torch()
+    row_off = _empty(n + 1, torch.int64)
+    col = _empty(nnz, torch.int32)
+    _check(lib().mlpg_get_pattern(h, _dev(row_off), _dev(col), _stream()))
+    return row_off, col
+
+
+def mlpg_get_blocks(h, n_blocks, nnz):
+    blocks = _empty((n_blocks, nnz))
+    E = _empty(nnz)
+    _check(lib().mlpg_get_blocks(h, _dev(blocks), _dev(E), _stream()))
+    return blocks, E
+
+
+def mlpg_assemble(h, omega: np.ndarray, w: np.ndarray, sigma_t, sigma_s, inv_c_dt: float, tau,
+                  precision: int = MLPG_FP64):
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    wq = np.ascontiguousarray(w, dtype=np.float64)
+    st = np.ascontiguousarray(np.atleast_1d(sigma_t), dtype=np.float64)
+    ss = np.ascontiguousarray(np.atleast_1d(sigma_s), dtype=np.float64)
+    _check(lib().mlpg_assemble(h, om.shape[0], _host(om), _host(wq), st.size, _host(st), _host(ss), float(inv_c_dt),
+                               _dev(tau), precision, _stream()))
+
+
+def mlpg_apply(h, which: int, X):
+    Y = _empty(X.shape)
+    _check(lib().mlpg_apply(h, which, _dev(X), _dev(Y), _stream()))
+    return Y
+
+
+def mlpg_default_opts() -> SolveOpts:
+    o = SolveOpts()
+    lib().mlpg_default_opts(C.byref(o))
+    return o
+
+
+def mlpg_set_state(h, psi):
+    _check(lib().mlpg_set_state(h, _dev(psi), _stream()))
+
+
+def mlpg_get_state(h, n, n_ord):
+    psi = _empty((n, n_ord))
+    phi = _empty(n)
+    _check(lib().mlpg_get_state(h, _dev(psi), _dev(phi), _stream()))
+    return psi, phi
+
+
+def mlpg_solve(h, q, psi_b=None, opts: Optional[SolveOpts] = None, want_psi: bool = True, raise_on_error=True):
+    n, M = q.shape
+    phi = _empty(n)
+    phi_pt = _empty(n)
+    psi = _empty((n, M)) if want_psi else None
+    info = SolveInfo()
+    o = opts or mlpg_default_opts()
+    rc = lib().mlpg_solve(h, _dev(q), _dev(psi_b), _dev(phi), _dev(phi_pt), _dev(psi), C.byref(o), C.byref(info),
+                          _stream())
+    if raise_on_error:
+        _check(rc)
+    d = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+    d["status"] = rc
+    return phi, phi_pt, psi, d
+
+
+def mlpg_point_values(h, coef):
+    out = _empty(coef.shape[0])
+    _check(lib().mlpg_point_values(h, _dev(coef), _dev(out), _stream()))
+    return out
+
+
+def mlpg_destroy(h):
+    if h is not None and h.value:
+        lib().mlpg_destroy(h)

@@ -20,9 +20,10 @@ import workloads as W
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_orders.json")))
 
 
-def _setup(n, jitter=0.2, seed=5, order=1, tri_n=5, lo=(0.0, 0.0), hi=(1.0, 1.0), regions=(), n_mat=1):
+def _setup(n, jitter=0.2, seed=5, order=1, tri_n=5, lo=(0.0, 0.0), hi=(1.0, 1.0), regions=(), n_mat=1,
+           rfac=2.0):
     x, dx = W.jittered_lattice((n, n), lo, hi, jitter, seed)
-    R = np.full(n * n, 2.0 * dx)
+    R = np.full(n * n, rfac * dx)
     g = oracle.geometry(x, R, lo, hi)
     it = oracle.integrate(g, order, regions=regions, n_mat=n_mat, tri_n=tri_n)
     return x, dx, g, it
@@ -234,6 +235,20 @@ def test_block_identities():
     for f in range(4):
         assert abs(it.block(f"s{f}").sum() - 1.0) <= 1e-13
     assert it.missing == 0
+
+
+def test_quadratic_rk_block_identities_and_conditioning():
+    """Order-2 RK near corners: the fallback rule keeps the moment matrices well enough
+    conditioned that the exact identities still hold to 1e-9 (a 1e-12 pivot bound let
+    them drift to 1e-4).  Support radius 2.5 h, as used with quadratic RK."""
+    x, dx, g, it = _setup(12, order=2, rfac=2.5)
+    n = g.n
+    rows = np.repeat(np.arange(n), np.diff(g.row_off))
+    assert abs(it.block("mass0").sum() - 1.0) <= 1e-12
+    for a, name in enumerate(("dx0", "dy0")):
+        assert np.abs(np.bincount(g.col, it.block(name), n)).max() <= 1e-9
+        lhs = np.bincount(g.col, it.block(name) * x[rows, a], n)
+        assert np.abs(lhs - np.bincount(g.col, it.block("mass0"), n)).max() <= 1e-9
 
 
 def test_divergence_identity_quadrature_level():
