@@ -171,7 +171,8 @@ int mlpg_get_blocks(mlpg_handle h, double *blocks, double *E, void *stream);
  *       + tau_i sum_ab W^a W^b K^ab + sum_f max(0, W.n_f) S_f,   W = Omega_m
  *   T_m = a0 (Mass + tau_i W.D),   MS_m = (1/4pi) sum_g sigma_s,g (Mass_g + tau_i W.D_g)
  * and the point-Jacobi diagonal of every L_m.
- *   omega: host [n_ord][dim]; w: host [n_ord]; sigma_t, sigma_s: host [n_mat];
+ *   n_ord: 1..256 ordinates; omega: host [n_ord][dim]; w: host [n_ord];
+ *   sigma_t, sigma_s: host [n_mat];
  *   tau: device [n] SUPG lengths (Sec. 4.1: about the point spacing);
  *   precision: MLPG_FP64 (FP64 values) or MLPG_MIXED (adds FP32 copies used
  *     by the FP32 inner solver inside FP64 refinement).
@@ -212,7 +213,7 @@ typedef struct {
     int restart_outer;    /* <= 30 (default 30) */
     int max_inner;        /* Arnoldi steps per ordinate per solve (default 3000) */
     int max_outer;        /* (default 500) */
-    int check_every;      /* Arnoldi steps between host convergence checks (default 4) */
+    int check_every;      /* Arnoldi steps queued ahead of the host convergence check (default 3) */
 } mlpg_solve_opts;
 
 typedef struct {

@@ -29,10 +29,11 @@ namespace {
 
 hipStream_t S(void *s) { return (hipStream_t)s; }
 
-int op_L(Problem &P, const double *in, const double *dinv, double *out, hipStream_t s, void *)
+int op_L(Problem &P, const OpCall &c, hipStream_t s, void *)
 {
     SpmvArgs a;
-    a.vals = P.sL.p; a.ns = P.nsL; a.coef = P.coefL.p; a.x = in; a.dinv = dinv; a.surface = 1; a.y = out;
+    a.vals = P.sL.p; a.ns = P.nsL; a.coef = P.coefL.p; a.x = c.in; a.dinv = c.dinv; a.surface = 1; a.y = c.out;
+    a.colscale = c.colscale; a.vout = c.vout; a.vsrc = c.vsrc; a.gate = c.gate;
     MLPG_HIP(launch_spmv(P, a, s));
     return MLPG_OK;
 }
@@ -48,20 +49,21 @@ struct SolveCounters {
 int inner_solve(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
 {
     c.solves++;
-    return gmres_batched(P, P.inner, op_L, nullptr, P.dinv.p, f, x, P.n, P.n_ord, c.o->tol_inner, c.o->restart_inner,
-                         c.o->max_inner, c.o->check_every, true, s, &c.its, &c.sweeps, &c.res_max, &c.conv);
+    return gmres_batched(P, P.inner, op_L, true, nullptr, P.dinv.p, f, x, P.n, P.n_ord, c.o->tol_inner,
+                         c.o->restart_inner, c.o->max_inner, c.o->check_every, true, s, &c.its, &c.sweeps, &c.res_max,
+                         &c.conv);
 }
 
 // A phi = phi - D L^-1 MS phi  (Eq. krylov-operator)
-int op_outer(Problem &P, const double *in, const double *, double *out, hipStream_t s, void *vctx)
+int op_outer(Problem &P, const OpCall &oc, hipStream_t s, void *vctx)
 {
     SolveCounters &c = *(SolveCounters *)vctx;
     SpmvArgs a;
-    a.vals = P.sMS.p; a.ns = P.nsMD; a.coef = P.coefMD.p; a.x = in; a.x_bcast = 1; a.y = P.t1.p;
+    a.vals = P.sMS.p; a.ns = P.nsMD; a.coef = P.coefMD.p; a.x = oc.in; a.x_bcast = 1; a.y = P.t1.p;
     MLPG_HIP(launch_spmv(P, a, s));
     int rc = inner_solve(P, c, P.t1.p, P.t2.p, s);
     if (rc) return rc;
-    MLPG_HIP(launch_ord_reduce(P, P.t2.p, out, in, -1.0, s));
+    MLPG_HIP(launch_ord_reduce(P, P.t2.p, oc.out, oc.in, -1.0, s));
     return MLPG_OK;
 }
 
@@ -342,7 +344,7 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
     int rc = check_stage(h, 2, "mlpg_assemble");
     if (rc) return rc;
     Problem *P = h;
-    MLPG_CHECK(n_ord >= 1 && n_ord <= 1024, MLPG_ERR_ARG, "mlpg_assemble: n_ord must be in [1, 1024]");
+    MLPG_CHECK(n_ord >= 1 && n_ord <= 256, MLPG_ERR_ARG, "mlpg_assemble: n_ord must be in [1, 256]");
     MLPG_CHECK(omega && w && sigma_t && sigma_s && tau, MLPG_ERR_ARG, "mlpg_assemble: null pointer");
     MLPG_CHECK(n_mat >= P->n_mat && n_mat <= 8, MLPG_ERR_ARG,
                "mlpg_assemble: n_mat must cover every material of the regions (and be <= 8)");
@@ -455,7 +457,7 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->restart_outer = 30;
     o->max_inner = 3000;
     o->max_outer = 500;
-    o->check_every = 4;
+    o->check_every = 3;
 }
 
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)
@@ -527,8 +529,8 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     int64_t oits = 0, osweeps = 0;
     double ores = 0.0;
     bool oconv = true;
-    rc = gmres_batched(*P, P->outer, op_outer, &c, nullptr, P->bphi.p, P->phi.p, n, 1, o.tol_outer, o.restart_outer,
-                       std::max(1, o.max_outer), 1, false, s, &oits, &osweeps, &ores, &oconv);
+    rc = gmres_batched(*P, P->outer, op_outer, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1, o.tol_outer,
+                       o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits, &osweeps, &ores, &oconv);
     if (rc) return rc;
     // recovery Psi = L^-1 MS Phi + b_psi
     {

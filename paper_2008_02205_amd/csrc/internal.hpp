@@ -88,8 +88,10 @@ struct Krylov {
     int nb = 0;
     int k = 0;
     DevBuf<double> V;        // [(k+1)][n][nb]
-    DevBuf<double> w;        // [n][nb]
+    DevBuf<double> w, w2;    // [n][nb] operator outputs (alternating)
+    DevBuf<double> z;        // [n][nb] dinv .* w, the next operator input
     DevBuf<double> r;        // [n][nb]
+    DevBuf<double> vscale;   // [nb] 1/h_{j+1,j} of the newest column (0 once a system stops)
     DevBuf<double> part;     // [nblk][k+2][nb] block partial sums
     DevBuf<double> h1, h2;   // [k+1][nb]
     DevBuf<double> H;        // [nb][k+1][k]
@@ -104,7 +106,9 @@ struct Krylov {
     DevBuf<int> its;         // [nb] Arnoldi steps so far in this solve
     DevBuf<int> jend;        // [nb] columns built in this cycle
     DevBuf<int> nactive;     // [1]
-    int *nactive_host = nullptr;   // pinned mirror
+    int *nactive_host = nullptr;   // pinned, host-visible mirrors of nactive (one slot per sweep in flight)
+    int *nactive_hdev = nullptr;   // device address of nactive_host
+    hipEvent_t ev[8] = {};
     int part_blocks = 0;
     hipError_t ensure(int64_t n_, int nb_, int k_);
     void release();
@@ -205,6 +209,9 @@ struct SpmvArgs {
     double *y = nullptr;
     const double *yadd = nullptr;     // optional: y = yadd - (A x) when set with ysign=-1
     int ysign = 1;
+    double *vout = nullptr;           // optional: vout[i][m] = colscale[m] vsrc[i][m] on each own row
+    const double *vsrc = nullptr;     //   (vsrc defaults to x)
+    const int *gate = nullptr;        // optional: the launch does nothing when *gate == 0
 };
 hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s);
 hipError_t launch_point_values(Problem &P, const double *coef, double *out, hipStream_t s);
@@ -215,9 +222,21 @@ hipError_t launch_add(double *y, const double *a, const double *b, int64_t count
 
 // Batched GMRES driver.  The operator callback computes out = A(in) for all
 // systems; `precond` (may be null) is the right point-Jacobi scaling.
-using OpFn = int (*)(Problem &P, const double *in, const double *dinv, double *out, hipStream_t s, void *ctx);
-int gmres_batched(Problem &P, Krylov &K, OpFn op, void *ctx, const double *dinv, const double *f, double *x,
-                  int64_t n, int nb, double tol, int restart, int max_its, int check_every, bool x_zero,
+// One operator application out = A(dinv .* (colscale .* in)).  When the
+// operator supports it (`fused`), it also writes vout = colscale .* in on its
+// own rows, which normalises the next Krylov vector inside the SpMV.
+struct OpCall {
+    const double *in = nullptr;
+    const double *dinv = nullptr;
+    const double *colscale = nullptr;
+    double *vout = nullptr;
+    const double *vsrc = nullptr;
+    double *out = nullptr;
+    const int *gate = nullptr;
+};
+using OpFn = int (*)(Problem &P, const OpCall &c, hipStream_t s, void *ctx);
+int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const double *dinv, const double *f,
+                  double *x, int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero,
                   hipStream_t s, int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged);
 
 }  // namespace mlpg

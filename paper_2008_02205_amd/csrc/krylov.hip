@@ -3,24 +3,32 @@
 // `nb` independent systems of `n` unknowns advance together, vectors stored
 // [n][nb] with the system index fastest (for the inner solves, nb = the
 // ordinates; the outer scattering iteration uses nb = 1).  Each Arnoldi step
-// is one operator application over all systems, classical Gram-Schmidt with
-// one reorthogonalisation in three streaming passes over the basis
+// is one operator application over all systems, then classical Gram-Schmidt
+// with one reorthogonalisation in three streaming passes over the basis
 //   pass 1: h1 = V^T w
 //   pass 2: w -= V h1 and h2 = V^T w       (fused: the basis is read once)
 //   pass 3: w -= V h2 and ||w||^2          (fused)
 // with block partial sums reduced in a fixed order (deterministic), and a
 // one-thread-per-system kernel for the Hessenberg column, Givens rotations,
-// residual estimate and convergence flag.  Converged systems stop updating;
-// the host looks at the count of active systems every few steps.
+// residual estimate and convergence flag.  The normalisation of the new
+// basis vector is folded into the next operator application when the
+// operator supports it.  Systems that converge stop updating; kernels of a
+// sweep in which no system is active return at once, and the host reads the
+// active count a few sweeps late (through host-visible memory and events) so
+// that the queue never drains while it waits.
 #include "internal.hpp"
 
 namespace mlpg {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPartBlocks = 512;
+constexpr int kThreads = 256;       // small kernels
+constexpr int kMaxThreads = 512;    // streaming Gram-Schmidt passes (2 waves per SIMD: ~190 VGPRs fit)
+constexpr int kPartBlocks = 256;    // workgroups (and partial sums) of a streaming pass
+constexpr int kRowsPerThread = 4;
 constexpr int KP = kMaxRestart + 1;   // basis vectors held in registers
+constexpr int QC = 8;                 // partial sums reduced per LDS round
+constexpr int kSlots = 8;
 
 inline int rpb_of(int nb)
 {
@@ -29,30 +37,48 @@ inline int rpb_of(int nb)
     return r;
 }
 
-// Reduce acc[q] over the row groups of the block into part[blockIdx][q][m].
-template <int NQMAX>
-__device__ __forceinline__ void block_reduce_store(double (&acc)[NQMAX], int nq, int rpb, int rl, int m, int nb,
+inline int pow2_floor(int v)
+{
+    int r = 1;
+    while (r * 2 <= v) r *= 2;
+    return r;
+}
+
+// Reduce acc[q] (q < nq) over the rpb row groups of the block into
+// part[blockIdx][q][m], QC values at a time through a fixed-shape LDS tree.
+__device__ __forceinline__ void block_reduce_store(const double (&acc)[KP], int nq, int rpb, int rl, int m, int nb,
                                                    double *red, double *part)
 {
-    for (int q = 0; q < NQMAX; ++q) {
-        if (q >= nq) break;
-        red[rl * nb + m] = acc[q];
+#pragma unroll
+    for (int q0 = 0; q0 < KP; q0 += QC) {
+        if (q0 >= nq) break;
+#pragma unroll
+        for (int qq = 0; qq < QC; ++qq)
+            if (q0 + qq < KP) red[(rl * QC + qq) * nb + m] = acc[q0 + qq < KP ? q0 + qq : 0];
         __syncthreads();
         for (int s = rpb >> 1; s > 0; s >>= 1) {
-            if (rl < s) red[rl * nb + m] += red[(rl + s) * nb + m];
+            if (rl < s) {
+#pragma unroll
+                for (int qq = 0; qq < QC; ++qq) red[(rl * QC + qq) * nb + m] += red[((rl + s) * QC + qq) * nb + m];
+            }
             __syncthreads();
         }
-        if (rl == 0) part[((int64_t)blockIdx.x * (KP + 1) + q) * nb + m] = red[m];
+        if (rl == 0) {
+#pragma unroll
+            for (int qq = 0; qq < QC; ++qq)
+                if (q0 + qq < nq) part[((int64_t)blockIdx.x * (KP + 1) + q0 + qq) * nb + m] = red[qq * nb + m];
+        }
         __syncthreads();
     }
 }
 
 // part[b][q][m] = sum over the block's rows of V_q[i][m] * w[i][m], q < nq.
-__global__ __launch_bounds__(kThreads) void dots_kernel(int64_t n, int nb, int nq, const double *__restrict__ V,
-                                                        int64_t vstride, const double *__restrict__ w,
-                                                        double *__restrict__ part)
+__global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, int nq, const double *__restrict__ V,
+                                                           int64_t vstride, const double *__restrict__ w,
+                                                           double *__restrict__ part, const int *__restrict__ gate)
 {
-    __shared__ double red[kThreads];
+    extern __shared__ double red[];
+    if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
     double acc[KP];
@@ -65,17 +91,21 @@ __global__ __launch_bounds__(kThreads) void dots_kernel(int64_t n, int nb, int n
         for (int q = 0; q < KP; ++q)
             if (q < nq) acc[q] += V[q * vstride + o] * wv;
     }
-    block_reduce_store<KP>(acc, nq, rpb, rl, m, nb, red, part);
+    block_reduce_store(acc, nq, rpb, rl, m, nb, red, part);
 }
 
-// w -= sum_q h[q][m] V_q ; then part = V^T w (MODE 0) or part[0] = ||w||^2 (MODE 1).
+// w -= sum_q h[q][m] V_q ; then part = V^T w (MODE 0) or part[0] = ||w||^2
+// (MODE 1, which also writes z = dinv .* w, the next operator input).
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void gs_update_kernel(int64_t n, int nb, int nq, const double *__restrict__ V,
-                                                             int64_t vstride, double *__restrict__ w,
-                                                             const double *__restrict__ h,
-                                                             double *__restrict__ part)
+__global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int nb, int nq,
+                                                                const double *__restrict__ V, int64_t vstride,
+                                                                double *__restrict__ w, const double *__restrict__ h,
+                                                                double *__restrict__ part,
+                                                                const double *__restrict__ dinv,
+                                                                double *__restrict__ z, const int *__restrict__ gate)
 {
-    __shared__ double red[kThreads];
+    extern __shared__ double red[];
+    if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
     double hq[KP], acc[KP];
@@ -95,6 +125,7 @@ __global__ __launch_bounds__(kThreads) void gs_update_kernel(int64_t n, int nb, 
                 wv -= hq[q] * vq[q];
             }
         w[o] = wv;
+        if (MODE == 1 && z) z[o] = dinv ? dinv[o] * wv : wv;
         if (MODE == 0) {
 #pragma unroll
             for (int q = 0; q < KP; ++q)
@@ -103,18 +134,38 @@ __global__ __launch_bounds__(kThreads) void gs_update_kernel(int64_t n, int nb, 
             acc[0] += wv * wv;
         }
     }
-    block_reduce_store<KP>(acc, MODE == 0 ? nq : 1, rpb, rl, m, nb, red, part);
+    block_reduce_store(acc, MODE == 0 ? nq : 1, rpb, rl, m, nb, red, part);
 }
 
-// out[q][m] = sum_b part[b][q][m]  (fixed order)
-__global__ void reduce_part_kernel(int nblk, int nq, int nb, const double *__restrict__ part, double *__restrict__ out)
+// out[q][m] = sum_b part[b][q][m]: one workgroup per q; threads split the
+// block partials into interleaved strands (four independent accumulators each
+// so that loads overlap), then a fixed-shape tree in LDS (deterministic).
+__global__ __launch_bounds__(kThreads) void reduce_part_kernel(int nblk, int nq, int nb,
+                                                               const double *__restrict__ part,
+                                                               double *__restrict__ out, const int *__restrict__ gate)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nq * nb) return;
-    int q = t / nb, m = t - q * nb;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[((int64_t)b * (KP + 1) + q) * nb + m];
-    out[t] = s;
+    __shared__ double red[kThreads];
+    if (gate && *gate == 0) return;
+    const int q = blockIdx.x;
+    const int ns = blockDim.x / nb;          // strands per system (power of two)
+    const int st = threadIdx.x / nb, m = threadIdx.x - st * nb;
+    if (st >= ns) return;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = st;
+    for (; b + 3 * ns < nblk; b += 4 * ns) {
+        a0 += part[((int64_t)b * (KP + 1) + q) * nb + m];
+        a1 += part[((int64_t)(b + ns) * (KP + 1) + q) * nb + m];
+        a2 += part[((int64_t)(b + 2 * ns) * (KP + 1) + q) * nb + m];
+        a3 += part[((int64_t)(b + 3 * ns) * (KP + 1) + q) * nb + m];
+    }
+    for (; b < nblk; b += ns) a0 += part[((int64_t)b * (KP + 1) + q) * nb + m];
+    red[threadIdx.x] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    for (int s = ns >> 1; s > 0; s >>= 1) {
+        if (st < s) red[threadIdx.x] += red[threadIdx.x + s * nb];
+        __syncthreads();
+    }
+    if (st == 0) out[q * nb + m] = red[m];
 }
 
 __global__ void sqrt_kernel(int nb, const double *in, double *out)
@@ -123,22 +174,27 @@ __global__ void sqrt_kernel(int nb, const double *in, double *out)
     if (m < nb) out[m] = sqrt(fmax(in[m], 0.0));
 }
 
-// Count of 1s in flag[0..nb) from a single block, written to *count.
-__device__ __forceinline__ void block_count(int v, int *count)
+// Number of threads of the (single) block with v != 0, written to count[0]
+// and, when given, to a host-visible slot.
+__device__ __forceinline__ void block_count(int v, int *count, int *host_slot)
 {
     __shared__ int s_cnt;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     if (v) atomicAdd(&s_cnt, 1);
     __syncthreads();
-    if (threadIdx.x == 0) *count = s_cnt;
+    if (threadIdx.x == 0) {
+        count[0] = s_cnt;
+        if (host_slot) host_slot[0] = s_cnt;
+    }
 }
 
 // Start of a restart cycle: beta = ||r||; decide which systems iterate.
-__global__ void cycle_init_kernel(int nb, int k, const double *__restrict__ beta2, const double *__restrict__ fnorm,
+__global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, const double *__restrict__ beta2, const double *__restrict__ fnorm,
                                   double tol, int max_its, const int *__restrict__ its, int *__restrict__ active,
                                   int *__restrict__ done, double *__restrict__ g, double *__restrict__ beta,
-                                  double *__restrict__ resid, int *__restrict__ jend, int *__restrict__ nactive)
+                                  double *__restrict__ resid, int *__restrict__ jend, int *__restrict__ nactive,
+                                  int *__restrict__ host_slot)
 {
     int m = threadIdx.x;
     int act = 0;
@@ -156,57 +212,88 @@ __global__ void cycle_init_kernel(int nb, int k, const double *__restrict__ beta
         for (int q = 0; q <= k; ++q) g[m * (k + 1) + q] = 0.0;
         g[m * (k + 1)] = b;
     }
-    block_count(act, nactive);
+    block_count(act, nactive, host_slot);
 }
 
-// Hessenberg column j, Givens rotations and convergence test per system.
-__global__ void arnoldi_kernel(int nb, int k, int j, const double *__restrict__ h1, const double *__restrict__ h2,
+// Hessenberg column j, Givens rotations and convergence test per system;
+// the column lives in registers while the earlier rotations are applied.
+__global__ __launch_bounds__(kThreads) void arnoldi_kernel(int nb, int k, int j, const double *__restrict__ h1, const double *__restrict__ h2,
                                const double *__restrict__ hn2, double *__restrict__ H, double *__restrict__ cs,
                                double *__restrict__ sn, double *__restrict__ g, const double *__restrict__ fnorm,
                                double tol, int max_its, int *__restrict__ active, int *__restrict__ its,
-                               int *__restrict__ jend, double *__restrict__ hnv, double *__restrict__ resid,
-                               int *__restrict__ nactive)
+                               int *__restrict__ jend, double *__restrict__ vscale, double *__restrict__ resid,
+                               int *__restrict__ nactive, int *__restrict__ host_slot, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) {
+        if (threadIdx.x == 0 && host_slot) host_slot[0] = 0;
+        return;
+    }
     int m = threadIdx.x;
     int still = 0;
     if (m < nb && active[m]) {
         double *Hm = H + (int64_t)m * (k + 1) * k;
         double *c = cs + m * k, *s = sn + m * k, *gm = g + m * (k + 1);
         double hn = sqrt(fmax(hn2[m], 0.0));
-        hnv[m] = hn;
-        for (int q = 0; q <= j; ++q) Hm[q * k + j] = h1[q * nb + m] + h2[q * nb + m];
-        Hm[(j + 1) * k + j] = hn;
-        for (int q = 0; q < j; ++q) {
-            double a = Hm[q * k + j], b = Hm[(q + 1) * k + j];
-            Hm[q * k + j] = c[q] * a + s[q] * b;
-            Hm[(q + 1) * k + j] = -s[q] * a + c[q] * b;
+        double col[KP + 1];
+        double cq[KP], sq[KP];
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            col[q] = (q <= j) ? h1[q * nb + m] + h2[q * nb + m] : 0.0;
+            cq[q] = (q < j) ? c[q] : 1.0;
+            sq[q] = (q < j) ? s[q] : 0.0;
         }
-        double a = Hm[j * k + j], b = Hm[(j + 1) * k + j];
-        double den = sqrt(a * a + b * b);
-        c[j] = den == 0.0 ? 1.0 : a / den;
-        s[j] = den == 0.0 ? 0.0 : b / den;
-        Hm[j * k + j] = den;
-        Hm[(j + 1) * k + j] = 0.0;
-        gm[j + 1] = -s[j] * gm[j];
-        gm[j] = c[j] * gm[j];
+        col[KP] = 0.0;
+#pragma unroll
+        for (int q = 0; q < KP - 1; ++q) {
+            if (q < j) {
+                double a = col[q], b = col[q + 1];
+                col[q] = cq[q] * a + sq[q] * b;
+                col[q + 1] = -sq[q] * a + cq[q] * b;
+            }
+        }
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < KP; ++q)
+            if (q == j) a = col[q];
+        double den = sqrt(a * a + hn * hn);
+        double cj = den == 0.0 ? 1.0 : a / den;
+        double sj = den == 0.0 ? 0.0 : hn / den;
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            if (q < j) Hm[q * k + j] = col[q];
+            if (q == j) Hm[q * k + j] = den;
+        }
+        c[j] = cj;
+        s[j] = sj;
+        double gj = gm[j];
+        gm[j + 1] = -sj * gj;
+        gm[j] = cj * gj;
         its[m] += 1;
         jend[m] = j + 1;
-        double r = fabs(gm[j + 1]);
+        double r = fabs(sj * gj);
         resid[m] = r / fnorm[m];
-        if (r <= tol * fnorm[m] || hn == 0.0 || its[m] >= max_its) active[m] = 0;
-        else still = 1;
+        if (r <= tol * fnorm[m] || hn == 0.0 || its[m] >= max_its) {
+            active[m] = 0;
+            vscale[m] = 0.0;
+        } else {
+            still = 1;
+            vscale[m] = 1.0 / hn;
+        }
+    } else if (m < nb) {
+        vscale[m] = 0.0;
     }
-    block_count(still, nactive);
+    block_count(still, nactive, host_slot);
 }
 
-// V_{j+1} = w / h_{j+1,j} for systems still iterating, else 0.
-__global__ void normalize_kernel(int64_t n, int nb, const double *__restrict__ w, const double *__restrict__ hnv,
-                                 const int *__restrict__ active, double *__restrict__ vout)
+// V_{j+1} = w * vscale (0 for systems that stopped).
+__global__ void normalize_kernel(int64_t n, int nb, const double *__restrict__ w, const double *__restrict__ vscale,
+                                 double *__restrict__ vout, const int *__restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     int m = (int)(t % nb);
-    vout[t] = active[m] ? w[t] / hnv[m] : 0.0;
+    vout[t] = w[t] * vscale[m];
 }
 
 __global__ void init_v0_kernel(int64_t n, int nb, const double *__restrict__ r, const double *__restrict__ beta,
@@ -257,6 +344,52 @@ __global__ void residual_kernel(int64_t count, const double *__restrict__ f, dou
 
 inline unsigned grid_of(int64_t count) { return (unsigned)((count + kThreads - 1) / kThreads); }
 
+struct Launch {
+    int rpb, threads;
+    unsigned blocks;
+    size_t shmem;
+};
+
+// Streaming passes: up to kPartBlocks workgroups of up to kMaxThreads
+// threads, each thread covering at least kRowsPerThread rows, at least one
+// full wave per workgroup.
+Launch vec_launch(int64_t n, int nb)
+{
+    Launch L;
+    const int rmax = pow2_floor(kMaxThreads / nb > 0 ? kMaxThreads / nb : 1);
+    const int rmin = nb >= 64 ? 1 : 64 / pow2_floor(nb);
+    int rpb = rmax;
+    while (rpb > rmin && (n + (int64_t)rpb * kRowsPerThread - 1) / ((int64_t)rpb * kRowsPerThread) < kPartBlocks)
+        rpb /= 2;
+    L.rpb = rpb;
+    L.threads = rpb * nb;
+    int64_t b = (n + (int64_t)kRowsPerThread * rpb - 1) / ((int64_t)kRowsPerThread * rpb);
+    if (b < 1) b = 1;
+    L.blocks = (unsigned)(b < kPartBlocks ? b : kPartBlocks);
+    L.shmem = sizeof(double) * QC * L.threads;
+    return L;
+}
+
+hipError_t dots(Krylov &K, const double *V, int nq, const double *w, double *out, const int *gate, hipStream_t s)
+{
+    Launch L = vec_launch(K.n, K.nb);
+    dots_kernel<<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, nq, V, K.n * K.nb, w, K.part.p, gate);
+    reduce_part_kernel<<<nq, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nq, K.nb, K.part.p, out, gate);
+    return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t gs_update(Krylov &K, int nq, double *w, const double *h, double *out, const double *dinv, double *z,
+                     const int *gate, hipStream_t s)
+{
+    Launch L = vec_launch(K.n, K.nb);
+    gs_update_kernel<MODE><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, nq, K.V.p, K.n * K.nb, w, h, K.part.p,
+                                                                dinv, z, gate);
+    reduce_part_kernel<<<MODE == 0 ? nq : 1, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, MODE == 0 ? nq : 1, K.nb,
+                                                                           K.part.p, out, gate);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t Krylov::ensure(int64_t n_, int nb_, int k_)
@@ -266,8 +399,10 @@ hipError_t Krylov::ensure(int64_t n_, int nb_, int k_)
     hipError_t e;
     if ((e = V.alloc((size_t)(k + 1) * n * nb)) != hipSuccess) return e;
     if ((e = w.alloc((size_t)n * nb)) != hipSuccess) return e;
+    if ((e = w2.alloc((size_t)n * nb)) != hipSuccess) return e;
+    if ((e = z.alloc((size_t)n * nb)) != hipSuccess) return e;
     if ((e = r.alloc((size_t)n * nb)) != hipSuccess) return e;
-    part_blocks = kPartBlocks;
+    part_blocks = kPartBlocks;   // partial-sum rows; vec_launch never exceeds it
     if ((e = part.alloc((size_t)part_blocks * (KP + 1) * nb)) != hipSuccess) return e;
     if ((e = h1.alloc((size_t)(KP + 1) * nb)) != hipSuccess) return e;
     if ((e = h2.alloc((size_t)(KP + 1) * nb)) != hipSuccess) return e;
@@ -276,6 +411,7 @@ hipError_t Krylov::ensure(int64_t n_, int nb_, int k_)
     if ((e = sn.alloc((size_t)nb * k)) != hipSuccess) return e;
     if ((e = g.alloc((size_t)nb * (k + 1))) != hipSuccess) return e;
     if ((e = y.alloc((size_t)k * nb)) != hipSuccess) return e;
+    if ((e = vscale.alloc(nb)) != hipSuccess) return e;
     if ((e = fnorm.alloc(nb)) != hipSuccess) return e;
     if ((e = beta.alloc(nb)) != hipSuccess) return e;
     if ((e = resid.alloc(nb)) != hipSuccess) return e;
@@ -285,116 +421,118 @@ hipError_t Krylov::ensure(int64_t n_, int nb_, int k_)
     if ((e = jend.alloc(nb)) != hipSuccess) return e;
     if ((e = nactive.alloc(1)) != hipSuccess) return e;
     if (!nactive_host) {
-        if ((e = hipHostMalloc((void **)&nactive_host, sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void **)&nactive_host, sizeof(int) * kSlots, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
+            return e;
+        if ((e = hipHostGetDevicePointer((void **)&nactive_hdev, nactive_host, 0)) != hipSuccess) return e;
+        for (int i = 0; i < kSlots; ++i)
+            if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 void Krylov::release()
 {
-    V.release(); w.release(); r.release(); part.release(); h1.release(); h2.release(); H.release();
-    cs.release(); sn.release(); g.release(); y.release(); fnorm.release(); beta.release(); resid.release();
-    active.release(); done.release(); its.release(); jend.release(); nactive.release();
-    if (nactive_host) (void)hipHostFree(nactive_host);
+    V.release(); w.release(); w2.release(); z.release(); r.release(); part.release(); h1.release(); h2.release(); H.release();
+    cs.release(); sn.release(); g.release(); y.release(); vscale.release(); fnorm.release(); beta.release();
+    resid.release(); active.release(); done.release(); its.release(); jend.release(); nactive.release();
+    if (nactive_host) {
+        (void)hipHostFree(nactive_host);
+        for (int i = 0; i < kSlots; ++i)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+    }
     nactive_host = nullptr;
+    nactive_hdev = nullptr;
+    for (int i = 0; i < kSlots; ++i) ev[i] = nullptr;
     n = 0; nb = 0; k = 0;
 }
 
-namespace {
-
-struct Launch {
-    int rpb, threads;
-    unsigned blocks;
-};
-
-Launch vec_launch(int64_t n, int nb, int part_blocks)
-{
-    Launch L;
-    L.rpb = rpb_of(nb);
-    L.threads = L.rpb * nb;
-    int64_t b = (n + L.rpb - 1) / L.rpb;
-    L.blocks = (unsigned)(b < part_blocks ? b : part_blocks);
-    return L;
-}
-
-hipError_t dots(Krylov &K, const double *V, int nq, const double *w, double *out, hipStream_t s)
-{
-    Launch L = vec_launch(K.n, K.nb, K.part_blocks);
-    dots_kernel<<<L.blocks, L.threads, 0, s>>>(K.n, K.nb, nq, V, K.n * K.nb, w, K.part.p);
-    reduce_part_kernel<<<grid_of((int64_t)nq * K.nb), kThreads, 0, s>>>((int)L.blocks, nq, K.nb, K.part.p, out);
-    return hipGetLastError();
-}
-
-template <int MODE>
-hipError_t gs_update(Krylov &K, int nq, const double *h, double *out, hipStream_t s)
-{
-    Launch L = vec_launch(K.n, K.nb, K.part_blocks);
-    gs_update_kernel<MODE><<<L.blocks, L.threads, 0, s>>>(K.n, K.nb, nq, K.V.p, K.n * K.nb, K.w.p, h, K.part.p);
-    reduce_part_kernel<<<grid_of((int64_t)(MODE == 0 ? nq : 1) * K.nb), kThreads, 0, s>>>(
-        (int)L.blocks, MODE == 0 ? nq : 1, K.nb, K.part.p, out);
-    return hipGetLastError();
-}
-
-}  // namespace
-
-int gmres_batched(Problem &P, Krylov &K, OpFn op, void *ctx, const double *dinv, const double *f, double *x,
-                  int64_t n, int nb, double tol, int restart, int max_its, int check_every, bool x_zero,
+int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const double *dinv, const double *f,
+                  double *x, int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero,
                   hipStream_t s, int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged)
 {
-    MLPG_CHECK(nb >= 1 && nb <= 1024, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 1024]");
+    MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
     MLPG_HIP(K.ensure(n, nb, restart));
+    if (lag < 1) lag = 1;
+    if (lag > kSlots - 1) lag = kSlots - 1;
     const int k = restart;
     const int64_t cnt = n * nb;
     const int nbt = ((nb + 63) / 64) * 64;
+    const int *gate = K.nactive.p;
     // ||f||
-    MLPG_HIP(dots(K, f, 1, f, K.beta.p, s));
+    MLPG_HIP(dots(K, f, 1, f, K.beta.p, nullptr, s));
     sqrt_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, K.beta.p, K.fnorm.p);
     MLPG_HIP(hipMemsetAsync(K.its.p, 0, sizeof(int) * nb, s));
     if (x_zero) {
         MLPG_HIP(hipMemsetAsync(x, 0, sizeof(double) * cnt, s));
         MLPG_HIP(hipMemcpyAsync(K.r.p, f, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
     } else {
-        int rc = op(P, x, nullptr, K.r.p, s, ctx);
+        OpCall c;
+        c.in = x;
+        c.out = K.r.p;
+        int rc = op(P, c, s, ctx);
         if (rc) return rc;
         residual_kernel<<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
     }
     int64_t sw = 0;
     for (;;) {
-        MLPG_HIP(dots(K, K.r.p, 1, K.r.p, K.h1.p, s));
+        MLPG_HIP(dots(K, K.r.p, 1, K.r.p, K.h1.p, nullptr, s));
         cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, max_its, K.its.p, K.active.p, K.done.p,
-                                            K.g.p, K.beta.p, K.resid.p, K.jend.p, K.nactive.p);
-        MLPG_HIP(hipMemcpyAsync(K.nactive_host, K.nactive.p, sizeof(int), hipMemcpyDeviceToHost, s));
+                                            K.g.p, K.beta.p, K.resid.p, K.jend.p, K.nactive.p, K.nactive_hdev);
         MLPG_HIP(hipStreamSynchronize(s));
-        if (*K.nactive_host == 0) break;
+        if (K.nactive_host[0] == 0) break;
         init_v0_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.r.p, K.beta.p, K.active.p, K.V.p);
         int jc = 0;
+        double *wcur = K.w.p, *wprev = K.w2.p;
+        const int64_t base = sw;   // sweeps before this cycle
         for (int j = 0; j < k; ++j) {
-            const double *vj = K.V.p + (int64_t)j * cnt;
-            int rc = op(P, vj, dinv, K.w.p, s, ctx);
+            OpCall c;
+            c.dinv = dinv;
+            c.gate = gate;
+            if (j == 0 || !fused) {
+                c.in = K.V.p + (int64_t)j * cnt;
+            } else {
+                // z = dinv .* w of the previous step, scaled by 1/h_{j,j-1};
+                // the SpMV also stores the normalised basis vector V_j
+                c.in = K.z.p;
+                c.dinv = nullptr;
+                c.colscale = K.vscale.p;
+                c.vout = K.V.p + (int64_t)j * cnt;
+                c.vsrc = wprev;
+            }
+            c.out = wcur;
+            int rc = op(P, c, s, ctx);
             if (rc) return rc;
-            MLPG_HIP(dots(K, K.V.p, j + 1, K.w.p, K.h1.p, s));
-            MLPG_HIP(gs_update<0>(K, j + 1, K.h1.p, K.h2.p, s));
-            MLPG_HIP(gs_update<1>(K, j + 1, K.h2.p, K.beta.p + 0, s));
-            // K.beta is reused as ||w||^2 scratch here; cycle_init rewrites it.
+            MLPG_HIP(dots(K, K.V.p, j + 1, wcur, K.h1.p, gate, s));
+            MLPG_HIP(gs_update<0>(K, j + 1, wcur, K.h1.p, K.h2.p, nullptr, nullptr, gate, s));
+            MLPG_HIP(gs_update<1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, fused ? K.z.p : nullptr, gate, s));
+            // K.beta holds ||w||^2 during the cycle; cycle_init rewrites it.
+            const int slot = (int)(sw % kSlots);
             arnoldi_kernel<<<1, nbt, 0, s>>>(nb, k, j, K.h1.p, K.h2.p, K.beta.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
-                                             K.fnorm.p, tol, max_its, K.active.p, K.its.p, K.jend.p, K.y.p,
-                                             K.resid.p, K.nactive.p);
+                                             K.fnorm.p, tol, max_its, K.active.p, K.its.p, K.jend.p, K.vscale.p,
+                                             K.resid.p, K.nactive.p, K.nactive_hdev + slot, gate);
+            MLPG_HIP(hipEventRecord(K.ev[slot], s));
             sw++;
             jc = j + 1;
             if (j == k - 1) break;
-            if ((j + 1) % check_every == 0) {
-                MLPG_HIP(hipMemcpyAsync(K.nactive_host, K.nactive.p, sizeof(int), hipMemcpyDeviceToHost, s));
-                MLPG_HIP(hipStreamSynchronize(s));
-                if (*K.nactive_host == 0) break;
+            if (!fused)
+                normalize_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, wcur, K.vscale.p,
+                                                                   K.V.p + (int64_t)(j + 1) * cnt, gate);
+            std::swap(wcur, wprev);
+            // read the active count of the sweep `lag` steps back (same cycle)
+            const int64_t chk = sw - lag;
+            if (chk >= base) {
+                const int cs = (int)(chk % kSlots);
+                MLPG_HIP(hipEventSynchronize(K.ev[cs]));
+                if (K.nactive_host[cs] == 0) break;
             }
-            // the ||w|| of each system sits in K.y (first nb entries) until lsq
-            normalize_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.w.p, K.y.p, K.active.p,
-                                                               K.V.p + (int64_t)(j + 1) * cnt);
         }
         lsq_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
         x_update_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, cnt, K.y.p, dinv, x);
-        int rc = op(P, x, nullptr, K.r.p, s, ctx);
+        OpCall c;
+        c.in = x;
+        c.out = K.r.p;
+        int rc = op(P, c, s, ctx);
         if (rc) return rc;
         residual_kernel<<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
         MLPG_HIP(hipGetLastError());

@@ -134,59 +134,190 @@ __global__ void jacobi_kernel(int64_t n, int M, int nsL, int nf, const int64_t *
     dinv[t] = d != 0.0 ? 1.0 / d : 1.0;
 }
 
-// Ordinate-batched SpMV.  Thread (row group, m): lanes of one row share the
-// row's stream values (broadcast loads) and each combines them with its own
-// ordinate coefficients held in registers.
-template <int NS>
-__global__ __launch_bounds__(256) void spmv_kernel(int64_t n, int M, const int64_t *__restrict__ row_off,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ vals,
-                                                   const double *__restrict__ coef, const double *__restrict__ x,
-                                                   int x_bcast, const double *__restrict__ x2, double xs,
-                                                   const double *__restrict__ dinv,
-                                                   const double *__restrict__ colscale,
-                                                   const int64_t *__restrict__ soff, const int32_t *__restrict__ scol,
-                                                   const double *__restrict__ sval, const double *__restrict__ coefF,
-                                                   int nf, double *__restrict__ y, const double *__restrict__ yadd,
-                                                   int ysign)
+struct SpmvK {
+    int64_t n;
+    int M;
+    const int64_t *row_off;
+    const int32_t *col;
+    const double *vals;
+    const double *coef;
+    const double *x;
+    int x_bcast;
+    const double *x2;
+    double xs;
+    const double *dinv;
+    const double *colscale;
+    const int64_t *soff;
+    const int32_t *scol;
+    const double *sval;
+    const double *coefF;
+    int nf;
+    double *y;
+    const double *yadd;
+    int ysign;
+    double *vout;
+    const double *vsrc;
+    const int *gate;
+    int64_t items_per_block;   // wave kernel: contiguous items per workgroup
+    int nxcd;                  // workgroups are dealt round-robin to this many dies
+};
+
+// x value of column j for ordinate m, with the optional second input and
+// right preconditioner applied.
+__device__ __forceinline__ double xin(const SpmvK &k, int64_t j, int m)
 {
+    const int64_t o = j * k.M + m;
+    double xv = k.xs * (k.x_bcast ? k.x[j] : k.x[o]);
+    if (k.x2) xv += k.x2[o];
+    if (k.dinv) xv *= k.dinv[o];
+    return xv;
+}
+
+__device__ __forceinline__ void spmv_finish(const SpmvK &k, int64_t i, int m, double acc)
+{
+    const int64_t o = i * k.M + m;
+    const double sc = k.colscale ? k.colscale[m] : 1.0;
+    if (k.vout) k.vout[o] = sc * (k.vsrc ? k.vsrc[o] : k.x[o]);
+    acc *= sc;
+    k.y[o] = k.yadd ? k.yadd[o] + k.ysign * acc : acc;
+}
+
+// Surface rows (few): the outflow blocks weighted by max(0, W.n_f).
+__device__ __forceinline__ double spmv_surface(const SpmvK &k, int64_t i, int m)
+{
+    double acc = 0.0;
+    double cf[6] = {0, 0, 0, 0, 0, 0};
+    for (int f = 0; f < k.nf; ++f) cf[f] = k.coefF[m * k.nf + f];
+    for (int64_t p = k.soff[i]; p < k.soff[i + 1]; ++p) {
+        double a = 0.0;
+        for (int f = 0; f < k.nf; ++f) a += cf[f] * k.sval[p * k.nf + f];
+        acc += a * xin(k, k.scol[p], m);
+    }
+    return acc;
+}
+
+// Wave-per-row SpMV (used when the ordinates fill whole waves): each wave
+// owns one (row, 64-ordinate chunk); the row index is wave-uniform, so the
+// column indices and stream values come through scalar loads, and four
+// nonzeros are gathered at a time so that their x loads overlap.
+__device__ __forceinline__ double bcast(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK k)
+{
+    if (k.gate && *k.gate == 0) return;
+    // Workgroups are dealt round-robin to the dies (XCDs), each with its own
+    // L2; renumber them so that every die walks one contiguous range of rows
+    // and keeps that range's x neighbourhood in its own L2.
+    const int G = gridDim.x, X = k.nxcd;
+    const int bx = blockIdx.x;
+    const int per = G / X;                    // the grid is a multiple of X
+    const int lb = (bx % X) * per + bx / X;
+    const int lane = threadIdx.x & 63;
+    const int nchunk = (k.M + 63) >> 6;
+    const int64_t nitems = k.n * nchunk;
+    const int64_t i0 = (int64_t)lb * k.items_per_block;
+    const int64_t i1 = i0 + k.items_per_block < nitems ? i0 + k.items_per_block : nitems;
+    for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += (blockDim.x >> 6)) {
+        const int64_t iu = __builtin_amdgcn_readfirstlane((int)(item / nchunk));
+        const int chunk = (int)(item - iu * nchunk);
+        const int m = chunk * 64 + lane;
+        const bool on = m < k.M;
+        const int mm = on ? m : 0;
+        double c[NS];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) c[b] = k.coef[mm * NS + b];
+        const int64_t p0 = k.row_off[iu], p1 = k.row_off[iu + 1];
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        for (int64_t pb = p0; pb < p1; pb += 64) {
+            // lane l holds nonzero pb + l: its column and stream values
+            const int cnt = (int)(p1 - pb < 64 ? p1 - pb : 64);
+            const bool has = lane < cnt;
+            const int lcol = has ? k.col[pb + lane] : 0;
+            double lv[NS];
+#pragma unroll
+            for (int b = 0; b < NS; ++b) lv[b] = has ? k.vals[(pb + lane) * NS + b] : 0.0;
+            int q = 0;
+            for (; q + 3 < cnt; q += 4) {
+                const int64_t j0 = __builtin_amdgcn_readlane(lcol, q);
+                const int64_t j1 = __builtin_amdgcn_readlane(lcol, q + 1);
+                const int64_t j2 = __builtin_amdgcn_readlane(lcol, q + 2);
+                const int64_t j3 = __builtin_amdgcn_readlane(lcol, q + 3);
+                const double x0 = xin(k, j0, mm), x1 = xin(k, j1, mm), x2 = xin(k, j2, mm), x3 = xin(k, j3, mm);
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+                for (int b = 0; b < NS; ++b) {
+                    a0 += c[b] * bcast(lv[b], q);
+                    a1 += c[b] * bcast(lv[b], q + 1);
+                    a2 += c[b] * bcast(lv[b], q + 2);
+                    a3 += c[b] * bcast(lv[b], q + 3);
+                }
+                acc0 += a0 * x0;
+                acc1 += a1 * x1;
+                acc2 += a2 * x2;
+                acc3 += a3 * x3;
+            }
+            for (; q < cnt; ++q) {
+                const int64_t j0 = __builtin_amdgcn_readlane(lcol, q);
+                double a0 = 0.0;
+#pragma unroll
+                for (int b = 0; b < NS; ++b) a0 += c[b] * bcast(lv[b], q);
+                acc0 += a0 * xin(k, j0, mm);
+            }
+        }
+        double acc = (acc0 + acc1) + (acc2 + acc3);
+        if (k.soff) acc += spmv_surface(k, iu, mm);
+        if (on) spmv_finish(k, iu, m, acc);
+    }
+}
+
+// Row-group SpMV for small ordinate counts: thread (row group, m); lanes of
+// one row share the row's stream values (broadcast loads).
+template <int NS>
+__global__ __launch_bounds__(256) void spmv_group_kernel(SpmvK k)
+{
+    if (k.gate && *k.gate == 0) return;
+    const int M = k.M;
     const int rpb = blockDim.x / M;
     const int rl = threadIdx.x / M;
     const int m = threadIdx.x - rl * M;
     if (rl >= rpb) return;
     double c[NS];
 #pragma unroll
-    for (int b = 0; b < NS; ++b) c[b] = coef[m * NS + b];
-    double cf[6] = {0, 0, 0, 0, 0, 0};
-    if (soff)
-        for (int f = 0; f < nf; ++f) cf[f] = coefF[m * nf + f];
-    const double sc = colscale ? colscale[m] : 1.0;
-    for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
-        double acc = 0.0;
-        const int64_t p0 = row_off[i], p1 = row_off[i + 1];
-        for (int64_t p = p0; p < p1; ++p) {
-            const int64_t j = col[p];
-            const double *v = vals + p * NS;
+    for (int b = 0; b < NS; ++b) c[b] = k.coef[m * NS + b];
+    for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < k.n; i += (int64_t)gridDim.x * rpb) {
+        const int64_t p0 = k.row_off[i], p1 = k.row_off[i + 1];
+        double acc0 = 0.0, acc1 = 0.0;
+        int64_t p = p0;
+        for (; p + 1 < p1; p += 2) {
+            const int64_t j0 = k.col[p], j1 = k.col[p + 1];
+            const double x0 = xin(k, j0, m), x1 = xin(k, j1, m);
+            const double *v = k.vals + p * NS;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) {
+                a0 += c[b] * v[b];
+                a1 += c[b] * v[NS + b];
+            }
+            acc0 += a0 * x0;
+            acc1 += a1 * x1;
+        }
+        for (; p < p1; ++p) {
+            const double *v = k.vals + p * NS;
             double a = 0.0;
 #pragma unroll
             for (int b = 0; b < NS; ++b) a += c[b] * v[b];
-            double xv = xs * (x_bcast ? x[j] : x[j * M + m]);
-            if (x2) xv += x2[j * M + m];
-            if (dinv) xv *= dinv[j * M + m];
-            acc += a * xv;
+            acc0 += a * xin(k, k.col[p], m);
         }
-        if (soff) {
-            for (int64_t p = soff[i]; p < soff[i + 1]; ++p) {
-                const int64_t j = scol[p];
-                double a = 0.0;
-                for (int f = 0; f < nf; ++f) a += cf[f] * sval[p * nf + f];
-                double xv = xs * (x_bcast ? x[j] : x[j * M + m]);
-                if (x2) xv += x2[j * M + m];
-                if (dinv) xv *= dinv[j * M + m];
-                acc += a * xv;
-            }
-        }
-        acc *= sc;
-        y[i * M + m] = yadd ? yadd[i * M + m] + ysign * acc : acc;
+        double acc = acc0 + acc1;
+        if (k.soff) acc += spmv_surface(k, i, m);
+        spmv_finish(k, i, m, acc);
     }
 }
 
@@ -286,17 +417,37 @@ hipError_t launch_jacobi(Problem &P, hipStream_t s)
 hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s)
 {
     const int M = P.n_ord;
-    const int rpb = rows_per_block(M);
-    const int threads = rpb * M;
-    if (threads > 1024) return hipErrorInvalidValue;
-    int64_t blocks = (P.n + rpb - 1) / rpb;
-    if (blocks > 65536) blocks = 65536;
-    const int64_t *soff = a.surface ? P.surf_off.p : nullptr;
-#define MLPG_SPMV(NSV)                                                                                         \
-    spmv_kernel<NSV><<<(unsigned)blocks, threads, 0, s>>>(P.n, M, P.row_off.p, P.col.p, a.vals, a.coef, a.x,   \
-                                                          a.x_bcast, a.x2, a.xs, a.dinv, a.colscale, soff,      \
-                                                          P.surf_col.p, P.surf_val.p, P.coefF.p, P.nfaces, a.y, \
-                                                          a.yadd, a.ysign)
+    SpmvK k;
+    k.items_per_block = 0;
+    k.nxcd = 8;
+    k.n = P.n; k.M = M; k.row_off = P.row_off.p; k.col = P.col.p; k.vals = a.vals; k.coef = a.coef; k.x = a.x;
+    k.x_bcast = a.x_bcast; k.x2 = a.x2; k.xs = a.xs; k.dinv = a.dinv; k.colscale = a.colscale;
+    k.soff = a.surface ? P.surf_off.p : nullptr; k.scol = P.surf_col.p; k.sval = P.surf_val.p; k.coefF = P.coefF.p;
+    k.nf = P.nfaces; k.y = a.y; k.yadd = a.yadd; k.ysign = a.ysign; k.vout = a.vout; k.vsrc = a.vsrc;
+    k.gate = a.gate;
+    if (a.vout && !a.vsrc && (a.x_bcast || a.x2)) return hipErrorInvalidValue;
+    const bool wave = M >= 48;
+    unsigned blocks;
+    int threads;
+    if (wave) {
+        // 4 waves per workgroup, one item per wave, grid a multiple of the 8 dies
+        threads = 256;
+        const int64_t items = P.n * ((M + 63) / 64);
+        int64_t b = (items + 3) / 4;
+        b = ((b + 7) / 8) * 8;
+        if (b < 8) b = 8;
+        blocks = (unsigned)b;
+        k.nxcd = 8;
+        k.items_per_block = (items + b - 1) / b;
+    } else {
+        const int rpb = rows_per_block(M);
+        threads = rpb * M;
+        int64_t b = (P.n + rpb - 1) / rpb;
+        blocks = (unsigned)(b > 65536 ? 65536 : b);
+    }
+#define MLPG_SPMV(NSV)                                                            \
+    if (wave) spmv_wave_kernel<NSV><<<blocks, threads, 0, s>>>(k);               \
+    else spmv_group_kernel<NSV><<<blocks, threads, 0, s>>>(k)
     switch (a.ns) {
     case 3: MLPG_SPMV(3); break;
     case 4: MLPG_SPMV(4); break;
