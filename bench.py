@@ -76,28 +76,36 @@ def main():
         its = 0
         sweeps = 0
         outer = 0
+        solves = 0
         phi = pv = None
         for s in range(w.steps):
             phi, pv, _, info = P.step(qs[s], None, None, want_psi=False)
             its += info["inner_iters"]
             sweeps += info["inner_sweeps"]
             outer += info["outer_iters"]
+            solves += info["inner_solves"]
         P.close()
-        return its, sweeps, outer, pv
+        return its, sweeps, outer, solves, pv
 
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot_its = tot_sw = tot_out = 0
+    tot_its = tot_sw = tot_out = tot_solves = 0
     pv = None
     for _ in range(args.steps):
-        its, sw, out, pv = one_step()
+        its, sw, out, solves, pv = one_step()
         tot_its += its
         tot_sw += sw
         tot_out += out
+        tot_solves += solves
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # one more step, identical to the timed ones, with HIP events around every
+    # launch of the profiled kernel classes (on the stream they run on)
+    mlpg.mlpg_profile_begin()
+    one_step()
+    prof = mlpg.mlpg_profile_end()
     ms = el / max(args.steps, 1) * 1e3
     value = n * tot_its / el
     ex = W.mms_sin_phi(x, w.steps * w.dt)
@@ -113,9 +121,14 @@ def main():
         "detail": {"inner_iters_per_step": tot_its / max(args.steps, 1),
                    "batched_sweeps_per_step": tot_sw / max(args.steps, 1),
                    "outer_iters_per_step": tot_out / max(args.steps, 1),
-                   "direction_solves_per_s": None,
+                   "direction_solves_per_s": tot_solves * M / el,
+                   "kernel_classes": {k: {"avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
+                                          "launches": v["launches"],
+                                          "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
+                                          "share_of_step": v["ms"] / ms if ms > 0 else None}
+                                      for k, v in prof.items()},
                    "rel_l1_phi_vs_manufactured": err},
-        "roofline": None,
+        "roofline": roofline(prof),
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
@@ -123,10 +136,28 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def cpu_baseline(w, x, R, dx, om, wq, k):
+def roofline(prof):
+    """Dominant kernel class of the profiled step against the HBM peak.
+
+    achieved = algorithmic bytes per launch (each operand once; see the
+    per-class byte model in the library) / average launch duration."""
+    name = max(prof, key=lambda k: prof[k]["ms"])
+    v = prof[name]
+    if v["launches"] == 0 or v["ms"] <= 0:
+        return None
+    avg_s = v["ms"] * 1e-3 / v["launches"]
+    per_launch = v["bytes"] / v["launches"]
+    achieved = per_launch / avg_s / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_launch_us": avg_s * 1e6,
+            "algorithmic_bytes_per_launch": per_launch}
+
+
+def cpu_baseline(w, x, R, dx, om, wq, k, min_seconds=10.0):
     """The oracle on a bounded sample of the same workload: the first-flight
     inner solves L_m^-1 F of the first backward-Euler step for the first k
-    ordinates (one per host thread by default)."""
+    ordinates (all by default), repeated until at least ``min_seconds`` of
+    CPU work has been timed."""
     import oracle
     g = oracle.geometry(x, R, w.lo, w.hi)
     it = oracle.integrate(g, w.rk_order)
@@ -134,13 +165,21 @@ def cpu_baseline(w, x, R, dx, om, wq, k):
     psi0 = W.initial_psi(w, x, om)
     F = tr.rhs(psi0, W.source_values(w, x, om, w.dt), None)
     th = oracle.num_threads()
-    k = k or min(om.shape[0], th)
+    k = k or om.shape[0]
+    its = 0
+    reps = 0
     t0 = time.perf_counter()
-    _, its, _ = tr.inner_solve(F, 0, k)
-    el = time.perf_counter() - t0
+    while True:
+        _, i, _ = tr.inner_solve(F, 0, k)
+        its += i
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
     return {"value": x.shape[0] * its / el, "unit": "DOF*ord*iter/s", "cores": th, "kind": "oracle",
-            "sample": f"first-flight inner GMRES solves of BE step 1, ordinates 0..{k - 1} of {om.shape[0]}, "
-                      f"full {x.shape[0]}-point problem ({its} Arnoldi steps in {el:.1f} s)"}
+            "sample": f"first-flight inner GMRES solves (right-Jacobi GMRES(30) to 1e-13) of BE step 1 for "
+                      f"ordinates 0..{k - 1} of {om.shape[0]}, full {x.shape[0]}-point problem, x{reps}: "
+                      f"{its} Arnoldi steps in {el:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -236,6 +236,23 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
  * coef, out: device [n]. */
 int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing for roofline reports.  Between mlpg_profile_begin and
+ * mlpg_profile_end every launch of the kernel classes below is bracketed by
+ * HIP events on the stream it runs on, and the algorithmic bytes it must
+ * move (each input and output counted once, gathered vectors once) are
+ * accumulated.  Process-wide; not thread-safe.
+ *   class 0: SpMV of the transport operator L (all ordinates)
+ *   class 1: Gram-Schmidt pass 1 (dot products)
+ *   class 2: Gram-Schmidt pass 2 (update + dot products)
+ *   class 3: Gram-Schmidt pass 3 (update + norm)
+ * mlpg_profile_end synchronises the device and fills, per class (arrays of
+ * MLPG_PROF_CLASSES): total kernel time in ms, launch count and bytes.
+ * ---------------------------------------------------------------------- */
+#define MLPG_PROF_CLASSES 4
+int mlpg_profile_begin(void);
+int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
+
 /* Releases the handle and all its device memory (NULL is ignored). */
 void mlpg_destroy(mlpg_handle h);
 

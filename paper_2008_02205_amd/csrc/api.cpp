@@ -34,7 +34,19 @@ int op_L(Problem &P, const OpCall &c, hipStream_t s, void *)
     SpmvArgs a;
     a.vals = P.sL.p; a.ns = P.nsL; a.coef = P.coefL.p; a.x = c.in; a.dinv = c.dinv; a.surface = 1; a.y = c.out;
     a.colscale = c.colscale; a.vout = c.vout; a.vsrc = c.vsrc; a.gate = c.gate;
+    int id = -1;
+    if (prof_on()) {
+        // streams and column indices once, row offsets, x once (plus dinv
+        // when gathered), y written, and the fused normalisation (vsrc read,
+        // vout written); surface rows
+        const double nm = 8.0 * (double)P.n * P.n_ord;
+        double b = (double)P.nnz * (8.0 * P.nsL + 4.0) + 8.0 * (P.n + 1) + nm * (c.dinv ? 2 : 1) + nm;
+        if (c.vout) b += 2.0 * nm;
+        b += (double)P.nnz_s * (8.0 * P.nfaces + 4.0) + 8.0 * (P.n + 1);
+        id = prof_start(0, b, s);
+    }
     MLPG_HIP(launch_spmv(P, a, s));
+    prof_stop(id, s);
     return MLPG_OK;
 }
 

@@ -176,6 +176,11 @@ struct Problem {
     void release();
 };
 
+// Kernel-class timing (mlpg_profile_*): prof_start returns -1 when off.
+bool prof_on();
+int prof_start(int cls, double bytes, hipStream_t s);
+void prof_stop(int id, hipStream_t s);
+
 // ---- kernel launchers -----------------------------------------------------
 hipError_t launch_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *counts,
                                   hipStream_t s);

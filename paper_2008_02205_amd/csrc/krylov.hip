@@ -370,10 +370,20 @@ Launch vec_launch(int64_t n, int nb)
     return L;
 }
 
-hipError_t dots(Krylov &K, const double *V, int nq, const double *w, double *out, const int *gate, hipStream_t s)
+// Algorithmic bytes of one streaming pass: nv vectors of n*nb doubles plus
+// the block partial sums it writes.
+double pass_bytes(const Krylov &K, double nvec, int nq, unsigned blocks)
+{
+    return 8.0 * (nvec * (double)K.n * K.nb + (double)blocks * nq * K.nb);
+}
+
+hipError_t dots(Krylov &K, const double *V, int nq, const double *w, double *out, const int *gate, hipStream_t s,
+                bool timed = false)
 {
     Launch L = vec_launch(K.n, K.nb);
+    int id = timed ? prof_start(1, pass_bytes(K, nq + 1, nq, L.blocks), s) : -1;
     dots_kernel<<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, nq, V, K.n * K.nb, w, K.part.p, gate);
+    prof_stop(id, s);
     reduce_part_kernel<<<nq, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nq, K.nb, K.part.p, out, gate);
     return hipGetLastError();
 }
@@ -383,8 +393,12 @@ hipError_t gs_update(Krylov &K, int nq, double *w, const double *h, double *out,
                      const int *gate, hipStream_t s)
 {
     Launch L = vec_launch(K.n, K.nb);
+    // V_0..V_{nq-1} read, w read and written, (MODE 1) dinv read and z written
+    double nvec = nq + 2 + ((MODE == 1 && z) ? (dinv ? 2 : 1) : 0);
+    int id = prof_start(MODE == 0 ? 2 : 3, pass_bytes(K, nvec, MODE == 0 ? nq : 1, L.blocks), s);
     gs_update_kernel<MODE><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, nq, K.V.p, K.n * K.nb, w, h, K.part.p,
                                                                 dinv, z, gate);
+    prof_stop(id, s);
     reduce_part_kernel<<<MODE == 0 ? nq : 1, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, MODE == 0 ? nq : 1, K.nb,
                                                                            K.part.p, out, gate);
     return hipGetLastError();
@@ -503,7 +517,7 @@ int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const d
             c.out = wcur;
             int rc = op(P, c, s, ctx);
             if (rc) return rc;
-            MLPG_HIP(dots(K, K.V.p, j + 1, wcur, K.h1.p, gate, s));
+            MLPG_HIP(dots(K, K.V.p, j + 1, wcur, K.h1.p, gate, s, true));
             MLPG_HIP(gs_update<0>(K, j + 1, wcur, K.h1.p, K.h2.p, nullptr, nullptr, gate, s));
             MLPG_HIP(gs_update<1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, fused ? K.z.p : nullptr, gate, s));
             // K.beta holds ||w||^2 during the cycle; cycle_init rewrites it.

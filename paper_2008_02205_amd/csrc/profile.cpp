@@ -1,0 +1,87 @@
+// Event timing of kernel classes for roofline reports (mlpg_profile_*).
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mlpg {
+
+namespace {
+
+struct Rec {
+    int cls;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+struct State {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> recs;
+    size_t used = 0;
+};
+
+State g_prof;
+
+hipEvent_t take()
+{
+    if (g_prof.used < g_prof.pool.size()) return g_prof.pool[g_prof.used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+    g_prof.used++;
+    return e;
+}
+
+}  // namespace
+
+bool prof_on() { return g_prof.on; }
+
+int prof_start(int cls, double bytes, hipStream_t s)
+{
+    if (!g_prof.on) return -1;
+    Rec r{cls, bytes, take(), take()};
+    if (!r.a || !r.b || hipEventRecord(r.a, s) != hipSuccess) return -1;
+    g_prof.recs.push_back(r);
+    return (int)g_prof.recs.size() - 1;
+}
+
+void prof_stop(int id, hipStream_t s)
+{
+    if (id < 0) return;
+    (void)hipEventRecord(g_prof.recs[id].b, s);
+}
+
+}  // namespace mlpg
+
+using namespace mlpg;
+
+extern "C" int mlpg_profile_begin(void)
+{
+    g_prof.on = true;
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    return MLPG_OK;
+}
+
+extern "C" int mlpg_profile_end(double *ms, int64_t *launches, double *bytes)
+{
+    MLPG_CHECK(ms && launches && bytes, MLPG_ERR_ARG, "mlpg_profile_end: null output");
+    for (int c = 0; c < MLPG_PROF_CLASSES; ++c) {
+        ms[c] = 0.0;
+        launches[c] = 0;
+        bytes[c] = 0.0;
+    }
+    g_prof.on = false;
+    MLPG_HIP(hipDeviceSynchronize());
+    for (const Rec &r : g_prof.recs) {
+        float t = 0.0f;
+        MLPG_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        if (r.cls < 0 || r.cls >= MLPG_PROF_CLASSES) continue;
+        ms[r.cls] += t;
+        launches[r.cls] += 1;
+        bytes[r.cls] += r.bytes;
+    }
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    return MLPG_OK;
+}

@@ -26,7 +26,7 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_geometry", "mlpg_get_info", "mlpg_get_volumes", "mlpg_cell_capacity", "mlpg_get_cells",
            "mlpg_boundary_points", "mlpg_integrate", "mlpg_get_pattern", "mlpg_get_blocks", "mlpg_assemble",
            "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
-           "mlpg_point_values", "mlpg_destroy"]
+           "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end"]
 
 
 class MlpgError(RuntimeError):
@@ -88,6 +88,8 @@ def lib() -> C.CDLL:
         L.mlpg_point_values.argtypes = [vp, vp, vp, vp]
         L.mlpg_destroy.restype = None
         L.mlpg_destroy.argtypes = [vp]
+        L.mlpg_profile_begin.argtypes = []
+        L.mlpg_profile_end.argtypes = [vp, vp, vp]
         for name in EXPORTS:
             if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy"):
                 getattr(L, name).restype = C.c_int
@@ -282,3 +284,19 @@ def mlpg_point_values(h, coef):
 def mlpg_destroy(h):
     if h is not None and h.value:
         lib().mlpg_destroy(h)
+
+
+PROF_CLASSES = ("spmv_L", "gs_dots", "gs_update_dots", "gs_update_norm")
+
+
+def mlpg_profile_begin():
+    _check(lib().mlpg_profile_begin())
+
+
+def mlpg_profile_end() -> dict:
+    ms = np.zeros(len(PROF_CLASSES))
+    launches = np.zeros(len(PROF_CLASSES), dtype=np.int64)
+    by = np.zeros(len(PROF_CLASSES))
+    _check(lib().mlpg_profile_end(_host(ms), _host(launches), _host(by)))
+    return {name: {"ms": float(ms[c]), "launches": int(launches[c]), "bytes": float(by[c])}
+            for c, name in enumerate(PROF_CLASSES)}
