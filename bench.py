@@ -39,7 +39,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=None, help="lattice points per axis (default 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-ordinates", type=int, default=0, help="ordinates in the CPU sample (0: one per thread)")
+    ap.add_argument("--cpu-ordinates", type=int, default=0, help="ordinates in the CPU sample (0: all)")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
+                    help="fp64: plain FP64 path; mixed: FP32 SpMV/basis inside FP64 refinement")
+    ap.add_argument("--tol-lo", type=float, default=None, help="FP32 correction tolerance of the mixed path")
     return ap.parse_args()
 
 
@@ -68,18 +71,21 @@ def main():
     tau = torch.full((n,), dx, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
 
-    def one_step():
+    def one_step(prec=mlpg.MLPG_FP64):
         P = GpuProblem(x, R, w.lo, w.hi)
         P.integrate(w.rk_order)
-        P.assemble(om, wq, list(w.sigma_t), list(w.sigma_s), w.inv_c_dt, tau)
+        P.assemble(om, wq, list(w.sigma_t), list(w.sigma_s), w.inv_c_dt, tau, precision=prec)
         P.set_state(psi0)
         its = 0
         sweeps = 0
         outer = 0
         solves = 0
         phi = pv = None
+        opts = mlpg.mlpg_default_opts()
+        if args.tol_lo:
+            opts.tol_inner_lo = args.tol_lo
         for s in range(w.steps):
-            phi, pv, _, info = P.step(qs[s], None, None, want_psi=False)
+            phi, pv, _, info = P.step(qs[s], None, opts, want_psi=False)
             its += info["inner_iters"]
             sweeps += info["inner_sweeps"]
             outer += info["outer_iters"]
@@ -87,25 +93,35 @@ def main():
         P.close()
         return its, sweeps, outer, solves, pv
 
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tot_its = tot_sw = tot_out = tot_solves = 0
-    pv = None
-    for _ in range(args.steps):
-        its, sw, out, solves, pv = one_step()
-        tot_its += its
-        tot_sw += sw
-        tot_out += out
-        tot_solves += solves
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    # one more step, identical to the timed ones, with HIP events around every
-    # launch of the profiled kernel classes (on the stream they run on)
-    mlpg.mlpg_profile_begin()
-    one_step()
-    prof = mlpg.mlpg_profile_end()
+    def timed(prec):
+        for _ in range(args.warmup):
+            one_step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot = {"its": 0, "sw": 0, "out": 0, "solves": 0}
+        pv = None
+        for _ in range(args.steps):
+            its, sw, out, solves, pv = one_step(prec)
+            tot["its"] += its
+            tot["sw"] += sw
+            tot["out"] += out
+            tot["solves"] += solves
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        # one more step, identical to the timed ones, with HIP events around every
+        # launch of the profiled kernel classes (on the stream they run on)
+        mlpg.mlpg_profile_begin()
+        one_step(prec)
+        prof = mlpg.mlpg_profile_end()
+        return el, tot, pv, prof
+
+    runs = {}
+    for name, prec in (("fp64", mlpg.MLPG_FP64), ("mixed", mlpg.MLPG_MIXED)):
+        if args.precision in (name, "both"):
+            runs[name] = timed(prec)
+    main_name = "fp64" if "fp64" in runs else "mixed"
+    el, tot, pv, prof = runs[main_name]
+    tot_its, tot_sw, tot_out, tot_solves = tot["its"], tot["sw"], tot["out"], tot["solves"]
     ms = el / max(args.steps, 1) * 1e3
     value = n * tot_its / el
     ex = W.mms_sin_phi(x, w.steps * w.dt)
@@ -131,6 +147,16 @@ def main():
         "roofline": roofline(prof),
         "cpu_baseline": None,
     }
+    if "mixed" in runs and main_name != "mixed":
+        el2, tot2, pv2, prof2 = runs["mixed"]
+        pv_np, pv2_np = pv.cpu().numpy(), pv2.cpu().numpy()
+        rec["detail"]["mixed"] = {
+            "value": n * tot2["its"] / el2, "ms_per_step": el2 / max(args.steps, 1) * 1e3,
+            "direction_solves_per_s": tot2["solves"] * M / el2,
+            "speedup_direction_solves_vs_fp64": (tot2["solves"] * M / el2) / (tot_solves * M / el),
+            "inner_iters_per_step": tot2["its"] / max(args.steps, 1),
+            "rel_l2_phi_point_vs_fp64": float(np.linalg.norm(pv2_np - pv_np) / np.linalg.norm(pv_np)),
+            "roofline": roofline(prof2)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
     print(json.dumps(rec), flush=True)

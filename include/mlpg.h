@@ -174,8 +174,11 @@ int mlpg_get_blocks(mlpg_handle h, double *blocks, double *E, void *stream);
  *   n_ord: 1..256 ordinates; omega: host [n_ord][dim]; w: host [n_ord];
  *   sigma_t, sigma_s: host [n_mat];
  *   tau: device [n] SUPG lengths (Sec. 4.1: about the point spacing);
- *   precision: MLPG_FP64 (FP64 values) or MLPG_MIXED (adds FP32 copies used
- *     by the FP32 inner solver inside FP64 refinement).
+ *   precision: MLPG_FP64 (every inner solve in FP64) or MLPG_MIXED (each
+ *     inner solve is FP64 iterative refinement: the residual f - L_m x is
+ *     formed with FP64 values, and each correction is an FP32 GMRES solve
+ *     with FP32 values, FP32 vectors and FP32 SpMV accumulation, FP64
+ *     Gram-Schmidt sums and Hessenberg; the stopping test is the FP64 one).
  * May be called again with new cross sections, dt or ordinates.
  * ---------------------------------------------------------------------- */
 int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w, int n_mat,
@@ -214,6 +217,8 @@ typedef struct {
     int max_inner;        /* Arnoldi steps per ordinate per solve (default 3000) */
     int max_outer;        /* (default 500) */
     int check_every;      /* Arnoldi steps queued ahead of the host convergence check (default 3) */
+    double tol_inner_lo;  /* MLPG_MIXED: FP32 correction solves stop at this relative residual (default 1e-4) */
+    int max_refine;       /* MLPG_MIXED: FP64 refinement steps per inner solve (default 12) */
 } mlpg_solve_opts;
 
 typedef struct {
@@ -224,6 +229,7 @@ typedef struct {
     double outer_res;            /* final outer relative residual */
     double inner_res_max;        /* largest final inner relative residual */
     int converged;               /* 1 if every solve met its tolerance */
+    int refinements;             /* MLPG_MIXED: FP64 refinement steps summed over inner solves */
 } mlpg_solve_info;
 
 void mlpg_default_opts(mlpg_solve_opts *o);

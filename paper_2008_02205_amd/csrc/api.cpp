@@ -22,7 +22,9 @@ void Problem::release()
     wq.release(); omega.release(); sL.release(); sMD.release(); sMS.release(); coefL.release(); coefMD.release();
     coefF.release(); surf_off.release(); surf_col.release(); surf_val.release(); dinv.release(); psi.release();
     phi.release(); F.release(); bpsi.release(); t1.release(); t2.release(); bphi.release(); ovec.release();
-    inner.release(); outer.release();
+    inner.release(); outer.release(); inner32.release();
+    sL32.release(); coefL32.release(); coefF32.release(); surf_val32.release(); dinv32.release(); r32.release();
+    d32.release(); mr.release(); rn2.release(); fn2.release();
 }
 
 namespace {
@@ -33,6 +35,7 @@ int op_L(Problem &P, const OpCall &c, hipStream_t s, void *)
 {
     SpmvArgs a;
     a.vals = P.sL.p; a.ns = P.nsL; a.coef = P.coefL.p; a.x = c.in; a.dinv = c.dinv; a.surface = 1; a.y = c.out;
+    a.sval = P.surf_val.p; a.coefF = P.coefF.p;
     a.colscale = c.colscale; a.vout = c.vout; a.vsrc = c.vsrc; a.gate = c.gate;
     int id = -1;
     if (prof_on()) {
@@ -50,20 +53,97 @@ int op_L(Problem &P, const OpCall &c, hipStream_t s, void *)
     return MLPG_OK;
 }
 
+// FP32 transport operator for the inner solves of the mixed path: FP32
+// values, FP32 vectors, FP32 accumulation.
+int op_L32(Problem &P, const OpCallT<float> &c, hipStream_t s, void *)
+{
+    SpmvArgsT<float> a;
+    a.vals = P.sL32.p; a.ns = P.nsL; a.coef = P.coefL32.p; a.x = c.in; a.dinv = c.dinv; a.surface = 1;
+    a.sval = P.surf_val32.p; a.coefF = P.coefF32.p; a.y = c.out;
+    a.colscale = c.colscale; a.vout = c.vout; a.vsrc = c.vsrc; a.gate = c.gate;
+    int id = -1;
+    if (prof_on()) {
+        const double nm = 4.0 * (double)P.n * P.n_ord;
+        double b = (double)P.nnz * (4.0 * P.nsL + 4.0) + 8.0 * (P.n + 1) + nm * (c.dinv ? 2 : 1) + nm;
+        if (c.vout) b += 2.0 * nm;
+        b += (double)P.nnz_s * (4.0 * P.nfaces + 4.0) + 8.0 * (P.n + 1);
+        id = prof_start(0, b, s);
+    }
+    MLPG_HIP(launch_spmv<float>(P, a, s));
+    prof_stop(id, s);
+    return MLPG_OK;
+}
+
 struct SolveCounters {
     const mlpg_solve_opts *o;
-    int64_t its = 0, sweeps = 0;
+    int64_t its = 0, sweeps = 0, refinements = 0;
     double res_max = 0.0;
     bool conv = true;
     int solves = 0;
 };
 
+int inner_solve_fp64(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
+{
+    return gmres_batched<double>(P, P.inner, op_L, true, nullptr, P.dinv.p, f, x, P.n, P.n_ord, c.o->tol_inner,
+                                 c.o->restart_inner, c.o->max_inner, c.o->check_every, true, s, &c.its, &c.sweeps,
+                                 &c.res_max, &c.conv);
+}
+
+// Mixed precision: iterative refinement in FP64 around FP32 GMRES.
+//   r = f - L x (FP64 values, FP64 accumulation); per ordinate, the
+//   correction solves L d = r / ||r|| with FP32 GMRES to tol_inner_lo
+//   (FP32 SpMV, FP32 basis, FP64 dot products and Hessenberg); x += ||r|| d.
+// Stops when every ordinate has ||f - L x|| <= tol_inner ||f||.
+int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
+{
+    const int64_t n = P.n;
+    const int M = P.n_ord;
+    const int64_t cnt = n * M;
+    const mlpg_solve_opts &o = *c.o;
+    MLPG_HIP(P.inner.ensure(n, M, o.restart_inner));
+    MLPG_HIP(hipMemsetAsync(x, 0, sizeof(double) * cnt, s));
+    MLPG_HIP(hipMemcpyAsync(P.mr.p, f, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+    MLPG_HIP(batched_norm2(P.inner, f, P.fn2.p, s));
+    std::vector<double> fn2(M), rn2(M);
+    MLPG_HIP(hipMemcpyAsync(fn2.data(), P.fn2.p, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    bool conv = false;
+    double worst = 0.0;
+    for (int it = 0;; ++it) {
+        MLPG_HIP(batched_norm2(P.inner, P.mr.p, P.rn2.p, s));
+        MLPG_HIP(hipMemcpyAsync(rn2.data(), P.rn2.p, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+        MLPG_HIP(hipStreamSynchronize(s));
+        worst = 0.0;
+        conv = true;
+        for (int m = 0; m < M; ++m) {
+            double rel = fn2[m] > 0.0 ? std::sqrt(rn2[m] / fn2[m]) : 0.0;
+            worst = std::max(worst, rel);
+            if (fn2[m] > 0.0 && rel > o.tol_inner) conv = false;
+        }
+        if (conv || it >= o.max_refine) break;
+        MLPG_HIP(launch_to_float_scaled(n, M, P.mr.p, P.rn2.p, P.fn2.p, o.tol_inner, P.r32.p, s));
+        bool c32 = true;
+        double rm32 = 0.0;
+        int rc = gmres_batched<float>(P, P.inner32, op_L32, true, nullptr, P.dinv32.p, P.r32.p, P.d32.p, n, M,
+                                      o.tol_inner_lo, o.restart_inner, o.max_inner, o.check_every, true, s, &c.its,
+                                      &c.sweeps, &rm32, &c32);
+        if (rc) return rc;
+        MLPG_HIP(launch_axpy_from_float(n, M, x, P.d32.p, P.rn2.p, s));
+        SpmvArgs a;
+        a.vals = P.sL.p; a.ns = P.nsL; a.coef = P.coefL.p; a.x = x; a.surface = 1; a.sval = P.surf_val.p;
+        a.coefF = P.coefF.p; a.y = P.mr.p; a.yadd = f; a.ysign = -1;
+        MLPG_HIP(launch_spmv<double>(P, a, s));
+        c.refinements++;
+    }
+    c.res_max = std::max(c.res_max, worst);
+    c.conv = c.conv && conv;
+    return MLPG_OK;
+}
+
 int inner_solve(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
 {
     c.solves++;
-    return gmres_batched(P, P.inner, op_L, true, nullptr, P.dinv.p, f, x, P.n, P.n_ord, c.o->tol_inner,
-                         c.o->restart_inner, c.o->max_inner, c.o->check_every, true, s, &c.its, &c.sweeps, &c.res_max,
-                         &c.conv);
+    if (P.precision == MLPG_MIXED) return inner_solve_mixed(P, c, f, x, s);
+    return inner_solve_fp64(P, c, f, x, s);
 }
 
 // A phi = phi - D L^-1 MS phi  (Eq. krylov-operator)
@@ -78,6 +158,8 @@ int op_outer(Problem &P, const OpCall &oc, hipStream_t s, void *vctx)
     MLPG_HIP(launch_ord_reduce(P, P.t2.p, oc.out, oc.in, -1.0, s));
     return MLPG_OK;
 }
+
+bool P_ok_lo(const mlpg_solve_opts &o) { return o.tol_inner_lo > 0.0 && o.tol_inner_lo < 1.0; }
 
 int check_stage(mlpg_handle h, int need, const char *who)
 {
@@ -361,7 +443,8 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
     MLPG_CHECK(n_mat >= P->n_mat && n_mat <= 8, MLPG_ERR_ARG,
                "mlpg_assemble: n_mat must cover every material of the regions (and be <= 8)");
     MLPG_CHECK(inv_c_dt >= 0.0 && std::isfinite(inv_c_dt), MLPG_ERR_ARG, "mlpg_assemble: 1/(c dt) must be >= 0");
-    MLPG_CHECK(precision == MLPG_FP64, MLPG_ERR_ARG, "mlpg_assemble: only MLPG_FP64 is implemented");
+    MLPG_CHECK(precision == MLPG_FP64 || precision == MLPG_MIXED, MLPG_ERR_ARG,
+               "mlpg_assemble: precision must be MLPG_FP64 or MLPG_MIXED");
     for (int g = 0; g < n_mat; ++g)
         MLPG_CHECK(sigma_t[g] >= 0.0 && sigma_s[g] >= 0.0 && sigma_s[g] <= sigma_t[g], MLPG_ERR_ARG,
                    "mlpg_assemble: need 0 <= sigma_s <= sigma_t");
@@ -420,6 +503,26 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
     MLPG_HIP(launch_surface_fill(*P, nullptr, s));
     MLPG_HIP(P->dinv.alloc((size_t)P->n * n_ord));
     MLPG_HIP(launch_jacobi(*P, s));
+    if (precision == MLPG_MIXED) {
+        // FP32 copies used by the inner FP32 solver (values rounded once)
+        std::vector<float> cL32(cL.begin(), cL.end()), cF32(cF.begin(), cF.end());
+        MLPG_HIP(P->sL32.alloc((size_t)P->nnz * P->nsL));
+        MLPG_HIP(P->coefL32.alloc(cL32.size()));
+        MLPG_HIP(P->coefF32.alloc(cF32.size()));
+        MLPG_HIP(P->surf_val32.alloc(std::max<int64_t>(1, P->nnz_s) * P->nfaces));
+        MLPG_HIP(P->dinv32.alloc((size_t)P->n * n_ord));
+        MLPG_HIP(P->r32.alloc((size_t)P->n * n_ord));
+        MLPG_HIP(P->d32.alloc((size_t)P->n * n_ord));
+        MLPG_HIP(P->mr.alloc((size_t)P->n * n_ord));
+        MLPG_HIP(P->rn2.alloc(n_ord));
+        MLPG_HIP(P->fn2.alloc(n_ord));
+        MLPG_HIP(launch_cast_f32(P->sL.p, P->sL32.p, (int64_t)P->nnz * P->nsL, s));
+        if (P->nnz_s) MLPG_HIP(launch_cast_f32(P->surf_val.p, P->surf_val32.p, P->nnz_s * P->nfaces, s));
+        MLPG_HIP(launch_cast_f32(P->dinv.p, P->dinv32.p, (int64_t)P->n * n_ord, s));
+        MLPG_HIP(hipMemcpyAsync(P->coefL32.p, cL32.data(), sizeof(float) * cL32.size(), hipMemcpyHostToDevice, s));
+        MLPG_HIP(hipMemcpyAsync(P->coefF32.p, cF32.data(), sizeof(float) * cF32.size(), hipMemcpyHostToDevice, s));
+        MLPG_HIP(hipStreamSynchronize(s));   // host staging vectors go out of scope
+    }
     // state and scratch
     size_t nm = (size_t)P->n * n_ord;
     bool fresh = P->psi.count != nm;
@@ -450,7 +553,10 @@ int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *strea
     a.x = X;
     a.y = Y;
     switch (which) {
-    case MLPG_OP_L: a.vals = P->sL.p; a.ns = P->nsL; a.coef = P->coefL.p; a.surface = 1; break;
+    case MLPG_OP_L:
+        a.vals = P->sL.p; a.ns = P->nsL; a.coef = P->coefL.p; a.surface = 1; a.sval = P->surf_val.p;
+        a.coefF = P->coefF.p;
+        break;
     case MLPG_OP_T: a.vals = P->sMD.p; a.ns = P->nsMD; a.coef = P->coefMD.p; a.xs = P->a0; break;
     case MLPG_OP_MS: a.vals = P->sMS.p; a.ns = P->nsMD; a.coef = P->coefMD.p; break;
     case MLPG_OP_SRC: a.vals = P->sMD.p; a.ns = P->nsMD; a.coef = P->coefMD.p; break;
@@ -470,6 +576,8 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->max_inner = 3000;
     o->max_outer = 500;
     o->check_every = 3;
+    o->tol_inner_lo = 1e-4;
+    o->max_refine = 12;
 }
 
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)
@@ -517,8 +625,9 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     MLPG_CHECK(o.restart_inner >= 1 && o.restart_inner <= kMaxRestart && o.restart_outer >= 1 &&
                    o.restart_outer <= kMaxRestart,
                MLPG_ERR_ARG, "mlpg_solve: restart lengths must be in [1, 30]");
-    MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1, MLPG_ERR_ARG,
+    MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1 && o.max_refine >= 0, MLPG_ERR_ARG,
                "mlpg_solve: iteration limits must be positive");
+    MLPG_CHECK(P_ok_lo(o), MLPG_ERR_ARG, "mlpg_solve: tol_inner_lo must be in (0, 1)");
     Problem *P = h;
     hipStream_t s = S(stream);
     const int64_t n = P->n;
@@ -541,7 +650,7 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     int64_t oits = 0, osweeps = 0;
     double ores = 0.0;
     bool oconv = true;
-    rc = gmres_batched(*P, P->outer, op_outer, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1, o.tol_outer,
+    rc = gmres_batched<double>(*P, P->outer, op_outer, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1, o.tol_outer,
                        o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits, &osweeps, &ores, &oconv);
     if (rc) return rc;
     // recovery Psi = L^-1 MS Phi + b_psi
@@ -564,6 +673,7 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
         info->outer_res = ores;
         info->inner_res_max = c.res_max;
         info->converged = (c.conv && oconv) ? 1 : 0;
+        info->refinements = (int)c.refinements;
     }
     if (!(c.conv && oconv)) {
         set_error("mlpg_solve: a Krylov solve reached its iteration limit");

@@ -82,15 +82,18 @@ void gauss_jacobi(int n, double alpha, double *x, double *w);
 enum Counter { kFallbacks = 0, kMissing = 1, kOverflow = 2, kNumCounters = 4 };
 
 // Batched GMRES workspace for `nb` simultaneous systems of `n` unknowns
-// (ordinates as the fastest index).
-struct Krylov {
+// (ordinates as the fastest index); T is the storage type of the basis and
+// vectors (partial sums, Hessenberg and rotations are FP64 either way).
+template <class T>
+struct KrylovT {
     int64_t n = 0;
     int nb = 0;
     int k = 0;
-    DevBuf<double> V;        // [(k+1)][n][nb]
-    DevBuf<double> w, w2;    // [n][nb] operator outputs (alternating)
-    DevBuf<double> z;        // [n][nb] dinv .* w, the next operator input
-    DevBuf<double> r;        // [n][nb]
+    int64_t vs = 0;          // element stride between basis vectors (n*nb plus padding)
+    DevBuf<T> V;             // [(k+1)][vs]
+    DevBuf<T> w, w2;         // [n][nb] operator outputs (alternating)
+    DevBuf<T> z;             // [n][nb] dinv .* w, the next operator input
+    DevBuf<T> r;             // [n][nb]
     DevBuf<double> vscale;   // [nb] 1/h_{j+1,j} of the newest column (0 once a system stops)
     DevBuf<double> part;     // [nblk][k+2][nb] block partial sums
     DevBuf<double> h1, h2;   // [k+1][nb]
@@ -113,6 +116,7 @@ struct Krylov {
     hipError_t ensure(int64_t n_, int nb_, int k_);
     void release();
 };
+using Krylov = KrylovT<double>;
 
 struct Problem {
     int dim = 0;
@@ -171,6 +175,11 @@ struct Problem {
     DevBuf<double> F, bpsi, t1, t2;       // [n][M]
     DevBuf<double> bphi, ovec;            // [n]
     Krylov inner, outer;
+    KrylovT<float> inner32;
+    // mixed precision: FP32 copies of the L streams, coefficients, surface
+    // values and Jacobi scaling; refinement scratch
+    DevBuf<float> sL32, coefL32, coefF32, surf_val32, dinv32, r32, d32;
+    DevBuf<double> mr, rn2, fn2;
     int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
 
     void release();
@@ -199,26 +208,36 @@ hipError_t launch_surface_fill(Problem &P, const double *omega_unused, hipStream
 hipError_t launch_jacobi(Problem &P, hipStream_t s);
 
 // y[i][m] = sum_p (sum_b coef[m][b] vals[p][b]) * xin[col[p]][m]  (+ surface part)
-// with xin = xa*(a_scale) + xb  and optional right preconditioner dinv.
-struct SpmvArgs {
-    const double *vals = nullptr;
+// with xin = xs*x + x2, optional right preconditioner dinv and per-ordinate
+// scale colscale; T is the value/vector type (FP32 accumulates in FP32).
+template <class T>
+struct SpmvArgsT {
+    const T *vals = nullptr;
     int ns = 0;
-    const double *coef = nullptr;     // [M][ns]
-    const double *x = nullptr;        // [n][M] or [n] when x_bcast
+    const T *coef = nullptr;          // [M][ns]
+    const T *x = nullptr;             // [n][M] or [n] when x_bcast
     int x_bcast = 0;
-    const double *x2 = nullptr;       // optional second input added: x_eff = xs*x + x2
-    double xs = 1.0;
-    const double *dinv = nullptr;     // optional [n][M] right preconditioner
+    const T *x2 = nullptr;            // optional second input added: x_eff = xs*x + x2
+    T xs = 1;
+    const T *dinv = nullptr;          // optional [n][M] right preconditioner
     const double *colscale = nullptr; // optional [M] per-ordinate scale of x
     int surface = 0;                  // add sum_f max(0, W.n_f) S_f
-    double *y = nullptr;
-    const double *yadd = nullptr;     // optional: y = yadd - (A x) when set with ysign=-1
+    const T *sval = nullptr;          // surface values [nnz_s][2d] (T copy)
+    const T *coefF = nullptr;         // [M][2d]
+    T *y = nullptr;
+    const T *yadd = nullptr;          // optional: y = yadd + ysign * (A x)
     int ysign = 1;
-    double *vout = nullptr;           // optional: vout[i][m] = colscale[m] vsrc[i][m] on each own row
-    const double *vsrc = nullptr;     //   (vsrc defaults to x)
+    T *vout = nullptr;                // optional: vout[i][m] = colscale[m] vsrc[i][m] on each own row
+    const T *vsrc = nullptr;          //   (vsrc defaults to x)
     const int *gate = nullptr;        // optional: the launch does nothing when *gate == 0
 };
-hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s);
+using SpmvArgs = SpmvArgsT<double>;
+template <class T>
+hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s);
+hipError_t launch_to_float_scaled(int64_t n, int M, const double *r, const double *rn2, const double *fn2, double tol,
+                                  float *out, hipStream_t s);
+hipError_t launch_axpy_from_float(int64_t n, int M, double *x, const float *d, const double *rn2, hipStream_t s);
+hipError_t launch_cast_f32(const double *in, float *out, int64_t count, hipStream_t s);
 hipError_t launch_point_values(Problem &P, const double *coef, double *out, hipStream_t s);
 hipError_t launch_boundary_rhs(Problem &P, const double *psib, double *F, hipStream_t s);
 hipError_t launch_ord_reduce(Problem &P, const double *X, double *out, const double *base, double sign,
@@ -228,20 +247,27 @@ hipError_t launch_add(double *y, const double *a, const double *b, int64_t count
 // Batched GMRES driver.  The operator callback computes out = A(in) for all
 // systems; `precond` (may be null) is the right point-Jacobi scaling.
 // One operator application out = A(dinv .* (colscale .* in)).  When the
-// operator supports it (`fused`), it also writes vout = colscale .* in on its
-// own rows, which normalises the next Krylov vector inside the SpMV.
-struct OpCall {
-    const double *in = nullptr;
-    const double *dinv = nullptr;
+// operator supports it (`fused`), it also writes vout = colscale .* vsrc on
+// its own rows, which normalises the next Krylov vector inside the SpMV.
+template <class T>
+struct OpCallT {
+    const T *in = nullptr;
+    const T *dinv = nullptr;
     const double *colscale = nullptr;
-    double *vout = nullptr;
-    const double *vsrc = nullptr;
-    double *out = nullptr;
+    T *vout = nullptr;
+    const T *vsrc = nullptr;
+    T *out = nullptr;
     const int *gate = nullptr;
 };
-using OpFn = int (*)(Problem &P, const OpCall &c, hipStream_t s, void *ctx);
-int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const double *dinv, const double *f,
-                  double *x, int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero,
-                  hipStream_t s, int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged);
+using OpCall = OpCallT<double>;
+template <class T>
+using OpFnT = int (*)(Problem &P, const OpCallT<T> &c, hipStream_t s, void *ctx);
+using OpFn = OpFnT<double>;
+template <class T>
+int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
+                  int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
+                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged);
+// out[m] = sum_i x[i][m]^2 for the nb systems of K's shape
+hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s);
 
 }  // namespace mlpg

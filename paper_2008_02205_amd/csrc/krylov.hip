@@ -44,97 +44,106 @@ inline int pow2_floor(int v)
     return r;
 }
 
-// Reduce acc[q] (q < nq) over the rpb row groups of the block into
+// Reduce acc[q] (q < NQ) over the rpb row groups of the block into
 // part[blockIdx][q][m], QC values at a time through a fixed-shape LDS tree.
-__device__ __forceinline__ void block_reduce_store(const double (&acc)[KP], int nq, int rpb, int rl, int m, int nb,
+template <int NQ>
+__device__ __forceinline__ void block_reduce_store(const double (&acc)[NQ], int rpb, int rl, int m, int nb,
                                                    double *red, double *part)
 {
 #pragma unroll
-    for (int q0 = 0; q0 < KP; q0 += QC) {
-        if (q0 >= nq) break;
+    for (int q0 = 0; q0 < NQ; q0 += QC) {
 #pragma unroll
         for (int qq = 0; qq < QC; ++qq)
-            if (q0 + qq < KP) red[(rl * QC + qq) * nb + m] = acc[q0 + qq < KP ? q0 + qq : 0];
+            if (q0 + qq < NQ) red[(rl * QC + qq) * nb + m] = acc[q0 + qq < NQ ? q0 + qq : 0];
         __syncthreads();
         for (int s = rpb >> 1; s > 0; s >>= 1) {
             if (rl < s) {
 #pragma unroll
-                for (int qq = 0; qq < QC; ++qq) red[(rl * QC + qq) * nb + m] += red[((rl + s) * QC + qq) * nb + m];
+                for (int qq = 0; qq < QC; ++qq)
+                    if (q0 + qq < NQ) red[(rl * QC + qq) * nb + m] += red[((rl + s) * QC + qq) * nb + m];
             }
             __syncthreads();
         }
         if (rl == 0) {
 #pragma unroll
             for (int qq = 0; qq < QC; ++qq)
-                if (q0 + qq < nq) part[((int64_t)blockIdx.x * (KP + 1) + q0 + qq) * nb + m] = red[qq * nb + m];
+                if (q0 + qq < NQ) part[((int64_t)blockIdx.x * (KP + 1) + q0 + qq) * nb + m] = red[qq * nb + m];
         }
         __syncthreads();
     }
 }
 
-// part[b][q][m] = sum over the block's rows of V_q[i][m] * w[i][m], q < nq.
-__global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, int nq, const double *__restrict__ V,
-                                                           int64_t vstride, const double *__restrict__ w,
+// part[b][q][m] = sum over the block's rows of V_q[i][m] * w[i][m], q < NQ
+// (products and sums in FP64 whatever the storage type T).  NQ is a
+// template argument so that all NQ loads of a row issue back to back.
+template <class T, int NQ>
+__global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, const T *__restrict__ V,
+                                                           int64_t vstride, const T *__restrict__ w,
                                                            double *__restrict__ part, const int *__restrict__ gate)
 {
     extern __shared__ double red[];
     if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
-    double acc[KP];
+    double acc[NQ];
 #pragma unroll
-    for (int q = 0; q < KP; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
         const int64_t o = i * nb + m;
-        const double wv = w[o];
+        T v[NQ];
+        const double wv = (double)w[o];
 #pragma unroll
-        for (int q = 0; q < KP; ++q)
-            if (q < nq) acc[q] += V[q * vstride + o] * wv;
+        for (int q = 0; q < NQ; ++q) v[q] = V[q * vstride + o];
+        // keep every load of the row in flight before the first use (left
+        // alone, the scheduler trades them for registers and serialises them)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] += (double)v[q] * wv;
     }
-    block_reduce_store(acc, nq, rpb, rl, m, nb, red, part);
+    block_reduce_store<NQ>(acc, rpb, rl, m, nb, red, part);
 }
 
 // w -= sum_q h[q][m] V_q ; then part = V^T w (MODE 0) or part[0] = ||w||^2
 // (MODE 1, which also writes z = dinv .* w, the next operator input).
-template <int MODE>
-__global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int nb, int nq,
-                                                                const double *__restrict__ V, int64_t vstride,
-                                                                double *__restrict__ w, const double *__restrict__ h,
+template <class T, int MODE, int NQ>
+__global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int nb, const T *__restrict__ V,
+                                                                int64_t vstride, T *__restrict__ w,
+                                                                const double *__restrict__ h,
                                                                 double *__restrict__ part,
-                                                                const double *__restrict__ dinv,
-                                                                double *__restrict__ z, const int *__restrict__ gate)
+                                                                const T *__restrict__ dinv,
+                                                                T *__restrict__ z, const int *__restrict__ gate)
 {
     extern __shared__ double red[];
     if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
-    double hq[KP], acc[KP];
+    constexpr int NA = MODE == 0 ? NQ : 1;
+    double hq[NQ], acc[NA];
 #pragma unroll
-    for (int q = 0; q < KP; ++q) {
-        hq[q] = (q < nq) ? h[q * nb + m] : 0.0;
-        acc[q] = 0.0;
-    }
+    for (int q = 0; q < NQ; ++q) hq[q] = h[q * nb + m];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
         const int64_t o = i * nb + m;
-        double vq[KP];
-        double wv = w[o];
+        T v[NQ];
+        double wv = (double)w[o];
 #pragma unroll
-        for (int q = 0; q < KP; ++q)
-            if (q < nq) {
-                vq[q] = V[q * vstride + o];
-                wv -= hq[q] * vq[q];
-            }
-        w[o] = wv;
-        if (MODE == 1 && z) z[o] = dinv ? dinv[o] * wv : wv;
+        for (int q = 0; q < NQ; ++q) v[q] = V[q * vstride + o];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) wv -= hq[q] * (double)v[q];
+        const T wt = (T)wv;
+        w[o] = wt;
+        wv = (double)wt;
+        if (MODE == 1 && z) z[o] = dinv ? dinv[o] * wt : wt;
         if (MODE == 0) {
 #pragma unroll
-            for (int q = 0; q < KP; ++q)
-                if (q < nq) acc[q] += vq[q] * wv;
+            for (int q = 0; q < NA; ++q) acc[q] += (double)v[q] * wv;
         } else {
             acc[0] += wv * wv;
         }
     }
-    block_reduce_store(acc, MODE == 0 ? nq : 1, rpb, rl, m, nb, red, part);
+    block_reduce_store<NA>(acc, rpb, rl, m, nb, red, part);
 }
 
 // out[q][m] = sum_b part[b][q][m]: one workgroup per q; threads split the
@@ -286,23 +295,25 @@ __global__ __launch_bounds__(kThreads) void arnoldi_kernel(int nb, int k, int j,
 }
 
 // V_{j+1} = w * vscale (0 for systems that stopped).
-__global__ void normalize_kernel(int64_t n, int nb, const double *__restrict__ w, const double *__restrict__ vscale,
-                                 double *__restrict__ vout, const int *__restrict__ gate)
+template <class T>
+__global__ void normalize_kernel(int64_t n, int nb, const T *__restrict__ w, const double *__restrict__ vscale,
+                                 T *__restrict__ vout, const int *__restrict__ gate)
 {
     if (gate && *gate == 0) return;
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     int m = (int)(t % nb);
-    vout[t] = w[t] * vscale[m];
+    vout[t] = (T)((double)w[t] * vscale[m]);
 }
 
-__global__ void init_v0_kernel(int64_t n, int nb, const double *__restrict__ r, const double *__restrict__ beta,
-                               const int *__restrict__ active, double *__restrict__ v0)
+template <class T>
+__global__ void init_v0_kernel(int64_t n, int nb, const T *__restrict__ r, const double *__restrict__ beta,
+                               const int *__restrict__ active, T *__restrict__ v0)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     int m = (int)(t % nb);
-    v0[t] = active[m] ? r[t] / beta[m] : 0.0;
+    v0[t] = active[m] ? (T)((double)r[t] / beta[m]) : (T)0;
 }
 
 // Least squares: back substitution H y = g over the jend columns.
@@ -323,20 +334,22 @@ __global__ void lsq_kernel(int nb, int k, const double *__restrict__ H, const do
 }
 
 // x += dinv .* (V y)
-__global__ __launch_bounds__(kThreads) void x_update_kernel(int64_t n, int nb, int nq, const double *__restrict__ V,
+template <class T>
+__global__ __launch_bounds__(kThreads) void x_update_kernel(int64_t n, int nb, int nq, const T *__restrict__ V,
                                                             int64_t vstride, const double *__restrict__ y,
-                                                            const double *__restrict__ dinv, double *__restrict__ x)
+                                                            const T *__restrict__ dinv, T *__restrict__ x)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     int m = (int)(t % nb);
     double s = 0.0;
-    for (int q = 0; q < nq; ++q) s += y[q * nb + m] * V[q * vstride + t];
-    x[t] += dinv ? dinv[t] * s : s;
+    for (int q = 0; q < nq; ++q) s += y[q * nb + m] * (double)V[q * vstride + t];
+    x[t] = (T)((double)x[t] + (dinv ? (double)dinv[t] * s : s));
 }
 
 // r = f - r
-__global__ void residual_kernel(int64_t count, const double *__restrict__ f, double *__restrict__ r)
+template <class T>
+__global__ void residual_kernel(int64_t count, const T *__restrict__ f, T *__restrict__ r)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) r[t] = f[t] - r[t];
@@ -370,34 +383,57 @@ Launch vec_launch(int64_t n, int nb)
     return L;
 }
 
-// Algorithmic bytes of one streaming pass: nv vectors of n*nb doubles plus
+// Algorithmic bytes of one streaming pass: nv vectors of n*nb elements plus
 // the block partial sums it writes.
-double pass_bytes(const Krylov &K, double nvec, int nq, unsigned blocks)
+template <class T>
+double pass_bytes(const KrylovT<T> &K, double nvec, int nq, unsigned blocks)
 {
-    return 8.0 * (nvec * (double)K.n * K.nb + (double)blocks * nq * K.nb);
+    return sizeof(T) * nvec * (double)K.n * K.nb + 8.0 * (double)blocks * nq * K.nb;
 }
 
-hipError_t dots(Krylov &K, const double *V, int nq, const double *w, double *out, const int *gate, hipStream_t s,
-                bool timed = false)
+#define MLPG_NQ_CASES(X)                                                                                   \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+    X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
+
+template <class T>
+hipError_t dots(KrylovT<T> &K, const T *V, int nq, const T *w, double *out, const int *gate, hipStream_t s,
+                bool timed = false, int64_t vstride = 0)
 {
+    if (vstride == 0) vstride = K.vs;
+    if (nq < 1 || nq > KP) return hipErrorInvalidValue;
     Launch L = vec_launch(K.n, K.nb);
     int id = timed ? prof_start(1, pass_bytes(K, nq + 1, nq, L.blocks), s) : -1;
-    dots_kernel<<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, nq, V, K.n * K.nb, w, K.part.p, gate);
+    switch (nq) {
+#define MLPG_DOTS_CASE(Q)                                                                                      \
+    case Q:                                                                                                     \
+        dots_kernel<T, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, V, vstride, w, K.part.p, gate);      \
+        break;
+        MLPG_NQ_CASES(MLPG_DOTS_CASE)
+#undef MLPG_DOTS_CASE
+    }
     prof_stop(id, s);
     reduce_part_kernel<<<nq, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nq, K.nb, K.part.p, out, gate);
     return hipGetLastError();
 }
 
-template <int MODE>
-hipError_t gs_update(Krylov &K, int nq, double *w, const double *h, double *out, const double *dinv, double *z,
+template <class T, int MODE>
+hipError_t gs_update(KrylovT<T> &K, int nq, T *w, const double *h, double *out, const T *dinv, T *z,
                      const int *gate, hipStream_t s)
 {
+    if (nq < 1 || nq > KP) return hipErrorInvalidValue;
     Launch L = vec_launch(K.n, K.nb);
     // V_0..V_{nq-1} read, w read and written, (MODE 1) dinv read and z written
     double nvec = nq + 2 + ((MODE == 1 && z) ? (dinv ? 2 : 1) : 0);
     int id = prof_start(MODE == 0 ? 2 : 3, pass_bytes(K, nvec, MODE == 0 ? nq : 1, L.blocks), s);
-    gs_update_kernel<MODE><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, nq, K.V.p, K.n * K.nb, w, h, K.part.p,
-                                                                dinv, z, gate);
+    switch (nq) {
+#define MLPG_GS_CASE(Q)                                                                                        \
+    case Q:                                                                                                     \
+        gs_update_kernel<T, MODE, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, w, h,         \
+                                                                          K.part.p, dinv, z, gate);            \
+        break;
+        MLPG_NQ_CASES(MLPG_GS_CASE)
+#undef MLPG_GS_CASE
+    }
     prof_stop(id, s);
     reduce_part_kernel<<<MODE == 0 ? nq : 1, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, MODE == 0 ? nq : 1, K.nb,
                                                                            K.part.p, out, gate);
@@ -406,12 +442,17 @@ hipError_t gs_update(Krylov &K, int nq, double *w, const double *h, double *out,
 
 }  // namespace
 
-hipError_t Krylov::ensure(int64_t n_, int nb_, int k_)
+template <class T>
+hipError_t KrylovT<T>::ensure(int64_t n_, int nb_, int k_)
 {
     if (n == n_ && nb == nb_ && k == k_ && V.p) return hipSuccess;
     n = n_; nb = nb_; k = k_;
     hipError_t e;
-    if ((e = V.alloc((size_t)(k + 1) * n * nb)) != hipSuccess) return e;
+    // Basis vectors are spaced by n*nb plus an odd number of 128-byte lines so
+    // that the same row of different vectors does not fall into the same
+    // cache set and memory channel (n*nb is often a large power of two).
+    vs = n * nb + (int64_t)(21 * 128 / sizeof(T));
+    if ((e = V.alloc((size_t)(k + 1) * vs)) != hipSuccess) return e;
     if ((e = w.alloc((size_t)n * nb)) != hipSuccess) return e;
     if ((e = w2.alloc((size_t)n * nb)) != hipSuccess) return e;
     if ((e = z.alloc((size_t)n * nb)) != hipSuccess) return e;
@@ -444,7 +485,8 @@ hipError_t Krylov::ensure(int64_t n_, int nb_, int k_)
     return hipSuccess;
 }
 
-void Krylov::release()
+template <class T>
+void KrylovT<T>::release()
 {
     V.release(); w.release(); w2.release(); z.release(); r.release(); part.release(); h1.release(); h2.release(); H.release();
     cs.release(); sn.release(); g.release(); y.release(); vscale.release(); fnorm.release(); beta.release();
@@ -460,9 +502,10 @@ void Krylov::release()
     n = 0; nb = 0; k = 0;
 }
 
-int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const double *dinv, const double *f,
-                  double *x, int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero,
-                  hipStream_t s, int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged)
+template <class T>
+int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
+                  int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
+                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged)
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
@@ -474,52 +517,52 @@ int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const d
     const int nbt = ((nb + 63) / 64) * 64;
     const int *gate = K.nactive.p;
     // ||f||
-    MLPG_HIP(dots(K, f, 1, f, K.beta.p, nullptr, s));
+    MLPG_HIP(dots<T>(K, f, 1, f, K.beta.p, nullptr, s, false, cnt));
     sqrt_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, K.beta.p, K.fnorm.p);
     MLPG_HIP(hipMemsetAsync(K.its.p, 0, sizeof(int) * nb, s));
     if (x_zero) {
-        MLPG_HIP(hipMemsetAsync(x, 0, sizeof(double) * cnt, s));
-        MLPG_HIP(hipMemcpyAsync(K.r.p, f, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+        MLPG_HIP(hipMemsetAsync(x, 0, sizeof(T) * cnt, s));
+        MLPG_HIP(hipMemcpyAsync(K.r.p, f, sizeof(T) * cnt, hipMemcpyDeviceToDevice, s));
     } else {
-        OpCall c;
+        OpCallT<T> c;
         c.in = x;
         c.out = K.r.p;
         int rc = op(P, c, s, ctx);
         if (rc) return rc;
-        residual_kernel<<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
+        residual_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
     }
     int64_t sw = 0;
     for (;;) {
-        MLPG_HIP(dots(K, K.r.p, 1, K.r.p, K.h1.p, nullptr, s));
+        MLPG_HIP(dots<T>(K, K.r.p, 1, K.r.p, K.h1.p, nullptr, s, false, cnt));
         cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, max_its, K.its.p, K.active.p, K.done.p,
                                             K.g.p, K.beta.p, K.resid.p, K.jend.p, K.nactive.p, K.nactive_hdev);
         MLPG_HIP(hipStreamSynchronize(s));
         if (K.nactive_host[0] == 0) break;
-        init_v0_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.r.p, K.beta.p, K.active.p, K.V.p);
+        init_v0_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.r.p, K.beta.p, K.active.p, K.V.p);
         int jc = 0;
-        double *wcur = K.w.p, *wprev = K.w2.p;
+        T *wcur = K.w.p, *wprev = K.w2.p;
         const int64_t base = sw;   // sweeps before this cycle
         for (int j = 0; j < k; ++j) {
-            OpCall c;
+            OpCallT<T> c;
             c.dinv = dinv;
             c.gate = gate;
             if (j == 0 || !fused) {
-                c.in = K.V.p + (int64_t)j * cnt;
+                c.in = K.V.p + (int64_t)j * K.vs;
             } else {
                 // z = dinv .* w of the previous step, scaled by 1/h_{j,j-1};
                 // the SpMV also stores the normalised basis vector V_j
                 c.in = K.z.p;
                 c.dinv = nullptr;
                 c.colscale = K.vscale.p;
-                c.vout = K.V.p + (int64_t)j * cnt;
+                c.vout = K.V.p + (int64_t)j * K.vs;
                 c.vsrc = wprev;
             }
             c.out = wcur;
             int rc = op(P, c, s, ctx);
             if (rc) return rc;
-            MLPG_HIP(dots(K, K.V.p, j + 1, wcur, K.h1.p, gate, s, true));
-            MLPG_HIP(gs_update<0>(K, j + 1, wcur, K.h1.p, K.h2.p, nullptr, nullptr, gate, s));
-            MLPG_HIP(gs_update<1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, fused ? K.z.p : nullptr, gate, s));
+            MLPG_HIP(dots<T>(K, K.V.p, j + 1, wcur, K.h1.p, gate, s, true));
+            MLPG_HIP((gs_update<T, 0>(K, j + 1, wcur, K.h1.p, K.h2.p, nullptr, nullptr, gate, s)));
+            MLPG_HIP((gs_update<T, 1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, fused ? K.z.p : nullptr, gate, s)));
             // K.beta holds ||w||^2 during the cycle; cycle_init rewrites it.
             const int slot = (int)(sw % kSlots);
             arnoldi_kernel<<<1, nbt, 0, s>>>(nb, k, j, K.h1.p, K.h2.p, K.beta.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
@@ -530,8 +573,8 @@ int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const d
             jc = j + 1;
             if (j == k - 1) break;
             if (!fused)
-                normalize_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, wcur, K.vscale.p,
-                                                                   K.V.p + (int64_t)(j + 1) * cnt, gate);
+                normalize_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, wcur, K.vscale.p,
+                                                                      K.V.p + (int64_t)(j + 1) * K.vs, gate);
             std::swap(wcur, wprev);
             // read the active count of the sweep `lag` steps back (same cycle)
             const int64_t chk = sw - lag;
@@ -542,13 +585,13 @@ int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const d
             }
         }
         lsq_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
-        x_update_kernel<<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, cnt, K.y.p, dinv, x);
-        OpCall c;
+        x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, dinv, x);
+        OpCallT<T> c;
         c.in = x;
         c.out = K.r.p;
         int rc = op(P, c, s, ctx);
         if (rc) return rc;
-        residual_kernel<<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
+        residual_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
         MLPG_HIP(hipGetLastError());
     }
     std::vector<int> its(nb), done(nb);
@@ -571,5 +614,19 @@ int gmres_batched(Problem &P, Krylov &K, OpFn op, bool fused, void *ctx, const d
     *converged = *converged && ok;
     return MLPG_OK;
 }
+
+hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s)
+{
+    return dots<double>(K, x, 1, x, out, nullptr, s, false, K.n * K.nb);
+}
+
+template struct KrylovT<double>;
+template struct KrylovT<float>;
+template int gmres_batched<double>(Problem &, KrylovT<double> &, OpFnT<double>, bool, void *, const double *,
+                                   const double *, double *, int64_t, int, double, int, int, int, bool, hipStream_t,
+                                   int64_t *, int64_t *, double *, bool *);
+template int gmres_batched<float>(Problem &, KrylovT<float> &, OpFnT<float>, bool, void *, const float *,
+                                  const float *, float *, int64_t, int, double, int, int, int, bool, hipStream_t,
+                                  int64_t *, int64_t *, double *, bool *);
 
 }  // namespace mlpg

@@ -134,72 +134,77 @@ __global__ void jacobi_kernel(int64_t n, int M, int nsL, int nf, const int64_t *
     dinv[t] = d != 0.0 ? 1.0 / d : 1.0;
 }
 
+template <class T>
 struct SpmvK {
     int64_t n;
     int M;
     const int64_t *row_off;
     const int32_t *col;
-    const double *vals;
-    const double *coef;
-    const double *x;
+    const T *vals;
+    const T *coef;
+    const T *x;
     int x_bcast;
-    const double *x2;
-    double xs;
-    const double *dinv;
+    const T *x2;
+    T xs;
+    const T *dinv;
     const double *colscale;
     const int64_t *soff;
     const int32_t *scol;
-    const double *sval;
-    const double *coefF;
+    const T *sval;
+    const T *coefF;
     int nf;
-    double *y;
-    const double *yadd;
+    T *y;
+    const T *yadd;
     int ysign;
-    double *vout;
-    const double *vsrc;
+    T *vout;
+    const T *vsrc;
     const int *gate;
     int64_t items_per_block;   // wave kernel: contiguous items per workgroup
     int nxcd;                  // workgroups are dealt round-robin to this many dies
 };
 
-// x value of column j for ordinate m, with the optional second input and
-// right preconditioner applied.
-__device__ __forceinline__ double xin(const SpmvK &k, int64_t j, int m)
+// Input modes of the SpMV (compile-time, so that the gathers of one row
+// carry no branches and issue back to back):
+enum { IN_PLAIN = 0, IN_DINV = 1, IN_BCAST = 2, IN_X2 = 3 };
+
+// x value of column j for ordinate m: xs*x, times dinv (IN_DINV), the
+// ordinate-independent x[j] (IN_BCAST), or plus a second input (IN_X2).
+template <int MODE, class T>
+__device__ __forceinline__ T xin(const SpmvK<T> &k, int64_t j, int m)
 {
     const int64_t o = j * k.M + m;
-    double xv = k.xs * (k.x_bcast ? k.x[j] : k.x[o]);
-    if (k.x2) xv += k.x2[o];
-    if (k.dinv) xv *= k.dinv[o];
+    if (MODE == IN_BCAST) return k.xs * k.x[j];
+    T xv = k.xs * k.x[o];
+    if (MODE == IN_X2) xv += k.x2[o];
+    if (MODE == IN_DINV) xv *= k.dinv[o];
     return xv;
 }
 
-__device__ __forceinline__ void spmv_finish(const SpmvK &k, int64_t i, int m, double acc)
+template <class T>
+__device__ __forceinline__ void spmv_finish(const SpmvK<T> &k, int64_t i, int m, T acc)
 {
     const int64_t o = i * k.M + m;
-    const double sc = k.colscale ? k.colscale[m] : 1.0;
+    const T sc = k.colscale ? (T)k.colscale[m] : (T)1;
     if (k.vout) k.vout[o] = sc * (k.vsrc ? k.vsrc[o] : k.x[o]);
     acc *= sc;
-    k.y[o] = k.yadd ? k.yadd[o] + k.ysign * acc : acc;
+    k.y[o] = k.yadd ? k.yadd[o] + (T)k.ysign * acc : acc;
 }
 
 // Surface rows (few): the outflow blocks weighted by max(0, W.n_f).
-__device__ __forceinline__ double spmv_surface(const SpmvK &k, int64_t i, int m)
+template <int MODE, class T>
+__device__ __forceinline__ T spmv_surface(const SpmvK<T> &k, int64_t i, int m)
 {
-    double acc = 0.0;
-    double cf[6] = {0, 0, 0, 0, 0, 0};
+    T acc = 0;
+    T cf[6] = {0, 0, 0, 0, 0, 0};
     for (int f = 0; f < k.nf; ++f) cf[f] = k.coefF[m * k.nf + f];
     for (int64_t p = k.soff[i]; p < k.soff[i + 1]; ++p) {
-        double a = 0.0;
+        T a = 0;
         for (int f = 0; f < k.nf; ++f) a += cf[f] * k.sval[p * k.nf + f];
-        acc += a * xin(k, k.scol[p], m);
+        acc += a * xin<MODE>(k, k.scol[p], m);
     }
     return acc;
 }
 
-// Wave-per-row SpMV (used when the ordinates fill whole waves): each wave
-// owns one (row, 64-ordinate chunk); the row index is wave-uniform, so the
-// column indices and stream values come through scalar loads, and four
-// nonzeros are gathered at a time so that their x loads overlap.
 __device__ __forceinline__ double bcast(double v, int lane)
 {
     const long long b = __double_as_longlong(v);
@@ -208,8 +213,18 @@ __device__ __forceinline__ double bcast(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <int NS>
-__global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK k)
+__device__ __forceinline__ float bcast(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Wave-per-row SpMV (used when the ordinates fill whole waves): each wave
+// owns one (row, 64-ordinate chunk).  The row's column indices and stream
+// values are read with one coalesced load (lane l holds nonzero l of the
+// chunk) and broadcast with readlane, and four x gathers are issued at a
+// time so that their latencies overlap.
+template <int NS, class T, int MODE>
+__global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK<T> k)
 {
     if (k.gate && *k.gate == 0) return;
     // Workgroups are dealt round-robin to the dies (XCDs), each with its own
@@ -230,27 +245,51 @@ __global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK k)
         const int m = chunk * 64 + lane;
         const bool on = m < k.M;
         const int mm = on ? m : 0;
-        double c[NS];
+        T c[NS];
 #pragma unroll
         for (int b = 0; b < NS; ++b) c[b] = k.coef[mm * NS + b];
         const int64_t p0 = k.row_off[iu], p1 = k.row_off[iu + 1];
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
         for (int64_t pb = p0; pb < p1; pb += 64) {
-            // lane l holds nonzero pb + l: its column and stream values
             const int cnt = (int)(p1 - pb < 64 ? p1 - pb : 64);
             const bool has = lane < cnt;
-            const int lcol = has ? k.col[pb + lane] : 0;
-            double lv[NS];
+            // unconditional loads from a clamped index (then a select), so
+            // that the column and the NS values are fetched together
+            const int64_t pl = pb + (has ? lane : 0);
+            int lcol = k.col[pl];
+            T lv[NS];
 #pragma unroll
-            for (int b = 0; b < NS; ++b) lv[b] = has ? k.vals[(pb + lane) * NS + b] : 0.0;
+            for (int b = 0; b < NS; ++b) lv[b] = k.vals[pl * NS + b];
+            lcol = has ? lcol : 0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) lv[b] = has ? lv[b] : (T)0;
             int q = 0;
+            for (; q + 7 < cnt; q += 8) {
+                int64_t jj[8];
+                T xx[8], aa[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) jj[u] = __builtin_amdgcn_readlane(lcol, q + u);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) xx[u] = xin<MODE>(k, jj[u], mm);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    T a = 0;
+#pragma unroll
+                    for (int b = 0; b < NS; ++b) a += c[b] * bcast(lv[b], q + u);
+                    aa[u] = a;
+                }
+                acc0 += aa[0] * xx[0] + aa[4] * xx[4];
+                acc1 += aa[1] * xx[1] + aa[5] * xx[5];
+                acc2 += aa[2] * xx[2] + aa[6] * xx[6];
+                acc3 += aa[3] * xx[3] + aa[7] * xx[7];
+            }
             for (; q + 3 < cnt; q += 4) {
                 const int64_t j0 = __builtin_amdgcn_readlane(lcol, q);
                 const int64_t j1 = __builtin_amdgcn_readlane(lcol, q + 1);
                 const int64_t j2 = __builtin_amdgcn_readlane(lcol, q + 2);
                 const int64_t j3 = __builtin_amdgcn_readlane(lcol, q + 3);
-                const double x0 = xin(k, j0, mm), x1 = xin(k, j1, mm), x2 = xin(k, j2, mm), x3 = xin(k, j3, mm);
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                const T x0 = xin<MODE>(k, j0, mm), x1 = xin<MODE>(k, j1, mm), x2 = xin<MODE>(k, j2, mm), x3 = xin<MODE>(k, j3, mm);
+                T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
                 for (int b = 0; b < NS; ++b) {
                     a0 += c[b] * bcast(lv[b], q);
@@ -265,22 +304,22 @@ __global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK k)
             }
             for (; q < cnt; ++q) {
                 const int64_t j0 = __builtin_amdgcn_readlane(lcol, q);
-                double a0 = 0.0;
+                T a0 = 0;
 #pragma unroll
                 for (int b = 0; b < NS; ++b) a0 += c[b] * bcast(lv[b], q);
-                acc0 += a0 * xin(k, j0, mm);
+                acc0 += a0 * xin<MODE>(k, j0, mm);
             }
         }
-        double acc = (acc0 + acc1) + (acc2 + acc3);
-        if (k.soff) acc += spmv_surface(k, iu, mm);
+        T acc = (acc0 + acc1) + (acc2 + acc3);
+        if (k.soff) acc += spmv_surface<MODE>(k, iu, mm);
         if (on) spmv_finish(k, iu, m, acc);
     }
 }
 
 // Row-group SpMV for small ordinate counts: thread (row group, m); lanes of
 // one row share the row's stream values (broadcast loads).
-template <int NS>
-__global__ __launch_bounds__(256) void spmv_group_kernel(SpmvK k)
+template <int NS, class T, int MODE>
+__global__ __launch_bounds__(256) void spmv_group_kernel(SpmvK<T> k)
 {
     if (k.gate && *k.gate == 0) return;
     const int M = k.M;
@@ -288,18 +327,18 @@ __global__ __launch_bounds__(256) void spmv_group_kernel(SpmvK k)
     const int rl = threadIdx.x / M;
     const int m = threadIdx.x - rl * M;
     if (rl >= rpb) return;
-    double c[NS];
+    T c[NS];
 #pragma unroll
     for (int b = 0; b < NS; ++b) c[b] = k.coef[m * NS + b];
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < k.n; i += (int64_t)gridDim.x * rpb) {
         const int64_t p0 = k.row_off[i], p1 = k.row_off[i + 1];
-        double acc0 = 0.0, acc1 = 0.0;
+        T acc0 = 0, acc1 = 0;
         int64_t p = p0;
         for (; p + 1 < p1; p += 2) {
             const int64_t j0 = k.col[p], j1 = k.col[p + 1];
-            const double x0 = xin(k, j0, m), x1 = xin(k, j1, m);
-            const double *v = k.vals + p * NS;
-            double a0 = 0.0, a1 = 0.0;
+            const T x0 = xin<MODE>(k, j0, m), x1 = xin<MODE>(k, j1, m);
+            const T *v = k.vals + p * NS;
+            T a0 = 0, a1 = 0;
 #pragma unroll
             for (int b = 0; b < NS; ++b) {
                 a0 += c[b] * v[b];
@@ -309,16 +348,41 @@ __global__ __launch_bounds__(256) void spmv_group_kernel(SpmvK k)
             acc1 += a1 * x1;
         }
         for (; p < p1; ++p) {
-            const double *v = k.vals + p * NS;
-            double a = 0.0;
+            const T *v = k.vals + p * NS;
+            T a = 0;
 #pragma unroll
             for (int b = 0; b < NS; ++b) a += c[b] * v[b];
-            acc0 += a * xin(k, k.col[p], m);
+            acc0 += a * xin<MODE>(k, k.col[p], m);
         }
-        double acc = acc0 + acc1;
-        if (k.soff) acc += spmv_surface(k, i, m);
+        T acc = acc0 + acc1;
+        if (k.soff) acc += spmv_surface<MODE>(k, i, m);
         spmv_finish(k, i, m, acc);
     }
+}
+
+// Mixed-precision helpers for the refinement loop.
+__global__ void to_float_scaled_kernel(int64_t n, int M, const double *r, const double *rn2, const double *fn2,
+                                       double tol, float *out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * M) return;
+    int m = (int)(t % M);
+    double rn = sqrt(rn2[m]), fn = sqrt(fn2[m]);
+    out[t] = (rn > tol * fn && rn > 0.0) ? (float)(r[t] / rn) : 0.0f;
+}
+
+__global__ void axpy_from_float_kernel(int64_t n, int M, double *x, const float *d, const double *rn2)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * M) return;
+    int m = (int)(t % M);
+    x[t] += sqrt(rn2[m]) * (double)d[t];
+}
+
+__global__ void cast_f32_kernel(const double *in, float *out, int64_t count)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) out[t] = (float)in[t];
 }
 
 __global__ void point_values_kernel(int64_t n, const int64_t *row_off, const int32_t *col, const double *E,
@@ -414,18 +478,20 @@ hipError_t launch_jacobi(Problem &P, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s)
+template <class T>
+hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
 {
     const int M = P.n_ord;
-    SpmvK k;
+    SpmvK<T> k;
     k.items_per_block = 0;
     k.nxcd = 8;
     k.n = P.n; k.M = M; k.row_off = P.row_off.p; k.col = P.col.p; k.vals = a.vals; k.coef = a.coef; k.x = a.x;
     k.x_bcast = a.x_bcast; k.x2 = a.x2; k.xs = a.xs; k.dinv = a.dinv; k.colscale = a.colscale;
-    k.soff = a.surface ? P.surf_off.p : nullptr; k.scol = P.surf_col.p; k.sval = P.surf_val.p; k.coefF = P.coefF.p;
+    k.soff = a.surface ? P.surf_off.p : nullptr; k.scol = P.surf_col.p; k.sval = a.sval; k.coefF = a.coefF;
     k.nf = P.nfaces; k.y = a.y; k.yadd = a.yadd; k.ysign = a.ysign; k.vout = a.vout; k.vsrc = a.vsrc;
     k.gate = a.gate;
     if (a.vout && !a.vsrc && (a.x_bcast || a.x2)) return hipErrorInvalidValue;
+    if (a.surface && (!a.sval || !a.coefF)) return hipErrorInvalidValue;
     const bool wave = M >= 48;
     unsigned blocks;
     int threads;
@@ -437,7 +503,6 @@ hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s)
         b = ((b + 7) / 8) * 8;
         if (b < 8) b = 8;
         blocks = (unsigned)b;
-        k.nxcd = 8;
         k.items_per_block = (items + b - 1) / b;
     } else {
         const int rpb = rows_per_block(M);
@@ -445,9 +510,21 @@ hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s)
         int64_t b = (P.n + rpb - 1) / rpb;
         blocks = (unsigned)(b > 65536 ? 65536 : b);
     }
+    int mode = IN_PLAIN;
+    if (a.x_bcast) mode = IN_BCAST;
+    if (a.x2) mode = IN_X2;
+    if (a.dinv) mode = IN_DINV;
+    if ((a.x_bcast != 0) + (a.x2 != nullptr) + (a.dinv != nullptr) > 1) return hipErrorInvalidValue;
+#define MLPG_SPMV_M(NSV, MD)                                                      \
+    if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k);        \
+    else spmv_group_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k)
 #define MLPG_SPMV(NSV)                                                            \
-    if (wave) spmv_wave_kernel<NSV><<<blocks, threads, 0, s>>>(k);               \
-    else spmv_group_kernel<NSV><<<blocks, threads, 0, s>>>(k)
+    switch (mode) {                                                               \
+    case IN_PLAIN: MLPG_SPMV_M(NSV, IN_PLAIN); break;                             \
+    case IN_DINV: MLPG_SPMV_M(NSV, IN_DINV); break;                               \
+    case IN_BCAST: MLPG_SPMV_M(NSV, IN_BCAST); break;                             \
+    default: MLPG_SPMV_M(NSV, IN_X2); break;                                      \
+    }
     switch (a.ns) {
     case 3: MLPG_SPMV(3); break;
     case 4: MLPG_SPMV(4); break;
@@ -456,6 +533,30 @@ hipError_t launch_spmv(Problem &P, const SpmvArgs &a, hipStream_t s)
     default: return hipErrorInvalidValue;
     }
 #undef MLPG_SPMV
+#undef MLPG_SPMV_M
+    return hipGetLastError();
+}
+template hipError_t launch_spmv<double>(Problem &, const SpmvArgsT<double> &, hipStream_t);
+template hipError_t launch_spmv<float>(Problem &, const SpmvArgsT<float> &, hipStream_t);
+
+hipError_t launch_to_float_scaled(int64_t n, int M, const double *r, const double *rn2, const double *fn2, double tol,
+                                  float *out, hipStream_t s)
+{
+    int64_t tot = n * M;
+    to_float_scaled_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(n, M, r, rn2, fn2, tol, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_from_float(int64_t n, int M, double *x, const float *d, const double *rn2, hipStream_t s)
+{
+    int64_t tot = n * M;
+    axpy_from_float_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(n, M, x, d, rn2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(const double *in, float *out, int64_t count, hipStream_t s)
+{
+    cast_f32_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(in, out, count);
     return hipGetLastError();
 }
 

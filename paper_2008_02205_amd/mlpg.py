@@ -44,13 +44,13 @@ class Info(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol_inner", C.c_double), ("tol_outer", C.c_double), ("restart_inner", C.c_int),
                 ("restart_outer", C.c_int), ("max_inner", C.c_int), ("max_outer", C.c_int),
-                ("check_every", C.c_int)]
+                ("check_every", C.c_int), ("tol_inner_lo", C.c_double), ("max_refine", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_solves", C.c_int), ("inner_iters", C.c_int64),
                 ("inner_sweeps", C.c_int64), ("outer_res", C.c_double), ("inner_res_max", C.c_double),
-                ("converged", C.c_int)]
+                ("converged", C.c_int), ("refinements", C.c_int)]
 
 
 _lib = None

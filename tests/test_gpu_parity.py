@@ -241,3 +241,53 @@ def test_state_roundtrip_and_errors():
                                         raise_on_error=False)
     assert info["status"] == -4 and info["converged"] == 0
     P.close()
+
+
+def _solve_mixed_vs_oracle(n, M, sig_t, sig_s, inv_c_dt, steps, q_fn, psi0_fn=None):
+    from paper_2008_02205_amd import mlpg
+    x, R, dx = lattice_case(n)
+    g = oracle.geometry(x, R, (0, 0), (1, 1))
+    it = oracle.integrate(g, 1)
+    omega, w = oracle.angular_quadrature(2, M)
+    tr = oracle.Transport(it, omega, w, sig_t, sig_s, inv_c_dt, dx)
+    P = _gpu_problem(x, R, (0, 0), (1, 1))
+    P.integrate(1)
+    P.assemble(omega, w, [sig_t], [sig_s], inv_c_dt, dx, precision=mlpg.MLPG_MIXED)
+    psi_o = psi0_fn(x, omega) if psi0_fn else None
+    phi_o = psi_o @ w if psi_o is not None else None
+    if psi_o is not None:
+        P.set_state(torch.from_numpy(np.ascontiguousarray(psi_o)).cuda())
+    out = []
+    for s in range(1, steps + 1):
+        t = s * (1.0 / inv_c_dt if inv_c_dt > 0 else 0.0)
+        q = q_fn(x, omega, t)
+        psi_o, phi_o, _ = tr.step(psi_o, q, None, phi_o)
+        phi_g, pv_g, psi_g, info = P.step(torch.from_numpy(np.ascontiguousarray(q)).cuda())
+        out.append((rel_l2(_cpu(phi_g), phi_o), rel_l2(_cpu(pv_g), tr.point_values(phi_o)),
+                    rel_l2(_cpu(psi_g), psi_o), info))
+    P.close()
+    return out
+
+
+MIXED_TOL = 1e-8   # relative L2 bar of the mixed path after FP64 refinement
+
+
+@pytest.mark.parametrize("n,M", [(16, 16), (32, 16)])
+def test_mixed_precision_steady(n, M):
+    """FP32 SpMV/basis inside FP64 refinement matches the FP64 oracle (cfg-1 family)."""
+    _print_case("mixed-steady", n=n, M=M)
+    for ephi, epv, epsi, info in _solve_mixed_vs_oracle(
+            n, M, 1.0, 0.5, 0.0, 1, lambda x, om, t: np.ones((x.shape[0], om.shape[0]))):
+        print(f"mixed steady: phi {ephi:.2e} psi {epsi:.2e} refinements {info['refinements']}", flush=True)
+        assert info["converged"] == 1 and info["refinements"] > 0
+        assert ephi <= MIXED_TOL and epv <= MIXED_TOL and epsi <= MIXED_TOL
+
+
+def test_mixed_precision_backward_euler():
+    _print_case("mixed-be", n=16, M=64)
+    for ephi, epv, epsi, info in _solve_mixed_vs_oracle(
+            16, 64, 1.0, 0.5, 100.0, 2, lambda x, om, t: W.mms_sin_source(x, om, t, 1.0, 0.5),
+            psi0_fn=lambda x, om: W.mms_sin_psi(x, om, 0.0)):
+        print(f"mixed BE: phi {ephi:.2e} psi {epsi:.2e} refinements {info['refinements']}", flush=True)
+        assert info["converged"] == 1
+        assert ephi <= MIXED_TOL and epv <= MIXED_TOL and epsi <= MIXED_TOL
