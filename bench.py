@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="fp64: plain FP64 path; mixed: FP32 SpMV/basis inside FP64 refinement")
     ap.add_argument("--tol-lo", type=float, default=None, help="FP32 correction tolerance of the mixed path")
+    ap.add_argument("--probe", action="store_true",
+                    help="hardware-counter probe: setup, one short solve of the workload and a 256 MiB "
+                         "device copy (the reference for counter scaling); prints nothing")
     return ap.parse_args()
 
 
@@ -114,6 +117,22 @@ def main():
         one_step(prec)
         prof = mlpg.mlpg_profile_end()
         return el, tot, pv, prof
+
+    if args.probe:
+        P = GpuProblem(x, R, w.lo, w.hi)
+        P.integrate(w.rk_order)
+        P.assemble(om, wq, list(w.sigma_t), list(w.sigma_s), w.inv_c_dt, tau)
+        P.set_state(psi0)
+        opts = mlpg.mlpg_default_opts()
+        opts.max_inner = 60
+        opts.max_outer = 1
+        mlpg.mlpg_solve(P.h, qs[0], None, opts, want_psi=False, raise_on_error=False)
+        P.close()
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        return
 
     runs = {}
     for name, prec in (("fp64", mlpg.MLPG_FP64), ("mixed", mlpg.MLPG_MIXED)):

@@ -73,8 +73,9 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NQ], int 
     }
 }
 
-// part[b][q][m] = sum over the block's rows of V_q[i][m] * w[i][m], q < NQ
-// (products and sums in FP64 whatever the storage type T).  NQ is a
+// part[b][q][m] = sum over the block's rows of V_q[i][m] * w[i][m], q < NQ,
+// and part[b][NQ][m] = the block's share of ||w_m||^2 (products and sums in
+// FP64 whatever the storage type T).  NQ is a
 // template argument so that all NQ loads of a row issue back to back.
 template <class T, int NQ>
 __global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, const T *__restrict__ V,
@@ -85,9 +86,9 @@ __global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, co
     if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
-    double acc[NQ];
+    double acc[NQ + 1];   // V_q^T w for q < NQ, then ||w||^2
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q <= NQ; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
         const int64_t o = i * nb + m;
         T v[NQ];
@@ -99,28 +100,45 @@ __global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, co
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] += (double)v[q] * wv;
+        acc[NQ] += wv * wv;
     }
-    block_reduce_store<NQ>(acc, rpb, rl, m, nb, red, part);
+    block_reduce_store<NQ + 1>(acc, rpb, rl, m, nb, red, part);
 }
 
-// w -= sum_q h[q][m] V_q ; then part = V^T w (MODE 0) or part[0] = ||w||^2
-// (MODE 1, which also writes z = dinv .* w, the next operator input).
+// Selective reorthogonalisation: a system needs the second Gram-Schmidt
+// pass when the first one cancelled most of w, ||w'|| < 0.7 ||w|| (the
+// "twice is enough" test of Kahan and Parlett).
+__device__ __forceinline__ bool needs_reorth(double s1, double s2) { return s2 < 0.49 * s1; }
+
+// MODE 0: w -= sum_q h1[q][m] V_q, then part = [V^T w, ||w||^2] and
+//         z = dinv .* w (the next operator input when no second pass runs).
+// MODE 1: the second pass, only for the systems that need it (s1, s2 are
+//         ||w||^2 before and after the first pass): w -= sum_q h2[q][m] V_q,
+//         part[0] = ||w||^2, z rewritten.  The whole launch returns at once
+//         when no system needs it.
 template <class T, int MODE, int NQ>
 __global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int nb, const T *__restrict__ V,
                                                                 int64_t vstride, T *__restrict__ w,
                                                                 const double *__restrict__ h,
                                                                 double *__restrict__ part,
                                                                 const T *__restrict__ dinv,
-                                                                T *__restrict__ z, const int *__restrict__ gate)
+                                                                T *__restrict__ z, const double *__restrict__ s1,
+                                                                const double *__restrict__ s2,
+                                                                const int *__restrict__ gate)
 {
     extern __shared__ double red[];
     if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
-    constexpr int NA = MODE == 0 ? NQ : 1;
+    bool mine = true;
+    if (MODE == 1) {
+        mine = needs_reorth(s1[m], s2[m]);
+        if (!__syncthreads_or(mine)) return;
+    }
+    constexpr int NA = MODE == 0 ? NQ + 1 : 1;
     double hq[NQ], acc[NA];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) hq[q] = h[q * nb + m];
+    for (int q = 0; q < NQ; ++q) hq[q] = mine ? h[q * nb + m] : 0.0;
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
@@ -133,12 +151,15 @@ __global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int n
 #pragma unroll
         for (int q = 0; q < NQ; ++q) wv -= hq[q] * (double)v[q];
         const T wt = (T)wv;
-        w[o] = wt;
+        if (MODE == 0 || mine) {
+            w[o] = wt;
+            if (z) z[o] = dinv ? dinv[o] * wt : wt;
+        }
         wv = (double)wt;
-        if (MODE == 1 && z) z[o] = dinv ? dinv[o] * wt : wt;
         if (MODE == 0) {
 #pragma unroll
-            for (int q = 0; q < NA; ++q) acc[q] += (double)v[q] * wv;
+            for (int q = 0; q < NQ; ++q) acc[q] += (double)v[q] * wv;
+            acc[NQ] += wv * wv;
         } else {
             acc[0] += wv * wv;
         }
@@ -151,13 +172,16 @@ __global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int n
 // so that loads overlap), then a fixed-shape tree in LDS (deterministic).
 __global__ __launch_bounds__(kThreads) void reduce_part_kernel(int nblk, int nq, int nb,
                                                                const double *__restrict__ part,
-                                                               double *__restrict__ out, const int *__restrict__ gate)
+                                                               double *__restrict__ out, const int *__restrict__ gate,
+                                                               const double *__restrict__ s1 = nullptr,
+                                                               const double *__restrict__ s2 = nullptr)
 {
     __shared__ double red[kThreads];
     if (gate && *gate == 0) return;
     const int q = blockIdx.x;
     const int ns = blockDim.x / nb;          // strands per system (power of two)
     const int st = threadIdx.x / nb, m = threadIdx.x - st * nb;
+    if (s1 && !__syncthreads_or(needs_reorth(s1[m], s2[m]))) return;
     if (st >= ns) return;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int b = st;
@@ -227,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, con
 // Hessenberg column j, Givens rotations and convergence test per system;
 // the column lives in registers while the earlier rotations are applied.
 __global__ __launch_bounds__(kThreads) void arnoldi_kernel(int nb, int k, int j, const double *__restrict__ h1, const double *__restrict__ h2,
-                               const double *__restrict__ hn2, double *__restrict__ H, double *__restrict__ cs,
+                               const double *__restrict__ hn2_second, double *__restrict__ H, double *__restrict__ cs,
                                double *__restrict__ sn, double *__restrict__ g, const double *__restrict__ fnorm,
                                double tol, int max_its, int *__restrict__ active, int *__restrict__ its,
                                int *__restrict__ jend, double *__restrict__ vscale, double *__restrict__ resid,
@@ -242,12 +266,15 @@ __global__ __launch_bounds__(kThreads) void arnoldi_kernel(int nb, int k, int j,
     if (m < nb && active[m]) {
         double *Hm = H + (int64_t)m * (k + 1) * k;
         double *c = cs + m * k, *s = sn + m * k, *gm = g + m * (k + 1);
-        double hn = sqrt(fmax(hn2[m], 0.0));
+        // h1[j+1] = ||w||^2 before, h2[j+1] = after the first pass; the
+        // second pass ran for this system only when it was needed
+        const bool re = needs_reorth(h1[(j + 1) * nb + m], h2[(j + 1) * nb + m]);
+        double hn = sqrt(fmax(re ? hn2_second[m] : h2[(j + 1) * nb + m], 0.0));
         double col[KP + 1];
         double cq[KP], sq[KP];
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-            col[q] = (q <= j) ? h1[q * nb + m] + h2[q * nb + m] : 0.0;
+            col[q] = (q <= j) ? h1[q * nb + m] + (re ? h2[q * nb + m] : 0.0) : 0.0;
             cq[q] = (q < j) ? c[q] : 1.0;
             sq[q] = (q < j) ? s[q] : 0.0;
         }
@@ -397,7 +424,7 @@ double pass_bytes(const KrylovT<T> &K, double nvec, int nq, unsigned blocks)
 
 template <class T>
 hipError_t dots(KrylovT<T> &K, const T *V, int nq, const T *w, double *out, const int *gate, hipStream_t s,
-                bool timed = false, int64_t vstride = 0)
+                bool timed = false, int64_t vstride = 0, bool norm_row = false)
 {
     if (vstride == 0) vstride = K.vs;
     if (nq < 1 || nq > KP) return hipErrorInvalidValue;
@@ -412,31 +439,34 @@ hipError_t dots(KrylovT<T> &K, const T *V, int nq, const T *w, double *out, cons
 #undef MLPG_DOTS_CASE
     }
     prof_stop(id, s);
-    reduce_part_kernel<<<nq, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nq, K.nb, K.part.p, out, gate);
+    // nq inner products, then ||w||^2 in row nq when norm_row is set
+    const int nr = nq + (norm_row ? 1 : 0);
+    reduce_part_kernel<<<nr, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nr, K.nb, K.part.p, out, gate);
     return hipGetLastError();
 }
 
 template <class T, int MODE>
 hipError_t gs_update(KrylovT<T> &K, int nq, T *w, const double *h, double *out, const T *dinv, T *z,
-                     const int *gate, hipStream_t s)
+                     const double *s1, const double *s2, const int *gate, hipStream_t s)
 {
     if (nq < 1 || nq > KP) return hipErrorInvalidValue;
     Launch L = vec_launch(K.n, K.nb);
-    // V_0..V_{nq-1} read, w read and written, (MODE 1) dinv read and z written
-    double nvec = nq + 2 + ((MODE == 1 && z) ? (dinv ? 2 : 1) : 0);
-    int id = prof_start(MODE == 0 ? 2 : 3, pass_bytes(K, nvec, MODE == 0 ? nq : 1, L.blocks), s);
+    // V_0..V_{nq-1} read, w read and written, dinv read and z written
+    double nvec = nq + 2 + (z ? (dinv ? 2 : 1) : 0);
+    int id = prof_start(MODE == 0 ? 2 : 3, pass_bytes(K, nvec, MODE == 0 ? nq + 1 : 1, L.blocks), s);
     switch (nq) {
 #define MLPG_GS_CASE(Q)                                                                                        \
     case Q:                                                                                                     \
         gs_update_kernel<T, MODE, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, w, h,         \
-                                                                          K.part.p, dinv, z, gate);            \
+                                                                          K.part.p, dinv, z, s1, s2, gate);    \
         break;
         MLPG_NQ_CASES(MLPG_GS_CASE)
 #undef MLPG_GS_CASE
     }
     prof_stop(id, s);
-    reduce_part_kernel<<<MODE == 0 ? nq : 1, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, MODE == 0 ? nq : 1, K.nb,
-                                                                           K.part.p, out, gate);
+    const int nr = MODE == 0 ? nq + 1 : 1;
+    reduce_part_kernel<<<nr, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nr, K.nb, K.part.p, out, gate,
+                                                          MODE == 1 ? s1 : nullptr, MODE == 1 ? s2 : nullptr);
     return hipGetLastError();
 }
 
@@ -560,9 +590,13 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             c.out = wcur;
             int rc = op(P, c, s, ctx);
             if (rc) return rc;
-            MLPG_HIP(dots<T>(K, K.V.p, j + 1, wcur, K.h1.p, gate, s, true));
-            MLPG_HIP((gs_update<T, 0>(K, j + 1, wcur, K.h1.p, K.h2.p, nullptr, nullptr, gate, s)));
-            MLPG_HIP((gs_update<T, 1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, fused ? K.z.p : nullptr, gate, s)));
+            MLPG_HIP(dots<T>(K, K.V.p, j + 1, wcur, K.h1.p, gate, s, true, 0, true));
+            // first pass (z written for every system), then the second pass for
+            // the systems whose first pass cancelled most of w
+            T *zz = fused ? K.z.p : nullptr;
+            const double *s1 = K.h1.p + (int64_t)(j + 1) * nb, *s2 = K.h2.p + (int64_t)(j + 1) * nb;
+            MLPG_HIP((gs_update<T, 0>(K, j + 1, wcur, K.h1.p, K.h2.p, dinv, zz, nullptr, nullptr, gate, s)));
+            MLPG_HIP((gs_update<T, 1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, zz, s1, s2, gate, s)));
             // K.beta holds ||w||^2 during the cycle; cycle_init rewrites it.
             const int slot = (int)(sw % kSlots);
             arnoldi_kernel<<<1, nbt, 0, s>>>(nb, k, j, K.h1.p, K.h2.p, K.beta.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
