@@ -30,6 +30,10 @@ if ROOT not in sys.path:
 import workloads as W  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+# HBM traffic of the operator sweep from the counter passes, valid for the
+# kernel source it was taken on
+COUNTERS = os.path.join(ROOT, "profiles", "counters_spmv_2d_mms_128x128_m64.md")
+SPMV_SOURCE = os.path.join(ROOT, "paper_2008_02205_amd", "csrc", "ops.hip")
 
 
 def parse():
@@ -163,7 +167,7 @@ def main():
                                           "share_of_step": v["ms"] / ms if ms > 0 else None}
                                       for k, v in prof.items()},
                    "rel_l1_phi_vs_manufactured": err},
-        "roofline": roofline(prof),
+        "roofline": roofline(prof, counters=main_name == "fp64"),
         "cpu_baseline": None,
     }
     if "mixed" in runs and main_name != "mixed":
@@ -175,13 +179,13 @@ def main():
             "speedup_direction_solves_vs_fp64": (tot2["solves"] * M / el2) / (tot_solves * M / el),
             "inner_iters_per_step": tot2["its"] / max(args.steps, 1),
             "rel_l2_phi_point_vs_fp64": float(np.linalg.norm(pv2_np - pv_np) / np.linalg.norm(pv_np)),
-            "roofline": roofline(prof2)}
+            "roofline": roofline(prof2, counters=False)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
     print(json.dumps(rec), flush=True)
 
 
-def roofline(prof):
+def roofline(prof, counters=True):
     """Dominant kernel class of the profiled step against the HBM peak.
 
     achieved = algorithmic bytes per launch (each operand once; see the
@@ -194,8 +198,25 @@ def roofline(prof):
     per_launch = v["bytes"] / v["launches"]
     achieved = per_launch / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_launch_us": avg_s * 1e6,
-            "algorithmic_bytes_per_launch": per_launch}
+            "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic() if counters and name == "spmv_L" else None,
+            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": per_launch}
+
+
+def measured_traffic():
+    """HBM bytes per launch of the operator sweep (FETCH_SIZE and WRITE_SIZE
+    scaled against a copy of known size), or None when the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(COUNTERS).read()
+        src = hashlib.sha256(open(SPMV_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    kv = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith(("source_sha256:",
+                                                                                   "traffic_bytes_per_launch:")))
+    if kv.get("source_sha256", "").strip() != src:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(w, x, R, dx, om, wq, k, min_seconds=10.0):

@@ -209,7 +209,7 @@ def config(k: int, scale: Optional[int] = None) -> Workload:
         return Workload("2d-beam-void-opaque", 2, (0.0, 0.0), (2.0, 1.0), None, 0.0, 2.0, 1,
                         256, "beam-dense", (1e-4, 100.0), (0.0, 99.0),
                         (((1.0, 0.0), (2.0, 1.0), 1),), 10, 0.05, 1.0, "none", "beam",
-                        SEED_BASE + 4, pd_radius=0.0046)
+                        SEED_BASE + 4, pd_radius=0.00438)
     raise ValueError(k)
 
 
