@@ -79,6 +79,13 @@ def _declare(L):
     L.orc_cells2d.restype = C.c_int64
     L.orc_cells2d.argtypes = [C.c_int64, _dp, _dp, _i64p, _i32p, _dp, _dp, C.c_int, _i32p, _dp, _i32p,
                               _dp, _dp]
+    L.orc_cells3d.restype = C.c_int64
+    L.orc_cells3d.argtypes = [C.c_int64, _dp, _dp, _i64p, _i32p, _dp, _dp, C.c_int64, _i64p, C.c_int, C.c_int,
+                              _i32p, _i32p, _dp, _i32p, _dp, _dp]
+    L.orc_integrate3d.restype = C.c_int64
+    L.orc_integrate3d.argtypes = [C.POINTER(IntegCtx), C.c_int, C.c_int, _i32p, _i32p, _dp, _i32p, C.c_int, _dp,
+                                  _dp, C.c_int, _dp, _dp, _dp, C.c_int64, C.c_int, _dp, _i32p, _dp, _i32p,
+                                  _i32p, _dp, _i64p]
     L.orc_rk_eval.restype = C.c_int
     L.orc_rk_eval.argtypes = [C.c_int, C.c_int, _dp, C.c_int, _i32p, _dp, _dp, _dp, C.c_double, _dp, _dp]
     L.orc_num_blocks.restype = C.c_int
@@ -277,6 +284,36 @@ def cells2d(x, R, off, idx, dom_lo, dom_hi, cap: int = 64) -> Cells2D:
     return Cells2D(nv, verts, tags, V, rho, int(bad), cap)
 
 
+@dataclass
+class Cells3D:
+    nf: np.ndarray       # [m] faces per cell
+    fnv: np.ndarray      # [m][fcap] vertices per face
+    fverts: np.ndarray   # [m][fcap][vcap][3], counter-clockwise seen from outside
+    ftags: np.ndarray    # [m][fcap]
+    V: np.ndarray
+    rho: np.ndarray
+    failed: int
+    fcap: int
+    vcap: int
+
+
+def cells3d(x, R, off, idx, dom_lo, dom_hi, ids=None, fcap: int = 64, vcap: int = 32) -> Cells3D:
+    """3D cells (Sec. 3.1) of the points ``ids`` (all points by default)."""
+    x = _f64(x); R = _f64(R)
+    n = x.shape[0]
+    ids_a = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
+    m = n if ids_a is None else ids_a.size
+    nf = np.zeros(m, dtype=np.int32)
+    fnv = np.zeros((m, fcap), dtype=np.int32)
+    fverts = np.zeros((m, fcap, vcap, 3))
+    ftags = np.zeros((m, fcap), dtype=np.int32)
+    V = np.zeros(m); rho = np.zeros(m)
+    bad = lib().orc_cells3d(n, _p(x), _p(R), _p(off, _i64p), _p(idx, _i32p), _p(_f64(dom_lo)), _p(_f64(dom_hi)),
+                            m, _p(ids_a, _i64p), fcap, vcap, _p(nf, _i32p), _p(fnv, _i32p), _p(fverts),
+                            _p(ftags, _i32p), _p(V), _p(rho))
+    return Cells3D(nf, fnv, fverts, ftags, V, rho, int(bad), fcap, vcap)
+
+
 def num_blocks(dim: int, n_mat: int) -> int:
     return n_mat * (1 + dim) + dim * dim + 2 * dim
 
@@ -312,7 +349,7 @@ class Geometry:
     dom_hi: np.ndarray
     nb_off: np.ndarray
     nb_idx: np.ndarray
-    cells: Cells2D
+    cells: object            # Cells2D or Cells3D
     row_off: np.ndarray = None
     col: np.ndarray = None
 
@@ -328,9 +365,10 @@ class Geometry:
 def geometry(x, R, dom_lo, dom_hi) -> Geometry:
     x = _f64(x); R = _f64(R)
     off, idx = neighbors(x, R)
-    if x.shape[1] != 2:
-        raise NotImplementedError("3D cells")
-    cl = cells2d(x, R, off, idx, dom_lo, dom_hi)
+    if x.shape[1] == 2:
+        cl = cells2d(x, R, off, idx, dom_lo, dom_hi)
+    else:
+        cl = cells3d(x, R, off, idx, dom_lo, dom_hi)
     g = Geometry(x.shape[1], x, R, _f64(dom_lo), _f64(dom_hi), off, idx, cl)
     g.row_off, g.col = pattern(g.n, off, idx)
     return g
@@ -361,10 +399,18 @@ class Integrated:
         return self.bq_y.shape[0]
 
 
-def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int = 5, seg_n: int = 5,
-              kmax: int = 64) -> Integrated:
-    """Blocks of Alg. 1 over all cells; boundary quadrature points; point-value matrix E."""
+def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int = None, seg_n: int = 5,
+              kmax: int = None, tet_n: int = 2) -> Integrated:
+    """Blocks of Alg. 1 over all cells; boundary quadrature points; point-value matrix E.
+
+    Rules: 2D, triangle rule n = 5 (25 points) in the cells and line rule
+    seg_n on domain edges; 3D, tetrahedron rule n = 2 (8 points) in the
+    cells and triangle rule n = 2 (4 points) on domain faces."""
     d = g.dim
+    if tri_n is None:
+        tri_n = 5 if d == 2 else 2
+    if kmax is None:
+        kmax = 64 if d == 2 else 128
     nnz = int(g.row_off[-1])
     nblk = num_blocks(d, n_mat)
     blocks = np.zeros((nblk, nnz))
@@ -377,20 +423,35 @@ def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int
                   _p(g.nb_idx, _i32p), _p(g.row_off, _i64p), _p(g.col, _i32p), nnz, len(regions),
                   _p(reg_lo), _p(reg_hi), _p(reg_mat, _i32p), _p(blocks), 0, 0)
     tp, tw = triangle_rule(tri_n)
-    sp, sw = segment_rule(seg_n)
-    tp = _f64(tp); tw = _f64(tw); sp = _f64(sp); sw = _f64(sw)
+    tp = _f64(tp); tw = _f64(tw)
     cl = g.cells
-    # upper bound on boundary points: every domain-tagged edge times the line rule
-    nbe = int(np.sum((cl.tags <= -1) & (cl.tags >= -4) & (np.arange(cl.cap)[None, :] < cl.nv[:, None])))
-    cap = nbe * seg_n
+    if d == 2:
+        sp, sw = segment_rule(seg_n)
+        sp = _f64(sp); sw = _f64(sw)
+        # upper bound on boundary points: every domain-tagged edge times the line rule
+        nbe = int(np.sum((cl.tags <= -1) & (cl.tags >= -4) & (np.arange(cl.cap)[None, :] < cl.nv[:, None])))
+        cap = nbe * seg_n
+    else:
+        qp, qw = tet_rule(tet_n)
+        qp = _f64(qp); qw = _f64(qw)
+        live = np.arange(cl.fcap)[None, :] < cl.nf[:, None]
+        dom = live & (cl.ftags <= -1) & (cl.ftags >= -6)
+        cap = int(np.sum(np.where(dom, np.maximum(cl.fnv - 2, 0), 0))) * tp.shape[0]
     bq_y = np.zeros((max(cap, 1), d)); bq_face = np.zeros(max(cap, 1), dtype=np.int32)
     bq_w = np.zeros(max(cap, 1)); bq_nact = np.zeros(max(cap, 1), dtype=np.int32)
     bq_act = np.zeros((max(cap, 1), kmax), dtype=np.int32); bq_N = np.zeros((max(cap, 1), kmax))
     stats = np.zeros(4, dtype=np.int64)
-    nbq = lib().orc_integrate2d(C.byref(ic), cl.cap, _p(cl.nv, _i32p), _p(cl.verts), _p(cl.tags, _i32p),
-                                tp.shape[0], _p(tp), _p(tw), sp.shape[0], _p(sp), _p(sw), _p(E), cap, kmax,
-                                _p(bq_y), _p(bq_face, _i32p), _p(bq_w), _p(bq_nact, _i32p),
-                                _p(bq_act, _i32p), _p(bq_N), _p(stats, _i64p))
+    if d == 2:
+        nbq = lib().orc_integrate2d(C.byref(ic), cl.cap, _p(cl.nv, _i32p), _p(cl.verts), _p(cl.tags, _i32p),
+                                    tp.shape[0], _p(tp), _p(tw), sp.shape[0], _p(sp), _p(sw), _p(E), cap, kmax,
+                                    _p(bq_y), _p(bq_face, _i32p), _p(bq_w), _p(bq_nact, _i32p),
+                                    _p(bq_act, _i32p), _p(bq_N), _p(stats, _i64p))
+    else:
+        nbq = lib().orc_integrate3d(C.byref(ic), cl.fcap, cl.vcap, _p(cl.nf, _i32p), _p(cl.fnv, _i32p),
+                                    _p(cl.fverts), _p(cl.ftags, _i32p), qp.shape[0], _p(qp), _p(qw),
+                                    tp.shape[0], _p(tp), _p(tw), _p(E), cap, kmax, _p(bq_y),
+                                    _p(bq_face, _i32p), _p(bq_w), _p(bq_nact, _i32p), _p(bq_act, _i32p),
+                                    _p(bq_N), _p(stats, _i64p))
     assert nbq <= cap
     if np.any(bq_nact[:nbq] >= kmax):
         raise RuntimeError("boundary point with more active functions than kmax")

@@ -178,6 +178,228 @@ int64_t orc_cells2d(int64_t n, const double *x, const double *R, const int64_t *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Voronoi-like cells in 3D (Sec. 3.1, the three-dimensional case).  The
+ * polyhedron starts as the box [x_i - R_i, x_i + R_i]^3 intersected with the
+ * domain box and is clipped by the half-space on x_i's side of the bisector
+ * plane of x_i and every overlap neighbour x_j.  It is stored as a list of
+ * convex faces; each face is a polygon whose vertices run counter-clockwise
+ * seen from outside the cell, and carries a tag as in 2D:
+ *   tag >= 0 : face on the bisector with neighbour tag
+ *   tag = -1 - a : face on domain face a (0:-x 1:+x 2:-y 3:+y 4:-z 5:+z)
+ *   tag = ORC_TAG_BOX : face of the kernel box not on the domain.
+ * One clip: every face is clipped as a polygon (vertices with n.y - off <= 0
+ * are kept; a crossing edge is cut at the point computed from its kept end),
+ * faces left with fewer than three vertices are dropped, and the cut points
+ * (together with kept vertices lying exactly on the plane) form the new face
+ * on the plane.  Its vertices are put in lexicographic order, duplicates are
+ * removed, and they are ordered by angle around the plane normal about their
+ * centroid; the angle is the "diamond" pseudo-angle (a monotone function of
+ * the angle using only arithmetic).  A plane that leaves every vertex kept
+ * changes nothing.                                                         */
+/* ------------------------------------------------------------------------ */
+#define ORC_FCAP3 64
+#define ORC_VCAP3 32
+
+typedef struct {
+    int nf;
+    int nv[ORC_FCAP3];
+    int32_t tag[ORC_FCAP3];
+    double v[ORC_FCAP3][ORC_VCAP3][3];
+} orc_poly3;
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static int lex_less3(const double *a, const double *b)
+{
+    if (a[0] != b[0]) return a[0] < b[0];
+    if (a[1] != b[1]) return a[1] < b[1];
+    return a[2] < b[2];
+}
+
+/* pseudo-angle in [0, 4) of (dx, dy), increasing with the polar angle */
+static double diamond_angle(double dx, double dy)
+{
+    if (dy >= 0.0) return dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (-dx + dy);
+    return dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+}
+
+static void box_poly3(orc_poly3 *P, const double *lo, const double *hi, const int32_t *t)
+{
+    /* corner (b0,b1,b2) with b = 0 for lo, 1 for hi; faces -x,+x,-y,+y,-z,+z */
+    static const int fc[6][4][3] = {
+        {{0, 0, 0}, {0, 0, 1}, {0, 1, 1}, {0, 1, 0}}, {{1, 0, 0}, {1, 1, 0}, {1, 1, 1}, {1, 0, 1}},
+        {{0, 0, 0}, {1, 0, 0}, {1, 0, 1}, {0, 0, 1}}, {{0, 1, 0}, {0, 1, 1}, {1, 1, 1}, {1, 1, 0}},
+        {{0, 0, 0}, {0, 1, 0}, {1, 1, 0}, {1, 0, 0}}, {{0, 0, 1}, {1, 0, 1}, {1, 1, 1}, {0, 1, 1}}};
+    P->nf = 6;
+    for (int f = 0; f < 6; ++f) {
+        P->nv[f] = 4;
+        P->tag[f] = t[f];
+        for (int k = 0; k < 4; ++k)
+            for (int a = 0; a < 3; ++a) P->v[f][k][a] = fc[f][k][a] ? hi[a] : lo[a];
+    }
+}
+
+/* Clip P by { y : nrm . y - off <= 0 }; the new face gets newtag.  Returns 0,
+ * or -1 when a capacity is exceeded.  tmp is scratch of the same size.     */
+static int clip_poly3(orc_poly3 *P, orc_poly3 *tmp, const double *nrm, double off, int32_t newtag)
+{
+    int any_out = 0;
+    for (int f = 0; f < P->nf; ++f)
+        for (int k = 0; k < P->nv[f]; ++k)
+            if (dot3(nrm, P->v[f][k]) - off > 0.0) any_out = 1;
+    if (!any_out) return 0;
+    double cuts[4 * ORC_VCAP3][3];
+    int ncut = 0;
+    tmp->nf = 0;
+    for (int f = 0; f < P->nf; ++f) {
+        int nv = P->nv[f], no = 0;
+        double(*out)[3] = tmp->v[tmp->nf];
+        for (int k = 0; k < nv; ++k) {
+            const double *A = P->v[f][k], *B = P->v[f][(k + 1) % nv];
+            double sa = dot3(nrm, A) - off, sb = dot3(nrm, B) - off;
+            if (sa <= 0.0) {
+                if (no >= ORC_VCAP3) return -1;
+                memcpy(out[no++], A, sizeof(double) * 3);
+                if (sa == 0.0) {
+                    if (ncut >= 4 * ORC_VCAP3) return -1;
+                    memcpy(cuts[ncut++], A, sizeof(double) * 3);
+                }
+            }
+            if ((sa < 0.0 && sb > 0.0) || (sa > 0.0 && sb < 0.0)) {
+                const double *I = sa < 0.0 ? A : B, *O = sa < 0.0 ? B : A;   /* kept end, removed end */
+                double si = sa < 0.0 ? sa : sb, so = sa < 0.0 ? sb : sa;
+                double t = si / (si - so);
+                double c[3] = {I[0] + t * (O[0] - I[0]), I[1] + t * (O[1] - I[1]), I[2] + t * (O[2] - I[2])};
+                if (no >= ORC_VCAP3 || ncut >= 4 * ORC_VCAP3) return -1;
+                memcpy(out[no++], c, sizeof(c));
+                memcpy(cuts[ncut++], c, sizeof(c));
+            }
+        }
+        if (no >= 3) {
+            tmp->nv[tmp->nf] = no;
+            tmp->tag[tmp->nf] = P->tag[f];
+            tmp->nf++;
+        }
+    }
+    /* the new face: sort the cut points, drop duplicates, order by angle */
+    for (int a = 1; a < ncut; ++a)
+        for (int b = a; b > 0 && lex_less3(cuts[b], cuts[b - 1]); --b) {
+            double s[3];
+            memcpy(s, cuts[b], sizeof(s));
+            memcpy(cuts[b], cuts[b - 1], sizeof(s));
+            memcpy(cuts[b - 1], s, sizeof(s));
+        }
+    int nu = 0;
+    for (int a = 0; a < ncut; ++a)
+        if (nu == 0 || memcmp(cuts[a], cuts[nu - 1], sizeof(double) * 3) != 0) memcpy(cuts[nu++], cuts[a], sizeof(double) * 3);
+    if (nu >= 3) {
+        if (tmp->nf >= ORC_FCAP3 || nu > ORC_VCAP3) return -1;
+        double g[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < nu; ++a)
+            for (int d = 0; d < 3; ++d) g[d] += cuts[a][d];
+        for (int d = 0; d < 3; ++d) g[d] /= nu;
+        int ax = 0;   /* axis least aligned with the normal (first on ties) */
+        for (int d = 1; d < 3; ++d)
+            if (fabs(nrm[d]) < fabs(nrm[ax])) ax = d;
+        double e[3] = {0.0, 0.0, 0.0}, u[3], v[3];
+        e[ax] = 1.0;
+        cross3(nrm, e, u);
+        cross3(nrm, u, v);
+        double ang[4 * ORC_VCAP3];
+        for (int a = 0; a < nu; ++a) {
+            double r[3] = {cuts[a][0] - g[0], cuts[a][1] - g[1], cuts[a][2] - g[2]};
+            ang[a] = diamond_angle(dot3(u, r), dot3(v, r));
+        }
+        /* stable insertion sort by angle (ties keep lexicographic order) */
+        int ord[4 * ORC_VCAP3];
+        for (int a = 0; a < nu; ++a) ord[a] = a;
+        for (int a = 1; a < nu; ++a)
+            for (int b = a; b > 0 && ang[ord[b]] < ang[ord[b - 1]]; --b) {
+                int s = ord[b]; ord[b] = ord[b - 1]; ord[b - 1] = s;
+            }
+        for (int a = 0; a < nu; ++a) memcpy(tmp->v[tmp->nf][a], cuts[ord[a]], sizeof(double) * 3);
+        tmp->nv[tmp->nf] = nu;
+        tmp->tag[tmp->nf] = newtag;
+        tmp->nf++;
+    }
+    memcpy(P, tmp, sizeof(*P));
+    return 0;
+}
+
+/* Cells of the points listed in ids[0..m) (all points when ids is NULL and
+ * m = n).  Outputs per listed cell k: nf[k] faces, fnv[k][f], fverts[k][f][v][3],
+ * ftags[k][f], volume V[k] (sum of the tetrahedra x_i, v_0, v_k, v_k+1 of
+ * every face fan) and rho[k] = max |v - x_i|.  fcap/vcap are the caller's
+ * capacities.  Returns the number of cells that failed (capacity).          */
+int64_t orc_cells3d(int64_t n, const double *x, const double *R, const int64_t *off, const int32_t *idx,
+                    const double *dom_lo, const double *dom_hi, int64_t m, const int64_t *ids, int fcap,
+                    int vcap, int32_t *nf_out, int32_t *fnv, double *fverts, int32_t *ftags, double *V,
+                    double *rho)
+{
+    (void)n;
+    orc_poly3 *P = (orc_poly3 *)malloc(sizeof(orc_poly3)), *T = (orc_poly3 *)malloc(sizeof(orc_poly3));
+    int64_t bad = 0;
+    for (int64_t k = 0; k < m; ++k) {
+        int64_t i = ids ? ids[k] : k;
+        const double *xi = x + 3 * i;
+        double lo[3], hi[3];
+        int32_t t[6];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = xi[a] - R[i]; hi[a] = xi[a] + R[i];
+            t[2 * a] = ORC_TAG_BOX; t[2 * a + 1] = ORC_TAG_BOX;
+            if (lo[a] <= dom_lo[a]) { lo[a] = dom_lo[a]; t[2 * a] = -1 - 2 * a; }
+            if (hi[a] >= dom_hi[a]) { hi[a] = dom_hi[a]; t[2 * a + 1] = -2 - 2 * a; }
+        }
+        box_poly3(P, lo, hi, t);
+        int ok = 1;
+        for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+            int32_t j = idx[p];
+            const double *xj = x + 3 * (int64_t)j;
+            double nrm[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+            double mid[3] = {0.5 * (xi[0] + xj[0]), 0.5 * (xi[1] + xj[1]), 0.5 * (xi[2] + xj[2])};
+            if (clip_poly3(P, T, nrm, dot3(nrm, mid), j) != 0) { ok = 0; break; }
+        }
+        if (ok && (P->nf > fcap)) ok = 0;
+        for (int f = 0; ok && f < P->nf; ++f)
+            if (P->nv[f] > vcap) ok = 0;
+        if (!ok || P->nf < 4) {
+            bad++;
+            nf_out[k] = 0; V[k] = 0.0; rho[k] = 0.0;
+            continue;
+        }
+        double vol = 0.0, r2 = 0.0;
+        nf_out[k] = P->nf;
+        for (int f = 0; f < P->nf; ++f) {
+            fnv[k * fcap + f] = P->nv[f];
+            ftags[k * fcap + f] = P->tag[f];
+            for (int q = 0; q < P->nv[f]; ++q) {
+                double d[3] = {P->v[f][q][0] - xi[0], P->v[f][q][1] - xi[1], P->v[f][q][2] - xi[2]};
+                if (dot3(d, d) > r2) r2 = dot3(d, d);
+                memcpy(fverts + ((k * fcap + f) * vcap + q) * 3, P->v[f][q], sizeof(double) * 3);
+            }
+            double e1[3] = {P->v[f][0][0] - xi[0], P->v[f][0][1] - xi[1], P->v[f][0][2] - xi[2]};
+            for (int q = 1; q + 1 < P->nv[f]; ++q) {
+                double e2[3], e3[3], c[3];
+                for (int a = 0; a < 3; ++a) { e2[a] = P->v[f][q][a] - xi[a]; e3[a] = P->v[f][q + 1][a] - xi[a]; }
+                cross3(e2, e3, c);
+                vol += dot3(e1, c) / 6.0;
+            }
+        }
+        V[k] = vol;
+        rho[k] = sqrt(r2);
+    }
+    free(P); free(T);
+    return bad;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Cubic B-spline base kernel (reading of the unnamed W^b of Sec. 2.1),
  * q = |y - x_j| / h_j with h_j = R_j / 2, support q < 2.  The
  * normalisation constant cancels in the RK functions and is omitted.
@@ -572,6 +794,92 @@ int64_t orc_integrate2d(integ_ctx *ic_in, int cap, const int32_t *nv, const doub
         /* point values at the generator x_c */
         if (E) {
             int ord = rk_eval_act(2, ic.rk_order, xc, nc, cand, ic.x, ic.R, ic.V, 0.5 * ic.R[c], N, dN, act);
+            if (ord >= 0) {
+                if (ord < ic.rk_order) ic.fallbacks++;
+                for (int a = 0; a < nc; ++a) {
+                    if (!act[a]) continue;
+                    int64_t p = pos[0 * nc + a];
+                    if (p < 0) { ic.missing++; continue; }
+                    E[p] = N[a];
+                }
+            }
+        }
+    }
+    free(cand); free(pos); free(N); free(dN); free(act);
+    stats[0] = ic.fallbacks;
+    stats[1] = ic.missing;
+    stats[2] = bo.count;
+    return bo.count;
+}
+
+/* 3D integration: every face of cell c is fan-triangulated from its vertex 0
+ * and each triangle is joined to the generator x_c, giving the tetrahedra
+ * (x_c, v_0, v_k, v_k+1) (Fig. 2 in three dimensions).  The reference
+ * tetrahedron {xi >= 0, xi0 + xi1 + xi2 <= 1} maps by
+ * x = x_c + (v_0 - x_c) xi0 + (v_k - x_c) xi1 + (v_k+1 - x_c) xi2, |J| = 6 x
+ * volume (App. A).  Domain faces get the triangle rule on each fan triangle
+ * (v_0, v_k, v_k+1) with |J| = twice its area.  E as in 2D.               */
+int64_t orc_integrate3d(integ_ctx *ic_in, int fcap, int vcap, const int32_t *nf, const int32_t *fnv,
+                        const double *fverts, const int32_t *ftags, int nq_tet, const double *tet_pts,
+                        const double *tet_w, int nq_tri, const double *tri_pts, const double *tri_w, double *E,
+                        int64_t bq_cap, int kmax, double *bq_y, int32_t *bq_face, double *bq_w,
+                        int32_t *bq_nact, int32_t *bq_act, double *bq_N, int64_t *stats)
+{
+    integ_ctx ic = *ic_in;
+    ic.fallbacks = 0;
+    ic.missing = 0;
+    int64_t n = ic.n;
+    int maxc = 1;
+    for (int64_t c = 0; c < n; ++c) {
+        int k = (int)(ic.nb_off[c + 1] - ic.nb_off[c]) + 1;
+        if (k > maxc) maxc = k;
+    }
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * maxc);
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * maxc * maxc);
+    double *N = (double *)malloc(sizeof(double) * maxc);
+    double *dN = (double *)malloc(sizeof(double) * maxc * 3);
+    unsigned char *act = (unsigned char *)malloc(maxc);
+    bq_out bo = {0, bq_cap, bq_y, bq_face, bq_w, kmax, bq_nact, bq_act, bq_N};
+    for (int64_t c = 0; c < n; ++c) {
+        int nc = cell_candidates(&ic, c, cand);
+        for (int a = 0; a < nc; ++a)
+            for (int b = 0; b < nc; ++b) pos[a * nc + b] = find_pos(ic.row_off, ic.col, cand[a], cand[b]);
+        const double *xc = ic.x + 3 * c;
+        for (int f = 0; f < nf[c]; ++f) {
+            int m = fnv[c * fcap + f];
+            const double *fv = fverts + (c * fcap + f) * vcap * 3;
+            int t = ftags[c * fcap + f];
+            for (int k = 1; k + 1 < m; ++k) {
+                const double *A = fv, *B = fv + 3 * k, *Cv = fv + 3 * (k + 1);
+                double e1[3], e2[3], e3[3], cr[3];
+                for (int a = 0; a < 3; ++a) { e1[a] = A[a] - xc[a]; e2[a] = B[a] - xc[a]; e3[a] = Cv[a] - xc[a]; }
+                cross3(e2, e3, cr);
+                double detJ = dot3(e1, cr);
+                if (detJ > 0.0) {
+                    for (int q = 0; q < nq_tet; ++q) {
+                        const double *xi = tet_pts + 3 * q;
+                        double y[3];
+                        for (int a = 0; a < 3; ++a) y[a] = xc[a] + e1[a] * xi[0] + e2[a] * xi[1] + e3[a] * xi[2];
+                        add_volume_point(&ic, c, y, tet_w[q] * detJ, nc, cand, pos, N, dN, act);
+                    }
+                }
+                if (t <= -1 && t >= -6) {
+                    int face = -1 - t;
+                    double g1[3], g2[3], nn[3];
+                    for (int a = 0; a < 3; ++a) { g1[a] = B[a] - A[a]; g2[a] = Cv[a] - A[a]; }
+                    cross3(g1, g2, nn);
+                    double area2 = sqrt(dot3(nn, nn));
+                    for (int q = 0; q < nq_tri; ++q) {
+                        const double *xi = tri_pts + 2 * q;
+                        double y[3];
+                        for (int a = 0; a < 3; ++a) y[a] = A[a] + g1[a] * xi[0] + g2[a] * xi[1];
+                        add_surface_point(&ic, c, y, tri_w[q] * area2, face, nc, cand, pos, N, dN, act, &bo);
+                    }
+                }
+            }
+        }
+        if (E) {
+            int ord = rk_eval_act(3, ic.rk_order, xc, nc, cand, ic.x, ic.R, ic.V, 0.5 * ic.R[c], N, dN, act);
             if (ord >= 0) {
                 if (ord < ic.rk_order) ic.fallbacks++;
                 for (int a = 0; a < nc; ++a) {
