@@ -195,7 +195,10 @@ int64_t orc_cells2d(int64_t n, const double *x, const double *R, const int64_t *
  * removed, and they are ordered by angle around the plane normal about their
  * centroid; the angle is the "diamond" pseudo-angle (a monotone function of
  * the angle using only arithmetic).  A plane that leaves every vertex kept
- * changes nothing.                                                         */
+ * changes nothing.  Neighbours are applied nearest first (ties by index):
+ * the cell does not depend on the order, but the faces' vertex order, and
+ * with it the fan of tetrahedra the quadrature uses, does, so the order is
+ * part of the definition.                                                  */
 /* ------------------------------------------------------------------------ */
 #define ORC_FCAP3 64
 #define ORC_VCAP3 32
@@ -333,6 +336,18 @@ static int clip_poly3(orc_poly3 *P, orc_poly3 *tmp, const double *nrm, double of
     return 0;
 }
 
+typedef struct {
+    double d2;
+    int32_t j;
+} nb_dist;
+
+static int cmp_nb_dist(const void *a, const void *b)
+{
+    const nb_dist *p = (const nb_dist *)a, *q = (const nb_dist *)b;
+    if (p->d2 != q->d2) return p->d2 < q->d2 ? -1 : 1;
+    return (p->j > q->j) - (p->j < q->j);
+}
+
 /* Cells of the points listed in ids[0..m) (all points when ids is NULL and
  * m = n).  Outputs per listed cell k: nf[k] faces, fnv[k][f], fverts[k][f][v][3],
  * ftags[k][f], volume V[k] (sum of the tetrahedra x_i, v_0, v_k, v_k+1 of
@@ -345,6 +360,8 @@ int64_t orc_cells3d(int64_t n, const double *x, const double *R, const int64_t *
 {
     (void)n;
     orc_poly3 *P = (orc_poly3 *)malloc(sizeof(orc_poly3)), *T = (orc_poly3 *)malloc(sizeof(orc_poly3));
+    nb_dist *ord = NULL;
+    int64_t ordcap = 0;
     int64_t bad = 0;
     for (int64_t k = 0; k < m; ++k) {
         int64_t i = ids ? ids[k] : k;
@@ -358,9 +375,22 @@ int64_t orc_cells3d(int64_t n, const double *x, const double *R, const int64_t *
             if (hi[a] >= dom_hi[a]) { hi[a] = dom_hi[a]; t[2 * a + 1] = -2 - 2 * a; }
         }
         box_poly3(P, lo, hi, t);
+        /* neighbours nearest first, ties by index */
+        int64_t cnt = off[i + 1] - off[i];
+        if (cnt > ordcap) {
+            ordcap = cnt;
+            ord = (nb_dist *)realloc(ord, sizeof(nb_dist) * ordcap);
+        }
+        for (int64_t p = 0; p < cnt; ++p) {
+            int32_t j = idx[off[i] + p];
+            double d[3] = {x[3 * (int64_t)j] - xi[0], x[3 * (int64_t)j + 1] - xi[1], x[3 * (int64_t)j + 2] - xi[2]};
+            ord[p].d2 = dot3(d, d);
+            ord[p].j = j;
+        }
+        qsort(ord, (size_t)cnt, sizeof(nb_dist), cmp_nb_dist);
         int ok = 1;
-        for (int64_t p = off[i]; p < off[i + 1]; ++p) {
-            int32_t j = idx[p];
+        for (int64_t p = 0; p < cnt; ++p) {
+            int32_t j = ord[p].j;
             const double *xj = x + 3 * (int64_t)j;
             double nrm[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
             double mid[3] = {0.5 * (xi[0] + xj[0]), 0.5 * (xi[1] + xj[1]), 0.5 * (xi[2] + xj[2])};
@@ -395,7 +425,7 @@ int64_t orc_cells3d(int64_t n, const double *x, const double *R, const int64_t *
         V[k] = vol;
         rho[k] = sqrt(r2);
     }
-    free(P); free(T);
+    free(P); free(T); free(ord);
     return bad;
 }
 
