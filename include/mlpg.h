@@ -99,9 +99,12 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
  *   dom_lo, dom_hi: host [dim] domain box;
  *   regions: host boxes [n_regions][dim] with material ids; a point of space
  *     takes the material of the last box containing it, 0 if none.
- * dim = 2 only in this release (3D returns MLPG_ERR_ARG).  The call
- * synchronises `stream` (it sizes the boundary quadrature).  On success
- * *out owns copies of all inputs.
+ * dim = 2 (polygons, at most 32 vertices) or 3 (polyhedra of at most 40
+ * convex faces with at most 16 vertices each; the faces of a clip are built
+ * from the cut points ordered about their centroid).  A cell over capacity
+ * fails the call with MLPG_ERR_GEOMETRY.  The call synchronises `stream` (it
+ * sizes the boundary quadrature).  On success *out owns copies of all
+ * inputs.
  * ---------------------------------------------------------------------- */
 int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R,
                   const int64_t *nbr_off, const int32_t *nbr_idx, const double *dom_lo,
@@ -115,7 +118,7 @@ typedef struct {
     int64_t nnz;             /* pattern entries: i and its overlap neighbours per row */
     int64_t n_bq;            /* boundary quadrature points (after mlpg_geometry) */
     int64_t oversize_cells;  /* cells reaching beyond their own support radius */
-    int64_t failed_cells;    /* cells with no area or over the vertex capacity */
+    int64_t failed_cells;    /* cells with no volume or over the face/vertex capacity */
     int64_t fallback_qps;    /* quadrature points whose moment matrix needed a lower order */
     int64_t missing_pairs;   /* co-active pairs absent from the pattern (expected 0) */
     int n_ord;               /* ordinates after mlpg_assemble, else 0 */
@@ -128,10 +131,10 @@ int mlpg_get_info(mlpg_handle h, mlpg_info *info);
 /* Cell volumes V_i: device [n] out. */
 int mlpg_get_volumes(mlpg_handle h, double *V, void *stream);
 
-/* Cell polygons (2D): nv device [n], verts device [n][cap][2], tags device
- * [n][cap] with tag >= 0 the neighbour index of a bisector edge and
- * tag = -1 - f an edge on domain face f (0:-x 1:+x 2:-y 3:+y).  cap is
- * returned by mlpg_cell_capacity. */
+/* Cell polygons of a 2D problem (MLPG_ERR_ARG for 3D): nv device [n], verts
+ * device [n][cap][2], tags device [n][cap] with tag >= 0 the neighbour index
+ * of a bisector edge and tag = -1 - f an edge on domain face f (0:-x 1:+x
+ * 2:-y 3:+y).  cap is returned by mlpg_cell_capacity. */
 int mlpg_cell_capacity(void);
 int mlpg_get_cells(mlpg_handle h, int32_t *nv, double *verts, int32_t *tags, void *stream);
 
@@ -142,8 +145,11 @@ int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream);
 
 /* ------------------------------------------------------------------------
  * Stage 2, integration (Sec. 2.2; Sec. 3.2 and Alg. 1; App. A).  At every
- * quadrature point of every cell (fan triangles from the generator, the
- * 25-point conical-product rule; 5-point Gauss-Legendre on boundary edges)
+ * quadrature point of every cell (2D: fan triangles from the generator with
+ * the 25-point conical-product rule, 5-point Gauss-Legendre on boundary
+ * edges; 3D: tetrahedra joining the generator to the fan triangles of every
+ * face with the 8-point conical-product rule, 4-point rule on boundary
+ * triangles)
  * the RK functions N_j = V_j U_j of order rk_order (0, 1, 2) and their
  * gradients are formed from the moment matrix (batched Cholesky in FP64,
  * falling back one order at a time when a pivot is below 1e-6 of the largest
@@ -152,6 +158,9 @@ int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream);
  *   Mass_g = <N_i,N_j>, D^a_g = <d^a N_i, N_j> per material g,
  *   K^ab = <d^a N_i, d^b N_j>, S_f = (N_i,N_j) on domain face f.
  * Also forms the point-value matrix E_ij = N_j(x_i) (Eq. flux-expansion).
+ * MLPG_ERR_CAPACITY when a cell has more candidate functions than the
+ * per-cell capacity (64 in 2D, 512 in 3D) or a boundary point more active
+ * functions than it stores (32 in 2D, 128 in 3D).
  * ---------------------------------------------------------------------- */
 int mlpg_integrate(mlpg_handle h, int rk_order, void *stream);
 

@@ -17,6 +17,7 @@ void Problem::release()
 {
     reg_lo.release(); reg_hi.release(); reg_mat.release(); x.release(); R.release(); nb_off.release();
     nb_idx.release(); nv.release(); tags.release(); verts.release(); V.release(); rho.release(); bq_off.release();
+    nf.release(); fnv.release(); ftags.release(); fverts.release();
     bq_y.release(); bq_w.release(); bq_N.release(); bq_face.release(); bq_nact.release(); bq_act.release();
     row_off.release(); diag_pos.release(); col.release(); blocks.release(); E.release(); counters.release();
     wq.release(); omega.release(); sL.release(); sMD.release(); sMS.release(); coefL.release(); coefMD.release();
@@ -220,7 +221,7 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
 {
     MLPG_CHECK(out, MLPG_ERR_ARG, "mlpg_geometry: null output handle");
     *out = nullptr;
-    MLPG_CHECK(dim == 2, MLPG_ERR_ARG, "mlpg_geometry: only dim = 2 is implemented");
+    MLPG_CHECK(dim == 2 || dim == 3, MLPG_ERR_ARG, "mlpg_geometry: dim must be 2 or 3");
     MLPG_CHECK(n > 0 && n < (int64_t)1 << 31, MLPG_ERR_ARG, "mlpg_geometry: n out of range");
     MLPG_CHECK(x && R && nbr_off && nbr_idx && dom_lo && dom_hi, MLPG_ERR_ARG, "mlpg_geometry: null pointer");
     for (int a = 0; a < dim; ++a)
@@ -278,9 +279,6 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
     TRY(hipMemcpyAsync(P->nb_off.p, nbr_off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (nnz_nb) TRY(hipMemcpyAsync(P->nb_idx.p, nbr_idx, sizeof(int32_t) * nnz_nb, hipMemcpyDeviceToDevice, s));
 
-    TRY(P->nv.alloc(n));
-    TRY(P->tags.alloc(n * kCellCap2D));
-    TRY(P->verts.alloc(n * kCellCap2D * 2));
     TRY(P->V.alloc(n));
     TRY(P->rho.alloc(n));
     DevBuf<int32_t> flags;
@@ -288,7 +286,20 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
     TRY(flags.alloc(n));
     TRY(bqc.alloc(n));
     TRY(P->bq_off.alloc(n + 1));
-    TRY(launch_clip2d(*P, s, flags.p, bqc.p));
+    if (dim == 2) {
+        TRY(P->nv.alloc(n));
+        TRY(P->tags.alloc(n * kCellCap2D));
+        TRY(P->verts.alloc(n * kCellCap2D * 2));
+        TRY(launch_clip2d(*P, s, flags.p, bqc.p));
+        P->bq_kmax = kBqAct;
+    } else {
+        TRY(P->nf.alloc(n));
+        TRY(P->fnv.alloc(n * kFaceCap3));
+        TRY(P->ftags.alloc(n * kFaceCap3));
+        TRY(P->fverts.alloc(n * kFaceCap3 * kFaceVerts3 * 3));
+        TRY(launch_clip3d(*P, s, flags.p, bqc.p));
+        P->bq_kmax = kBqAct3;
+    }
     TRY(launch_exclusive_scan(bqc.p, P->bq_off.p, n, s));
     std::vector<int32_t> hf(n);
     TRY(hipMemcpyAsync(hf.data(), flags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
@@ -301,7 +312,7 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
         if (hf[i] == 2) P->oversize++;
     }
     if (P->failed) {
-        set_error("mlpg_geometry: " + std::to_string(P->failed) + " cells empty or over the vertex capacity");
+        set_error("mlpg_geometry: " + std::to_string(P->failed) + " cells empty or over the face/vertex capacity");
         return fail(MLPG_ERR_GEOMETRY);
     }
     P->nnz = nnz_nb + n;
@@ -314,8 +325,8 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
     TRY(P->bq_w.alloc(nbq));
     TRY(P->bq_face.alloc(nbq));
     TRY(P->bq_nact.alloc(nbq));
-    TRY(P->bq_act.alloc(nbq * kBqAct));
-    TRY(P->bq_N.alloc(nbq * kBqAct));
+    TRY(P->bq_act.alloc(nbq * P->bq_kmax));
+    TRY(P->bq_N.alloc(nbq * P->bq_kmax));
     TRY(P->counters.alloc(kNumCounters));
     TRY(hipStreamSynchronize(s));
 #undef TRY
@@ -358,6 +369,7 @@ int mlpg_get_cells(mlpg_handle h, int32_t *nv, double *verts, int32_t *tags, voi
     int rc = check_stage(h, 1, "mlpg_get_cells");
     if (rc) return rc;
     MLPG_CHECK(nv && verts && tags, MLPG_ERR_ARG, "mlpg_get_cells: null output");
+    MLPG_CHECK(h->dim == 2, MLPG_ERR_ARG, "mlpg_get_cells: polygons of 2D problems only");
     hipStream_t s = S(stream);
     MLPG_HIP(hipMemcpyAsync(nv, h->nv.p, sizeof(int32_t) * h->n, hipMemcpyDeviceToDevice, s));
     MLPG_HIP(hipMemcpyAsync(verts, h->verts.p, sizeof(double) * h->n * kCellCap2D * 2, hipMemcpyDeviceToDevice, s));
@@ -392,7 +404,7 @@ int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
     MLPG_HIP(hipMemsetAsync(P->E.p, 0, sizeof(double) * P->nnz, s));
     MLPG_HIP(hipMemsetAsync(P->counters.p, 0, sizeof(unsigned long long) * kNumCounters, s));
     MLPG_HIP(hipMemsetAsync(P->bq_nact.p, 0, sizeof(int32_t) * std::max<int64_t>(1, P->n_bq), s));
-    hipError_t e = launch_integrate2d(*P, s);
+    hipError_t e = P->dim == 2 ? launch_integrate2d(*P, s) : launch_integrate3d(*P, s);
     if (e == hipErrorInvalidValue) {
         set_error("mlpg_integrate: a cell has more candidate functions (" + std::to_string(P->cand_max) +
                   ") than the per-cell capacity");

@@ -1,4 +1,5 @@
-// Meshless integration on gfx950 (Sec. 2.2, Sec. 3.2, Alg. 1, App. A).
+// Meshless integration on gfx950 (Sec. 2.2, Sec. 3.2, Alg. 1, App. A), in
+// 2D (fan triangles) and 3D (fan tetrahedra).
 //
 // One workgroup per cell.  The functions that can be nonzero on the cell
 // (the cell's generator and the overlap neighbours whose support reaches the
@@ -20,6 +21,10 @@ __constant__ double c_tri_w[kTriRule];
 __constant__ double c_seg_pts[kSegRule];
 __constant__ double c_seg_w[kSegRule];
 
+namespace {
+hipError_t upload_rules3(hipStream_t s);
+}
+
 hipError_t upload_rules(hipStream_t s)
 {
     const Rules &r = rules();
@@ -31,6 +36,7 @@ hipError_t upload_rules(hipStream_t s)
         e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_seg_pts), r.seg_pts, sizeof(r.seg_pts), 0, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_seg_w), r.seg_w, sizeof(r.seg_w), 0, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = upload_rules3(s);
     return e;
 }
 
@@ -508,6 +514,529 @@ __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
     }
 }
 
+// ---- 3D integration ---------------------------------------------------------
+//
+// As in 2D, one workgroup per cell, with the functions that can reach the
+// cell staged in LDS.  The cell's faces are fan-triangulated from their
+// vertex 0 and joined to the generator, giving the tetrahedra
+// (x_c, v_0, v_k, v_k+1) that carry the 8-point conical-product rule.  The
+// moment matrix is kept as a packed lower triangle and factored once: the
+// leading b x b block of its Cholesky factor is the factor of the moment
+// matrix of the lower orders, so the pivots decide the order used (the
+// highest whose pivots all exceed 1e-6 of its largest diagonal entry).  The
+// gradient correction dC = -M^-1 (dM C) is formed from dM C accumulated
+// directly in a second pass over the functions, never from dM itself.
+
+__constant__ double c_tet_pts[kTetRule][3];
+__constant__ double c_tet_w[kTetRule];
+__constant__ double c_tri3_pts[kTri3Rule][2];
+__constant__ double c_tri3_w[kTri3Rule];
+
+template <int ORD>
+struct Basis3 {
+    static constexpr int B = ORD == 0 ? 1 : (ORD == 1 ? 4 : 10);
+};
+
+__host__ __device__ constexpr int bsize3(int o) { return o == 0 ? 1 : (o == 1 ? 4 : 10); }
+
+// Unique monomials of degree <= ORD in z: [1, z0, z1, z2, z0z0, z0z1, z0z2,
+// z1z1, z1z2, z2z2] and their derivatives D[g] = dP/dz_g.
+template <int ORD>
+__device__ __forceinline__ void basis3(const double (&z)[3], double (&P)[Basis3<ORD>::B],
+                                       double (&D)[3][Basis3<ORD>::B])
+{
+    P[0] = 1.0;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) D[g][0] = 0.0;
+    if (ORD >= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            P[1 + a] = z[a];
+#pragma unroll
+            for (int g = 0; g < 3; ++g) D[g][1 + a] = (g == a) ? 1.0 : 0.0;
+        }
+    }
+    if (ORD >= 2) {
+        int k = 4;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int c = a; c < 3; ++c) {
+                P[k] = z[a] * z[c];
+#pragma unroll
+                for (int g = 0; g < 3; ++g) D[g][k] = (g == a ? z[c] : 0.0) + (g == c ? z[a] : 0.0);
+                k++;
+            }
+    }
+}
+
+__device__ __forceinline__ constexpr int tri_idx(int r, int s) { return r * (r + 1) / 2 + s; }
+
+// Solve L L^T out = rhs on the leading b x b block of the packed factor.
+template <int B>
+__device__ __forceinline__ void chol_solve_packed(int b, const double (&L)[B * (B + 1) / 2], const double (&rhs)[B],
+                                                  double (&out)[B])
+{
+    double t[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        if (k >= b) { t[k] = 0.0; continue; }
+        double s = rhs[k];
+#pragma unroll
+        for (int p = 0; p < B; ++p)
+            if (p < k) s -= L[tri_idx(k, p)] * t[p];
+        t[k] = s / L[tri_idx(k, k)];
+    }
+#pragma unroll
+    for (int k = B - 1; k >= 0; --k) {
+        if (k >= b) { out[k] = 0.0; continue; }
+        double s = t[k];
+#pragma unroll
+        for (int p = 0; p < B; ++p)
+            if (p > k && p < b) s -= L[tri_idx(p, k)] * out[p];
+        out[k] = s / L[tri_idx(k, k)];
+    }
+}
+
+// RK correction at y from the staged candidates; returns the order used
+// (-1: no function covers y).  C and dC are zero beyond the order's size.
+template <int ORD>
+__device__ int rk_prepare3(const double (&y)[3], int A, const double *sx, const double *sR, const double *sV,
+                           double hs, double (&C)[Basis3<ORD>::B], double (&dC)[3][Basis3<ORD>::B])
+{
+    constexpr int B = Basis3<ORD>::B;
+    constexpr int NP = B * (B + 1) / 2;
+    double L[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) L[k] = 0.0;
+    bool any = false;
+    const double ihs = 1.0 / hs;
+    for (int a = 0; a < A; ++a) {
+        double r[3] = {y[0] - sx[3 * a], y[1] - sx[3 * a + 1], y[2] - sx[3 * a + 2]};
+        double h = 0.5 * sR[a];
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (!(r2 < 4.0 * h * h)) continue;
+        double dfac;
+        double W = spline(r2, h, &dfac);
+        if (W == 0.0) continue;
+        any = true;
+        double z[3] = {r[0] * ihs, r[1] * ihs, r[2] * ihs};
+        double P[B], D[3][B];
+        basis3<ORD>(z, P, D);
+        double v = sV[a];
+#pragma unroll
+        for (int p = 0; p < B; ++p)
+#pragma unroll
+            for (int q = 0; q <= p; ++q) L[tri_idx(p, q)] += v * P[p] * P[q] * W;
+    }
+    if (!any) return -1;
+    double diag[B], piv[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) diag[k] = L[tri_idx(k, k)];
+    // kfail = number of leading pivots that are positive; past a failed pivot
+    // the factor is continued with a unit diagonal and never used
+    int kfail = 0;
+    bool alive = true;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        double s = L[tri_idx(k, k)];
+#pragma unroll
+        for (int p = 0; p < B; ++p)
+            if (p < k) s -= L[tri_idx(k, p)] * L[tri_idx(k, p)];
+        piv[k] = s;
+        alive = alive && (s > 0.0);
+        kfail += alive ? 1 : 0;
+        L[tri_idx(k, k)] = alive ? sqrt(s) : 1.0;
+#pragma unroll
+        for (int rr = 0; rr < B; ++rr) {
+            if (rr <= k) continue;
+            double t = L[tri_idx(rr, k)];
+#pragma unroll
+            for (int p = 0; p < B; ++p)
+                if (p < k) t -= L[tri_idx(rr, p)] * L[tri_idx(k, p)];
+            L[tri_idx(rr, k)] = t / L[tri_idx(k, k)];
+        }
+    }
+    int o = -1;
+#pragma unroll
+    for (int oo = ORD; oo >= 0; --oo) {
+        if (o >= 0) break;
+        const int b = bsize3(oo);
+        if (b > kfail) continue;
+        double dmax = 0.0;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (k < b) dmax = fmax(dmax, diag[k]);
+        if (!(dmax > 0.0)) continue;
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (k < b) ok = ok && (piv[k] > 1e-6 * dmax);
+        if (ok) o = oo;
+    }
+    if (o < 0) return -1;
+    const int b = bsize3(o);
+    double e0[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) e0[k] = (k == 0) ? 1.0 : 0.0;
+    chol_solve_packed<B>(b, L, e0, C);
+    // dM_g C = sum_j V_j [ (D_g P^T + P D_g^T) C W / hs + P (P.C) dW_g ]
+    double rg[3][B];
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+        for (int k = 0; k < B; ++k) rg[g][k] = 0.0;
+    for (int a = 0; a < A; ++a) {
+        double r[3] = {y[0] - sx[3 * a], y[1] - sx[3 * a + 1], y[2] - sx[3 * a + 2]};
+        double h = 0.5 * sR[a];
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (!(r2 < 4.0 * h * h)) continue;
+        double dfac;
+        double W = spline(r2, h, &dfac);
+        if (W == 0.0) continue;
+        double z[3] = {r[0] * ihs, r[1] * ihs, r[2] * ihs};
+        double P[B], D[3][B];
+        basis3<ORD>(z, P, D);
+        double v = sV[a];
+        double PC = 0.0;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (k < b) PC += P[k] * C[k];
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            double DC = 0.0;
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (k < b) DC += D[g][k] * C[k];
+            double dW = dfac * r[g];
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (k < b) rg[g][k] += v * ((D[g][k] * PC + P[k] * DC) * ihs * W + P[k] * PC * dW);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        double t[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) t[k] = -rg[g][k];
+        chol_solve_packed<B>(b, L, t, dC[g]);
+    }
+    return o;
+}
+
+template <int ORD>
+__device__ __forceinline__ bool rk_value3(const double (&y)[3], int a, const double *sx, const double *sR,
+                                          const double *sV, double hs, const double (&C)[Basis3<ORD>::B],
+                                          const double (&dC)[3][Basis3<ORD>::B], double *N, double (&dN)[3])
+{
+    constexpr int B = Basis3<ORD>::B;
+    double r[3] = {y[0] - sx[3 * a], y[1] - sx[3 * a + 1], y[2] - sx[3 * a + 2]};
+    double h = 0.5 * sR[a];
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    if (!(r2 < 4.0 * h * h)) return false;
+    double dfac;
+    double W = spline(r2, h, &dfac);
+    if (W == 0.0) return false;
+    const double ihs = 1.0 / hs;
+    double z[3] = {r[0] * ihs, r[1] * ihs, r[2] * ihs};
+    double P[B], D[3][B];
+    basis3<ORD>(z, P, D);
+    double PC = 0.0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) PC += P[k] * C[k];
+    double v = sV[a];
+    *N = v * PC * W;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            t1 += D[g][k] * ihs * C[k];
+            t2 += P[k] * dC[g][k];
+        }
+        dN[g] = v * ((t1 + t2) * W + PC * (dfac * r[g]));
+    }
+    return true;
+}
+
+__device__ __forceinline__ int material_at3(const double (&y)[3], int nreg, const double *lo, const double *hi,
+                                            const int32_t *mat)
+{
+    int m = 0;
+    for (int r = 0; r < nreg; ++r)
+        if (y[0] >= lo[3 * r] && y[0] <= hi[3 * r] && y[1] >= lo[3 * r + 1] && y[1] <= hi[3 * r + 1] &&
+            y[2] >= lo[3 * r + 2] && y[2] <= hi[3 * r + 2])
+            m = mat[r];
+    return m;
+}
+
+struct Integ3Args {
+    int64_t n;
+    const double *x, *R, *V, *rho;
+    const int64_t *nb_off;
+    const int32_t *nb_idx;
+    const int32_t *nf, *fnv, *ftags;
+    const double *fverts;
+    const int64_t *row_off;
+    const int32_t *col;
+    int64_t nnz;
+    int G;
+    int nreg;
+    const double *reg_lo, *reg_hi;
+    const int32_t *reg_mat;
+    double *blocks;
+    double *E;
+    const int64_t *bq_off;
+    double *bq_y, *bq_w, *bq_N;
+    int32_t *bq_face, *bq_nact, *bq_act;
+    unsigned long long *counters;
+    int amax;
+    int tile_rows;
+};
+
+__global__ void cand_count3_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ R,
+                                   const double *__restrict__ rho, const int64_t *__restrict__ nb_off,
+                                   const int32_t *__restrict__ nb_idx, int32_t *__restrict__ cnt)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double rc = rho[c];
+    int k = 1;
+    for (int64_t p = nb_off[c]; p < nb_off[c + 1]; ++p) {
+        int64_t j = nb_idx[p];
+        double d0 = x[3 * j] - x[3 * c], d1 = x[3 * j + 1] - x[3 * c + 1], d2 = x[3 * j + 2] - x[3 * c + 2];
+        double lim = R[j] + rc;
+        if (d0 * d0 + d1 * d1 + d2 * d2 < lim * lim) k++;
+    }
+    cnt[c] = k;
+}
+
+template <int ORD>
+__global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
+{
+    extern __shared__ double lds[];
+    __shared__ int sA, sntet, snbt;
+    __shared__ int tet_pre[kFaceCap3 + 1], bnd_pre[kFaceCap3 + 1];
+    const int G = g.G;
+    const int NB = 4 * G + 6;
+    const int amax = g.amax;
+    double *sx = lds;
+    double *sR = sx + 3 * amax;
+    double *sV = sR + amax;
+    int32_t *sidx = (int32_t *)(sV + amax);
+    double *gram = sV + amax + (amax + 1) / 2;
+    const int64_t c = blockIdx.x;
+    const double xc[3] = {g.x[3 * c], g.x[3 * c + 1], g.x[3 * c + 2]};
+    const double hs = 0.5 * g.R[c];
+    const int nfc = g.nf[c];
+    if (threadIdx.x == 0) {
+        int A = 0;
+        double rc = g.rho[c];
+        sidx[0] = (int32_t)c; sx[0] = xc[0]; sx[1] = xc[1]; sx[2] = xc[2]; sR[0] = g.R[c]; sV[0] = g.V[c];
+        A = 1;
+        for (int64_t p = g.nb_off[c]; p < g.nb_off[c + 1]; ++p) {
+            int64_t j = g.nb_idx[p];
+            double d0 = g.x[3 * j] - xc[0], d1 = g.x[3 * j + 1] - xc[1], d2 = g.x[3 * j + 2] - xc[2];
+            double lim = g.R[j] + rc;
+            if (d0 * d0 + d1 * d1 + d2 * d2 < lim * lim) {
+                if (A >= amax) { A = -1; break; }
+                sidx[A] = (int32_t)j;
+                sx[3 * A] = g.x[3 * j]; sx[3 * A + 1] = g.x[3 * j + 1]; sx[3 * A + 2] = g.x[3 * j + 2];
+                sR[A] = g.R[j];
+                sV[A] = g.V[j];
+                A++;
+            }
+        }
+        if (A < 0) atomicAdd(&g.counters[kOverflow], 1ull);
+        sA = A;
+        int nt = 0, nb = 0;
+        tet_pre[0] = 0;
+        bnd_pre[0] = 0;
+        for (int f = 0; f < nfc; ++f) {
+            int m = g.fnv[c * kFaceCap3 + f];
+            int tg = g.ftags[c * kFaceCap3 + f];
+            nt += m - 2;
+            if (tg <= -1 && tg >= -6) nb += m - 2;
+            tet_pre[f + 1] = nt;
+            bnd_pre[f + 1] = nb;
+        }
+        sntet = nt;
+        snbt = nb;
+    }
+    __syncthreads();
+    const int A = sA;
+    if (A <= 0) return;
+    constexpr int B = Basis3<ORD>::B;
+    const int nq = sntet * kTetRule;
+    const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
+    const int64_t nnz = g.nnz;
+
+    for (int a0 = 0; a0 < A; a0 += g.tile_rows) {
+        const int a1 = min(A, a0 + g.tile_rows);
+        const int TR = a1 - a0;
+        const int TT = TR * A;
+        for (int t = threadIdx.x; t < NB * TT; t += kThreads) gram[t] = 0.0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nq; t += kThreads) {
+            const int te = t / kTetRule, q = t - te * kTetRule;
+            int f = 0;
+            while (tet_pre[f + 1] <= te) f++;
+            const int k = 1 + te - tet_pre[f];
+            const double *v0 = fvc + (f * kFaceVerts3) * 3;
+            const double *vk = fvc + (f * kFaceVerts3 + k) * 3;
+            const double *vk1 = fvc + (f * kFaceVerts3 + k + 1) * 3;
+            double e1[3], e2[3], e3[3], cr[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = v0[d] - xc[d]; e2[d] = vk[d] - xc[d]; e3[d] = vk1[d] - xc[d]; }
+            cr[0] = e2[1] * e3[2] - e2[2] * e3[1];
+            cr[1] = e2[2] * e3[0] - e2[0] * e3[2];
+            cr[2] = e2[0] * e3[1] - e2[1] * e3[0];
+            const double detJ = e1[0] * cr[0] + e1[1] * cr[1] + e1[2] * cr[2];
+            if (!(detJ > 0.0)) continue;
+            double y[3];
+            for (int d = 0; d < 3; ++d)
+                y[d] = xc[d] + e1[d] * c_tet_pts[q][0] + e2[d] * c_tet_pts[q][1] + e3[d] * c_tet_pts[q][2];
+            const double w = c_tet_w[q] * detJ;
+            double C[B], dC[3][B];
+            int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
+            if (o < 0) continue;
+            if (a0 == 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            const int mat = material_at3(y, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
+            for (int a = a0; a < a1; ++a) {
+                double Na, dNa[3];
+                if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
+                const double wa = w * Na, wa0 = w * dNa[0], wa1 = w * dNa[1], wa2 = w * dNa[2];
+                double *gr = gram + (a - a0) * A;
+                for (int b = 0; b < A; ++b) {
+                    double Nb, dNb[3];
+                    if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
+                    atomicAdd(&gr[(4 * mat + 0) * TT + b], wa * Nb);
+                    atomicAdd(&gr[(4 * mat + 1) * TT + b], wa0 * Nb);
+                    atomicAdd(&gr[(4 * mat + 2) * TT + b], wa1 * Nb);
+                    atomicAdd(&gr[(4 * mat + 3) * TT + b], wa2 * Nb);
+                    atomicAdd(&gr[(4 * G + 0) * TT + b], wa0 * dNb[0]);
+                    atomicAdd(&gr[(4 * G + 1) * TT + b], wa0 * dNb[1]);
+                    atomicAdd(&gr[(4 * G + 2) * TT + b], wa0 * dNb[2]);
+                    atomicAdd(&gr[(4 * G + 3) * TT + b], wa1 * dNb[1]);
+                    atomicAdd(&gr[(4 * G + 4) * TT + b], wa1 * dNb[2]);
+                    atomicAdd(&gr[(4 * G + 5) * TT + b], wa2 * dNb[2]);
+                }
+            }
+        }
+        __syncthreads();
+        // scatter: K^ab for a <= b from the tile, K^ba[j][i] = K^ab[i][j] as its transpose
+        const int kb = 4 * G;
+        for (int t = threadIdx.x; t < TT; t += kThreads) {
+            const int al = t / A, b = t - al * A;
+            const int a = a0 + al;
+            bool nz = false;
+            for (int q = 0; q < NB; ++q) nz |= (gram[q * TT + t] != 0.0);
+            if (!nz) continue;
+            const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+            if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+            for (int m = 0; m < G; ++m)
+                for (int q = 0; q < 4; ++q) {
+                    double v = gram[(4 * m + q) * TT + t];
+                    if (v != 0.0) atomicAdd(&g.blocks[(int64_t)(4 * m + q) * nnz + pos], v);
+                }
+            // tile order xx, xy, xz, yy, yz, zz -> block kb + 3 alpha + beta
+            const int ab[6] = {0, 1, 2, 4, 5, 8};
+            for (int q = 0; q < 6; ++q)
+                atomicAdd(&g.blocks[(int64_t)(kb + ab[q]) * nnz + pos], gram[(4 * G + q) * TT + t]);
+            const int64_t pos_t = find_col(g.row_off, g.col, sidx[b], sidx[a]);
+            if (pos_t < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+            const int ba[3] = {3, 6, 7};          // yx, zx, zy
+            const int src[3] = {1, 2, 4};         // from xy, xz, yz
+            for (int q = 0; q < 3; ++q)
+                atomicAdd(&g.blocks[(int64_t)(kb + ba[q]) * nnz + pos_t], gram[(4 * G + src[q]) * TT + t]);
+        }
+        __syncthreads();
+    }
+
+    // boundary triangles on domain faces: 4-point rule, surface blocks and
+    // the boundary point table used for the inflow term
+    const int nbq = snbt * kTri3Rule;
+    const int sb = 4 * G + 9;
+    for (int t = threadIdx.x; t < nbq; t += kThreads) {
+        const int tr = t / kTri3Rule, q = t - tr * kTri3Rule;
+        int f = 0;
+        while (bnd_pre[f + 1] <= tr) f++;
+        const int k = 1 + tr - bnd_pre[f];
+        const int face = -1 - g.ftags[c * kFaceCap3 + f];
+        const double *A0 = fvc + (f * kFaceVerts3) * 3;
+        const double *B0 = fvc + (f * kFaceVerts3 + k) * 3;
+        const double *C0 = fvc + (f * kFaceVerts3 + k + 1) * 3;
+        double g1[3], g2[3], nn[3];
+        for (int d = 0; d < 3; ++d) { g1[d] = B0[d] - A0[d]; g2[d] = C0[d] - A0[d]; }
+        nn[0] = g1[1] * g2[2] - g1[2] * g2[1];
+        nn[1] = g1[2] * g2[0] - g1[0] * g2[2];
+        nn[2] = g1[0] * g2[1] - g1[1] * g2[0];
+        const double area2 = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        double y[3];
+        for (int d = 0; d < 3; ++d) y[d] = A0[d] + g1[d] * c_tri3_pts[q][0] + g2[d] * c_tri3_pts[q][1];
+        const double w = c_tri3_w[q] * area2;
+        const int64_t bq = g.bq_off[c] + t;
+        for (int d = 0; d < 3; ++d) g.bq_y[3 * bq + d] = y[d];
+        g.bq_face[bq] = face;
+        g.bq_w[bq] = w;
+        double C[B], dC[3][B];
+        int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
+        int na = 0;
+        if (o >= 0) {
+            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            for (int a = 0; a < A; ++a) {
+                double Na, d_[3];
+                if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
+                if (na < kBqAct3) {
+                    g.bq_act[bq * kBqAct3 + na] = sidx[a];
+                    g.bq_N[bq * kBqAct3 + na] = Na;
+                } else {
+                    atomicAdd(&g.counters[kOverflow], 1ull);
+                }
+                na++;
+                for (int b = 0; b < A; ++b) {
+                    double Nb, e_[3];
+                    if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, e_)) continue;
+                    const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+                    if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+                    atomicAdd(&g.blocks[(int64_t)(sb + face) * nnz + pos], w * Na * Nb);
+                }
+            }
+        }
+        g.bq_nact[bq] = na < kBqAct3 ? na : kBqAct3;
+    }
+
+    // point values at the generator: E[c, j] = N_j(x_c)
+    if (threadIdx.x == 0) {
+        double C[B], dC[3][B];
+        int o = rk_prepare3<ORD>(xc, A, sx, sR, sV, hs, C, dC);
+        if (o >= 0) {
+            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            for (int a = 0; a < A; ++a) {
+                double Na, d_[3];
+                if (!rk_value3<ORD>(xc, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
+                const int64_t pos = find_col(g.row_off, g.col, (int32_t)c, sidx[a]);
+                if (pos >= 0) g.E[pos] = Na;
+                else atomicAdd(&g.counters[kMissing], 1ull);
+            }
+        }
+    }
+}
+
+hipError_t upload_rules3(hipStream_t s)
+{
+    const Rules &r = rules();
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tet_pts), r.tet_pts, sizeof(r.tet_pts), 0,
+                                          hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tet_w), r.tet_w, sizeof(r.tet_w), 0, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tri3_pts), r.tri3_pts, sizeof(r.tri3_pts), 0,
+                                   hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tri3_w), r.tri3_w, sizeof(r.tri3_w), 0, hipMemcpyHostToDevice, s);
+    return e;
+}
+
 }  // namespace
 
 hipError_t launch_integrate2d(Problem &P, hipStream_t s)
@@ -562,6 +1091,62 @@ hipError_t launch_integrate2d(Problem &P, hipStream_t s)
     default:
         if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
         integrate2d_kernel<2><<<grid, kThreads, shmem, s>>>(g);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate3d(Problem &P, hipStream_t s)
+{
+    DevBuf<int32_t> cnt;
+    hipError_t e = cnt.alloc(P.n);
+    if (e != hipSuccess) return e;
+    cand_count3_kernel<<<(int)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.x.p, P.R.p, P.rho.p, P.nb_off.p, P.nb_idx.p,
+                                                                  cnt.p);
+    std::vector<int32_t> h(P.n);
+    e = hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    cnt.release();
+    if (e != hipSuccess) return e;
+    int amax = 1;
+    for (int32_t v : h) amax = v > amax ? v : amax;
+    P.cand_max = amax;
+    if (amax > kCandMax3D) return hipErrorInvalidValue;   // reported as capacity by the caller
+
+    int dev = 0;
+    int lds_max = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev)) != hipSuccess) return e;
+    const int NB = 4 * P.n_mat + 6;
+    size_t fixed = sizeof(double) * (5 * amax + (amax + 1) / 2) + 64 + 2 * sizeof(int) * (kFaceCap3 + 1) + 16;
+    size_t budget = (lds_max > 0 ? (size_t)lds_max : 65536) - fixed;
+    int tile_rows = (int)(budget / (sizeof(double) * NB * amax));
+    if (tile_rows > amax) tile_rows = amax;
+    if (tile_rows < 1) return hipErrorInvalidValue;
+    size_t shmem = sizeof(double) * (5 * amax + (amax + 1) / 2) + sizeof(double) * (size_t)NB * tile_rows * amax;
+
+    Integ3Args g;
+    g.n = P.n; g.x = P.x.p; g.R = P.R.p; g.V = P.V.p; g.rho = P.rho.p;
+    g.nb_off = P.nb_off.p; g.nb_idx = P.nb_idx.p; g.nf = P.nf.p; g.fnv = P.fnv.p; g.ftags = P.ftags.p;
+    g.fverts = P.fverts.p; g.row_off = P.row_off.p; g.col = P.col.p; g.nnz = P.nnz; g.G = P.n_mat;
+    g.nreg = P.n_regions; g.reg_lo = P.reg_lo.p; g.reg_hi = P.reg_hi.p; g.reg_mat = P.reg_mat.p;
+    g.blocks = P.blocks.p; g.E = P.E.p; g.bq_off = P.bq_off.p; g.bq_y = P.bq_y.p; g.bq_w = P.bq_w.p;
+    g.bq_N = P.bq_N.p; g.bq_face = P.bq_face.p; g.bq_nact = P.bq_nact.p; g.bq_act = P.bq_act.p;
+    g.counters = P.counters.p; g.amax = amax; g.tile_rows = tile_rows;
+    if ((e = upload_rules(s)) != hipSuccess) return e;
+    dim3 grid((unsigned)P.n);
+    switch (P.rk_order) {
+    case 0:
+        if ((e = hipFuncSetAttribute((const void *)integrate3d_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
+        integrate3d_kernel<0><<<grid, kThreads, shmem, s>>>(g);
+        break;
+    case 1:
+        if ((e = hipFuncSetAttribute((const void *)integrate3d_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
+        integrate3d_kernel<1><<<grid, kThreads, shmem, s>>>(g);
+        break;
+    default:
+        if ((e = hipFuncSetAttribute((const void *)integrate3d_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
+        integrate3d_kernel<2><<<grid, kThreads, shmem, s>>>(g);
         break;
     }
     return hipGetLastError();

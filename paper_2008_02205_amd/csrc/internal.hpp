@@ -17,8 +17,16 @@ constexpr int kCellCap2D = 32;     // polygon vertex capacity of a 2D cell
 constexpr int kSegRule = 5;        // Gauss-Legendre points on a boundary edge
 constexpr int kTriN = 5;           // conical-product order on a triangle (25 points)
 constexpr int kTriRule = kTriN * kTriN;
-constexpr int kBqAct = 32;         // active functions stored per boundary point
+constexpr int kBqAct = 32;         // active functions stored per boundary point (2D)
 constexpr int kCandMax2D = 64;     // functions possibly active on one 2D cell
+constexpr int kFaceCap3 = 40;      // face capacity of a 3D cell
+constexpr int kFaceVerts3 = 16;    // vertex capacity of one face of a 3D cell
+constexpr int kTetN = 2;           // conical-product order on a tetrahedron (8 points)
+constexpr int kTetRule = kTetN * kTetN * kTetN;
+constexpr int kTri3N = 2;          // conical-product order on a boundary triangle in 3D (4 points)
+constexpr int kTri3Rule = kTri3N * kTri3N;
+constexpr int kBqAct3 = 128;       // active functions stored per boundary point (3D)
+constexpr int kCandMax3D = 512;    // functions possibly active on one 3D cell
 constexpr int kMaxRestart = 30;
 constexpr int kTagBox = -100;      // edge of the kernel box not on the domain
 
@@ -70,6 +78,10 @@ struct Rules {
     double tri_w[kTriRule];
     double seg_pts[kSegRule];
     double seg_w[kSegRule];
+    double tet_pts[kTetRule][3];
+    double tet_w[kTetRule];
+    double tri3_pts[kTri3Rule][2];
+    double tri3_w[kTri3Rule];
 };
 const Rules &rules();
 hipError_t upload_rules(hipStream_t s);   // copies the tables to __constant__ memory
@@ -132,13 +144,17 @@ struct Problem {
     DevBuf<int32_t> nb_idx;
     int64_t nnz_nb = 0;
 
-    // cells
+    // cells: 2D polygons (nv, tags, verts) or 3D polyhedra (nf, fnv, ftags,
+    // fverts: [n][kFaceCap3][kFaceVerts3][3])
     DevBuf<int32_t> nv, tags;
     DevBuf<double> verts, V, rho;
+    DevBuf<int32_t> nf, fnv, ftags;
+    DevBuf<double> fverts;
     int64_t oversize = 0, failed = 0;
 
     // boundary quadrature
     int64_t n_bq = 0;
+    int bq_kmax = kBqAct;     // active functions stored per boundary point
     DevBuf<int64_t> bq_off;   // [n+1] first boundary point of each cell
     DevBuf<double> bq_y, bq_w, bq_N;
     DevBuf<int32_t> bq_face, bq_nact, bq_act;
@@ -198,8 +214,10 @@ hipError_t launch_neighbors_fill(int dim, int64_t n, const double *x, const doub
 hipError_t launch_exclusive_scan(const int64_t *counts, int64_t *off, int64_t n, hipStream_t s);
 
 hipError_t launch_clip2d(Problem &P, hipStream_t s, int32_t *flags, int64_t *bq_count);
+hipError_t launch_clip3d(Problem &P, hipStream_t s, int32_t *flags, int64_t *bq_count);
 hipError_t launch_pattern(Problem &P, hipStream_t s);
 hipError_t launch_integrate2d(Problem &P, hipStream_t s);
+hipError_t launch_integrate3d(Problem &P, hipStream_t s);
 
 hipError_t launch_assemble(Problem &P, const double *sig_t, const double *sig_s, const double *tau,
                            hipStream_t s);

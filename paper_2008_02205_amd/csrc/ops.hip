@@ -396,7 +396,7 @@ __global__ void point_values_kernel(int64_t n, const int64_t *row_off, const int
 }
 
 // Inflow term (N_i, |W.n| psi_b)_{W.n<0}: one thread per (boundary point, m).
-__global__ void boundary_rhs_kernel(int64_t nbq, int M, int dim, const int32_t *face, const double *bw,
+__global__ void boundary_rhs_kernel(int64_t nbq, int M, int dim, int kmax, const int32_t *face, const double *bw,
                                     const int32_t *nact, const int32_t *act, const double *bN, const double *omega,
                                     const double *psib, double *F)
 {
@@ -412,7 +412,7 @@ __global__ void boundary_rhs_kernel(int64_t nbq, int M, int dim, const int32_t *
     double val = psib[t];
     if (val == 0.0) return;
     double s = bw[k] * (-wn) * val;
-    for (int a = 0; a < nact[k]; ++a) atomicAdd(&F[(int64_t)act[k * kBqAct + a] * M + m], s * bN[k * kBqAct + a]);
+    for (int a = 0; a < nact[k]; ++a) atomicAdd(&F[(int64_t)act[k * kmax + a] * M + m], s * bN[k * kmax + a]);
 }
 
 // out[i] = base[i] + sign * sum_m w_m X[i][m]; one wave per row.
@@ -570,7 +570,8 @@ hipError_t launch_boundary_rhs(Problem &P, const double *psib, double *F, hipStr
 {
     int64_t tot = P.n_bq * P.n_ord;
     if (tot == 0) return hipSuccess;
-    boundary_rhs_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(P.n_bq, P.n_ord, P.dim, P.bq_face.p, P.bq_w.p,
+    boundary_rhs_kernel<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(P.n_bq, P.n_ord, P.dim, P.bq_kmax, P.bq_face.p,
+                                                                        P.bq_w.p,
                                                                         P.bq_nact.p, P.bq_act.p, P.bq_N.p,
                                                                         P.omega.p, psib, F);
     return hipGetLastError();

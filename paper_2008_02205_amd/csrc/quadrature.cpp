@@ -141,6 +141,44 @@ void make_rules()
         }
     }
     gauss_legendre(kSegRule, g_rules.seg_pts, g_rules.seg_w);
+
+    // Tetrahedron {xi >= 0, xi0 + xi1 + xi2 <= 1}: collapsed coordinates
+    // (u, v, s) -> (u, (1-u) v, (1-u)(1-v) s) with Jacobian (1-u)^2 (1-v),
+    // absorbed by Gauss-Jacobi rules in u (alpha 2) and v (alpha 1).
+    double tu[kTetN], twu[kTetN], tv[kTetN], twv[kTetN], ts[kTetN], tws[kTetN];
+    gauss_jacobi(kTetN, 2.0, tu, twu);
+    gauss_jacobi(kTetN, 1.0, tv, twv);
+    gauss_legendre(kTetN, ts, tws);
+    q = 0;
+    for (int a = 0; a < kTetN; ++a) {
+        double ua = 0.5 * (tu[a] + 1.0), wa = twu[a] / 8.0;
+        for (int b = 0; b < kTetN; ++b) {
+            double vb = 0.5 * (tv[b] + 1.0), wb = twv[b] / 4.0;
+            for (int c = 0; c < kTetN; ++c) {
+                double sc = 0.5 * (ts[c] + 1.0), wc = 0.5 * tws[c];
+                g_rules.tet_pts[q][0] = ua;
+                g_rules.tet_pts[q][1] = (1.0 - ua) * vb;
+                g_rules.tet_pts[q][2] = (1.0 - ua) * (1.0 - vb) * sc;
+                g_rules.tet_w[q] = wa * wb * wc;
+                q++;
+            }
+        }
+    }
+    // boundary triangles in 3D: the same construction as the cell triangles
+    double u3[kTri3N], wu3[kTri3N], v3[kTri3N], wv3[kTri3N];
+    gauss_jacobi(kTri3N, 1.0, u3, wu3);
+    gauss_legendre(kTri3N, v3, wv3);
+    q = 0;
+    for (int a = 0; a < kTri3N; ++a) {
+        double ua = 0.5 * (u3[a] + 1.0), wa = wu3[a] / 4.0;
+        for (int b = 0; b < kTri3N; ++b) {
+            double vb = 0.5 * (v3[b] + 1.0), wb = 0.5 * wv3[b];
+            g_rules.tri3_pts[q][0] = ua;
+            g_rules.tri3_pts[q][1] = (1.0 - ua) * vb;
+            g_rules.tri3_w[q] = wa * wb;
+            q++;
+        }
+    }
 }
 
 }  // namespace
