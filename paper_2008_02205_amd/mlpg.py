@@ -219,10 +219,10 @@ def mlpg_get_pattern(h, n, nnz):
     return row_off, col
 
 
-def mlpg_get_blocks(h, n_blocks, nnz):
+def mlpg_get_blocks(h, n_blocks, nnz, want_E=True):
     blocks = _empty((n_blocks, nnz))
-    E = _empty(nnz)
-    _check(lib().mlpg_get_blocks(h, _dev(blocks), _dev(E), _stream()))
+    E = _empty(nnz) if want_E else None
+    _check(lib().mlpg_get_blocks(h, _dev(blocks), _dev(E) if want_E else None, _stream()))
     return blocks, E
 
 

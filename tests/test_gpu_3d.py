@@ -101,11 +101,22 @@ def test_stages_3d(n, jitter, order):
     y, face = P.boundary_points()
     y, face = _cpu(y), _cpu(face)
     assert y.shape[0] == it.nbq
-    ka = np.lexsort((it.bq_y[:, 2], it.bq_y[:, 1], it.bq_y[:, 0], it.bq_face))
-    kb = np.lexsort((y[:, 2], y[:, 1], y[:, 0], face))
-    assert np.array_equal(face[kb], it.bq_face[ka])
-    assert np.abs(y[kb] - it.bq_y[ka]).max() <= 1e-14
+    _match_point_sets(y, face, it.bq_y, it.bq_face)
     P.close()
+
+
+def _match_point_sets(y, face, yo, fo, tol=1e-13):
+    """The two boundary-point sets are equal up to rounding: a one-to-one
+    nearest-neighbour matching within tol, on the same face."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.column_stack([yo, fo * 10.0]))
+    d, k = tree.query(np.column_stack([y, face * 10.0]))
+    bad = np.nonzero(d > tol)[0]
+    for b in bad[:8]:
+        print(f"unmatched boundary point {y[b]} face {face[b]}; nearest oracle {yo[k[b]]} face {fo[k[b]]} "
+              f"at {d[b]:.2e}", flush=True)
+    assert bad.size == 0
+    assert np.unique(k).size == k.size
 
 
 def test_operator_sweeps_3d():

@@ -235,3 +235,54 @@ def test_beam_void_opaque_reduced(precision, _beam_reference):
               flush=True)
         assert max(e) <= tol
     P.close()
+
+
+def test_full_size_3d_gaussian_workload_stages():
+    """The 3D workload at its own size (40^3 jittered lattice, quadratic RK, R = 2.5 h):
+    neighbour lists and pattern bit for bit, sampled cells against the oracle one by one,
+    and the block identities that hold at any size."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    w = W.config(3)
+    _print_case("full-stages-3d", workload=w.name, n=w.counts)
+    x, dx = W.points_for(w)
+    R = W.radii_for(w, x, dx)
+    off, idx = oracle.neighbors(x, R)
+    P = GpuProblem(x, R, w.lo, w.hi)
+    assert np.array_equal(_cpu(P.nbr_off), off)
+    assert np.array_equal(_cpu(P.nbr_idx), idx)
+    V = _cpu(mlpg.mlpg_get_volumes(P.h, P.n))
+    assert abs(V.sum() - 1.0) <= 1e-12
+    assert P.info["oversize_cells"] == 0 and P.info["failed_cells"] == 0
+    ids = np.random.default_rng(5).choice(x.shape[0], 300, replace=False)
+    cl = oracle.cells3d(x, R, off, idx, w.lo, w.hi, ids=ids)
+    assert cl.failed == 0
+    eps = np.finfo(np.float64).eps
+    assert np.abs(V[ids] - cl.V).max() <= 64 * eps * cl.V.max()
+    import time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = P.integrate(w.rk_order)
+    torch.cuda.synchronize()
+    print(f"3D integration of {x.shape[0]} cells: {time.perf_counter() - t0:.2f} s, nnz {info['nnz']}, "
+          f"fallbacks {info['fallback_qps']}", flush=True)
+    assert info["missing_pairs"] == 0
+    row_off, col = mlpg.mlpg_get_pattern(P.h, P.n, info["nnz"])
+    row_off, col = _cpu(row_off), _cpu(col)
+    ro, co = oracle.pattern(P.n, off, idx)
+    assert np.array_equal(row_off, ro) and np.array_equal(col, co)
+    blocks, _ = mlpg.mlpg_get_blocks(P.h, info["n_blocks"], info["nnz"], want_E=False)
+    names = oracle.block_names(3, 1)
+    blk = lambda nm: _cpu(blocks[names.index(nm)])
+    n = P.n
+    mass = blk("mass0")
+    assert abs(mass.sum() - 1.0) <= 1e-10
+    rows = np.repeat(np.arange(n), np.diff(row_off))
+    for a, nm in enumerate(("dx0", "dy0", "dz0")):
+        D = blk(nm)
+        assert np.abs(np.bincount(col, D, n)).max() <= 1e-9
+        lhs = np.bincount(col, D * x[rows, a], n)
+        assert np.abs(lhs - np.bincount(col, mass, n)).max() <= 1e-9
+    for f in range(6):
+        assert abs(blk(f"s{f}").sum() - 1.0) <= 1e-10
+    P.close()
