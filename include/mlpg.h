@@ -258,9 +258,11 @@ int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stre
  * move (each input and output counted once, gathered vectors once) are
  * accumulated.  Process-wide; not thread-safe.
  *   class 0: SpMV of the transport operator L (all ordinates)
- *   class 1: Gram-Schmidt pass 1 (dot products)
- *   class 2: Gram-Schmidt pass 2 (update + dot products)
- *   class 3: Gram-Schmidt pass 3 (update + norm)
+ *   class 1: Gram-Schmidt pass A (projections of the new vector and of the
+ *            operator output on the basis)
+ *   class 2: Gram-Schmidt pass B (reorthogonalised basis vector, projected
+ *            operator output, its norm)
+ *   class 3: end-of-cycle pass A (projections of the last vector only)
  * mlpg_profile_end synchronises the device and fills, per class (arrays of
  * MLPG_PROF_CLASSES): total kernel time in ms, launch count and bytes.
  * ---------------------------------------------------------------------- */

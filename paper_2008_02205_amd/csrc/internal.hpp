@@ -107,9 +107,10 @@ struct KrylovT {
     DevBuf<T> z;             // [n][nb] dinv .* w, the next operator input
     DevBuf<T> r;             // [n][nb]
     DevBuf<double> vscale;   // [nb] 1/h_{j+1,j} of the newest column (0 once a system stops)
-    DevBuf<double> part;     // [nblk][k+2][nb] block partial sums
-    DevBuf<double> h1, h2;   // [k+1][nb]
-    DevBuf<double> H;        // [nb][k+1][k]
+    DevBuf<double> part;     // [nblk][2k+2][nb] block partial sums
+    DevBuf<double> h1, h2;   // [2k+2][nb] reduced projections, pass-B coefficients
+    DevBuf<double> H;        // [nb][k+1][k] rotated Hessenberg (upper triangular part used)
+    DevBuf<double> Ht;       // [nb][k+1][k] unrotated Hessenberg
     DevBuf<double> cs, sn;   // [nb][k]
     DevBuf<double> g;        // [nb][k+1]
     DevBuf<double> y;        // [k][nb]
@@ -120,7 +121,7 @@ struct KrylovT {
     DevBuf<int> done;        // [nb] 1 once converged (or out of steps)
     DevBuf<int> its;         // [nb] Arnoldi steps so far in this solve
     DevBuf<int> jend;        // [nb] columns built in this cycle
-    DevBuf<int> nactive;     // [1]
+    DevBuf<int> nactive;     // [3] rotating active counters (the gates of consecutive steps)
     int *nactive_host = nullptr;   // pinned, host-visible mirrors of nactive (one slot per sweep in flight)
     int *nactive_hdev = nullptr;   // device address of nactive_host
     hipEvent_t ev[8] = {};

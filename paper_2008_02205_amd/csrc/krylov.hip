@@ -2,20 +2,26 @@
 //
 // `nb` independent systems of `n` unknowns advance together, vectors stored
 // [n][nb] with the system index fastest (for the inner solves, nb = the
-// ordinates; the outer scattering iteration uses nb = 1).  Each Arnoldi step
-// is one operator application over all systems, then classical Gram-Schmidt
-// with one reorthogonalisation in three streaming passes over the basis
-//   pass 1: h1 = V^T w
-//   pass 2: w -= V h1 and h2 = V^T w       (fused: the basis is read once)
-//   pass 3: w -= V h2 and ||w||^2          (fused)
-// with block partial sums reduced in a fixed order (deterministic), and a
-// one-thread-per-system kernel for the Hessenberg column, Givens rotations,
-// residual estimate and convergence flag.  The normalisation of the new
-// basis vector is folded into the next operator application when the
-// operator supports it.  Systems that converge stop updating; kernels of a
-// sweep in which no system is active return at once, and the host reads the
-// active count a few sweeps late (through host-visible memory and events) so
-// that the queue never drains while it waits.
+// ordinates; the outer scattering iteration uses nb = 1).  Gram-Schmidt is
+// classical with one reorthogonalisation (CGS2), but the second projection of
+// each basis vector is delayed into the next Arnoldi step, so that a step
+// streams the basis twice instead of three times:
+//   operator:  w = A u_j   (u_j: the new vector after one projection, normalised)
+//   pass A:    a = V^T u_j, b = V^T w, u_j.w, u_j.u_j      (one pass)
+//   small:     v_j = (u_j - V a)/rho with rho^2 = u_j.u_j - |a|^2; the previous
+//              Hessenberg column is corrected (h_{:,j-1} += beta a, h_{j,j-1} =
+//              beta rho) and rotated; column j = [V v_j]^T A v_j follows from
+//              A v_j = (w - V H a)/rho without touching the vectors
+//   pass B:    v_j and w_j = (w - s u_j - V (b - s a))/rho = A v_j - [V v_j] h_j
+//              written together, with |w_j|^2 (one pass)
+// (delayed CGS2 as in the low-synchronisation Gram-Schmidt literature; the
+// algebra above is derived here for this solver).  Block partial sums are
+// reduced in a fixed order (deterministic).  The normalisation of the next
+// vector is folded into the next operator application when the operator
+// supports it.  Systems that converge stop updating; kernels of a sweep in
+// which no system is active return at once, and the host reads the active
+// count a few sweeps late (through host-visible memory and events) so that
+// the queue never drains while it waits.
 #include "internal.hpp"
 
 namespace mlpg {
@@ -23,12 +29,15 @@ namespace mlpg {
 namespace {
 
 constexpr int kThreads = 256;       // small kernels
-constexpr int kMaxThreads = 512;    // streaming Gram-Schmidt passes (2 waves per SIMD: ~190 VGPRs fit)
+constexpr int kMaxThreads = 512;    // streaming passes (2 waves per SIMD: ~190 VGPRs fit)
 constexpr int kPartBlocks = 256;    // workgroups (and partial sums) of a streaming pass
 constexpr int kRowsPerThread = 4;
-constexpr int KP = kMaxRestart + 1;   // basis vectors held in registers
+constexpr int KP = kMaxRestart + 1;   // register capacity for the Hessenberg column
+constexpr int kRows = 2 * kMaxRestart + 2;   // partial-sum rows: a, b, u.w, u.u
 constexpr int QC = 8;                 // partial sums reduced per LDS round
 constexpr int kSlots = 8;
+constexpr int kGroup = 32;            // threads per system in the small kernel
+constexpr int kGroupsPerBlock = kThreads / kGroup;
 
 inline int rpb_of(int nb)
 {
@@ -67,138 +76,175 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NQ], int 
         if (rl == 0) {
 #pragma unroll
             for (int qq = 0; qq < QC; ++qq)
-                if (q0 + qq < NQ) part[((int64_t)blockIdx.x * (KP + 1) + q0 + qq) * nb + m] = red[qq * nb + m];
+                if (q0 + qq < NQ) part[((int64_t)blockIdx.x * kRows + q0 + qq) * nb + m] = red[qq * nb + m];
         }
         __syncthreads();
     }
 }
 
-// part[b][q][m] = sum over the block's rows of V_q[i][m] * w[i][m], q < NQ,
-// and part[b][NQ][m] = the block's share of ||w_m||^2 (products and sums in
-// FP64 whatever the storage type T).  NQ is a
-// template argument so that all NQ loads of a row issue back to back.
-template <class T, int NQ>
-__global__ __launch_bounds__(kMaxThreads) void dots_kernel(int64_t n, int nb, const T *__restrict__ V,
-                                                           int64_t vstride, const T *__restrict__ w,
-                                                           double *__restrict__ part, const int *__restrict__ gate)
+// part[b][0][m] = the block's share of ||x_m||^2 (FP64 whatever T is).
+template <class T>
+__global__ __launch_bounds__(kMaxThreads) void norm2_kernel(int64_t n, int nb, const T *__restrict__ x,
+                                                            double *__restrict__ part)
 {
     extern __shared__ double red[];
-    if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
-    double acc[NQ + 1];   // V_q^T w for q < NQ, then ||w||^2
-#pragma unroll
-    for (int q = 0; q <= NQ; ++q) acc[q] = 0.0;
+    double acc[1] = {0.0};
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
-        const int64_t o = i * nb + m;
-        T v[NQ];
-        const double wv = (double)w[o];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = V[q * vstride + o];
-        // keep every load of the row in flight before the first use (left
-        // alone, the scheduler trades them for registers and serialises them)
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += (double)v[q] * wv;
-        acc[NQ] += wv * wv;
+        const double v = (double)x[i * nb + m];
+        acc[0] += v * v;
     }
-    block_reduce_store<NQ + 1>(acc, rpb, rl, m, nb, red, part);
+    block_reduce_store<1>(acc, rpb, rl, m, nb, red, part);
 }
 
-// Selective reorthogonalisation: a system needs the second Gram-Schmidt
-// pass when the first one cancelled most of w, ||w'|| < 0.7 ||w|| (the
-// "twice is enough" test of Kahan and Parlett).
-__device__ __forceinline__ bool needs_reorth(double s1, double s2) { return s2 < 0.49 * s1; }
-
-// MODE 0: w -= sum_q h1[q][m] V_q, then part = [V^T w, ||w||^2] and
-//         z = dinv .* w (the next operator input when no second pass runs).
-// MODE 1: the second pass, only for the systems that need it (s1, s2 are
-//         ||w||^2 before and after the first pass): w -= sum_q h2[q][m] V_q,
-//         part[0] = ||w||^2, z rewritten.  The whole launch returns at once
-//         when no system needs it.
-template <class T, int MODE, int NQ>
-__global__ __launch_bounds__(kMaxThreads) void gs_update_kernel(int64_t n, int nb, const T *__restrict__ V,
-                                                                int64_t vstride, T *__restrict__ w,
-                                                                const double *__restrict__ h,
-                                                                double *__restrict__ part,
-                                                                const T *__restrict__ dinv,
-                                                                T *__restrict__ z, const double *__restrict__ s1,
-                                                                const double *__restrict__ s2,
-                                                                const int *__restrict__ gate)
+// Pass A of step j (NQ = j basis vectors V_0..V_{j-1}, the new vector u and,
+// when HW, the operator output w): partial sums of
+//   HW:  rows [0, NQ) a_q = V_q.u, [NQ, 2NQ) b_q = V_q.w, 2NQ u.w, 2NQ+1 u.u
+//   !HW: rows [0, NQ) a_q, NQ u.u            (end of a restart cycle)
+// All loads of a row are issued before the first use.
+template <class T, int NQ, bool HW>
+__global__ __launch_bounds__(kMaxThreads) void pass_a_kernel(int64_t n, int nb, const T *__restrict__ V,
+                                                             int64_t vstride, const T *__restrict__ u,
+                                                             const T *__restrict__ w, double *__restrict__ part,
+                                                             const int *__restrict__ gate)
 {
     extern __shared__ double red[];
     if (gate && *gate == 0) return;
     const int rpb = blockDim.x / nb;
     const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
-    bool mine = true;
-    if (MODE == 1) {
-        mine = needs_reorth(s1[m], s2[m]);
-        if (!__syncthreads_or(mine)) return;
-    }
-    constexpr int NA = MODE == 0 ? NQ + 1 : 1;
-    double hq[NQ], acc[NA];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) hq[q] = mine ? h[q * nb + m] : 0.0;
+    constexpr int NA = HW ? 2 * NQ + 2 : NQ + 1;
+    double acc[NA];
 #pragma unroll
     for (int q = 0; q < NA; ++q) acc[q] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
         const int64_t o = i * nb + m;
-        T v[NQ];
-        double wv = (double)w[o];
+        T v[NQ > 0 ? NQ : 1];
+        const double uv = (double)u[o];
+        const double wv = HW ? (double)w[o] : 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) v[q] = V[q * vstride + o];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) wv -= hq[q] * (double)v[q];
-        const T wt = (T)wv;
-        if (MODE == 0 || mine) {
-            w[o] = wt;
-            if (z) z[o] = dinv ? dinv[o] * wt : wt;
+        for (int q = 0; q < NQ; ++q) {
+            acc[q] += (double)v[q] * uv;
+            if (HW) acc[NQ + q] += (double)v[q] * wv;
         }
-        wv = (double)wt;
-        if (MODE == 0) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) acc[q] += (double)v[q] * wv;
-            acc[NQ] += wv * wv;
+        if (HW) {
+            acc[2 * NQ] += uv * wv;
+            acc[2 * NQ + 1] += uv * uv;
         } else {
-            acc[0] += wv * wv;
+            acc[NQ] += uv * uv;
         }
     }
     block_reduce_store<NA>(acc, rpb, rl, m, nb, red, part);
 }
 
+// Pass B of step j, from the per-system coefficients c (rows [0, NQ) a_q,
+// [NQ, 2NQ) g_q = b_q - s a_q, 2NQ s, 2NQ+1 1/rho; all zero for a system that
+// stopped):  u <- (u - sum a_q V_q)/rho  (the final basis vector v_j, in place),
+// w <- (w - s u - sum g_q V_q)/rho, z = dinv .* w, and the partial sums of
+// ||w||^2.
+template <class T, int NQ>
+__global__ __launch_bounds__(kMaxThreads) void pass_b_kernel(int64_t n, int nb, const T *__restrict__ V,
+                                                             int64_t vstride, T *__restrict__ u, T *__restrict__ w,
+                                                             const double *__restrict__ c,
+                                                             const T *__restrict__ dinv, T *__restrict__ z,
+                                                             double *__restrict__ part,
+                                                             const int *__restrict__ gate)
+{
+    extern __shared__ double red[];
+    if (gate && *gate == 0) return;
+    const int rpb = blockDim.x / nb;
+    const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
+    double ca[NQ > 0 ? NQ : 1], cg[NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        ca[q] = c[q * nb + m];
+        cg[q] = c[(NQ + q) * nb + m];
+    }
+    const double cs = c[(2 * NQ) * nb + m], ir = c[(2 * NQ + 1) * nb + m];
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
+        const int64_t o = i * nb + m;
+        T v[NQ > 0 ? NQ : 1];
+        const double uv = (double)u[o];
+        const double wv = (double)w[o];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = V[q * vstride + o];
+        __builtin_amdgcn_sched_barrier(0);
+        double vj = uv, wj = wv - cs * uv;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            vj -= ca[q] * (double)v[q];
+            wj -= cg[q] * (double)v[q];
+        }
+        const T vt = (T)(vj * ir), wt = (T)(wj * ir);
+        u[o] = vt;
+        w[o] = wt;
+        if (z) z[o] = dinv ? dinv[o] * wt : wt;
+        acc[0] += (double)wt * (double)wt;
+    }
+    block_reduce_store<1>(acc, rpb, rl, m, nb, red, part);
+}
+
 // out[q][m] = sum_b part[b][q][m]: one workgroup per q; threads split the
 // block partials into interleaved strands (four independent accumulators each
 // so that loads overlap), then a fixed-shape tree in LDS (deterministic).
-__global__ __launch_bounds__(kThreads) void reduce_part_kernel(int nblk, int nq, int nb,
-                                                               const double *__restrict__ part,
-                                                               double *__restrict__ out, const int *__restrict__ gate,
-                                                               const double *__restrict__ s1 = nullptr,
-                                                               const double *__restrict__ s2 = nullptr)
+__device__ __forceinline__ double reduce_rows(int nblk, int q, int nb, const double *__restrict__ part, double *red)
 {
-    __shared__ double red[kThreads];
-    if (gate && *gate == 0) return;
-    const int q = blockIdx.x;
     const int ns = blockDim.x / nb;          // strands per system (power of two)
     const int st = threadIdx.x / nb, m = threadIdx.x - st * nb;
-    if (s1 && !__syncthreads_or(needs_reorth(s1[m], s2[m]))) return;
-    if (st >= ns) return;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int b = st;
-    for (; b + 3 * ns < nblk; b += 4 * ns) {
-        a0 += part[((int64_t)b * (KP + 1) + q) * nb + m];
-        a1 += part[((int64_t)(b + ns) * (KP + 1) + q) * nb + m];
-        a2 += part[((int64_t)(b + 2 * ns) * (KP + 1) + q) * nb + m];
-        a3 += part[((int64_t)(b + 3 * ns) * (KP + 1) + q) * nb + m];
+    if (st < ns) {
+        int b = st;
+        for (; b + 3 * ns < nblk; b += 4 * ns) {
+            a0 += part[((int64_t)b * kRows + q) * nb + m];
+            a1 += part[((int64_t)(b + ns) * kRows + q) * nb + m];
+            a2 += part[((int64_t)(b + 2 * ns) * kRows + q) * nb + m];
+            a3 += part[((int64_t)(b + 3 * ns) * kRows + q) * nb + m];
+        }
+        for (; b < nblk; b += ns) a0 += part[((int64_t)b * kRows + q) * nb + m];
     }
-    for (; b < nblk; b += ns) a0 += part[((int64_t)b * (KP + 1) + q) * nb + m];
     red[threadIdx.x] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     for (int s = ns >> 1; s > 0; s >>= 1) {
         if (st < s) red[threadIdx.x] += red[threadIdx.x + s * nb];
         __syncthreads();
     }
-    if (st == 0) out[q * nb + m] = red[m];
+    return red[m];
+}
+
+__global__ __launch_bounds__(kThreads) void reduce_part_kernel(int nblk, int nb, const double *__restrict__ part,
+                                                               double *__restrict__ out, const int *__restrict__ gate)
+{
+    __shared__ double red[kThreads];
+    if (gate && *gate == 0) return;
+    const int q = blockIdx.x;
+    const double v = reduce_rows(nblk, q, nb, part, red);
+    if ((int)threadIdx.x < nb) out[q * nb + threadIdx.x] = v;
+}
+
+// After pass B: beta = ||w_j|| (the unrotated h_{j+1,j} before its
+// correction), vscale = 1/beta for the systems still iterating (0 for the
+// others), and the active count published to the host slot.
+__global__ __launch_bounds__(kThreads) void reduce_norm_kernel(int nblk, int nb, const double *__restrict__ part,
+                                                               const int *__restrict__ active,
+                                                               double *__restrict__ beta,
+                                                               double *__restrict__ vscale,
+                                                               const int *__restrict__ gate,
+                                                               int *__restrict__ host_slot)
+{
+    __shared__ double red[kThreads];
+    if (threadIdx.x == 0 && host_slot) host_slot[0] = gate ? *gate : 1;
+    if (gate && *gate == 0) return;
+    const double v = reduce_rows(nblk, 0, nb, part, red);
+    const int m = threadIdx.x;
+    if (m < nb) {
+        const double b = sqrt(fmax(v, 0.0));
+        beta[m] = b;
+        vscale[m] = (active[m] && b > 0.0) ? 1.0 / b : 0.0;
+    }
 }
 
 __global__ void sqrt_kernel(int nb, const double *in, double *out)
@@ -207,30 +253,21 @@ __global__ void sqrt_kernel(int nb, const double *in, double *out)
     if (m < nb) out[m] = sqrt(fmax(in[m], 0.0));
 }
 
-// Number of threads of the (single) block with v != 0, written to count[0]
-// and, when given, to a host-visible slot.
-__device__ __forceinline__ void block_count(int v, int *count, int *host_slot)
+// Start of a restart cycle: beta = ||r||; decide which systems iterate; the
+// active count goes to nact0, nact1 is cleared for step 0's count.
+__global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, const double *__restrict__ beta2,
+                                                              const double *__restrict__ fnorm, double tol,
+                                                              int max_its, const int *__restrict__ its,
+                                                              int *__restrict__ active, int *__restrict__ done,
+                                                              double *__restrict__ g, double *__restrict__ beta,
+                                                              double *__restrict__ resid, int *__restrict__ jend,
+                                                              int *__restrict__ nact0, int *__restrict__ nact1,
+                                                              int *__restrict__ host_slot)
 {
     __shared__ int s_cnt;
     if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
-    if (v) atomicAdd(&s_cnt, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        count[0] = s_cnt;
-        if (host_slot) host_slot[0] = s_cnt;
-    }
-}
-
-// Start of a restart cycle: beta = ||r||; decide which systems iterate.
-__global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, const double *__restrict__ beta2, const double *__restrict__ fnorm,
-                                  double tol, int max_its, const int *__restrict__ its, int *__restrict__ active,
-                                  int *__restrict__ done, double *__restrict__ g, double *__restrict__ beta,
-                                  double *__restrict__ resid, int *__restrict__ jend, int *__restrict__ nactive,
-                                  int *__restrict__ host_slot)
-{
     int m = threadIdx.x;
-    int act = 0;
     if (m < nb) {
         double b = sqrt(fmax(beta2[m], 0.0));
         double fn = fnorm[m];
@@ -239,86 +276,171 @@ __global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, con
         bool ok = (fn == 0.0) || (b <= tol * fn);
         bool out = its[m] >= max_its;
         done[m] = ok ? 1 : (out ? 2 : 0);
-        act = (!ok && !out) ? 1 : 0;
+        int act = (!ok && !out) ? 1 : 0;
         active[m] = act;
         jend[m] = 0;
         for (int q = 0; q <= k; ++q) g[m * (k + 1) + q] = 0.0;
         g[m * (k + 1)] = b;
+        if (act) atomicAdd(&s_cnt, 1);
     }
-    block_count(act, nactive, host_slot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        nact0[0] = s_cnt;
+        nact1[0] = 0;
+        if (host_slot) host_slot[0] = s_cnt;
+    }
 }
 
-// Hessenberg column j, Givens rotations and convergence test per system;
-// the column lives in registers while the earlier rotations are applied.
-__global__ __launch_bounds__(kThreads) void arnoldi_kernel(int nb, int k, int j, const double *__restrict__ h1, const double *__restrict__ h2,
-                               const double *__restrict__ hn2_second, double *__restrict__ H, double *__restrict__ cs,
-                               double *__restrict__ sn, double *__restrict__ g, const double *__restrict__ fnorm,
-                               double tol, int max_its, int *__restrict__ active, int *__restrict__ its,
-                               int *__restrict__ jend, double *__restrict__ vscale, double *__restrict__ resid,
-                               int *__restrict__ nactive, int *__restrict__ host_slot, const int *__restrict__ gate)
+// The small part of step j, kGroup threads per system (thread q owns row q).
+// From pass A: rho = sqrt(u.u - |a|^2); the previous column of the
+// unrotated Hessenberg Ht is corrected with beta (the norm pass B gave the
+// previous vector) and a, then rotated by the earlier Givens rotations into
+// R, with the residual estimate and the convergence flag.  Unless FINAL (the
+// end of a cycle: only the correction), column j of Ht and the pass-B
+// coefficients follow:
+//   t = Ht a (rows 0..j),  v_j.w = (u.w - a.b)/rho,  h_jj = (v_j.w - t_j)/rho,
+//   Ht[q][j] = (b_q - t_q)/rho,  s = t_j/rho + h_jj,  g_q = b_q - s a_q.
+// Active systems are counted into nact_out; nact_clear (the counter of two
+// steps ahead) is cleared.
+// mode: kStep (correct j-1, test, coefficients), kEnd (end of a cycle:
+// correct and test only, every system stops), kPre (before the operator of
+// step j: correct and test only, P holds the projections of u_j alone),
+// kAfterPre (coefficients only; column j-1 was corrected by kPre).
+enum { kStep = 0, kEnd = 1, kPre = 2, kAfterPre = 3 };
+
+__global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, int k, int j, const double *__restrict__ P,
+                                                              const double *__restrict__ betap,
+                                                              double *__restrict__ Ht, double *__restrict__ R,
+                                                              double *__restrict__ cs, double *__restrict__ sn,
+                                                              double *__restrict__ g,
+                                                              const double *__restrict__ fnorm, double tol,
+                                                              int max_its, int *__restrict__ active,
+                                                              int *__restrict__ its, int *__restrict__ jend,
+                                                              double *__restrict__ resid, double *__restrict__ coef,
+                                                              const int *__restrict__ gate,
+                                                              int *__restrict__ nact_out,
+                                                              int *__restrict__ nact_clear)
 {
-    if (gate && *gate == 0) {
-        if (threadIdx.x == 0 && host_slot) host_slot[0] = 0;
+    __shared__ double sa[kGroupsPerBlock][KP + 1], scol[kGroupsPerBlock][KP + 1];
+    __shared__ int sstill[kGroupsPerBlock];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nact_clear) nact_clear[0] = 0;
+    if (gate && *gate == 0) return;
+    const bool FINAL = mode == kEnd || mode == kPre;     // no coefficients
+    const bool correct = mode != kAfterPre && j >= 1;   // correct and test column j-1
+    const int grp = threadIdx.x / kGroup, q = threadIdx.x % kGroup;
+    const int m = blockIdx.x * kGroupsPerBlock + grp;
+    const bool act = m < nb && active[m] != 0;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+    if (act) {
+        if (q < j) a = P[q * nb + m];
+        if (!FINAL) {
+            if (q < j) b = P[(j + q) * nb + m];
+            c = P[(2 * j) * nb + m];
+            d = P[(2 * j + 1) * nb + m];
+        } else {
+            d = P[j * nb + m];
+        }
+    }
+    double aa = a * a, ab = a * b;
+    for (int o = kGroup / 2; o > 0; o >>= 1) {
+        aa += __shfl_xor(aa, o, kGroup);
+        ab += __shfl_xor(ab, o, kGroup);
+    }
+    const double rho2 = d - aa;
+    const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
+    double *Hm = Ht + (int64_t)(m < nb ? m : 0) * (k + 1) * k;
+    sa[grp][q] = a;
+    if (act && mode == kAfterPre && j >= 1 && q <= j) scol[grp][q] = Hm[q * k + (j - 1)];
+    if (act && correct) {
+        const double bp = betap[m];
+        if (q < j) {
+            const double v = Hm[q * k + (j - 1)] + bp * a;
+            Hm[q * k + (j - 1)] = v;
+            scol[grp][q] = v;
+        } else if (q == j) {
+            const double v = bp * rho;
+            Hm[j * k + (j - 1)] = v;
+            scol[grp][q] = v;
+        }
+    }
+    __syncthreads();
+    if (q == 0 && m < nb) {
+        bool still = act;
+        if (act && j == 0) {
+            g[m * (k + 1)] *= rho;   // r = beta u_0 = beta rho v_0
+        } else if (act && correct) {
+            double *Rm = R + (int64_t)m * (k + 1) * k;
+            double *cm = cs + m * k, *sm = sn + m * k, *gm = g + m * (k + 1);
+            double col[KP + 1];
+#pragma unroll
+            for (int r = 0; r <= KP; ++r) col[r] = (r <= j) ? scol[grp][r] : 0.0;
+#pragma unroll
+            for (int r = 0; r < KP - 1; ++r) {
+                if (r < j - 1) {
+                    const double x0 = col[r], x1 = col[r + 1];
+                    col[r] = cm[r] * x0 + sm[r] * x1;
+                    col[r + 1] = -sm[r] * x0 + cm[r] * x1;
+                }
+            }
+            double aj = 0.0, hn = 0.0;
+#pragma unroll
+            for (int r = 0; r <= KP; ++r) {
+                if (r == j - 1) aj = col[r];
+                if (r == j) hn = col[r];
+            }
+            const double den = sqrt(aj * aj + hn * hn);
+            const double cj = den == 0.0 ? 1.0 : aj / den;
+            const double sj = den == 0.0 ? 0.0 : hn / den;
+#pragma unroll
+            for (int r = 0; r < KP; ++r) {
+                if (r < j - 1) Rm[r * k + (j - 1)] = col[r];
+                if (r == j - 1) Rm[r * k + (j - 1)] = den;
+            }
+            cm[j - 1] = cj;
+            sm[j - 1] = sj;
+            const double gj = gm[j - 1];
+            gm[j] = -sj * gj;
+            gm[j - 1] = cj * gj;
+            its[m] += 1;
+            jend[m] = j;
+            const double r = fabs(sj * gj);
+            resid[m] = r / fnorm[m];
+            if (r <= tol * fnorm[m] || hn == 0.0 || its[m] >= max_its) still = false;
+        }
+        if (!FINAL && still && !(rho > 0.0)) still = false;   // u_j in the span: nothing new
+        if (mode == kEnd || j >= k) still = false;
+        if (act && !still) active[m] = 0;
+        sstill[grp] = still ? 1 : 0;
+        if (still && nact_out) atomicAdd(nact_out, 1);
+    }
+    __syncthreads();
+    if (FINAL || m >= nb) return;
+    const int rows = 2 * j + 2;
+    if (!sstill[grp]) {
+        for (int r = q; r < rows; r += kGroup) coef[r * nb + m] = 0.0;
         return;
     }
-    int m = threadIdx.x;
-    int still = 0;
-    if (m < nb && active[m]) {
-        double *Hm = H + (int64_t)m * (k + 1) * k;
-        double *c = cs + m * k, *s = sn + m * k, *gm = g + m * (k + 1);
-        // h1[j+1] = ||w||^2 before, h2[j+1] = after the first pass; the
-        // second pass ran for this system only when it was needed
-        const bool re = needs_reorth(h1[(j + 1) * nb + m], h2[(j + 1) * nb + m]);
-        double hn = sqrt(fmax(re ? hn2_second[m] : h2[(j + 1) * nb + m], 0.0));
-        double col[KP + 1];
-        double cq[KP], sq[KP];
-#pragma unroll
-        for (int q = 0; q < KP; ++q) {
-            col[q] = (q <= j) ? h1[q * nb + m] + (re ? h2[q * nb + m] : 0.0) : 0.0;
-            cq[q] = (q < j) ? c[q] : 1.0;
-            sq[q] = (q < j) ? s[q] : 0.0;
-        }
-        col[KP] = 0.0;
-#pragma unroll
-        for (int q = 0; q < KP - 1; ++q) {
-            if (q < j) {
-                double a = col[q], b = col[q + 1];
-                col[q] = cq[q] * a + sq[q] * b;
-                col[q + 1] = -sq[q] * a + cq[q] * b;
-            }
-        }
-        double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < KP; ++q)
-            if (q == j) a = col[q];
-        double den = sqrt(a * a + hn * hn);
-        double cj = den == 0.0 ? 1.0 : a / den;
-        double sj = den == 0.0 ? 0.0 : hn / den;
-#pragma unroll
-        for (int q = 0; q < KP; ++q) {
-            if (q < j) Hm[q * k + j] = col[q];
-            if (q == j) Hm[q * k + j] = den;
-        }
-        c[j] = cj;
-        s[j] = sj;
-        double gj = gm[j];
-        gm[j + 1] = -sj * gj;
-        gm[j] = cj * gj;
-        its[m] += 1;
-        jend[m] = j + 1;
-        double r = fabs(sj * gj);
-        resid[m] = r / fnorm[m];
-        if (r <= tol * fnorm[m] || hn == 0.0 || its[m] >= max_its) {
-            active[m] = 0;
-            vscale[m] = 0.0;
-        } else {
-            still = 1;
-            vscale[m] = 1.0 / hn;
-        }
-    } else if (m < nb) {
-        vscale[m] = 0.0;
+    // t_q = sum_{p = max(q-1, 0)}^{j-1} a_p Ht[q][p] for q <= j (column j-1
+    // as corrected above)
+    double t = 0.0;
+    if (q <= j && j >= 1) {
+        for (int p = (q > 0 ? q - 1 : 0); p < j - 1; ++p) t += sa[grp][p] * Hm[q * k + p];
+        t += sa[grp][j - 1] * scol[grp][q];
     }
-    block_count(still, nactive, host_slot);
+    const double tj = __shfl(t, j < kGroup ? j : 0, kGroup);
+    const double vw = (c - ab) / rho;
+    const double hjj = (vw - tj) / rho;
+    const double sc = tj / rho + hjj;
+    if (q < j) Hm[q * k + j] = (b - t) / rho;
+    if (q == j) Hm[j * k + j] = hjj;
+    if (q < j) {
+        coef[q * nb + m] = a;
+        coef[(j + q) * nb + m] = b - sc * a;
+    }
+    if (q == 0) {
+        coef[(2 * j) * nb + m] = sc;
+        coef[(2 * j + 1) * nb + m] = 1.0 / rho;
+    }
 }
 
 // V_{j+1} = w * vscale (0 for systems that stopped).
@@ -343,7 +465,7 @@ __global__ void init_v0_kernel(int64_t n, int nb, const T *__restrict__ r, const
     v0[t] = active[m] ? (T)((double)r[t] / beta[m]) : (T)0;
 }
 
-// Least squares: back substitution H y = g over the jend columns.
+// Least squares: back substitution R y = g over the jend columns.
 __global__ void lsq_kernel(int nb, int k, const double *__restrict__ H, const double *__restrict__ g,
                            const int *__restrict__ jend, double *__restrict__ y)
 {
@@ -418,55 +540,72 @@ double pass_bytes(const KrylovT<T> &K, double nvec, int nq, unsigned blocks)
     return sizeof(T) * nvec * (double)K.n * K.nb + 8.0 * (double)blocks * nq * K.nb;
 }
 
-#define MLPG_NQ_CASES(X)                                                                                   \
-    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
-    X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31)
+#define MLPG_J_CASES(X)                                                                                     \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) \
+    X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30)
 
+// ||x_m||^2 for every system into out[m] (x of K's shape)
 template <class T>
-hipError_t dots(KrylovT<T> &K, const T *V, int nq, const T *w, double *out, const int *gate, hipStream_t s,
-                bool timed = false, int64_t vstride = 0, bool norm_row = false)
+hipError_t norm2(KrylovT<T> &K, const T *x, double *out, hipStream_t s)
 {
-    if (vstride == 0) vstride = K.vs;
-    if (nq < 1 || nq > KP) return hipErrorInvalidValue;
     Launch L = vec_launch(K.n, K.nb);
-    int id = timed ? prof_start(1, pass_bytes(K, nq + 1, nq, L.blocks), s) : -1;
-    switch (nq) {
-#define MLPG_DOTS_CASE(Q)                                                                                      \
-    case Q:                                                                                                     \
-        dots_kernel<T, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, V, vstride, w, K.part.p, gate);      \
-        break;
-        MLPG_NQ_CASES(MLPG_DOTS_CASE)
-#undef MLPG_DOTS_CASE
-    }
-    prof_stop(id, s);
-    // nq inner products, then ||w||^2 in row nq when norm_row is set
-    const int nr = nq + (norm_row ? 1 : 0);
-    reduce_part_kernel<<<nr, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nr, K.nb, K.part.p, out, gate);
+    norm2_kernel<T><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, x, K.part.p);
+    reduce_part_kernel<<<1, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, K.nb, K.part.p, out, nullptr);
     return hipGetLastError();
 }
 
-template <class T, int MODE>
-hipError_t gs_update(KrylovT<T> &K, int nq, T *w, const double *h, double *out, const T *dinv, T *z,
-                     const double *s1, const double *s2, const int *gate, hipStream_t s)
+// Pass A of step j (hw: with the operator output w) and its reduction into
+// K.h1 (rows as in pass_a_kernel).
+template <class T>
+hipError_t pass_a(KrylovT<T> &K, int j, const T *w, const int *gate, hipStream_t s)
 {
-    if (nq < 1 || nq > KP) return hipErrorInvalidValue;
+    if (j < 0 || j > kMaxRestart) return hipErrorInvalidValue;
     Launch L = vec_launch(K.n, K.nb);
-    // V_0..V_{nq-1} read, w read and written, dinv read and z written
-    double nvec = nq + 2 + (z ? (dinv ? 2 : 1) : 0);
-    int id = prof_start(MODE == 0 ? 2 : 3, pass_bytes(K, nvec, MODE == 0 ? nq + 1 : 1, L.blocks), s);
-    switch (nq) {
-#define MLPG_GS_CASE(Q)                                                                                        \
-    case Q:                                                                                                     \
-        gs_update_kernel<T, MODE, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, w, h,         \
-                                                                          K.part.p, dinv, z, s1, s2, gate);    \
+    const bool hw = w != nullptr;
+    const int rows = hw ? 2 * j + 2 : j + 1;
+    const T *u = K.V.p + (int64_t)j * K.vs;
+    int id = prof_start(hw ? 1 : 3, pass_bytes(K, j + (hw ? 2 : 1), rows, L.blocks), s);
+    switch (j) {
+#define MLPG_PA_CASE(Q)                                                                                          \
+    case Q:                                                                                                       \
+        if (hw)                                                                                                   \
+            pass_a_kernel<T, Q, true><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, w,          \
+                                                                           K.part.p, gate);                       \
+        else                                                                                                      \
+            pass_a_kernel<T, Q, false><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, nullptr,   \
+                                                                            K.part.p, gate);                      \
         break;
-        MLPG_NQ_CASES(MLPG_GS_CASE)
-#undef MLPG_GS_CASE
+        MLPG_J_CASES(MLPG_PA_CASE)
+#undef MLPG_PA_CASE
     }
     prof_stop(id, s);
-    const int nr = MODE == 0 ? nq + 1 : 1;
-    reduce_part_kernel<<<nr, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, nr, K.nb, K.part.p, out, gate,
-                                                          MODE == 1 ? s1 : nullptr, MODE == 1 ? s2 : nullptr);
+    reduce_part_kernel<<<rows, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, K.nb, K.part.p, K.h1.p, gate);
+    return hipGetLastError();
+}
+
+// Pass B of step j on w (in place) with the coefficients in K.h2, then the
+// norm reduction (beta, vscale) and the host slot.
+template <class T>
+hipError_t pass_b(KrylovT<T> &K, int j, T *w, const T *dinv, T *z, const int *gate, int *host_slot, hipStream_t s)
+{
+    if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
+    Launch L = vec_launch(K.n, K.nb);
+    T *u = K.V.p + (int64_t)j * K.vs;
+    // V_0..V_{j-1}, u and w read; u and w written; dinv read and z written
+    const double nvec = j + 4 + (z ? (dinv ? 2 : 1) : 0);
+    int id = prof_start(2, pass_bytes(K, nvec, 1, L.blocks), s);
+    switch (j) {
+#define MLPG_PB_CASE(Q)                                                                                      \
+    case Q:                                                                                                   \
+        pass_b_kernel<T, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, w, K.h2.p, dinv, \
+                                                                 z, K.part.p, gate);                          \
+        break;
+        MLPG_J_CASES(MLPG_PB_CASE)
+#undef MLPG_PB_CASE
+    }
+    prof_stop(id, s);
+    reduce_norm_kernel<<<1, rpb_of(K.nb) * K.nb, 0, s>>>((int)L.blocks, K.nb, K.part.p, K.active.p, K.beta.p,
+                                                         K.vscale.p, gate, host_slot);
     return hipGetLastError();
 }
 
@@ -488,10 +627,11 @@ hipError_t KrylovT<T>::ensure(int64_t n_, int nb_, int k_)
     if ((e = z.alloc((size_t)n * nb)) != hipSuccess) return e;
     if ((e = r.alloc((size_t)n * nb)) != hipSuccess) return e;
     part_blocks = kPartBlocks;   // partial-sum rows; vec_launch never exceeds it
-    if ((e = part.alloc((size_t)part_blocks * (KP + 1) * nb)) != hipSuccess) return e;
-    if ((e = h1.alloc((size_t)(KP + 1) * nb)) != hipSuccess) return e;
-    if ((e = h2.alloc((size_t)(KP + 1) * nb)) != hipSuccess) return e;
+    if ((e = part.alloc((size_t)part_blocks * kRows * nb)) != hipSuccess) return e;
+    if ((e = h1.alloc((size_t)kRows * nb)) != hipSuccess) return e;
+    if ((e = h2.alloc((size_t)kRows * nb)) != hipSuccess) return e;
     if ((e = H.alloc((size_t)nb * (k + 1) * k)) != hipSuccess) return e;
+    if ((e = Ht.alloc((size_t)nb * (k + 1) * k)) != hipSuccess) return e;
     if ((e = cs.alloc((size_t)nb * k)) != hipSuccess) return e;
     if ((e = sn.alloc((size_t)nb * k)) != hipSuccess) return e;
     if ((e = g.alloc((size_t)nb * (k + 1))) != hipSuccess) return e;
@@ -504,7 +644,7 @@ hipError_t KrylovT<T>::ensure(int64_t n_, int nb_, int k_)
     if ((e = done.alloc(nb)) != hipSuccess) return e;
     if ((e = its.alloc(nb)) != hipSuccess) return e;
     if ((e = jend.alloc(nb)) != hipSuccess) return e;
-    if ((e = nactive.alloc(1)) != hipSuccess) return e;
+    if ((e = nactive.alloc(3)) != hipSuccess) return e;
     if (!nactive_host) {
         if ((e = hipHostMalloc((void **)&nactive_host, sizeof(int) * kSlots, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
             return e;
@@ -519,7 +659,7 @@ template <class T>
 void KrylovT<T>::release()
 {
     V.release(); w.release(); w2.release(); z.release(); r.release(); part.release(); h1.release(); h2.release(); H.release();
-    cs.release(); sn.release(); g.release(); y.release(); vscale.release(); fnorm.release(); beta.release();
+    Ht.release(); cs.release(); sn.release(); g.release(); y.release(); vscale.release(); fnorm.release(); beta.release();
     resid.release(); active.release(); done.release(); its.release(); jend.release(); nactive.release();
     if (nactive_host) {
         (void)hipHostFree(nactive_host);
@@ -545,9 +685,11 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     const int k = restart;
     const int64_t cnt = n * nb;
     const int nbt = ((nb + 63) / 64) * 64;
-    const int *gate = K.nactive.p;
+    const unsigned small_blocks = (unsigned)((nb + kGroupsPerBlock - 1) / kGroupsPerBlock);
+    const bool precheck = !fused;   // the operator without fused normalisation is the outer one
+    int *nact = K.nactive.p;   // three rotating active counters (gates)
     // ||f||
-    MLPG_HIP(dots<T>(K, f, 1, f, K.beta.p, nullptr, s, false, cnt));
+    MLPG_HIP(norm2<T>(K, f, K.beta.p, s));
     sqrt_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, K.beta.p, K.fnorm.p);
     MLPG_HIP(hipMemsetAsync(K.its.p, 0, sizeof(int) * nb, s));
     if (x_zero) {
@@ -563,24 +705,45 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     }
     int64_t sw = 0;
     for (;;) {
-        MLPG_HIP(dots<T>(K, K.r.p, 1, K.r.p, K.h1.p, nullptr, s, false, cnt));
+        MLPG_HIP(norm2<T>(K, K.r.p, K.h1.p, s));
         cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, max_its, K.its.p, K.active.p, K.done.p,
-                                            K.g.p, K.beta.p, K.resid.p, K.jend.p, K.nactive.p, K.nactive_hdev);
+                                            K.g.p, K.beta.p, K.resid.p, K.jend.p, nact, nact + 1, K.nactive_hdev);
         MLPG_HIP(hipStreamSynchronize(s));
         if (K.nactive_host[0] == 0) break;
         init_v0_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.r.p, K.beta.p, K.active.p, K.V.p);
         int jc = 0;
+        bool early = false;
         T *wcur = K.w.p, *wprev = K.w2.p;
         const int64_t base = sw;   // sweeps before this cycle
         for (int j = 0; j < k; ++j) {
+            const int *gate = nact + (j % 3);          // active going into step j
+            int *nnext = nact + ((j + 1) % 3);         // active after step j
+            // An expensive operator (the outer iteration, whose every
+            // application is a full set of inner solves) is not applied to a
+            // vector that would not be needed: the previous column is
+            // corrected and tested first, and the host stops when no system
+            // is left.
+            const bool pre = precheck && j >= 1;
+            if (pre) {
+                MLPG_HIP(pass_a<T>(K, j, nullptr, gate, s));
+                step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
+                    kPre, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol,
+                    max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nullptr, nullptr);
+                std::vector<int> act(nb);
+                MLPG_HIP(hipMemcpyAsync(act.data(), K.active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+                MLPG_HIP(hipStreamSynchronize(s));
+                bool any = false;
+                for (int v : act) any = any || v != 0;
+                if (!any) { early = true; break; }
+            }
             OpCallT<T> c;
             c.dinv = dinv;
             c.gate = gate;
             if (j == 0 || !fused) {
                 c.in = K.V.p + (int64_t)j * K.vs;
             } else {
-                // z = dinv .* w of the previous step, scaled by 1/h_{j,j-1};
-                // the SpMV also stores the normalised basis vector V_j
+                // z = dinv .* w_{j-1}, scaled by 1/beta; the SpMV also stores
+                // the normalised new vector u_j in basis slot j
                 c.in = K.z.p;
                 c.dinv = nullptr;
                 c.colscale = K.vscale.p;
@@ -590,33 +753,36 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             c.out = wcur;
             int rc = op(P, c, s, ctx);
             if (rc) return rc;
-            MLPG_HIP(dots<T>(K, K.V.p, j + 1, wcur, K.h1.p, gate, s, true, 0, true));
-            // first pass (z written for every system), then the second pass for
-            // the systems whose first pass cancelled most of w
-            T *zz = fused ? K.z.p : nullptr;
-            const double *s1 = K.h1.p + (int64_t)(j + 1) * nb, *s2 = K.h2.p + (int64_t)(j + 1) * nb;
-            MLPG_HIP((gs_update<T, 0>(K, j + 1, wcur, K.h1.p, K.h2.p, dinv, zz, nullptr, nullptr, gate, s)));
-            MLPG_HIP((gs_update<T, 1>(K, j + 1, wcur, K.h2.p, K.beta.p, dinv, zz, s1, s2, gate, s)));
-            // K.beta holds ||w||^2 during the cycle; cycle_init rewrites it.
+            MLPG_HIP(pass_a<T>(K, j, wcur, gate, s));
+            step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
+                pre ? kAfterPre : kStep, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
+                K.fnorm.p, tol, max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nnext,
+                nact + ((j + 2) % 3));
             const int slot = (int)(sw % kSlots);
-            arnoldi_kernel<<<1, nbt, 0, s>>>(nb, k, j, K.h1.p, K.h2.p, K.beta.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
-                                             K.fnorm.p, tol, max_its, K.active.p, K.its.p, K.jend.p, K.vscale.p,
-                                             K.resid.p, K.nactive.p, K.nactive_hdev + slot, gate);
+            MLPG_HIP(pass_b<T>(K, j, wcur, dinv, fused ? K.z.p : nullptr, nnext, K.nactive_hdev + slot, s));
             MLPG_HIP(hipEventRecord(K.ev[slot], s));
             sw++;
             jc = j + 1;
-            if (j == k - 1) break;
-            if (!fused)
+            if (!fused || j == k - 1)
                 normalize_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, wcur, K.vscale.p,
-                                                                      K.V.p + (int64_t)(j + 1) * K.vs, gate);
+                                                                      K.V.p + (int64_t)(j + 1) * K.vs, nnext);
+            if (j == k - 1) break;
             std::swap(wcur, wprev);
             // read the active count of the sweep `lag` steps back (same cycle)
             const int64_t chk = sw - lag;
             if (chk >= base) {
                 const int cs = (int)(chk % kSlots);
                 MLPG_HIP(hipEventSynchronize(K.ev[cs]));
-                if (K.nactive_host[cs] == 0) break;
+                if (K.nactive_host[cs] == 0) { early = true; break; }
             }
+        }
+        if (!early && jc == k) {
+            // end of the cycle: the last column's delayed correction
+            const int *gate = nact + (k % 3);
+            MLPG_HIP(pass_a<T>(K, k, nullptr, gate, s));
+            step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
+                kEnd, nb, k, k, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol,
+                max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nact + ((k + 1) % 3), nullptr);
         }
         lsq_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
         x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, dinv, x);
@@ -651,7 +817,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
 
 hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s)
 {
-    return dots<double>(K, x, 1, x, out, nullptr, s, false, K.n * K.nb);
+    return norm2<double>(K, x, out, s);
 }
 
 template struct KrylovT<double>;

@@ -286,7 +286,7 @@ def mlpg_destroy(h):
         lib().mlpg_destroy(h)
 
 
-PROF_CLASSES = ("spmv_L", "gs_dots", "gs_update_dots", "gs_update_norm")
+PROF_CLASSES = ("spmv_L", "gs_pass_a", "gs_pass_b", "gs_cycle_end")
 
 
 def mlpg_profile_begin():

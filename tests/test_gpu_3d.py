@@ -138,7 +138,7 @@ def test_operator_sweeps_3d():
 
 
 def _solve_both_3d(n, M, order, sig_t, sig_s, inv_c_dt, steps, q_fn, psib_fn=None, psi0_fn=None, jitter=0.2,
-                   rfac=2.5, precision=None, omega=None, w=None):
+                   rfac=2.5, precision=None, omega=None, w=None, max_inner=None):
     from paper_2008_02205_amd import mlpg
     x, R, dx = _lattice3(n, jitter, rfac=rfac)
     g = oracle.geometry(x, R, LO, HI)
@@ -164,7 +164,11 @@ def _solve_both_3d(n, M, order, sig_t, sig_s, inv_c_dt, steps, q_fn, psib_fn=Non
         pb_o = psib_fn(it.bq_y, om_o, t) if psib_fn else None
         psi_o, phi_o, info_o = tr.step(psi_o, q_fn(x, om_o, t), pb_o, phi_o)
         pb_g = _dev(psib_fn(_cpu(y_g), om_g, t)) if psib_fn else None
-        phi_g, pv_g, psi_g, info_g = P.step(_dev(q_fn(x, om_g, t)), pb_g)
+        opts = None
+        if max_inner:
+            opts = mlpg.mlpg_default_opts()
+            opts.max_inner = max_inner
+        phi_g, pv_g, psi_g, info_g = P.step(_dev(q_fn(x, om_g, t)), pb_g, opts)
         e = (rel_l2(_cpu(phi_g), phi_o), rel_l2(_cpu(pv_g), tr.point_values(phi_o)), rel_l2(_cpu(psi_g), psi_o))
         print(f"step {s}: phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} outer {info_g['outer_iters']} "
               f"(oracle {info_o['outer_iters']})", flush=True)
@@ -191,7 +195,9 @@ def test_steady_gaussian_source_3d(precision):
 def test_quadratic_rk_scattering_3d():
     """Quadratic RK with R = 2.5 h (the 3D workload's discretisation) at 5^3, 12 ordinates."""
     _print_case("quadratic3d", n=5, M=12)
-    for e, info in _solve_both_3d(5, 12, 2, 1.0, 0.9, 0.0, 1, _gauss):
+    # restarted GMRES(30) with point Jacobi needs 700-2300 steps per ordinate
+    # here, and the tail depends on rounding; the GPU gets room beyond 3000
+    for e, info in _solve_both_3d(5, 12, 2, 1.0, 0.9, 0.0, 1, _gauss, max_inner=10000):
         assert info["converged"] == 1
         # quadratic-RK blocks agree to ~1e-10 (see the stage test); the solve
         # amplifies that by the condition of the transport system
