@@ -219,12 +219,15 @@ __device__ __forceinline__ float bcast(float v, int lane)
 }
 
 // Wave-per-row SpMV (used when the ordinates fill whole waves): each wave
-// owns one (row, 64-ordinate chunk).  The row's column indices and stream
-// values are read with one coalesced load (lane l holds nonzero l of the
-// chunk) and broadcast with readlane, and four x gathers are issued at a
-// time so that their latencies overlap.
+// owns one (row, 64-ordinate chunk).  The row index is wave-uniform, so the
+// row's column indices and stream values are read with scalar loads straight
+// into SGPRs (read-only kernel arguments, no vector broadcast needed) and
+// combined with the lane's own coefficients; the x gathers of eight nonzeros
+// are issued back to back so that their latencies overlap.
 template <int NS, class T, int MODE>
-__global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK<T> k)
+__global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
+                                                        const int32_t *__restrict__ col,
+                                                        const T *__restrict__ vals)
 {
     if (k.gate && *k.gate == 0) return;
     // Workgroups are dealt round-robin to the dies (XCDs), each with its own
@@ -248,67 +251,50 @@ __global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK<T> k)
         T c[NS];
 #pragma unroll
         for (int b = 0; b < NS; ++b) c[b] = k.coef[mm * NS + b];
-        const int64_t p0 = k.row_off[iu], p1 = k.row_off[iu + 1];
+        const int64_t p0 = row_off[iu], p1 = row_off[iu + 1];
         T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        for (int64_t pb = p0; pb < p1; pb += 64) {
-            const int cnt = (int)(p1 - pb < 64 ? p1 - pb : 64);
-            const bool has = lane < cnt;
-            // unconditional loads from a clamped index (then a select), so
-            // that the column and the NS values are fetched together
-            const int64_t pl = pb + (has ? lane : 0);
-            int lcol = k.col[pl];
-            T lv[NS];
+        int64_t p = p0;
+        for (; p + 7 < p1; p += 8) {
+            int32_t jj[8];
+            T xx[8], aa[8];
 #pragma unroll
-            for (int b = 0; b < NS; ++b) lv[b] = k.vals[pl * NS + b];
-            lcol = has ? lcol : 0;
+            for (int u = 0; u < 8; ++u) jj[u] = col[p + u];
 #pragma unroll
-            for (int b = 0; b < NS; ++b) lv[b] = has ? lv[b] : (T)0;
-            int q = 0;
-            for (; q + 7 < cnt; q += 8) {
-                int64_t jj[8];
-                T xx[8], aa[8];
+            for (int u = 0; u < 8; ++u) xx[u] = xin<MODE>(k, jj[u], mm);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) jj[u] = __builtin_amdgcn_readlane(lcol, q + u);
+            for (int u = 0; u < 8; ++u) {
+                T a = 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) xx[u] = xin<MODE>(k, jj[u], mm);
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    T a = 0;
-#pragma unroll
-                    for (int b = 0; b < NS; ++b) a += c[b] * bcast(lv[b], q + u);
-                    aa[u] = a;
-                }
-                acc0 += aa[0] * xx[0] + aa[4] * xx[4];
-                acc1 += aa[1] * xx[1] + aa[5] * xx[5];
-                acc2 += aa[2] * xx[2] + aa[6] * xx[6];
-                acc3 += aa[3] * xx[3] + aa[7] * xx[7];
+                for (int b = 0; b < NS; ++b) a += c[b] * vals[(p + u) * NS + b];
+                aa[u] = a;
             }
-            for (; q + 3 < cnt; q += 4) {
-                const int64_t j0 = __builtin_amdgcn_readlane(lcol, q);
-                const int64_t j1 = __builtin_amdgcn_readlane(lcol, q + 1);
-                const int64_t j2 = __builtin_amdgcn_readlane(lcol, q + 2);
-                const int64_t j3 = __builtin_amdgcn_readlane(lcol, q + 3);
-                const T x0 = xin<MODE>(k, j0, mm), x1 = xin<MODE>(k, j1, mm), x2 = xin<MODE>(k, j2, mm), x3 = xin<MODE>(k, j3, mm);
-                T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+            acc0 += aa[0] * xx[0] + aa[4] * xx[4];
+            acc1 += aa[1] * xx[1] + aa[5] * xx[5];
+            acc2 += aa[2] * xx[2] + aa[6] * xx[6];
+            acc3 += aa[3] * xx[3] + aa[7] * xx[7];
+        }
+        for (; p + 3 < p1; p += 4) {
+            const int32_t j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
+            const T x0 = xin<MODE>(k, j0, mm), x1 = xin<MODE>(k, j1, mm), x2 = xin<MODE>(k, j2, mm),
+                    x3 = xin<MODE>(k, j3, mm);
+            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
-                for (int b = 0; b < NS; ++b) {
-                    a0 += c[b] * bcast(lv[b], q);
-                    a1 += c[b] * bcast(lv[b], q + 1);
-                    a2 += c[b] * bcast(lv[b], q + 2);
-                    a3 += c[b] * bcast(lv[b], q + 3);
-                }
-                acc0 += a0 * x0;
-                acc1 += a1 * x1;
-                acc2 += a2 * x2;
-                acc3 += a3 * x3;
+            for (int b = 0; b < NS; ++b) {
+                a0 += c[b] * vals[p * NS + b];
+                a1 += c[b] * vals[(p + 1) * NS + b];
+                a2 += c[b] * vals[(p + 2) * NS + b];
+                a3 += c[b] * vals[(p + 3) * NS + b];
             }
-            for (; q < cnt; ++q) {
-                const int64_t j0 = __builtin_amdgcn_readlane(lcol, q);
-                T a0 = 0;
+            acc0 += a0 * x0;
+            acc1 += a1 * x1;
+            acc2 += a2 * x2;
+            acc3 += a3 * x3;
+        }
+        for (; p < p1; ++p) {
+            T a0 = 0;
 #pragma unroll
-                for (int b = 0; b < NS; ++b) a0 += c[b] * bcast(lv[b], q);
-                acc0 += a0 * xin<MODE>(k, j0, mm);
-            }
+            for (int b = 0; b < NS; ++b) a0 += c[b] * vals[p * NS + b];
+            acc0 += a0 * xin<MODE>(k, col[p], mm);
         }
         T acc = (acc0 + acc1) + (acc2 + acc3);
         if (k.soff) acc += spmv_surface<MODE>(k, iu, mm);
@@ -516,7 +502,7 @@ hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
     if (a.dinv) mode = IN_DINV;
     if ((a.x_bcast != 0) + (a.x2 != nullptr) + (a.dinv != nullptr) > 1) return hipErrorInvalidValue;
 #define MLPG_SPMV_M(NSV, MD)                                                      \
-    if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k);        \
+    if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals); \
     else spmv_group_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k)
 #define MLPG_SPMV(NSV)                                                            \
     switch (mode) {                                                               \
