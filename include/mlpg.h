@@ -226,7 +226,8 @@ typedef struct {
     int max_inner;        /* Arnoldi steps per ordinate per solve (default 3000) */
     int max_outer;        /* (default 500) */
     int check_every;      /* Arnoldi steps queued ahead of the host convergence check (default 3) */
-    double tol_inner_lo;  /* MLPG_MIXED: FP32 correction solves stop at this relative residual (default 1e-4) */
+    double tol_inner_lo;  /* MLPG_MIXED: FP32 correction solves stop at this relative residual, or earlier
+                             for an ordinate whose remaining gap to tol_inner is smaller (default 3e-5) */
     int max_refine;       /* MLPG_MIXED: FP64 refinement steps per inner solve (default 12) */
 } mlpg_solve_opts;
 

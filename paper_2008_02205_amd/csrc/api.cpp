@@ -25,7 +25,7 @@ void Problem::release()
     phi.release(); F.release(); bpsi.release(); t1.release(); t2.release(); bphi.release(); ovec.release();
     inner.release(); outer.release(); inner32.release();
     sL32.release(); coefL32.release(); coefF32.release(); surf_val32.release(); dinv32.release(); r32.release();
-    d32.release(); mr.release(); rn2.release(); fn2.release();
+    d32.release(); mr.release(); rn2.release(); fn2.release(); tolv.release();
 }
 
 namespace {
@@ -105,7 +105,8 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
     MLPG_HIP(hipMemsetAsync(x, 0, sizeof(double) * cnt, s));
     MLPG_HIP(hipMemcpyAsync(P.mr.p, f, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
     MLPG_HIP(batched_norm2(P.inner, f, P.fn2.p, s));
-    std::vector<double> fn2(M), rn2(M);
+    std::vector<double> fn2(M), rn2(M), tolm(M);
+    MLPG_HIP(P.tolv.alloc(M));
     MLPG_HIP(hipMemcpyAsync(fn2.data(), P.fn2.p, sizeof(double) * M, hipMemcpyDeviceToHost, s));
     bool conv = false;
     double worst = 0.0;
@@ -121,12 +122,21 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
             if (fn2[m] > 0.0 && rel > o.tol_inner) conv = false;
         }
         if (conv || it >= o.max_refine) break;
+        // Per ordinate, the correction only has to close the remaining gap
+        // (with a factor 2 to spare), never looser than 1/2 and never
+        // tighter than tol_inner_lo.
+        for (int m = 0; m < M; ++m) {
+            const double need = rn2[m] > 0.0 ? 0.5 * o.tol_inner * std::sqrt(fn2[m] / rn2[m]) : 0.5;
+            tolm[m] = std::min(0.5, std::max(o.tol_inner_lo, need));
+        }
+        MLPG_HIP(hipMemcpyAsync(P.tolv.p, tolm.data(), sizeof(double) * M, hipMemcpyHostToDevice, s));
         MLPG_HIP(launch_to_float_scaled(n, M, P.mr.p, P.rn2.p, P.fn2.p, o.tol_inner, P.r32.p, s));
         bool c32 = true;
         double rm32 = 0.0;
         int rc = gmres_batched<float>(P, P.inner32, op_L32, true, nullptr, P.dinv32.p, P.r32.p, P.d32.p, n, M,
                                       o.tol_inner_lo, o.restart_inner, o.max_inner, o.check_every, true, s, &c.its,
-                                      &c.sweeps, &rm32, &c32);
+                                      &c.sweeps, &rm32, &c32, P.tolv.p);
+        MLPG_HIP(hipStreamSynchronize(s));   // tolm is read by the copy above
         if (rc) return rc;
         MLPG_HIP(launch_axpy_from_float(n, M, x, P.d32.p, P.rn2.p, s));
         SpmvArgs a;
@@ -588,7 +598,7 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->max_inner = 3000;
     o->max_outer = 500;
     o->check_every = 3;
-    o->tol_inner_lo = 1e-4;
+    o->tol_inner_lo = 3e-5;
     o->max_refine = 12;
 }
 

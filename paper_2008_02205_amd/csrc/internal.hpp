@@ -196,7 +196,7 @@ struct Problem {
     // mixed precision: FP32 copies of the L streams, coefficients, surface
     // values and Jacobi scaling; refinement scratch
     DevBuf<float> sL32, coefL32, coefF32, surf_val32, dinv32, r32, d32;
-    DevBuf<double> mr, rn2, fn2;
+    DevBuf<double> mr, rn2, fn2, tolv;
     int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
 
     void release();
@@ -285,7 +285,8 @@ using OpFn = OpFnT<double>;
 template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
-                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged);
+                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged,
+                  const double *tolv = nullptr);   // optional per-system relative tolerance (device [nb])
 // out[m] = sum_i x[i][m]^2 for the nb systems of K's shape
 hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s);
 

@@ -256,7 +256,8 @@ __global__ void sqrt_kernel(int nb, const double *in, double *out)
 // Start of a restart cycle: beta = ||r||; decide which systems iterate; the
 // active count goes to nact0, nact1 is cleared for step 0's count.
 __global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, const double *__restrict__ beta2,
-                                                              const double *__restrict__ fnorm, double tol,
+                                                              const double *__restrict__ fnorm, double tol0,
+                                                              const double *__restrict__ tolv,
                                                               int max_its, const int *__restrict__ its,
                                                               int *__restrict__ active, int *__restrict__ done,
                                                               double *__restrict__ g, double *__restrict__ beta,
@@ -269,6 +270,7 @@ __global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, con
     __syncthreads();
     int m = threadIdx.x;
     if (m < nb) {
+        const double tol = tolv ? tolv[m] : tol0;
         double b = sqrt(fmax(beta2[m], 0.0));
         double fn = fnorm[m];
         beta[m] = b;
@@ -313,7 +315,8 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
                                                               double *__restrict__ Ht, double *__restrict__ R,
                                                               double *__restrict__ cs, double *__restrict__ sn,
                                                               double *__restrict__ g,
-                                                              const double *__restrict__ fnorm, double tol,
+                                                              const double *__restrict__ fnorm, double tol0,
+                                                              const double *__restrict__ tolv,
                                                               int max_its, int *__restrict__ active,
                                                               int *__restrict__ its, int *__restrict__ jend,
                                                               double *__restrict__ resid, double *__restrict__ coef,
@@ -405,6 +408,7 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
             jend[m] = j;
             const double r = fabs(sj * gj);
             resid[m] = r / fnorm[m];
+            const double tol = tolv ? tolv[m] : tol0;
             if (r <= tol * fnorm[m] || hn == 0.0 || its[m] >= max_its) still = false;
         }
         if (!FINAL && still && !(rho > 0.0)) still = false;   // u_j in the span: nothing new
@@ -675,7 +679,7 @@ void KrylovT<T>::release()
 template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
-                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged)
+                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged, const double *tolv)
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
@@ -706,7 +710,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     int64_t sw = 0;
     for (;;) {
         MLPG_HIP(norm2<T>(K, K.r.p, K.h1.p, s));
-        cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, max_its, K.its.p, K.active.p, K.done.p,
+        cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, tolv, max_its, K.its.p, K.active.p, K.done.p,
                                             K.g.p, K.beta.p, K.resid.p, K.jend.p, nact, nact + 1, K.nactive_hdev);
         MLPG_HIP(hipStreamSynchronize(s));
         if (K.nactive_host[0] == 0) break;
@@ -727,7 +731,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             if (pre) {
                 MLPG_HIP(pass_a<T>(K, j, nullptr, gate, s));
                 step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
-                    kPre, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol,
+                    kPre, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
                     max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nullptr, nullptr);
                 std::vector<int> act(nb);
                 MLPG_HIP(hipMemcpyAsync(act.data(), K.active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
@@ -756,7 +760,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             MLPG_HIP(pass_a<T>(K, j, wcur, gate, s));
             step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
                 pre ? kAfterPre : kStep, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
-                K.fnorm.p, tol, max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nnext,
+                K.fnorm.p, tol, tolv, max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nnext,
                 nact + ((j + 2) % 3));
             const int slot = (int)(sw % kSlots);
             MLPG_HIP(pass_b<T>(K, j, wcur, dinv, fused ? K.z.p : nullptr, nnext, K.nactive_hdev + slot, s));
@@ -781,7 +785,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             const int *gate = nact + (k % 3);
             MLPG_HIP(pass_a<T>(K, k, nullptr, gate, s));
             step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
-                kEnd, nb, k, k, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol,
+                kEnd, nb, k, k, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
                 max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nact + ((k + 1) % 3), nullptr);
         }
         lsq_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
@@ -824,9 +828,9 @@ template struct KrylovT<double>;
 template struct KrylovT<float>;
 template int gmres_batched<double>(Problem &, KrylovT<double> &, OpFnT<double>, bool, void *, const double *,
                                    const double *, double *, int64_t, int, double, int, int, int, bool, hipStream_t,
-                                   int64_t *, int64_t *, double *, bool *);
+                                   int64_t *, int64_t *, double *, bool *, const double *);
 template int gmres_batched<float>(Problem &, KrylovT<float> &, OpFnT<float>, bool, void *, const float *,
                                   const float *, float *, int64_t, int, double, int, int, int, bool, hipStream_t,
-                                  int64_t *, int64_t *, double *, bool *);
+                                  int64_t *, int64_t *, double *, bool *, const double *);
 
 }  // namespace mlpg
