@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both",
                     help="fp64: plain FP64 path; mixed: FP32 SpMV/basis inside FP64 refinement")
     ap.add_argument("--tol-lo", type=float, default=None, help="FP32 correction tolerance of the mixed path")
+    ap.add_argument("--serving", type=int, default=0,
+                    help="instead of the benchmark: serve this many requests of the seeded request stream "
+                         "(Poisson arrivals at 50/s, mixed precision) and print latency and throughput")
+    ap.add_argument("--slots", type=int, default=4, help="concurrent problems in the serving mode")
     ap.add_argument("--probe", action="store_true",
                     help="hardware-counter probe: setup, one short solve of the workload and a 256 MiB "
                          "device copy (the reference for counter scaling); prints nothing")
@@ -65,6 +69,9 @@ def main():
 
     torch.cuda.set_device(0)
     mlpg.lib()
+    if args.serving:
+        serve(args)
+        return
     w = W.config(2, args.scale)
     x, dx = W.points_for(w)
     R = W.radii_for(w, x, dx)
@@ -182,6 +189,32 @@ def main():
             "roofline": roofline(prof2, counters=False)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
+    print(json.dumps(rec), flush=True)
+
+
+def serve(args):
+    """Request-stream mode: continuous batching with HBM-budget admission."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.serving import Server, latency_summary
+
+    def build(spec):
+        x, R, dx = W.request_problem(spec)
+        om, wq = mlpg.mlpg_angular_quadrature(2, spec.n_ord)
+        return x, R, dx, om, wq, spec.sigma_t, spec.sigma_s, np.ones((x.shape[0], spec.n_ord))
+
+    specs = W.request_stream(args.serving)
+    t0 = time.perf_counter()
+    res = Server(slots=args.slots).run(specs, build, realtime=True, keep_fields=False)
+    el = time.perf_counter() - t0
+    summ = latency_summary(res)
+    its = sum(r.info["inner_iters"] * r_spec.side ** 2 for r, r_spec in zip(res, specs) if r.info)
+    rec = {"metric": "request-stream latency (p50/p99) and throughput", "value": summ["p50_s"], "unit": "s",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"request stream: {args.serving} steady 2D problems, Poisson arrivals at 50/s, "
+                                  f"N log-uniform in [1024, 65536], M in {{16,32,64,128}}, mixed precision",
+                      "slots": args.slots},
+           "serving": summ, "offered_req_s": len(specs) / specs[-1].arrival,
+           "DOF*ord*iter_per_s": its / el, "wall_s": el}
     print(json.dumps(rec), flush=True)
 
 

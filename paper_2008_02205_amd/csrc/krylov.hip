@@ -325,6 +325,7 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
                                                               int *__restrict__ nact_clear)
 {
     __shared__ double sa[kGroupsPerBlock][KP + 1], scol[kGroupsPerBlock][KP + 1];
+    __shared__ double scs[kGroupsPerBlock][KP + 1], ssn[kGroupsPerBlock][KP + 1];
     __shared__ int sstill[kGroupsPerBlock];
     if (blockIdx.x == 0 && threadIdx.x == 0 && nact_clear) nact_clear[0] = 0;
     if (gate && *gate == 0) return;
@@ -354,6 +355,11 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     double *Hm = Ht + (int64_t)(m < nb ? m : 0) * (k + 1) * k;
     sa[grp][q] = a;
     if (act && mode == kAfterPre && j >= 1 && q <= j) scol[grp][q] = Hm[q * k + (j - 1)];
+    // the earlier rotations, staged for the serial part below
+    if (act && correct && q < j - 1) {
+        scs[grp][q] = cs[m * k + q];
+        ssn[grp][q] = sn[m * k + q];
+    }
     if (act && correct) {
         const double bp = betap[m];
         if (q < j) {
@@ -380,9 +386,10 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
 #pragma unroll
             for (int r = 0; r < KP - 1; ++r) {
                 if (r < j - 1) {
+                    const double cr = scs[grp][r], sr = ssn[grp][r];
                     const double x0 = col[r], x1 = col[r + 1];
-                    col[r] = cm[r] * x0 + sm[r] * x1;
-                    col[r + 1] = -sm[r] * x0 + cm[r] * x1;
+                    col[r] = cr * x0 + sr * x1;
+                    col[r + 1] = -sr * x0 + cr * x1;
                 }
             }
             double aj = 0.0, hn = 0.0;
@@ -428,7 +435,12 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     // as corrected above)
     double t = 0.0;
     if (q <= j && j >= 1) {
-        for (int p = (q > 0 ? q - 1 : 0); p < j - 1; ++p) t += sa[grp][p] * Hm[q * k + p];
+        // all loads of the row issue together (predicated, no dependence)
+        double hv[KP];
+#pragma unroll
+        for (int p = 0; p < KP; ++p) hv[p] = (p + 1 >= q && p < j - 1) ? Hm[q * k + p] : 0.0;
+#pragma unroll
+        for (int p = 0; p < KP; ++p) t += sa[grp][p] * hv[p];
         t += sa[grp][j - 1] * scol[grp][q];
     }
     const double tj = __shfl(t, j < kGroup ? j : 0, kGroup);

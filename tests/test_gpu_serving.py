@@ -1,0 +1,79 @@
+"""The request-stream loop: results alone and in the mix agree, budgeted
+admission holds requests back, and a served request matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests._cases import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MIXED_TOL = 1e-8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_02205_amd import mlpg
+    mlpg.lib()
+
+
+def _specs(count=8):
+    return W.request_stream(count, rate=200.0, n_min=100, n_max=700, ordinates=(16, 32), sigma_range=(0.5, 20.0))
+
+
+def _build(spec):
+    from paper_2008_02205_amd import mlpg
+    x, R, dx = W.request_problem(spec)
+    om, w = mlpg.mlpg_angular_quadrature(2, spec.n_ord)
+    q = np.ones((x.shape[0], spec.n_ord))
+    return x, R, dx, om, w, spec.sigma_t, spec.sigma_s, q
+
+
+def test_alone_and_in_the_mix_agree():
+    from paper_2008_02205_amd.serving import Server, latency_summary
+    specs = _specs()
+    print("[case] serving mix", [(s.side, s.n_ord, round(s.sigma_t, 2)) for s in specs], flush=True)
+    mix = Server(slots=4).run(specs, _build, realtime=False)
+    alone = Server(slots=1).run(specs, _build, realtime=False)
+    print(latency_summary(mix), flush=True)
+    for a, b in zip(mix, alone):
+        assert a.error is None and b.error is None, (a.error, b.error)
+        assert a.info["converged"] == 1
+        e = rel_l2(a.phi, b.phi)
+        print(f"request {a.rid}: mix vs alone {e:.1e}", flush=True)
+        assert e <= MIXED_TOL
+    # the mix really overlapped: some request was admitted before another finished
+    assert any(b.admitted < a.done and b.rid != a.rid and b.admitted >= a.admitted for a in mix for b in mix)
+
+
+def test_budget_admission_serialises():
+    from paper_2008_02205_amd.serving import Server, hbm_estimate
+    from paper_2008_02205_amd import mlpg
+    specs = _specs(4)
+    need = max(hbm_estimate(s.side * s.side, s.n_ord, mlpg.MLPG_MIXED) for s in specs)
+    res = Server(slots=4, budget_bytes=need + 1).run(specs, _build, realtime=False)
+    spans = sorted((r.admitted, r.done) for r in res)
+    for (a0, d0), (a1, d1) in zip(spans, spans[1:]):
+        assert a1 >= d0 - 1e-3   # one request at a time fits the budget
+    assert all(r.error is None for r in res)
+
+
+def test_served_request_matches_oracle():
+    from paper_2008_02205_amd.serving import Server
+    spec = _specs(3)[2]
+    print(f"[case] served vs oracle side={spec.side} M={spec.n_ord}", flush=True)
+    res = Server(slots=2).run([spec], _build, realtime=False)[0]
+    assert res.error is None
+    x, R, dx = W.request_problem(spec)
+    g = oracle.geometry(x, R, (0, 0), (1, 1))
+    it = oracle.integrate(g, 1)
+    om, w = oracle.angular_quadrature(2, spec.n_ord)
+    tr = oracle.Transport(it, om, w, spec.sigma_t, spec.sigma_s, 0.0, dx)
+    psi, phi, _ = tr.step(None, np.ones((g.n, spec.n_ord)))
+    assert rel_l2(res.phi, phi) <= MIXED_TOL
+    assert rel_l2(res.point, tr.point_values(phi)) <= MIXED_TOL

@@ -261,3 +261,46 @@ def inflow_values(w: Workload, y: np.ndarray, omega: np.ndarray) -> np.ndarray:
         win = (np.abs(ang) <= math.radians(10.0) + 1e-12) & (omega[:, 0] > 0)
         return (on[:, None] & win[None, :]).astype(np.float64)
     raise ValueError(w.inflow)
+
+
+# ---------------------------------------------------------------------------
+# Request stream (many independent steady problems arriving over time)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class RequestSpec:
+    rid: int
+    arrival: float           # seconds after the start of the stream
+    side: int                # lattice points per axis (N = side^2)
+    n_ord: int
+    sigma_t: float
+    sigma_s: float
+    seed: int
+
+
+def request_stream(count: int, seed: int = SEED_BASE + 5, rate: float = 50.0, n_min: int = 1024,
+                   n_max: int = 65536, ordinates=(16, 32, 64, 128), sigma_range=(0.1, 100.0),
+                   c_max: float = 0.95) -> list:
+    """Independent 2D steady problems with Poisson arrivals: point count
+    log-uniform in [n_min, n_max] (rounded to a square lattice), ordinate count
+    uniform over ``ordinates``, sigma_t log-uniform, scattering ratio uniform in
+    [0, c_max].  One seed for the whole stream."""
+    g = rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += g.exponential(1.0 / rate)
+        n = math.exp(g.uniform(math.log(n_min), math.log(n_max)))
+        side = max(2, int(round(math.sqrt(n))))
+        m = int(ordinates[int(g.integers(len(ordinates)))])
+        st = math.exp(g.uniform(math.log(sigma_range[0]), math.log(sigma_range[1])))
+        c = g.uniform(0.0, c_max)
+        out.append(RequestSpec(k, t, side, m, st, c * st, int(seed * 1000 + k)))
+    return out
+
+
+def request_problem(r: RequestSpec):
+    """Points, radii (R = 2 dx) and the uniform per-steradian source of one request."""
+    x, dx = jittered_lattice((r.side, r.side), (0.0, 0.0), (1.0, 1.0), 0.2, r.seed)
+    R = np.full(x.shape[0], 2.0 * dx)
+    return x, R, dx
