@@ -51,6 +51,13 @@ def parse():
                     help="instead of the benchmark: serve this many requests of the seeded request stream "
                          "(Poisson arrivals at 50/s, mixed precision) and print latency and throughput")
     ap.add_argument("--slots", type=int, default=4, help="concurrent problems in the serving mode")
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4],
+                    help="2: the benchmark above; 1, 3, 4: time that workload's whole path instead (phase times, "
+                         "p50/p99 over --steps repetitions) and print its own record")
+    ap.add_argument("--be-steps", type=int, default=None, help="backward-Euler steps per repetition (workloads 3/4)")
+    ap.add_argument("--max-outer", type=int, default=None,
+                    help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
+    ap.add_argument("--max-inner", type=int, default=None, help="inner-iteration cap per solve (--workload mode)")
     ap.add_argument("--probe", action="store_true",
                     help="hardware-counter probe: setup, one short solve of the workload and a 256 MiB "
                          "device copy (the reference for counter scaling); prints nothing")
@@ -71,6 +78,9 @@ def main():
     mlpg.lib()
     if args.serving:
         serve(args)
+        return
+    if args.workload != 2:
+        other_workload(args)
         return
     w = W.config(2, args.scale)
     x, dx = W.points_for(w)
@@ -189,6 +199,98 @@ def main():
             "roofline": roofline(prof2, counters=False)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
+    print(json.dumps(rec), flush=True)
+
+
+def other_workload(args):
+    """One workload's whole path (geometry, integration, assembly, every solve of a repetition) timed
+    phase by phase, with p50/p99 over repetitions; FP64 and mixed where the workload asks for both."""
+    import torch
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    w = W.config(args.workload, args.scale)
+    x, dx = W.points_for(w)
+    R = W.radii_for(w, x, dx)
+    n = x.shape[0]
+    kind = mlpg.MLPG_QUAD_BEAM_DENSE if w.ord_kind == "beam-dense" else mlpg.MLPG_QUAD_PRODUCT
+    om, wq = mlpg.mlpg_angular_quadrature(w.dim, w.n_ord, kind)
+    M = om.shape[0]
+    steps = w.steps if w.steps > 0 else 1
+    if args.be_steps:
+        steps = min(steps, args.be_steps)
+    qs = [torch.from_numpy(np.ascontiguousarray(W.source_values(w, x, om, (s + 1) * w.dt))).cuda()
+          for s in range(steps)]
+    psi0 = torch.from_numpy(np.ascontiguousarray(W.initial_psi(w, x, om))).cuda()
+    tau = torch.full((n,), dx, dtype=torch.float64, device="cuda")
+    precs = {1: ("fp64",), 3: ("mixed",), 4: ("mixed", "fp64")}[args.workload]
+    if args.precision != "both":
+        precs = (args.precision,)
+
+    def sync_time():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    def rep(prec):
+        t = {}
+        t0 = sync_time()
+        P = GpuProblem(x, R, w.lo, w.hi, w.regions)
+        t1 = sync_time()
+        info = P.integrate(w.rk_order)
+        t2 = sync_time()
+        P.assemble(om, wq, list(w.sigma_t), list(w.sigma_s), w.inv_c_dt, tau,
+                   precision=mlpg.MLPG_FP64 if prec == "fp64" else mlpg.MLPG_MIXED)
+        P.set_state(psi0)
+        pb = None
+        if w.inflow != "vacuum":
+            y, _ = P.boundary_points()
+            pb = torch.from_numpy(np.ascontiguousarray(W.inflow_values(w, y.cpu().numpy(), om))).cuda()
+        t3 = sync_time()
+        print(f"[{w.name} {prec}] setup: geometry {t1 - t0:.2f} s, integrate {t2 - t1:.2f} s, "
+              f"assemble {t3 - t2:.2f} s", file=sys.stderr, flush=True)
+        its = solves = outer = 0
+        conv = True
+        opts = mlpg.mlpg_default_opts()
+        if args.max_outer:
+            opts.max_outer = args.max_outer
+        if args.max_inner:
+            opts.max_inner = args.max_inner
+        for s in range(steps):
+            _, _, _, inf = mlpg.mlpg_solve(P.h, qs[s], pb, opts, want_psi=False, raise_on_error=False)
+            conv = conv and inf["converged"] == 1
+            its += inf["inner_iters"]
+            solves += inf["inner_solves"]
+            outer += inf["outer_iters"]
+            print(f"[{w.name} {prec}] step {s + 1}/{steps}: outer {inf['outer_iters']}, inner solves "
+                  f"{inf['inner_solves']}, Krylov steps {inf['inner_iters']}, {time.perf_counter() - t3:.1f} s",
+                  file=sys.stderr, flush=True)
+        t4 = sync_time()
+        P.close()
+        return {"geometry_s": t1 - t0, "integrate_s": t2 - t1, "assemble_s": t3 - t2, "solve_s": t4 - t3,
+                "total_s": t4 - t0, "iters": its, "solves": solves, "outer": outer,
+                "fallback_qps": info["fallback_qps"], "converged": conv}
+
+    out = {}
+    for prec in precs:
+        for _ in range(args.warmup):
+            rep(prec)
+        rs = [rep(prec) for _ in range(max(args.steps, 1))]
+        tot = np.array([r["total_s"] for r in rs])
+        out[prec] = {"value": float(np.mean([n * r["iters"] / r["total_s"] for r in rs])),
+                     "direction_solves_per_s": float(np.mean([r["solves"] * M / r["total_s"] for r in rs])),
+                     "p50_total_s": float(np.percentile(tot, 50)), "p99_total_s": float(np.percentile(tot, 99)),
+                     "phases_s": {k: float(np.mean([r[k] for r in rs]))
+                                  for k in ("geometry_s", "integrate_s", "assemble_s", "solve_s")},
+                     "iters_per_rep": rs[0]["iters"], "outer_per_rep": rs[0]["outer"],
+                     "fallback_qps": rs[0]["fallback_qps"], "converged": all(r["converged"] for r in rs),
+                     "max_outer": args.max_outer, "max_inner": args.max_inner}
+    main_p = precs[0]
+    rec = {"metric": "DOF*ordinate*Krylov-iter/s", "value": out[main_p]["value"], "unit": "DOF*ord*iter/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "dtype": "f64" if main_p == "fp64" else "f32+f64", "data": "synthetic",
+           "config": {"workload": f"{w.name}: {n} points, {M} ordinates, rk order {w.rk_order}, "
+                                  f"{'steady' if w.steps == 0 else f'{steps} BE steps'}", "points": n,
+                      "ordinates": M, "dim": w.dim},
+           "detail": out}
     print(json.dumps(rec), flush=True)
 
 

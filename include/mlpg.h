@@ -240,6 +240,8 @@ typedef struct {
     double inner_res_max;        /* largest final inner relative residual */
     int converged;               /* 1 if every solve met its tolerance */
     int refinements;             /* MLPG_MIXED: FP64 refinement steps summed over inner solves */
+    int fp64_completions;        /* MLPG_MIXED: inner solves finished in FP64 after the FP32
+                                    corrections stagnated or the refinement budget was spent */
 } mlpg_solve_info;
 
 void mlpg_default_opts(mlpg_solve_opts *o);

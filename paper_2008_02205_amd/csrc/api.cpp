@@ -77,7 +77,7 @@ int op_L32(Problem &P, const OpCallT<float> &c, hipStream_t s, void *)
 
 struct SolveCounters {
     const mlpg_solve_opts *o;
-    int64_t its = 0, sweeps = 0, refinements = 0;
+    int64_t its = 0, sweeps = 0, refinements = 0, fp64_completions = 0;
     double res_max = 0.0;
     bool conv = true;
     int solves = 0;
@@ -94,7 +94,11 @@ int inner_solve_fp64(Problem &P, SolveCounters &c, const double *f, double *x, h
 //   r = f - L x (FP64 values, FP64 accumulation); per ordinate, the
 //   correction solves L d = r / ||r|| with FP32 GMRES to tol_inner_lo
 //   (FP32 SpMV, FP32 basis, FP64 dot products and Hessenberg); x += ||r|| d.
-// Stops when every ordinate has ||f - L x|| <= tol_inner ||f||.
+// Stops when every ordinate has ||f - L x|| <= tol_inner ||f||.  Each
+// correction gets at most ten restart cycles.  When a refinement fails to
+// halve the residual of some unconverged ordinate (FP32 stagnating on an
+// ill-conditioned operator) or the refinement budget is spent, the solve is
+// finished by FP64 GMRES from the current iterate.
 int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
 {
     const int64_t n = P.n;
@@ -108,8 +112,9 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
     std::vector<double> fn2(M), rn2(M), tolm(M);
     MLPG_HIP(P.tolv.alloc(M));
     MLPG_HIP(hipMemcpyAsync(fn2.data(), P.fn2.p, sizeof(double) * M, hipMemcpyDeviceToHost, s));
-    bool conv = false;
+    bool conv = false, stalled = false;
     double worst = 0.0;
+    std::vector<double> prev(M, -1.0);
     for (int it = 0;; ++it) {
         MLPG_HIP(batched_norm2(P.inner, P.mr.p, P.rn2.p, s));
         MLPG_HIP(hipMemcpyAsync(rn2.data(), P.rn2.p, sizeof(double) * M, hipMemcpyDeviceToHost, s));
@@ -119,9 +124,13 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         for (int m = 0; m < M; ++m) {
             double rel = fn2[m] > 0.0 ? std::sqrt(rn2[m] / fn2[m]) : 0.0;
             worst = std::max(worst, rel);
-            if (fn2[m] > 0.0 && rel > o.tol_inner) conv = false;
+            if (fn2[m] > 0.0 && rel > o.tol_inner) {
+                conv = false;
+                if (prev[m] > 0.0 && rn2[m] > 0.25 * prev[m]) stalled = true;   // less than halved
+            }
+            prev[m] = rn2[m];
         }
-        if (conv || it >= o.max_refine) break;
+        if (conv || stalled || it >= o.max_refine) break;
         // Per ordinate, the correction only has to close the remaining gap
         // (with a factor 2 to spare), never looser than 1/2 and never
         // tighter than tol_inner_lo.
@@ -133,8 +142,9 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         MLPG_HIP(launch_to_float_scaled(n, M, P.mr.p, P.rn2.p, P.fn2.p, o.tol_inner, P.r32.p, s));
         bool c32 = true;
         double rm32 = 0.0;
+        const int cap = std::min(o.max_inner, 10 * o.restart_inner);
         int rc = gmres_batched<float>(P, P.inner32, op_L32, true, nullptr, P.dinv32.p, P.r32.p, P.d32.p, n, M,
-                                      o.tol_inner_lo, o.restart_inner, o.max_inner, o.check_every, true, s, &c.its,
+                                      o.tol_inner_lo, o.restart_inner, cap, o.check_every, true, s, &c.its,
                                       &c.sweeps, &rm32, &c32, P.tolv.p);
         MLPG_HIP(hipStreamSynchronize(s));   // tolm is read by the copy above
         if (rc) return rc;
@@ -144,6 +154,18 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         a.coefF = P.coefF.p; a.y = P.mr.p; a.yadd = f; a.ysign = -1;
         MLPG_HIP(launch_spmv<double>(P, a, s));
         c.refinements++;
+    }
+    if (!conv) {
+        // FP64 completion from the current iterate
+        bool c64 = true;
+        double rm = 0.0;
+        int rc = gmres_batched<double>(P, P.inner, op_L, true, nullptr, P.dinv.p, f, x, n, M, o.tol_inner,
+                                       o.restart_inner, o.max_inner, o.check_every, false, s, &c.its, &c.sweeps,
+                                       &rm, &c64);
+        if (rc) return rc;
+        c.fp64_completions++;
+        conv = c64;
+        worst = rm;
     }
     c.res_max = std::max(c.res_max, worst);
     c.conv = c.conv && conv;
@@ -696,6 +718,7 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
         info->inner_res_max = c.res_max;
         info->converged = (c.conv && oconv) ? 1 : 0;
         info->refinements = (int)c.refinements;
+        info->fp64_completions = (int)c.fp64_completions;
     }
     if (!(c.conv && oconv)) {
         set_error("mlpg_solve: a Krylov solve reached its iteration limit");

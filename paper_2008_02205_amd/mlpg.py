@@ -50,7 +50,7 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_solves", C.c_int), ("inner_iters", C.c_int64),
                 ("inner_sweeps", C.c_int64), ("outer_res", C.c_double), ("inner_res_max", C.c_double),
-                ("converged", C.c_int), ("refinements", C.c_int)]
+                ("converged", C.c_int), ("refinements", C.c_int), ("fp64_completions", C.c_int)]
 
 
 _lib = None
