@@ -230,6 +230,14 @@ def other_workload(args):
         torch.cuda.synchronize()
         return time.perf_counter()
 
+    t_start = time.perf_counter()
+
+    def progress(level, iters, resid):
+        print(f"[{w.name}] {'outer' if level else 'inner'} solve done: {iters} Krylov steps, residual {resid:.1e}, "
+              f"{time.perf_counter() - t_start:.0f} s", file=sys.stderr, flush=True)
+
+    mlpg.mlpg_set_progress(progress)
+
     def rep(prec):
         t = {}
         t0 = sync_time()

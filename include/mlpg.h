@@ -273,6 +273,17 @@ int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stre
 int mlpg_profile_begin(void);
 int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
 
+/* ------------------------------------------------------------------------
+ * Progress reports for long solves.  When set, the library calls
+ * fn(user, level, iters, resid) on the calling host thread after every
+ * batched Krylov solve: level 0 = an inner solve over all ordinates, 1 = the
+ * outer solve; iters = Arnoldi steps of that solve summed over its systems;
+ * resid = its largest final relative residual.  Process-wide; NULL turns it
+ * off.  The callback must not call back into the library.
+ * ---------------------------------------------------------------------- */
+typedef void (*mlpg_progress_fn)(void *user, int level, int64_t iters, double resid);
+int mlpg_set_progress(mlpg_progress_fn fn, void *user);
+
 /* Releases the handle and all its device memory (NULL is ignored). */
 void mlpg_destroy(mlpg_handle h);
 

@@ -202,6 +202,9 @@ struct Problem {
     void release();
 };
 
+// Progress callback (mlpg_set_progress); no-op when unset.
+void report_progress(int level, int64_t iters, double resid);
+
 // Kernel-class timing (mlpg_profile_*): prof_start returns -1 when off.
 bool prof_on();
 int prof_start(int cls, double bytes, hipStream_t s);

@@ -828,6 +828,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     *sweeps += sw;
     if (rm > *res_max) *res_max = rm;
     *converged = *converged && ok;
+    report_progress(nb == 1 ? 1 : 0, tot, rm);
     return MLPG_OK;
 }
 

@@ -1,6 +1,8 @@
 // Event timing of kernel classes for roofline reports (mlpg_profile_*).
 #include <vector>
 
+#include <atomic>
+
 #include "internal.hpp"
 
 namespace mlpg {
@@ -83,5 +85,25 @@ extern "C" int mlpg_profile_end(double *ms, int64_t *launches, double *bytes)
     }
     g_prof.recs.clear();
     g_prof.used = 0;
+    return MLPG_OK;
+}
+
+namespace mlpg {
+namespace {
+std::atomic<mlpg_progress_fn> g_progress{nullptr};
+std::atomic<void *> g_progress_user{nullptr};
+}  // namespace
+
+void report_progress(int level, int64_t iters, double resid)
+{
+    mlpg_progress_fn fn = g_progress.load();
+    if (fn) fn(g_progress_user.load(), level, iters, resid);
+}
+}  // namespace mlpg
+
+extern "C" int mlpg_set_progress(mlpg_progress_fn fn, void *user)
+{
+    mlpg::g_progress_user.store(user);
+    mlpg::g_progress.store(fn);
     return MLPG_OK;
 }

@@ -26,7 +26,7 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_geometry", "mlpg_get_info", "mlpg_get_volumes", "mlpg_cell_capacity", "mlpg_get_cells",
            "mlpg_boundary_points", "mlpg_integrate", "mlpg_get_pattern", "mlpg_get_blocks", "mlpg_assemble",
            "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
-           "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end"]
+           "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress"]
 
 
 class MlpgError(RuntimeError):
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         L.mlpg_destroy.argtypes = [vp]
         L.mlpg_profile_begin.argtypes = []
         L.mlpg_profile_end.argtypes = [vp, vp, vp]
+        L.mlpg_set_progress.argtypes = [PROGRESS_FN, vp]
         for name in EXPORTS:
             if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy"):
                 getattr(L, name).restype = C.c_int
@@ -287,6 +288,18 @@ def mlpg_destroy(h):
 
 
 PROF_CLASSES = ("spmv_L", "gs_pass_a", "gs_pass_b", "gs_cycle_end")
+
+
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int, C.c_int64, C.c_double)
+_progress_keep = None
+
+
+def mlpg_set_progress(fn=None):
+    """fn(level, iters, resid) after every batched Krylov solve (None: off)."""
+    global _progress_keep
+    cb = PROGRESS_FN(lambda _u, level, iters, resid: fn(level, iters, resid)) if fn else PROGRESS_FN()
+    _progress_keep = cb
+    _check(lib().mlpg_set_progress(cb, None))
 
 
 def mlpg_profile_begin():
