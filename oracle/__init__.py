@@ -58,7 +58,8 @@ class IntegCtx(C.Structure):
                 ("x", _dp), ("R", _dp), ("V", _dp), ("nb_off", _i64p), ("nb_idx", _i32p),
                 ("row_off", _i64p), ("col", _i32p), ("nnz", C.c_int64), ("n_regions", C.c_int),
                 ("reg_lo", _dp), ("reg_hi", _dp), ("reg_mat", _i32p), ("blocks", _dp),
-                ("fallbacks", C.c_int64), ("missing", C.c_int64)]
+                ("fallbacks", C.c_int64), ("missing", C.c_int64), ("n_fields", C.c_int),
+                ("field_par", _dp), ("field_mat", _i32p)]
 
 
 class OpCtx(C.Structure):
@@ -400,12 +401,18 @@ class Integrated:
 
 
 def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int = None, seg_n: int = 5,
-              kmax: int = None, tet_n: int = 2) -> Integrated:
+              kmax: int = None, tet_n: int = 2, fields=()) -> Integrated:
     """Blocks of Alg. 1 over all cells; boundary quadrature points; point-value matrix E.
 
     Rules: 2D, triangle rule n = 5 (25 points) in the cells and line rule
     seg_n on domain edges; 3D, tetrahedron rule n = 2 (8 points) in the
-    cells and triangle rule n = 2 (4 points) on domain faces."""
+    cells and triangle rule n = 2 (4 points) on domain faces.
+
+    ``regions``: boxes ``(lo, hi, material)`` (last match wins, material 0
+    elsewhere).  ``fields``: smooth material fractions ``(a, b, k, phase,
+    material)``; each moves ``a + b prod_alpha cos(k y_alpha + phase)`` of the
+    quadrature point's weight from material 0 to ``material`` (the spatially
+    varying opacities of Sec. 5.1 are sums of such terms)."""
     d = g.dim
     if tri_n is None:
         tri_n = 5 if d == 2 else 2
@@ -419,9 +426,16 @@ def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int
     reg_hi = np.array([r[1] for r in regions], dtype=np.float64).reshape(-1, d) if regions else np.zeros((1, d))
     reg_mat = np.array([r[2] for r in regions], dtype=np.int32) if regions else np.zeros(1, dtype=np.int32)
     V = _f64(g.V)
+    fpar = np.array([f[:4] for f in fields], dtype=np.float64).reshape(-1, 4) if fields else np.zeros((1, 4))
+    fmat = np.array([f[4] for f in fields], dtype=np.int32) if fields else np.zeros(1, dtype=np.int32)
+    if fields and (fmat.min() < 1 or fmat.max() >= n_mat):
+        raise ValueError("a field moves weight to a material in [1, n_mat)")
+    if n_mat > 8:
+        raise ValueError("at most 8 materials")
     ic = IntegCtx(d, rk_order, n_mat, g.n, _p(g.x), _p(g.R), _p(V), _p(g.nb_off, _i64p),
                   _p(g.nb_idx, _i32p), _p(g.row_off, _i64p), _p(g.col, _i32p), nnz, len(regions),
-                  _p(reg_lo), _p(reg_hi), _p(reg_mat, _i32p), _p(blocks), 0, 0)
+                  _p(reg_lo), _p(reg_hi), _p(reg_mat, _i32p), _p(blocks), 0, 0, len(fields),
+                  _p(fpar), _p(fmat, _i32p))
     tp, tw = triangle_rule(tri_n)
     tp = _f64(tp); tw = _f64(tw)
     cl = g.cells

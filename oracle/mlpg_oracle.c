@@ -675,7 +675,31 @@ typedef struct {
     const int32_t *reg_mat;
     double *blocks;             /* [nblk][nnz] */
     int64_t fallbacks, missing;
+    int n_fields;               /* smooth material fields (may be 0) */
+    const double *field_par;    /* [n_fields][4]: a, b, k, phase */
+    const int32_t *field_mat;   /* [n_fields] material that receives the field */
 } integ_ctx;
+
+/* Material fractions f[0..n_mat) at y.  Box regions give an indicator (last
+ * match wins, material 0 elsewhere).  Each smooth field r then moves
+ *   v_r(y) = a + b prod_alpha cos(k y_alpha + phase)
+ * from material 0 to material field_mat[r], so the fractions still sum to
+ * one.  With one material per cross-section component this represents the
+ * spatially varying opacities of the manufactured problems (Sec. 5.1), whose
+ * products of sines and cosines are cosines with a phase. */
+static void material_fractions(const integ_ctx *ic, const double *y, double *f)
+{
+    for (int g = 0; g < ic->n_mat; ++g) f[g] = 0.0;
+    f[material_at(ic->dim, y, ic->n_regions, ic->reg_lo, ic->reg_hi, ic->reg_mat)] = 1.0;
+    for (int r = 0; r < ic->n_fields; ++r) {
+        const double *fp = ic->field_par + 4 * r;
+        double pr = 1.0;
+        for (int a = 0; a < ic->dim; ++a) pr *= cos(fp[2] * y[a] + fp[3]);
+        const double v = fp[0] + fp[1] * pr;
+        f[ic->field_mat[r]] += v;
+        f[0] -= v;
+    }
+}
 
 /* Candidate functions for a cell c: c itself and its overlap neighbours
  * (the doubled-radius argument of Sec. 3.4). */
@@ -696,7 +720,8 @@ static void add_volume_point(integ_ctx *ic, int64_t c, const double *y, double w
     int ord = rk_eval_act(dim, ic->rk_order, y, nc, cand, ic->x, ic->R, ic->V, 0.5 * ic->R[c], N, dN, act);
     if (ord < 0) return;
     if (ord < ic->rk_order) ic->fallbacks++;
-    int g = material_at(dim, y, ic->n_regions, ic->reg_lo, ic->reg_hi, ic->reg_mat);
+    double f[8];
+    material_fractions(ic, y, f);
     int64_t nnz = ic->nnz;
     for (int a = 0; a < nc; ++a) {
         if (!act[a]) continue;
@@ -704,9 +729,13 @@ static void add_volume_point(integ_ctx *ic, int64_t c, const double *y, double w
             if (!act[b]) continue;
             int64_t p = pos[a * nc + b];
             if (p < 0) { ic->missing++; continue; }
-            ic->blocks[(int64_t)(g * (1 + dim)) * nnz + p] += w * N[a] * N[b];
-            for (int al = 0; al < dim; ++al)
-                ic->blocks[(int64_t)(g * (1 + dim) + 1 + al) * nnz + p] += w * dN[a * dim + al] * N[b];
+            for (int g = 0; g < ic->n_mat; ++g) {
+                if (f[g] == 0.0) continue;
+                const double wg = w * f[g];
+                ic->blocks[(int64_t)(g * (1 + dim)) * nnz + p] += wg * N[a] * N[b];
+                for (int al = 0; al < dim; ++al)
+                    ic->blocks[(int64_t)(g * (1 + dim) + 1 + al) * nnz + p] += wg * dN[a * dim + al] * N[b];
+            }
             int kb = ic->n_mat * (1 + dim);
             for (int al = 0; al < dim; ++al)
                 for (int be = 0; be < dim; ++be)

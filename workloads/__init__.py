@@ -142,6 +142,71 @@ def mms_sin_phi(x: np.ndarray, t: float) -> np.ndarray:
     return 4.0 * np.pi * np.sin(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1]) * math.exp(-t)
 
 
+# The manufactured problems of the paper's results section (Sec. 5.1), on
+# [-1, 1]^d.  Both solutions are isotropic, so phi = 4 pi psi and the
+# scattering term cancels sigma_s psi:  q = (1/c) d_t psi + Omega.grad psi + sigma_a psi.
+
+def mms_cos_psi(x: np.ndarray, t: float) -> np.ndarray:
+    """psi = 1 + (1/(2 pi)) prod_alpha cos(pi (x_alpha + t)), per point ``[N]``."""
+    return 1.0 + np.prod(np.cos(np.pi * (x + t)), axis=1) / (2.0 * np.pi)
+
+
+def mms_cos_sigma_a(x: np.ndarray) -> np.ndarray:
+    """sigma_a = 1 + (2/3) prod_alpha cos(3 x_alpha)."""
+    return 1.0 + (2.0 / 3.0) * np.prod(np.cos(3.0 * x), axis=1)
+
+
+def mms_cos_sigma_s(x: np.ndarray) -> np.ndarray:
+    """sigma_s = 1 + (3/4) prod_alpha sin(2 x_alpha)."""
+    return 1.0 + 0.75 * np.prod(np.sin(2.0 * x), axis=1)
+
+
+# The opacities above as material fields (a, b, k, phase, material): material
+# 1 absorbs (sigma_t = 1), material 2 scatters (sigma_t = sigma_s = 1) and
+# material 0 is void; sin(2x) = cos(2x - pi/2).
+MMS_COS_FIELDS = ((1.0, 2.0 / 3.0, 3.0, 0.0, 1), (1.0, 0.75, 2.0, -0.5 * math.pi, 2))
+MMS_COS_SIGMA_T = (0.0, 1.0, 1.0)
+MMS_COS_SIGMA_S = (0.0, 0.0, 1.0)
+
+
+def mms_cos_source(x: np.ndarray, omega: np.ndarray, t: float, inv_c: float) -> np.ndarray:
+    """Source ``[N][M]`` of the sinusoidal manufactured problem at time t."""
+    d = x.shape[1]
+    c = np.cos(np.pi * (x + t))
+    s = np.sin(np.pi * (x + t))
+    grad = np.empty_like(x)
+    for b in range(d):
+        others = np.prod(np.delete(c, b, axis=1), axis=1) if d > 1 else 1.0
+        grad[:, b] = -0.5 * s[:, b] * others          # (1/(2 pi)) * (-pi sin) * prod of the others
+    dpsi_dt = grad.sum(axis=1)
+    psi = mms_cos_psi(x, t)
+    odg = grad @ omega[:, :d].T
+    return inv_c * dpsi_dt[:, None] + odg + (mms_cos_sigma_a(x) * psi)[:, None]
+
+
+def mms_wave_psi(x: np.ndarray, t: float) -> np.ndarray:
+    """psi = 1 + exp(-10 (|x| - t)^2) / (t^2 + 6), per point ``[N]``."""
+    r = np.sqrt(np.sum(x * x, axis=1))
+    return 1.0 + np.exp(-10.0 * (r - t) ** 2) / (t * t + 6.0)
+
+
+MMS_WAVE_SIGMA_A, MMS_WAVE_SIGMA_S = 0.5, 2.0
+
+
+def mms_wave_source(x: np.ndarray, omega: np.ndarray, t: float, inv_c: float) -> np.ndarray:
+    """Source ``[N][M]`` of the outgoing-wave manufactured problem (constant opacities)."""
+    d = x.shape[1]
+    r = np.sqrt(np.sum(x * x, axis=1))
+    e = np.exp(-10.0 * (r - t) ** 2)
+    den = t * t + 6.0
+    dr = -20.0 * (r - t) * e / den                   # d psi / d r
+    rs = np.where(r > 0.0, r, 1.0)
+    grad = np.where(r[:, None] > 0.0, dr[:, None] * x / rs[:, None], 0.0)
+    dpsi_dt = -2.0 * t * e / (den * den) + 20.0 * (r - t) * e / den
+    odg = grad @ omega[:, :d].T
+    return inv_c * dpsi_dt[:, None] + odg + (MMS_WAVE_SIGMA_A * mms_wave_psi(x, t))[:, None]
+
+
 def gaussian_source(x: np.ndarray, center: Sequence[float], s: float) -> np.ndarray:
     """Isotropic per-steradian source of unit total emission: a Gaussian of std ``s``."""
     d = x.shape[1]
