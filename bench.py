@@ -51,9 +51,11 @@ def parse():
                     help="instead of the benchmark: serve this many requests of the seeded request stream "
                          "(Poisson arrivals at 50/s, mixed precision) and print latency and throughput")
     ap.add_argument("--slots", type=int, default=4, help="concurrent problems in the serving mode")
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4],
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 6, 7],
                     help="2: the benchmark above; 1, 3, 4: time that workload's whole path instead (phase times, "
-                         "p50/p99 over --steps repetitions) and print its own record")
+                         "p50/p99 over --steps repetitions) and print its own record; 6, 7: the paper's sinusoidal "
+                         "and outgoing-wave manufactured problems (steady, [-1,1]^2, --scale points per axis), "
+                         "with the relative error against the exact scalar flux")
     ap.add_argument("--be-steps", type=int, default=None, help="backward-Euler steps per repetition (workloads 3/4)")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
@@ -218,11 +220,15 @@ def other_workload(args):
     steps = w.steps if w.steps > 0 else 1
     if args.be_steps:
         steps = min(steps, args.be_steps)
-    qs = [torch.from_numpy(np.ascontiguousarray(W.source_values(w, x, om, (s + 1) * w.dt))).cuda()
+    qs = [torch.from_numpy(np.ascontiguousarray(W.source_values(w, x, om, w.t0 + (s + 1) * w.dt))).cuda()
           for s in range(steps)]
     psi0 = torch.from_numpy(np.ascontiguousarray(W.initial_psi(w, x, om))).cuda()
     tau = torch.full((n,), dx, dtype=torch.float64, device="cuda")
-    precs = {1: ("fp64",), 3: ("mixed",), 4: ("mixed", "fp64")}[args.workload]
+    precs = {1: ("fp64",), 3: ("mixed",), 4: ("mixed", "fp64"), 6: ("fp64", "mixed"),
+             7: ("fp64", "mixed")}[args.workload]
+    exact = None
+    if w.source in ("paper-cos", "paper-wave"):
+        exact = 4.0 * np.pi * W.paper_mms_psi(w, x, w.t0 + steps * w.dt)
     if args.precision != "both":
         precs = (args.precision,)
 
@@ -241,7 +247,7 @@ def other_workload(args):
     def rep(prec):
         t = {}
         t0 = sync_time()
-        P = GpuProblem(x, R, w.lo, w.hi, w.regions)
+        P = GpuProblem(x, R, w.lo, w.hi, w.regions, w.fields)
         t1 = sync_time()
         info = P.integrate(w.rk_order)
         t2 = sync_time()
@@ -262,8 +268,9 @@ def other_workload(args):
             opts.max_outer = args.max_outer
         if args.max_inner:
             opts.max_inner = args.max_inner
+        err = None
         for s in range(steps):
-            _, _, _, inf = mlpg.mlpg_solve(P.h, qs[s], pb, opts, want_psi=False, raise_on_error=False)
+            _, pv, _, inf = mlpg.mlpg_solve(P.h, qs[s], pb, opts, want_psi=False, raise_on_error=False)
             conv = conv and inf["converged"] == 1
             its += inf["inner_iters"]
             solves += inf["inner_solves"]
@@ -272,10 +279,13 @@ def other_workload(args):
                   f"{inf['inner_solves']}, Krylov steps {inf['inner_iters']}, {time.perf_counter() - t3:.1f} s",
                   file=sys.stderr, flush=True)
         t4 = sync_time()
+        if exact is not None:
+            # relative error of the scalar flux at the centres (Sec. 5): sum |phi - phi_exact| / sum phi_exact
+            err = float(np.abs(pv.cpu().numpy() - exact).sum() / exact.sum())
         P.close()
         return {"geometry_s": t1 - t0, "integrate_s": t2 - t1, "assemble_s": t3 - t2, "solve_s": t4 - t3,
                 "total_s": t4 - t0, "iters": its, "solves": solves, "outer": outer,
-                "fallback_qps": info["fallback_qps"], "converged": conv}
+                "fallback_qps": info["fallback_qps"], "converged": conv, "rel_error": err}
 
     out = {}
     for prec in precs:
@@ -290,6 +300,7 @@ def other_workload(args):
                                   for k in ("geometry_s", "integrate_s", "assemble_s", "solve_s")},
                      "iters_per_rep": rs[0]["iters"], "outer_per_rep": rs[0]["outer"],
                      "fallback_qps": rs[0]["fallback_qps"], "converged": all(r["converged"] for r in rs),
+                     "rel_error_vs_exact": rs[0]["rel_error"],
                      "max_outer": args.max_outer, "max_inner": args.max_inner}
     main_p = precs[0]
     rec = {"metric": "DOF*ordinate*Krylov-iter/s", "value": out[main_p]["value"], "unit": "DOF*ord*iter/s",

@@ -144,6 +144,27 @@ int mlpg_get_cells(mlpg_handle h, int32_t *nv, double *verts, int32_t *tags, voi
 int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Spatially varying materials (Sec. 5.1: opacities that vary smoothly in
+ * space, evaluated at the integration points).  Optional, between
+ * mlpg_geometry and mlpg_integrate.  Field r moves the fraction
+ *   v_r(y) = a + b prod_alpha cos(k y_alpha + phase)
+ * of every volume quadrature point y from material 0 to material mat[r],
+ * after the region boxes have set the point's material; so the fractions
+ * still sum to one and the integrated blocks become
+ *   Mass_g[i,j] = <f_g N_i, N_j>,  D^a_g[i,j] = <f_g d^a N_i, N_j>.
+ * With sigma_t, sigma_s given per material at assembly, the cross sections
+ * at a point are sum_g f_g sigma_g (a product of sines is a product of
+ * cosines with phase -pi/2).
+ *   n_fields: 0..8 (0 removes the fields); param: host [n_fields][4]
+ *   (a, b, k, phase); mat: host [n_fields], each in [1, 8).  Raises the
+ *   handle's material count to cover every mat[r].  Resets the handle to the
+ *   state after mlpg_geometry (integrate again before assembling).
+ * Errors: MLPG_ERR_ARG for a count or material out of range or a NULL array
+ * with n_fields > 0; MLPG_ERR_STATE before mlpg_geometry.
+ * ---------------------------------------------------------------------- */
+int mlpg_material_fields(mlpg_handle h, int n_fields, const double *param, const int32_t *mat);
+
+/* ------------------------------------------------------------------------
  * Stage 2, integration (Sec. 2.2; Sec. 3.2 and Alg. 1; App. A).  At every
  * quadrature point of every cell (2D: fan triangles from the generator with
  * the 25-point conical-product rule, 5-point Gauss-Legendre on boundary

@@ -421,6 +421,25 @@ int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream)
     return MLPG_OK;
 }
 
+int mlpg_material_fields(mlpg_handle h, int n_fields, const double *param, const int32_t *mat)
+{
+    int rc = check_stage(h, 1, "mlpg_material_fields");
+    if (rc) return rc;
+    MLPG_CHECK(n_fields >= 0 && n_fields <= kMaxFields, MLPG_ERR_ARG, "mlpg_material_fields: n_fields in [0, 8]");
+    MLPG_CHECK(n_fields == 0 || (param && mat), MLPG_ERR_ARG, "mlpg_material_fields: NULL param or mat");
+    for (int r = 0; r < n_fields; ++r)
+        MLPG_CHECK(mat[r] >= 1 && mat[r] < kMaxMat, MLPG_ERR_ARG, "mlpg_material_fields: material in [1, 8)");
+    Problem *P = h;
+    P->n_fields = n_fields;
+    for (int r = 0; r < kMaxFields; ++r) {
+        for (int q = 0; q < 4; ++q) P->field_par[r][q] = r < n_fields ? param[4 * r + q] : 0.0;
+        P->field_mat[r] = r < n_fields ? mat[r] : 0;
+        if (r < n_fields) P->n_mat = std::max(P->n_mat, mat[r] + 1);
+    }
+    P->stage = 1;
+    return MLPG_OK;
+}
+
 int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
 {
     int rc = check_stage(h, 1, "mlpg_integrate");

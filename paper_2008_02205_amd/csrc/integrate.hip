@@ -244,6 +244,40 @@ __device__ __forceinline__ void rk_value(double y0, double y1, int a, const doub
     *dN1 = v * (t1 * W + pc * dW1);
 }
 
+// Smooth material fields: each moves a + b prod_a cos(k y_a + phase) of a
+// quadrature point's weight from material 0 to its material (the spatially
+// varying opacities of the manufactured problems, Sec. 5.1).
+struct FieldSet {
+    int n;
+    double par[kMaxFields][4];   // a, b, k, phase
+    int mat[kMaxFields];
+};
+
+// w times the fraction of every material at y: the box indicator (material
+// `mat`), then the fields in order.  Unrolled over kMaxMat so that the
+// fractions stay in registers.
+template <int D>
+__device__ __forceinline__ void material_weights(const double *y, int mat, double w, const FieldSet &F,
+                                                 double (&wf)[kMaxMat])
+{
+    double f[kMaxMat];
+#pragma unroll
+    for (int m = 0; m < kMaxMat; ++m) f[m] = m == mat ? 1.0 : 0.0;
+    for (int r = 0; r < F.n; ++r) {
+        double pr = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) pr *= cos(F.par[r][2] * y[a] + F.par[r][3]);
+        const double v = F.par[r][0] + F.par[r][1] * pr;
+        const int t = F.mat[r];
+#pragma unroll
+        for (int m = 1; m < kMaxMat; ++m)
+            if (m == t) f[m] += v;
+        f[0] -= v;
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxMat; ++m) wf[m] = w * f[m];
+}
+
 __device__ __forceinline__ int material_at(double y0, double y1, int nreg, const double *lo, const double *hi,
                                            const int32_t *mat)
 {
@@ -289,6 +323,7 @@ struct IntegArgs {
     unsigned long long *counters;
     int amax;       // candidate capacity staged in LDS
     int tile_rows;  // pair rows per Gram tile
+    FieldSet fields;
 };
 
 // Candidate count per cell (to size LDS).
@@ -309,7 +344,7 @@ __global__ void cand_count_kernel(int64_t n, const double *__restrict__ x, const
     cnt[c] = k;
 }
 
-template <int ORD>
+template <int ORD, bool FIELDS>
 __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
 {
     extern __shared__ double lds[];
@@ -376,6 +411,11 @@ __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
             if (o < 0) continue;
             if (a0 == 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
             int mat = material_at(y0, y1, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
+            double wf[kMaxMat];
+            if (FIELDS) {
+                const double yy[2] = {y0, y1};
+                material_weights<2>(yy, mat, w, g.fields, wf);
+            }
             uint64_t ma = mask & ((a1 >= 64 ? ~0ull : ((1ull << a1) - 1)) & ~((1ull << a0) - 1));
             while (ma) {
                 int a = __builtin_ctzll(ma);
@@ -390,9 +430,19 @@ __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
                     mb &= mb - 1;
                     double Nb, dNb0, dNb1;
                     rk_value<ORD>(y0, y1, b, sx, sR, sV, hs, C, dC0, dC1, &Nb, &dNb0, &dNb1);
-                    atomicAdd(&gr[(3 * mat + 0) * TT + b], wa * Nb);
-                    atomicAdd(&gr[(3 * mat + 1) * TT + b], wa0 * Nb);
-                    atomicAdd(&gr[(3 * mat + 2) * TT + b], wa1 * Nb);
+                    if (!FIELDS) {
+                        atomicAdd(&gr[(3 * mat + 0) * TT + b], wa * Nb);
+                        atomicAdd(&gr[(3 * mat + 1) * TT + b], wa0 * Nb);
+                        atomicAdd(&gr[(3 * mat + 2) * TT + b], wa1 * Nb);
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < kMaxMat; ++m) {
+                            if (m >= G || wf[m] == 0.0) continue;
+                            atomicAdd(&gr[(3 * m + 0) * TT + b], wf[m] * Na * Nb);
+                            atomicAdd(&gr[(3 * m + 1) * TT + b], wf[m] * dNa0 * Nb);
+                            atomicAdd(&gr[(3 * m + 2) * TT + b], wf[m] * dNa1 * Nb);
+                        }
+                    }
                     atomicAdd(&gr[(3 * G + 0) * TT + b], wa0 * dNb0);
                     atomicAdd(&gr[(3 * G + 1) * TT + b], wa0 * dNb1);
                     atomicAdd(&gr[(3 * G + 2) * TT + b], wa1 * dNb1);
@@ -792,6 +842,7 @@ struct Integ3Args {
     unsigned long long *counters;
     int amax;
     int tile_rows;
+    FieldSet fields;
 };
 
 __global__ void cand_count3_kernel(int64_t n, const double *__restrict__ x, const double *__restrict__ R,
@@ -811,7 +862,7 @@ __global__ void cand_count3_kernel(int64_t n, const double *__restrict__ x, cons
     cnt[c] = k;
 }
 
-template <int ORD>
+template <int ORD, bool FIELDS>
 __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
 {
     extern __shared__ double lds[];
@@ -901,6 +952,8 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
             if (o < 0) continue;
             if (a0 == 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
             const int mat = material_at3(y, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
+            double wf[kMaxMat];
+            if (FIELDS) material_weights<3>(y, mat, w, g.fields, wf);
             for (int a = a0; a < a1; ++a) {
                 double Na, dNa[3];
                 if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
@@ -909,10 +962,21 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
                 for (int b = 0; b < A; ++b) {
                     double Nb, dNb[3];
                     if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
-                    atomicAdd(&gr[(4 * mat + 0) * TT + b], wa * Nb);
-                    atomicAdd(&gr[(4 * mat + 1) * TT + b], wa0 * Nb);
-                    atomicAdd(&gr[(4 * mat + 2) * TT + b], wa1 * Nb);
-                    atomicAdd(&gr[(4 * mat + 3) * TT + b], wa2 * Nb);
+                    if (!FIELDS) {
+                        atomicAdd(&gr[(4 * mat + 0) * TT + b], wa * Nb);
+                        atomicAdd(&gr[(4 * mat + 1) * TT + b], wa0 * Nb);
+                        atomicAdd(&gr[(4 * mat + 2) * TT + b], wa1 * Nb);
+                        atomicAdd(&gr[(4 * mat + 3) * TT + b], wa2 * Nb);
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < kMaxMat; ++m) {
+                            if (m >= G || wf[m] == 0.0) continue;
+                            atomicAdd(&gr[(4 * m + 0) * TT + b], wf[m] * Na * Nb);
+                            atomicAdd(&gr[(4 * m + 1) * TT + b], wf[m] * dNa[0] * Nb);
+                            atomicAdd(&gr[(4 * m + 2) * TT + b], wf[m] * dNa[1] * Nb);
+                            atomicAdd(&gr[(4 * m + 3) * TT + b], wf[m] * dNa[2] * Nb);
+                        }
+                    }
                     atomicAdd(&gr[(4 * G + 0) * TT + b], wa0 * dNb[0]);
                     atomicAdd(&gr[(4 * G + 1) * TT + b], wa0 * dNb[1]);
                     atomicAdd(&gr[(4 * G + 2) * TT + b], wa0 * dNb[2]);
@@ -1039,6 +1103,28 @@ hipError_t upload_rules3(hipStream_t s)
 
 }  // namespace
 
+template <int ORD, class Args>
+hipError_t launch_integ(void (*plain)(Args), void (*fields)(Args), bool use_fields, dim3 grid, size_t shmem,
+                        const Args &g, hipStream_t s)
+{
+    void (*k)(Args) = use_fields ? fields : plain;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    k<<<grid, kThreads, shmem, s>>>(g);
+    return hipGetLastError();
+}
+
+static FieldSet field_set(const Problem &P)
+{
+    FieldSet F;
+    F.n = P.n_fields;
+    for (int r = 0; r < kMaxFields; ++r) {
+        for (int q = 0; q < 4; ++q) F.par[r][q] = P.field_par[r][q];
+        F.mat[r] = P.field_mat[r];
+    }
+    return F;
+}
+
 hipError_t launch_integrate2d(Problem &P, hipStream_t s)
 {
     // Candidate capacity from the largest candidate set.
@@ -1077,20 +1163,21 @@ hipError_t launch_integrate2d(Problem &P, hipStream_t s)
     g.bq_off = P.bq_off.p; g.bq_y = P.bq_y.p; g.bq_w = P.bq_w.p; g.bq_N = P.bq_N.p; g.bq_face = P.bq_face.p;
     g.bq_nact = P.bq_nact.p; g.bq_act = P.bq_act.p; g.counters = P.counters.p; g.amax = amax;
     g.tile_rows = tile_rows;
+    g.fields = field_set(P);
     if ((e = upload_rules(s)) != hipSuccess) return e;
     dim3 grid((unsigned)P.n);
     switch (P.rk_order) {
     case 0:
-        if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
-        integrate2d_kernel<0><<<grid, kThreads, shmem, s>>>(g);
+        e = launch_integ<0>(integrate2d_kernel<0, false>, integrate2d_kernel<0, true>, P.n_fields > 0, grid, shmem, g, s);
+        if (e != hipSuccess) return e;
         break;
     case 1:
-        if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
-        integrate2d_kernel<1><<<grid, kThreads, shmem, s>>>(g);
+        e = launch_integ<1>(integrate2d_kernel<1, false>, integrate2d_kernel<1, true>, P.n_fields > 0, grid, shmem, g, s);
+        if (e != hipSuccess) return e;
         break;
     default:
-        if ((e = hipFuncSetAttribute((const void *)integrate2d_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
-        integrate2d_kernel<2><<<grid, kThreads, shmem, s>>>(g);
+        e = launch_integ<2>(integrate2d_kernel<2, false>, integrate2d_kernel<2, true>, P.n_fields > 0, grid, shmem, g, s);
+        if (e != hipSuccess) return e;
         break;
     }
     return hipGetLastError();
@@ -1133,20 +1220,21 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
     g.blocks = P.blocks.p; g.E = P.E.p; g.bq_off = P.bq_off.p; g.bq_y = P.bq_y.p; g.bq_w = P.bq_w.p;
     g.bq_N = P.bq_N.p; g.bq_face = P.bq_face.p; g.bq_nact = P.bq_nact.p; g.bq_act = P.bq_act.p;
     g.counters = P.counters.p; g.amax = amax; g.tile_rows = tile_rows;
+    g.fields = field_set(P);
     if ((e = upload_rules(s)) != hipSuccess) return e;
     dim3 grid((unsigned)P.n);
     switch (P.rk_order) {
     case 0:
-        if ((e = hipFuncSetAttribute((const void *)integrate3d_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
-        integrate3d_kernel<0><<<grid, kThreads, shmem, s>>>(g);
+        e = launch_integ<0>(integrate3d_kernel<0, false>, integrate3d_kernel<0, true>, P.n_fields > 0, grid, shmem, g, s);
+        if (e != hipSuccess) return e;
         break;
     case 1:
-        if ((e = hipFuncSetAttribute((const void *)integrate3d_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
-        integrate3d_kernel<1><<<grid, kThreads, shmem, s>>>(g);
+        e = launch_integ<1>(integrate3d_kernel<1, false>, integrate3d_kernel<1, true>, P.n_fields > 0, grid, shmem, g, s);
+        if (e != hipSuccess) return e;
         break;
     default:
-        if ((e = hipFuncSetAttribute((const void *)integrate3d_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem)) != hipSuccess) return e;
-        integrate3d_kernel<2><<<grid, kThreads, shmem, s>>>(g);
+        e = launch_integ<2>(integrate3d_kernel<2, false>, integrate3d_kernel<2, true>, P.n_fields > 0, grid, shmem, g, s);
+        if (e != hipSuccess) return e;
         break;
     }
     return hipGetLastError();

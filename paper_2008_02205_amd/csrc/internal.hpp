@@ -28,6 +28,8 @@ constexpr int kTri3Rule = kTri3N * kTri3N;
 constexpr int kBqAct3 = 128;       // active functions stored per boundary point (3D)
 constexpr int kCandMax3D = 512;    // functions possibly active on one 3D cell
 constexpr int kMaxRestart = 30;
+constexpr int kMaxFields = 8;    // smooth material fields per problem
+constexpr int kMaxMat = 8;       // materials per problem
 constexpr int kTagBox = -100;      // edge of the kernel box not on the domain
 
 // Thread-local error message for mlpg_last_error.
@@ -139,6 +141,9 @@ struct Problem {
     int n_regions = 0;
     DevBuf<double> reg_lo, reg_hi;
     DevBuf<int32_t> reg_mat;
+    int n_fields = 0;                          // smooth material fields (mlpg_material_fields)
+    double field_par[kMaxFields][4] = {};      // a, b, k, phase
+    int field_mat[kMaxFields] = {};
 
     DevBuf<double> x, R;
     DevBuf<int64_t> nb_off;

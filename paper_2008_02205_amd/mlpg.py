@@ -26,7 +26,8 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_geometry", "mlpg_get_info", "mlpg_get_volumes", "mlpg_cell_capacity", "mlpg_get_cells",
            "mlpg_boundary_points", "mlpg_integrate", "mlpg_get_pattern", "mlpg_get_blocks", "mlpg_assemble",
            "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
-           "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress"]
+           "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress",
+           "mlpg_material_fields"]
 
 
 class MlpgError(RuntimeError):
@@ -76,6 +77,7 @@ def lib() -> C.CDLL:
         L.mlpg_get_cells.argtypes = [vp, vp, vp, vp, vp]
         L.mlpg_boundary_points.argtypes = [vp, vp, vp, vp]
         L.mlpg_integrate.argtypes = [vp, i32, vp]
+        L.mlpg_material_fields.argtypes = [vp, i32, vp, vp]
         L.mlpg_get_pattern.argtypes = [vp, vp, vp, vp]
         L.mlpg_get_blocks.argtypes = [vp, vp, vp, vp]
         L.mlpg_assemble.argtypes = [vp, i32, vp, vp, i32, vp, vp, dbl, vp, i32, vp]
@@ -172,6 +174,16 @@ def mlpg_geometry(x, R, nbr_off, nbr_idx, dom_lo, dom_hi, regions=()):
     _check(lib().mlpg_geometry(C.byref(h), dim, n, _dev(x), _dev(R), _dev(nbr_off), _dev(idx), _host(lo), _host(hi),
                                len(regions), _host(rlo), _host(rhi), _host(rmat), _stream()))
     return h
+
+
+def mlpg_material_fields(h, fields=()):
+    """Smooth material fields ``(a, b, k, phase, material)`` (see the C declaration)."""
+    if fields:
+        par = np.ascontiguousarray([f[:4] for f in fields], dtype=np.float64)
+        mat = np.ascontiguousarray([f[4] for f in fields], dtype=np.int32)
+    else:
+        par = mat = None
+    _check(lib().mlpg_material_fields(h, len(fields), _host(par), _host(mat)))
 
 
 def mlpg_get_info(h) -> dict:

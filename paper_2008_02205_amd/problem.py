@@ -12,13 +12,15 @@ from . import mlpg as api
 
 
 class GpuProblem:
-    def __init__(self, x: np.ndarray, R: np.ndarray, dom_lo, dom_hi, regions=()):
+    def __init__(self, x: np.ndarray, R: np.ndarray, dom_lo, dom_hi, regions=(), fields=()):
         self.dim = x.shape[1]
         self.x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
         self.R = torch.from_numpy(np.ascontiguousarray(R, dtype=np.float64)).cuda()
         self.nbr_off, total = api.mlpg_neighbors_count(self.x, self.R)
         self.nbr_idx = api.mlpg_neighbors_fill(self.x, self.R, self.nbr_off, total)
         self.h = api.mlpg_geometry(self.x, self.R, self.nbr_off, self.nbr_idx, dom_lo, dom_hi, regions)
+        if fields:
+            api.mlpg_material_fields(self.h, fields)
         self.info = api.mlpg_get_info(self.h)
         self.n = self.info["n"]
         self.M = 0

@@ -246,6 +246,8 @@ class Workload:
     inflow: str                      # "vacuum" | "beam"
     seed: int
     pd_radius: float = 0.0           # Poisson-disk spacing when counts is None
+    fields: tuple = ()               # smooth material fields (a, b, k, phase, material)
+    t0: float = 0.0                  # time of the initial state (steady problems: time of the solution)
 
     @property
     def inv_c_dt(self) -> float:
@@ -275,7 +277,29 @@ def config(k: int, scale: Optional[int] = None) -> Workload:
                         256, "beam-dense", (1e-4, 100.0), (0.0, 99.0),
                         (((1.0, 0.0), (2.0, 1.0), 1),), 10, 0.05, 1.0, "none", "beam",
                         SEED_BASE + 4, pd_radius=0.00438)
+    if k == 6:
+        # Sec. 5.1 sinusoidal manufactured problem: uniform lattice on [-1, 1]^2,
+        # varying opacities as material fields, steady (solution at t = 0)
+        n = scale or 128
+        return Workload("2d-paper-mms-cos", 2, (-1.0, -1.0), (1.0, 1.0), (n, n), 0.0, 2.0, 1, 16, "product",
+                        MMS_COS_SIGMA_T, MMS_COS_SIGMA_S, (), 0, 0.0, 1.0, "paper-cos", "paper-cos",
+                        SEED_BASE + 6, fields=MMS_COS_FIELDS)
+    if k == 7:
+        # Sec. 5.1 outgoing-wave manufactured problem, steady (solution at t = 0.5)
+        n = scale or 128
+        return Workload("2d-paper-mms-wave", 2, (-1.0, -1.0), (1.0, 1.0), (n, n), 0.0, 2.0, 1, 16, "product",
+                        (MMS_WAVE_SIGMA_A + MMS_WAVE_SIGMA_S,), (MMS_WAVE_SIGMA_S,), (), 0, 0.0, 1.0,
+                        "paper-wave", "paper-wave", SEED_BASE + 7, t0=0.5)
     raise ValueError(k)
+
+
+def paper_mms_psi(w: Workload, x: np.ndarray, t: float) -> np.ndarray:
+    """The isotropic manufactured solution of a Sec. 5.1 workload at time t, per point."""
+    if w.source == "paper-cos":
+        return mms_cos_psi(x, t)
+    if w.source == "paper-wave":
+        return mms_wave_psi(x, t)
+    raise ValueError(w.source)
 
 
 def points_for(w: Workload) -> tuple[np.ndarray, float]:
@@ -302,24 +326,32 @@ def source_values(w: Workload, x: np.ndarray, omega: np.ndarray, t: float) -> np
         return np.repeat(g[:, None], m, axis=1)
     if w.source == "none":
         return np.zeros((x.shape[0], m))
+    if w.source in ("paper-cos", "paper-wave"):
+        fn = mms_cos_source if w.source == "paper-cos" else mms_wave_source
+        return fn(x, omega, t, 1.0 / w.c if w.steps > 0 else 0.0)
     raise ValueError(w.source)
 
 
 def initial_psi(w: Workload, x: np.ndarray, omega: np.ndarray) -> np.ndarray:
     if w.source == "mms-sin":
         return mms_sin_psi(x, omega, 0.0)
+    if w.source in ("paper-cos", "paper-wave"):
+        return np.repeat(paper_mms_psi(w, x, w.t0)[:, None], omega.shape[0], axis=1)
     return np.zeros((x.shape[0], omega.shape[0]))
 
 
-def inflow_values(w: Workload, y: np.ndarray, omega: np.ndarray) -> np.ndarray:
+def inflow_values(w: Workload, y: np.ndarray, omega: np.ndarray, t: Optional[float] = None) -> np.ndarray:
     """Incoming angular flux psi_b at boundary points ``y[nb][d]`` for each ordinate: ``[nb][M]``.
 
     Beam: psi_b = 1 on the face x = 0 where |y - 1/2| < 0.05, for ordinates
-    within 10 degrees of +x; 0 elsewhere.
+    within 10 degrees of +x; 0 elsewhere.  Manufactured problems: the
+    solution itself at time t (default: the workload's t0).
     """
     nb, m = y.shape[0], omega.shape[0]
     if w.inflow == "vacuum":
         return np.zeros((nb, m))
+    if w.inflow in ("paper-cos", "paper-wave"):
+        return np.repeat(paper_mms_psi(w, y, w.t0 if t is None else t)[:, None], m, axis=1)
     if w.inflow == "beam":
         on = (np.abs(y[:, 0] - w.lo[0]) < 1e-12) & (np.abs(y[:, 1] - 0.5) < 0.05)
         ang = np.arctan2(omega[:, 1], omega[:, 0])
