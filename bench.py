@@ -51,11 +51,13 @@ def parse():
                     help="instead of the benchmark: serve this many requests of the seeded request stream "
                          "(Poisson arrivals at 50/s, mixed precision) and print latency and throughput")
     ap.add_argument("--slots", type=int, default=4, help="concurrent problems in the serving mode")
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 6, 7],
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 6, 7, 8, 9],
                     help="2: the benchmark above; 1, 3, 4: time that workload's whole path instead (phase times, "
                          "p50/p99 over --steps repetitions) and print its own record; 6, 7: the paper's sinusoidal "
                          "and outgoing-wave manufactured problems (steady, [-1,1]^2, --scale points per axis), "
-                         "with the relative error against the exact scalar flux")
+                         "with the relative error against the exact scalar flux; 8: workload 2 with points "
+                         "that move every step (geometry, integration and assembly inside the time loop); 9: the asteroid of "
+                         "Sec. 5.4 at one tenth of its lengths (shell materials, Alg. 2 refined quadrature)")
     ap.add_argument("--be-steps", type=int, default=None, help="backward-Euler steps per repetition (workloads 3/4)")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
@@ -80,6 +82,9 @@ def main():
     mlpg.lib()
     if args.serving:
         serve(args)
+        return
+    if args.workload == 9:
+        asteroid_workload(args)
         return
     if args.workload != 2:
         other_workload(args)
@@ -220,15 +225,22 @@ def other_workload(args):
     steps = w.steps if w.steps > 0 else 1
     if args.be_steps:
         steps = min(steps, args.be_steps)
-    qs = [torch.from_numpy(np.ascontiguousarray(W.source_values(w, x, om, w.t0 + (s + 1) * w.dt))).cuda()
-          for s in range(steps)]
+    # moving points: the positions of every step are inputs (the caller's motion), made before timing
+    xs = [x]
+    for s in range(steps if w.velocity else 0):
+        xs.append(W.advect_points(w, xs[-1], w.dt))
+    qs = [torch.from_numpy(np.ascontiguousarray(
+        W.source_values(w, xs[s + 1] if w.velocity else x, om, w.t0 + (s + 1) * w.dt))).cuda()
+        for s in range(steps)]
     psi0 = torch.from_numpy(np.ascontiguousarray(W.initial_psi(w, x, om))).cuda()
     tau = torch.full((n,), dx, dtype=torch.float64, device="cuda")
     precs = {1: ("fp64",), 3: ("mixed",), 4: ("mixed", "fp64"), 6: ("fp64", "mixed"),
-             7: ("fp64", "mixed")}[args.workload]
+             7: ("fp64", "mixed"), 8: ("fp64", "mixed")}[args.workload]
     exact = None
     if w.source in ("paper-cos", "paper-wave"):
         exact = 4.0 * np.pi * W.paper_mms_psi(w, x, w.t0 + steps * w.dt)
+    elif w.source == "mms-sin":
+        exact = W.mms_sin_phi(xs[-1], w.t0 + steps * w.dt)
     if args.precision != "both":
         precs = (args.precision,)
 
@@ -269,7 +281,19 @@ def other_workload(args):
         if args.max_inner:
             opts.max_inner = args.max_inner
         err = None
+        mv = {"geometry_s": 0.0, "integrate_s": 0.0, "assemble_s": 0.0}
         for s in range(steps):
+            if w.velocity:
+                # the points have moved: neighbours, cells, integration and assembly again
+                ta = sync_time()
+                P.move(xs[s + 1], R)
+                tb = sync_time()
+                P.integrate(w.rk_order)
+                tc = sync_time()
+                P.assemble(om, wq, list(w.sigma_t), list(w.sigma_s), w.inv_c_dt, tau,
+                           precision=mlpg.MLPG_FP64 if prec == "fp64" else mlpg.MLPG_MIXED)
+                td = sync_time()
+                mv["geometry_s"] += tb - ta; mv["integrate_s"] += tc - tb; mv["assemble_s"] += td - tc
             _, pv, _, inf = mlpg.mlpg_solve(P.h, qs[s], pb, opts, want_psi=False, raise_on_error=False)
             conv = conv and inf["converged"] == 1
             its += inf["inner_iters"]
@@ -279,13 +303,20 @@ def other_workload(args):
                   f"{inf['inner_solves']}, Krylov steps {inf['inner_iters']}, {time.perf_counter() - t3:.1f} s",
                   file=sys.stderr, flush=True)
         t4 = sync_time()
+        if w.velocity:
+            # per-step rebuild times are reported separately from the solves
+            t_solve = t4 - t3 - sum(mv.values())
+        else:
+            t_solve = t4 - t3
         if exact is not None:
             # relative error of the scalar flux at the centres (Sec. 5): sum |phi - phi_exact| / sum phi_exact
             err = float(np.abs(pv.cpu().numpy() - exact).sum() / exact.sum())
         P.close()
-        return {"geometry_s": t1 - t0, "integrate_s": t2 - t1, "assemble_s": t3 - t2, "solve_s": t4 - t3,
+        return {"geometry_s": t1 - t0 + mv["geometry_s"], "integrate_s": t2 - t1 + mv["integrate_s"],
+                "assemble_s": t3 - t2 + mv["assemble_s"], "solve_s": t_solve,
                 "total_s": t4 - t0, "iters": its, "solves": solves, "outer": outer,
-                "fallback_qps": info["fallback_qps"], "converged": conv, "rel_error": err}
+                "fallback_qps": info["fallback_qps"], "converged": conv, "rel_error": err,
+                "rebuild_per_step_s": sum(mv.values()) / steps if w.velocity else None}
 
     out = {}
     for prec in precs:
@@ -301,6 +332,7 @@ def other_workload(args):
                      "iters_per_rep": rs[0]["iters"], "outer_per_rep": rs[0]["outer"],
                      "fallback_qps": rs[0]["fallback_qps"], "converged": all(r["converged"] for r in rs),
                      "rel_error_vs_exact": rs[0]["rel_error"],
+                     "rebuild_per_step_s": rs[0]["rebuild_per_step_s"],
                      "max_outer": args.max_outer, "max_inner": args.max_inner}
     main_p = precs[0]
     rec = {"metric": "DOF*ordinate*Krylov-iter/s", "value": out[main_p]["value"], "unit": "DOF*ord*iter/s",
@@ -309,6 +341,76 @@ def other_workload(args):
            "config": {"workload": f"{w.name}: {n} points, {M} ordinates, rk order {w.rk_order}, "
                                   f"{'steady' if w.steps == 0 else f'{steps} BE steps'}", "points": n,
                       "ordinates": M, "dim": w.dim},
+           "detail": out}
+    print(json.dumps(rec), flush=True)
+
+
+def asteroid_workload(args):
+    """Sec. 5.4 asteroid at one tenth of the paper's lengths: an absorbing shell (20 mean free paths)
+    lit by a small source through the Alg. 2 refined quadrature (goal 2048 ordinates); steady.  The
+    error is taken where the refined ordinates resolve the flux (the lit cone in front of the asteroid)
+    against the exact line-source flux for the same polar levels."""
+    import torch
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    a = W.asteroid(0.1)
+    spacing = 15.0 / args.scale if args.scale else 0.05
+    x, R, dx = W.asteroid_points(a, spacing)
+    shells, st, ss = W.asteroid_materials(a)
+    om, wq = mlpg.mlpg_refined_quadrature(0, 8, a.src, (0.0, 0.0), a.radius)
+    n, M = x.shape[0], om.shape[0]
+    q = torch.from_numpy(np.ascontiguousarray(W.asteroid_source(a, x, M))).cuda()
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    exact = W.asteroid_phi_ordinates(a, x, xg[xg > 0], wg[xg > 0])
+    lit = W.asteroid_lit_region(a, x, 1.0)
+    precs = ("fp64", "mixed") if args.precision == "both" else (args.precision,)
+
+    def sync_time():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    def rep(prec):
+        t0 = sync_time()
+        P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
+        t1 = sync_time()
+        info = P.integrate(1)
+        t2 = sync_time()
+        P.assemble(om, wq, list(st), list(ss), 0.0, dx, precision=mlpg.MLPG_FP64 if prec == "fp64" else mlpg.MLPG_MIXED)
+        t3 = sync_time()
+        opts = mlpg.mlpg_default_opts()
+        if args.max_inner:
+            opts.max_inner = args.max_inner
+        _, pv, _, inf = mlpg.mlpg_solve(P.h, q, None, opts, want_psi=False, raise_on_error=False)
+        t4 = sync_time()
+        pv = pv.cpu().numpy()
+        P.close()
+        print(f"[asteroid {prec}] geometry {t1 - t0:.2f} s, integrate {t2 - t1:.2f} s, assemble {t3 - t2:.2f} s, "
+              f"solve {t4 - t3:.2f} s, Krylov steps {inf['inner_iters']}", file=sys.stderr, flush=True)
+        return {"geometry_s": t1 - t0, "integrate_s": t2 - t1, "assemble_s": t3 - t2, "solve_s": t4 - t3,
+                "total_s": t4 - t0, "iters": inf["inner_iters"], "converged": inf["converged"] == 1,
+                "lit_rel_error": float(np.abs(pv[lit] - exact[lit]).sum() / exact[lit].sum()),
+                "negative_fraction": float(np.mean(pv < 0.0)), "fallback_qps": info["fallback_qps"]}
+
+    out = {}
+    for prec in precs:
+        for _ in range(args.warmup):
+            rep(prec)
+        rs = [rep(prec) for _ in range(max(args.steps, 1))]
+        tot = np.array([r["total_s"] for r in rs])
+        out[prec] = {"value": float(np.mean([n * r["iters"] / r["total_s"] for r in rs])),
+                     "direction_solves_per_s": float(np.mean([M / r["total_s"] for r in rs])),
+                     "p50_total_s": float(np.percentile(tot, 50)), "p99_total_s": float(np.percentile(tot, 99)),
+                     "phases_s": {k: float(np.mean([r[k] for r in rs]))
+                                  for k in ("geometry_s", "integrate_s", "assemble_s", "solve_s")},
+                     "iters_per_rep": rs[0]["iters"], "converged": all(r["converged"] for r in rs),
+                     "lit_rel_error_vs_exact": rs[0]["lit_rel_error"], "lit_points": int(lit.sum()),
+                     "negative_fraction": rs[0]["negative_fraction"], "fallback_qps": rs[0]["fallback_qps"]}
+    main_p = precs[0]
+    rec = {"metric": "DOF*ordinate*Krylov-iter/s", "value": out[main_p]["value"], "unit": "DOF*ord*iter/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "dtype": "f64" if main_p == "fp64" else "f32+f64", "data": "synthetic",
+           "config": {"workload": f"asteroid (lengths x0.1): {n} points, {M} refined ordinates, steady",
+                      "points": n, "ordinates": M, "dim": 2},
            "detail": out}
     print(json.dumps(rec), flush=True)
 

@@ -74,6 +74,34 @@ const char *mlpg_last_error(void);
 int mlpg_angular_quadrature(int dim, int n_ord, int kind, double *omega, double *w);
 
 /* ------------------------------------------------------------------------
+ * Refined angular quadrature (Sec. 4.3 and Alg. 2): keep every ordinate of a
+ * fine goal rule whose ray hits an object and merge the others into the
+ * coarsest ordinates of a hierarchy that contain no hitting goal ordinate.
+ * Host-only, dim = 2.  The hierarchy is azimuthal bisection of the 2D product
+ * rule (mlpg_angular_quadrature, kind MLPG_QUAD_PRODUCT): level L has
+ * A_L = 4 * 2^L equal azimuthal sectors per polar level, sector k spanning
+ * [2 pi k / A_L, 2 pi (k+1) / A_L] with its ordinate at the midpoint and
+ * weight 2 w_p (2 pi / A_L) (w_p the polar weight), so that every sector of
+ * level L is the union of two of level L+1.  A goal ordinate (level
+ * goal_level) hits when the ray from `src` along its projected direction
+ * meets the disk (center, radius) (every ray does when src is inside).  A
+ * sector of level >= min_level is kept whole when none of its goal
+ * subsectors hits and no coarser kept sector contains it; goal sectors
+ * are kept otherwise.  Both polar levels are refined alike (the test depends
+ * on the azimuth only).  With no hit the result is the product rule of
+ * level min_level; with every goal ordinate hitting it is the goal rule.
+ * Order: polar level outer (increasing cosine), azimuth inner (increasing
+ * sector start).  The weights sum to 4 pi.
+ *   src, center: host [2]; radius >= 0; 0 <= min_level <= goal_level <= 12.
+ *   cap = 0: only the count is returned (omega, w may be NULL); otherwise
+ *   omega: host [cap][2] out, w: host [cap] out.
+ * Returns the number of ordinates, MLPG_ERR_CAPACITY when 0 < cap < count,
+ * MLPG_ERR_ARG for invalid levels, radius or pointers.
+ * ---------------------------------------------------------------------- */
+int mlpg_refined_quadrature(int min_level, int goal_level, const double *src, const double *center, double radius,
+                            int cap, double *omega, double *w);
+
+/* ------------------------------------------------------------------------
  * Overlap connectivity (Sec. 3.4, Eq. mlpg-connectivity): j != i is a
  * neighbour of i when |x_i - x_j| <= R_i + R_j.  Lists are in increasing j.
  * Two calls: count fills nbr_off (device [n+1], exclusive prefix sums) and
@@ -110,6 +138,26 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
                   const int64_t *nbr_off, const int32_t *nbr_idx, const double *dom_lo,
                   const double *dom_hi, int n_regions, const double *region_lo, const double *region_hi,
                   const int32_t *region_mat, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Moving points (Sec. 1: with points that move every time step, as in
+ * radiation hydrodynamics, the integration is redone at each step and must
+ * need no manual adjustment; Sec. 3.1: the cells depend only on the point
+ * positions and kernel extents).  Replaces the positions, radii and overlap
+ * lists of an existing handle (same n, dim, domain, regions and material
+ * fields) and rebuilds the cells, the boundary quadrature sizing and the
+ * pattern.  The handle returns to the state after mlpg_geometry: call
+ * mlpg_integrate and mlpg_assemble again before the next mlpg_solve.  The
+ * state kept by mlpg_solve (the per-point angular flux coefficients
+ * Psi^{n-1} and Phi) stays with the points, so the next backward-Euler step
+ * uses the old coefficients with the new functions.
+ *   x, R, nbr_off, nbr_idx: device, as for mlpg_geometry (n points).
+ * Synchronises `stream`.  Errors: MLPG_ERR_STATE without a geometry,
+ * MLPG_ERR_GEOMETRY for a cell over capacity (the handle must then be
+ * destroyed), MLPG_ERR_ARG for null pointers.
+ * ---------------------------------------------------------------------- */
+int mlpg_update_points(mlpg_handle h, const double *x, const double *R, const int64_t *nbr_off,
+                       const int32_t *nbr_idx, void *stream);
 
 typedef struct {
     int64_t n;               /* points */
@@ -163,6 +211,23 @@ int mlpg_boundary_points(mlpg_handle h, double *y, int32_t *face, void *stream);
  * with n_fields > 0; MLPG_ERR_STATE before mlpg_geometry.
  * ---------------------------------------------------------------------- */
 int mlpg_material_fields(mlpg_handle h, int n_fields, const double *param, const int32_t *mat);
+
+/* ------------------------------------------------------------------------
+ * Shells of material (the asteroid of Sec. 5.4: an absorbing shell around a
+ * centre; annuli in 2D).  Optional, between mlpg_geometry and mlpg_integrate.
+ * At every volume quadrature point y the material set by the region boxes is
+ * replaced by mat[r] for each shell r with r_in <= |y - centre_r| <= r_out
+ * (in order, last match wins); material fields then apply as described
+ * above.
+ *   n_shells: 0..8 (0 removes the shells); center: host [n_shells][dim];
+ *   radii: host [n_shells][2] (r_in, r_out, 0 <= r_in <= r_out); mat: host
+ *   [n_shells], each in [0, 8).  Raises the material count to cover every
+ *   mat[r]; resets the handle to the state after mlpg_geometry.
+ * Errors: MLPG_ERR_ARG for a count, radius or material out of range or a
+ * NULL array with n_shells > 0; MLPG_ERR_STATE before mlpg_geometry.
+ * ---------------------------------------------------------------------- */
+int mlpg_material_shells(mlpg_handle h, int n_shells, const double *center, const double *radii,
+                         const int32_t *mat);
 
 /* ------------------------------------------------------------------------
  * Stage 2, integration (Sec. 2.2; Sec. 3.2 and Alg. 1; App. A).  At every

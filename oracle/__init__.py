@@ -59,7 +59,8 @@ class IntegCtx(C.Structure):
                 ("row_off", _i64p), ("col", _i32p), ("nnz", C.c_int64), ("n_regions", C.c_int),
                 ("reg_lo", _dp), ("reg_hi", _dp), ("reg_mat", _i32p), ("blocks", _dp),
                 ("fallbacks", C.c_int64), ("missing", C.c_int64), ("n_fields", C.c_int),
-                ("field_par", _dp), ("field_mat", _i32p)]
+                ("field_par", _dp), ("field_mat", _i32p), ("n_shells", C.c_int), ("shell_par", _dp),
+                ("shell_mat", _i32p)]
 
 
 class OpCtx(C.Structure):
@@ -171,6 +172,60 @@ def tet_rule(n: int = 2):
                 pts.append([ua, (1 - ua) * vb, (1 - ua) * (1 - vb) * sc])
                 wts.append(wu[a] * wv[b] * ws[c])
     return np.array(pts), np.array(wts)
+
+
+def refined_quadrature(min_level: int, goal_level: int, src, center, radius: float):
+    """Angular refinement of Alg. 2 (Sec. 4.3) on the 2D product rule's azimuthal hierarchy.
+
+    Rule L has 4 * 2^L equal azimuthal sectors per polar level (midpoint
+    ordinates, the polar levels of the 2D product rule).  Following Alg. 2:
+    start from the goal rule; for every rule from min_level up to the one
+    below the goal, add each of its ordinates whose goal ordinates are all
+    still present and none of which hits the object, removing those goal
+    ordinates; finally add the goal ordinates that remain.  An ordinate hits
+    when its azimuth lies within asin(radius / distance) of the direction
+    from src to the disk centre (always, when src is inside the disk).
+    Returned in the order polar level, then sector start angle.
+    """
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    pos = xg > 0
+    xi, wp = xg[pos], wg[pos]
+    dx, dy = center[0] - src[0], center[1] - src[1]
+    dist = math.hypot(dx, dy)
+    inside = dist <= radius
+    half = math.asin(radius / dist) if not inside else math.pi
+    aim = math.atan2(dy, dx)
+
+    def hits(phi):
+        if inside:
+            return True
+        dphi = (phi - aim + math.pi) % (2.0 * math.pi) - math.pi
+        return abs(dphi) <= half
+
+    ng = 4 * 2 ** goal_level
+    goal_hit = [hits(2.0 * math.pi * (c + 0.5) / ng) for c in range(ng)]
+    picked = []                         # (polar level, rule, sector)
+    for p in range(2):
+        present = [True] * ng
+        for rule in range(min_level, goal_level):
+            na = 4 * 2 ** rule
+            span = ng // na
+            for k in range(na):
+                kids = range(k * span, (k + 1) * span)
+                if all(present[c] for c in kids) and not any(goal_hit[c] for c in kids):
+                    picked.append((p, rule, k))
+                    for c in kids:
+                        present[c] = False
+        picked += [(p, goal_level, c) for c in range(ng) if present[c]]
+    picked.sort(key=lambda e: (e[0], e[2] / (4 * 2 ** e[1])))
+    om, w = [], []
+    for p, rule, k in picked:
+        na = 4 * 2 ** rule
+        st = math.sqrt(1.0 - xi[p] ** 2)
+        ph = (2.0 * (k + 1) - 1.0) * np.pi / na
+        om.append([st * math.cos(ph), st * math.sin(ph)])
+        w.append(2.0 * wp[p] * 2.0 * np.pi / na)
+    return np.array(om), np.array(w)
 
 
 def angular_quadrature(dim: int, n_ord: int, kind: str = "product"):
@@ -401,7 +456,7 @@ class Integrated:
 
 
 def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int = None, seg_n: int = 5,
-              kmax: int = None, tet_n: int = 2, fields=()) -> Integrated:
+              kmax: int = None, tet_n: int = 2, fields=(), shells=()) -> Integrated:
     """Blocks of Alg. 1 over all cells; boundary quadrature points; point-value matrix E.
 
     Rules: 2D, triangle rule n = 5 (25 points) in the cells and line rule
@@ -412,7 +467,9 @@ def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int
     elsewhere).  ``fields``: smooth material fractions ``(a, b, k, phase,
     material)``; each moves ``a + b prod_alpha cos(k y_alpha + phase)`` of the
     quadrature point's weight from material 0 to ``material`` (the spatially
-    varying opacities of Sec. 5.1 are sums of such terms)."""
+    varying opacities of Sec. 5.1 are sums of such terms).  ``shells``:
+    ``(centre, r_in, r_out, material)``, applied after the boxes (last match
+    wins): the points with r_in <= |y - centre| <= r_out take the material."""
     d = g.dim
     if tri_n is None:
         tri_n = 5 if d == 2 else 2
@@ -432,10 +489,15 @@ def integrate(g: Geometry, rk_order: int, regions=(), n_mat: int = 1, tri_n: int
         raise ValueError("a field moves weight to a material in [1, n_mat)")
     if n_mat > 8:
         raise ValueError("at most 8 materials")
+    spar = np.array([list(sh[0]) + [sh[1], sh[2]] for sh in shells], dtype=np.float64).reshape(-1, d + 2) \
+        if shells else np.zeros((1, d + 2))
+    smat = np.array([sh[3] for sh in shells], dtype=np.int32) if shells else np.zeros(1, dtype=np.int32)
+    if shells and (smat.min() < 0 or smat.max() >= n_mat):
+        raise ValueError("a shell's material must be in [0, n_mat)")
     ic = IntegCtx(d, rk_order, n_mat, g.n, _p(g.x), _p(g.R), _p(V), _p(g.nb_off, _i64p),
                   _p(g.nb_idx, _i32p), _p(g.row_off, _i64p), _p(g.col, _i32p), nnz, len(regions),
                   _p(reg_lo), _p(reg_hi), _p(reg_mat, _i32p), _p(blocks), 0, 0, len(fields),
-                  _p(fpar), _p(fmat, _i32p))
+                  _p(fpar), _p(fmat, _i32p), len(shells), _p(spar), _p(smat, _i32p))
     tp, tw = triangle_rule(tri_n)
     tp = _f64(tp); tw = _f64(tw)
     cl = g.cells

@@ -678,6 +678,9 @@ typedef struct {
     int n_fields;               /* smooth material fields (may be 0) */
     const double *field_par;    /* [n_fields][4]: a, b, k, phase */
     const int32_t *field_mat;   /* [n_fields] material that receives the field */
+    int n_shells;               /* spherical shells (may be 0) */
+    const double *shell_par;    /* [n_shells][dim + 2]: centre, inner radius, outer radius */
+    const int32_t *shell_mat;   /* [n_shells] material inside the shell */
 } integ_ctx;
 
 /* Material fractions f[0..n_mat) at y.  Box regions give an indicator (last
@@ -690,7 +693,16 @@ typedef struct {
 static void material_fractions(const integ_ctx *ic, const double *y, double *f)
 {
     for (int g = 0; g < ic->n_mat; ++g) f[g] = 0.0;
-    f[material_at(ic->dim, y, ic->n_regions, ic->reg_lo, ic->reg_hi, ic->reg_mat)] = 1.0;
+    int m = material_at(ic->dim, y, ic->n_regions, ic->reg_lo, ic->reg_hi, ic->reg_mat);
+    /* shells (annuli in 2D, such as the asteroid of Sec. 5.4) after the boxes, last match wins */
+    for (int r = 0; r < ic->n_shells; ++r) {
+        const double *sp = ic->shell_par + (ic->dim + 2) * r;
+        double d2 = 0.0;
+        for (int a = 0; a < ic->dim; ++a) d2 += (y[a] - sp[a]) * (y[a] - sp[a]);
+        const double d = sqrt(d2);
+        if (d >= sp[ic->dim] && d <= sp[ic->dim + 1]) m = ic->shell_mat[r];
+    }
+    f[m] = 1.0;
     for (int r = 0; r < ic->n_fields; ++r) {
         const double *fp = ic->field_par + 4 * r;
         double pr = 1.0;

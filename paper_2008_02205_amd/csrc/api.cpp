@@ -247,6 +247,95 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
     return MLPG_OK;
 }
 
+// Positions, radii and overlap lists of the points, then the cells (Sec. 3.1),
+// the boundary quadrature sizing and the pattern: the part of stage 1 that
+// depends on where the points are.  Reallocates what grew; counters reset.
+static int build_geometry(Problem &P, const double *x, const double *R, const int64_t *nbr_off,
+                          const int32_t *nbr_idx, hipStream_t s)
+{
+    const int64_t n = P.n;
+    const int dim = P.dim;
+#define TRY(call)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (call);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));          \
+            return MLPG_ERR_HIP;                                                   \
+        }                                                                          \
+    } while (0)
+    P.failed = 0;
+    P.oversize = 0;
+    int64_t nnz_nb = 0;
+    TRY(hipMemcpyAsync(&nnz_nb, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    if (nnz_nb < 0 || nnz_nb > ((int64_t)1 << 40)) {
+        set_error("mlpg_geometry: neighbour list size out of range");
+        return MLPG_ERR_ARG;
+    }
+    P.nnz_nb = nnz_nb;
+    TRY(P.x.alloc(n * dim));
+    TRY(P.R.alloc(n));
+    TRY(P.nb_off.alloc(n + 1));
+    TRY(P.nb_idx.alloc(std::max<int64_t>(1, nnz_nb)));
+    TRY(hipMemcpyAsync(P.x.p, x, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
+    TRY(hipMemcpyAsync(P.R.p, R, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    TRY(hipMemcpyAsync(P.nb_off.p, nbr_off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz_nb) TRY(hipMemcpyAsync(P.nb_idx.p, nbr_idx, sizeof(int32_t) * nnz_nb, hipMemcpyDeviceToDevice, s));
+
+    TRY(P.V.alloc(n));
+    TRY(P.rho.alloc(n));
+    DevBuf<int32_t> flags;
+    DevBuf<int64_t> bqc;
+    TRY(flags.alloc(n));
+    TRY(bqc.alloc(n));
+    TRY(P.bq_off.alloc(n + 1));
+    if (dim == 2) {
+        TRY(P.nv.alloc(n));
+        TRY(P.tags.alloc(n * kCellCap2D));
+        TRY(P.verts.alloc(n * kCellCap2D * 2));
+        TRY(launch_clip2d(P, s, flags.p, bqc.p));
+        P.bq_kmax = kBqAct;
+    } else {
+        TRY(P.nf.alloc(n));
+        TRY(P.fnv.alloc(n * kFaceCap3));
+        TRY(P.ftags.alloc(n * kFaceCap3));
+        TRY(P.fverts.alloc(n * kFaceCap3 * kFaceVerts3 * 3));
+        TRY(launch_clip3d(P, s, flags.p, bqc.p));
+        P.bq_kmax = kBqAct3;
+    }
+    TRY(launch_exclusive_scan(bqc.p, P.bq_off.p, n, s));
+    std::vector<int32_t> hf(n);
+    TRY(hipMemcpyAsync(hf.data(), flags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(&P.n_bq, P.bq_off.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    flags.release();
+    bqc.release();
+    for (int64_t i = 0; i < n; ++i) {
+        if (hf[i] == 1) P.failed++;
+        if (hf[i] == 2) P.oversize++;
+    }
+    if (P.failed) {
+        set_error("mlpg_geometry: " + std::to_string(P.failed) + " cells empty or over the face/vertex capacity");
+        return MLPG_ERR_GEOMETRY;
+    }
+    P.nnz = nnz_nb + n;
+    TRY(P.row_off.alloc(n + 1));
+    TRY(P.col.alloc(P.nnz));
+    TRY(P.diag_pos.alloc(n));
+    TRY(launch_pattern(P, s));
+    int64_t nbq = std::max<int64_t>(1, P.n_bq);
+    TRY(P.bq_y.alloc(nbq * dim));
+    TRY(P.bq_w.alloc(nbq));
+    TRY(P.bq_face.alloc(nbq));
+    TRY(P.bq_nact.alloc(nbq));
+    TRY(P.bq_act.alloc(nbq * P.bq_kmax));
+    TRY(P.bq_N.alloc(nbq * P.bq_kmax));
+    TRY(P.counters.alloc(kNumCounters));
+    TRY(hipStreamSynchronize(s));
+#undef TRY
+    return MLPG_OK;
+}
+
 int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R, const int64_t *nbr_off,
                   const int32_t *nbr_idx, const double *dom_lo, const double *dom_hi, int n_regions,
                   const double *region_lo, const double *region_hi, const int32_t *region_mat, void *stream)
@@ -294,77 +383,26 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
         TRY(hipMemcpyAsync(P->reg_hi.p, region_hi, sizeof(double) * n_regions * dim, hipMemcpyHostToDevice, s));
         TRY(hipMemcpyAsync(P->reg_mat.p, region_mat, sizeof(int32_t) * n_regions, hipMemcpyHostToDevice, s));
     }
-    int64_t nnz_nb = 0;
-    TRY(hipMemcpyAsync(&nnz_nb, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    TRY(hipStreamSynchronize(s));
-    if (nnz_nb < 0 || nnz_nb > ((int64_t)1 << 40)) {
-        set_error("mlpg_geometry: neighbour list size out of range");
-        return fail(MLPG_ERR_ARG);
-    }
-    P->nnz_nb = nnz_nb;
-    TRY(P->x.alloc(n * dim));
-    TRY(P->R.alloc(n));
-    TRY(P->nb_off.alloc(n + 1));
-    TRY(P->nb_idx.alloc(std::max<int64_t>(1, nnz_nb)));
-    TRY(hipMemcpyAsync(P->x.p, x, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
-    TRY(hipMemcpyAsync(P->R.p, R, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    TRY(hipMemcpyAsync(P->nb_off.p, nbr_off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
-    if (nnz_nb) TRY(hipMemcpyAsync(P->nb_idx.p, nbr_idx, sizeof(int32_t) * nnz_nb, hipMemcpyDeviceToDevice, s));
-
-    TRY(P->V.alloc(n));
-    TRY(P->rho.alloc(n));
-    DevBuf<int32_t> flags;
-    DevBuf<int64_t> bqc;
-    TRY(flags.alloc(n));
-    TRY(bqc.alloc(n));
-    TRY(P->bq_off.alloc(n + 1));
-    if (dim == 2) {
-        TRY(P->nv.alloc(n));
-        TRY(P->tags.alloc(n * kCellCap2D));
-        TRY(P->verts.alloc(n * kCellCap2D * 2));
-        TRY(launch_clip2d(*P, s, flags.p, bqc.p));
-        P->bq_kmax = kBqAct;
-    } else {
-        TRY(P->nf.alloc(n));
-        TRY(P->fnv.alloc(n * kFaceCap3));
-        TRY(P->ftags.alloc(n * kFaceCap3));
-        TRY(P->fverts.alloc(n * kFaceCap3 * kFaceVerts3 * 3));
-        TRY(launch_clip3d(*P, s, flags.p, bqc.p));
-        P->bq_kmax = kBqAct3;
-    }
-    TRY(launch_exclusive_scan(bqc.p, P->bq_off.p, n, s));
-    std::vector<int32_t> hf(n);
-    TRY(hipMemcpyAsync(hf.data(), flags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    TRY(hipMemcpyAsync(&P->n_bq, P->bq_off.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    TRY(hipStreamSynchronize(s));
-    flags.release();
-    bqc.release();
-    for (int64_t i = 0; i < n; ++i) {
-        if (hf[i] == 1) P->failed++;
-        if (hf[i] == 2) P->oversize++;
-    }
-    if (P->failed) {
-        set_error("mlpg_geometry: " + std::to_string(P->failed) + " cells empty or over the face/vertex capacity");
-        return fail(MLPG_ERR_GEOMETRY);
-    }
-    P->nnz = nnz_nb + n;
-    TRY(P->row_off.alloc(n + 1));
-    TRY(P->col.alloc(P->nnz));
-    TRY(P->diag_pos.alloc(n));
-    TRY(launch_pattern(*P, s));
-    int64_t nbq = std::max<int64_t>(1, P->n_bq);
-    TRY(P->bq_y.alloc(nbq * dim));
-    TRY(P->bq_w.alloc(nbq));
-    TRY(P->bq_face.alloc(nbq));
-    TRY(P->bq_nact.alloc(nbq));
-    TRY(P->bq_act.alloc(nbq * P->bq_kmax));
-    TRY(P->bq_N.alloc(nbq * P->bq_kmax));
-    TRY(P->counters.alloc(kNumCounters));
-    TRY(hipStreamSynchronize(s));
+    int rc = build_geometry(*P, x, R, nbr_off, nbr_idx, s);
+    if (rc) return fail(rc);
 #undef TRY
     P->stage = 1;
     *out = P;
     return MLPG_OK;
+}
+
+int mlpg_update_points(mlpg_handle h, const double *x, const double *R, const int64_t *nbr_off,
+                       const int32_t *nbr_idx, void *stream)
+{
+    int rc = check_stage(h, 1, "mlpg_update_points");
+    if (rc) return rc;
+    MLPG_CHECK(x && R && nbr_off && nbr_idx, MLPG_ERR_ARG, "mlpg_update_points: null pointer");
+    Problem *P = h;
+    rc = build_geometry(*P, x, R, nbr_off, nbr_idx, S(stream));
+    // the integrated blocks and the assembled operators belong to the old
+    // positions; the state (per-point coefficients) and the solver settings stay
+    P->stage = 1;
+    return rc;
 }
 
 int mlpg_get_info(mlpg_handle h, mlpg_info *info)
@@ -435,6 +473,34 @@ int mlpg_material_fields(mlpg_handle h, int n_fields, const double *param, const
         for (int q = 0; q < 4; ++q) P->field_par[r][q] = r < n_fields ? param[4 * r + q] : 0.0;
         P->field_mat[r] = r < n_fields ? mat[r] : 0;
         if (r < n_fields) P->n_mat = std::max(P->n_mat, mat[r] + 1);
+    }
+    P->stage = 1;
+    return MLPG_OK;
+}
+
+int mlpg_material_shells(mlpg_handle h, int n_shells, const double *center, const double *radii,
+                         const int32_t *mat)
+{
+    int rc = check_stage(h, 1, "mlpg_material_shells");
+    if (rc) return rc;
+    MLPG_CHECK(n_shells >= 0 && n_shells <= kMaxFields, MLPG_ERR_ARG, "mlpg_material_shells: n_shells in [0, 8]");
+    MLPG_CHECK(n_shells == 0 || (center && radii && mat), MLPG_ERR_ARG, "mlpg_material_shells: null array");
+    for (int r = 0; r < n_shells; ++r) {
+        MLPG_CHECK(mat[r] >= 0 && mat[r] < kMaxMat, MLPG_ERR_ARG, "mlpg_material_shells: material in [0, 8)");
+        MLPG_CHECK(radii[2 * r] >= 0.0 && radii[2 * r + 1] >= radii[2 * r], MLPG_ERR_ARG,
+                   "mlpg_material_shells: need 0 <= r_in <= r_out");
+    }
+    Problem *P = h;
+    P->n_shells = n_shells;
+    for (int r = 0; r < kMaxFields; ++r) {
+        for (int q = 0; q < 5; ++q) P->shell_par[r][q] = 0.0;
+        P->shell_mat[r] = 0;
+        if (r >= n_shells) continue;
+        for (int a = 0; a < P->dim; ++a) P->shell_par[r][a] = center[P->dim * r + a];
+        P->shell_par[r][P->dim] = radii[2 * r];
+        P->shell_par[r][P->dim + 1] = radii[2 * r + 1];
+        P->shell_mat[r] = mat[r];
+        P->n_mat = std::max(P->n_mat, mat[r] + 1);
     }
     P->stage = 1;
     return MLPG_OK;

@@ -251,15 +251,26 @@ struct FieldSet {
     int n;
     double par[kMaxFields][4];   // a, b, k, phase
     int mat[kMaxFields];
+    int nshell;                  // shells (annuli in 2D): centre, inner and outer radius
+    double shell[kMaxFields][5];
+    int shell_mat[kMaxFields];
 };
 
 // w times the fraction of every material at y: the box indicator (material
-// `mat`), then the fields in order.  Unrolled over kMaxMat so that the
-// fractions stay in registers.
+// `mat`), overridden by the shells containing y (last match wins), then the
+// fields in order.  Unrolled over kMaxMat so that the fractions stay in
+// registers.
 template <int D>
 __device__ __forceinline__ void material_weights(const double *y, int mat, double w, const FieldSet &F,
                                                  double (&wf)[kMaxMat])
 {
+    for (int r = 0; r < F.nshell; ++r) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) d2 += (y[a] - F.shell[r][a]) * (y[a] - F.shell[r][a]);
+        const double d = sqrt(d2);
+        if (d >= F.shell[r][D] && d <= F.shell[r][D + 1]) mat = F.shell_mat[r];
+    }
     double f[kMaxMat];
 #pragma unroll
     for (int m = 0; m < kMaxMat; ++m) f[m] = m == mat ? 1.0 : 0.0;
@@ -1118,9 +1129,12 @@ static FieldSet field_set(const Problem &P)
 {
     FieldSet F;
     F.n = P.n_fields;
+    F.nshell = P.n_shells;
     for (int r = 0; r < kMaxFields; ++r) {
         for (int q = 0; q < 4; ++q) F.par[r][q] = P.field_par[r][q];
         F.mat[r] = P.field_mat[r];
+        for (int q = 0; q < 5; ++q) F.shell[r][q] = P.shell_par[r][q];
+        F.shell_mat[r] = P.shell_mat[r];
     }
     return F;
 }
@@ -1168,15 +1182,15 @@ hipError_t launch_integrate2d(Problem &P, hipStream_t s)
     dim3 grid((unsigned)P.n);
     switch (P.rk_order) {
     case 0:
-        e = launch_integ<0>(integrate2d_kernel<0, false>, integrate2d_kernel<0, true>, P.n_fields > 0, grid, shmem, g, s);
+        e = launch_integ<0>(integrate2d_kernel<0, false>, integrate2d_kernel<0, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
         if (e != hipSuccess) return e;
         break;
     case 1:
-        e = launch_integ<1>(integrate2d_kernel<1, false>, integrate2d_kernel<1, true>, P.n_fields > 0, grid, shmem, g, s);
+        e = launch_integ<1>(integrate2d_kernel<1, false>, integrate2d_kernel<1, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
         if (e != hipSuccess) return e;
         break;
     default:
-        e = launch_integ<2>(integrate2d_kernel<2, false>, integrate2d_kernel<2, true>, P.n_fields > 0, grid, shmem, g, s);
+        e = launch_integ<2>(integrate2d_kernel<2, false>, integrate2d_kernel<2, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
         if (e != hipSuccess) return e;
         break;
     }
@@ -1225,15 +1239,15 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
     dim3 grid((unsigned)P.n);
     switch (P.rk_order) {
     case 0:
-        e = launch_integ<0>(integrate3d_kernel<0, false>, integrate3d_kernel<0, true>, P.n_fields > 0, grid, shmem, g, s);
+        e = launch_integ<0>(integrate3d_kernel<0, false>, integrate3d_kernel<0, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
         if (e != hipSuccess) return e;
         break;
     case 1:
-        e = launch_integ<1>(integrate3d_kernel<1, false>, integrate3d_kernel<1, true>, P.n_fields > 0, grid, shmem, g, s);
+        e = launch_integ<1>(integrate3d_kernel<1, false>, integrate3d_kernel<1, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
         if (e != hipSuccess) return e;
         break;
     default:
-        e = launch_integ<2>(integrate3d_kernel<2, false>, integrate3d_kernel<2, true>, P.n_fields > 0, grid, shmem, g, s);
+        e = launch_integ<2>(integrate3d_kernel<2, false>, integrate3d_kernel<2, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
         if (e != hipSuccess) return e;
         break;
     }

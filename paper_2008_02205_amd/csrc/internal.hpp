@@ -144,6 +144,9 @@ struct Problem {
     int n_fields = 0;                          // smooth material fields (mlpg_material_fields)
     double field_par[kMaxFields][4] = {};      // a, b, k, phase
     int field_mat[kMaxFields] = {};
+    int n_shells = 0;                          // shells (mlpg_material_shells)
+    double shell_par[kMaxFields][5] = {};      // centre (dim), inner and outer radius
+    int shell_mat[kMaxFields] = {};
 
     DevBuf<double> x, R;
     DevBuf<int64_t> nb_off;

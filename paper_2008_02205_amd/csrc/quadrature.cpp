@@ -254,3 +254,79 @@ extern "C" int mlpg_angular_quadrature(int dim, int n_ord, int kind, double *ome
     mlpg::set_error("mlpg_angular_quadrature: unsupported dim/kind");
     return MLPG_ERR_ARG;
 }
+
+namespace mlpg {
+namespace {
+
+// Does the ray from src along the plane direction (cos phi, sin phi) meet the
+// disk (center, radius)?  (A source inside the disk sees it in every direction.)
+bool ray_hits_disk(const double *src, const double *center, double radius, double phi)
+{
+    const double dx = center[0] - src[0], dy = center[1] - src[1];
+    const double d2 = dx * dx + dy * dy;
+    if (d2 <= radius * radius) return true;
+    const double t = dx * std::cos(phi) + dy * std::sin(phi);   // distance to the closest approach
+    if (t <= 0.0) return false;
+    return d2 - t * t <= radius * radius;
+}
+
+// Sectors kept for one polar level, in increasing azimuth: (level, index).
+// Top-down: a sector of level >= min_level whose goal subsectors all miss the
+// object is kept whole; otherwise its two halves are examined, down to the
+// goal level, where a sector is always kept.
+void refine_sectors(int level, long k, int min_level, int goal_level, const std::vector<char> &hit,
+                    std::vector<std::pair<int, long>> &out)
+{
+    const long span = 1L << (goal_level - level);
+    if (level >= min_level) {
+        bool any = false;
+        for (long c = k * span; c < (k + 1) * span && !any; ++c) any = hit[c] != 0;
+        if (!any || level == goal_level) {
+            out.emplace_back(level, k);
+            return;
+        }
+    }
+    refine_sectors(level + 1, 2 * k, min_level, goal_level, hit, out);
+    refine_sectors(level + 1, 2 * k + 1, min_level, goal_level, hit, out);
+}
+
+}  // namespace
+}  // namespace mlpg
+
+extern "C" int mlpg_refined_quadrature(int min_level, int goal_level, const double *src, const double *center,
+                                       double radius, int cap, double *omega, double *w)
+{
+    using namespace mlpg;
+    MLPG_CHECK(min_level >= 0 && goal_level >= min_level && goal_level <= 12, MLPG_ERR_ARG,
+               "mlpg_refined_quadrature: need 0 <= min_level <= goal_level <= 12");
+    MLPG_CHECK(src && center && radius >= 0.0, MLPG_ERR_ARG, "mlpg_refined_quadrature: null point or negative radius");
+    MLPG_CHECK(cap >= 0, MLPG_ERR_ARG, "mlpg_refined_quadrature: negative capacity");
+    const long ng = 4L << goal_level;   // goal sectors per polar level
+    std::vector<char> hit(ng);
+    for (long c = 0; c < ng; ++c) hit[c] = ray_hits_disk(src, center, radius, 2.0 * M_PI * (c + 0.5) / ng) ? 1 : 0;
+    std::vector<std::pair<int, long>> sec;
+    for (long k = 0; k < 4; ++k) refine_sectors(0, k, min_level, goal_level, hit, sec);
+    const int count = 2 * (int)sec.size();
+    if (cap == 0) return count;
+    MLPG_CHECK(omega && w, MLPG_ERR_ARG, "mlpg_refined_quadrature: null output");
+    if (cap < count) {
+        set_error("mlpg_refined_quadrature: " + std::to_string(count) + " ordinates exceed the capacity");
+        return MLPG_ERR_CAPACITY;
+    }
+    double xg[4], wg[4];
+    gauss_legendre(4, xg, wg);
+    const double xi[2] = {xg[2], xg[3]}, wp[2] = {wg[2], wg[3]};
+    int m = 0;
+    for (int p = 0; p < 2; ++p) {
+        const double st = std::sqrt(1.0 - xi[p] * xi[p]);
+        for (const auto &e : sec) {
+            const double na = (double)(4L << e.first);
+            const double mid = (2.0 * (e.second + 1) - 1.0) * M_PI / na;
+            omega[2 * m] = st * std::cos(mid);
+            omega[2 * m + 1] = st * std::sin(mid);
+            w[m] = 2.0 * wp[p] * (2.0 * M_PI / na);
+            ++m;
+        }
+    }
+    return count;
+}

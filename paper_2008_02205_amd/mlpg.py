@@ -27,7 +27,8 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_boundary_points", "mlpg_integrate", "mlpg_get_pattern", "mlpg_get_blocks", "mlpg_assemble",
            "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
            "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress",
-           "mlpg_material_fields"]
+           "mlpg_material_fields", "mlpg_update_points", "mlpg_refined_quadrature",
+           "mlpg_material_shells"]
 
 
 class MlpgError(RuntimeError):
@@ -78,6 +79,9 @@ def lib() -> C.CDLL:
         L.mlpg_boundary_points.argtypes = [vp, vp, vp, vp]
         L.mlpg_integrate.argtypes = [vp, i32, vp]
         L.mlpg_material_fields.argtypes = [vp, i32, vp, vp]
+        L.mlpg_material_shells.argtypes = [vp, i32, vp, vp, vp]
+        L.mlpg_update_points.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mlpg_refined_quadrature.argtypes = [i32, i32, vp, vp, dbl, i32, vp, vp]
         L.mlpg_get_pattern.argtypes = [vp, vp, vp, vp]
         L.mlpg_get_blocks.argtypes = [vp, vp, vp, vp]
         L.mlpg_assemble.argtypes = [vp, i32, vp, vp, i32, vp, vp, dbl, vp, i32, vp]
@@ -184,6 +188,39 @@ def mlpg_material_fields(h, fields=()):
     else:
         par = mat = None
     _check(lib().mlpg_material_fields(h, len(fields), _host(par), _host(mat)))
+
+
+def mlpg_refined_quadrature(min_level, goal_level, src, center, radius):
+    """Alg. 2 refinement of the 2D product rule toward a disk seen from src (see the C declaration)."""
+    s = np.ascontiguousarray(src, dtype=np.float64)
+    c = np.ascontiguousarray(center, dtype=np.float64)
+    n = lib().mlpg_refined_quadrature(min_level, goal_level, _host(s), _host(c), float(radius), 0, None, None)
+    if n < 0:
+        _check(n)
+    om = np.zeros((n, 2))
+    w = np.zeros(n)
+    got = lib().mlpg_refined_quadrature(min_level, goal_level, _host(s), _host(c), float(radius), n, _host(om),
+                                        _host(w))
+    if got < 0:
+        _check(got)
+    return om, w
+
+
+def mlpg_material_shells(h, shells=()):
+    """Shells ``(centre, r_in, r_out, material)`` (see the C declaration)."""
+    if shells:
+        cen = np.ascontiguousarray([list(sh[0]) for sh in shells], dtype=np.float64)
+        rad = np.ascontiguousarray([[sh[1], sh[2]] for sh in shells], dtype=np.float64)
+        mat = np.ascontiguousarray([sh[3] for sh in shells], dtype=np.int32)
+    else:
+        cen = rad = mat = None
+    _check(lib().mlpg_material_shells(h, len(shells), _host(cen), _host(rad), _host(mat)))
+
+
+def mlpg_update_points(h, x, R, nbr_off, nbr_idx):
+    """New positions and radii for an existing handle (see the C declaration)."""
+    idx = nbr_idx if nbr_idx.numel() > 0 else _empty(1, _torch().int32)
+    _check(lib().mlpg_update_points(h, _dev(x), _dev(R), _dev(nbr_off), _dev(idx), _stream()))
 
 
 def mlpg_get_info(h) -> dict:

@@ -12,7 +12,7 @@ from . import mlpg as api
 
 
 class GpuProblem:
-    def __init__(self, x: np.ndarray, R: np.ndarray, dom_lo, dom_hi, regions=(), fields=()):
+    def __init__(self, x: np.ndarray, R: np.ndarray, dom_lo, dom_hi, regions=(), fields=(), shells=()):
         self.dim = x.shape[1]
         self.x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
         self.R = torch.from_numpy(np.ascontiguousarray(R, dtype=np.float64)).cuda()
@@ -21,9 +21,21 @@ class GpuProblem:
         self.h = api.mlpg_geometry(self.x, self.R, self.nbr_off, self.nbr_idx, dom_lo, dom_hi, regions)
         if fields:
             api.mlpg_material_fields(self.h, fields)
+        if shells:
+            api.mlpg_material_shells(self.h, shells)
         self.info = api.mlpg_get_info(self.h)
         self.n = self.info["n"]
         self.M = 0
+
+    def move(self, x: np.ndarray, R: np.ndarray):
+        """New point positions and radii (same count): neighbour lists and cells
+        are rebuilt; integrate and assemble again before the next step."""
+        self.x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+        self.R = torch.from_numpy(np.ascontiguousarray(R, dtype=np.float64)).cuda()
+        self.nbr_off, total = api.mlpg_neighbors_count(self.x, self.R)
+        self.nbr_idx = api.mlpg_neighbors_fill(self.x, self.R, self.nbr_off, total)
+        api.mlpg_update_points(self.h, self.x, self.R, self.nbr_off, self.nbr_idx)
+        return self.refresh()
 
     def refresh(self):
         self.info = api.mlpg_get_info(self.h)

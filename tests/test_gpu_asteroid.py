@@ -1,0 +1,73 @@
+"""The asteroid problem of Sec. 5.4 at reduced size: shells of material, the refined quadrature of
+Alg. 2 and a small source, the HIP path against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests._cases import FP64_TOL, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+MIXED_TOL = 1e-8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_02205_amd import mlpg
+    mlpg.lib()
+
+
+def _cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def test_shell_blocks_match_oracle():
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    a = W.asteroid(0.1)
+    x, R, dx = W.asteroid_points(a, 0.3)
+    shells, st, ss = W.asteroid_materials(a)
+    print(f"[case] asteroid shell blocks n={x.shape[0]}", flush=True)
+    g = oracle.geometry(x, R, a.lo, a.hi)
+    it = oracle.integrate(g, 1, n_mat=2, shells=shells)
+    P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
+    info = P.integrate(1)
+    assert info["n_mat"] == 2
+    blocks = _cpu(mlpg.mlpg_get_blocks(P.h, info["n_blocks"], info["nnz"])[0])
+    for b, name in enumerate(oracle.block_names(2, 2)):
+        ref = it.blocks[b]
+        assert np.abs(blocks[b] - ref).max() <= 1e-12 * np.abs(ref).max(), name
+    assert np.abs(it.blocks[3]).max() > 0          # the shell is seen by some cell
+    P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_asteroid_solve_matches_oracle(precision):
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    a = W.asteroid(0.1)
+    x, R, dx = W.asteroid_points(a, 0.3)
+    shells, st, ss = W.asteroid_materials(a)
+    print(f"[case] asteroid solve n={x.shape[0]} {precision}", flush=True)
+    om_o, w_o = oracle.refined_quadrature(0, 5, a.src, (0.0, 0.0), a.radius)
+    om_g, w_g = mlpg.mlpg_refined_quadrature(0, 5, a.src, (0.0, 0.0), a.radius)
+    g = oracle.geometry(x, R, a.lo, a.hi)
+    it = oracle.integrate(g, 1, n_mat=2, shells=shells)
+    tr = oracle.Transport(it, om_o, w_o, st, ss, 0.0, dx)
+    psi_o, phi_o, _ = tr.step(None, W.asteroid_source(a, x, om_o.shape[0]))
+    P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
+    P.integrate(1)
+    P.assemble(om_g, w_g, list(st), list(ss), 0.0, dx,
+               precision=mlpg.MLPG_FP64 if precision == "fp64" else mlpg.MLPG_MIXED)
+    q = torch.from_numpy(np.ascontiguousarray(W.asteroid_source(a, x, om_g.shape[0]))).cuda()
+    phi, pv, psi, info = P.step(q)
+    assert info["converged"] == 1
+    e = (rel_l2(_cpu(phi), phi_o), rel_l2(_cpu(pv), tr.point_values(phi_o)), rel_l2(_cpu(psi), psi_o))
+    print(f"phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} ordinates {om_g.shape[0]}", flush=True)
+    assert max(e) <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
+    P.close()

@@ -120,3 +120,27 @@ def test_paper_mms_spatial_order_two(kind):
     errs, hs = zip(*[_mms_error(n, kind) for n in (8, 16, 32)])
     slope = np.polyfit(np.log(hs), np.log(errs), 1)[0]
     assert abs(slope - GOLD["mms_spatial_order_linear_rk"]) <= GOLD["order_tolerance"], (errs, slope)
+
+
+# --------------------------------------------------------------------- shells
+def test_shells_cover_everything_or_nothing():
+    """A shell containing the whole domain moves every block to its material; one outside changes nothing."""
+    x, dx, g = _geom(8)
+    ref = oracle.integrate(g, 1, n_mat=2)
+    full = oracle.integrate(g, 1, n_mat=2, shells=(((0.1, -0.2), 0.0, 10.0, 1),))
+    none = oracle.integrate(g, 1, n_mat=2, shells=(((0.1, -0.2), 5.0, 10.0, 1),))
+    assert np.array_equal(full.blocks[3:6], ref.blocks[0:3]) and not np.any(full.blocks[0:3])
+    assert np.array_equal(none.blocks, ref.blocks)
+
+
+def test_shell_area_converges_and_boxes_come_first():
+    """sum_ij Mass_g over an annulus tends to its area; a shell overrides a box that covers the domain."""
+    c, r0, r1 = (0.13, -0.07), 0.35, 0.8
+    exact = math.pi * (r1 * r1 - r0 * r0)
+    errs = []
+    for n in (8, 16, 32):
+        x, dx, g = _geom(n)
+        it = oracle.integrate(g, 1, n_mat=2, regions=(((-1.0, -1.0), (1.0, 1.0), 1),), shells=((c, r0, r1, 0),))
+        errs.append(abs(it.blocks[0].sum() - exact) / exact)
+        assert abs(it.blocks[0].sum() + it.blocks[3].sum() - 4.0) <= 1e-12
+    assert errs[2] < errs[1] < errs[0] and errs[2] <= 2e-3, errs

@@ -248,6 +248,7 @@ class Workload:
     pd_radius: float = 0.0           # Poisson-disk spacing when counts is None
     fields: tuple = ()               # smooth material fields (a, b, k, phase, material)
     t0: float = 0.0                  # time of the initial state (steady problems: time of the solution)
+    velocity: float = 0.0            # points move with the cellular flow of this amplitude (0: fixed)
 
     @property
     def inv_c_dt(self) -> float:
@@ -277,6 +278,13 @@ def config(k: int, scale: Optional[int] = None) -> Workload:
                         256, "beam-dense", (1e-4, 100.0), (0.0, 99.0),
                         (((1.0, 0.0), (2.0, 1.0), 1),), 10, 0.05, 1.0, "none", "beam",
                         SEED_BASE + 4, pd_radius=0.00438)
+    if k == 8:
+        # workload 2 with points that move every step (the cellular flow below),
+        # so that cells, integration and assembly are redone inside the time loop
+        n = scale or 128
+        return Workload("2d-mms-be20-moving", 2, (0.0, 0.0), (1.0, 1.0), (n, n), 0.2, 2.0, 1,
+                        64, "product", (1.0,), (0.5,), (), 20, 1e-2, 1.0, "mms-sin", "vacuum",
+                        SEED_BASE + 8, velocity=0.25)
     if k == 6:
         # Sec. 5.1 sinusoidal manufactured problem: uniform lattice on [-1, 1]^2,
         # varying opacities as material fields, steady (solution at t = 0)
@@ -300,6 +308,124 @@ def paper_mms_psi(w: Workload, x: np.ndarray, t: float) -> np.ndarray:
     if w.source == "paper-wave":
         return mms_wave_psi(x, t)
     raise ValueError(w.source)
+
+
+# ---------------------------------------------------------------------------
+# Asteroid problem (Sec. 5.4 and its appendix), 2D: an absorbing shell around
+# the origin lit by a small source in a thin background.  Lengths are scaled
+# by ``scale`` from the paper's (asteroid radius 35, source 70 from the
+# surface); the shell stays 20 mean free paths thick.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Asteroid:
+    radius: float            # outer radius of the asteroid
+    thickness: float         # shell thickness
+    sigma_shell: float
+    sigma_back: float
+    src: tuple               # source centre
+    src_radius: float        # radius of the small disk that stands in for the point source
+    strength: float          # emission per unit length of the source (isotropic)
+    lo: tuple
+    hi: tuple
+
+
+def asteroid(scale: float = 0.1) -> Asteroid:
+    R = 35.0 * scale
+    sig = 10.0 / scale                      # keeps 20 mean free paths in 2.0 * scale
+    return Asteroid(R, 2.0 * scale, sig, 0.001 / scale, (-(R + 70.0 * scale), 0.0), 1.0 * scale, 1.0,
+                    (-(R + 75.0 * scale), -(R + 5.0 * scale)), (R + 5.0 * scale, R + 5.0 * scale))
+
+
+def asteroid_source(a: Asteroid, x: np.ndarray, m: int) -> np.ndarray:
+    """Isotropic per-steradian source ``[N][M]``: the strength spread uniformly over the source disk."""
+    inside = np.sum((x - np.asarray(a.src)) ** 2, axis=1) <= a.src_radius ** 2
+    q = np.where(inside, a.strength / (4.0 * np.pi * np.pi * a.src_radius ** 2), 0.0)
+    return np.repeat(q[:, None], m, axis=1)
+
+
+def chord_in_circle(src: np.ndarray, xe: np.ndarray, radius: float) -> np.ndarray:
+    """Length of the segment src -> xe (per point) inside the circle |x| <= radius, from the
+    intercepts s = (-l1 +- sqrt(l1^2 - l0 l2)) / l2 of the parametric line x = src + (xe - src) s."""
+    d = xe - src[None, :]
+    l0 = src @ src - radius * radius
+    l1 = d @ src
+    l2 = np.sum(d * d, axis=1)
+    disc = l1 * l1 - l0 * l2
+    ok = (disc > 0.0) & (l2 > 0.0)
+    sq = np.sqrt(np.where(ok, disc, 0.0))
+    l2s = np.where(l2 > 0.0, l2, 1.0)
+    s0 = np.clip((-l1 - sq) / l2s, 0.0, 1.0)
+    s1 = np.clip((-l1 + sq) / l2s, 0.0, 1.0)
+    return np.where(ok, (s1 - s0) * np.sqrt(l2), 0.0)
+
+
+def asteroid_optical_depth(a: Asteroid, x: np.ndarray) -> np.ndarray:
+    """omega = integral of sigma_a from the source centre to each point (straight ray)."""
+    src = np.asarray(a.src, dtype=np.float64)
+    r = np.sqrt(np.sum((x - src[None, :]) ** 2, axis=1))
+    in_shell = chord_in_circle(src, x, a.radius) - chord_in_circle(src, x, a.radius - a.thickness)
+    return a.sigma_back * (r - in_shell) + a.sigma_shell * in_shell
+
+
+def asteroid_phi_paper(a: Asteroid, x: np.ndarray) -> np.ndarray:
+    """The appendix's scalar flux (1/r) [exp(-omega) - omega E1(omega)] of a unit line source."""
+    from scipy.special import exp1
+    r = np.sqrt(np.sum((x - np.asarray(a.src)[None, :]) ** 2, axis=1))
+    om = asteroid_optical_depth(a, x)
+    e1 = np.where(om > 0.0, exp1(np.maximum(om, 1e-300)), 0.0)
+    return (np.exp(-om) - om * e1) / r
+
+
+def asteroid_phi_ordinates(a: Asteroid, x: np.ndarray, xi: np.ndarray, wp: np.ndarray) -> np.ndarray:
+    """Scalar flux of a line source of the asteroid's strength seen through polar levels with cosines
+    xi and weights wp (folded: 2 wp each) and a continuum of azimuths: along the in-plane ray of length
+    r the path is r / sin(theta), so phi = S / (4 pi r) sum_p 2 wp_p exp(-omega / st_p) / st_p."""
+    r = np.sqrt(np.sum((x - np.asarray(a.src)[None, :]) ** 2, axis=1))
+    om = asteroid_optical_depth(a, x)
+    st = np.sqrt(1.0 - np.asarray(xi) ** 2)
+    tot = sum(2.0 * w * np.exp(-om / t) / t for w, t in zip(wp, st))
+    return a.strength / (4.0 * np.pi * r) * tot
+
+
+def asteroid_points(a: Asteroid, spacing: float, seed: int = SEED_BASE + 9, jitter: float = 0.2):
+    """Jittered lattice of the given spacing over the asteroid domain; returns (x, R, dx) with R = 2 dx."""
+    counts = [max(2, int(round((h - l) / spacing))) for l, h in zip(a.lo, a.hi)]
+    x, dx = jittered_lattice(counts, a.lo, a.hi, jitter, seed)
+    return x, np.full(x.shape[0], 2.0 * dx), dx
+
+
+def asteroid_materials(a: Asteroid):
+    """Shells ((centre, r_in, r_out, material),), sigma_t and sigma_s per material (no scattering)."""
+    return ((((0.0, 0.0), a.radius - a.thickness, a.radius, 1),), (a.sigma_back, a.sigma_shell), (0.0, 0.0))
+
+
+def asteroid_lit_region(a: Asteroid, x: np.ndarray, near: float) -> np.ndarray:
+    """Points in the background between the source and the asteroid, inside the cone of rays that
+    hit it and at least ``near`` from the source: where the refined ordinates resolve the flux."""
+    src = np.asarray(a.src)
+    d = np.linalg.norm(src)
+    v = x - src[None, :]
+    r = np.linalg.norm(v, axis=1)
+    ang = np.abs(np.arctan2(v[:, 1], v[:, 0]))
+    return (r >= near) & (ang <= math.asin(a.radius / d)) & (np.linalg.norm(x, axis=1) > a.radius + 2 * a.thickness) \
+        & (x[:, 0] < 0.0)
+
+
+def cellular_flow(x: np.ndarray, amplitude: float) -> np.ndarray:
+    """Divergence-free velocity U (sin(pi x) cos(pi y), -cos(pi x) sin(pi y)) on the unit square.
+
+    Its normal component vanishes on the boundary, so points stay inside and
+    their density stays uniform while the lattice shears."""
+    u = np.empty_like(x)
+    u[:, 0] = amplitude * np.sin(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1])
+    u[:, 1] = -amplitude * np.cos(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])
+    return u
+
+
+def advect_points(w: Workload, x: np.ndarray, dt: float) -> np.ndarray:
+    """Positions after one step of the workload's point motion (explicit Euler)."""
+    return x + dt * cellular_flow(x, w.velocity)
 
 
 def points_for(w: Workload) -> tuple[np.ndarray, float]:
