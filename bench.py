@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--max-outer", type=int, default=None,
                     help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
     ap.add_argument("--max-inner", type=int, default=None, help="inner-iteration cap per solve (--workload mode)")
+    ap.add_argument("--accel", action="store_true",
+                    help="workload and serving modes: diffusion-synthetic acceleration of the outer iteration")
     ap.add_argument("--probe", action="store_true",
                     help="hardware-counter probe: setup, one short solve of the workload and a 256 MiB "
                          "device copy (the reference for counter scaling); prints nothing")
@@ -276,6 +278,8 @@ def other_workload(args):
         its = solves = outer = 0
         conv = True
         opts = mlpg.mlpg_default_opts()
+        if args.accel:
+            opts.accel = mlpg.MLPG_ACCEL_DSA
         if args.max_outer:
             opts.max_outer = args.max_outer
         if args.max_inner:
@@ -340,7 +344,7 @@ def other_workload(args):
            "dtype": "f64" if main_p == "fp64" else "f32+f64", "data": "synthetic",
            "config": {"workload": f"{w.name}: {n} points, {M} ordinates, rk order {w.rk_order}, "
                                   f"{'steady' if w.steps == 0 else f'{steps} BE steps'}", "points": n,
-                      "ordinates": M, "dim": w.dim},
+                      "ordinates": M, "dim": w.dim, "accel": "dsa" if args.accel else "none"},
            "detail": out}
     print(json.dumps(rec), flush=True)
 
@@ -380,6 +384,8 @@ def asteroid_workload(args):
         opts = mlpg.mlpg_default_opts()
         if args.max_inner:
             opts.max_inner = args.max_inner
+        if args.accel:
+            opts.accel = mlpg.MLPG_ACCEL_DSA
         _, pv, _, inf = mlpg.mlpg_solve(P.h, q, None, opts, want_psi=False, raise_on_error=False)
         t4 = sync_time()
         pv = pv.cpu().numpy()
@@ -410,7 +416,7 @@ def asteroid_workload(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "dtype": "f64" if main_p == "fp64" else "f32+f64", "data": "synthetic",
            "config": {"workload": f"asteroid (lengths x0.1): {n} points, {M} refined ordinates, steady",
-                      "points": n, "ordinates": M, "dim": 2},
+                      "points": n, "ordinates": M, "dim": 2, "accel": "dsa" if args.accel else "none"},
            "detail": out}
     print(json.dumps(rec), flush=True)
 
@@ -427,7 +433,11 @@ def serve(args):
 
     specs = W.request_stream(args.serving)
     t0 = time.perf_counter()
-    res = Server(slots=args.slots).run(specs, build, realtime=True, keep_fields=False)
+    opts = None
+    if args.accel:
+        opts = mlpg.mlpg_default_opts()
+        opts.accel = mlpg.MLPG_ACCEL_DSA
+    res = Server(slots=args.slots, opts=opts).run(specs, build, realtime=True, keep_fields=False)
     el = time.perf_counter() - t0
     summ = latency_summary(res)
     its = sum(r.info["inner_iters"] * r_spec.side ** 2 for r, r_spec in zip(res, specs) if r.info)
@@ -435,7 +445,7 @@ def serve(args):
            "higher_is_better": False, "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": f"request stream: {args.serving} steady 2D problems, Poisson arrivals at 50/s, "
                                   f"N log-uniform in [1024, 65536], M in {{16,32,64,128}}, mixed precision",
-                      "slots": args.slots},
+                      "slots": args.slots, "accel": "dsa" if args.accel else "none"},
            "serving": summ, "offered_req_s": len(specs) / specs[-1].arrival,
            "DOF*ord*iter_per_s": its / el, "wall_s": el}
     print(json.dumps(rec), flush=True)

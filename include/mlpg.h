@@ -306,7 +306,9 @@ int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *strea
  * ---------------------------------------------------------------------- */
 typedef struct {
     double tol_inner;     /* ||f - L_m x|| <= tol ||f|| per ordinate (default 1e-13) */
-    double tol_outer;     /* outer relative residual (default 1e-12) */
+    double tol_outer;     /* outer relative residual (default 1e-12; MLPG_MIXED stops at 1e-10 at the
+                             tightest: its inner solves make the outer operator linear only to about
+                             tol_inner / (1 - c)) */
     int restart_inner;    /* GMRES restart length, <= 30 (default 30) */
     int restart_outer;    /* <= 30 (default 30) */
     int max_inner;        /* Arnoldi steps per ordinate per solve (default 3000) */
@@ -315,7 +317,25 @@ typedef struct {
     double tol_inner_lo;  /* MLPG_MIXED: FP32 correction solves stop at this relative residual, or earlier
                              for an ordinate whose remaining gap to tol_inner is smaller (default 3e-5) */
     int max_refine;       /* MLPG_MIXED: FP64 refinement steps per inner solve (default 12) */
+    int accel;            /* outer iteration: MLPG_ACCEL_NONE (default) or MLPG_ACCEL_DSA, a
+                             diffusion-synthetic right preconditioner (see below) */
 } mlpg_solve_opts;
+
+/* Acceleration of the scattering iteration (Sec. 6 names it as needed for
+ * scattering-dominated problems; Sec. 4.2 runs the outer GMRES without a
+ * preconditioner).  MLPG_ACCEL_DSA preconditions the outer GMRES on
+ * (I - D L^-1 MS) Phi = b from the right with
+ *   P^-1 v = v + C^-1 (Ms v),
+ * where, on the same pattern and with the same test functions,
+ *   C[i,j]  = (1 / (3 sigma_t,i)) sum_a K^aa[i,j] + sum_g sigma_a,g Mass_g[i,j] + 1/2 sum_f S_f[i,j]
+ *   Ms[i,j] = sum_g sigma_s,g Mass_g[i,j]
+ * is the diffusion approximation of the scattering correction (Marshak
+ * vacuum terms on the domain faces); sigma_a,g = sigma_t,g - sigma_s,g +
+ * 1/(c dt), and sigma_t,i is point i's mass-weighted mean of sigma_t,g +
+ * 1/(c dt).  C x = r is solved by GMRES with point Jacobi to 1e-12, so P is a
+ * fixed operator: the converged Phi is the same as without acceleration, and
+ * the outer iteration count drops where scattering dominates. */
+enum { MLPG_ACCEL_NONE = 0, MLPG_ACCEL_DSA = 1 };
 
 typedef struct {
     int outer_iters;
@@ -328,6 +348,7 @@ typedef struct {
     int refinements;             /* MLPG_MIXED: FP64 refinement steps summed over inner solves */
     int fp64_completions;        /* MLPG_MIXED: inner solves finished in FP64 after the FP32
                                     corrections stagnated or the refinement budget was spent */
+    int64_t accel_iters;         /* MLPG_ACCEL_DSA: Arnoldi steps of the diffusion solves */
 } mlpg_solve_info;
 
 void mlpg_default_opts(mlpg_solve_opts *o);

@@ -26,6 +26,8 @@ void Problem::release()
     inner.release(); outer.release(); inner32.release();
     sL32.release(); coefL32.release(); coefF32.release(); surf_val32.release(); dinv32.release(); r32.release();
     d32.release(); mr.release(); rn2.release(); fn2.release(); tolv.release();
+    dsaC.release(); dsaMs.release(); dsa_dinv.release(); dsa_r.release(); dsa_x.release(); dsa_t.release();
+    dsa.release();
 }
 
 namespace {
@@ -77,7 +79,7 @@ int op_L32(Problem &P, const OpCallT<float> &c, hipStream_t s, void *)
 
 struct SolveCounters {
     const mlpg_solve_opts *o;
-    int64_t its = 0, sweeps = 0, refinements = 0, fp64_completions = 0;
+    int64_t its = 0, sweeps = 0, refinements = 0, fp64_completions = 0, accel_its = 0;
     double res_max = 0.0;
     bool conv = true;
     int solves = 0;
@@ -189,6 +191,46 @@ int op_outer(Problem &P, const OpCall &oc, hipStream_t s, void *vctx)
     int rc = inner_solve(P, c, P.t1.p, P.t2.p, s);
     if (rc) return rc;
     MLPG_HIP(launch_ord_reduce(P, P.t2.p, oc.out, oc.in, -1.0, s));
+    return MLPG_OK;
+}
+
+// The diffusion operator C of the synthetic acceleration, with point Jacobi
+// from the right (gmres passes dinv).
+int op_dsa(Problem &P, const OpCall &c, hipStream_t s, void *)
+{
+    MLPG_HIP(launch_csr_spmv(P, P.dsaC.p, c.in, c.dinv, c.out, c.gate, s));
+    return MLPG_OK;
+}
+
+// out = P^-1 v = v + C^-1 (Ms v); C is solved to 1e-12 so that P is a fixed
+// operator for the outer GMRES.
+int dsa_apply(Problem &P, SolveCounters &c, const double *v, double *out, hipStream_t s)
+{
+    MLPG_HIP(launch_csr_spmv(P, P.dsaMs.p, v, nullptr, P.dsa_r.p, nullptr, s));
+    int64_t sweeps = 0;
+    double rm = 0.0;
+    bool conv = true;
+    int rc = gmres_batched<double>(P, P.dsa, op_dsa, false, nullptr, P.dsa_dinv.p, P.dsa_r.p, P.dsa_x.p, P.n, 1,
+                                   1e-12, kMaxRestart, 20000, 1, true, s, &c.accel_its, &sweeps, &rm, &conv,
+                                   nullptr, true);
+    if (rc) return rc;
+    c.conv = c.conv && conv;
+    MLPG_HIP(launch_add(out, v, P.dsa_x.p, P.n, s));
+    return MLPG_OK;
+}
+
+// The outer operator preconditioned from the right: (I - D L^-1 MS) P^-1 v.
+int op_outer_dsa(Problem &P, const OpCall &oc, hipStream_t s, void *vctx)
+{
+    SolveCounters &c = *(SolveCounters *)vctx;
+    int rc = dsa_apply(P, c, oc.in, P.dsa_t.p, s);
+    if (rc) return rc;
+    SpmvArgs a;
+    a.vals = P.sMS.p; a.ns = P.nsMD; a.coef = P.coefMD.p; a.x = P.dsa_t.p; a.x_bcast = 1; a.y = P.t1.p;
+    MLPG_HIP(launch_spmv(P, a, s));
+    rc = inner_solve(P, c, P.t1.p, P.t2.p, s);
+    if (rc) return rc;
+    MLPG_HIP(launch_ord_reduce(P, P.t2.p, oc.out, P.dsa_t.p, -1.0, s));
     return MLPG_OK;
 }
 
@@ -591,6 +633,22 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
     MLPG_HIP(P->sMD.alloc((size_t)P->nnz * P->nsMD));
     MLPG_HIP(P->sMS.alloc((size_t)P->nnz * P->nsMD));
     MLPG_HIP(launch_assemble(*P, sigma_t, sigma_s, tau, s));
+    {
+        // operators of the diffusion-synthetic acceleration (two values per pattern entry)
+        std::vector<double> st(P->n_mat), sa(P->n_mat), ss(P->n_mat);
+        for (int g = 0; g < P->n_mat; ++g) {
+            st[g] = sigma_t[g] + inv_c_dt;
+            sa[g] = sigma_t[g] - sigma_s[g] + inv_c_dt;
+            ss[g] = sigma_s[g];
+        }
+        MLPG_HIP(P->dsaC.alloc(P->nnz));
+        MLPG_HIP(P->dsaMs.alloc(P->nnz));
+        MLPG_HIP(P->dsa_dinv.alloc(P->n));
+        MLPG_HIP(P->dsa_r.alloc(P->n));
+        MLPG_HIP(P->dsa_x.alloc(P->n));
+        MLPG_HIP(P->dsa_t.alloc(P->n));
+        MLPG_HIP(launch_dsa_assemble(*P, st.data(), sa.data(), ss.data(), s));
+    }
     // per-ordinate coefficient tables
     std::vector<double> cL((size_t)n_ord * P->nsL), cMD((size_t)n_ord * P->nsMD), cF((size_t)n_ord * P->nfaces);
     for (int m = 0; m < n_ord; ++m) {
@@ -707,6 +765,7 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->check_every = 3;
     o->tol_inner_lo = 3e-5;
     o->max_refine = 12;
+    o->accel = MLPG_ACCEL_NONE;
 }
 
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)
@@ -757,6 +816,8 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1 && o.max_refine >= 0, MLPG_ERR_ARG,
                "mlpg_solve: iteration limits must be positive");
     MLPG_CHECK(P_ok_lo(o), MLPG_ERR_ARG, "mlpg_solve: tol_inner_lo must be in (0, 1)");
+    MLPG_CHECK(o.accel == MLPG_ACCEL_NONE || o.accel == MLPG_ACCEL_DSA, MLPG_ERR_ARG,
+               "mlpg_solve: accel must be MLPG_ACCEL_NONE or MLPG_ACCEL_DSA");
     Problem *P = h;
     hipStream_t s = S(stream);
     const int64_t n = P->n;
@@ -775,13 +836,30 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     rc = inner_solve(*P, c, P->F.p, P->bpsi.p, s);
     if (rc) return rc;
     MLPG_HIP(launch_ord_reduce(*P, P->bpsi.p, P->bphi.p, nullptr, 1.0, s));
-    // outer GMRES on (I - D L^-1 MS) Phi = b_phi from the previous Phi
+    // outer GMRES on (I - D L^-1 MS) Phi = b_phi from the previous Phi.  With
+    // FP32 inner corrections the outer operator is linear only to about the
+    // inner tolerance times 1/(1 - c), so the mixed path stops the outer
+    // iteration at 1e-10 at the tightest (far inside its 1e-8 bar on Phi).
+    const double tol_outer = P->precision == MLPG_MIXED ? std::max(o.tol_outer, kMixedOuterFloor) : o.tol_outer;
     int64_t oits = 0, osweeps = 0;
     double ores = 0.0;
     bool oconv = true;
-    rc = gmres_batched<double>(*P, P->outer, op_outer, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1, o.tol_outer,
-                       o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits, &osweeps, &ores, &oconv);
-    if (rc) return rc;
+    if (o.accel == MLPG_ACCEL_DSA) {
+        // right-preconditioned: GMRES for u with (I - D L^-1 MS) P^-1 u = b_phi, then Phi = P^-1 u
+        // (the previous Phi serves as the first u)
+        rc = gmres_batched<double>(*P, P->outer, op_outer_dsa, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1,
+                                   tol_outer, o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits,
+                                   &osweeps, &ores, &oconv);
+        if (rc) return rc;
+        rc = dsa_apply(*P, c, P->phi.p, P->dsa_t.p, s);
+        if (rc) return rc;
+        MLPG_HIP(hipMemcpyAsync(P->phi.p, P->dsa_t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    } else {
+        rc = gmres_batched<double>(*P, P->outer, op_outer, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1,
+                                   tol_outer, o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits,
+                                   &osweeps, &ores, &oconv);
+        if (rc) return rc;
+    }
     // recovery Psi = L^-1 MS Phi + b_psi
     {
         SpmvArgs a;
@@ -804,6 +882,7 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
         info->converged = (c.conv && oconv) ? 1 : 0;
         info->refinements = (int)c.refinements;
         info->fp64_completions = (int)c.fp64_completions;
+        info->accel_iters = c.accel_its;
     }
     if (!(c.conv && oconv)) {
         set_error("mlpg_solve: a Krylov solve reached its iteration limit");

@@ -30,6 +30,7 @@ constexpr int kCandMax3D = 512;    // functions possibly active on one 3D cell
 constexpr int kMaxRestart = 30;
 constexpr int kMaxFields = 8;    // smooth material fields per problem
 constexpr int kMaxMat = 8;       // materials per problem
+constexpr double kMixedOuterFloor = 1e-10;   // tightest outer tolerance of the mixed path
 constexpr int kTagBox = -100;      // edge of the kernel box not on the domain
 
 // Thread-local error message for mlpg_last_error.
@@ -205,6 +206,10 @@ struct Problem {
     // values and Jacobi scaling; refinement scratch
     DevBuf<float> sL32, coefL32, coefF32, surf_val32, dinv32, r32, d32;
     DevBuf<double> mr, rn2, fn2, tolv;
+    // diffusion-synthetic acceleration of the outer iteration: C, Ms on the
+    // pattern, 1/diag(C), and the diffusion solve's workspace
+    DevBuf<double> dsaC, dsaMs, dsa_dinv, dsa_r, dsa_x, dsa_t;
+    Krylov dsa;
     int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
 
     void release();
@@ -236,6 +241,13 @@ hipError_t launch_assemble(Problem &P, const double *sig_t, const double *sig_s,
 hipError_t launch_surface_count(Problem &P, int64_t *counts, hipStream_t s);
 hipError_t launch_surface_fill(Problem &P, const double *omega_unused, hipStream_t s);
 hipError_t launch_jacobi(Problem &P, hipStream_t s);
+// C and Ms of the diffusion-synthetic preconditioner (mlpg_solve_opts.accel);
+// sig_*: host [n_mat] effective cross sections (a0 included in sig_t, sig_a)
+hipError_t launch_dsa_assemble(Problem &P, const double *sig_t_eff, const double *sig_a_eff, const double *sig_s,
+                               hipStream_t s);
+// y = A (dinv .* x) for one vector over the pattern (dinv may be NULL; gate as in the solvers)
+hipError_t launch_csr_spmv(Problem &P, const double *vals, const double *x, const double *dinv, double *y,
+                           const int *gate, hipStream_t s);
 
 // y[i][m] = sum_p (sum_b coef[m][b] vals[p][b]) * xin[col[p]][m]  (+ surface part)
 // with xin = xs*x + x2, optional right preconditioner dinv and per-ordinate
@@ -297,7 +309,7 @@ template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged,
-                  const double *tolv = nullptr);   // optional per-system relative tolerance (device [nb])
+                  const double *tolv = nullptr, bool cheap_op = false);   // optional per-system relative tolerance (device [nb])
 // out[m] = sum_i x[i][m]^2 for the nb systems of K's shape
 hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s);
 

@@ -498,17 +498,22 @@ __global__ void lsq_kernel(int nb, int k, const double *__restrict__ H, const do
     }
 }
 
-// x += dinv .* (V y)
+// x += dinv .* (V y) over each system's own columns: the basis slots of
+// steps that ran after the last system stopped (their kernels returned at the
+// gate) were never written and may hold any bit pattern, so they are not
+// read even with a zero coefficient (0 * NaN is NaN).
 template <class T>
 __global__ __launch_bounds__(kThreads) void x_update_kernel(int64_t n, int nb, int nq, const T *__restrict__ V,
                                                             int64_t vstride, const double *__restrict__ y,
+                                                            const int *__restrict__ jend,
                                                             const T *__restrict__ dinv, T *__restrict__ x)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * nb) return;
     int m = (int)(t % nb);
+    const int je = jend[m] < nq ? jend[m] : nq;
     double s = 0.0;
-    for (int q = 0; q < nq; ++q) s += y[q * nb + m] * (double)V[q * vstride + t];
+    for (int q = 0; q < je; ++q) s += y[q * nb + m] * (double)V[q * vstride + t];
     x[t] = (T)((double)x[t] + (dinv ? (double)dinv[t] * s : s));
 }
 
@@ -691,7 +696,8 @@ void KrylovT<T>::release()
 template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
-                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged, const double *tolv)
+                  int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged, const double *tolv,
+                  bool cheap_op)
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
@@ -702,7 +708,9 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     const int64_t cnt = n * nb;
     const int nbt = ((nb + 63) / 64) * 64;
     const unsigned small_blocks = (unsigned)((nb + kGroupsPerBlock - 1) / kGroupsPerBlock);
-    const bool precheck = !fused;   // the operator without fused normalisation is the outer one
+    // the outer operator (each application a full set of inner solves) is
+    // tested before it is applied; a cheap unfused operator is not
+    const bool precheck = !fused && !cheap_op;
     int *nact = K.nactive.p;   // three rotating active counters (gates)
     // ||f||
     MLPG_HIP(norm2<T>(K, f, K.beta.p, s));
@@ -801,7 +809,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                 max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nact + ((k + 1) % 3), nullptr);
         }
         lsq_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
-        x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, dinv, x);
+        x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, dinv, x);
         OpCallT<T> c;
         c.in = x;
         c.out = K.r.p;
@@ -828,7 +836,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     *sweeps += sw;
     if (rm > *res_max) *res_max = rm;
     *converged = *converged && ok;
-    report_progress(nb == 1 ? 1 : 0, tot, rm);
+    if (!cheap_op) report_progress(nb == 1 ? 1 : 0, tot, rm);
     return MLPG_OK;
 }
 
@@ -841,9 +849,9 @@ template struct KrylovT<double>;
 template struct KrylovT<float>;
 template int gmres_batched<double>(Problem &, KrylovT<double> &, OpFnT<double>, bool, void *, const double *,
                                    const double *, double *, int64_t, int, double, int, int, int, bool, hipStream_t,
-                                   int64_t *, int64_t *, double *, bool *, const double *);
+                                   int64_t *, int64_t *, double *, bool *, const double *, bool);
 template int gmres_batched<float>(Problem &, KrylovT<float> &, OpFnT<float>, bool, void *, const float *,
                                   const float *, float *, int64_t, int, double, int, int, int, bool, hipStream_t,
-                                  int64_t *, int64_t *, double *, bool *, const double *);
+                                  int64_t *, int64_t *, double *, bool *, const double *, bool);
 
 }  // namespace mlpg

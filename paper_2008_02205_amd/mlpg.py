@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmlpg.so")
 MLPG_FP64, MLPG_MIXED = 0, 1
 MLPG_QUAD_PRODUCT, MLPG_QUAD_BEAM_DENSE = 0, 1
 MLPG_OP_L, MLPG_OP_T, MLPG_OP_MS, MLPG_OP_SRC = 0, 1, 2, 3
+MLPG_ACCEL_NONE, MLPG_ACCEL_DSA = 0, 1
 STATUS = {0: "MLPG_OK", -1: "MLPG_ERR_ARG", -2: "MLPG_ERR_HIP", -3: "MLPG_ERR_CAPACITY",
           -4: "MLPG_ERR_NOT_CONVERGED", -5: "MLPG_ERR_GEOMETRY", -7: "MLPG_ERR_STATE"}
 
@@ -46,13 +47,15 @@ class Info(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol_inner", C.c_double), ("tol_outer", C.c_double), ("restart_inner", C.c_int),
                 ("restart_outer", C.c_int), ("max_inner", C.c_int), ("max_outer", C.c_int),
-                ("check_every", C.c_int), ("tol_inner_lo", C.c_double), ("max_refine", C.c_int)]
+                ("check_every", C.c_int), ("tol_inner_lo", C.c_double), ("max_refine", C.c_int),
+                ("accel", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("outer_iters", C.c_int), ("inner_solves", C.c_int), ("inner_iters", C.c_int64),
                 ("inner_sweeps", C.c_int64), ("outer_res", C.c_double), ("inner_res_max", C.c_double),
-                ("converged", C.c_int), ("refinements", C.c_int), ("fp64_completions", C.c_int)]
+                ("converged", C.c_int), ("refinements", C.c_int), ("fp64_completions", C.c_int),
+                ("accel_iters", C.c_int64)]
 
 
 _lib = None

@@ -1,5 +1,7 @@
 """The asteroid problem of Sec. 5.4 at reduced size: shells of material, the refined quadrature of
 Alg. 2 and a small source, the HIP path against the FP64 oracle."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -50,7 +52,9 @@ def test_shell_blocks_match_oracle():
 def test_asteroid_solve_matches_oracle(precision):
     from paper_2008_02205_amd import mlpg
     from paper_2008_02205_amd.problem import GpuProblem
-    a = W.asteroid(0.1)
+    # on this coarse lattice the shell is thinner than the point spacing; at the paper's 20 mean free
+    # paths restarted GMRES with point Jacobi stagnates on both sides, so the shell is made 1 mfp thick
+    a = dataclasses.replace(W.asteroid(0.1), sigma_shell=5.0)
     x, R, dx = W.asteroid_points(a, 0.3)
     shells, st, ss = W.asteroid_materials(a)
     print(f"[case] asteroid solve n={x.shape[0]} {precision}", flush=True)
@@ -58,14 +62,17 @@ def test_asteroid_solve_matches_oracle(precision):
     om_g, w_g = mlpg.mlpg_refined_quadrature(0, 5, a.src, (0.0, 0.0), a.radius)
     g = oracle.geometry(x, R, a.lo, a.hi)
     it = oracle.integrate(g, 1, n_mat=2, shells=shells)
-    tr = oracle.Transport(it, om_o, w_o, st, ss, 0.0, dx)
-    psi_o, phi_o, _ = tr.step(None, W.asteroid_source(a, x, om_o.shape[0]))
+    tr = oracle.Transport(it, om_o, w_o, st, ss, 0.0, dx, opts=oracle.SolveOpts(max_in=20000))
+    psi_o, phi_o, info_o = tr.step(None, W.asteroid_source(a, x, om_o.shape[0]))
+    assert info_o["inner_res_max"] <= 1e-12
     P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
     P.integrate(1)
     P.assemble(om_g, w_g, list(st), list(ss), 0.0, dx,
                precision=mlpg.MLPG_FP64 if precision == "fp64" else mlpg.MLPG_MIXED)
     q = torch.from_numpy(np.ascontiguousarray(W.asteroid_source(a, x, om_g.shape[0]))).cuda()
-    phi, pv, psi, info = P.step(q)
+    opts = mlpg.mlpg_default_opts()
+    opts.max_inner = 20000
+    phi, pv, psi, info = P.step(q, None, opts)
     assert info["converged"] == 1
     e = (rel_l2(_cpu(phi), phi_o), rel_l2(_cpu(pv), tr.point_values(phi_o)), rel_l2(_cpu(psi), psi_o))
     print(f"phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} ordinates {om_g.shape[0]}", flush=True)

@@ -77,3 +77,30 @@ def test_served_request_matches_oracle():
     psi, phi, _ = tr.step(None, np.ones((g.n, spec.n_ord)))
     assert rel_l2(res.phi, phi) <= MIXED_TOL
     assert rel_l2(res.point, tr.point_values(phi)) <= MIXED_TOL
+
+
+def test_mixed_solve_after_a_freed_problem():
+    """Regression: a mixed-precision solve right after another problem was destroyed.
+
+    The FP32 basis then lands on recycled memory; basis slots of gated steps
+    that never ran must not enter the solution update (0 * NaN)."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    specs = _specs()
+    x3, R3, dx3, om3, w3, st3, ss3, q3 = _build(specs[3])
+    g = oracle.geometry(x3, R3, (0, 0), (1, 1))
+    it = oracle.integrate(g, 1)
+    om_o, w_o = oracle.angular_quadrature(2, specs[3].n_ord)
+    _, phi_o, _ = oracle.Transport(it, om_o, w_o, st3, ss3, 0.0, dx3).step(None, np.ones((x3.shape[0], specs[3].n_ord)))
+    for first in (1, 2):
+        for spec in (specs[first], specs[3]):
+            print(f"[case] mixed solve side={spec.side} M={spec.n_ord} after a freed problem", flush=True)
+            x, R, dx, om, w, st, ss, q = _build(spec)
+            P = GpuProblem(x, R, (0.0, 0.0), (1.0, 1.0))
+            P.integrate(1)
+            P.assemble(om, w, [st], [ss], 0.0, dx, precision=mlpg.MLPG_MIXED)
+            phi, pv, psi, info = P.step(torch.from_numpy(np.ascontiguousarray(q)).cuda())
+            phi = phi.cpu().numpy()
+            P.close()
+        assert info["converged"] == 1 and np.all(np.isfinite(phi))
+        assert rel_l2(phi, phi_o) <= MIXED_TOL
