@@ -286,3 +286,31 @@ def test_full_size_3d_gaussian_workload_stages():
     for f in range(6):
         assert abs(blk(f"s{f}").sum() - 1.0) <= 1e-10
     P.close()
+
+
+def test_3d_sweeps_at_the_workload_launch_shape():
+    """The 3D workload's sweep configuration (R = 2.5h, ~450 nonzeros per interior row, 10 streams, 96
+    ordinates: one full and one half-empty 64-lane chunk per row) against the oracle's operators, at 8^3
+    points.  Linear RK keeps the blocks equal to rounding (the stream layout does not depend on the
+    order; quadratic-RK blocks are compared in the stage tests)."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    w = W.config(3, 8)
+    x, dx = W.points_for(w)
+    R = W.radii_for(w, x, dx)
+    _print_case("3d-sweeps", workload=w.name, n=x.shape[0], M=w.n_ord)
+    g = oracle.geometry(x, R, w.lo, w.hi)
+    it = oracle.integrate(g, 1)
+    om, wq = oracle.angular_quadrature(3, w.n_ord)
+    tr = oracle.Transport(it, om, wq, w.sigma_t[0], w.sigma_s[0], 0.0, dx)
+    P = GpuProblem(x, R, w.lo, w.hi)
+    P.integrate(1)
+    P.assemble(*mlpg.mlpg_angular_quadrature(3, w.n_ord), [w.sigma_t[0]], [w.sigma_s[0]], 0.0, dx)
+    X = np.random.default_rng(11).uniform(-1, 1, (g.n, w.n_ord))
+    for name, code in (("L", mlpg.MLPG_OP_L), ("T", mlpg.MLPG_OP_T), ("MS", mlpg.MLPG_OP_MS),
+                       ("MD", mlpg.MLPG_OP_SRC)):
+        Y = _cpu(mlpg.mlpg_apply(P.h, code, _dev(X)))
+        e = rel_l2(Y, tr.apply(name, X))
+        print(f"{name}: {e:.2e}", flush=True)
+        assert e <= 1e-13, name
+    P.close()
