@@ -39,10 +39,12 @@ constexpr int kSlots = 8;
 constexpr int kGroup = 32;            // threads per system in the small kernel
 constexpr int kGroupsPerBlock = kThreads / kGroup;
 
+constexpr int kRedThreads = 1024;   // partial-sum reductions: every strand's loads in flight at once
+
 inline int rpb_of(int nb)
 {
     int r = 1;
-    while (r * 2 * nb <= kThreads) r *= 2;
+    while (r * 2 * nb <= kRedThreads) r *= 2;
     return r;
 }
 
@@ -189,23 +191,23 @@ __global__ __launch_bounds__(kMaxThreads) void pass_b_kernel(int64_t n, int nb, 
 }
 
 // out[q][m] = sum_b part[b][q][m]: one workgroup per q; threads split the
-// block partials into interleaved strands (four independent accumulators each
-// so that loads overlap), then a fixed-shape tree in LDS (deterministic).
+// block partials into interleaved strands (eight independent accumulators
+// each, so that a strand's loads are all in flight together), then a
+// fixed-shape tree in LDS (deterministic).
 __device__ __forceinline__ double reduce_rows(int nblk, int q, int nb, const double *__restrict__ part, double *red)
 {
     const int ns = blockDim.x / nb;          // strands per system (power of two)
     const int st = threadIdx.x / nb, m = threadIdx.x - st * nb;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (st < ns) {
         int b = st;
-        for (; b + 3 * ns < nblk; b += 4 * ns) {
-            a0 += part[((int64_t)b * kRows + q) * nb + m];
-            a1 += part[((int64_t)(b + ns) * kRows + q) * nb + m];
-            a2 += part[((int64_t)(b + 2 * ns) * kRows + q) * nb + m];
-            a3 += part[((int64_t)(b + 3 * ns) * kRows + q) * nb + m];
+        for (; b + 7 * ns < nblk; b += 8 * ns) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[u] += part[((int64_t)(b + u * ns) * kRows + q) * nb + m];
         }
-        for (; b < nblk; b += ns) a0 += part[((int64_t)b * kRows + q) * nb + m];
+        for (; b < nblk; b += ns) acc[0] += part[((int64_t)b * kRows + q) * nb + m];
     }
+    const double a0 = acc[0] + acc[4], a1 = acc[1] + acc[5], a2 = acc[2] + acc[6], a3 = acc[3] + acc[7];
     red[threadIdx.x] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     for (int s = ns >> 1; s > 0; s >>= 1) {
@@ -215,10 +217,11 @@ __device__ __forceinline__ double reduce_rows(int nblk, int q, int nb, const dou
     return red[m];
 }
 
-__global__ __launch_bounds__(kThreads) void reduce_part_kernel(int nblk, int nb, const double *__restrict__ part,
-                                                               double *__restrict__ out, const int *__restrict__ gate)
+__global__ __launch_bounds__(kRedThreads) void reduce_part_kernel(int nblk, int nb, const double *__restrict__ part,
+                                                                  double *__restrict__ out,
+                                                                  const int *__restrict__ gate)
 {
-    __shared__ double red[kThreads];
+    __shared__ double red[kRedThreads];
     if (gate && *gate == 0) return;
     const int q = blockIdx.x;
     const double v = reduce_rows(nblk, q, nb, part, red);
@@ -228,14 +231,14 @@ __global__ __launch_bounds__(kThreads) void reduce_part_kernel(int nblk, int nb,
 // After pass B: beta = ||w_j|| (the unrotated h_{j+1,j} before its
 // correction), vscale = 1/beta for the systems still iterating (0 for the
 // others), and the active count published to the host slot.
-__global__ __launch_bounds__(kThreads) void reduce_norm_kernel(int nblk, int nb, const double *__restrict__ part,
+__global__ __launch_bounds__(kRedThreads) void reduce_norm_kernel(int nblk, int nb, const double *__restrict__ part,
                                                                const int *__restrict__ active,
                                                                double *__restrict__ beta,
                                                                double *__restrict__ vscale,
                                                                const int *__restrict__ gate,
                                                                int *__restrict__ host_slot)
 {
-    __shared__ double red[kThreads];
+    __shared__ double red[kRedThreads];
     if (threadIdx.x == 0 && host_slot) host_slot[0] = gate ? *gate : 1;
     if (gate && *gate == 0) return;
     const double v = reduce_rows(nblk, 0, nb, part, red);
@@ -333,17 +336,44 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     const bool correct = mode != kAfterPre && j >= 1;   // correct and test column j-1
     const int grp = threadIdx.x / kGroup, q = threadIdx.x % kGroup;
     const int m = blockIdx.x * kGroupsPerBlock + grp;
-    const bool act = m < nb && active[m] != 0;
-    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
-    if (act) {
-        if (q < j) a = P[q * nb + m];
-        if (!FINAL) {
-            if (q < j) b = P[(j + q) * nb + m];
-            c = P[(2 * j) * nb + m];
-            d = P[(2 * j + 1) * nb + m];
-        } else {
-            d = P[j * nb + m];
-        }
+    const int mc = m < nb ? m : 0;
+    double *Hm = Ht + (int64_t)mc * (k + 1) * k;
+    // Every load of the kernel is issued here, before any of them is used:
+    // the previous kernels wrote these values (partly from other dies), so
+    // each dependent round trip would cost a full memory latency.
+    const int actv = active[mc];
+    double a = q < j ? P[q * nb + mc] : 0.0, b = 0.0, c = 0.0, d;
+    if (!FINAL) {
+        if (q < j) b = P[(j + q) * nb + mc];
+        c = P[(2 * j) * nb + mc];
+        d = P[(2 * j + 1) * nb + mc];
+    } else {
+        d = P[j * nb + mc];
+    }
+    const double bp = correct ? betap[mc] : 0.0;
+    // column j-1: corrected below (q < j), or read as corrected by kPre
+    const double hprev = (j >= 1 && q <= j && (mode == kAfterPre || q < j)) ? Hm[q * k + (j - 1)] : 0.0;
+    const double csq = (correct && q < j - 1) ? cs[mc * k + q] : 0.0;
+    const double snq = (correct && q < j - 1) ? sn[mc * k + q] : 0.0;
+    // row q of Ht left of column j-1 (not written by this kernel), for t
+    double hv[KP];
+#pragma unroll
+    for (int p = 0; p < KP; ++p) hv[p] = (!FINAL && q <= j && p + 1 >= q && p < j - 1) ? Hm[q * k + p] : 0.0;
+    // the serial part's scalars (thread 0 of each system)
+    double g_prev = 0.0, fn = 0.0, tl = tol0;
+    int it0 = 0;
+    if (q == 0) {
+        g_prev = g[mc * (k + 1) + (j >= 1 ? j - 1 : 0)];
+        fn = fnorm[mc];
+        if (tolv) tl = tolv[mc];
+        it0 = its[mc];
+    }
+    const bool act = m < nb && actv != 0;
+    if (!act) {
+        a = 0.0;
+        b = 0.0;
+        c = 0.0;
+        d = 0.0;
     }
     double aa = a * a, ab = a * b;
     for (int o = kGroup / 2; o > 0; o >>= 1) {
@@ -352,18 +382,16 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     }
     const double rho2 = d - aa;
     const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
-    double *Hm = Ht + (int64_t)(m < nb ? m : 0) * (k + 1) * k;
     sa[grp][q] = a;
-    if (act && mode == kAfterPre && j >= 1 && q <= j) scol[grp][q] = Hm[q * k + (j - 1)];
+    if (act && mode == kAfterPre && j >= 1 && q <= j) scol[grp][q] = hprev;
     // the earlier rotations, staged for the serial part below
     if (act && correct && q < j - 1) {
-        scs[grp][q] = cs[m * k + q];
-        ssn[grp][q] = sn[m * k + q];
+        scs[grp][q] = csq;
+        ssn[grp][q] = snq;
     }
     if (act && correct) {
-        const double bp = betap[m];
         if (q < j) {
-            const double v = Hm[q * k + (j - 1)] + bp * a;
+            const double v = hprev + bp * a;
             Hm[q * k + (j - 1)] = v;
             scol[grp][q] = v;
         } else if (q == j) {
@@ -376,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     if (q == 0 && m < nb) {
         bool still = act;
         if (act && j == 0) {
-            g[m * (k + 1)] *= rho;   // r = beta u_0 = beta rho v_0
+            g[m * (k + 1)] = g_prev * rho;   // r = beta u_0 = beta rho v_0
         } else if (act && correct) {
             double *Rm = R + (int64_t)m * (k + 1) * k;
             double *cm = cs + m * k, *sm = sn + m * k, *gm = g + m * (k + 1);
@@ -408,15 +436,14 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
             }
             cm[j - 1] = cj;
             sm[j - 1] = sj;
-            const double gj = gm[j - 1];
+            const double gj = g_prev;
             gm[j] = -sj * gj;
             gm[j - 1] = cj * gj;
-            its[m] += 1;
+            its[m] = it0 + 1;
             jend[m] = j;
             const double r = fabs(sj * gj);
-            resid[m] = r / fnorm[m];
-            const double tol = tolv ? tolv[m] : tol0;
-            if (r <= tol * fnorm[m] || hn == 0.0 || its[m] >= max_its) still = false;
+            resid[m] = r / fn;
+            if (r <= tl * fn || hn == 0.0 || it0 + 1 >= max_its) still = false;
         }
         if (!FINAL && still && !(rho > 0.0)) still = false;   // u_j in the span: nothing new
         if (mode == kEnd || j >= k) still = false;
@@ -435,10 +462,6 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     // as corrected above)
     double t = 0.0;
     if (q <= j && j >= 1) {
-        // all loads of the row issue together (predicated, no dependence)
-        double hv[KP];
-#pragma unroll
-        for (int p = 0; p < KP; ++p) hv[p] = (p + 1 >= q && p < j - 1) ? Hm[q * k + p] : 0.0;
 #pragma unroll
         for (int p = 0; p < KP; ++p) t += sa[grp][p] * hv[p];
         t += sa[grp][j - 1] * scol[grp][q];
