@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_part_kernel(int nblk, int 
                                                                   const int *__restrict__ gate)
 {
     __shared__ double red[kRedThreads];
-    if (gate && *gate == 0) return;
+    (void)gate;   // runs even for a gated step: it then only rewrites rows no active system reads
     const int q = blockIdx.x;
     const double v = reduce_rows(nblk, q, nb, part, red);
     if ((int)threadIdx.x < nb) out[q * nb + threadIdx.x] = v;
@@ -239,15 +239,20 @@ __global__ __launch_bounds__(kRedThreads) void reduce_norm_kernel(int nblk, int 
                                                                int *__restrict__ host_slot)
 {
     __shared__ double red[kRedThreads];
-    if (threadIdx.x == 0 && host_slot) host_slot[0] = gate ? *gate : 1;
-    if (gate && *gate == 0) return;
-    const double v = reduce_rows(nblk, 0, nb, part, red);
+    // No early return on the gate: a gated step has no active system, and
+    // the kernel then only writes vscale = 0 and a beta nobody reads.  The
+    // gate is still published to the host slot, read up front so that its
+    // latency overlaps the reduction.
+    const int gv = (threadIdx.x == 0 && host_slot && gate) ? *gate : 1;
     const int m = threadIdx.x;
+    const int actm = m < nb ? active[m] : 0;
+    const double v = reduce_rows(nblk, 0, nb, part, red);
     if (m < nb) {
         const double b = sqrt(fmax(v, 0.0));
         beta[m] = b;
-        vscale[m] = (active[m] && b > 0.0) ? 1.0 / b : 0.0;
+        vscale[m] = (actm && b > 0.0) ? 1.0 / b : 0.0;
     }
+    if (threadIdx.x == 0 && host_slot) host_slot[0] = gv;
 }
 
 __global__ void sqrt_kernel(int nb, const double *in, double *out)
@@ -331,7 +336,10 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     __shared__ double scs[kGroupsPerBlock][KP + 1], ssn[kGroupsPerBlock][KP + 1];
     __shared__ int sstill[kGroupsPerBlock];
     if (blockIdx.x == 0 && threadIdx.x == 0 && nact_clear) nact_clear[0] = 0;
-    if (gate && *gate == 0) return;
+    // No early return on the gate: a gated step has no active system, and
+    // every effect below then reduces to clearing the stopped systems'
+    // pass-B coefficients, so the kernel does not wait for the gate's value.
+    (void)gate;
     const bool FINAL = mode == kEnd || mode == kPre;     // no coefficients
     const bool correct = mode != kAfterPre && j >= 1;   // correct and test column j-1
     const int grp = threadIdx.x / kGroup, q = threadIdx.x % kGroup;
