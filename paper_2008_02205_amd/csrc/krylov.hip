@@ -513,20 +513,32 @@ __global__ void init_v0_kernel(int64_t n, int nb, const T *__restrict__ r, const
 }
 
 // Least squares: back substitution R y = g over the jend columns.
-__global__ void lsq_kernel(int nb, int k, const double *__restrict__ H, const double *__restrict__ g,
-                           const int *__restrict__ jend, double *__restrict__ y)
+__global__ __launch_bounds__(kThreads) void lsq_kernel(int nb, int k, const double *__restrict__ H,
+                                                       const double *__restrict__ g,
+                                                       const int *__restrict__ jend, double *__restrict__ y)
 {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= nb) return;
-    const double *Hm = H + (int64_t)m * (k + 1) * k;
-    const double *gm = g + m * (k + 1);
-    int je = jend[m];
-    for (int q = k - 1; q >= 0; --q) {
-        if (q >= je) { y[q * nb + m] = 0.0; continue; }
-        double s = gm[q];
-        for (int p = q + 1; p < je; ++p) s -= Hm[q * k + p] * y[p * nb + m];
-        y[q * nb + m] = s / Hm[q * k + q];
+    // One kGroup-lane group per system: lane r holds row r of R (loaded at
+    // once, no dependent round trips) and its running right-hand side; step
+    // q divides on lane q and broadcasts y_q to the rows above it.
+    const int grp = threadIdx.x / kGroup, r = threadIdx.x % kGroup;
+    const int m = blockIdx.x * kGroupsPerBlock + grp;
+    const int mc = m < nb ? m : 0;
+    const double *Hm = H + (int64_t)mc * (k + 1) * k;
+    const int je = jend[mc];   // <= k < KP, the same on every lane of the group
+    double h[KP];
+#pragma unroll
+    for (int p = 0; p < KP; ++p) h[p] = (r < je && p >= r && p < je) ? Hm[r * k + p] : 0.0;
+    double s = r < je ? g[mc * (k + 1) + r] : 0.0;
+    double yr = 0.0;
+#pragma unroll
+    for (int q = KP - 1; q >= 0; --q) {
+        if (q < je) {
+            const double yq = __shfl(s / h[q], q, kGroup);   // lane q: R[q][q]
+            if (r == q) yr = yq;
+            if (r < q) s -= h[q] * yq;                      // lane r: R[r][q]
+        }
     }
+    if (m < nb && r < k) y[r * nb + m] = r < je ? yr : 0.0;
 }
 
 // x += dinv .* (V y) over each system's own columns: the basis slots of
@@ -839,7 +851,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                 kEnd, nb, k, k, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
                 max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nact + ((k + 1) % 3), nullptr);
         }
-        lsq_kernel<<<(nb + 255) / 256, 256, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
+        lsq_kernel<<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
         x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, dinv, x);
         OpCallT<T> c;
         c.in = x;
