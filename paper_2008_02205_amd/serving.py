@@ -68,6 +68,10 @@ class Server:
         self.precision = precision
         self.opts = opts
 
+    def _stream(self):
+        """The HIP stream of one slot."""
+        return torch.cuda.Stream()
+
     def _solve(self, build: Callable, spec, stream: torch.cuda.Stream):
         x, R, dx, om, w, sig_t, sig_s, q = build(spec)
         with torch.cuda.stream(stream):
@@ -92,7 +96,7 @@ class Server:
         state = {"bytes": 0, "running": 0}
         results: List[Result] = []
         order = sorted(specs, key=lambda s: s.arrival)
-        streams = [torch.cuda.Stream() for _ in range(self.slots)]
+        streams = [self._stream() for _ in range(self.slots)]
         free_streams = list(range(self.slots))
         threads = []
         t0 = time.perf_counter()
