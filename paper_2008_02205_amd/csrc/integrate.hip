@@ -428,6 +428,11 @@ __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
                 material_weights<2>(yy, mat, w, g.fields, wf);
             }
             uint64_t ma = mask & ((a1 >= 64 ? ~0ull : ((1ull << a1) - 1)) & ~((1ull << a0) - 1));
+            // the lanes of a wave (neighbouring quadrature points) walk the
+            // active columns from different starting columns, so that their
+            // LDS atomics rarely meet on one address (they would serialise)
+            const int bs = (int)(threadIdx.x & 63) % A;
+            const uint64_t below = (1ull << bs) - 1;
             while (ma) {
                 int a = __builtin_ctzll(ma);
                 ma &= ma - 1;
@@ -435,8 +440,9 @@ __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
                 rk_value<ORD>(y0, y1, a, sx, sR, sV, hs, C, dC0, dC1, &Na, &dNa0, &dNa1);
                 double wa = w * Na, wa0 = w * dNa0, wa1 = w * dNa1;
                 double *gr = gram + (a - a0) * A;
-                uint64_t mb = mask;
-                while (mb) {
+                uint64_t mhi = mask & ~below, mlo = mask & below;   // columns >= bs first, then the rest
+                while (mhi | mlo) {
+                    uint64_t &mb = mhi ? mhi : mlo;
                     int b = __builtin_ctzll(mb);
                     mb &= mb - 1;
                     double Nb, dNb0, dNb1;
@@ -965,12 +971,17 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
             const int mat = material_at3(y, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
             double wf[kMaxMat];
             if (FIELDS) material_weights<3>(y, mat, w, g.fields, wf);
+            // the lanes of a wave (neighbouring quadrature points) start the
+            // column loop at different columns, so that their LDS atomics
+            // never meet on one address (they would serialise)
+            const int bstart = (int)(threadIdx.x & 63) % A;
             for (int a = a0; a < a1; ++a) {
                 double Na, dNa[3];
                 if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
                 const double wa = w * Na, wa0 = w * dNa[0], wa1 = w * dNa[1], wa2 = w * dNa[2];
                 double *gr = gram + (a - a0) * A;
-                for (int b = 0; b < A; ++b) {
+                for (int bi = 0; bi < A; ++bi) {
+                    const int b = bstart + bi < A ? bstart + bi : bstart + bi - A;
                     double Nb, dNb[3];
                     if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
                     if (!FIELDS) {
