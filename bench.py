@@ -73,8 +73,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not part of "
-                                   "this build (the angular sharding design is described in DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: only the single-GPU path is "
+                                   "implemented (sharding the ordinates across GPUs is a design, not code)"}))
         sys.exit(2)
     import torch
     from paper_2008_02205_amd import mlpg
