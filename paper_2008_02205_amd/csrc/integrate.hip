@@ -972,24 +972,57 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
             double wf[kMaxMat];
             if (FIELDS) material_weights<3>(y, mat, w, g.fields, wf);
             // the lanes of a wave (neighbouring quadrature points) start the
-            // column loop at different columns, so that their LDS atomics
+            // column walk at different columns, so that their LDS atomics
             // never meet on one address (they would serialise)
             const int bstart = (int)(threadIdx.x & 63) % A;
-            for (int a = a0; a < a1; ++a) {
-                double Na, dNa[3];
-                if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
-                const double wa = w * Na, wa0 = w * dNa[0], wa1 = w * dNa[1], wa2 = w * dNa[2];
-                double *gr = gram + (a - a0) * A;
+            if constexpr (!FIELDS) {
+                // the tile rows' values at y once (registers), then every
+                // column's values once, added against all active rows
+                double ta[kTileRows3], td0[kTileRows3], td1[kTileRows3], td2[kTileRows3];
+                unsigned amask = 0;
+#pragma unroll
+                for (int al = 0; al < kTileRows3; ++al) {
+                    ta[al] = td0[al] = td1[al] = td2[al] = 0.0;
+                    double Na, dNa[3];
+                    if (a0 + al < a1 && rk_value3<ORD>(y, a0 + al, sx, sR, sV, hs, C, dC, &Na, dNa)) {
+                        ta[al] = Na; td0[al] = dNa[0]; td1[al] = dNa[1]; td2[al] = dNa[2];
+                        amask |= 1u << al;
+                    }
+                }
+                if (!amask) continue;
                 for (int bi = 0; bi < A; ++bi) {
                     const int b = bstart + bi < A ? bstart + bi : bstart + bi - A;
                     double Nb, dNb[3];
                     if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
-                    if (!FIELDS) {
-                        atomicAdd(&gr[(4 * mat + 0) * TT + b], wa * Nb);
-                        atomicAdd(&gr[(4 * mat + 1) * TT + b], wa0 * Nb);
-                        atomicAdd(&gr[(4 * mat + 2) * TT + b], wa1 * Nb);
-                        atomicAdd(&gr[(4 * mat + 3) * TT + b], wa2 * Nb);
-                    } else {
+                    const double wNb = w * Nb, wd0 = w * dNb[0], wd1 = w * dNb[1], wd2 = w * dNb[2];
+#pragma unroll
+                    for (int al = 0; al < kTileRows3; ++al) {
+                        if (!((amask >> al) & 1u)) continue;
+                        double *gr = gram + al * A;
+                        atomicAdd(&gr[(4 * mat + 0) * TT + b], ta[al] * wNb);
+                        atomicAdd(&gr[(4 * mat + 1) * TT + b], td0[al] * wNb);
+                        atomicAdd(&gr[(4 * mat + 2) * TT + b], td1[al] * wNb);
+                        atomicAdd(&gr[(4 * mat + 3) * TT + b], td2[al] * wNb);
+                        atomicAdd(&gr[(4 * G + 0) * TT + b], td0[al] * wd0);
+                        atomicAdd(&gr[(4 * G + 1) * TT + b], td0[al] * wd1);
+                        atomicAdd(&gr[(4 * G + 2) * TT + b], td0[al] * wd2);
+                        atomicAdd(&gr[(4 * G + 3) * TT + b], td1[al] * wd1);
+                        atomicAdd(&gr[(4 * G + 4) * TT + b], td1[al] * wd2);
+                        atomicAdd(&gr[(4 * G + 5) * TT + b], td2[al] * wd2);
+                    }
+                }
+            } else {
+                // with material fields (per-material weights per point) the
+                // rows are taken one at a time, each column re-evaluated
+                for (int a = a0; a < a1; ++a) {
+                    double Na, dNa[3];
+                    if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
+                    const double wa0 = w * dNa[0], wa1 = w * dNa[1], wa2 = w * dNa[2];
+                    double *gr = gram + (a - a0) * A;
+                    for (int bi = 0; bi < A; ++bi) {
+                        const int b = bstart + bi < A ? bstart + bi : bstart + bi - A;
+                        double Nb, dNb[3];
+                        if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
 #pragma unroll
                         for (int m = 0; m < kMaxMat; ++m) {
                             if (m >= G || wf[m] == 0.0) continue;
@@ -998,13 +1031,13 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
                             atomicAdd(&gr[(4 * m + 2) * TT + b], wf[m] * dNa[1] * Nb);
                             atomicAdd(&gr[(4 * m + 3) * TT + b], wf[m] * dNa[2] * Nb);
                         }
+                        atomicAdd(&gr[(4 * G + 0) * TT + b], wa0 * dNb[0]);
+                        atomicAdd(&gr[(4 * G + 1) * TT + b], wa0 * dNb[1]);
+                        atomicAdd(&gr[(4 * G + 2) * TT + b], wa0 * dNb[2]);
+                        atomicAdd(&gr[(4 * G + 3) * TT + b], wa1 * dNb[1]);
+                        atomicAdd(&gr[(4 * G + 4) * TT + b], wa1 * dNb[2]);
+                        atomicAdd(&gr[(4 * G + 5) * TT + b], wa2 * dNb[2]);
                     }
-                    atomicAdd(&gr[(4 * G + 0) * TT + b], wa0 * dNb[0]);
-                    atomicAdd(&gr[(4 * G + 1) * TT + b], wa0 * dNb[1]);
-                    atomicAdd(&gr[(4 * G + 2) * TT + b], wa0 * dNb[2]);
-                    atomicAdd(&gr[(4 * G + 3) * TT + b], wa1 * dNb[1]);
-                    atomicAdd(&gr[(4 * G + 4) * TT + b], wa1 * dNb[2]);
-                    atomicAdd(&gr[(4 * G + 5) * TT + b], wa2 * dNb[2]);
                 }
             }
         }
@@ -1234,6 +1267,8 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
     size_t budget = (lds_max > 0 ? (size_t)lds_max : 65536) - fixed;
     int tile_rows = (int)(budget / (sizeof(double) * NB * amax));
     if (tile_rows > amax) tile_rows = amax;
+    // without material fields the rows' values live in registers
+    if (!(P.n_fields > 0 || P.n_shells > 0) && tile_rows > kTileRows3) tile_rows = kTileRows3;
     if (tile_rows < 1) return hipErrorInvalidValue;
     size_t shmem = sizeof(double) * (5 * amax + (amax + 1) / 2) + sizeof(double) * (size_t)NB * tile_rows * amax;
 

@@ -27,6 +27,7 @@ constexpr int kTri3N = 2;          // conical-product order on a boundary triang
 constexpr int kTri3Rule = kTri3N * kTri3N;
 constexpr int kBqAct3 = 128;       // active functions stored per boundary point (3D)
 constexpr int kCandMax3D = 512;    // functions possibly active on one 3D cell
+constexpr int kTileRows3 = 8;      // most Gram rows per 3D tile without fields (their values sit in registers)
 constexpr int kMaxRestart = 30;
 constexpr int kMaxFields = 8;    // smooth material fields per problem
 constexpr int kMaxMat = 8;       // materials per problem
