@@ -130,9 +130,12 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
  * dim = 2 (polygons, at most 32 vertices) or 3 (polyhedra of at most 40
  * convex faces with at most 16 vertices each; the faces of a clip are built
  * from the cut points ordered about their centroid).  A cell over capacity
- * fails the call with MLPG_ERR_GEOMETRY.  The call synchronises `stream` (it
- * sizes the boundary quadrature).  On success *out owns copies of all
- * inputs.
+ * fails the call with MLPG_ERR_GEOMETRY.  The overlap lists are validated on
+ * the device before any other kernel reads them: nbr_off[0] = 0, offsets
+ * non-decreasing and within nbr_off[n], every index in [0, n), never the row
+ * itself, strictly increasing along a row; otherwise MLPG_ERR_ARG.  The call
+ * synchronises `stream` (it sizes the boundary quadrature).  On success *out
+ * owns copies of all inputs.
  * ---------------------------------------------------------------------- */
 int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R,
                   const int64_t *nbr_off, const int32_t *nbr_idx, const double *dom_lo,
@@ -246,7 +249,9 @@ int mlpg_material_shells(mlpg_handle h, int n_shells, const double *center, cons
  * Also forms the point-value matrix E_ij = N_j(x_i) (Eq. flux-expansion).
  * MLPG_ERR_CAPACITY when a cell has more candidate functions than the
  * per-cell capacity (64 in 2D, 512 in 3D) or a boundary point more active
- * functions than it stores (32 in 2D, 128 in 3D).
+ * functions than it stores (32 in 2D, 128 in 3D).  MLPG_ERR_ARG when two
+ * functions active at one quadrature point are not overlap neighbours (the
+ * caller's lists were incomplete; the blocks would silently lose entries).
  * ---------------------------------------------------------------------- */
 int mlpg_integrate(mlpg_handle h, int rk_order, void *stream);
 
@@ -301,8 +306,13 @@ int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *strea
  *   phi_coef: device [n] out, Phi; phi_point: device [n] out, phi(x_i) (may be NULL);
  *   psi_out: device [n][n_ord] out, Psi (may be NULL);
  *   opts: host, NULL for defaults; info: host out, may be NULL.
- * The call synchronises `stream` at Krylov convergence checks.  Returns
- * MLPG_ERR_NOT_CONVERGED (with outputs written) when a limit was hit.
+ * The call synchronises `stream` at Krylov convergence checks.  An inner
+ * solve that reaches max_inner before tol_inner ends the step at once (the
+ * outer iteration needs every L_m^-1 as a fixed linear map): the call returns
+ * MLPG_ERR_NOT_CONVERGED with the outputs and the state unwritten and `info`
+ * counting the work done.  When only the outer iteration reaches max_outer,
+ * it returns MLPG_ERR_NOT_CONVERGED with the outputs of the last iterate
+ * written.
  * ---------------------------------------------------------------------- */
 typedef struct {
     double tol_inner;     /* ||f - L_m x|| <= tol ||f|| per ordinate (default 1e-13) */

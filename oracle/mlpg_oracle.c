@@ -1046,6 +1046,26 @@ static void apply_L(const op_ctx *o, int m, const double *x, double *y)
     }
 }
 
+/* The entries L_m[i, col[p]] of one ordinate, evaluated once (the same
+ * L_entry values apply_L uses, kept for the length of one inner solve). */
+static double *L_values(const op_ctx *o, int m)
+{
+    double *Lv = (double *)malloc(sizeof(double) * (o->nnz > 0 ? o->nnz : 1));
+    for (int64_t i = 0; i < o->n; ++i)
+        for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p) Lv[p] = L_entry(o, m, i, p);
+    return Lv;
+}
+
+/* y = L_m x from the stored entries of L_values: the sums of apply_L. */
+static void apply_Lv(const op_ctx *o, const double *Lv, const double *x, double *y)
+{
+    for (int64_t i = 0; i < o->n; ++i) {
+        double s = 0.0;
+        for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p) s += Lv[p] * x[o->col[p]];
+        y[i] = s;
+    }
+}
+
 /* kind 0: (Mass + tau W.D) x ; kind 1: 1/(4 pi) sigma_s-weighted version */
 static void apply_MD(const op_ctx *o, int m, int kind, const double *x, double *y)
 {
@@ -1089,10 +1109,11 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
     double *H = (double *)calloc((size_t)(k + 1) * k, sizeof(double));
     double *cs = (double *)malloc(sizeof(double) * k), *sn = (double *)malloc(sizeof(double) * k);
     double *g = (double *)malloc(sizeof(double) * (k + 1)), *yv = (double *)malloc(sizeof(double) * k);
+    double *Lv = L_values(o, m);
     for (int64_t i = 0; i < n; ++i) {
         double d = 0.0;
         for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p)
-            if (o->col[p] == i) d = L_entry(o, m, i, p);
+            if (o->col[p] == i) d = Lv[p];
         dinv[i] = d != 0.0 ? 1.0 / d : 1.0;
         x[i] = 0.0;
     }
@@ -1101,7 +1122,7 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
     double rel = 0.0;
     if (fn == 0.0) goto done;
     for (;;) {
-        apply_L(o, m, x, r);
+        apply_Lv(o, Lv, x, r);
         for (int64_t i = 0; i < n; ++i) r[i] = f[i] - r[i];
         double beta = sqrt(dot(n, r, r));
         rel = beta / fn;
@@ -1113,7 +1134,7 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
         for (int j = 0; j < k; ++j) {
             const double *vj = Vb + (int64_t)j * n;
             for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * vj[i];
-            apply_L(o, m, z, w);
+            apply_Lv(o, Lv, z, w);
             for (int q = 0; q <= j; ++q) {
                 const double *vq = Vb + (int64_t)q * n;
                 double h = dot(n, w, vq);
@@ -1153,7 +1174,7 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
     }
 done:
     *res = rel;
-    free(Vb); free(z); free(w); free(r); free(dinv); free(H); free(cs); free(sn); free(g); free(yv);
+    free(Lv); free(Vb); free(z); free(w); free(r); free(dinv); free(H); free(cs); free(sn); free(g); free(yv);
     return its;
 }
 

@@ -174,11 +174,20 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
     return MLPG_OK;
 }
 
+// One batched L^-1 application.  An inner solve that misses its tolerance
+// ends the whole step at once: the outer GMRES needs L^-1 as a fixed linear
+// map, and iterating on an operator that is not one only burns sweeps.
 int inner_solve(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
 {
     c.solves++;
-    if (P.precision == MLPG_MIXED) return inner_solve_mixed(P, c, f, x, s);
-    return inner_solve_fp64(P, c, f, x, s);
+    int rc = P.precision == MLPG_MIXED ? inner_solve_mixed(P, c, f, x, s) : inner_solve_fp64(P, c, f, x, s);
+    if (rc) return rc;
+    if (!c.conv) {
+        set_error("mlpg_solve: an inner solve reached max_inner (" + std::to_string(c.o->max_inner) +
+                  " Arnoldi steps) before its tolerance; largest relative residual " + std::to_string(c.res_max));
+        return MLPG_ERR_NOT_CONVERGED;
+    }
+    return MLPG_OK;
 }
 
 // A phi = phi - D L^-1 MS phi  (Eq. krylov-operator)
@@ -214,7 +223,12 @@ int dsa_apply(Problem &P, SolveCounters &c, const double *v, double *out, hipStr
                                    1e-12, kMaxRestart, 20000, 1, true, s, &c.accel_its, &sweeps, &rm, &conv,
                                    nullptr, true);
     if (rc) return rc;
-    c.conv = c.conv && conv;
+    if (!conv) {
+        // without a converged diffusion solve P is not a fixed operator
+        c.conv = false;
+        set_error("mlpg_solve: the diffusion solve of the synthetic acceleration did not reach 1e-12");
+        return MLPG_ERR_NOT_CONVERGED;
+    }
     MLPG_HIP(launch_add(out, v, P.dsa_x.p, P.n, s));
     return MLPG_OK;
 }
@@ -323,6 +337,22 @@ static int build_geometry(Problem &P, const double *x, const double *R, const in
     TRY(hipMemcpyAsync(P.R.p, R, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     TRY(hipMemcpyAsync(P.nb_off.p, nbr_off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (nnz_nb) TRY(hipMemcpyAsync(P.nb_idx.p, nbr_idx, sizeof(int32_t) * nnz_nb, hipMemcpyDeviceToDevice, s));
+    // the lists steer every later kernel's reads: validate them before use
+    TRY(P.counters.alloc(kNumCounters));
+    TRY(hipMemsetAsync(P.counters.p, 0, sizeof(unsigned long long) * kNumCounters, s));
+    TRY(launch_check_lists(n, nnz_nb, P.nb_off.p, P.nb_idx.p, P.counters.p + kBadLists, s));
+    {
+        unsigned long long bad = 0;
+        TRY(hipMemcpyAsync(&bad, P.counters.p + kBadLists, sizeof(bad), hipMemcpyDeviceToHost, s));
+        TRY(hipStreamSynchronize(s));
+        if (bad) {
+            set_error(std::string("mlpg_geometry: malformed overlap lists (") +
+                      ((bad & 1) ? "offsets not non-decreasing from 0 within the list length" :
+                                   "an index out of [0, n), equal to its row, or not strictly increasing") +
+                      ")");
+            return MLPG_ERR_ARG;
+        }
+    }
 
     TRY(P.V.alloc(n));
     TRY(P.rho.alloc(n));
@@ -372,7 +402,6 @@ static int build_geometry(Problem &P, const double *x, const double *R, const in
     TRY(P.bq_nact.alloc(nbq));
     TRY(P.bq_act.alloc(nbq * P.bq_kmax));
     TRY(P.bq_N.alloc(nbq * P.bq_kmax));
-    TRY(P.counters.alloc(kNumCounters));
     TRY(hipStreamSynchronize(s));
 #undef TRY
     return MLPG_OK;
@@ -576,6 +605,11 @@ int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
     P->fallbacks = (int64_t)cnt[kFallbacks];
     P->missing = (int64_t)cnt[kMissing];
     MLPG_CHECK(cnt[kOverflow] == 0, MLPG_ERR_CAPACITY, "mlpg_integrate: per-cell or per-point capacity exceeded");
+    // two functions active at one quadrature point overlap, so a pair absent
+    // from the pattern means the caller's overlap lists were incomplete
+    MLPG_CHECK(cnt[kMissing] == 0, MLPG_ERR_ARG,
+               "mlpg_integrate: " + std::to_string(cnt[kMissing]) +
+                   " co-active function pairs are missing from the overlap lists");
     P->stage = 2;
     return MLPG_OK;
 }
@@ -824,71 +858,84 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     const int M = P->n_ord;
     SolveCounters c;
     c.o = &o;
+    int64_t oits = 0, osweeps = 0;
+    double ores = 0.0;
+    bool oconv = true;
+    // every exit after this point reports what was done so far
+    auto finish = [&](int code) {
+        if (info) {
+            info->outer_iters = (int)oits;
+            info->inner_solves = c.solves;
+            info->inner_iters = c.its;
+            info->inner_sweeps = c.sweeps;
+            info->outer_res = ores;
+            info->inner_res_max = c.res_max;
+            info->converged = (code == MLPG_OK && c.conv && oconv) ? 1 : 0;
+            info->refinements = (int)c.refinements;
+            info->fp64_completions = (int)c.fp64_completions;
+            info->accel_iters = c.accel_its;
+        }
+        return code;
+    };
+#define STEP_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));                 \
+            return finish(MLPG_ERR_HIP);                                                  \
+        }                                                                                 \
+    } while (0)
     // F = (Mass + tau W.D)(a0 Psi^{n-1} + q) + inflow term   (T Psi^{n-1} + r)
     {
         SpmvArgs a;
         a.vals = P->sMD.p; a.ns = P->nsMD; a.coef = P->coefMD.p; a.x = P->psi.p; a.xs = P->a0; a.x2 = q;
         a.y = P->F.p;
-        MLPG_HIP(launch_spmv(*P, a, s));
-        if (psi_b) MLPG_HIP(launch_boundary_rhs(*P, psi_b, P->F.p, s));
+        STEP_HIP(launch_spmv(*P, a, s));
+        if (psi_b) STEP_HIP(launch_boundary_rhs(*P, psi_b, P->F.p, s));
     }
     // b_psi = L^-1 F, b_phi = D b_psi
     rc = inner_solve(*P, c, P->F.p, P->bpsi.p, s);
-    if (rc) return rc;
-    MLPG_HIP(launch_ord_reduce(*P, P->bpsi.p, P->bphi.p, nullptr, 1.0, s));
+    if (rc) return finish(rc);
+    STEP_HIP(launch_ord_reduce(*P, P->bpsi.p, P->bphi.p, nullptr, 1.0, s));
     // outer GMRES on (I - D L^-1 MS) Phi = b_phi from the previous Phi.  With
     // FP32 inner corrections the outer operator is linear only to about the
     // inner tolerance times 1/(1 - c), so the mixed path stops the outer
     // iteration at 1e-10 at the tightest (far inside its 1e-8 bar on Phi).
     const double tol_outer = P->precision == MLPG_MIXED ? std::max(o.tol_outer, kMixedOuterFloor) : o.tol_outer;
-    int64_t oits = 0, osweeps = 0;
-    double ores = 0.0;
-    bool oconv = true;
     if (o.accel == MLPG_ACCEL_DSA) {
         // right-preconditioned: GMRES for u with (I - D L^-1 MS) P^-1 u = b_phi, then Phi = P^-1 u
         // (the previous Phi serves as the first u)
         rc = gmres_batched<double>(*P, P->outer, op_outer_dsa, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1,
                                    tol_outer, o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits,
                                    &osweeps, &ores, &oconv);
-        if (rc) return rc;
+        if (rc) return finish(rc);
         rc = dsa_apply(*P, c, P->phi.p, P->dsa_t.p, s);
-        if (rc) return rc;
-        MLPG_HIP(hipMemcpyAsync(P->phi.p, P->dsa_t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        if (rc) return finish(rc);
+        STEP_HIP(hipMemcpyAsync(P->phi.p, P->dsa_t.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     } else {
         rc = gmres_batched<double>(*P, P->outer, op_outer, false, &c, nullptr, P->bphi.p, P->phi.p, n, 1,
                                    tol_outer, o.restart_outer, std::max(1, o.max_outer), 1, false, s, &oits,
                                    &osweeps, &ores, &oconv);
-        if (rc) return rc;
+        if (rc) return finish(rc);
     }
     // recovery Psi = L^-1 MS Phi + b_psi
     {
         SpmvArgs a;
         a.vals = P->sMS.p; a.ns = P->nsMD; a.coef = P->coefMD.p; a.x = P->phi.p; a.x_bcast = 1; a.y = P->t1.p;
-        MLPG_HIP(launch_spmv(*P, a, s));
+        STEP_HIP(launch_spmv(*P, a, s));
     }
     rc = inner_solve(*P, c, P->t1.p, P->t2.p, s);
-    if (rc) return rc;
-    MLPG_HIP(launch_add(P->psi.p, P->t2.p, P->bpsi.p, n * M, s));
-    MLPG_HIP(hipMemcpyAsync(phi_coef, P->phi.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    if (phi_point) MLPG_HIP(launch_point_values(*P, P->phi.p, phi_point, s));
-    if (psi_out) MLPG_HIP(hipMemcpyAsync(psi_out, P->psi.p, sizeof(double) * n * M, hipMemcpyDeviceToDevice, s));
-    if (info) {
-        info->outer_iters = (int)oits;
-        info->inner_solves = c.solves;
-        info->inner_iters = c.its;
-        info->inner_sweeps = c.sweeps;
-        info->outer_res = ores;
-        info->inner_res_max = c.res_max;
-        info->converged = (c.conv && oconv) ? 1 : 0;
-        info->refinements = (int)c.refinements;
-        info->fp64_completions = (int)c.fp64_completions;
-        info->accel_iters = c.accel_its;
-    }
+    if (rc) return finish(rc);
+    STEP_HIP(launch_add(P->psi.p, P->t2.p, P->bpsi.p, n * M, s));
+    STEP_HIP(hipMemcpyAsync(phi_coef, P->phi.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    if (phi_point) STEP_HIP(launch_point_values(*P, P->phi.p, phi_point, s));
+    if (psi_out) STEP_HIP(hipMemcpyAsync(psi_out, P->psi.p, sizeof(double) * n * M, hipMemcpyDeviceToDevice, s));
+#undef STEP_HIP
     if (!(c.conv && oconv)) {
-        set_error("mlpg_solve: a Krylov solve reached its iteration limit");
-        return MLPG_ERR_NOT_CONVERGED;
+        set_error("mlpg_solve: the outer Krylov iteration reached max_outer before its tolerance");
+        return finish(MLPG_ERR_NOT_CONVERGED);
     }
-    return MLPG_OK;
+    return finish(MLPG_OK);
 }
 
 void mlpg_destroy(mlpg_handle h)

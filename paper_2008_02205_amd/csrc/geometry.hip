@@ -553,7 +553,39 @@ __global__ void pattern_kernel(int64_t n, const int64_t *__restrict__ nb_off, co
     }
 }
 
+// Caller-supplied overlap lists: row offsets within [0, total] and
+// non-decreasing from 0, indices in [0, n), never i itself, strictly
+// increasing along a row.  A row whose offsets are out of range is not read.
+// Sets bit 1 (offsets) or bit 2 (indices) of *bad.
+__global__ void check_lists_kernel(int64_t n, int64_t total, const int64_t *__restrict__ off,
+                                   const int32_t *__restrict__ idx, unsigned long long *bad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t a = off[i], b = off[i + 1];
+    if ((i == 0 && a != 0) || a < 0 || b < a || b > total) {
+        atomicOr(bad, 1ull);
+        return;
+    }
+    int64_t prev = -1;
+    for (int64_t p = a; p < b; ++p) {
+        const int64_t j = idx[p];
+        if (j < 0 || j >= n || j == i || j <= prev) {
+            atomicOr(bad, 2ull);
+            return;
+        }
+        prev = j;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_check_lists(int64_t n, int64_t total, const int64_t *off, const int32_t *idx,
+                              unsigned long long *bad, hipStream_t s)
+{
+    check_lists_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, total, off, idx, bad);
+    return hipGetLastError();
+}
 
 hipError_t launch_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *counts, hipStream_t s)
 {

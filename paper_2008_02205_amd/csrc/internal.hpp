@@ -95,7 +95,7 @@ void gauss_legendre(int n, double *x, double *w);
 void gauss_jacobi(int n, double alpha, double *x, double *w);
 
 // Counters written by kernels (device, zeroed at each stage that uses them).
-enum Counter { kFallbacks = 0, kMissing = 1, kOverflow = 2, kNumCounters = 4 };
+enum Counter { kFallbacks = 0, kMissing = 1, kOverflow = 2, kBadLists = 3, kNumCounters = 4 };
 
 // Batched GMRES workspace for `nb` simultaneous systems of `n` unknowns
 // (ordinates as the fastest index); T is the storage type of the basis and
@@ -230,6 +230,9 @@ hipError_t launch_neighbors_count(int dim, int64_t n, const double *x, const dou
 hipError_t launch_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *off,
                                  int32_t *idx, hipStream_t s);
 hipError_t launch_exclusive_scan(const int64_t *counts, int64_t *off, int64_t n, hipStream_t s);
+// validates caller-supplied overlap lists (sets bits of *bad, see geometry.hip)
+hipError_t launch_check_lists(int64_t n, int64_t total, const int64_t *off, const int32_t *idx,
+                              unsigned long long *bad, hipStream_t s);
 
 hipError_t launch_clip2d(Problem &P, hipStream_t s, int32_t *flags, int64_t *bq_count);
 hipError_t launch_clip3d(Problem &P, hipStream_t s, int32_t *flags, int64_t *bq_count);

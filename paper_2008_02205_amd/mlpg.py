@@ -112,6 +112,11 @@ def _check(rc: int):
         raise MlpgError(rc, lib().mlpg_last_error().decode())
 
 
+def last_error() -> str:
+    """Message of the last failing call on this thread (mlpg_last_error)."""
+    return lib().mlpg_last_error().decode()
+
+
 def _torch():
     import torch
     return torch
