@@ -70,7 +70,8 @@ class OpCtx(C.Structure):
                 ("tau", _dp), ("nbq", C.c_int64), ("kmax", C.c_int), ("bq_face", _i32p),
                 ("bq_w", _dp), ("bq_nact", _i32p), ("bq_act", _i32p), ("bq_N", _dp),
                 ("tol_in", C.c_double), ("tol_out", C.c_double), ("restart_in", C.c_int),
-                ("restart_out", C.c_int), ("max_in", C.c_int), ("max_out", C.c_int)]
+                ("restart_out", C.c_int), ("max_in", C.c_int), ("max_out", C.c_int),
+                ("precond", C.c_int), ("x", _dp), ("dom_lo", _dp), ("dom_hi", _dp)]
 
 
 def _declare(L):
@@ -108,6 +109,10 @@ def _declare(L):
     L.orc_point_values.argtypes = [C.c_int64, _i64p, _i32p, _dp, _dp, C.c_int, _dp]
     L.orc_Linv_range.restype = C.c_int64
     L.orc_Linv_range.argtypes = [C.POINTER(OpCtx), _dp, _dp, C.c_int, C.c_int, _dp]
+    L.orc_patches_of.restype = C.c_int64
+    L.orc_patches_of.argtypes = [C.POINTER(OpCtx), _i64p, _i32p]
+    L.orc_patch_precond.restype = None
+    L.orc_patch_precond.argtypes = [C.POINTER(OpCtx), C.c_int, _dp, _dp]
     L.orc_num_threads.restype = C.c_int
     L.orc_num_threads.argtypes = []
 
@@ -547,6 +552,7 @@ class SolveOpts:
     restart_out: int = 30
     max_in: int = 3000
     max_out: int = 500
+    precond: str = "jacobi"     # inner right preconditioner: "jacobi" (point) or "patch" (patch block Jacobi)
 
 
 class Transport:
@@ -573,12 +579,29 @@ class Transport:
         bq_nact = np.ascontiguousarray(it.bq_nact if it.nbq else np.zeros(1, np.int32))
         bq_act = np.ascontiguousarray(it.bq_act if it.nbq else np.zeros((1, it.kmax), np.int32))
         bq_N = _f64(it.bq_N if it.nbq else np.zeros((1, it.kmax)))
-        self._keep = [bq_face, bq_w, bq_nact, bq_act, bq_N]
+        lo = _f64(np.asarray(g.dom_lo, dtype=np.float64).reshape(-1))
+        hi = _f64(np.asarray(g.dom_hi, dtype=np.float64).reshape(-1))
+        self._keep = [bq_face, bq_w, bq_nact, bq_act, bq_N, lo, hi]
+        pc = {"jacobi": 0, "patch": 1}[o.precond]
         return OpCtx(g.dim, it.n_mat, self.M, g.n, int(g.row_off[-1]), _p(g.row_off, _i64p), _p(g.col, _i32p),
                      _p(it.blocks), _p(self.omega), _p(self.w), _p(self.sig_t), _p(self.sig_s), self.a0,
                      _p(self.tau), it.nbq, it.kmax, _p(bq_face, _i32p), _p(bq_w), _p(bq_nact, _i32p),
                      _p(bq_act, _i32p), _p(bq_N), o.tol_in, o.tol_out, o.restart_in, o.restart_out, o.max_in,
-                     o.max_out)
+                     o.max_out, pc, _p(g.x), _p(lo), _p(hi))
+
+    def patches(self):
+        """Patches of the block-Jacobi preconditioner: (start[np+1], points[n])."""
+        n = self.it.geom.n
+        start = np.zeros(n + 1, dtype=np.int64)
+        pts = np.zeros(n, dtype=np.int32)
+        np_ = lib().orc_patches_of(C.byref(self.ctx), _p(start, _i64p), _p(pts, _i32p))
+        return start[:np_ + 1], pts
+
+    def patch_precond(self, m: int, v: np.ndarray) -> np.ndarray:
+        """z = M^-1 v of the patch block-Jacobi preconditioner for ordinate m."""
+        z = np.zeros(self.it.geom.n)
+        lib().orc_patch_precond(C.byref(self.ctx), int(m), _p(_f64(v)), _p(z))
+        return z
 
     def apply(self, which: str, X: np.ndarray) -> np.ndarray:
         code = {"L": 0, "T": 1, "MS": 2, "MD": 3}[which]

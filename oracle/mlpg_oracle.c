@@ -1002,6 +1002,11 @@ typedef struct {
     /* solver settings */
     double tol_in, tol_out;
     int restart_in, restart_out, max_in, max_out;
+    /* right preconditioner of the inner solves: 0 point Jacobi, 1 patch
+     * block Jacobi over the spatial patches below (needs x and the box) */
+    int precond;
+    const double *x;
+    const double *dom_lo, *dom_hi;
 } op_ctx;
 
 static const double face_normal[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
@@ -1094,6 +1099,169 @@ static double dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Patch block-Jacobi preconditioner.  Patches: the domain box is cut into
+ * cubes of side h = 2 (|box| / n)^(1/dim) (doubled while the grid would have
+ * more than 2^26 cells); a point belongs to the cube floor((x - lo) / h)
+ * (taken as (x - lo) * (1/h), clamped to the grid), cubes are numbered with
+ * the last axis fastest, and the points of one cube in increasing index form
+ * patches of at most ORC_PATCH_MAX consecutive points.  For an ordinate m the
+ * preconditioner solves L_m[P,P] z_P = v_P on every patch P (dense LU with
+ * partial pivoting); the GMRES iterate is unchanged in the limit, only the
+ * iteration count depends on it.                                            */
+#define ORC_PATCH_MAX 16
+
+typedef struct {
+    int64_t np;         /* patches */
+    int64_t *start;     /* [np+1] into pts */
+    int32_t *pts;       /* [n] points, patch by patch */
+} orc_patches;
+
+typedef struct { int64_t cell; int32_t i; } cell_pt;
+
+static int cmp_cell_pt(const void *a, const void *b)
+{
+    const cell_pt *p = (const cell_pt *)a, *q = (const cell_pt *)b;
+    if (p->cell != q->cell) return p->cell < q->cell ? -1 : 1;
+    return p->i < q->i ? -1 : (p->i > q->i);
+}
+
+static void make_patches(const op_ctx *o, orc_patches *pt)
+{
+    int dim = o->dim;
+    int64_t n = o->n;
+    double vol = 1.0;
+    for (int a = 0; a < dim; ++a) vol *= o->dom_hi[a] - o->dom_lo[a];
+    double h = 2.0 * pow(vol / (double)n, 1.0 / dim);
+    int64_t dims[3];
+    for (;;) {
+        int64_t tot = 1;
+        for (int a = 0; a < dim; ++a) {
+            int64_t c = (int64_t)ceil((o->dom_hi[a] - o->dom_lo[a]) / h);
+            dims[a] = c < 1 ? 1 : c;
+            tot *= dims[a];
+        }
+        if (tot <= ((int64_t)1 << 26)) break;
+        h *= 2.0;
+    }
+    double ih = 1.0 / h;
+    cell_pt *cp = (cell_pt *)malloc(sizeof(cell_pt) * n);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t id = 0;
+        for (int a = 0; a < dim; ++a) {
+            double t = (o->x[i * dim + a] - o->dom_lo[a]) * ih;
+            int64_t b = t < 0.0 ? 0 : (int64_t)floor(t);
+            if (b > dims[a] - 1) b = dims[a] - 1;
+            id = id * dims[a] + b;
+        }
+        cp[i].cell = id;
+        cp[i].i = (int32_t)i;
+    }
+    qsort(cp, (size_t)n, sizeof(cell_pt), cmp_cell_pt);
+    pt->pts = (int32_t *)malloc(sizeof(int32_t) * n);
+    pt->start = (int64_t *)malloc(sizeof(int64_t) * (n + 1));
+    pt->np = 0;
+    int64_t run = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        pt->pts[k] = cp[k].i;
+        int fresh = k == 0 || cp[k].cell != cp[k - 1].cell;
+        if (fresh) run = 0;
+        if (fresh || run == ORC_PATCH_MAX) {
+            pt->start[pt->np++] = k;
+            run = 0;
+        }
+        run++;
+    }
+    pt->start[pt->np] = n;
+    free(cp);
+}
+
+/* LU factors (row pivoting) of the patch blocks L_m[P,P] of one ordinate,
+ * from its entries Lv; lu[p] holds s*s values, piv[p] s row indices.  A zero
+ * pivot leaves the block as its diagonal (or 1 where that is 0).            */
+typedef struct {
+    double **lu;
+    int **piv;
+} orc_patch_lu;
+
+static double Lv_at(const op_ctx *o, const double *Lv, int64_t i, int32_t j)
+{
+    for (int64_t p = o->row_off[i]; p < o->row_off[i + 1]; ++p)
+        if (o->col[p] == j) return Lv[p];
+    return 0.0;
+}
+
+static void patch_factor(const op_ctx *o, const orc_patches *pt, const double *Lv, orc_patch_lu *f)
+{
+    f->lu = (double **)malloc(sizeof(double *) * pt->np);
+    f->piv = (int **)malloc(sizeof(int *) * pt->np);
+    for (int64_t p = 0; p < pt->np; ++p) {
+        int s = (int)(pt->start[p + 1] - pt->start[p]);
+        const int32_t *q = pt->pts + pt->start[p];
+        double *A = (double *)malloc(sizeof(double) * s * s);
+        int *pv = (int *)malloc(sizeof(int) * s);
+        for (int a = 0; a < s; ++a)
+            for (int b = 0; b < s; ++b) A[a * s + b] = Lv_at(o, Lv, q[a], q[b]);
+        int ok = 1;
+        for (int k = 0; k < s; ++k) {
+            int r = k;
+            for (int a = k + 1; a < s; ++a)
+                if (fabs(A[a * s + k]) > fabs(A[r * s + k])) r = a;
+            pv[k] = r;
+            if (A[r * s + k] == 0.0) { ok = 0; break; }
+            if (r != k)
+                for (int b = 0; b < s; ++b) { double t = A[k * s + b]; A[k * s + b] = A[r * s + b]; A[r * s + b] = t; }
+            for (int a = k + 1; a < s; ++a) {
+                double l = A[a * s + k] / A[k * s + k];
+                A[a * s + k] = l;
+                for (int b = k + 1; b < s; ++b) A[a * s + b] -= l * A[k * s + b];
+            }
+        }
+        if (!ok) {
+            /* diagonal fallback: an identity permutation and a diagonal U */
+            for (int a = 0; a < s; ++a) {
+                double d = Lv_at(o, Lv, q[a], q[a]);
+                for (int b = 0; b < s; ++b) A[a * s + b] = 0.0;
+                A[a * s + a] = d != 0.0 ? d : 1.0;
+                pv[a] = a;
+            }
+        }
+        f->lu[p] = A;
+        f->piv[p] = pv;
+    }
+}
+
+/* z = M^-1 v: on every patch, the LU solve of L_m[P,P] z_P = v_P. */
+static void patch_solve(const orc_patches *pt, const orc_patch_lu *f, const double *v, double *z)
+{
+    double t[ORC_PATCH_MAX];
+    for (int64_t p = 0; p < pt->np; ++p) {
+        int s = (int)(pt->start[p + 1] - pt->start[p]);
+        const int32_t *q = pt->pts + pt->start[p];
+        const double *A = f->lu[p];
+        const int *pv = f->piv[p];
+        for (int a = 0; a < s; ++a) t[a] = v[q[a]];
+        for (int k = 0; k < s; ++k) {
+            int r = pv[k];
+            if (r != k) { double u = t[k]; t[k] = t[r]; t[r] = u; }
+        }
+        for (int a = 1; a < s; ++a)
+            for (int b = 0; b < a; ++b) t[a] -= A[a * s + b] * t[b];
+        for (int a = s - 1; a >= 0; --a) {
+            for (int b = a + 1; b < s; ++b) t[a] -= A[a * s + b] * t[b];
+            t[a] /= A[a * s + a];
+        }
+        for (int a = 0; a < s; ++a) z[q[a]] = t[a];
+    }
+}
+
+static void patch_free(const orc_patches *pt, orc_patch_lu *f)
+{
+    for (int64_t p = 0; p < pt->np; ++p) { free(f->lu[p]); free(f->piv[p]); }
+    free(f->lu);
+    free(f->piv);
+}
+
 /* Restarted GMRES with right point-Jacobi preconditioning for L_m x = f,
  * x0 = 0, modified Gram-Schmidt Arnoldi and Givens rotations (Saad,
  * Iterative Methods for Sparse Linear Systems, Alg. 6.9 with right
@@ -1117,6 +1285,14 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
         dinv[i] = d != 0.0 ? 1.0 / d : 1.0;
         x[i] = 0.0;
     }
+    orc_patches pt = {0, NULL, NULL};
+    orc_patch_lu plu = {NULL, NULL};
+    double *u = NULL;
+    if (o->precond == 1) {
+        make_patches(o, &pt);
+        patch_factor(o, &pt, Lv, &plu);
+        u = (double *)malloc(sizeof(double) * n);
+    }
     double fn = sqrt(dot(n, f, f));
     int64_t its = 0;
     double rel = 0.0;
@@ -1133,7 +1309,9 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
         int jend = 0;
         for (int j = 0; j < k; ++j) {
             const double *vj = Vb + (int64_t)j * n;
-            for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * vj[i];
+            if (o->precond == 1) patch_solve(&pt, &plu, vj, z);
+            else
+                for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * vj[i];
             apply_Lv(o, Lv, z, w);
             for (int q = 0; q <= j; ++q) {
                 const double *vq = Vb + (int64_t)q * n;
@@ -1167,13 +1345,28 @@ static int64_t gmres_L(const op_ctx *o, int m, const double *f, double *x, doubl
             for (int p = q + 1; p < jend; ++p) s -= H[q * k + p] * yv[p];
             yv[q] = s / H[q * k + q];
         }
-        for (int q = 0; q < jend; ++q) {
-            const double *vq = Vb + (int64_t)q * n;
-            for (int64_t i = 0; i < n; ++i) x[i] += dinv[i] * yv[q] * vq[i];
+        if (o->precond == 1) {
+            /* x += M^-1 (V y) */
+            for (int64_t i = 0; i < n; ++i) u[i] = 0.0;
+            for (int q = 0; q < jend; ++q) {
+                const double *vq = Vb + (int64_t)q * n;
+                for (int64_t i = 0; i < n; ++i) u[i] += yv[q] * vq[i];
+            }
+            patch_solve(&pt, &plu, u, z);
+            for (int64_t i = 0; i < n; ++i) x[i] += z[i];
+        } else {
+            for (int q = 0; q < jend; ++q) {
+                const double *vq = Vb + (int64_t)q * n;
+                for (int64_t i = 0; i < n; ++i) x[i] += dinv[i] * yv[q] * vq[i];
+            }
         }
     }
 done:
     *res = rel;
+    if (o->precond == 1) {
+        patch_free(&pt, &plu);
+        free(pt.start); free(pt.pts); free(u);
+    }
     free(Lv); free(Vb); free(z); free(w); free(r); free(dinv); free(H); free(cs); free(sn); free(g); free(yv);
     return its;
 }
@@ -1459,6 +1652,32 @@ void orc_point_values(int64_t n, const int64_t *row_off, const int32_t *col, con
             for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) s += E[p] * coef[(int64_t)col[p] * ncomp + c];
             out[i * ncomp + c] = s;
         }
+}
+
+/* The patches of the preconditioner (for tests): returns the count, fills
+ * start[np+1] and pts[n] (both sized by the caller: n+1 and n).            */
+int64_t orc_patches_of(op_ctx *o, int64_t *start, int32_t *pts)
+{
+    orc_patches pt;
+    make_patches(o, &pt);
+    for (int64_t p = 0; p <= pt.np; ++p) start[p] = pt.start[p];
+    for (int64_t k = 0; k < o->n; ++k) pts[k] = pt.pts[k];
+    int64_t np = pt.np;
+    free(pt.start); free(pt.pts);
+    return np;
+}
+
+/* z = M^-1 v for ordinate m (for tests): v, z [n]. */
+void orc_patch_precond(op_ctx *o, int m, const double *v, double *z)
+{
+    orc_patches pt;
+    orc_patch_lu plu;
+    double *Lv = L_values(o, m);
+    make_patches(o, &pt);
+    patch_factor(o, &pt, Lv, &plu);
+    patch_solve(&pt, &plu, v, z);
+    patch_free(&pt, &plu);
+    free(pt.start); free(pt.pts); free(Lv);
 }
 
 int orc_num_threads(void)

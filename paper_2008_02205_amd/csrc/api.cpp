@@ -28,6 +28,8 @@ void Problem::release()
     d32.release(); mr.release(); rn2.release(); fn2.release(); tolv.release();
     dsaC.release(); dsaMs.release(); dsa_dinv.release(); dsa_r.release(); dsa_x.release(); dsa_t.release();
     dsa.release();
+    poff.release(); boff.release(); pidx.release(); binv.release(); binv32.release();
+    patches_ok = binv_ok = false;
 }
 
 namespace {
@@ -85,11 +87,25 @@ struct SolveCounters {
     int solves = 0;
 };
 
+template <class T>
+PatchPrecT<T> patch_prec(const Problem &P, const T *binv)
+{
+    PatchPrecT<T> pp;
+    pp.npatch = P.npatch;
+    pp.poff = P.poff.p;
+    pp.pidx = P.pidx.p;
+    pp.boff = P.boff.p;
+    pp.binv = binv;
+    return pp;
+}
+
 int inner_solve_fp64(Problem &P, SolveCounters &c, const double *f, double *x, hipStream_t s)
 {
-    return gmres_batched<double>(P, P.inner, op_L, true, nullptr, P.dinv.p, f, x, P.n, P.n_ord, c.o->tol_inner,
-                                 c.o->restart_inner, c.o->max_inner, c.o->check_every, true, s, &c.its, &c.sweeps,
-                                 &c.res_max, &c.conv);
+    const bool patch = c.o->precond == MLPG_PRECOND_PATCH;
+    const PatchPrecT<double> pp = patch_prec<double>(P, P.binv.p);
+    return gmres_batched<double>(P, P.inner, op_L, true, nullptr, patch ? nullptr : P.dinv.p, f, x, P.n, P.n_ord,
+                                 c.o->tol_inner, c.o->restart_inner, c.o->max_inner, c.o->check_every, true, s,
+                                 &c.its, &c.sweeps, &c.res_max, &c.conv, nullptr, false, patch ? &pp : nullptr);
 }
 
 // Mixed precision: iterative refinement in FP64 around FP32 GMRES.
@@ -145,9 +161,11 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         bool c32 = true;
         double rm32 = 0.0;
         const int cap = std::min(o.max_inner, 10 * o.restart_inner);
-        int rc = gmres_batched<float>(P, P.inner32, op_L32, true, nullptr, P.dinv32.p, P.r32.p, P.d32.p, n, M,
-                                      o.tol_inner_lo, o.restart_inner, cap, o.check_every, true, s, &c.its,
-                                      &c.sweeps, &rm32, &c32, P.tolv.p);
+        const bool patch = o.precond == MLPG_PRECOND_PATCH;
+        const PatchPrecT<float> pp32 = patch_prec<float>(P, P.binv32.p);
+        int rc = gmres_batched<float>(P, P.inner32, op_L32, true, nullptr, patch ? nullptr : P.dinv32.p, P.r32.p,
+                                      P.d32.p, n, M, o.tol_inner_lo, o.restart_inner, cap, o.check_every, true, s,
+                                      &c.its, &c.sweeps, &rm32, &c32, P.tolv.p, false, patch ? &pp32 : nullptr);
         MLPG_HIP(hipStreamSynchronize(s));   // tolm is read by the copy above
         if (rc) return rc;
         MLPG_HIP(launch_axpy_from_float(n, M, x, P.d32.p, P.rn2.p, s));
@@ -161,9 +179,11 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         // FP64 completion from the current iterate
         bool c64 = true;
         double rm = 0.0;
-        int rc = gmres_batched<double>(P, P.inner, op_L, true, nullptr, P.dinv.p, f, x, n, M, o.tol_inner,
-                                       o.restart_inner, o.max_inner, o.check_every, false, s, &c.its, &c.sweeps,
-                                       &rm, &c64);
+        const bool patch = o.precond == MLPG_PRECOND_PATCH;
+        const PatchPrecT<double> pp = patch_prec<double>(P, P.binv.p);
+        int rc = gmres_batched<double>(P, P.inner, op_L, true, nullptr, patch ? nullptr : P.dinv.p, f, x, n, M,
+                                       o.tol_inner, o.restart_inner, o.max_inner, o.check_every, false, s, &c.its,
+                                       &c.sweeps, &rm, &c64, nullptr, false, patch ? &pp : nullptr);
         if (rc) return rc;
         c.fp64_completions++;
         conv = c64;
@@ -321,6 +341,7 @@ static int build_geometry(Problem &P, const double *x, const double *R, const in
     } while (0)
     P.failed = 0;
     P.oversize = 0;
+    P.patches_ok = P.binv_ok = false;   // patches follow the positions, inverses the operators
     int64_t nnz_nb = 0;
     TRY(hipMemcpyAsync(&nnz_nb, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
@@ -655,6 +676,7 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
                    "mlpg_assemble: need 0 <= sigma_s <= sigma_t");
     hipStream_t s = S(stream);
     const int d = P->dim;
+    P->binv_ok = false;   // the patch inverses belong to the previous operators
     P->n_ord = n_ord;
     P->a0 = inv_c_dt;
     P->precision = precision;
@@ -787,6 +809,29 @@ int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *strea
     return MLPG_OK;
 }
 
+int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t *n_patches, void *stream)
+{
+    int rc = check_stage(h, 3, "mlpg_apply_patch_precond");
+    if (rc) return rc;
+    MLPG_CHECK(X && Y && X != Y, MLPG_ERR_ARG, "mlpg_apply_patch_precond: need distinct X and Y");
+    Problem *P = h;
+    hipStream_t s = S(stream);
+    if (!P->patches_ok) {
+        rc = build_patches(*P, s);
+        if (rc) return rc;
+        P->patches_ok = true;
+    }
+    if (!P->binv_ok) {
+        rc = build_patch_inverses(*P, s);
+        if (rc) return rc;
+        P->binv_ok = true;
+    }
+    PatchPrecT<double> pp = patch_prec<double>(*P, P->binv.p);
+    MLPG_HIP(launch_patch_apply<double>(pp, P->n_ord, X, Y, false, nullptr, s));
+    if (n_patches) *n_patches = P->npatch;
+    return MLPG_OK;
+}
+
 void mlpg_default_opts(mlpg_solve_opts *o)
 {
     if (!o) return;
@@ -800,6 +845,7 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->tol_inner_lo = 3e-5;
     o->max_refine = 12;
     o->accel = MLPG_ACCEL_NONE;
+    o->precond = MLPG_PRECOND_JACOBI;
 }
 
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)
@@ -852,8 +898,23 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     MLPG_CHECK(P_ok_lo(o), MLPG_ERR_ARG, "mlpg_solve: tol_inner_lo must be in (0, 1)");
     MLPG_CHECK(o.accel == MLPG_ACCEL_NONE || o.accel == MLPG_ACCEL_DSA, MLPG_ERR_ARG,
                "mlpg_solve: accel must be MLPG_ACCEL_NONE or MLPG_ACCEL_DSA");
+    MLPG_CHECK(o.precond == MLPG_PRECOND_JACOBI || o.precond == MLPG_PRECOND_PATCH, MLPG_ERR_ARG,
+               "mlpg_solve: precond must be MLPG_PRECOND_JACOBI or MLPG_PRECOND_PATCH");
     Problem *P = h;
     hipStream_t s = S(stream);
+    if (o.precond == MLPG_PRECOND_PATCH) {
+        // built on first use after a change of positions or operators
+        if (!P->patches_ok) {
+            rc = build_patches(*P, s);
+            if (rc) return rc;
+            P->patches_ok = true;
+        }
+        if (!P->binv_ok) {
+            rc = build_patch_inverses(*P, s);
+            if (rc) return rc;
+            P->binv_ok = true;
+        }
+    }
     const int64_t n = P->n;
     const int M = P->n_ord;
     SolveCounters c;

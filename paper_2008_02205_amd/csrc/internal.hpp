@@ -33,6 +33,7 @@ constexpr int kMaxFields = 8;    // smooth material fields per problem
 constexpr int kMaxMat = 8;       // materials per problem
 constexpr double kMixedOuterFloor = 1e-10;   // tightest outer tolerance of the mixed path
 constexpr int kTagBox = -100;      // edge of the kernel box not on the domain
+constexpr int kPatchMax = 16;      // points per patch of the block-Jacobi preconditioner
 
 // Thread-local error message for mlpg_last_error.
 void set_error(const std::string &msg);
@@ -135,6 +136,18 @@ struct KrylovT {
 };
 using Krylov = KrylovT<double>;
 
+// Patch block-Jacobi right preconditioner of the inner solves (patches.hip):
+// patch p holds the points pidx[poff[p] .. poff[p+1]) and the inverse of
+// L_m restricted to them, binv[boff[p] M + (i s + j) M + m].
+template <class T>
+struct PatchPrecT {
+    int64_t npatch = 0;
+    const int64_t *poff = nullptr;
+    const int32_t *pidx = nullptr;
+    const int64_t *boff = nullptr;
+    const T *binv = nullptr;
+};
+
 struct Problem {
     int dim = 0;
     int64_t n = 0;
@@ -211,10 +224,27 @@ struct Problem {
     // pattern, 1/diag(C), and the diffusion solve's workspace
     DevBuf<double> dsaC, dsaMs, dsa_dinv, dsa_r, dsa_x, dsa_t;
     Krylov dsa;
+    // patch block-Jacobi preconditioner (mlpg_solve_opts.precond): patches of
+    // the current positions, block inverses of the current operators
+    int64_t npatch = 0, nbsq = 0, patch_singular = 0;
+    DevBuf<int64_t> poff, boff;
+    DevBuf<int32_t> pidx;
+    DevBuf<double> binv;
+    DevBuf<float> binv32;
+    bool patches_ok = false, binv_ok = false;
     int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
 
     void release();
 };
+
+// Patch block-Jacobi preconditioner (patches.hip): patches of the current
+// points, then the block inverses of the assembled operators (FP32 copies in
+// the mixed path); out = M^-1 in (add: out += M^-1 in).
+int build_patches(Problem &P, hipStream_t s);
+int build_patch_inverses(Problem &P, hipStream_t s);
+template <class T>
+hipError_t launch_patch_apply(const PatchPrecT<T> &pp, int M, const T *in, T *out, bool add, const int *gate,
+                              hipStream_t s);
 
 // Progress callback (mlpg_set_progress); no-op when unset.
 void report_progress(int level, int64_t iters, double resid);
@@ -313,7 +343,8 @@ template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged,
-                  const double *tolv = nullptr, bool cheap_op = false);   // optional per-system relative tolerance (device [nb])
+                  const double *tolv = nullptr, bool cheap_op = false,   // optional per-system relative tolerance (device [nb])
+                  const PatchPrecT<T> *pp = nullptr);   // patch block-Jacobi instead of dinv (dinv must be null)
 // out[m] = sum_i x[i][m]^2 for the nb systems of K's shape
 hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s);
 

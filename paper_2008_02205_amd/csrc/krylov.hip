@@ -560,6 +560,22 @@ __global__ __launch_bounds__(kThreads) void x_update_kernel(int64_t n, int nb, i
     x[t] = (T)((double)x[t] + (dinv ? (double)dinv[t] * s : s));
 }
 
+// out = V y over each system's own columns (the patch preconditioner is then
+// applied to it and added to x).
+template <class T>
+__global__ __launch_bounds__(kThreads) void vy_kernel(int64_t n, int nb, int nq, const T *__restrict__ V,
+                                                      int64_t vstride, const double *__restrict__ y,
+                                                      const int *__restrict__ jend, T *__restrict__ out)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nb) return;
+    int m = (int)(t % nb);
+    const int je = jend[m] < nq ? jend[m] : nq;
+    double s = 0.0;
+    for (int q = 0; q < je; ++q) s += y[q * nb + m] * (double)V[q * vstride + t];
+    out[t] = (T)s;
+}
+
 // r = f - r
 template <class T>
 __global__ void residual_kernel(int64_t count, const T *__restrict__ f, T *__restrict__ r)
@@ -740,9 +756,10 @@ template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged, const double *tolv,
-                  bool cheap_op)
+                  bool cheap_op, const PatchPrecT<T> *pp)
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
+    MLPG_CHECK(!(pp && dinv), MLPG_ERR_ARG, "batched GMRES: one right preconditioner at a time");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
     MLPG_HIP(K.ensure(n, nb, restart));
     if (lag < 1) lag = 1;
@@ -808,6 +825,11 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             c.gate = gate;
             if (j == 0 || !fused) {
                 c.in = K.V.p + (int64_t)j * K.vs;
+                if (pp) {
+                    // the operator's input is M^-1 v_j
+                    MLPG_HIP(launch_patch_apply<T>(*pp, nb, c.in, K.z.p, false, gate, s));
+                    c.in = K.z.p;
+                }
             } else {
                 // z = dinv .* w_{j-1}, scaled by 1/beta; the SpMV also stores
                 // the normalised new vector u_j in basis slot j
@@ -826,7 +848,9 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                 K.fnorm.p, tol, tolv, max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nnext,
                 nact + ((j + 2) % 3));
             const int slot = (int)(sw % kSlots);
-            MLPG_HIP(pass_b<T>(K, j, wcur, dinv, fused ? K.z.p : nullptr, nnext, K.nactive_hdev + slot, s));
+            MLPG_HIP(pass_b<T>(K, j, wcur, dinv, (fused && !pp) ? K.z.p : nullptr, nnext, K.nactive_hdev + slot, s));
+            // the next operator input M^-1 w_j (normalised inside the next sweep)
+            if (fused && pp && j < k - 1) MLPG_HIP(launch_patch_apply<T>(*pp, nb, wcur, K.z.p, false, nnext, s));
             MLPG_HIP(hipEventRecord(K.ev[slot], s));
             sw++;
             jc = j + 1;
@@ -852,7 +876,13 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                 max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nact + ((k + 1) % 3), nullptr);
         }
         lsq_kernel<<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
-        x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, dinv, x);
+        if (pp) {
+            // x += M^-1 (V y)
+            vy_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, K.z.p);
+            MLPG_HIP(launch_patch_apply<T>(*pp, nb, K.z.p, x, true, nullptr, s));
+        } else {
+            x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, dinv, x);
+        }
         OpCallT<T> c;
         c.in = x;
         c.out = K.r.p;
@@ -892,9 +922,11 @@ template struct KrylovT<double>;
 template struct KrylovT<float>;
 template int gmres_batched<double>(Problem &, KrylovT<double> &, OpFnT<double>, bool, void *, const double *,
                                    const double *, double *, int64_t, int, double, int, int, int, bool, hipStream_t,
-                                   int64_t *, int64_t *, double *, bool *, const double *, bool);
+                                   int64_t *, int64_t *, double *, bool *, const double *, bool,
+                                   const PatchPrecT<double> *);
 template int gmres_batched<float>(Problem &, KrylovT<float> &, OpFnT<float>, bool, void *, const float *,
                                   const float *, float *, int64_t, int, double, int, int, int, bool, hipStream_t,
-                                  int64_t *, int64_t *, double *, bool *, const double *, bool);
+                                  int64_t *, int64_t *, double *, bool *, const double *, bool,
+                                  const PatchPrecT<float> *);
 
 }  // namespace mlpg

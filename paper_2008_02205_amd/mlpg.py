@@ -20,6 +20,7 @@ MLPG_FP64, MLPG_MIXED = 0, 1
 MLPG_QUAD_PRODUCT, MLPG_QUAD_BEAM_DENSE = 0, 1
 MLPG_OP_L, MLPG_OP_T, MLPG_OP_MS, MLPG_OP_SRC = 0, 1, 2, 3
 MLPG_ACCEL_NONE, MLPG_ACCEL_DSA = 0, 1
+MLPG_PRECOND_JACOBI, MLPG_PRECOND_PATCH = 0, 1
 STATUS = {0: "MLPG_OK", -1: "MLPG_ERR_ARG", -2: "MLPG_ERR_HIP", -3: "MLPG_ERR_CAPACITY",
           -4: "MLPG_ERR_NOT_CONVERGED", -5: "MLPG_ERR_GEOMETRY", -7: "MLPG_ERR_STATE"}
 
@@ -29,7 +30,7 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
            "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress",
            "mlpg_material_fields", "mlpg_update_points", "mlpg_refined_quadrature",
-           "mlpg_material_shells"]
+           "mlpg_material_shells", "mlpg_apply_patch_precond"]
 
 
 class MlpgError(RuntimeError):
@@ -48,7 +49,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol_inner", C.c_double), ("tol_outer", C.c_double), ("restart_inner", C.c_int),
                 ("restart_outer", C.c_int), ("max_inner", C.c_int), ("max_outer", C.c_int),
                 ("check_every", C.c_int), ("tol_inner_lo", C.c_double), ("max_refine", C.c_int),
-                ("accel", C.c_int)]
+                ("accel", C.c_int), ("precond", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -89,6 +90,7 @@ def lib() -> C.CDLL:
         L.mlpg_get_blocks.argtypes = [vp, vp, vp, vp]
         L.mlpg_assemble.argtypes = [vp, i32, vp, vp, i32, vp, vp, dbl, vp, i32, vp]
         L.mlpg_apply.argtypes = [vp, i32, vp, vp, vp]
+        L.mlpg_apply_patch_precond.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), vp]
         L.mlpg_default_opts.restype = None
         L.mlpg_default_opts.argtypes = [C.POINTER(SolveOpts)]
         L.mlpg_set_state.argtypes = [vp, vp, vp]
@@ -298,6 +300,14 @@ def mlpg_apply(h, which: int, X):
     Y = _empty(X.shape)
     _check(lib().mlpg_apply(h, which, _dev(X), _dev(Y), _stream()))
     return Y
+
+
+def mlpg_apply_patch_precond(h, X):
+    """Y = M^-1 X with the patch block-Jacobi preconditioner; returns (Y, patch count)."""
+    Y = _empty(X.shape)
+    npt = C.c_int64(0)
+    _check(lib().mlpg_apply_patch_precond(h, _dev(X), _dev(Y), C.byref(npt), _stream()))
+    return Y, npt.value
 
 
 def mlpg_default_opts() -> SolveOpts:

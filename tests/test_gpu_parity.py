@@ -280,7 +280,7 @@ def test_malformed_overlap_lists_are_rejected():
     boff = off.copy(); boff[0] = 1; cases["offsets not from 0"] = (boff, idx)
     for name, (o_, i_) in cases.items():
         with pytest.raises(mlpg.MlpgError) as e:
-            mlpg.mlpg_geometry(2, _dev(x), _dev(R), _dev(o_), _dev(i_), (0, 0), (1, 1))
+            mlpg.mlpg_geometry(_dev(x), _dev(R), _dev(o_), _dev(i_), (0, 0), (1, 1))
         assert e.value.code == -1, name
         assert "malformed overlap lists" in str(e.value), name
     # a list with a neighbour missing on both sides passes the check but loses
@@ -291,7 +291,7 @@ def test_malformed_overlap_lists_are_rejected():
     keep[off[j] + int(np.searchsorted(idx[off[j]:off[j + 1]], i))] = False
     cnt = np.diff(off) - np.bincount(np.repeat(np.arange(n), np.diff(off))[~keep], minlength=n)
     off2 = np.concatenate(([0], np.cumsum(cnt))).astype(np.int64)
-    h = mlpg.mlpg_geometry(2, _dev(x), _dev(R), _dev(off2), _dev(idx[keep]), (0, 0), (1, 1))
+    h = mlpg.mlpg_geometry(_dev(x), _dev(R), _dev(off2), _dev(idx[keep]), (0, 0), (1, 1))
     with pytest.raises(mlpg.MlpgError) as e:
         mlpg.mlpg_integrate(h, 1)
     assert e.value.code == -1 and "missing from the overlap lists" in str(e.value)
