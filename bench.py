@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--max-outer", type=int, default=None,
                     help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
     ap.add_argument("--max-inner", type=int, default=None, help="inner-iteration cap per solve (--workload mode)")
+    ap.add_argument("--precond", choices=["jacobi", "patch"], default="jacobi",
+                    help="right preconditioner of the inner solves: point Jacobi or patch block Jacobi")
     ap.add_argument("--accel", action="store_true",
                     help="workload and serving modes: diffusion-synthetic acceleration of the outer iteration")
     ap.add_argument("--probe", action="store_true",
@@ -115,6 +117,7 @@ def main():
         solves = 0
         phi = pv = None
         opts = mlpg.mlpg_default_opts()
+        opts.precond = mlpg.MLPG_PRECOND_PATCH if args.precond == "patch" else mlpg.MLPG_PRECOND_JACOBI
         if args.tol_lo:
             opts.tol_inner_lo = args.tol_lo
         for s in range(w.steps):
@@ -156,7 +159,7 @@ def main():
         opts = mlpg.mlpg_default_opts()
         opts.max_inner = 60
         opts.max_outer = 1
-        mlpg.mlpg_solve(P.h, qs[0], None, opts, want_psi=False, raise_on_error=False)
+        mlpg.mlpg_solve(P.h, qs[0], None, opts, want_psi=False, raise_on_error=False, ws=P.solve_workspace(opts))
         P.close()
         src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -278,6 +281,7 @@ def other_workload(args):
         its = solves = outer = 0
         conv = True
         opts = mlpg.mlpg_default_opts()
+        opts.precond = mlpg.MLPG_PRECOND_PATCH if args.precond == "patch" else mlpg.MLPG_PRECOND_JACOBI
         if args.accel:
             opts.accel = mlpg.MLPG_ACCEL_DSA
         if args.max_outer:
@@ -298,7 +302,8 @@ def other_workload(args):
                            precision=mlpg.MLPG_FP64 if prec == "fp64" else mlpg.MLPG_MIXED)
                 td = sync_time()
                 mv["geometry_s"] += tb - ta; mv["integrate_s"] += tc - tb; mv["assemble_s"] += td - tc
-            _, pv, _, inf = mlpg.mlpg_solve(P.h, qs[s], pb, opts, want_psi=False, raise_on_error=False)
+            _, pv, _, inf = mlpg.mlpg_solve(P.h, qs[s], pb, opts, want_psi=False, raise_on_error=False,
+                                            ws=P.solve_workspace(opts))
             conv = conv and inf["converged"] == 1
             its += inf["inner_iters"]
             solves += inf["inner_solves"]
@@ -382,11 +387,13 @@ def asteroid_workload(args):
         P.assemble(om, wq, list(st), list(ss), 0.0, dx, precision=mlpg.MLPG_FP64 if prec == "fp64" else mlpg.MLPG_MIXED)
         t3 = sync_time()
         opts = mlpg.mlpg_default_opts()
+        opts.precond = mlpg.MLPG_PRECOND_PATCH if args.precond == "patch" else mlpg.MLPG_PRECOND_JACOBI
         if args.max_inner:
             opts.max_inner = args.max_inner
         if args.accel:
             opts.accel = mlpg.MLPG_ACCEL_DSA
-        _, pv, _, inf = mlpg.mlpg_solve(P.h, q, None, opts, want_psi=False, raise_on_error=False)
+        _, pv, _, inf = mlpg.mlpg_solve(P.h, q, None, opts, want_psi=False, raise_on_error=False,
+                                        ws=P.solve_workspace(opts))
         t4 = sync_time()
         pv = pv.cpu().numpy()
         P.close()

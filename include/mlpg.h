@@ -20,9 +20,19 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   - Arrays of per-point, per-ordinate values are [n][n_ord] with the
  *     ordinate index fastest.  Points keep the caller's order.
- *   - The handle owns every device allocation it makes (hipMalloc); they are
- *     released by mlpg_destroy.  A handle is not thread-safe; separate
- *     handles may be used concurrently on separate streams.
+ *   - Device memory: the four stage calls (and mlpg_update_points,
+ *     mlpg_apply_patch_precond) take a caller-owned workspace, a device
+ *     buffer of at least the bytes its *_workspace_bytes query returns,
+ *     256-byte aligned; the stage carves all of its buffers and temporaries
+ *     out of it and the handle keeps pointers into it, so every workspace
+ *     must stay allocated and untouched until it is replaced by the same
+ *     stage or the handle is destroyed.  A smaller workspace fails with
+ *     MLPG_ERR_WORKSPACE before anything is enqueued.  A NULL workspace makes
+ *     the library allocate one of the queried size itself (released by
+ *     mlpg_destroy).  Host-side, a handle holds a few pinned host words and
+ *     HIP events for its Krylov loops.  mlpg_neighbors_count allocates a
+ *     temporary of n counts.  A handle is not thread-safe; separate handles
+ *     may be used concurrently on separate streams.
  *   - Every call returns MLPG_OK (0) or a negative mlpg_status.  Arguments are
  *     validated on the host before anything is enqueued; the message of the
  *     last failure on the calling thread is returned by mlpg_last_error().
@@ -46,6 +56,7 @@ typedef enum {
     MLPG_ERR_CAPACITY = -3,       /* a fixed per-cell or per-point capacity was exceeded */
     MLPG_ERR_NOT_CONVERGED = -4,  /* a Krylov solve hit its iteration limit */
     MLPG_ERR_GEOMETRY = -5,       /* a cell came out empty or a moment matrix stayed singular */
+    MLPG_ERR_WORKSPACE = -6,      /* a workspace smaller than its *_workspace_bytes query */
     MLPG_ERR_STATE = -7           /* stage called out of order */
 } mlpg_status;
 
@@ -140,7 +151,15 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
 int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R,
                   const int64_t *nbr_off, const int32_t *nbr_idx, const double *dom_lo,
                   const double *dom_hi, int n_regions, const double *region_lo, const double *region_hi,
-                  const int32_t *region_mat, void *stream);
+                  const int32_t *region_mat, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of the geometry workspace for n points with nnz_nbr overlap-list
+ * entries in the box [dom_lo, dom_hi] (host [dim]): copies of the inputs,
+ * the cells (2D: 32 vertices per cell; 3D: 40 faces of 16 vertices), the
+ * pattern, the preconditioner patches and the stage's temporaries.  0 for
+ * invalid arguments. */
+size_t mlpg_geometry_workspace_bytes(int dim, int64_t n, int64_t nnz_nbr, const double *dom_lo,
+                                     const double *dom_hi);
 
 /* ------------------------------------------------------------------------
  * Moving points (Sec. 1: with points that move every time step, as in
@@ -160,7 +179,7 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
  * destroyed), MLPG_ERR_ARG for null pointers.
  * ---------------------------------------------------------------------- */
 int mlpg_update_points(mlpg_handle h, const double *x, const double *R, const int64_t *nbr_off,
-                       const int32_t *nbr_idx, void *stream);
+                       const int32_t *nbr_idx, void *workspace, size_t ws_bytes, void *stream);
 
 typedef struct {
     int64_t n;               /* points */
@@ -253,7 +272,13 @@ int mlpg_material_shells(mlpg_handle h, int n_shells, const double *center, cons
  * functions active at one quadrature point are not overlap neighbours (the
  * caller's lists were incomplete; the blocks would silently lose entries).
  * ---------------------------------------------------------------------- */
-int mlpg_integrate(mlpg_handle h, int rk_order, void *stream);
+int mlpg_integrate(mlpg_handle h, int rk_order, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of the integration workspace of handle h (after mlpg_geometry and any
+ * mlpg_material_fields / mlpg_material_shells, which set the material
+ * count): the blocks, the point-value matrix, the boundary quadrature and the
+ * surface-row offsets.  0 before mlpg_geometry or for an invalid order. */
+size_t mlpg_integrate_workspace_bytes(mlpg_handle h, int rk_order);
 
 /* Pattern and blocks for parity checks.  row_off: device [n+1]; col: device
  * [nnz]; blocks: device [n_blocks][nnz] in the order
@@ -283,7 +308,15 @@ int mlpg_get_blocks(mlpg_handle h, double *blocks, double *E, void *stream);
  * ---------------------------------------------------------------------- */
 int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w, int n_mat,
                   const double *sigma_t, const double *sigma_s, double inv_c_dt, const double *tau,
-                  int precision, void *stream);
+                  int precision, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of the assembly workspace (after mlpg_integrate): the state Psi, Phi
+ * (kept at the start of the workspace: passing the same workspace again with
+ * the same n_ord keeps the state; a different one receives a copy of it, and
+ * the previous one must stay valid until the call returns), the value
+ * streams, coefficient tables, surface rows, Jacobi scaling, the
+ * diffusion-synthetic operators and, for MLPG_MIXED, the FP32 copies. */
+size_t mlpg_assemble_workspace_bytes(mlpg_handle h, int n_ord, int precision);
 
 /* One operator application Y = op X for all ordinates (parity accessor):
  * which = MLPG_OP_L, MLPG_OP_T, MLPG_OP_MS or MLPG_OP_SRC (Mass + tau W.D);
@@ -352,10 +385,12 @@ typedef struct {
 enum { MLPG_PRECOND_JACOBI = 0, MLPG_PRECOND_PATCH = 1 };
 
 /* Y = M^-1 X for every ordinate with the patch block-Jacobi preconditioner
- * of the assembled operators (parity accessor; builds the patches and the
- * inverses when they are not current).  X, Y: device [n][n_ord], distinct;
- * *n_patches (host, may be NULL) gets the patch count. */
-int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t *n_patches, void *stream);
+ * of the assembled operators (parity accessor; builds the inverses when they
+ * are not current).  X, Y: device [n][n_ord], distinct; *n_patches (host, may
+ * be NULL) gets the patch count; workspace: a solve workspace for options
+ * with precond = MLPG_PRECOND_PATCH (or NULL). */
+int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t *n_patches, void *workspace,
+                             size_t ws_bytes, void *stream);
 
 /* Acceleration of the scattering iteration (Sec. 6 names it as needed for
  * scattering-dominated problems; Sec. 4.2 runs the outer GMRES without a
@@ -391,7 +426,16 @@ void mlpg_default_opts(mlpg_solve_opts *o);
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream);
 int mlpg_get_state(mlpg_handle h, double *psi, double *phi, void *stream);
 int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_coef, double *phi_point,
-               double *psi_out, const mlpg_solve_opts *opts, mlpg_solve_info *info, void *stream);
+               double *psi_out, const mlpg_solve_opts *opts, mlpg_solve_info *info, void *workspace,
+               size_t ws_bytes, void *stream);
+
+/* Bytes of the solve workspace for opts (NULL: defaults) after mlpg_assemble:
+ * right-hand sides and intermediate fields, the batched inner Krylov space
+ * (restart_inner), the outer one (restart_outer), the FP32 space and
+ * refinement vectors of MLPG_MIXED, the diffusion solve's space of
+ * MLPG_ACCEL_DSA and the patch inverses of MLPG_PRECOND_PATCH (rebuilt when
+ * the operators change or the workspace moves).  0 for invalid options. */
+size_t mlpg_solve_workspace_bytes(mlpg_handle h, const mlpg_solve_opts *opts);
 
 /* Point values out[i] = sum_j N_j(x_i) coef[j] (Eq. flux-expansion);
  * coef, out: device [n]. */

@@ -30,6 +30,10 @@ void Problem::release()
     dsa.release();
     poff.release(); boff.release(); pidx.release(); binv.release(); binv32.release();
     patches_ok = binv_ok = false;
+    tmp_flags.release(); tmp_cand.release(); tmp_bqc.release(); tmp_key.release(); tmp_s2.release();
+    tmp_npc.release(); tmp_off.release(); tmp_pbase.release(); tmp_scnt.release(); tmp_cnt.release();
+    tmp_sing.release(); tmp_work.release();
+    own_geo.release(); own_int.release(); own_asm.release(); own_slv.release();
 }
 
 namespace {
@@ -123,12 +127,10 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
     const int M = P.n_ord;
     const int64_t cnt = n * M;
     const mlpg_solve_opts &o = *c.o;
-    MLPG_HIP(P.inner.ensure(n, M, o.restart_inner));
     MLPG_HIP(hipMemsetAsync(x, 0, sizeof(double) * cnt, s));
     MLPG_HIP(hipMemcpyAsync(P.mr.p, f, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
     MLPG_HIP(batched_norm2(P.inner, f, P.fn2.p, s));
     std::vector<double> fn2(M), rn2(M), tolm(M);
-    MLPG_HIP(P.tolv.alloc(M));
     MLPG_HIP(hipMemcpyAsync(fn2.data(), P.fn2.p, sizeof(double) * M, hipMemcpyDeviceToHost, s));
     bool conv = false, stalled = false;
     double worst = 0.0;
@@ -284,6 +286,47 @@ int check_stage(mlpg_handle h, int need, const char *who)
     return MLPG_OK;
 }
 
+// Binds a stage's buffers: into the caller's workspace `ws` (at least the
+// measured size, 256-byte aligned), or, when ws is null, into a library
+// allocation `own` of the measured size (grown when needed).
+template <class F>
+static int bind_stage(Problem &P, DevBuf<char> &own, void *ws, size_t ws_bytes, const char *who, F layout)
+{
+    // measured on a copy, so that a workspace that is too small leaves the
+    // handle's current buffers as they were
+    Arena m;
+    {
+        Problem tmp = P;
+        layout(tmp, m);
+    }
+    const size_t need = m.used;
+    Arena A;
+    if (ws) {
+        if (((uintptr_t)ws & 255) != 0) {
+            set_error(std::string(who) + ": the workspace must be 256-byte aligned");
+            return MLPG_ERR_ARG;
+        }
+        if (ws_bytes < need) {
+            set_error(std::string(who) + ": workspace of " + std::to_string(ws_bytes) + " bytes, the stage needs " +
+                      std::to_string(need));
+            return MLPG_ERR_WORKSPACE;
+        }
+        own.release();
+        A.base = (char *)ws;
+        A.cap = ws_bytes;
+    } else {
+        if (!own.p || !own.owned || own.count < need) MLPG_HIP(own.alloc(need));
+        A.base = own.p;
+        A.cap = own.count;
+    }
+    layout(P, A);
+    if (A.over || A.used != need) {
+        set_error(std::string(who) + ": workspace layout mismatch");
+        return MLPG_ERR_WORKSPACE;
+    }
+    return MLPG_OK;
+}
+
 }  // namespace
 }  // namespace mlpg
 
@@ -324,10 +367,11 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
 }
 
 // Positions, radii and overlap lists of the points, then the cells (Sec. 3.1),
-// the boundary quadrature sizing and the pattern: the part of stage 1 that
-// depends on where the points are.  Reallocates what grew; counters reset.
+// the boundary quadrature sizing, the pattern and the preconditioner patches:
+// the part of stage 1 that depends on where the points are.  Every buffer is
+// carved from the geometry workspace; counters reset.
 static int build_geometry(Problem &P, const double *x, const double *R, const int64_t *nbr_off,
-                          const int32_t *nbr_idx, hipStream_t s)
+                          const int32_t *nbr_idx, void *ws, size_t ws_bytes, const char *who, hipStream_t s)
 {
     const int64_t n = P.n;
     const int dim = P.dim;
@@ -346,20 +390,26 @@ static int build_geometry(Problem &P, const double *x, const double *R, const in
     TRY(hipMemcpyAsync(&nnz_nb, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
     if (nnz_nb < 0 || nnz_nb > ((int64_t)1 << 40)) {
-        set_error("mlpg_geometry: neighbour list size out of range");
+        set_error(std::string(who) + ": neighbour list size out of range");
         return MLPG_ERR_ARG;
     }
     P.nnz_nb = nnz_nb;
-    TRY(P.x.alloc(n * dim));
-    TRY(P.R.alloc(n));
-    TRY(P.nb_off.alloc(n + 1));
-    TRY(P.nb_idx.alloc(std::max<int64_t>(1, nnz_nb)));
+    int64_t dims[3];
+    P.ncell = patch_grid_cells(dim, n, P.dom_lo, P.dom_hi, nullptr, dims);
+    int rc = bind_stage(P, P.own_geo, ws, ws_bytes, who,
+                        [&](Problem &Q, Arena &A) { layout_geometry(Q, A, nnz_nb); });
+    if (rc) return rc;
+    P.ws_geo = ws;
+    if (P.n_regions) {
+        TRY(hipMemcpyAsync(P.reg_lo.p, P.reg_lo_h, sizeof(double) * P.n_regions * dim, hipMemcpyHostToDevice, s));
+        TRY(hipMemcpyAsync(P.reg_hi.p, P.reg_hi_h, sizeof(double) * P.n_regions * dim, hipMemcpyHostToDevice, s));
+        TRY(hipMemcpyAsync(P.reg_mat.p, P.reg_mat_h, sizeof(int32_t) * P.n_regions, hipMemcpyHostToDevice, s));
+    }
     TRY(hipMemcpyAsync(P.x.p, x, sizeof(double) * n * dim, hipMemcpyDeviceToDevice, s));
     TRY(hipMemcpyAsync(P.R.p, R, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     TRY(hipMemcpyAsync(P.nb_off.p, nbr_off, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToDevice, s));
     if (nnz_nb) TRY(hipMemcpyAsync(P.nb_idx.p, nbr_idx, sizeof(int32_t) * nnz_nb, hipMemcpyDeviceToDevice, s));
     // the lists steer every later kernel's reads: validate them before use
-    TRY(P.counters.alloc(kNumCounters));
     TRY(hipMemsetAsync(P.counters.p, 0, sizeof(unsigned long long) * kNumCounters, s));
     TRY(launch_check_lists(n, nnz_nb, P.nb_off.p, P.nb_idx.p, P.counters.p + kBadLists, s));
     {
@@ -367,70 +417,47 @@ static int build_geometry(Problem &P, const double *x, const double *R, const in
         TRY(hipMemcpyAsync(&bad, P.counters.p + kBadLists, sizeof(bad), hipMemcpyDeviceToHost, s));
         TRY(hipStreamSynchronize(s));
         if (bad) {
-            set_error(std::string("mlpg_geometry: malformed overlap lists (") +
+            set_error(std::string(who) + ": malformed overlap lists (" +
                       ((bad & 1) ? "offsets not non-decreasing from 0 within the list length" :
                                    "an index out of [0, n), equal to its row, or not strictly increasing") +
                       ")");
             return MLPG_ERR_ARG;
         }
     }
-
-    TRY(P.V.alloc(n));
-    TRY(P.rho.alloc(n));
-    DevBuf<int32_t> flags;
-    DevBuf<int64_t> bqc;
-    TRY(flags.alloc(n));
-    TRY(bqc.alloc(n));
-    TRY(P.bq_off.alloc(n + 1));
     if (dim == 2) {
-        TRY(P.nv.alloc(n));
-        TRY(P.tags.alloc(n * kCellCap2D));
-        TRY(P.verts.alloc(n * kCellCap2D * 2));
-        TRY(launch_clip2d(P, s, flags.p, bqc.p));
+        TRY(launch_clip2d(P, s, P.tmp_flags.p, P.tmp_bqc.p));
         P.bq_kmax = kBqAct;
     } else {
-        TRY(P.nf.alloc(n));
-        TRY(P.fnv.alloc(n * kFaceCap3));
-        TRY(P.ftags.alloc(n * kFaceCap3));
-        TRY(P.fverts.alloc(n * kFaceCap3 * kFaceVerts3 * 3));
-        TRY(launch_clip3d(P, s, flags.p, bqc.p));
+        TRY(launch_clip3d(P, s, P.tmp_flags.p, P.tmp_bqc.p));
         P.bq_kmax = kBqAct3;
     }
-    TRY(launch_exclusive_scan(bqc.p, P.bq_off.p, n, s));
+    TRY(launch_exclusive_scan(P.tmp_bqc.p, P.bq_off.p, n, s));
     std::vector<int32_t> hf(n);
-    TRY(hipMemcpyAsync(hf.data(), flags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(hf.data(), P.tmp_flags.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
     TRY(hipMemcpyAsync(&P.n_bq, P.bq_off.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
-    flags.release();
-    bqc.release();
     for (int64_t i = 0; i < n; ++i) {
         if (hf[i] == 1) P.failed++;
         if (hf[i] == 2) P.oversize++;
     }
     if (P.failed) {
-        set_error("mlpg_geometry: " + std::to_string(P.failed) + " cells empty or over the face/vertex capacity");
+        set_error(std::string(who) + ": " + std::to_string(P.failed) +
+                  " cells empty or over the face/vertex capacity");
         return MLPG_ERR_GEOMETRY;
     }
     P.nnz = nnz_nb + n;
-    TRY(P.row_off.alloc(n + 1));
-    TRY(P.col.alloc(P.nnz));
-    TRY(P.diag_pos.alloc(n));
     TRY(launch_pattern(P, s));
-    int64_t nbq = std::max<int64_t>(1, P.n_bq);
-    TRY(P.bq_y.alloc(nbq * dim));
-    TRY(P.bq_w.alloc(nbq));
-    TRY(P.bq_face.alloc(nbq));
-    TRY(P.bq_nact.alloc(nbq));
-    TRY(P.bq_act.alloc(nbq * P.bq_kmax));
-    TRY(P.bq_N.alloc(nbq * P.bq_kmax));
-    TRY(hipStreamSynchronize(s));
 #undef TRY
+    rc = build_patches(P, s);
+    if (rc) return rc;
+    P.patches_ok = true;
     return MLPG_OK;
 }
 
 int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const double *R, const int64_t *nbr_off,
                   const int32_t *nbr_idx, const double *dom_lo, const double *dom_hi, int n_regions,
-                  const double *region_lo, const double *region_hi, const int32_t *region_mat, void *stream)
+                  const double *region_lo, const double *region_hi, const int32_t *region_mat, void *workspace,
+                  size_t ws_bytes, void *stream)
 {
     MLPG_CHECK(out, MLPG_ERR_ARG, "mlpg_geometry: null output handle");
     *out = nullptr;
@@ -449,52 +476,57 @@ int mlpg_geometry(mlpg_handle *out, int dim, int64_t n, const double *x, const d
     }
     hipStream_t s = S(stream);
     mlpg_problem *P = new mlpg_problem();
-    auto fail = [&](int code) {
-        P->release();
-        delete P;
-        return code;
-    };
     P->dim = dim;
     P->n = n;
     P->n_mat = n_mat;
     for (int a = 0; a < dim; ++a) { P->dom_lo[a] = dom_lo[a]; P->dom_hi[a] = dom_hi[a]; }
     P->n_regions = n_regions;
-#define TRY(call)                                                                  \
-    do {                                                                           \
-        hipError_t e_ = (call);                                                    \
-        if (e_ != hipSuccess) {                                                    \
-            set_error(std::string(#call) + ": " + hipGetErrorString(e_));          \
-            return fail(MLPG_ERR_HIP);                                             \
-        }                                                                          \
-    } while (0)
-    TRY(P->reg_lo.alloc(std::max(1, n_regions) * dim));
-    TRY(P->reg_hi.alloc(std::max(1, n_regions) * dim));
-    TRY(P->reg_mat.alloc(std::max(1, n_regions)));
-    if (n_regions) {
-        TRY(hipMemcpyAsync(P->reg_lo.p, region_lo, sizeof(double) * n_regions * dim, hipMemcpyHostToDevice, s));
-        TRY(hipMemcpyAsync(P->reg_hi.p, region_hi, sizeof(double) * n_regions * dim, hipMemcpyHostToDevice, s));
-        TRY(hipMemcpyAsync(P->reg_mat.p, region_mat, sizeof(int32_t) * n_regions, hipMemcpyHostToDevice, s));
+    for (int r = 0; r < n_regions; ++r) {
+        for (int a = 0; a < dim; ++a) {
+            P->reg_lo_h[r * dim + a] = region_lo[r * dim + a];
+            P->reg_hi_h[r * dim + a] = region_hi[r * dim + a];
+        }
+        P->reg_mat_h[r] = region_mat[r];
     }
-    int rc = build_geometry(*P, x, R, nbr_off, nbr_idx, s);
-    if (rc) return fail(rc);
-#undef TRY
+    int rc = build_geometry(*P, x, R, nbr_off, nbr_idx, workspace, ws_bytes, "mlpg_geometry", s);
+    if (rc) {
+        P->release();
+        delete P;
+        return rc;
+    }
     P->stage = 1;
     *out = P;
     return MLPG_OK;
 }
 
 int mlpg_update_points(mlpg_handle h, const double *x, const double *R, const int64_t *nbr_off,
-                       const int32_t *nbr_idx, void *stream)
+                       const int32_t *nbr_idx, void *workspace, size_t ws_bytes, void *stream)
 {
     int rc = check_stage(h, 1, "mlpg_update_points");
     if (rc) return rc;
     MLPG_CHECK(x && R && nbr_off && nbr_idx, MLPG_ERR_ARG, "mlpg_update_points: null pointer");
     Problem *P = h;
-    rc = build_geometry(*P, x, R, nbr_off, nbr_idx, S(stream));
+    rc = build_geometry(*P, x, R, nbr_off, nbr_idx, workspace, ws_bytes, "mlpg_update_points", S(stream));
     // the integrated blocks and the assembled operators belong to the old
     // positions; the state (per-point coefficients) and the solver settings stay
     P->stage = 1;
     return rc;
+}
+
+size_t mlpg_geometry_workspace_bytes(int dim, int64_t n, int64_t nnz_nbr, const double *dom_lo, const double *dom_hi)
+{
+    if ((dim != 2 && dim != 3) || n <= 0 || nnz_nbr < 0 || !dom_lo || !dom_hi) return 0;
+    for (int a = 0; a < dim; ++a)
+        if (!(dom_hi[a] > dom_lo[a])) return 0;
+    Problem P;
+    P.dim = dim;
+    P.n = n;
+    for (int a = 0; a < dim; ++a) { P.dom_lo[a] = dom_lo[a]; P.dom_hi[a] = dom_hi[a]; }
+    int64_t dims[3];
+    P.ncell = patch_grid_cells(dim, n, P.dom_lo, P.dom_hi, nullptr, dims);
+    Arena A;
+    layout_geometry(P, A, nnz_nbr);
+    return A.used;
 }
 
 int mlpg_get_info(mlpg_handle h, mlpg_info *info)
@@ -598,17 +630,20 @@ int mlpg_material_shells(mlpg_handle h, int n_shells, const double *center, cons
     return MLPG_OK;
 }
 
-int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
+int mlpg_integrate(mlpg_handle h, int rk_order, void *workspace, size_t ws_bytes, void *stream)
 {
     int rc = check_stage(h, 1, "mlpg_integrate");
     if (rc) return rc;
     MLPG_CHECK(rk_order >= 0 && rk_order <= 2, MLPG_ERR_ARG, "mlpg_integrate: rk_order must be 0, 1 or 2");
     Problem *P = h;
     hipStream_t s = S(stream);
+    P->stage = 1;   // the blocks are rebuilt; the operators must be assembled again
     P->rk_order = rk_order;
     P->n_blocks = P->n_mat * (1 + P->dim) + P->dim * P->dim + 2 * P->dim;
-    MLPG_HIP(P->blocks.alloc((size_t)P->n_blocks * P->nnz));
-    MLPG_HIP(P->E.alloc(P->nnz));
+    rc = bind_stage(*P, P->own_int, workspace, ws_bytes, "mlpg_integrate",
+                    [&](Problem &Q, Arena &A) { layout_integrate(Q, A); });
+    if (rc) return rc;
+    P->ws_int = workspace;
     MLPG_HIP(hipMemsetAsync(P->blocks.p, 0, sizeof(double) * P->n_blocks * P->nnz, s));
     MLPG_HIP(hipMemsetAsync(P->E.p, 0, sizeof(double) * P->nnz, s));
     MLPG_HIP(hipMemsetAsync(P->counters.p, 0, sizeof(unsigned long long) * kNumCounters, s));
@@ -620,8 +655,12 @@ int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
         return MLPG_ERR_CAPACITY;
     }
     MLPG_HIP(e);
+    // surface rows (direction independent): offsets here, entries at assembly
+    MLPG_HIP(launch_surface_count(*P, P->tmp_scnt.p, s));
+    MLPG_HIP(launch_exclusive_scan(P->tmp_scnt.p, P->surf_off.p, P->n, s));
     unsigned long long cnt[kNumCounters];
     MLPG_HIP(hipMemcpyAsync(cnt, P->counters.p, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    MLPG_HIP(hipMemcpyAsync(&P->nnz_s, P->surf_off.p + P->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MLPG_HIP(hipStreamSynchronize(s));
     P->fallbacks = (int64_t)cnt[kFallbacks];
     P->missing = (int64_t)cnt[kMissing];
@@ -633,6 +672,16 @@ int mlpg_integrate(mlpg_handle h, int rk_order, void *stream)
                    " co-active function pairs are missing from the overlap lists");
     P->stage = 2;
     return MLPG_OK;
+}
+
+size_t mlpg_integrate_workspace_bytes(mlpg_handle h, int rk_order)
+{
+    if (!h || h->stage < 1 || rk_order < 0 || rk_order > 2) return 0;
+    Problem Q;   // sizes only
+    Q.n = h->n; Q.nnz = h->nnz; Q.n_bq = h->n_bq; Q.bq_kmax = h->bq_kmax; Q.dim = h->dim; Q.n_mat = h->n_mat;
+    Arena A;
+    layout_integrate(Q, A);
+    return A.used;
 }
 
 int mlpg_get_pattern(mlpg_handle h, int64_t *row_off, int32_t *col, void *stream)
@@ -659,7 +708,8 @@ int mlpg_get_blocks(mlpg_handle h, double *blocks, double *E, void *stream)
 }
 
 int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w, int n_mat, const double *sigma_t,
-                  const double *sigma_s, double inv_c_dt, const double *tau, int precision, void *stream)
+                  const double *sigma_s, double inv_c_dt, const double *tau, int precision, void *workspace,
+                  size_t ws_bytes, void *stream)
 {
     int rc = check_stage(h, 2, "mlpg_assemble");
     if (rc) return rc;
@@ -676,7 +726,46 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
                    "mlpg_assemble: need 0 <= sigma_s <= sigma_t");
     hipStream_t s = S(stream);
     const int d = P->dim;
+    // The state Psi^{n-1}, Phi sits at the start of the assembly workspace.
+    // It is kept when the ordinate count is unchanged: in place when the same
+    // workspace comes back, copied from the previous one otherwise (which must
+    // then stay valid until this call returns).
+    const bool keep = P->psi.p && P->psi.count == (size_t)P->n * n_ord && P->phi.p;
+    double *old_psi = P->psi.p, *old_phi = P->phi.p;
+    DevBuf<char> prev_own;
+    if (!workspace && P->own_asm.owned) {
+        // a library-owned workspace is replaced only after the state is copied
+        prev_own = P->own_asm;
+        P->own_asm.p = nullptr;
+        P->own_asm.count = 0;
+        P->own_asm.owned = false;
+    }
+    rc = bind_stage(*P, P->own_asm, workspace, ws_bytes, "mlpg_assemble",
+                    [&](Problem &Q, Arena &A) { layout_assemble(Q, A, n_ord, precision); });
+    if (rc) {
+        if (prev_own.p) {
+            P->own_asm.release();
+            P->own_asm = prev_own;
+        }
+        return rc;
+    }
+    P->stage = 2;         // until the new operators are complete
     P->binv_ok = false;   // the patch inverses belong to the previous operators
+    P->ws_asm = workspace;
+    const size_t nm = (size_t)P->n * n_ord;
+    if (keep) {
+        if (P->psi.p != old_psi)
+            MLPG_HIP(hipMemcpyAsync(P->psi.p, old_psi, sizeof(double) * nm, hipMemcpyDeviceToDevice, s));
+        if (P->phi.p != old_phi)
+            MLPG_HIP(hipMemcpyAsync(P->phi.p, old_phi, sizeof(double) * P->n, hipMemcpyDeviceToDevice, s));
+    } else {
+        MLPG_HIP(hipMemsetAsync(P->psi.p, 0, sizeof(double) * nm, s));
+        MLPG_HIP(hipMemsetAsync(P->phi.p, 0, sizeof(double) * P->n, s));
+    }
+    if (prev_own.p) {
+        MLPG_HIP(hipStreamSynchronize(s));
+        prev_own.release();
+    }
     P->n_ord = n_ord;
     P->a0 = inv_c_dt;
     P->precision = precision;
@@ -685,9 +774,6 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
     P->nfaces = 2 * d;
     P->omega_h.assign(omega, omega + (size_t)n_ord * d);
     P->w_h.assign(w, w + n_ord);
-    MLPG_HIP(P->sL.alloc((size_t)P->nnz * P->nsL));
-    MLPG_HIP(P->sMD.alloc((size_t)P->nnz * P->nsMD));
-    MLPG_HIP(P->sMS.alloc((size_t)P->nnz * P->nsMD));
     MLPG_HIP(launch_assemble(*P, sigma_t, sigma_s, tau, s));
     {
         // operators of the diffusion-synthetic acceleration (two values per pattern entry)
@@ -697,12 +783,6 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
             sa[g] = sigma_t[g] - sigma_s[g] + inv_c_dt;
             ss[g] = sigma_s[g];
         }
-        MLPG_HIP(P->dsaC.alloc(P->nnz));
-        MLPG_HIP(P->dsaMs.alloc(P->nnz));
-        MLPG_HIP(P->dsa_dinv.alloc(P->n));
-        MLPG_HIP(P->dsa_r.alloc(P->n));
-        MLPG_HIP(P->dsa_x.alloc(P->n));
-        MLPG_HIP(P->dsa_t.alloc(P->n));
         MLPG_HIP(launch_dsa_assemble(*P, st.data(), sa.data(), ss.data(), s));
     }
     // per-ordinate coefficient tables
@@ -722,68 +802,41 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
             cF[(size_t)m * P->nfaces + f] = wn > 0.0 ? wn : 0.0;
         }
     }
-    MLPG_HIP(P->coefL.alloc(cL.size()));
-    MLPG_HIP(P->coefMD.alloc(cMD.size()));
-    MLPG_HIP(P->coefF.alloc(cF.size()));
-    MLPG_HIP(P->omega.alloc((size_t)n_ord * d));
-    MLPG_HIP(P->wq.alloc(n_ord));
     MLPG_HIP(hipMemcpyAsync(P->coefL.p, cL.data(), sizeof(double) * cL.size(), hipMemcpyHostToDevice, s));
     MLPG_HIP(hipMemcpyAsync(P->coefMD.p, cMD.data(), sizeof(double) * cMD.size(), hipMemcpyHostToDevice, s));
     MLPG_HIP(hipMemcpyAsync(P->coefF.p, cF.data(), sizeof(double) * cF.size(), hipMemcpyHostToDevice, s));
     MLPG_HIP(hipMemcpyAsync(P->omega.p, omega, sizeof(double) * n_ord * d, hipMemcpyHostToDevice, s));
     MLPG_HIP(hipMemcpyAsync(P->wq.p, w, sizeof(double) * n_ord, hipMemcpyHostToDevice, s));
-    // surface rows
-    DevBuf<int64_t> cnt;
-    MLPG_HIP(cnt.alloc(P->n));
-    MLPG_HIP(P->surf_off.alloc(P->n + 1));
-    MLPG_HIP(launch_surface_count(*P, cnt.p, s));
-    MLPG_HIP(launch_exclusive_scan(cnt.p, P->surf_off.p, P->n, s));
-    MLPG_HIP(hipMemcpyAsync(&P->nnz_s, P->surf_off.p + P->n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    MLPG_HIP(hipStreamSynchronize(s));
-    cnt.release();
-    MLPG_HIP(P->surf_col.alloc(std::max<int64_t>(1, P->nnz_s)));
-    MLPG_HIP(P->surf_val.alloc(std::max<int64_t>(1, P->nnz_s) * P->nfaces));
+    // surface rows (offsets from the integration)
     MLPG_HIP(launch_surface_fill(*P, nullptr, s));
-    MLPG_HIP(P->dinv.alloc((size_t)P->n * n_ord));
     MLPG_HIP(launch_jacobi(*P, s));
+    std::vector<float> cL32, cF32;
     if (precision == MLPG_MIXED) {
         // FP32 copies used by the inner FP32 solver (values rounded once)
-        std::vector<float> cL32(cL.begin(), cL.end()), cF32(cF.begin(), cF.end());
-        MLPG_HIP(P->sL32.alloc((size_t)P->nnz * P->nsL));
-        MLPG_HIP(P->coefL32.alloc(cL32.size()));
-        MLPG_HIP(P->coefF32.alloc(cF32.size()));
-        MLPG_HIP(P->surf_val32.alloc(std::max<int64_t>(1, P->nnz_s) * P->nfaces));
-        MLPG_HIP(P->dinv32.alloc((size_t)P->n * n_ord));
-        MLPG_HIP(P->r32.alloc((size_t)P->n * n_ord));
-        MLPG_HIP(P->d32.alloc((size_t)P->n * n_ord));
-        MLPG_HIP(P->mr.alloc((size_t)P->n * n_ord));
-        MLPG_HIP(P->rn2.alloc(n_ord));
-        MLPG_HIP(P->fn2.alloc(n_ord));
+        cL32.assign(cL.begin(), cL.end());
+        cF32.assign(cF.begin(), cF.end());
         MLPG_HIP(launch_cast_f32(P->sL.p, P->sL32.p, (int64_t)P->nnz * P->nsL, s));
         if (P->nnz_s) MLPG_HIP(launch_cast_f32(P->surf_val.p, P->surf_val32.p, P->nnz_s * P->nfaces, s));
         MLPG_HIP(launch_cast_f32(P->dinv.p, P->dinv32.p, (int64_t)P->n * n_ord, s));
         MLPG_HIP(hipMemcpyAsync(P->coefL32.p, cL32.data(), sizeof(float) * cL32.size(), hipMemcpyHostToDevice, s));
         MLPG_HIP(hipMemcpyAsync(P->coefF32.p, cF32.data(), sizeof(float) * cF32.size(), hipMemcpyHostToDevice, s));
-        MLPG_HIP(hipStreamSynchronize(s));   // host staging vectors go out of scope
     }
-    // state and scratch
-    size_t nm = (size_t)P->n * n_ord;
-    bool fresh = P->psi.count != nm;
-    MLPG_HIP(P->psi.alloc(nm));
-    MLPG_HIP(P->F.alloc(nm));
-    MLPG_HIP(P->bpsi.alloc(nm));
-    MLPG_HIP(P->t1.alloc(nm));
-    MLPG_HIP(P->t2.alloc(nm));
-    MLPG_HIP(P->phi.alloc(P->n));
-    MLPG_HIP(P->bphi.alloc(P->n));
-    MLPG_HIP(P->ovec.alloc(P->n));
-    if (fresh) {
-        MLPG_HIP(hipMemsetAsync(P->psi.p, 0, sizeof(double) * nm, s));
-        MLPG_HIP(hipMemsetAsync(P->phi.p, 0, sizeof(double) * P->n, s));
-    }
+    MLPG_HIP(hipStreamSynchronize(s));   // host staging vectors go out of scope
     MLPG_HIP(hipGetLastError());
+    P->ws_slv_key = 0;   // the solve layout depends on the ordinates and the precision
     P->stage = 3;
     return MLPG_OK;
+}
+
+size_t mlpg_assemble_workspace_bytes(mlpg_handle h, int n_ord, int precision)
+{
+    if (!h || h->stage < 2 || n_ord < 1 || n_ord > 256 || (precision != MLPG_FP64 && precision != MLPG_MIXED))
+        return 0;
+    Problem Q;   // sizes only
+    Q.n = h->n; Q.nnz = h->nnz; Q.dim = h->dim; Q.nnz_s = h->nnz_s;
+    Arena A;
+    layout_assemble(Q, A, n_ord, precision);
+    return A.used;
 }
 
 int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *stream)
@@ -809,23 +862,76 @@ int mlpg_apply(mlpg_handle h, int which, const double *X, double *Y, void *strea
     return MLPG_OK;
 }
 
-int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t *n_patches, void *stream)
+// Binds the solve workspace for the options; the patch inverses are built
+// when they are not current (new operators, or a layout that moved them).
+static int bind_solve(Problem &P, const mlpg_solve_opts &o, void *ws, size_t ws_bytes, const char *who, hipStream_t s)
+{
+    const double *old_binv = P.binv.p;
+    int rc = bind_stage(P, P.own_slv, ws, ws_bytes, who, [&](Problem &Q, Arena &A) { layout_solve(Q, A, o); });
+    if (rc) return rc;
+    P.ws_slv = ws;
+    if (o.precond == MLPG_PRECOND_PATCH) {
+        if (P.binv.p != old_binv) P.binv_ok = false;
+        if (!P.patches_ok) {
+            rc = build_patches(P, s);
+            if (rc) return rc;
+            P.patches_ok = true;
+        }
+        if (!P.binv_ok) {
+            rc = build_patch_inverses(P, s);
+            if (rc) return rc;
+            P.binv_ok = true;
+        }
+    } else {
+        P.binv_ok = false;   // the layout has no inverses
+    }
+    return MLPG_OK;
+}
+
+static int check_opts(const mlpg_solve_opts &o, const char *who)
+{
+    const std::string w(who);
+    MLPG_CHECK(o.tol_inner > 0 && o.tol_outer > 0, MLPG_ERR_ARG, w + ": tolerances must be positive");
+    MLPG_CHECK(o.restart_inner >= 1 && o.restart_inner <= kMaxRestart && o.restart_outer >= 1 &&
+                   o.restart_outer <= kMaxRestart,
+               MLPG_ERR_ARG, w + ": restart lengths must be in [1, 30]");
+    MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1 && o.max_refine >= 0, MLPG_ERR_ARG,
+               w + ": iteration limits must be positive");
+    MLPG_CHECK(P_ok_lo(o), MLPG_ERR_ARG, w + ": tol_inner_lo must be in (0, 1)");
+    MLPG_CHECK(o.accel == MLPG_ACCEL_NONE || o.accel == MLPG_ACCEL_DSA, MLPG_ERR_ARG,
+               w + ": accel must be MLPG_ACCEL_NONE or MLPG_ACCEL_DSA");
+    MLPG_CHECK(o.precond == MLPG_PRECOND_JACOBI || o.precond == MLPG_PRECOND_PATCH, MLPG_ERR_ARG,
+               w + ": precond must be MLPG_PRECOND_JACOBI or MLPG_PRECOND_PATCH");
+    return MLPG_OK;
+}
+
+size_t mlpg_solve_workspace_bytes(mlpg_handle h, const mlpg_solve_opts *opts)
+{
+    if (!h || h->stage < 3) return 0;
+    mlpg_solve_opts o;
+    mlpg_default_opts(&o);
+    if (opts) o = *opts;
+    if (check_opts(o, "mlpg_solve_workspace_bytes")) return 0;
+    Problem Q;   // sizes only
+    Q.n = h->n; Q.n_ord = h->n_ord; Q.precision = h->precision; Q.nbsq = h->nbsq;
+    Arena A;
+    layout_solve(Q, A, o);
+    return A.used;
+}
+
+int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t *n_patches, void *workspace,
+                             size_t ws_bytes, void *stream)
 {
     int rc = check_stage(h, 3, "mlpg_apply_patch_precond");
     if (rc) return rc;
     MLPG_CHECK(X && Y && X != Y, MLPG_ERR_ARG, "mlpg_apply_patch_precond: need distinct X and Y");
     Problem *P = h;
     hipStream_t s = S(stream);
-    if (!P->patches_ok) {
-        rc = build_patches(*P, s);
-        if (rc) return rc;
-        P->patches_ok = true;
-    }
-    if (!P->binv_ok) {
-        rc = build_patch_inverses(*P, s);
-        if (rc) return rc;
-        P->binv_ok = true;
-    }
+    mlpg_solve_opts o;
+    mlpg_default_opts(&o);
+    o.precond = MLPG_PRECOND_PATCH;
+    rc = bind_solve(*P, o, workspace, ws_bytes, "mlpg_apply_patch_precond", s);
+    if (rc) return rc;
     PatchPrecT<double> pp = patch_prec<double>(*P, P->binv.p);
     MLPG_HIP(launch_patch_apply<double>(pp, P->n_ord, X, Y, false, nullptr, s));
     if (n_patches) *n_patches = P->npatch;
@@ -881,7 +987,8 @@ int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stre
 }
 
 int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_coef, double *phi_point,
-               double *psi_out, const mlpg_solve_opts *opts, mlpg_solve_info *info, void *stream)
+               double *psi_out, const mlpg_solve_opts *opts, mlpg_solve_info *info, void *workspace,
+               size_t ws_bytes, void *stream)
 {
     int rc = check_stage(h, 3, "mlpg_solve");
     if (rc) return rc;
@@ -889,32 +996,12 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     mlpg_solve_opts o;
     mlpg_default_opts(&o);
     if (opts) o = *opts;
-    MLPG_CHECK(o.tol_inner > 0 && o.tol_outer > 0, MLPG_ERR_ARG, "mlpg_solve: tolerances must be positive");
-    MLPG_CHECK(o.restart_inner >= 1 && o.restart_inner <= kMaxRestart && o.restart_outer >= 1 &&
-                   o.restart_outer <= kMaxRestart,
-               MLPG_ERR_ARG, "mlpg_solve: restart lengths must be in [1, 30]");
-    MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1 && o.max_refine >= 0, MLPG_ERR_ARG,
-               "mlpg_solve: iteration limits must be positive");
-    MLPG_CHECK(P_ok_lo(o), MLPG_ERR_ARG, "mlpg_solve: tol_inner_lo must be in (0, 1)");
-    MLPG_CHECK(o.accel == MLPG_ACCEL_NONE || o.accel == MLPG_ACCEL_DSA, MLPG_ERR_ARG,
-               "mlpg_solve: accel must be MLPG_ACCEL_NONE or MLPG_ACCEL_DSA");
-    MLPG_CHECK(o.precond == MLPG_PRECOND_JACOBI || o.precond == MLPG_PRECOND_PATCH, MLPG_ERR_ARG,
-               "mlpg_solve: precond must be MLPG_PRECOND_JACOBI or MLPG_PRECOND_PATCH");
+    rc = check_opts(o, "mlpg_solve");
+    if (rc) return rc;
     Problem *P = h;
     hipStream_t s = S(stream);
-    if (o.precond == MLPG_PRECOND_PATCH) {
-        // built on first use after a change of positions or operators
-        if (!P->patches_ok) {
-            rc = build_patches(*P, s);
-            if (rc) return rc;
-            P->patches_ok = true;
-        }
-        if (!P->binv_ok) {
-            rc = build_patch_inverses(*P, s);
-            if (rc) return rc;
-            P->binv_ok = true;
-        }
-    }
+    rc = bind_solve(*P, o, workspace, ws_bytes, "mlpg_solve", s);
+    if (rc) return rc;
     const int64_t n = P->n;
     const int M = P->n_ord;
     SolveCounters c;

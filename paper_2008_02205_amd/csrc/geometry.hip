@@ -64,9 +64,9 @@ __global__ __launch_bounds__(kTile) void neighbors_kernel(int dim, int64_t n, co
 
 // Exclusive prefix sum of n counts into off[0..n] with a single workgroup:
 // each thread sums a contiguous chunk, the chunk totals are scanned in LDS,
-// then every chunk is written.
-__global__ __launch_bounds__(1024) void scan_kernel(const int64_t *__restrict__ counts, int64_t *__restrict__ off,
-                                                    int64_t n)
+// then every chunk is written.  counts and off may be the same array (each
+// thread reads an entry of its own chunk before overwriting it).
+__global__ __launch_bounds__(1024) void scan_kernel(const int64_t *counts, int64_t *off, int64_t n)
 {
     __shared__ int64_t sums[1024];
     int t = threadIdx.x;
@@ -84,8 +84,9 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int64_t *__restrict__ 
     }
     int64_t run = sums[t] - s;
     for (int64_t k = lo; k < hi; ++k) {
+        const int64_t c = counts[k];
         off[k] = run;
-        run += counts[k];
+        run += c;
     }
     if (t == 1023) off[n] = sums[1023];
 }

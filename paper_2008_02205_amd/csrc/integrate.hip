@@ -1186,15 +1186,12 @@ static FieldSet field_set(const Problem &P)
 hipError_t launch_integrate2d(Problem &P, hipStream_t s)
 {
     // Candidate capacity from the largest candidate set.
-    DevBuf<int32_t> cnt;
-    hipError_t e = cnt.alloc(P.n);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     cand_count_kernel<<<(int)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.x.p, P.R.p, P.rho.p, P.nb_off.p, P.nb_idx.p,
-                                                                 cnt.p);
+                                                                 P.tmp_cand.p);
     std::vector<int32_t> h(P.n);
-    e = hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(h.data(), P.tmp_cand.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    cnt.release();
     if (e != hipSuccess) return e;
     int amax = 1;
     for (int32_t v : h) amax = v > amax ? v : amax;
@@ -1243,15 +1240,12 @@ hipError_t launch_integrate2d(Problem &P, hipStream_t s)
 
 hipError_t launch_integrate3d(Problem &P, hipStream_t s)
 {
-    DevBuf<int32_t> cnt;
-    hipError_t e = cnt.alloc(P.n);
-    if (e != hipSuccess) return e;
+    hipError_t e;
     cand_count3_kernel<<<(int)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.x.p, P.R.p, P.rho.p, P.nb_off.p, P.nb_idx.p,
-                                                                  cnt.p);
+                                                                  P.tmp_cand.p);
     std::vector<int32_t> h(P.n);
-    e = hipMemcpyAsync(h.data(), cnt.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(h.data(), P.tmp_cand.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    cnt.release();
     if (e != hipSuccess) return e;
     int amax = 1;
     for (int32_t v : h) amax = v > amax ? v : amax;

@@ -55,24 +55,58 @@ void set_error(const std::string &msg);
         }                                                                                 \
     } while (0)
 
-// Device buffer owned by the handle.
+// Device buffer: a view into a stage workspace (bound by an Arena), or an
+// allocation of its own (alloc: only for the helper entry points outside the
+// four stages and for workspaces the library allocates when the caller
+// passes none).
 template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t count = 0;
+    bool owned = false;
     hipError_t alloc(size_t n) {
-        if (n <= count && p) return hipSuccess;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        count = 0;
+        if (n <= count && p && owned) return hipSuccess;
+        release();
         hipError_t e = hipMalloc(&p, (n ? n : 1) * sizeof(T));
-        if (e == hipSuccess) count = n;
+        if (e == hipSuccess) {
+            count = n;
+            owned = true;
+        } else {
+            p = nullptr;
+        }
         return e;
     }
+    void bind(T *q, size_t n) {
+        release();
+        p = q;
+        count = n;
+        owned = false;
+    }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && owned) (void)hipFree(p);
         p = nullptr;
         count = 0;
+        owned = false;
+    }
+};
+
+// Carves the buffers of one stage out of a workspace, in a fixed order with
+// 256-byte alignment.  In measuring mode (base == nullptr) it only adds up
+// the bytes, so that a stage's size query and the stage itself run the same
+// layout code and agree to the byte.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    bool over = false;
+    static size_t align(size_t b) { return (b + 255) & ~(size_t)255; }
+    template <class T>
+    void take(DevBuf<T> &b, size_t n) {
+        const size_t bytes = align((n ? n : 1) * sizeof(T));
+        if (base && used + bytes <= cap) b.bind((T *)(base + used), n);
+        else b.bind(nullptr, n);
+        if (base && used + bytes > cap) over = true;
+        used += bytes;
     }
 };
 
@@ -131,7 +165,9 @@ struct KrylovT {
     int *nactive_hdev = nullptr;   // device address of nactive_host
     hipEvent_t ev[8] = {};
     int part_blocks = 0;
-    hipError_t ensure(int64_t n_, int nb_, int k_);
+    // device buffers for nb systems of n unknowns, restart length up to k_
+    void carve(Arena &A, int64_t n_, int nb_, int k_);
+    hipError_t host_init();   // pinned host mirrors of the active counts, events (once per handle)
     void release();
 };
 using Krylov = KrylovT<double>;
@@ -232,10 +268,34 @@ struct Problem {
     DevBuf<double> binv;
     DevBuf<float> binv32;
     bool patches_ok = false, binv_ok = false;
+
+    // stage workspaces: the caller's (views) or, when the caller passes none,
+    // one allocation per stage made by the library; temporaries of a stage
+    // live in its workspace too
+    DevBuf<char> own_geo, own_int, own_asm, own_slv;
+    void *ws_geo = nullptr, *ws_int = nullptr, *ws_asm = nullptr, *ws_slv = nullptr;
+    size_t ws_slv_key = 0;                  // hash of the solve layout last carved
+    double reg_lo_h[64 * 3] = {}, reg_hi_h[64 * 3] = {};
+    int32_t reg_mat_h[64] = {};
+    int64_t ncell = 0;                      // cells of the patch grid
+    DevBuf<int32_t> tmp_flags, tmp_cand;
+    DevBuf<int64_t> tmp_bqc, tmp_key, tmp_s2, tmp_npc, tmp_off, tmp_pbase, tmp_scnt;
+    DevBuf<unsigned long long> tmp_cnt, tmp_sing;
+    DevBuf<double> tmp_work;
     int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
 
     void release();
 };
+
+// Stage layouts (workspace.cpp): carve every buffer of a stage, in order.
+// The inputs are the sizes the stage depends on; the Problem's sizes from
+// earlier stages are read.
+void layout_geometry(Problem &P, Arena &A, int64_t nnz_nb);
+void layout_integrate(Problem &P, Arena &A);
+void layout_assemble(Problem &P, Arena &A, int n_ord, int precision);
+void layout_solve(Problem &P, Arena &A, const mlpg_solve_opts &o);
+// Cells of the patch grid over the domain box for n points (patches.hip).
+int64_t patch_grid_cells(int dim, int64_t n, const double *lo, const double *hi, double *h, int64_t dims[3]);
 
 // Patch block-Jacobi preconditioner (patches.hip): patches of the current
 // points, then the block inverses of the assembled operators (FP32 copies in

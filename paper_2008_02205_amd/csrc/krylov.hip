@@ -692,46 +692,50 @@ hipError_t pass_b(KrylovT<T> &K, int j, T *w, const T *dinv, T *z, const int *ga
 }  // namespace
 
 template <class T>
-hipError_t KrylovT<T>::ensure(int64_t n_, int nb_, int k_)
+void KrylovT<T>::carve(Arena &A, int64_t n_, int nb_, int k_)
 {
-    if (n == n_ && nb == nb_ && k == k_ && V.p) return hipSuccess;
     n = n_; nb = nb_; k = k_;
-    hipError_t e;
     // Basis vectors are spaced by n*nb plus an odd number of 128-byte lines so
     // that the same row of different vectors does not fall into the same
     // cache set and memory channel (n*nb is often a large power of two).
     vs = n * nb + (int64_t)(21 * 128 / sizeof(T));
-    if ((e = V.alloc((size_t)(k + 1) * vs)) != hipSuccess) return e;
-    if ((e = w.alloc((size_t)n * nb)) != hipSuccess) return e;
-    if ((e = w2.alloc((size_t)n * nb)) != hipSuccess) return e;
-    if ((e = z.alloc((size_t)n * nb)) != hipSuccess) return e;
-    if ((e = r.alloc((size_t)n * nb)) != hipSuccess) return e;
+    A.take(V, (size_t)(k + 1) * vs);
+    A.take(w, (size_t)n * nb);
+    A.take(w2, (size_t)n * nb);
+    A.take(z, (size_t)n * nb);
+    A.take(r, (size_t)n * nb);
     part_blocks = kPartBlocks;   // partial-sum rows; vec_launch never exceeds it
-    if ((e = part.alloc((size_t)part_blocks * kRows * nb)) != hipSuccess) return e;
-    if ((e = h1.alloc((size_t)kRows * nb)) != hipSuccess) return e;
-    if ((e = h2.alloc((size_t)kRows * nb)) != hipSuccess) return e;
-    if ((e = H.alloc((size_t)nb * (k + 1) * k)) != hipSuccess) return e;
-    if ((e = Ht.alloc((size_t)nb * (k + 1) * k)) != hipSuccess) return e;
-    if ((e = cs.alloc((size_t)nb * k)) != hipSuccess) return e;
-    if ((e = sn.alloc((size_t)nb * k)) != hipSuccess) return e;
-    if ((e = g.alloc((size_t)nb * (k + 1))) != hipSuccess) return e;
-    if ((e = y.alloc((size_t)k * nb)) != hipSuccess) return e;
-    if ((e = vscale.alloc(nb)) != hipSuccess) return e;
-    if ((e = fnorm.alloc(nb)) != hipSuccess) return e;
-    if ((e = beta.alloc(nb)) != hipSuccess) return e;
-    if ((e = resid.alloc(nb)) != hipSuccess) return e;
-    if ((e = active.alloc(nb)) != hipSuccess) return e;
-    if ((e = done.alloc(nb)) != hipSuccess) return e;
-    if ((e = its.alloc(nb)) != hipSuccess) return e;
-    if ((e = jend.alloc(nb)) != hipSuccess) return e;
-    if ((e = nactive.alloc(3)) != hipSuccess) return e;
-    if (!nactive_host) {
-        if ((e = hipHostMalloc((void **)&nactive_host, sizeof(int) * kSlots, hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
-            return e;
-        if ((e = hipHostGetDevicePointer((void **)&nactive_hdev, nactive_host, 0)) != hipSuccess) return e;
-        for (int i = 0; i < kSlots; ++i)
-            if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return e;
-    }
+    A.take(part, (size_t)part_blocks * kRows * nb);
+    A.take(h1, (size_t)kRows * nb);
+    A.take(h2, (size_t)kRows * nb);
+    A.take(H, (size_t)nb * (k + 1) * k);
+    A.take(Ht, (size_t)nb * (k + 1) * k);
+    A.take(cs, (size_t)nb * k);
+    A.take(sn, (size_t)nb * k);
+    A.take(g, (size_t)nb * (k + 1));
+    A.take(y, (size_t)k * nb);
+    A.take(vscale, nb);
+    A.take(fnorm, nb);
+    A.take(beta, nb);
+    A.take(resid, nb);
+    A.take(active, nb);
+    A.take(done, nb);
+    A.take(its, nb);
+    A.take(jend, nb);
+    A.take(nactive, 3);
+}
+
+template <class T>
+hipError_t KrylovT<T>::host_init()
+{
+    if (nactive_host) return hipSuccess;
+    hipError_t e;
+    if ((e = hipHostMalloc((void **)&nactive_host, sizeof(int) * kSlots, hipHostMallocMapped | hipHostMallocCoherent)) !=
+        hipSuccess)
+        return e;
+    if ((e = hipHostGetDevicePointer((void **)&nactive_hdev, nactive_host, 0)) != hipSuccess) return e;
+    for (int i = 0; i < kSlots; ++i)
+        if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -761,7 +765,9 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(!(pp && dinv), MLPG_ERR_ARG, "batched GMRES: one right preconditioner at a time");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
-    MLPG_HIP(K.ensure(n, nb, restart));
+    MLPG_CHECK(K.V.p && K.n == n && K.nb == nb && K.k >= restart, MLPG_ERR_WORKSPACE,
+               "batched GMRES: the solve workspace was laid out for another shape");
+    MLPG_HIP(K.host_init());
     if (lag < 1) lag = 1;
     if (lag > kSlots - 1) lag = kSlots - 1;
     const int k = restart;

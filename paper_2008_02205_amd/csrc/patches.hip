@@ -263,83 +263,88 @@ inline unsigned blocks_of(int64_t count, int threads) { return (unsigned)((count
 
 }  // namespace
 
-int build_patches(Problem &P, hipStream_t s)
+int64_t patch_grid_cells(int dim, int64_t n, const double *lo, const double *hi, double *h_out, int64_t dims[3])
 {
-    const int d = P.dim;
-    const int64_t n = P.n;
     double vol = 1.0;
-    for (int a = 0; a < d; ++a) vol *= P.dom_hi[a] - P.dom_lo[a];
-    double h = 2.0 * std::pow(vol / (double)n, 1.0 / d);
-    Grid g;
-    g.dim = d;
+    for (int a = 0; a < dim; ++a) vol *= hi[a] - lo[a];
+    double h = 2.0 * std::pow(vol / (double)(n > 0 ? n : 1), 1.0 / dim);
     int64_t ncell = 1;
     for (;;) {
         ncell = 1;
-        for (int a = 0; a < d; ++a) {
-            g.lo[a] = P.dom_lo[a];
-            g.dims[a] = std::max<int64_t>(1, (int64_t)std::ceil((P.dom_hi[a] - P.dom_lo[a]) / h));
-            ncell *= g.dims[a];
+        for (int a = 0; a < dim; ++a) {
+            dims[a] = std::max<int64_t>(1, (int64_t)std::ceil((hi[a] - lo[a]) / h));
+            ncell *= dims[a];
         }
         if (ncell <= ((int64_t)1 << 26)) break;
         h *= 2.0;
     }
-    for (int a = d; a < 3; ++a) { g.lo[a] = 0.0; g.dims[a] = 1; }
+    for (int a = dim; a < 3; ++a) dims[a] = 1;
+    if (h_out) *h_out = h;
+    return ncell;
+}
+
+// Patches of the current points into P.poff, P.pidx, P.boff (carved by the
+// geometry layout with n-sized bounds; temporaries from the same workspace).
+int build_patches(Problem &P, hipStream_t s)
+{
+    const int d = P.dim;
+    const int64_t n = P.n;
+    Grid g;
+    g.dim = d;
+    double h = 1.0;
+    const int64_t ncell = patch_grid_cells(d, n, P.dom_lo, P.dom_hi, &h, g.dims);
+    if (ncell != P.ncell) {
+        set_error("patch grid does not match the geometry workspace");
+        return MLPG_ERR_WORKSPACE;
+    }
+    for (int a = 0; a < 3; ++a) g.lo[a] = a < d ? P.dom_lo[a] : 0.0;
     g.inv_h = 1.0 / h;
-    DevBuf<int64_t> key, off, pbase, s2, npc;
-    DevBuf<unsigned long long> cnt;
-    MLPG_HIP(key.alloc(n));
-    MLPG_HIP(npc.alloc(ncell));
-    MLPG_HIP(off.alloc(ncell + 1));
-    MLPG_HIP(pbase.alloc(ncell + 1));
-    MLPG_HIP(cnt.alloc(ncell));
-    MLPG_HIP(P.pidx.alloc(n));
-    MLPG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long) * ncell, s));
-    bin_count_kernel<<<blocks_of(n, 256), 256, 0, s>>>(n, g, P.x.p, key.p, cnt.p);
-    MLPG_HIP(launch_exclusive_scan((const int64_t *)cnt.p, off.p, ncell, s));
-    MLPG_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long) * ncell, s));
-    bin_fill_kernel<<<blocks_of(n, 256), 256, 0, s>>>(n, key.p, off.p, cnt.p, P.pidx.p);
-    bin_sort_kernel<<<blocks_of(ncell, 256), 256, 0, s>>>(ncell, off.p, P.pidx.p, npc.p);
-    MLPG_HIP(launch_exclusive_scan(npc.p, pbase.p, ncell, s));
+    MLPG_HIP(hipMemsetAsync(P.tmp_cnt.p, 0, sizeof(unsigned long long) * ncell, s));
+    bin_count_kernel<<<blocks_of(n, 256), 256, 0, s>>>(n, g, P.x.p, P.tmp_key.p, P.tmp_cnt.p);
+    MLPG_HIP(launch_exclusive_scan((const int64_t *)P.tmp_cnt.p, P.tmp_off.p, ncell, s));
+    MLPG_HIP(hipMemsetAsync(P.tmp_cnt.p, 0, sizeof(unsigned long long) * ncell, s));
+    bin_fill_kernel<<<blocks_of(n, 256), 256, 0, s>>>(n, P.tmp_key.p, P.tmp_off.p, P.tmp_cnt.p, P.pidx.p);
+    bin_sort_kernel<<<blocks_of(ncell, 256), 256, 0, s>>>(ncell, P.tmp_off.p, P.pidx.p, P.tmp_npc.p);
+    MLPG_HIP(launch_exclusive_scan(P.tmp_npc.p, P.tmp_pbase.p, ncell, s));
     int64_t npatch = 0;
-    MLPG_HIP(hipMemcpyAsync(&npatch, pbase.p + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MLPG_HIP(hipMemcpyAsync(&npatch, P.tmp_pbase.p + ncell, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MLPG_HIP(hipStreamSynchronize(s));
-    MLPG_HIP(P.poff.alloc(npatch + 1));
-    MLPG_HIP(s2.alloc(npatch));
-    MLPG_HIP(P.boff.alloc(npatch + 1));
-    patch_fill_kernel<<<blocks_of(ncell, 256), 256, 0, s>>>(ncell, off.p, pbase.p, P.poff.p, s2.p, npatch, n);
-    MLPG_HIP(launch_exclusive_scan(s2.p, P.boff.p, npatch, s));
+    if (npatch < 1 || npatch > n) {
+        set_error("patch construction: patch count out of range");
+        return MLPG_ERR_GEOMETRY;
+    }
+    patch_fill_kernel<<<blocks_of(ncell, 256), 256, 0, s>>>(ncell, P.tmp_off.p, P.tmp_pbase.p, P.poff.p, P.tmp_s2.p,
+                                                              npatch, n);
+    MLPG_HIP(launch_exclusive_scan(P.tmp_s2.p, P.boff.p, npatch, s));
     MLPG_HIP(hipMemcpyAsync(&P.nbsq, P.boff.p + npatch, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MLPG_HIP(hipStreamSynchronize(s));
     MLPG_HIP(hipGetLastError());
-    key.release(); off.release(); pbase.release(); s2.release(); cnt.release(); npc.release();
     P.npatch = npatch;
     return MLPG_OK;
 }
 
+// Block inverses of the assembled operators into P.binv (and P.binv32 in the
+// mixed path), carved by the solve layout for the current patches.
 int build_patch_inverses(Problem &P, hipStream_t s)
 {
     const int M = P.n_ord;
-    const size_t cnt = (size_t)P.nbsq * M;
-    MLPG_HIP(P.binv.alloc(cnt));
-    DevBuf<double> work;
-    MLPG_HIP(work.alloc(cnt));
-    DevBuf<unsigned long long> sing;
-    MLPG_HIP(sing.alloc(1));
-    MLPG_HIP(hipMemsetAsync(sing.p, 0, sizeof(unsigned long long), s));
+    const int64_t cnt = P.nbsq * M;
+    if (!P.binv.p || P.binv.count < (size_t)cnt || P.tmp_work.count < (size_t)cnt) {
+        set_error("patch preconditioner: the solve workspace was laid out without it");
+        return MLPG_ERR_WORKSPACE;
+    }
+    MLPG_HIP(hipMemsetAsync(P.tmp_sing.p, 0, sizeof(unsigned long long), s));
     patch_build_kernel<<<blocks_of(P.npatch * M, 256), 256, 0, s>>>(
         P.npatch, M, P.poff.p, P.pidx.p, P.boff.p, P.row_off.p, P.col.p, P.nsL, P.sL.p, P.coefL.p, P.surf_off.p,
-        P.surf_col.p, P.surf_val.p, P.nfaces, P.coefF.p, work.p, P.binv.p, sing.p);
+        P.surf_col.p, P.surf_val.p, P.nfaces, P.coefF.p, P.tmp_work.p, P.binv.p, P.tmp_sing.p);
     MLPG_HIP(hipGetLastError());
     if (P.precision == MLPG_MIXED) {
-        MLPG_HIP(P.binv32.alloc(cnt));
-        cast_f32_patch_kernel<<<blocks_of((int64_t)cnt, 256), 256, 0, s>>>(P.binv.p, P.binv32.p, (int64_t)cnt);
+        cast_f32_patch_kernel<<<blocks_of(cnt, 256), 256, 0, s>>>(P.binv.p, P.binv32.p, cnt);
         MLPG_HIP(hipGetLastError());
     }
     unsigned long long ns = 0;
-    MLPG_HIP(hipMemcpyAsync(&ns, sing.p, sizeof(ns), hipMemcpyDeviceToHost, s));
+    MLPG_HIP(hipMemcpyAsync(&ns, P.tmp_sing.p, sizeof(ns), hipMemcpyDeviceToHost, s));
     MLPG_HIP(hipStreamSynchronize(s));
-    work.release();
-    sing.release();
     P.patch_singular = (int64_t)ns;
     return MLPG_OK;
 }

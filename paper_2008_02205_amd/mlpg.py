@@ -22,7 +22,7 @@ MLPG_OP_L, MLPG_OP_T, MLPG_OP_MS, MLPG_OP_SRC = 0, 1, 2, 3
 MLPG_ACCEL_NONE, MLPG_ACCEL_DSA = 0, 1
 MLPG_PRECOND_JACOBI, MLPG_PRECOND_PATCH = 0, 1
 STATUS = {0: "MLPG_OK", -1: "MLPG_ERR_ARG", -2: "MLPG_ERR_HIP", -3: "MLPG_ERR_CAPACITY",
-          -4: "MLPG_ERR_NOT_CONVERGED", -5: "MLPG_ERR_GEOMETRY", -7: "MLPG_ERR_STATE"}
+          -4: "MLPG_ERR_NOT_CONVERGED", -5: "MLPG_ERR_GEOMETRY", -6: "MLPG_ERR_WORKSPACE", -7: "MLPG_ERR_STATE"}
 
 EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count", "mlpg_neighbors_fill",
            "mlpg_geometry", "mlpg_get_info", "mlpg_get_volumes", "mlpg_cell_capacity", "mlpg_get_cells",
@@ -30,7 +30,8 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_apply", "mlpg_default_opts", "mlpg_set_state", "mlpg_get_state", "mlpg_solve",
            "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress",
            "mlpg_material_fields", "mlpg_update_points", "mlpg_refined_quadrature",
-           "mlpg_material_shells", "mlpg_apply_patch_precond"]
+           "mlpg_material_shells", "mlpg_apply_patch_precond", "mlpg_geometry_workspace_bytes",
+           "mlpg_integrate_workspace_bytes", "mlpg_assemble_workspace_bytes", "mlpg_solve_workspace_bytes"]
 
 
 class MlpgError(RuntimeError):
@@ -75,27 +76,37 @@ def lib() -> C.CDLL:
         L.mlpg_angular_quadrature.argtypes = [i32, i32, i32, vp, vp]
         L.mlpg_neighbors_count.argtypes = [i32, i64, vp, vp, vp, C.POINTER(C.c_int64), vp]
         L.mlpg_neighbors_fill.argtypes = [i32, i64, vp, vp, vp, vp, vp]
-        L.mlpg_geometry.argtypes = [C.POINTER(vp), i32, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.mlpg_geometry.argtypes = [C.POINTER(vp), i32, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, C.c_size_t,
+                                    vp]
+        L.mlpg_geometry_workspace_bytes.restype = C.c_size_t
+        L.mlpg_geometry_workspace_bytes.argtypes = [i32, i64, i64, vp, vp]
+        L.mlpg_integrate_workspace_bytes.restype = C.c_size_t
+        L.mlpg_integrate_workspace_bytes.argtypes = [vp, i32]
+        L.mlpg_assemble_workspace_bytes.restype = C.c_size_t
+        L.mlpg_assemble_workspace_bytes.argtypes = [vp, i32, i32]
+        L.mlpg_solve_workspace_bytes.restype = C.c_size_t
+        L.mlpg_solve_workspace_bytes.argtypes = [vp, C.POINTER(SolveOpts)]
         L.mlpg_get_info.argtypes = [vp, C.POINTER(Info)]
         L.mlpg_get_volumes.argtypes = [vp, vp, vp]
         L.mlpg_cell_capacity.argtypes = []
         L.mlpg_get_cells.argtypes = [vp, vp, vp, vp, vp]
         L.mlpg_boundary_points.argtypes = [vp, vp, vp, vp]
-        L.mlpg_integrate.argtypes = [vp, i32, vp]
+        L.mlpg_integrate.argtypes = [vp, i32, vp, C.c_size_t, vp]
         L.mlpg_material_fields.argtypes = [vp, i32, vp, vp]
         L.mlpg_material_shells.argtypes = [vp, i32, vp, vp, vp]
-        L.mlpg_update_points.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.mlpg_update_points.argtypes = [vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
         L.mlpg_refined_quadrature.argtypes = [i32, i32, vp, vp, dbl, i32, vp, vp]
         L.mlpg_get_pattern.argtypes = [vp, vp, vp, vp]
         L.mlpg_get_blocks.argtypes = [vp, vp, vp, vp]
-        L.mlpg_assemble.argtypes = [vp, i32, vp, vp, i32, vp, vp, dbl, vp, i32, vp]
+        L.mlpg_assemble.argtypes = [vp, i32, vp, vp, i32, vp, vp, dbl, vp, i32, vp, C.c_size_t, vp]
         L.mlpg_apply.argtypes = [vp, i32, vp, vp, vp]
-        L.mlpg_apply_patch_precond.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), vp]
+        L.mlpg_apply_patch_precond.argtypes = [vp, vp, vp, C.POINTER(C.c_int64), vp, C.c_size_t, vp]
         L.mlpg_default_opts.restype = None
         L.mlpg_default_opts.argtypes = [C.POINTER(SolveOpts)]
         L.mlpg_set_state.argtypes = [vp, vp, vp]
         L.mlpg_get_state.argtypes = [vp, vp, vp, vp]
-        L.mlpg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.mlpg_solve.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp, C.c_size_t,
+                                 vp]
         L.mlpg_point_values.argtypes = [vp, vp, vp, vp]
         L.mlpg_destroy.restype = None
         L.mlpg_destroy.argtypes = [vp]
@@ -103,7 +114,8 @@ def lib() -> C.CDLL:
         L.mlpg_profile_end.argtypes = [vp, vp, vp]
         L.mlpg_set_progress.argtypes = [PROGRESS_FN, vp]
         for name in EXPORTS:
-            if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy"):
+            if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy") and \
+                    not name.endswith("_workspace_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -173,7 +185,41 @@ def mlpg_neighbors_fill(x, R, off, total):
     return idx[:total]
 
 
-def mlpg_geometry(x, R, nbr_off, nbr_idx, dom_lo, dom_hi, regions=()):
+def _ws(t):
+    """(pointer, bytes) of a workspace tensor, or (None, 0) to let the library allocate."""
+    if t is None:
+        return None, 0
+    return C.c_void_p(t.data_ptr()), t.numel() * t.element_size()
+
+
+def workspace(nbytes: int):
+    """A device workspace of nbytes (torch-owned, 256-byte aligned by torch's allocator)."""
+    torch = _torch()
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def mlpg_geometry_workspace_bytes(dim, n, nnz_nbr, dom_lo, dom_hi) -> int:
+    lo = np.ascontiguousarray(dom_lo, dtype=np.float64)
+    hi = np.ascontiguousarray(dom_hi, dtype=np.float64)
+    return int(lib().mlpg_geometry_workspace_bytes(dim, n, nnz_nbr, _host(lo), _host(hi)))
+
+
+def mlpg_integrate_workspace_bytes(h, rk_order) -> int:
+    return int(lib().mlpg_integrate_workspace_bytes(h, rk_order))
+
+
+def mlpg_assemble_workspace_bytes(h, n_ord, precision) -> int:
+    return int(lib().mlpg_assemble_workspace_bytes(h, n_ord, precision))
+
+
+def mlpg_solve_workspace_bytes(h, opts=None) -> int:
+    o = opts or mlpg_default_opts()
+    return int(lib().mlpg_solve_workspace_bytes(h, C.byref(o)))
+
+
+def mlpg_geometry(x, R, nbr_off, nbr_idx, dom_lo, dom_hi, regions=(), ws=None):
     n, dim = x.shape
     lo = np.ascontiguousarray(dom_lo, dtype=np.float64)
     hi = np.ascontiguousarray(dom_hi, dtype=np.float64)
@@ -185,8 +231,9 @@ def mlpg_geometry(x, R, nbr_off, nbr_idx, dom_lo, dom_hi, regions=()):
         rlo = rhi = rmat = None
     h = C.c_void_p(None)
     idx = nbr_idx if nbr_idx.numel() > 0 else _empty(1, _torch().int32)
+    wp, wb = _ws(ws)
     _check(lib().mlpg_geometry(C.byref(h), dim, n, _dev(x), _dev(R), _dev(nbr_off), _dev(idx), _host(lo), _host(hi),
-                               len(regions), _host(rlo), _host(rhi), _host(rmat), _stream()))
+                               len(regions), _host(rlo), _host(rhi), _host(rmat), wp, wb, _stream()))
     return h
 
 
@@ -227,10 +274,11 @@ def mlpg_material_shells(h, shells=()):
     _check(lib().mlpg_material_shells(h, len(shells), _host(cen), _host(rad), _host(mat)))
 
 
-def mlpg_update_points(h, x, R, nbr_off, nbr_idx):
+def mlpg_update_points(h, x, R, nbr_off, nbr_idx, ws=None):
     """New positions and radii for an existing handle (see the C declaration)."""
     idx = nbr_idx if nbr_idx.numel() > 0 else _empty(1, _torch().int32)
-    _check(lib().mlpg_update_points(h, _dev(x), _dev(R), _dev(nbr_off), _dev(idx), _stream()))
+    wp, wb = _ws(ws)
+    _check(lib().mlpg_update_points(h, _dev(x), _dev(R), _dev(nbr_off), _dev(idx), wp, wb, _stream()))
 
 
 def mlpg_get_info(h) -> dict:
@@ -267,8 +315,9 @@ def mlpg_boundary_points(h, n_bq, dim):
     return y[:n_bq], face[:n_bq]
 
 
-def mlpg_integrate(h, rk_order: int):
-    _check(lib().mlpg_integrate(h, rk_order, _stream()))
+def mlpg_integrate(h, rk_order: int, ws=None):
+    wp, wb = _ws(ws)
+    _check(lib().mlpg_integrate(h, rk_order, wp, wb, _stream()))
 
 
 def mlpg_get_pattern(h, n, nnz):
@@ -287,13 +336,14 @@ def mlpg_get_blocks(h, n_blocks, nnz, want_E=True):
 
 
 def mlpg_assemble(h, omega: np.ndarray, w: np.ndarray, sigma_t, sigma_s, inv_c_dt: float, tau,
-                  precision: int = MLPG_FP64):
+                  precision: int = MLPG_FP64, ws=None):
     om = np.ascontiguousarray(omega, dtype=np.float64)
     wq = np.ascontiguousarray(w, dtype=np.float64)
     st = np.ascontiguousarray(np.atleast_1d(sigma_t), dtype=np.float64)
     ss = np.ascontiguousarray(np.atleast_1d(sigma_s), dtype=np.float64)
+    wp, wb = _ws(ws)
     _check(lib().mlpg_assemble(h, om.shape[0], _host(om), _host(wq), st.size, _host(st), _host(ss), float(inv_c_dt),
-                               _dev(tau), precision, _stream()))
+                               _dev(tau), precision, wp, wb, _stream()))
 
 
 def mlpg_apply(h, which: int, X):
@@ -302,11 +352,12 @@ def mlpg_apply(h, which: int, X):
     return Y
 
 
-def mlpg_apply_patch_precond(h, X):
+def mlpg_apply_patch_precond(h, X, ws=None):
     """Y = M^-1 X with the patch block-Jacobi preconditioner; returns (Y, patch count)."""
     Y = _empty(X.shape)
     npt = C.c_int64(0)
-    _check(lib().mlpg_apply_patch_precond(h, _dev(X), _dev(Y), C.byref(npt), _stream()))
+    wp, wb = _ws(ws)
+    _check(lib().mlpg_apply_patch_precond(h, _dev(X), _dev(Y), C.byref(npt), wp, wb, _stream()))
     return Y, npt.value
 
 
@@ -327,15 +378,17 @@ def mlpg_get_state(h, n, n_ord):
     return psi, phi
 
 
-def mlpg_solve(h, q, psi_b=None, opts: Optional[SolveOpts] = None, want_psi: bool = True, raise_on_error=True):
+def mlpg_solve(h, q, psi_b=None, opts: Optional[SolveOpts] = None, want_psi: bool = True, raise_on_error=True,
+               ws=None):
     n, M = q.shape
     phi = _empty(n)
     phi_pt = _empty(n)
     psi = _empty((n, M)) if want_psi else None
     info = SolveInfo()
     o = opts or mlpg_default_opts()
+    wp, wb = _ws(ws)
     rc = lib().mlpg_solve(h, _dev(q), _dev(psi_b), _dev(phi), _dev(phi_pt), _dev(psi), C.byref(o), C.byref(info),
-                          _stream())
+                          wp, wb, _stream())
     if raise_on_error:
         _check(rc)
     d = {k: getattr(info, k) for k, _ in SolveInfo._fields_}

@@ -40,14 +40,20 @@ def test_host_argument_validation(lib):
     from paper_2008_02205_amd import mlpg
     h = C.c_void_p(None)
     lo = np.zeros(2); hi = np.ones(2)
-    rc = lib.mlpg_geometry(C.byref(h), 4, 10, 1, 1, 1, 1, lo.ctypes.data, hi.ctypes.data, 0, None, None, None, None)
+    rc = lib.mlpg_geometry(C.byref(h), 4, 10, 1, 1, 1, 1, lo.ctypes.data, hi.ctypes.data, 0, None, None, None, None,
+                           0, None)
     assert rc == -1 and b"dim" in lib.mlpg_last_error()
-    rc = lib.mlpg_geometry(C.byref(h), 2, 0, 1, 1, 1, 1, lo.ctypes.data, hi.ctypes.data, 0, None, None, None, None)
+    rc = lib.mlpg_geometry(C.byref(h), 2, 0, 1, 1, 1, 1, lo.ctypes.data, hi.ctypes.data, 0, None, None, None, None,
+                           0, None)
     assert rc == -1
-    rc = lib.mlpg_geometry(C.byref(h), 2, 10, 1, 1, 1, 1, hi.ctypes.data, lo.ctypes.data, 0, None, None, None, None)
+    rc = lib.mlpg_geometry(C.byref(h), 2, 10, 1, 1, 1, 1, hi.ctypes.data, lo.ctypes.data, 0, None, None, None, None,
+                           0, None)
     assert rc == -1 and b"empty domain" in lib.mlpg_last_error()
-    assert lib.mlpg_integrate(None, 1, None) == -1
-    assert lib.mlpg_solve(None, None, None, None, None, None, None, None, None) == -1
+    assert lib.mlpg_integrate(None, 1, None, 0, None) == -1
+    assert lib.mlpg_solve(None, None, None, None, None, None, None, None, None, 0, None) == -1
+    assert lib.mlpg_integrate_workspace_bytes(None, 1) == 0
+    assert lib.mlpg_assemble_workspace_bytes(None, 16, 0) == 0
+    assert lib.mlpg_solve_workspace_bytes(None, None) == 0
     o = mlpg.SolveOpts()
     lib.mlpg_default_opts(C.byref(o))
     assert o.restart_inner == 30 and o.tol_inner == 1e-13
@@ -64,3 +70,29 @@ def test_angular_quadrature_host(lib, dim, M, kind):
     assert np.abs(w - w_o).max() <= 1e-14
     with pytest.raises(mlpg.MlpgError):
         mlpg.mlpg_angular_quadrature(2, 7)
+
+
+def _aligned(b):
+    return (b + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("dim,n,nnz", [(2, 16384, 766798), (3, 64000, 28536256), (2, 1, 0)])
+def test_geometry_workspace_query_is_the_sum_of_its_buffers(lib, dim, n, nnz):
+    """The geometry workspace is host-computable: every buffer the stage carves, 256-byte aligned."""
+    from paper_2008_02205_amd import mlpg
+    lo, hi = (0.0,) * dim, (1.0,) * dim
+    got = mlpg.mlpg_geometry_workspace_bytes(dim, n, nnz, lo, hi)
+    h = 2.0 * (1.0 / n) ** (1.0 / dim)
+    ncell = int(np.ceil(1.0 / h)) ** dim
+    d = dim
+    sizes = [64 * d * 8, 64 * d * 8, 64 * 4, n * d * 8, n * 8, (n + 1) * 8, max(1, nnz) * 4, 4 * 8, n * 8, n * 8,
+             (n + 1) * 8]
+    if dim == 2:
+        sizes += [n * 4, n * 32 * 4, n * 32 * 2 * 8]
+    else:
+        sizes += [n * 4, n * 40 * 4, n * 40 * 4, n * 40 * 16 * 3 * 8]
+    sizes += [(n + 1) * 8, (nnz + n) * 4, n * 8, (n + 1) * 8, (n + 1) * 8, n * 4,
+              n * 4, n * 8, n * 8, n * 8, ncell * 8, (ncell + 1) * 8, (ncell + 1) * 8, ncell * 8]
+    assert got == sum(_aligned(b) for b in sizes)
+    assert mlpg.mlpg_geometry_workspace_bytes(dim, n, nnz, hi, lo) == 0
+    assert mlpg.mlpg_geometry_workspace_bytes(4, n, nnz, lo, hi) == 0
