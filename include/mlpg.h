@@ -364,6 +364,13 @@ typedef struct {
                              diffusion-synthetic right preconditioner (see below) */
     int precond;          /* inner solves: MLPG_PRECOND_JACOBI (default, point Jacobi) or
                              MLPG_PRECOND_PATCH (patch block Jacobi, see below) */
+    int graphs;           /* 1 (default): every restart cycle of an inner solve (its Arnoldi steps,
+                             the least-squares update, the new residual and the next cycle's start)
+                             is captured once as a HIP graph and replayed; the host then waits once
+                             per cycle instead of every few steps, and steps after the last system
+                             converges return at their device gates.  0: launched one by one.  The
+                             results are the same bit for bit.  Kernel timing (mlpg_profile_begin)
+                             launches one by one. */
 } mlpg_solve_opts;
 
 /* Right preconditioning of the inner solves L_m x = f (Sec. 4.2 preconditions
@@ -459,6 +466,32 @@ int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stre
 #define MLPG_PROF_CLASSES 4
 int mlpg_profile_begin(void);
 int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Launch-shape autotuning of the transport sweep.  Before the first solve of
+ * a problem shape (rows n, ordinates, value streams, value size) the library
+ * times every candidate launch shape of the sweep on the problem's own
+ * operator, as the inner solver calls it, and keeps the fastest in a
+ * process-wide table used by every later sweep of that shape:
+ *   n_ord >= 48: 2, 4 or 8 waves per workgroup, 1 or 2 (row, 64-ordinate)
+ *     items per wave, workgroups renumbered so that each of the 8 dies walks
+ *     one contiguous row range (xcd_split = 8) or not (1);
+ *   n_ord < 48: 128, 256 or 512 threads per workgroup.
+ * mlpg_set_autotune(0) keeps the built-in shape (4 waves, 1 item, split 8;
+ * 256 threads) for shapes not yet in the table, (1) measures again (the
+ * default), (2) empties the table.  Every shape computes each row's sums in
+ * the same order, so the results do not depend on the choice.
+ * mlpg_get_tuning copies up to cap entries to out (host) and returns the
+ * table's size.  Process-wide; the table is guarded by a lock.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int64_t n;
+    int n_ord, streams, value_bytes;
+    int waves_per_block, items_per_wave, xcd_split, threads;
+    float us_best, us_default;   /* measured duration of the chosen and of the built-in shape */
+} mlpg_tune_entry;
+int mlpg_set_autotune(int mode);
+int mlpg_get_tuning(int cap, mlpg_tune_entry *out);
 
 /* ------------------------------------------------------------------------
  * Progress reports for long solves.  When set, the library calls

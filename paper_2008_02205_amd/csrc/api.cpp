@@ -109,7 +109,8 @@ int inner_solve_fp64(Problem &P, SolveCounters &c, const double *f, double *x, h
     const PatchPrecT<double> pp = patch_prec<double>(P, P.binv.p);
     return gmres_batched<double>(P, P.inner, op_L, true, nullptr, patch ? nullptr : P.dinv.p, f, x, P.n, P.n_ord,
                                  c.o->tol_inner, c.o->restart_inner, c.o->max_inner, c.o->check_every, true, s,
-                                 &c.its, &c.sweeps, &c.res_max, &c.conv, nullptr, false, patch ? &pp : nullptr);
+                                 &c.its, &c.sweeps, &c.res_max, &c.conv, nullptr, false, patch ? &pp : nullptr,
+                                 c.o->graphs != 0);
 }
 
 // Mixed precision: iterative refinement in FP64 around FP32 GMRES.
@@ -167,7 +168,8 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         const PatchPrecT<float> pp32 = patch_prec<float>(P, P.binv32.p);
         int rc = gmres_batched<float>(P, P.inner32, op_L32, true, nullptr, patch ? nullptr : P.dinv32.p, P.r32.p,
                                       P.d32.p, n, M, o.tol_inner_lo, o.restart_inner, cap, o.check_every, true, s,
-                                      &c.its, &c.sweeps, &rm32, &c32, P.tolv.p, false, patch ? &pp32 : nullptr);
+                                      &c.its, &c.sweeps, &rm32, &c32, P.tolv.p, false, patch ? &pp32 : nullptr,
+                                      o.graphs != 0);
         MLPG_HIP(hipStreamSynchronize(s));   // tolm is read by the copy above
         if (rc) return rc;
         MLPG_HIP(launch_axpy_from_float(n, M, x, P.d32.p, P.rn2.p, s));
@@ -185,7 +187,7 @@ int inner_solve_mixed(Problem &P, SolveCounters &c, const double *f, double *x, 
         const PatchPrecT<double> pp = patch_prec<double>(P, P.binv.p);
         int rc = gmres_batched<double>(P, P.inner, op_L, true, nullptr, patch ? nullptr : P.dinv.p, f, x, n, M,
                                        o.tol_inner, o.restart_inner, o.max_inner, o.check_every, false, s, &c.its,
-                                       &c.sweeps, &rm, &c64, nullptr, false, patch ? &pp : nullptr);
+                                       &c.sweeps, &rm, &c64, nullptr, false, patch ? &pp : nullptr, o.graphs != 0);
         if (rc) return rc;
         c.fp64_completions++;
         conv = c64;
@@ -400,6 +402,7 @@ static int build_geometry(Problem &P, const double *x, const double *R, const in
                         [&](Problem &Q, Arena &A) { layout_geometry(Q, A, nnz_nb); });
     if (rc) return rc;
     P.ws_geo = ws;
+    P.gen++;
     if (P.n_regions) {
         TRY(hipMemcpyAsync(P.reg_lo.p, P.reg_lo_h, sizeof(double) * P.n_regions * dim, hipMemcpyHostToDevice, s));
         TRY(hipMemcpyAsync(P.reg_hi.p, P.reg_hi_h, sizeof(double) * P.n_regions * dim, hipMemcpyHostToDevice, s));
@@ -644,6 +647,7 @@ int mlpg_integrate(mlpg_handle h, int rk_order, void *workspace, size_t ws_bytes
                     [&](Problem &Q, Arena &A) { layout_integrate(Q, A); });
     if (rc) return rc;
     P->ws_int = workspace;
+    P->gen++;
     MLPG_HIP(hipMemsetAsync(P->blocks.p, 0, sizeof(double) * P->n_blocks * P->nnz, s));
     MLPG_HIP(hipMemsetAsync(P->E.p, 0, sizeof(double) * P->nnz, s));
     MLPG_HIP(hipMemsetAsync(P->counters.p, 0, sizeof(unsigned long long) * kNumCounters, s));
@@ -752,6 +756,7 @@ int mlpg_assemble(mlpg_handle h, int n_ord, const double *omega, const double *w
     P->stage = 2;         // until the new operators are complete
     P->binv_ok = false;   // the patch inverses belong to the previous operators
     P->ws_asm = workspace;
+    P->gen++;
     const size_t nm = (size_t)P->n * n_ord;
     if (keep) {
         if (P->psi.p != old_psi)
@@ -938,6 +943,19 @@ int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t 
     return MLPG_OK;
 }
 
+int mlpg_set_autotune(int mode)
+{
+    MLPG_CHECK(mode >= 0 && mode <= 2, MLPG_ERR_ARG, "mlpg_set_autotune: mode must be 0, 1 or 2");
+    set_autotune(mode);
+    return MLPG_OK;
+}
+
+int mlpg_get_tuning(int cap, mlpg_tune_entry *out)
+{
+    MLPG_CHECK(cap >= 0 && (cap == 0 || out), MLPG_ERR_ARG, "mlpg_get_tuning: need cap >= 0 and out");
+    return get_tuning(cap, out);
+}
+
 void mlpg_default_opts(mlpg_solve_opts *o)
 {
     if (!o) return;
@@ -952,6 +970,7 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->max_refine = 12;
     o->accel = MLPG_ACCEL_NONE;
     o->precond = MLPG_PRECOND_JACOBI;
+    o->graphs = 1;
 }
 
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)
@@ -1002,6 +1021,24 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
     hipStream_t s = S(stream);
     rc = bind_solve(*P, o, workspace, ws_bytes, "mlpg_solve", s);
     if (rc) return rc;
+    {
+        // launch shapes of the inner sweeps, measured once per problem shape
+        // (on scratch vectors of this solve, before any graph is captured)
+        const size_t nm = (size_t)P->n * P->n_ord;
+        MLPG_HIP(hipMemsetAsync(P->t1.p, 0, sizeof(double) * nm, s));
+        SpmvArgs a;
+        a.vals = P->sL.p; a.ns = P->nsL; a.coef = P->coefL.p; a.x = P->t1.p; a.surface = 1; a.y = P->t2.p;
+        a.sval = P->surf_val.p; a.coefF = P->coefF.p; a.colscale = P->wq.p; a.vout = P->bpsi.p; a.vsrc = P->t1.p;
+        MLPG_HIP(tune_spmv<double>(*P, a, s));
+        if (P->precision == MLPG_MIXED) {
+            MLPG_HIP(hipMemsetAsync(P->r32.p, 0, sizeof(float) * nm, s));
+            SpmvArgsT<float> b;
+            b.vals = P->sL32.p; b.ns = P->nsL; b.coef = P->coefL32.p; b.x = P->r32.p; b.surface = 1;
+            b.y = P->d32.p; b.sval = P->surf_val32.p; b.coefF = P->coefF32.p; b.colscale = P->wq.p;
+            b.vout = P->inner32.w.p; b.vsrc = P->r32.p;
+            MLPG_HIP(tune_spmv<float>(*P, b, s));
+        }
+    }
     const int64_t n = P->n;
     const int M = P->n_ord;
     SolveCounters c;

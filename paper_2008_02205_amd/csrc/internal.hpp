@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mlpg.h"
@@ -132,6 +133,33 @@ void gauss_jacobi(int n, double alpha, double *x, double *w);
 // Counters written by kernels (device, zeroed at each stage that uses them).
 enum Counter { kFallbacks = 0, kMissing = 1, kOverflow = 2, kBadLists = 3, kNumCounters = 4 };
 
+// Launch arguments a captured restart cycle depends on (pointers, values and
+// the problem's layout generation); a graph is replayed only for an equal key.
+struct GraphKey {
+    const void *ptr[11] = {};
+    double tol = 0.0;
+    int64_t val[6] = {};
+    void set(uint64_t gen, const void *op, const void *ctx, const void *dinv, const void *f, const void *x,
+             const void *tolv, const void *binv, const void *V, const void *part, const void *H, const void *nact,
+             double tol_, int64_t n, int nb, int k, int max_its, int fused)
+    {
+        const void *p[11] = {op, ctx, dinv, f, x, tolv, binv, V, part, H, nact};
+        for (int i = 0; i < 11; ++i) ptr[i] = p[i];
+        tol = tol_;
+        const int64_t v[6] = {(int64_t)gen, n, nb, k, max_its, fused};
+        for (int i = 0; i < 6; ++i) val[i] = v[i];
+    }
+    bool operator==(const GraphKey &o) const
+    {
+        for (int i = 0; i < 11; ++i)
+            if (ptr[i] != o.ptr[i]) return false;
+        for (int i = 0; i < 6; ++i)
+            if (val[i] != o.val[i]) return false;
+        return tol == o.tol;
+    }
+};
+constexpr size_t kGraphCache = 8;   // captured cycles kept per Krylov space
+
 // Batched GMRES workspace for `nb` simultaneous systems of `n` unknowns
 // (ordinates as the fastest index); T is the storage type of the basis and
 // vectors (partial sums, Hessenberg and rotations are FP64 either way).
@@ -165,6 +193,9 @@ struct KrylovT {
     int *nactive_hdev = nullptr;   // device address of nactive_host
     hipEvent_t ev[8] = {};
     int part_blocks = 0;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // captured restart cycles
+    hipGraphExec_t find_graph(const GraphKey &key) const;
+    void add_graph(const GraphKey &key, hipGraphExec_t ge);
     // device buffers for nb systems of n unknowns, restart length up to k_
     void carve(Arena &A, int64_t n_, int nb_, int k_);
     hipError_t host_init();   // pinned host mirrors of the active counts, events (once per handle)
@@ -283,6 +314,7 @@ struct Problem {
     DevBuf<unsigned long long> tmp_cnt, tmp_sing;
     DevBuf<double> tmp_work;
     int stage = 0;                        // 1 geometry, 2 integrated, 3 assembled
+    uint64_t gen = 0;                     // bumped whenever a stage lays its buffers out again
 
     void release();
 };
@@ -370,6 +402,11 @@ struct SpmvArgsT {
 using SpmvArgs = SpmvArgsT<double>;
 template <class T>
 hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s);
+// measures the sweep's launch shapes for this problem's size once per process (ops.hip)
+template <class T>
+hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s);
+void set_autotune(int mode);   // 0 off, 1 on, 2 clear the table
+int get_tuning(int cap, mlpg_tune_entry *out);
 hipError_t launch_to_float_scaled(int64_t n, int M, const double *r, const double *rn2, const double *fn2, double tol,
                                   float *out, hipStream_t s);
 hipError_t launch_axpy_from_float(int64_t n, int M, double *x, const float *d, const double *rn2, hipStream_t s);
@@ -404,7 +441,8 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged,
                   const double *tolv = nullptr, bool cheap_op = false,   // optional per-system relative tolerance (device [nb])
-                  const PatchPrecT<T> *pp = nullptr);   // patch block-Jacobi instead of dinv (dinv must be null)
+                  const PatchPrecT<T> *pp = nullptr,    // patch block-Jacobi instead of dinv (dinv must be null)
+                  bool graphs = false);                 // replay restart cycles from captured HIP graphs
 // out[m] = sum_i x[i][m]^2 for the nb systems of K's shape
 hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s);
 

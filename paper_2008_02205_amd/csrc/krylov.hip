@@ -740,8 +740,28 @@ hipError_t KrylovT<T>::host_init()
 }
 
 template <class T>
+hipGraphExec_t KrylovT<T>::find_graph(const GraphKey &key) const
+{
+    for (const auto &e : graphs)
+        if (e.first == key) return e.second;
+    return nullptr;
+}
+
+template <class T>
+void KrylovT<T>::add_graph(const GraphKey &key, hipGraphExec_t ge)
+{
+    if (graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(graphs.front().second);
+        graphs.erase(graphs.begin());
+    }
+    graphs.emplace_back(key, ge);
+}
+
+template <class T>
 void KrylovT<T>::release()
 {
+    for (auto &e : graphs) (void)hipGraphExecDestroy(e.second);
+    graphs.clear();
     V.release(); w.release(); w2.release(); z.release(); r.release(); part.release(); h1.release(); h2.release(); H.release();
     Ht.release(); cs.release(); sn.release(); g.release(); y.release(); vscale.release(); fnorm.release(); beta.release();
     resid.release(); active.release(); done.release(); its.release(); jend.release(); nactive.release();
@@ -760,7 +780,7 @@ template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged, const double *tolv,
-                  bool cheap_op, const PatchPrecT<T> *pp)
+                  bool cheap_op, const PatchPrecT<T> *pp, bool graphs)
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(!(pp && dinv), MLPG_ERR_ARG, "batched GMRES: one right preconditioner at a time");
@@ -794,12 +814,14 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
         residual_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
     }
     int64_t sw = 0;
-    for (;;) {
-        MLPG_HIP(norm2<T>(K, K.r.p, K.h1.p, s));
-        cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, tolv, max_its, K.its.p, K.active.p, K.done.p,
-                                            K.g.p, K.beta.p, K.resid.p, K.jend.p, nact, nact + 1, K.nactive_hdev);
-        MLPG_HIP(hipStreamSynchronize(s));
-        if (K.nactive_host[0] == 0) break;
+    // One restart cycle: the Arnoldi steps, the end-of-cycle correction, the
+    // least-squares update of x, the new residual, its norm and the next
+    // cycle's start (which decides which systems go on).  In graph mode the
+    // whole cycle is issued without host checks (steps after the last system
+    // stops return at their gates), so that it can be captured once and
+    // replayed; otherwise the host reads the active count a few steps late
+    // and stops issuing when no system is left.
+    auto cycle = [&](bool graph_mode) -> int {
         init_v0_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.r.p, K.beta.p, K.active.p, K.V.p);
         int jc = 0;
         bool early = false;
@@ -857,7 +879,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             MLPG_HIP(pass_b<T>(K, j, wcur, dinv, (fused && !pp) ? K.z.p : nullptr, nnext, K.nactive_hdev + slot, s));
             // the next operator input M^-1 w_j (normalised inside the next sweep)
             if (fused && pp && j < k - 1) MLPG_HIP(launch_patch_apply<T>(*pp, nb, wcur, K.z.p, false, nnext, s));
-            MLPG_HIP(hipEventRecord(K.ev[slot], s));
+            if (!graph_mode) MLPG_HIP(hipEventRecord(K.ev[slot], s));
             sw++;
             jc = j + 1;
             if (!fused || j == k - 1)
@@ -865,6 +887,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                                                                       K.V.p + (int64_t)(j + 1) * K.vs, nnext);
             if (j == k - 1) break;
             std::swap(wcur, wprev);
+            if (graph_mode) continue;
             // read the active count of the sweep `lag` steps back (same cycle)
             const int64_t chk = sw - lag;
             if (chk >= base) {
@@ -895,7 +918,51 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
         int rc = op(P, c, s, ctx);
         if (rc) return rc;
         residual_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(cnt, f, K.r.p);
+        MLPG_HIP(norm2<T>(K, K.r.p, K.h1.p, s));
+        cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, tolv, max_its, K.its.p, K.active.p,
+                                            K.done.p, K.g.p, K.beta.p, K.resid.p, K.jend.p, nact, nact + 1,
+                                            K.nactive_hdev);
         MLPG_HIP(hipGetLastError());
+        return MLPG_OK;
+    };
+    // Cycles are replayed from a captured HIP graph when the operator is the
+    // fused inner one (no host decision inside a cycle) and no kernel timing
+    // is on; a graph is captured once per set of launch arguments.
+    const bool use_graph = graphs && fused && !precheck && !prof_on();
+    MLPG_HIP(norm2<T>(K, K.r.p, K.h1.p, s));
+    cycle_init_kernel<<<1, nbt, 0, s>>>(nb, k, K.h1.p, K.fnorm.p, tol, tolv, max_its, K.its.p, K.active.p, K.done.p,
+                                        K.g.p, K.beta.p, K.resid.p, K.jend.p, nact, nact + 1, K.nactive_hdev);
+    for (;;) {
+        MLPG_HIP(hipStreamSynchronize(s));
+        if (K.nactive_host[0] == 0) break;
+        if (use_graph) {
+            GraphKey key;
+            key.set(P.gen, (const void *)op, ctx, dinv, f, x, tolv, pp ? pp->binv : nullptr, K.V.p, K.part.p, K.H.p,
+                    K.nactive.p, tol, (int64_t)n, nb, k, max_its, (int)fused);
+            hipGraphExec_t ge = K.find_graph(key);
+            if (!ge) {
+                MLPG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                const int64_t sw0 = sw;
+                int rc = cycle(true);
+                hipGraph_t g = nullptr;
+                hipError_t ec = hipStreamEndCapture(s, &g);
+                sw = sw0;
+                if (rc) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                MLPG_HIP(ec);
+                hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                MLPG_HIP(ei);
+                K.add_graph(key, ge);
+            }
+            MLPG_HIP(hipGraphLaunch(ge, s));
+            sw += k;
+        } else {
+            int rc = cycle(false);
+            if (rc) return rc;
+        }
     }
     std::vector<int> its(nb), done(nb);
     std::vector<double> res(nb);
@@ -929,10 +996,10 @@ template struct KrylovT<float>;
 template int gmres_batched<double>(Problem &, KrylovT<double> &, OpFnT<double>, bool, void *, const double *,
                                    const double *, double *, int64_t, int, double, int, int, int, bool, hipStream_t,
                                    int64_t *, int64_t *, double *, bool *, const double *, bool,
-                                   const PatchPrecT<double> *);
+                                   const PatchPrecT<double> *, bool);
 template int gmres_batched<float>(Problem &, KrylovT<float> &, OpFnT<float>, bool, void *, const float *,
                                   const float *, float *, int64_t, int, double, int, int, int, bool, hipStream_t,
                                   int64_t *, int64_t *, double *, bool *, const double *, bool,
-                                  const PatchPrecT<float> *);
+                                  const PatchPrecT<float> *, bool);
 
 }  // namespace mlpg

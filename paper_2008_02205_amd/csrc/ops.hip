@@ -7,6 +7,10 @@
 // values are read together; every lane of a row owns one ordinate and
 // combines the streams with its own coefficients (products of Omega_m
 // components) in registers, so L_m is never stored per ordinate.
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "internal.hpp"
 
 namespace mlpg {
@@ -225,7 +229,7 @@ __device__ __forceinline__ float bcast(float v, int lane)
 // combined with the lane's own coefficients; the x gathers of eight nonzeros
 // are issued back to back so that their latencies overlap.
 template <int NS, class T, int MODE>
-__global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
+__global__ __launch_bounds__(512) void spmv_wave_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
                                                         const int32_t *__restrict__ col,
                                                         const T *__restrict__ vals)
 {
@@ -305,7 +309,7 @@ __global__ __launch_bounds__(256) void spmv_wave_kernel(SpmvK<T> k, const int64_
 // Row-group SpMV for small ordinate counts: thread (row group, m); lanes of
 // one row share the row's stream values (broadcast loads).
 template <int NS, class T, int MODE>
-__global__ __launch_bounds__(256) void spmv_group_kernel(SpmvK<T> k)
+__global__ __launch_bounds__(512) void spmv_group_kernel(SpmvK<T> k)
 {
     if (k.gate && *k.gate == 0) return;
     const int M = k.M;
@@ -464,13 +468,47 @@ hipError_t launch_jacobi(Problem &P, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---- launch shapes of the sweep and their autotuning -------------------------
+// Wave kernel (M >= 48): `wpb` waves per workgroup, each wave sweeping `ipw`
+// (row, 64-ordinate chunk) items; with `xcd` = 8 workgroups are renumbered so
+// that every die walks one contiguous range of rows.  Group kernel (M < 48):
+// `threads` per workgroup (rows of M lanes).  The best shape per (rows,
+// ordinates, streams, value size) is measured once per process on the
+// problem's own operator and kept in a table (mlpg_get_tuning).
+struct SpmvShape {
+    int wpb = 4, ipw = 1, xcd = 8, threads = 256;
+};
+
+namespace {
+struct TuneEntry {
+    int64_t n;
+    int M, ns, tbytes;
+    SpmvShape shape;
+    float us_best, us_default;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_autotune = true;
+
+bool find_shape(int64_t n, int M, int ns, int tb, SpmvShape *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &e : g_tune)
+        if (e.n == n && e.M == M && e.ns == ns && e.tbytes == tb) {
+            *out = e.shape;
+            return true;
+        }
+    return false;
+}
+}  // namespace
+
 template <class T>
-hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
+static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const SpmvShape &sh, hipStream_t s)
 {
     const int M = P.n_ord;
     SpmvK<T> k;
     k.items_per_block = 0;
-    k.nxcd = 8;
+    k.nxcd = sh.xcd;
     k.n = P.n; k.M = M; k.row_off = P.row_off.p; k.col = P.col.p; k.vals = a.vals; k.coef = a.coef; k.x = a.x;
     k.x_bcast = a.x_bcast; k.x2 = a.x2; k.xs = a.xs; k.dinv = a.dinv; k.colscale = a.colscale;
     k.soff = a.surface ? P.surf_off.p : nullptr; k.scol = P.surf_col.p; k.sval = a.sval; k.coefF = a.coefF;
@@ -482,16 +520,17 @@ hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
     unsigned blocks;
     int threads;
     if (wave) {
-        // 4 waves per workgroup, one item per wave, grid a multiple of the 8 dies
-        threads = 256;
+        // sh.wpb waves per workgroup, sh.ipw items per wave, grid a multiple of the xcd count
+        threads = 64 * sh.wpb;
         const int64_t items = P.n * ((M + 63) / 64);
-        int64_t b = (items + 3) / 4;
-        b = ((b + 7) / 8) * 8;
-        if (b < 8) b = 8;
+        const int64_t per_block = (int64_t)sh.wpb * sh.ipw;
+        int64_t b = (items + per_block - 1) / per_block;
+        b = ((b + sh.xcd - 1) / sh.xcd) * sh.xcd;
+        if (b < sh.xcd) b = sh.xcd;
         blocks = (unsigned)b;
         k.items_per_block = (items + b - 1) / b;
     } else {
-        const int rpb = rows_per_block(M);
+        const int rpb = std::max(1, sh.threads / M);
         threads = rpb * M;
         int64_t b = (P.n + rpb - 1) / rpb;
         blocks = (unsigned)(b > 65536 ? 65536 : b);
@@ -522,6 +561,104 @@ hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
 #undef MLPG_SPMV_M
     return hipGetLastError();
 }
+
+template <class T>
+hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
+{
+    SpmvShape sh;
+    (void)find_shape(P.n, P.n_ord, a.ns, (int)sizeof(T), &sh);
+    return launch_spmv_shape<T>(P, a, sh, s);
+}
+
+// Times every candidate shape of the transport sweep as the inner solver
+// calls it (normalisation fused, per-ordinate column scale) on x -> y, both
+// [n][M] scratch vectors of the caller, and records the fastest.  Runs once
+// per (rows, ordinates, streams, value size) and process; never during a
+// graph capture (the caller tunes before the first solve).
+template <class T>
+hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
+{
+    SpmvShape cur;
+    if (!g_autotune || find_shape(P.n, P.n_ord, a.ns, (int)sizeof(T), &cur)) return hipSuccess;
+    std::vector<SpmvShape> cand;
+    if (P.n_ord >= 48) {
+        for (int wpb : {2, 4, 8})
+            for (int ipw : {1, 2})
+                for (int xcd : {8, 1}) {
+                    SpmvShape c;
+                    c.wpb = wpb; c.ipw = ipw; c.xcd = xcd;
+                    cand.push_back(c);
+                }
+    } else {
+        for (int th : {128, 256, 512}) {
+            SpmvShape c;
+            c.threads = th;
+            cand.push_back(c);
+        }
+    }
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) return e;
+    float best = 1e30f, dflt = 0.0f;
+    SpmvShape pick;
+    for (const SpmvShape &c : cand) {
+        if ((e = launch_spmv_shape<T>(P, a, c, s)) != hipSuccess) break;   // warm-up
+        float t = 1e30f;
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+            if ((e = launch_spmv_shape<T>(P, a, c, s)) != hipSuccess) break;
+            if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            t = std::min(t, ms);
+        }
+        if (e != hipSuccess) break;
+        const SpmvShape d;
+        if (c.wpb == d.wpb && c.ipw == d.ipw && c.xcd == d.xcd && c.threads == d.threads) dflt = t;
+        if (t < best) {
+            best = t;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.push_back({P.n, P.n_ord, a.ns, (int)sizeof(T), pick, 1e3f * best, 1e3f * dflt});
+    return hipSuccess;
+}
+template hipError_t tune_spmv<double>(Problem &, const SpmvArgsT<double> &, hipStream_t);
+template hipError_t tune_spmv<float>(Problem &, const SpmvArgsT<float> &, hipStream_t);
+
+void set_autotune(int mode)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (mode == 2) g_tune.clear();
+    else g_autotune = mode != 0;
+}
+
+int get_tuning(int cap, mlpg_tune_entry *out)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const int cnt = (int)g_tune.size();
+    for (int i = 0; i < cnt && i < cap; ++i) {
+        const TuneEntry &e = g_tune[i];
+        out[i].n = e.n;
+        out[i].n_ord = e.M;
+        out[i].streams = e.ns;
+        out[i].value_bytes = e.tbytes;
+        out[i].waves_per_block = e.M >= 48 ? e.shape.wpb : 0;
+        out[i].items_per_wave = e.M >= 48 ? e.shape.ipw : 0;
+        out[i].xcd_split = e.M >= 48 ? e.shape.xcd : 0;
+        out[i].threads = e.M >= 48 ? 64 * e.shape.wpb : e.shape.threads;
+        out[i].us_best = e.us_best;
+        out[i].us_default = e.us_default;
+    }
+    return cnt;
+}
+
 template hipError_t launch_spmv<double>(Problem &, const SpmvArgsT<double> &, hipStream_t);
 template hipError_t launch_spmv<float>(Problem &, const SpmvArgsT<float> &, hipStream_t);
 

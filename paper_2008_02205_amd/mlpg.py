@@ -31,7 +31,8 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_point_values", "mlpg_destroy", "mlpg_profile_begin", "mlpg_profile_end", "mlpg_set_progress",
            "mlpg_material_fields", "mlpg_update_points", "mlpg_refined_quadrature",
            "mlpg_material_shells", "mlpg_apply_patch_precond", "mlpg_geometry_workspace_bytes",
-           "mlpg_integrate_workspace_bytes", "mlpg_assemble_workspace_bytes", "mlpg_solve_workspace_bytes"]
+           "mlpg_integrate_workspace_bytes", "mlpg_assemble_workspace_bytes", "mlpg_solve_workspace_bytes",
+           "mlpg_set_autotune", "mlpg_get_tuning"]
 
 
 class MlpgError(RuntimeError):
@@ -50,7 +51,13 @@ class SolveOpts(C.Structure):
     _fields_ = [("tol_inner", C.c_double), ("tol_outer", C.c_double), ("restart_inner", C.c_int),
                 ("restart_outer", C.c_int), ("max_inner", C.c_int), ("max_outer", C.c_int),
                 ("check_every", C.c_int), ("tol_inner_lo", C.c_double), ("max_refine", C.c_int),
-                ("accel", C.c_int), ("precond", C.c_int)]
+                ("accel", C.c_int), ("precond", C.c_int), ("graphs", C.c_int)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_ord", C.c_int), ("streams", C.c_int), ("value_bytes", C.c_int),
+                ("waves_per_block", C.c_int), ("items_per_wave", C.c_int), ("xcd_split", C.c_int),
+                ("threads", C.c_int), ("us_best", C.c_float), ("us_default", C.c_float)]
 
 
 class SolveInfo(C.Structure):
@@ -113,6 +120,8 @@ def lib() -> C.CDLL:
         L.mlpg_profile_begin.argtypes = []
         L.mlpg_profile_end.argtypes = [vp, vp, vp]
         L.mlpg_set_progress.argtypes = [PROGRESS_FN, vp]
+        L.mlpg_set_autotune.argtypes = [i32]
+        L.mlpg_get_tuning.argtypes = [i32, C.POINTER(TuneEntry)]
         for name in EXPORTS:
             if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy") and \
                     not name.endswith("_workspace_bytes"):
@@ -359,6 +368,21 @@ def mlpg_apply_patch_precond(h, X, ws=None):
     wp, wb = _ws(ws)
     _check(lib().mlpg_apply_patch_precond(h, _dev(X), _dev(Y), C.byref(npt), wp, wb, _stream()))
     return Y, npt.value
+
+
+def mlpg_set_autotune(mode: int):
+    """0: keep the built-in launch shape for new problem shapes; 1: measure (default); 2: empty the table."""
+    _check(lib().mlpg_set_autotune(int(mode)))
+
+
+def mlpg_get_tuning() -> list:
+    """The launch shapes chosen so far: one dict per (n, n_ord, streams, value size)."""
+    cnt = lib().mlpg_get_tuning(0, None)
+    if cnt < 0:
+        _check(cnt)
+    arr = (TuneEntry * max(cnt, 1))()
+    lib().mlpg_get_tuning(cnt, arr)
+    return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_} for i in range(cnt)]
 
 
 def mlpg_default_opts() -> SolveOpts:

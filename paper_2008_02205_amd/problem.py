@@ -36,6 +36,13 @@ class GpuProblem:
         self.M = 0
         self.precision = api.MLPG_FP64
 
+    def device_bytes(self, opts=None) -> int:
+        """Exact device bytes of the problem once assembled: its inputs on the device (positions, radii,
+        overlap lists) and the four stage workspaces (the solve's for ``opts``, whether held yet or not)."""
+        inputs = sum(t.numel() * t.element_size() for t in (self.x, self.R, self.nbr_off, self.nbr_idx))
+        held = sum(v.numel() for k, v in self.ws.items() if k != "solve")
+        return inputs + held + api.mlpg_solve_workspace_bytes(self.h, opts)
+
     def workspace_bytes(self) -> dict:
         """Bytes of every stage workspace held now (the device memory the problem uses beyond its inputs)."""
         return {k: v.numel() for k, v in self.ws.items()}

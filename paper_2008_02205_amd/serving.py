@@ -1,12 +1,19 @@
 """Continuous batching of independent transport problems on one GPU.
 
 Requests arrive over time.  A request is admitted as soon as a slot is free
-and its estimated HBM footprint fits in what the running requests leave of
-the budget (first waiting request that fits, in arrival order).  Every
-admitted request runs the library's four stage calls (geometry, integration,
-assembly, one steady solve) on its own HIP stream from its own host thread,
-so that the kernels of several problems overlap on the device while each
-problem's Krylov state stays resident in its handle until it completes.
+and its HBM reservation fits in what the running requests leave of the budget
+(first waiting request that fits, in arrival order).  The reservation starts
+as a bound from the request's size (points, ordinates) and is replaced by the
+exact bytes -- the problem's device inputs plus its four stage workspaces,
+from the library's workspace queries -- as soon as they are known (after the
+assembly, before the solve's workspace is taken), which usually returns part
+of the bound to the pool.  Every admitted request runs the library's four
+stage calls (geometry, integration, assembly, one steady solve) on its own HIP
+stream from its own host thread, so that the kernels of several problems
+overlap on the device while each problem's Krylov state stays resident until
+it completes.  All device memory comes from torch's caching allocator (the
+workspaces are torch tensors), so a finished request's memory is reused by
+the next without a device-wide free.
 
 Control flow only: every numerical step runs in libmlpg.so.  Latency is
 measured from arrival to the result being ready on the host.
@@ -48,6 +55,8 @@ class Result:
     point: Optional[np.ndarray] = None
     info: Optional[dict] = None
     error: Optional[str] = None
+    reserved: int = 0          # bytes reserved at admission (the bound)
+    exact_bytes: int = 0       # device bytes the problem holds, from the workspace queries
 
     @property
     def latency(self) -> float:
@@ -72,13 +81,15 @@ class Server:
         """The HIP stream of one slot."""
         return torch.cuda.Stream()
 
-    def _solve(self, build: Callable, spec, stream: torch.cuda.Stream):
+    def _solve(self, build: Callable, spec, stream: torch.cuda.Stream, true_up: Optional[Callable] = None):
         x, R, dx, om, w, sig_t, sig_s, q = build(spec)
         with torch.cuda.stream(stream):
             P = GpuProblem(x, R, (0.0, 0.0), (1.0, 1.0))
             try:
                 P.integrate(1)
                 P.assemble(om, w, [sig_t], [sig_s], 0.0, dx, precision=self.precision)
+                if true_up is not None:
+                    true_up(P.device_bytes(self.opts))
                 qd = torch.from_numpy(np.ascontiguousarray(q)).to("cuda", non_blocking=False)
                 phi, pv, _, info = P.step(qd, None, self.opts, want_psi=False)
                 phi_h, pv_h = phi.cpu().numpy(), pv.cpu().numpy()
@@ -102,9 +113,19 @@ class Server:
         t0 = time.perf_counter()
 
         def worker(spec, sidx, need, t_adm):
-            res = Result(spec.rid, spec.arrival, t_adm, 0.0)
+            res = Result(spec.rid, spec.arrival, t_adm, 0.0, reserved=need)
+            held = [need]
+
+            def true_up(exact):
+                # the exact footprint replaces the bound in the budget
+                with lock:
+                    state["bytes"] += int(exact) - held[0]
+                    held[0] = int(exact)
+                    res.exact_bytes = int(exact)
+                    lock.notify_all()
+
             try:
-                phi, pv, info = self._solve(build, spec, streams[sidx])
+                phi, pv, info = self._solve(build, spec, streams[sidx], true_up)
                 if keep_fields:
                     res.phi, res.point = phi, pv
                 res.info = info
@@ -113,7 +134,7 @@ class Server:
             res.done = time.perf_counter() - t0
             with lock:
                 results.append(res)
-                state["bytes"] -= need
+                state["bytes"] -= held[0]
                 state["running"] -= 1
                 free_streams.append(sidx)
                 lock.notify_all()
@@ -153,7 +174,10 @@ class Server:
 def latency_summary(results: List[Result]) -> dict:
     lat = np.array([r.latency for r in results if r.error is None])
     span = max(r.done for r in results) - min(r.arrival for r in results)
+    exact = [r for r in results if r.exact_bytes > 0]
     return {"requests": len(results), "failed": sum(r.error is not None for r in results),
+            "exact_over_reserved": (float(np.mean([r.exact_bytes / r.reserved for r in exact]))
+                                    if exact else None),
             "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_s": float(lat.mean()) if lat.size else None,

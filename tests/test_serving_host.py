@@ -36,7 +36,7 @@ class _Recorder(Server):
     def _stream(self):
         return None
 
-    def _solve(self, build, spec, stream):
+    def _solve(self, build, spec, stream, true_up=None):
         need = hbm_estimate(spec.side * spec.side, spec.n_ord, self.precision)
         with self.lock:
             self.running[spec.rid] = need
@@ -113,3 +113,26 @@ def test_latency_summary_by_hand():
     assert summ["p50_s"] == pytest.approx(2.0)          # latencies 1, 2, 3
     assert summ["mean_s"] == pytest.approx(2.0)
     assert summ["throughput_req_s"] == pytest.approx(4 / 9.0)
+
+
+class _TrueUp(_Recorder):
+    """Stand-in whose exact footprint (reported after 'assembly') is a quarter of the bound."""
+
+    def _solve(self, build, spec, stream, true_up=None):
+        if true_up is not None:
+            true_up(hbm_estimate(spec.side * spec.side, spec.n_ord, self.precision) // 4)
+        return super()._solve(build, spec, stream)
+
+
+def test_exact_bytes_replace_the_reservation():
+    """Once a running request reports its exact bytes, the freed part of its bound admits the
+    next request while it still runs; the bytes return to zero at the end."""
+    specs = [Spec(0, 0.0, 64, 64, secs=0.2), Spec(1, 0.0, 64, 64, secs=0.05)]
+    budget = _need(64, 64) + _need(64, 64) // 2       # two bounds do not fit, bound + exact do
+    srv = _TrueUp(slots=2, budget=budget)
+    res = srv.run(specs, build=None, realtime=False)
+    assert all(r.error is None for r in res)
+    assert any(len(snap) == 2 for snap in srv.snapshots)   # they overlapped
+    assert all(r.exact_bytes == _need(64, 64) // 4 for r in res)
+    summ = latency_summary(res)
+    assert summ["exact_over_reserved"] == pytest.approx(0.25, rel=1e-6)
