@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--max-outer", type=int, default=None,
                     help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
     ap.add_argument("--max-inner", type=int, default=None, help="inner-iteration cap per solve (--workload mode)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the inner solves' restart cycles from captured HIP graphs (default: one by one)")
     ap.add_argument("--precond", choices=["jacobi", "patch"], default="jacobi",
                     help="right preconditioner of the inner solves: point Jacobi or patch block Jacobi")
     ap.add_argument("--accel", action="store_true",
@@ -118,30 +120,43 @@ def main():
         phi = pv = None
         opts = mlpg.mlpg_default_opts()
         opts.precond = mlpg.MLPG_PRECOND_PATCH if args.precond == "patch" else mlpg.MLPG_PRECOND_JACOBI
+        opts.graphs = 1 if args.graphs else 0
         if args.tol_lo:
             opts.tol_inner_lo = args.tol_lo
+        ref = f64c = 0
         for s in range(w.steps):
             phi, pv, _, info = P.step(qs[s], None, opts, want_psi=False)
             its += info["inner_iters"]
             sweeps += info["inner_sweeps"]
             outer += info["outer_iters"]
             solves += info["inner_solves"]
+            ref += info["refinements"]
+            f64c += info["fp64_completions"]
         P.close()
+        extra["refinements"] = ref
+        extra["fp64_completions"] = f64c
         return its, sweeps, outer, solves, pv
+
+    extra = {}
 
     def timed(prec):
         for _ in range(args.warmup):
             one_step(prec)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tot = {"its": 0, "sw": 0, "out": 0, "solves": 0}
+        tot = {"its": 0, "sw": 0, "out": 0, "solves": 0, "refinements": 0, "fp64_completions": 0, "step_s": []}
         pv = None
         for _ in range(args.steps):
+            ts = time.perf_counter()
             its, sw, out, solves, pv = one_step(prec)
+            torch.cuda.synchronize()
+            tot["step_s"].append(time.perf_counter() - ts)
             tot["its"] += its
             tot["sw"] += sw
             tot["out"] += out
             tot["solves"] += solves
+            tot["refinements"] += extra["refinements"]
+            tot["fp64_completions"] += extra["fp64_completions"]
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         # one more step, identical to the timed ones, with HIP events around every
@@ -186,7 +201,11 @@ def main():
         "config": {"workload": f"2d-mms-be20: {int(math.sqrt(n))}^2 jittered lattice, linear RK, R=2h, "
                                f"{M} ordinates, 20 BE steps dt=0.01", "points": n, "ordinates": M,
                    "be_steps": w.steps},
-        "detail": {"inner_iters_per_step": tot_its / max(args.steps, 1),
+        "detail": {"p50_step_s": float(np.percentile(tot["step_s"], 50)),
+                   "p99_step_s": float(np.percentile(tot["step_s"], 99)),
+                   "precond": args.precond, "graphs": bool(args.graphs),
+                   "sweep_launch_shapes": mlpg.mlpg_get_tuning(),
+                   "inner_iters_per_step": tot_its / max(args.steps, 1),
                    "batched_sweeps_per_step": tot_sw / max(args.steps, 1),
                    "outer_iters_per_step": tot_out / max(args.steps, 1),
                    "direction_solves_per_s": tot_solves * M / el,
@@ -206,7 +225,11 @@ def main():
             "value": n * tot2["its"] / el2, "ms_per_step": el2 / max(args.steps, 1) * 1e3,
             "direction_solves_per_s": tot2["solves"] * M / el2,
             "speedup_direction_solves_vs_fp64": (tot2["solves"] * M / el2) / (tot_solves * M / el),
+            "p50_step_s": float(np.percentile(tot2["step_s"], 50)),
+            "p99_step_s": float(np.percentile(tot2["step_s"], 99)),
             "inner_iters_per_step": tot2["its"] / max(args.steps, 1),
+            "refinements_per_step": tot2["refinements"] / max(args.steps, 1),
+            "fp64_completions_per_step": tot2["fp64_completions"] / max(args.steps, 1),
             "rel_l2_phi_point_vs_fp64": float(np.linalg.norm(pv2_np - pv_np) / np.linalg.norm(pv_np)),
             "roofline": roofline(prof2, counters=False)}
     if not args.no_cpu_baseline:
@@ -515,10 +538,30 @@ def cpu_baseline(w, x, R, dx, om, wq, k, min_seconds=10.0):
         el = time.perf_counter() - t0
         if el >= min_seconds:
             break
+    # the same sample on one thread (one ordinate's solves: the oracle runs one ordinate per thread)
+    t1 = time.perf_counter()
+    _, i1, _ = tr.inner_solve(F, 0, 1)
+    el1 = time.perf_counter() - t1
     return {"value": x.shape[0] * its / el, "unit": "DOF*ord*iter/s", "cores": th, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "one_thread_value": x.shape[0] * i1 / el1,
             "sample": f"first-flight inner GMRES solves (right-Jacobi GMRES(30) to 1e-13) of BE step 1 for "
                       f"ordinates 0..{k - 1} of {om.shape[0]}, full {x.shape[0]}-point problem, x{reps}: "
-                      f"{its} Arnoldi steps in {el:.1f} s"}
+                      f"{its} Arnoldi steps in {el:.1f} s on {th} threads; one thread: ordinate 0 alone, "
+                      f"{i1} Arnoldi steps in {el1:.2f} s"}
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu), or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    for line in out.splitlines():
+        if line.startswith("Model name:"):
+            return line.split(":", 1)[1].strip()
+    return None
 
 
 if __name__ == "__main__":

@@ -364,13 +364,14 @@ typedef struct {
                              diffusion-synthetic right preconditioner (see below) */
     int precond;          /* inner solves: MLPG_PRECOND_JACOBI (default, point Jacobi) or
                              MLPG_PRECOND_PATCH (patch block Jacobi, see below) */
-    int graphs;           /* 1 (default): every restart cycle of an inner solve (its Arnoldi steps,
-                             the least-squares update, the new residual and the next cycle's start)
-                             is captured once as a HIP graph and replayed; the host then waits once
-                             per cycle instead of every few steps, and steps after the last system
-                             converges return at their device gates.  0: launched one by one.  The
-                             results are the same bit for bit.  Kernel timing (mlpg_profile_begin)
-                             launches one by one. */
+    int graphs;           /* 1: every restart cycle of an inner solve (its Arnoldi steps, the
+                             least-squares update, the new residual and the next cycle's start) is
+                             captured once per set of launch arguments as a HIP graph and replayed;
+                             the host then waits once per cycle instead of every few steps, and
+                             steps after the last system converges return at their device gates.
+                             0 (default): launched one by one, the host stopping a few steps after
+                             the last system converges.  The results are the same bit for bit.
+                             Kernel timing (mlpg_profile_begin) launches one by one. */
 } mlpg_solve_opts;
 
 /* Right preconditioning of the inner solves L_m x = f (Sec. 4.2 preconditions

@@ -349,13 +349,16 @@ int mlpg_neighbors_count(int dim, int64_t n, const double *x, const double *R, i
     MLPG_CHECK(n > 0 && n < (int64_t)1 << 31, MLPG_ERR_ARG, "mlpg_neighbors_count: n out of range");
     MLPG_CHECK(x && R && nbr_off && total, MLPG_ERR_ARG, "mlpg_neighbors_count: null pointer");
     hipStream_t s = S(stream);
-    DevBuf<int64_t> cnt;
-    MLPG_HIP(cnt.alloc(n));
-    MLPG_HIP(launch_neighbors_count(dim, n, x, R, cnt.p, s));
-    MLPG_HIP(launch_exclusive_scan(cnt.p, nbr_off, n, s));
+    const int64_t mc = nb_max_cells(n);
+    DevBuf<char> scratch;
+    MLPG_HIP(scratch.alloc(nb_scratch_bytes(n, mc)));
+    const NbScratch sc = nb_scratch_at(scratch.p, n, mc);
+    // the counts go into nbr_off itself and are scanned in place
+    MLPG_HIP(launch_neighbors_count(dim, n, x, R, nbr_off, sc, s));
+    MLPG_HIP(launch_exclusive_scan(nbr_off, nbr_off, n, s));
     MLPG_HIP(hipMemcpyAsync(total, nbr_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MLPG_HIP(hipStreamSynchronize(s));
-    cnt.release();
+    scratch.release();
     return MLPG_OK;
 }
 
@@ -363,8 +366,16 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
                         int32_t *nbr_idx, void *stream)
 {
     MLPG_CHECK(dim == 2 || dim == 3, MLPG_ERR_ARG, "mlpg_neighbors_fill: dim must be 2 or 3");
-    MLPG_CHECK(n > 0 && x && R && nbr_off && nbr_idx, MLPG_ERR_ARG, "mlpg_neighbors_fill: bad argument");
-    MLPG_HIP(launch_neighbors_fill(dim, n, x, R, nbr_off, nbr_idx, S(stream)));
+    MLPG_CHECK(n > 0 && n < (int64_t)1 << 31 && x && R && nbr_off && nbr_idx, MLPG_ERR_ARG,
+               "mlpg_neighbors_fill: bad argument");
+    hipStream_t s = S(stream);
+    const int64_t mc = nb_max_cells(n);
+    DevBuf<char> scratch;
+    MLPG_HIP(scratch.alloc(nb_scratch_bytes(n, mc)));
+    const NbScratch sc = nb_scratch_at(scratch.p, n, mc);
+    MLPG_HIP(launch_neighbors_fill(dim, n, x, R, nbr_off, nbr_idx, sc, s));
+    MLPG_HIP(hipStreamSynchronize(s));   // the scratch is released below
+    scratch.release();
     return MLPG_OK;
 }
 
@@ -970,7 +981,7 @@ void mlpg_default_opts(mlpg_solve_opts *o)
     o->max_refine = 12;
     o->accel = MLPG_ACCEL_NONE;
     o->precond = MLPG_PRECOND_JACOBI;
-    o->graphs = 1;
+    o->graphs = 0;
 }
 
 int mlpg_set_state(mlpg_handle h, const double *psi, void *stream)

@@ -6,62 +6,6 @@ namespace mlpg {
 
 namespace {
 
-constexpr int kTile = 256;
-
-// |x_i - x_j| <= R_i + R_j in plain IEEE double with no contraction, so that
-// every implementation of the same definition draws the same lists.
-__device__ __forceinline__ bool overlap_test(int dim, const double *xi, const double *xj, double ri, double rj)
-{
-#pragma clang fp contract(off)
-    double d2 = 0.0;
-    for (int a = 0; a < dim; ++a) {
-        double t = xj[a] - xi[a];
-        d2 = d2 + t * t;
-    }
-    double s = ri + rj;
-    return d2 <= s * s;
-}
-
-// One thread per point i, all j streamed through LDS tiles.  mode 0 counts,
-// mode 1 writes the list in increasing j.
-template <int MODE>
-__global__ __launch_bounds__(kTile) void neighbors_kernel(int dim, int64_t n, const double *__restrict__ x,
-                                                          const double *__restrict__ R, int64_t *__restrict__ counts,
-                                                          const int64_t *__restrict__ off, int32_t *__restrict__ idx)
-{
-    __shared__ double tx[kTile * 3];
-    __shared__ double tr[kTile];
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double xi[3] = {0, 0, 0}, ri = 0.0;
-    if (i < n) {
-        for (int a = 0; a < dim; ++a) xi[a] = x[i * dim + a];
-        ri = R[i];
-    }
-    int64_t cnt = 0;
-    int64_t p = (MODE == 1 && i < n) ? off[i] : 0;
-    for (int64_t base = 0; base < n; base += kTile) {
-        __syncthreads();
-        int64_t j = base + threadIdx.x;
-        if (j < n) {
-            for (int a = 0; a < dim; ++a) tx[threadIdx.x * 3 + a] = x[j * dim + a];
-            tr[threadIdx.x] = R[j];
-        }
-        __syncthreads();
-        if (i < n) {
-            int lim = (int)((n - base) < kTile ? (n - base) : kTile);
-            for (int t = 0; t < lim; ++t) {
-                int64_t jj = base + t;
-                if (jj == i) continue;
-                if (overlap_test(dim, xi, &tx[t * 3], ri, tr[t])) {
-                    if (MODE == 0) cnt++;
-                    else idx[p++] = (int32_t)jj;
-                }
-            }
-        }
-    }
-    if (MODE == 0 && i < n) counts[i] = cnt;
-}
-
 // Exclusive prefix sum of n counts into off[0..n] with a single workgroup:
 // each thread sums a contiguous chunk, the chunk totals are scanned in LDS,
 // then every chunk is written.  counts and off may be the same array (each
@@ -585,21 +529,6 @@ hipError_t launch_check_lists(int64_t n, int64_t total, const int64_t *off, cons
                               unsigned long long *bad, hipStream_t s)
 {
     check_lists_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, total, off, idx, bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *counts, hipStream_t s)
-{
-    int grid = (int)((n + kTile - 1) / kTile);
-    neighbors_kernel<0><<<grid, kTile, 0, s>>>(dim, n, x, R, counts, nullptr, nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *off,
-                                 int32_t *idx, hipStream_t s)
-{
-    int grid = (int)((n + kTile - 1) / kTile);
-    neighbors_kernel<1><<<grid, kTile, 0, s>>>(dim, n, x, R, nullptr, off, idx);
     return hipGetLastError();
 }
 

@@ -194,6 +194,7 @@ struct KrylovT {
     hipEvent_t ev[8] = {};
     int part_blocks = 0;
     std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;   // captured restart cycles
+    hipStream_t capture_stream = nullptr;                       // where they are captured (default priority)
     hipGraphExec_t find_graph(const GraphKey &key) const;
     void add_graph(const GraphKey &key, hipGraphExec_t ge);
     // device buffers for nb systems of n unknowns, restart length up to k_
@@ -347,10 +348,24 @@ int prof_start(int cls, double bytes, hipStream_t s);
 void prof_stop(int id, hipStream_t s);
 
 // ---- kernel launchers -----------------------------------------------------
+// Cell-list neighbour search (neighbors.hip).  Scratch: bounding box (8
+// doubles), each point's cell [n], cell counts [max_cells], cell starts
+// [max_cells + 1], points in cell order [n].
+struct NbScratch {
+    double *bbox = nullptr;
+    int32_t *cell = nullptr;
+    uint32_t *cnt = nullptr;
+    int64_t *coff = nullptr;
+    int32_t *pts = nullptr;
+    int64_t max_cells = 0;
+};
+int64_t nb_max_cells(int64_t n);
+size_t nb_scratch_bytes(int64_t n, int64_t max_cells);
+NbScratch nb_scratch_at(void *base, int64_t n, int64_t max_cells);
 hipError_t launch_neighbors_count(int dim, int64_t n, const double *x, const double *R, int64_t *counts,
-                                  hipStream_t s);
+                                  const NbScratch &sc, hipStream_t s);
 hipError_t launch_neighbors_fill(int dim, int64_t n, const double *x, const double *R, const int64_t *off,
-                                 int32_t *idx, hipStream_t s);
+                                 int32_t *idx, const NbScratch &sc, hipStream_t s);
 hipError_t launch_exclusive_scan(const int64_t *counts, int64_t *off, int64_t n, hipStream_t s);
 // validates caller-supplied overlap lists (sets bits of *bad, see geometry.hip)
 hipError_t launch_check_lists(int64_t n, int64_t total, const int64_t *off, const int32_t *idx,

@@ -736,6 +736,7 @@ hipError_t KrylovT<T>::host_init()
     if ((e = hipHostGetDevicePointer((void **)&nactive_hdev, nactive_host, 0)) != hipSuccess) return e;
     for (int i = 0; i < kSlots; ++i)
         if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -770,6 +771,8 @@ void KrylovT<T>::release()
         for (int i = 0; i < kSlots; ++i)
             if (ev[i]) (void)hipEventDestroy(ev[i]);
     }
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
     nactive_host = nullptr;
     nactive_hdev = nullptr;
     for (int i = 0; i < kSlots; ++i) ev[i] = nullptr;
@@ -821,7 +824,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     // stops return at their gates), so that it can be captured once and
     // replayed; otherwise the host reads the active count a few steps late
     // and stops issuing when no system is left.
-    auto cycle = [&](bool graph_mode) -> int {
+    auto cycle = [&](bool graph_mode, hipStream_t s) -> int {
         init_v0_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, K.r.p, K.beta.p, K.active.p, K.V.p);
         int jc = 0;
         bool early = false;
@@ -941,11 +944,14 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
                     K.nactive.p, tol, (int64_t)n, nb, k, max_its, (int)fused);
             hipGraphExec_t ge = K.find_graph(key);
             if (!ge) {
-                MLPG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                // captured on the Krylov space's own stream (the caller's may be
+                // the legacy default stream, which cannot capture); replayed on s
+                hipStream_t cs = K.capture_stream;
+                MLPG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
                 const int64_t sw0 = sw;
-                int rc = cycle(true);
+                int rc = cycle(true, cs);
                 hipGraph_t g = nullptr;
-                hipError_t ec = hipStreamEndCapture(s, &g);
+                hipError_t ec = hipStreamEndCapture(cs, &g);
                 sw = sw0;
                 if (rc) {
                     if (g) (void)hipGraphDestroy(g);
@@ -960,7 +966,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             MLPG_HIP(hipGraphLaunch(ge, s));
             sw += k;
         } else {
-            int rc = cycle(false);
+            int rc = cycle(false, s);
             if (rc) return rc;
         }
     }

@@ -35,9 +35,10 @@ __device__ __forceinline__ int64_t cell_of(const Grid &g, const double *x)
 {
     int64_t id = 0;
     for (int a = 0; a < g.dim; ++a) {
-        double t = (x[a] - g.lo[a]) * g.inv_h;
-        int64_t b = t < 0.0 ? 0 : (int64_t)t;
-        if (b >= g.dims[a]) b = g.dims[a] - 1;
+        const double t = (x[a] - g.lo[a]) * g.inv_h;
+        int64_t b = 0;   // below the box or NaN
+        if (t >= 0.0 && t < (double)g.dims[a]) b = (int64_t)t;
+        else if (t >= (double)g.dims[a]) b = g.dims[a] - 1;
         id = id * g.dims[a] + b;
     }
     return id;

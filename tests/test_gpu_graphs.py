@@ -33,6 +33,7 @@ def _dev(a):
 
 
 def _problem(n, M, precision, a0=100.0):
+    """A lattice problem, integrated and assembled once."""
     from paper_2008_02205_amd import mlpg
     from paper_2008_02205_amd.problem import GpuProblem
     x, R, dx = lattice_case(n)
@@ -43,9 +44,10 @@ def _problem(n, M, precision, a0=100.0):
     return x, om, P
 
 
-def _run(n, M, precision, precond, graphs, steps=2):
+def _run(P, x, om, precond, graphs, steps=2):
+    """BE steps from the same initial state on an existing problem (one set of integrated
+    blocks: the integration's atomics make separately built problems differ in the last bits)."""
     from paper_2008_02205_amd import mlpg
-    x, om, P = _problem(n, M, precision)
     P.set_state(_dev(W.mms_sin_psi(x, om, 0.0)))
     o = mlpg.mlpg_default_opts()
     o.graphs = 1 if graphs else 0
@@ -58,7 +60,6 @@ def _run(n, M, precision, precond, graphs, steps=2):
         junk = torch.randn(1 << 20, device="cuda").sum()
         torch.cuda.synchronize()
         out.append((phi.cpu().numpy(), psi.cpu().numpy(), info["inner_iters"], info["outer_iters"], float(junk)))
-    P.close()
     return out
 
 
@@ -68,11 +69,15 @@ def test_graph_replay_equals_eager_launches(precision, precond):
     from paper_2008_02205_amd import mlpg
     print(f"[case] graphs precision={precision} precond={precond}", flush=True)
     prec = mlpg.MLPG_FP64 if precision == "fp64" else mlpg.MLPG_MIXED
-    eager = _run(16, 64, prec, precond, graphs=False, steps=3)
-    graph = _run(16, 64, prec, precond, graphs=True, steps=3)
-    for (pe, se, ie, oe, _), (pg, sg, ig, og, _) in zip(eager, graph):
+    x, om, P = _problem(16, 64, prec)
+    eager = _run(P, x, om, precond, graphs=False, steps=3)
+    graph = _run(P, x, om, precond, graphs=True, steps=3)
+    again = _run(P, x, om, precond, graphs=True, steps=3)   # replays of the cached graphs only
+    P.close()
+    for (pe, se, ie, oe, _), (pg, sg, ig, og, _), (pa, sa, ia, oa, _) in zip(eager, graph, again):
         assert np.array_equal(pe, pg) and np.array_equal(se, sg)
-        assert ie == ig and oe == og
+        assert np.array_equal(pe, pa) and np.array_equal(se, sa)
+        assert ie == ig == ia and oe == og == oa
 
 
 def test_autotuned_shape_is_recorded_and_exact():
@@ -80,10 +85,12 @@ def test_autotuned_shape_is_recorded_and_exact():
     print("[case] autotune", flush=True)
     mlpg.mlpg_set_autotune(2)     # empty table
     mlpg.mlpg_set_autotune(0)     # built-in shape
-    ref = _run(14, 96, mlpg.MLPG_FP64, "jacobi", graphs=True, steps=1)
+    x, om, P = _problem(14, 96, mlpg.MLPG_FP64)
+    ref = _run(P, x, om, "jacobi", graphs=True, steps=1)
     assert mlpg.mlpg_get_tuning() == []
     mlpg.mlpg_set_autotune(1)
-    got = _run(14, 96, mlpg.MLPG_FP64, "jacobi", graphs=True, steps=1)
+    got = _run(P, x, om, "jacobi", graphs=True, steps=1)
+    P.close()
     table = mlpg.mlpg_get_tuning()
     print(table, flush=True)
     e = [t for t in table if t["n"] == 196 and t["n_ord"] == 96 and t["streams"] == 6 and t["value_bytes"] == 8]
@@ -93,6 +100,8 @@ def test_autotuned_shape_is_recorded_and_exact():
     assert 0 < e["us_best"] <= e["us_default"]
     assert np.array_equal(ref[0][0], got[0][0]) and np.array_equal(ref[0][1], got[0][1])
     # a small ordinate count tunes the row-group kernel's block size
-    _run(10, 16, mlpg.MLPG_MIXED, "jacobi", graphs=True, steps=1)
+    x, om, P = _problem(10, 16, mlpg.MLPG_MIXED)
+    _run(P, x, om, "jacobi", graphs=True, steps=1)
+    P.close()
     small = [t for t in mlpg.mlpg_get_tuning() if t["n_ord"] == 16]
     assert small and all(t["threads"] in (128, 256, 512) for t in small)
