@@ -48,12 +48,14 @@ int op_L(Problem &P, const OpCall &c, hipStream_t s, void *)
     a.colscale = c.colscale; a.vout = c.vout; a.vsrc = c.vsrc; a.gate = c.gate;
     int id = -1;
     if (prof_on()) {
-        // streams and column indices once, row offsets, x once (plus dinv
-        // when gathered), y written, and the fused normalisation (vsrc read,
-        // vout written); surface rows
+        // the sweep's algorithmic bytes per unit (one row and ordinate): the
+        // streams and column indices once per row, shared by the ordinates,
+        // x read and y written once; summed over the rows and ordinates of
+        // the launch, with the row offsets and the surface rows.  A fused
+        // normalisation (the previous vector read, the basis vector written)
+        // belongs to the Gram-Schmidt side of the step and is not counted.
         const double nm = 8.0 * (double)P.n * P.n_ord;
-        double b = (double)P.nnz * (8.0 * P.nsL + 4.0) + 8.0 * (P.n + 1) + nm * (c.dinv ? 2 : 1) + nm;
-        if (c.vout) b += 2.0 * nm;
+        double b = (double)P.nnz * (8.0 * P.nsL + 4.0) + 8.0 * (P.n + 1) + 2.0 * nm;
         b += (double)P.nnz_s * (8.0 * P.nfaces + 4.0) + 8.0 * (P.n + 1);
         id = prof_start(0, b, s);
     }
@@ -72,9 +74,9 @@ int op_L32(Problem &P, const OpCallT<float> &c, hipStream_t s, void *)
     a.colscale = c.colscale; a.vout = c.vout; a.vsrc = c.vsrc; a.gate = c.gate;
     int id = -1;
     if (prof_on()) {
+        // as for the FP64 sweep, with 4-byte values and vectors
         const double nm = 4.0 * (double)P.n * P.n_ord;
-        double b = (double)P.nnz * (4.0 * P.nsL + 4.0) + 8.0 * (P.n + 1) + nm * (c.dinv ? 2 : 1) + nm;
-        if (c.vout) b += 2.0 * nm;
+        double b = (double)P.nnz * (4.0 * P.nsL + 4.0) + 8.0 * (P.n + 1) + 2.0 * nm;
         b += (double)P.nnz_s * (4.0 * P.nfaces + 4.0) + 8.0 * (P.n + 1);
         id = prof_start(0, b, s);
     }
