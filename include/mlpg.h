@@ -126,6 +126,27 @@ int mlpg_neighbors_fill(int dim, int64_t n, const double *x, const double *R, co
                         int32_t *nbr_idx, void *stream);
 
 /* ------------------------------------------------------------------------
+ * The same overlap lists without any allocation, for callers that cannot
+ * allocate device memory while they run (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The search's scratch (the
+ * points' bounding box and cells, the cell counts and starts, the points in
+ * cell order) lives in a static device array of about 20 MiB that every GPU
+ * holds until the process ends; no hipMalloc, hipFree or allocating library
+ * call is made.  Counts into nbr_off (device [n+1], exclusive prefix sums),
+ * the total into *total (host), then, when it is at most cap, the lists into
+ * nbr_idx (device [cap]) -- the lists of mlpg_neighbors_count/_fill exactly.
+ *   n: 1 .. 2^20 points (MLPG_ERR_ARG beyond: the array's capacity);
+ *   cap: entries nbr_idx holds; cap < *total returns MLPG_ERR_CAPACITY with
+ *        *total set and nbr_idx untouched (cap = 0: count only).
+ * Synchronises `stream`.  Every call on one GPU uses that GPU's one array,
+ * which keeps the previous call's contents (the search clears what must
+ * start at zero): calls that overlap on one GPU (other threads or streams)
+ * race and must be serialised by the caller.
+ * ---------------------------------------------------------------------- */
+int mlpg_neighbors_static(int dim, int64_t n, const double *x, const double *R, int64_t *nbr_off,
+                          int32_t *nbr_idx, int64_t cap, int64_t *total, void *stream);
+
+/* ------------------------------------------------------------------------
  * Stage 1, geometry (Sec. 3.1, Fig. 1; Sec. 3.4).  Creates a handle.  Each
  * point gets the convex cell obtained by clipping the box
  * [x_i - R_i, x_i + R_i]^dim intersected with the domain box by the

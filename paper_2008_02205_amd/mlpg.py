@@ -32,7 +32,7 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_material_fields", "mlpg_update_points", "mlpg_refined_quadrature",
            "mlpg_material_shells", "mlpg_apply_patch_precond", "mlpg_geometry_workspace_bytes",
            "mlpg_integrate_workspace_bytes", "mlpg_assemble_workspace_bytes", "mlpg_solve_workspace_bytes",
-           "mlpg_set_autotune", "mlpg_get_tuning"]
+           "mlpg_set_autotune", "mlpg_get_tuning", "mlpg_neighbors_static"]
 
 
 class MlpgError(RuntimeError):
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
         L.mlpg_angular_quadrature.argtypes = [i32, i32, i32, vp, vp]
         L.mlpg_neighbors_count.argtypes = [i32, i64, vp, vp, vp, C.POINTER(C.c_int64), vp]
         L.mlpg_neighbors_fill.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+        L.mlpg_neighbors_static.argtypes = [i32, i64, vp, vp, vp, vp, i64, C.POINTER(C.c_int64), vp]
         L.mlpg_geometry.argtypes = [C.POINTER(vp), i32, i64, vp, vp, vp, vp, vp, vp, i32, vp, vp, vp, vp, C.c_size_t,
                                     vp]
         L.mlpg_geometry_workspace_bytes.restype = C.c_size_t
