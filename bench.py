@@ -51,6 +51,9 @@ def parse():
                     help="instead of the benchmark: serve this many requests of the seeded request stream "
                          "(Poisson arrivals at 50/s, mixed precision) and print latency and throughput")
     ap.add_argument("--slots", type=int, default=4, help="concurrent problems in the serving mode")
+    ap.add_argument("--serving-sample", type=int, default=40,
+                    help="after the benchmark, serve the first K requests of the seeded request stream and add "
+                         "their latency p50/p99 and offered/achieved load to the record (0: skip)")
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 6, 7, 8, 9],
                     help="2: the benchmark above; 1, 3, 4: time that workload's whole path instead (phase times, "
                          "p50/p99 over --steps repetitions) and print its own record; 6, 7: the paper's sinusoidal "
@@ -234,6 +237,8 @@ def main():
             "roofline": roofline(prof2, counters=False)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
+    if args.serving_sample:
+        rec["detail"]["serving_sample"] = serving_record(args.serving_sample, args.slots, None)
     print(json.dumps(rec), flush=True)
 
 
@@ -451,8 +456,10 @@ def asteroid_workload(args):
     print(json.dumps(rec), flush=True)
 
 
-def serve(args):
-    """Request-stream mode: continuous batching with HBM-budget admission."""
+def serving_record(k, slots, opts):
+    """The first k requests of the seeded request stream (Poisson arrivals at 50/s, real time) through
+    the request server: latency p50/p99 from arrival to result, offered and achieved load, aggregate
+    iteration rate, and the exact device bytes of the requests against their admission bounds."""
     from paper_2008_02205_amd import mlpg
     from paper_2008_02205_amd.serving import Server, latency_summary
 
@@ -461,23 +468,34 @@ def serve(args):
         om, wq = mlpg.mlpg_angular_quadrature(2, spec.n_ord)
         return x, R, dx, om, wq, spec.sigma_t, spec.sigma_s, np.ones((x.shape[0], spec.n_ord))
 
-    specs = W.request_stream(args.serving)
+    specs = W.request_stream(k)
     t0 = time.perf_counter()
+    res = Server(slots=slots, opts=opts).run(specs, build, realtime=True, keep_fields=False)
+    el = time.perf_counter() - t0
+    summ = latency_summary(res)
+    its = sum(r.info["inner_iters"] * r_spec.side ** 2 for r, r_spec in zip(res, specs) if r.info)
+    return {"requests": k, "slots": slots, "p50_s": summ["p50_s"], "p99_s": summ["p99_s"],
+            "mean_s": summ["mean_s"], "failed": summ["failed"],
+            "offered_req_s": len(specs) / specs[-1].arrival if specs[-1].arrival > 0 else None,
+            "achieved_req_s": summ["throughput_req_s"], "DOF*ord*iter_per_s": its / el, "wall_s": el,
+            "exact_bytes_over_admission_bound": summ["exact_over_reserved"],
+            "workload": "steady 2D problems, N log-uniform in [1024, 65536] (square lattices), M in "
+                        "{16,32,64,128}, sigma_t log-uniform [0.1,100], c uniform [0,0.95], mixed precision"}
+
+
+def serve(args):
+    """Request-stream mode: continuous batching with HBM-budget admission."""
+    from paper_2008_02205_amd import mlpg
     opts = None
     if args.accel:
         opts = mlpg.mlpg_default_opts()
         opts.accel = mlpg.MLPG_ACCEL_DSA
-    res = Server(slots=args.slots, opts=opts).run(specs, build, realtime=True, keep_fields=False)
-    el = time.perf_counter() - t0
-    summ = latency_summary(res)
-    its = sum(r.info["inner_iters"] * r_spec.side ** 2 for r, r_spec in zip(res, specs) if r.info)
-    rec = {"metric": "request-stream latency (p50/p99) and throughput", "value": summ["p50_s"], "unit": "s",
+    r = serving_record(args.serving, args.slots, opts)
+    rec = {"metric": "request-stream latency (p50/p99) and throughput", "value": r["p50_s"], "unit": "s",
            "higher_is_better": False, "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
-           "config": {"workload": f"request stream: {args.serving} steady 2D problems, Poisson arrivals at 50/s, "
-                                  f"N log-uniform in [1024, 65536], M in {{16,32,64,128}}, mixed precision",
+           "config": {"workload": f"request stream: {args.serving} " + r["workload"] + ", Poisson arrivals at 50/s",
                       "slots": args.slots, "accel": "dsa" if args.accel else "none"},
-           "serving": summ, "offered_req_s": len(specs) / specs[-1].arrival,
-           "DOF*ord*iter_per_s": its / el, "wall_s": el}
+           "serving": r}
     print(json.dumps(rec), flush=True)
 
 

@@ -499,14 +499,12 @@ int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
  * times every candidate launch shape of the sweep on the problem's own
  * operator, as the inner solver calls it, and keeps the fastest in a
  * process-wide table used by every later sweep of that shape:
- *   n_ord >= 48: 8, 16 or 32 nonzeros per batch of column loads and x
- *     gathers, 2, 4 or 8 waves per workgroup, workgroups renumbered so that
- *     each of the 8 dies walks one contiguous row range (xcd_split = 8) or
- *     not (1), one (row, 64-ordinate) item per wave (and the built-in shape
- *     with two items per wave);
+ *   n_ord >= 48: 2, 4 or 8 waves per workgroup, 1 or 2 (row, 64-ordinate)
+ *     items per wave, workgroups renumbered so that each of the 8 dies walks
+ *     one contiguous row range (xcd_split = 8) or not (1);
  *   n_ord < 48: 128, 256 or 512 threads per workgroup.
- * mlpg_set_autotune(0) keeps the built-in shape (batch 8, 4 waves, 1 item,
- * split 8; 256 threads) for shapes not yet in the table, (1) measures again (the
+ * mlpg_set_autotune(0) keeps the built-in shape (4 waves, 1 item, split 8;
+ * 256 threads) for shapes not yet in the table, (1) measures again (the
  * default), (2) empties the table.  Every shape computes each row's sums in
  * the same order, so the results do not depend on the choice.
  * mlpg_get_tuning copies up to cap entries to out (host) and returns the
@@ -515,7 +513,7 @@ int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
 typedef struct {
     int64_t n;
     int n_ord, streams, value_bytes;
-    int waves_per_block, items_per_wave, xcd_split, threads, batch;
+    int waves_per_block, items_per_wave, xcd_split, threads;
     float us_best, us_default;   /* measured duration of the chosen and of the built-in shape */
 } mlpg_tune_entry;
 int mlpg_set_autotune(int mode);

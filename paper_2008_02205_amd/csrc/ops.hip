@@ -226,19 +226,13 @@ __device__ __forceinline__ float bcast(float v, int lane)
 // owns one (row, 64-ordinate chunk).  The row index is wave-uniform, so the
 // row's column indices and stream values are read with scalar loads straight
 // into SGPRs (read-only kernel arguments, no vector broadcast needed) and
-// combined with the lane's own coefficients.  The row is taken BATCH
-// nonzeros at a time: the batch's column indices first, then all its x
-// gathers back to back (their latencies overlap), then the stream values and
-// the products.  A row's last batch reads its last entry again in place of
-// the missing ones and adds them as zeros, so nothing past the row is read.
-// Nonzero u of the row always goes to accumulator u mod 4 in increasing
-// order, whatever BATCH is, so every batch size gives the same sums.
-template <int NS, class T, int MODE, int BATCH>
+// combined with the lane's own coefficients; the x gathers of eight nonzeros
+// are issued back to back so that their latencies overlap.
+template <int NS, class T, int MODE>
 __global__ __launch_bounds__(512) void spmv_wave_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
                                                         const int32_t *__restrict__ col,
                                                         const T *__restrict__ vals)
 {
-    static_assert(BATCH % 4 == 0, "batches keep the accumulator of each nonzero");
     if (k.gate && *k.gate == 0) return;
     // Workgroups are dealt round-robin to the dies (XCDs), each with its own
     // L2; renumber them so that every die walks one contiguous range of rows
@@ -262,28 +256,53 @@ __global__ __launch_bounds__(512) void spmv_wave_kernel(SpmvK<T> k, const int64_
 #pragma unroll
         for (int b = 0; b < NS; ++b) c[b] = k.coef[mm * NS + b];
         const int64_t p0 = row_off[iu], p1 = row_off[iu + 1];
-        T acc[4] = {0, 0, 0, 0};
-        for (int64_t p = p0; p < p1; p += BATCH) {
-            int32_t jj[BATCH];
-            T xx[BATCH], aa[BATCH];
+        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+        int64_t p = p0;
+        for (; p + 7 < p1; p += 8) {
+            int32_t jj[8];
+            T xx[8], aa[8];
 #pragma unroll
-            for (int u = 0; u < BATCH; ++u) jj[u] = col[p + u < p1 ? p + u : p1 - 1];
+            for (int u = 0; u < 8; ++u) jj[u] = col[p + u];
 #pragma unroll
-            for (int u = 0; u < BATCH; ++u) xx[u] = xin<MODE>(k, jj[u], mm);
+            for (int u = 0; u < 8; ++u) xx[u] = xin<MODE>(k, jj[u], mm);
 #pragma unroll
-            for (int u = 0; u < BATCH; ++u) {
-                const int64_t q = p + u < p1 ? p + u : p1 - 1;
+            for (int u = 0; u < 8; ++u) {
                 T a = 0;
 #pragma unroll
-                for (int b = 0; b < NS; ++b) a += c[b] * vals[q * NS + b];
-                aa[u] = p + u < p1 ? a : (T)0;
+                for (int b = 0; b < NS; ++b) a += c[b] * vals[(p + u) * NS + b];
+                aa[u] = a;
             }
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) acc[u & 3] += aa[u] * xx[u];
+            acc0 += aa[0] * xx[0] + aa[4] * xx[4];
+            acc1 += aa[1] * xx[1] + aa[5] * xx[5];
+            acc2 += aa[2] * xx[2] + aa[6] * xx[6];
+            acc3 += aa[3] * xx[3] + aa[7] * xx[7];
         }
-        T accs = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        if (k.soff) accs += spmv_surface<MODE>(k, iu, mm);
-        if (on) spmv_finish(k, iu, m, accs);
+        for (; p + 3 < p1; p += 4) {
+            const int32_t j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
+            const T x0 = xin<MODE>(k, j0, mm), x1 = xin<MODE>(k, j1, mm), x2 = xin<MODE>(k, j2, mm),
+                    x3 = xin<MODE>(k, j3, mm);
+            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) {
+                a0 += c[b] * vals[p * NS + b];
+                a1 += c[b] * vals[(p + 1) * NS + b];
+                a2 += c[b] * vals[(p + 2) * NS + b];
+                a3 += c[b] * vals[(p + 3) * NS + b];
+            }
+            acc0 += a0 * x0;
+            acc1 += a1 * x1;
+            acc2 += a2 * x2;
+            acc3 += a3 * x3;
+        }
+        for (; p < p1; ++p) {
+            T a0 = 0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) a0 += c[b] * vals[p * NS + b];
+            acc0 += a0 * xin<MODE>(k, col[p], mm);
+        }
+        T acc = (acc0 + acc1) + (acc2 + acc3);
+        if (k.soff) acc += spmv_surface<MODE>(k, iu, mm);
+        if (on) spmv_finish(k, iu, m, acc);
     }
 }
 
@@ -457,7 +476,7 @@ hipError_t launch_jacobi(Problem &P, hipStream_t s)
 // ordinates, streams, value size) is measured once per process on the
 // problem's own operator and kept in a table (mlpg_get_tuning).
 struct SpmvShape {
-    int wpb = 4, ipw = 1, xcd = 8, threads = 256, batch = 8;
+    int wpb = 4, ipw = 1, xcd = 8, threads = 256;
 };
 
 namespace {
@@ -521,13 +540,9 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
     if (a.x2) mode = IN_X2;
     if (a.dinv) mode = IN_DINV;
     if ((a.x_bcast != 0) + (a.x2 != nullptr) + (a.dinv != nullptr) > 1) return hipErrorInvalidValue;
-#define MLPG_SPMV_W(NSV, MD, BT) spmv_wave_kernel<NSV, T, MD, BT><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals)
 #define MLPG_SPMV_M(NSV, MD)                                                      \
-    if (wave) {                                                                   \
-        if (sh.batch == 32) MLPG_SPMV_W(NSV, MD, 32);                             \
-        else if (sh.batch == 16) MLPG_SPMV_W(NSV, MD, 16);                        \
-        else MLPG_SPMV_W(NSV, MD, 8);                                             \
-    } else spmv_group_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k)
+    if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals); \
+    else spmv_group_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k)
 #define MLPG_SPMV(NSV)                                                            \
     switch (mode) {                                                               \
     case IN_PLAIN: MLPG_SPMV_M(NSV, IN_PLAIN); break;                             \
@@ -544,7 +559,6 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
     }
 #undef MLPG_SPMV
 #undef MLPG_SPMV_M
-#undef MLPG_SPMV_W
     return hipGetLastError();
 }
 
@@ -568,16 +582,13 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
     if (!g_autotune || find_shape(P.n, P.n_ord, a.ns, (int)sizeof(T), &cur)) return hipSuccess;
     std::vector<SpmvShape> cand;
     if (P.n_ord >= 48) {
-        for (int batch : {8, 16, 32})
-            for (int wpb : {2, 4, 8})
+        for (int wpb : {2, 4, 8})
+            for (int ipw : {1, 2})
                 for (int xcd : {8, 1}) {
                     SpmvShape c;
-                    c.wpb = wpb; c.xcd = xcd; c.batch = batch;
+                    c.wpb = wpb; c.ipw = ipw; c.xcd = xcd;
                     cand.push_back(c);
                 }
-        SpmvShape c2;   // two items per wave
-        c2.ipw = 2;
-        cand.push_back(c2);
     } else {
         for (int th : {128, 256, 512}) {
             SpmvShape c;
@@ -605,8 +616,7 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
         }
         if (e != hipSuccess) break;
         const SpmvShape d;
-        if (c.wpb == d.wpb && c.ipw == d.ipw && c.xcd == d.xcd && c.threads == d.threads && c.batch == d.batch)
-            dflt = t;
+        if (c.wpb == d.wpb && c.ipw == d.ipw && c.xcd == d.xcd && c.threads == d.threads) dflt = t;
         if (t < best) {
             best = t;
             pick = c;
@@ -643,7 +653,6 @@ int get_tuning(int cap, mlpg_tune_entry *out)
         out[i].items_per_wave = e.M >= 48 ? e.shape.ipw : 0;
         out[i].xcd_split = e.M >= 48 ? e.shape.xcd : 0;
         out[i].threads = e.M >= 48 ? 64 * e.shape.wpb : e.shape.threads;
-        out[i].batch = e.M >= 48 ? e.shape.batch : 0;
         out[i].us_best = e.us_best;
         out[i].us_default = e.us_default;
     }
