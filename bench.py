@@ -213,9 +213,8 @@ def main():
                    "outer_iters_per_step": tot_out / max(args.steps, 1),
                    "direction_solves_per_s": tot_solves * M / el,
                    "kernel_classes": {k: {"avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
-                                          "launches": v["launches"],
-                                          "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None,
-                                          "share_of_step": v["ms"] / ms if ms > 0 else None}
+                                          "timed_launches": v["launches"],
+                                          "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                                       for k, v in prof.items()},
                    "rel_l1_phi_vs_manufactured": err},
         "roofline": roofline(prof, counters=main_name == "fp64"),

@@ -486,8 +486,10 @@ int mlpg_point_values(mlpg_handle h, const double *coef, double *out, void *stre
  *   class 2: Gram-Schmidt pass B (reorthogonalised basis vector, projected
  *            operator output, its norm)
  *   class 3: end-of-cycle pass A (projections of the last vector only)
+ * Only the first 4096 launches of each class in a session are bracketed.
  * mlpg_profile_end synchronises the device and fills, per class (arrays of
- * MLPG_PROF_CLASSES): total kernel time in ms, launch count and bytes.
+ * MLPG_PROF_CLASSES): total time in ms, launch count and bytes of the
+ * bracketed launches.
  * ---------------------------------------------------------------------- */
 #define MLPG_PROF_CLASSES 4
 int mlpg_profile_begin(void);

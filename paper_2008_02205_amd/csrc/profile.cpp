@@ -15,11 +15,17 @@ struct Rec {
     hipEvent_t a, b;
 };
 
+// At most this many launches of a class are bracketed per profiling session
+// (the first ones): enough for a per-launch average, and a bounded number of
+// events however long the profiled work is.
+constexpr int64_t kMaxPerClass = 4096;
+
 struct State {
     bool on = false;
     std::vector<hipEvent_t> pool;
     std::vector<Rec> recs;
     size_t used = 0;
+    int64_t per_class[MLPG_PROF_CLASSES] = {};
 };
 
 State g_prof;
@@ -40,7 +46,8 @@ bool prof_on() { return g_prof.on; }
 
 int prof_start(int cls, double bytes, hipStream_t s)
 {
-    if (!g_prof.on) return -1;
+    if (!g_prof.on || cls < 0 || cls >= MLPG_PROF_CLASSES || g_prof.per_class[cls] >= kMaxPerClass) return -1;
+    g_prof.per_class[cls]++;
     Rec r{cls, bytes, take(), take()};
     if (!r.a || !r.b || hipEventRecord(r.a, s) != hipSuccess) return -1;
     g_prof.recs.push_back(r);
@@ -62,6 +69,7 @@ extern "C" int mlpg_profile_begin(void)
     g_prof.on = true;
     g_prof.recs.clear();
     g_prof.used = 0;
+    for (int c = 0; c < MLPG_PROF_CLASSES; ++c) g_prof.per_class[c] = 0;
     return MLPG_OK;
 }
 
