@@ -499,27 +499,41 @@ int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
  * Launch-shape autotuning of the transport sweep.  Before the first solve of
  * a problem shape (rows n, ordinates, value streams, value size) the library
  * times every candidate launch shape of the sweep on the problem's own
- * operator, as the inner solver calls it, and keeps the fastest in a
- * process-wide table used by every later sweep of that shape:
- *   n_ord >= 48: 2, 4 or 8 waves per workgroup, 1 or 2 (row, 64-ordinate)
- *     items per wave, workgroups renumbered so that each of the 8 dies walks
- *     one contiguous row range (xcd_split = 8) or not (1);
+ * operator, as the inner solver calls it and with the caches evicted by a
+ * read of the solve's Krylov basis before each timed launch (as between two
+ * sweeps of the Arnoldi loop), and keeps the fastest in a process-wide table
+ * used by every later sweep of that shape:
+ *   n_ord >= 48, form 0 (stream values read with scalar loads by each wave):
+ *     2, 4 or 8 waves per workgroup, 1 or 2 (row, 64-ordinate) items per
+ *     wave, workgroups renumbered so that each of the 8 dies walks one
+ *     contiguous row range (xcd_split = 8) or not (1);
+ *   48 <= n_ord <= 64 with 6 or 10 streams, form 1 (stream values staged
+ *     through LDS by the workgroup, two rounds deep): 4 or 8 waves (4 only
+ *     for 10 FP64 streams), 2 or 4 rounds of one row per wave, xcd_split 8;
  *   n_ord < 48: 128, 256 or 512 threads per workgroup.
- * mlpg_set_autotune(0) keeps the built-in shape (4 waves, 1 item, split 8;
- * 256 threads) for shapes not yet in the table, (1) measures again (the
- * default), (2) empties the table.  Every shape computes each row's sums in
- * the same order, so the results do not depend on the choice.
+ * mlpg_set_autotune(0) keeps the built-in shape (form 0, 4 waves, 1 item,
+ * split 8; 256 threads) for shapes not yet in the table, (1) measures again
+ * (the default), (2) empties the table.  Every shape computes each row's sums
+ * in the same order, so the results do not depend on the choice.
  * mlpg_get_tuning copies up to cap entries to out (host) and returns the
- * table's size.  Process-wide; the table is guarded by a lock.
+ * table's size.  mlpg_set_tuning inserts or replaces the entry of
+ * entry->(n, n_ord, streams, value_bytes) (host struct; us_best and
+ * us_default are stored as given), so that a table saved from one process
+ * can be loaded into the next, or a shape pinned; MLPG_ERR_ARG for a shape
+ * outside the ranges above (form 1: 4 or 8 waves, 1..64 rounds; form 0: 1..8
+ * waves, 1..64 items; xcd_split 1 or 8; threads in [n_ord, 512]).
+ * Process-wide; the table is guarded by a lock.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int64_t n;
     int n_ord, streams, value_bytes;
-    int waves_per_block, items_per_wave, xcd_split, threads;
+    int form;                    /* 0 or 1 as above (0 for n_ord < 48) */
+    int waves_per_block, items_per_wave, rounds, xcd_split, threads;
     float us_best, us_default;   /* measured duration of the chosen and of the built-in shape */
 } mlpg_tune_entry;
 int mlpg_set_autotune(int mode);
 int mlpg_get_tuning(int cap, mlpg_tune_entry *out);
+int mlpg_set_tuning(const mlpg_tune_entry *entry);
 
 /* ------------------------------------------------------------------------
  * Progress reports for long solves.  When set, the library calls

@@ -969,6 +969,14 @@ int mlpg_get_tuning(int cap, mlpg_tune_entry *out)
     return get_tuning(cap, out);
 }
 
+int mlpg_set_tuning(const mlpg_tune_entry *entry)
+{
+    MLPG_CHECK(entry, MLPG_ERR_ARG, "mlpg_set_tuning: null entry");
+    const std::string why = set_tuning(*entry);
+    MLPG_CHECK(why.empty(), MLPG_ERR_ARG, "mlpg_set_tuning: " + why);
+    return MLPG_OK;
+}
+
 void mlpg_default_opts(mlpg_solve_opts *o)
 {
     if (!o) return;
@@ -1042,14 +1050,14 @@ int mlpg_solve(mlpg_handle h, const double *q, const double *psi_b, double *phi_
         SpmvArgs a;
         a.vals = P->sL.p; a.ns = P->nsL; a.coef = P->coefL.p; a.x = P->t1.p; a.surface = 1; a.y = P->t2.p;
         a.sval = P->surf_val.p; a.coefF = P->coefF.p; a.colscale = P->wq.p; a.vout = P->bpsi.p; a.vsrc = P->t1.p;
-        MLPG_HIP(tune_spmv<double>(*P, a, s));
+        MLPG_HIP(tune_spmv<double>(*P, a, P->inner.V.p, sizeof(double) * P->inner.V.count, s));
         if (P->precision == MLPG_MIXED) {
             MLPG_HIP(hipMemsetAsync(P->r32.p, 0, sizeof(float) * nm, s));
             SpmvArgsT<float> b;
             b.vals = P->sL32.p; b.ns = P->nsL; b.coef = P->coefL32.p; b.x = P->r32.p; b.surface = 1;
             b.y = P->d32.p; b.sval = P->surf_val32.p; b.coefF = P->coefF32.p; b.colscale = P->wq.p;
             b.vout = P->inner32.w.p; b.vsrc = P->r32.p;
-            MLPG_HIP(tune_spmv<float>(*P, b, s));
+            MLPG_HIP(tune_spmv<float>(*P, b, P->inner32.V.p, sizeof(float) * P->inner32.V.count, s));
         }
     }
     const int64_t n = P->n;

@@ -417,11 +417,13 @@ struct SpmvArgsT {
 using SpmvArgs = SpmvArgsT<double>;
 template <class T>
 hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s);
-// measures the sweep's launch shapes for this problem's size once per process (ops.hip)
+// measures the sweep's launch shapes for this problem's size once per process,
+// reading the scratch region `evict` before each timed launch (ops.hip)
 template <class T>
-hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s);
+hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, const void *evict, size_t evict_bytes, hipStream_t s);
 void set_autotune(int mode);   // 0 off, 1 on, 2 clear the table
 int get_tuning(int cap, mlpg_tune_entry *out);
+std::string set_tuning(const mlpg_tune_entry &t);   // "" or what is wrong with t
 hipError_t launch_to_float_scaled(int64_t n, int M, const double *r, const double *rn2, const double *fn2, double tol,
                                   float *out, hipStream_t s);
 hipError_t launch_axpy_from_float(int64_t n, int M, double *x, const float *d, const double *rn2, hipStream_t s);

@@ -8,6 +8,7 @@
 // combines the streams with its own coefficients (products of Omega_m
 // components) in registers, so L_m is never stored per ordinate.
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -88,19 +89,19 @@ __global__ void assemble_kernel(AsmArgs a)
     }
 }
 
-// Surface rows: count entries of row i with any nonzero face block.
+// Surface rows: a row with any nonzero face block keeps the face values of
+// every one of its nonzeros (zeros included), so that its surface entry
+// s0 + (p - p0) belongs to nonzero p and the sweep can add the faces' sums
+// in the row's main loop; other rows keep none.
 __global__ void surface_count_kernel(int64_t n, int64_t nnz, int nf, int sb, const int64_t *row_off,
                                      const double *blocks, int64_t *counts)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int64_t c = 0;
-    for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) {
-        bool nz = false;
+    bool nz = false;
+    for (int64_t p = row_off[i]; p < row_off[i + 1] && !nz; ++p)
         for (int f = 0; f < nf; ++f) nz |= blocks[(int64_t)(sb + f) * nnz + p] != 0.0;
-        c += nz;
-    }
-    counts[i] = c;
+    counts[i] = nz ? row_off[i + 1] - row_off[i] : 0;
 }
 
 __global__ void surface_fill_kernel(int64_t n, int64_t nnz, int nf, int sb, const int64_t *row_off,
@@ -108,15 +109,11 @@ __global__ void surface_fill_kernel(int64_t n, int64_t nnz, int nf, int sb, cons
                                     double *sval)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || soff[i + 1] == soff[i]) return;
     int64_t o = soff[i];
-    for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p) {
-        bool nz = false;
-        for (int f = 0; f < nf; ++f) nz |= blocks[(int64_t)(sb + f) * nnz + p] != 0.0;
-        if (!nz) continue;
+    for (int64_t p = row_off[i]; p < row_off[i + 1]; ++p, ++o) {
         scol[o] = col[p];
         for (int f = 0; f < nf; ++f) sval[o * nf + f] = blocks[(int64_t)(sb + f) * nnz + p];
-        o++;
     }
 }
 
@@ -184,26 +181,90 @@ __device__ __forceinline__ T xin(const SpmvK<T> &k, int64_t j, int m)
     return xv;
 }
 
-template <class T>
-__device__ __forceinline__ void spmv_finish(const SpmvK<T> &k, int64_t i, int m, T acc)
+// The same without the factor xs, where xs can be applied once to the row's
+// sum instead (every mode but IN_X2); xs_out() is that factor.
+template <int MODE, class T>
+__device__ __forceinline__ T xraw(const SpmvK<T> &k, int64_t j, int m)
 {
-    const int64_t o = i * k.M + m;
-    const T sc = k.colscale ? (T)k.colscale[m] : (T)1;
-    if (k.vout) k.vout[o] = sc * (k.vsrc ? k.vsrc[o] : k.x[o]);
-    acc *= sc;
-    k.y[o] = k.yadd ? k.yadd[o] + (T)k.ysign * acc : acc;
+    if (MODE == IN_X2) return xin<MODE>(k, j, m);
+    if (MODE == IN_BCAST) return k.x[j];
+    const int64_t o = j * k.M + m;
+    if (MODE == IN_DINV) return k.x[o] * k.dinv[o];
+    return k.x[o];
 }
 
-// Surface rows (few): the outflow blocks weighted by max(0, W.n_f).
 template <int MODE, class T>
-__device__ __forceinline__ T spmv_surface(const SpmvK<T> &k, int64_t i, int m)
+__device__ __forceinline__ T xs_out(const SpmvK<T> &k)
 {
+    return MODE == IN_X2 ? (T)1 : k.xs;
+}
+
+// Operands of one output entry o = (i, m) besides the row's nonzeros:
+// the per-ordinate column scale, the input entry that becomes the scaled
+// basis vector, the addend, and the row's range of surface entries.  Loaded
+// before the row's nonzeros so that their latency hides under that loop.
+template <class T>
+struct RowEnds {
+    T sc, vin, yad;
+    int64_t s0, s1;
+};
+
+template <class T>
+__device__ __forceinline__ RowEnds<T> row_ends(const SpmvK<T> &k, int64_t i, int m)
+{
+    const int64_t o = i * k.M + m;
+    RowEnds<T> r;
+    r.sc = k.colscale ? (T)k.colscale[m] : (T)1;
+    r.vin = k.vout ? (k.vsrc ? k.vsrc[o] : k.x[o]) : (T)0;
+    r.yad = k.yadd ? k.yadd[o] : (T)0;
+    r.s0 = k.soff ? k.soff[i] : 0;
+    r.s1 = k.soff ? k.soff[i + 1] : 0;
+    return r;
+}
+
+template <class T>
+__device__ __forceinline__ void spmv_finish(const SpmvK<T> &k, int64_t i, int m, T acc, const RowEnds<T> &r)
+{
+    const int64_t o = i * k.M + m;
+    if (k.vout) k.vout[o] = r.sc * r.vin;
+    acc *= r.sc;
+    k.y[o] = k.yadd ? r.yad + (T)k.ysign * acc : acc;
+}
+
+// Surface entries [s0, s1) of a row (rows within a support radius of the
+// boundary have some tens): the outflow blocks weighted by max(0, W.n_f), at
+// most six faces.  Columns are read eight at a time and their x gathers
+// issued together, as in the row's main loop; the sum runs over p in order.
+template <int MODE, class T>
+__device__ __forceinline__ T spmv_surface(const SpmvK<T> &k, int64_t s0, int64_t s1, int m)
+{
+    const int nf = k.nf;
+    T cf[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) cf[f] = f < nf ? k.coefF[m * nf + f] : (T)0;
     T acc = 0;
-    T cf[6] = {0, 0, 0, 0, 0, 0};
-    for (int f = 0; f < k.nf; ++f) cf[f] = k.coefF[m * k.nf + f];
-    for (int64_t p = k.soff[i]; p < k.soff[i + 1]; ++p) {
+    int64_t p = s0;
+    for (; p + 7 < s1; p += 8) {
+        int32_t jj[8];
+        T xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) jj[u] = k.scol[p + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = xin<MODE>(k, jj[u], m);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            T a = 0;
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+                if (f < nf) a += cf[f] * k.sval[(p + u) * nf + f];
+            acc += a * xx[u];
+        }
+    }
+    for (; p < s1; ++p) {
         T a = 0;
-        for (int f = 0; f < k.nf; ++f) a += cf[f] * k.sval[p * k.nf + f];
+#pragma unroll
+        for (int f = 0; f < 6; ++f)
+            if (f < nf) a += cf[f] * k.sval[p * nf + f];
         acc += a * xin<MODE>(k, k.scol[p], m);
     }
     return acc;
@@ -222,16 +283,119 @@ __device__ __forceinline__ float bcast(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// The per-stream row sums t_b of one row from nonzeros [p, p1) whose column
+// indices and stream values are read through `cl` and `vl` (global memory or
+// the LDS stage): eight x gathers issued back to back, then the FMAs.
+template <int NS, class T, int MODE, class CI, class VI>
+__device__ __forceinline__ void row_streams(const SpmvK<T> &k, CI cl, VI vl, int64_t p, int64_t p1, int mm, T (&t)[NS])
+{
+    for (; p + 7 < p1; p += 8) {
+        int32_t jj[8];
+        T xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) jj[u] = cl[p + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = xraw<MODE>(k, jj[u], mm);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int b = 0; b < NS; ++b) t[b] += vl[(p + u) * NS + b] * xx[u];
+    }
+    for (; p < p1; ++p) {
+        const T xv = xraw<MODE>(k, cl[p], mm);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) t[b] += vl[p * NS + b] * xv;
+    }
+}
+
+// Face count of the transport operators' surface term: 4 in 2D (6 value
+// streams), 6 in 3D (10 streams).
+template <int NS>
+struct FacesOf {
+    static constexpr int value = NS == 10 ? 6 : 4;
+};
+
+// row_streams on a surface row, whose face values are stored aligned with
+// its nonzeros (surface entry p + fofs belongs to nonzero p): the per-face
+// sums u_f = sum_p s_f[p] x[col p] are accumulated from the same x gathers.
+template <int NS, int NF, class T, int MODE, class CI, class VI>
+__device__ __forceinline__ void row_streams_faces(const SpmvK<T> &k, CI cl, VI vl, const T *__restrict__ fv,
+                                                  int64_t p, int64_t p1, int64_t fofs, int mm, T (&t)[NS],
+                                                  T (&uf)[NF])
+{
+    for (; p + 7 < p1; p += 8) {
+        int32_t jj[8];
+        T xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) jj[u] = cl[p + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xx[u] = xraw<MODE>(k, jj[u], mm);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+#pragma unroll
+            for (int b = 0; b < NS; ++b) t[b] += vl[(p + u) * NS + b] * xx[u];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) uf[f] += fv[(p + u + fofs) * NF + f] * xx[u];
+        }
+    }
+    for (; p < p1; ++p) {
+        const T xv = xraw<MODE>(k, cl[p], mm);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) t[b] += vl[p * NS + b] * xv;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) uf[f] += fv[(p + fofs) * NF + f] * xv;
+    }
+}
+
+// One row's sum over nonzeros [p0, p1) (indices into cl/vl; the row's
+// surface entries start at re.s0) for the lane's ordinate, before the column
+// scale: sum_b c_b t_b, plus sum_f max(0, W.n_f) u_f on a surface row, times
+// xs.  The same operations in the same order for every launch form.  `fv`
+// is the face values' array (k.sval), passed as a read-only kernel argument
+// so that its wave-uniform reads become scalar loads.
+template <int NS, class T, int MODE, class CI, class VI, class CO>
+__device__ __forceinline__ T row_sum(const SpmvK<T> &k, CI cl, VI vl, const T *__restrict__ fv, int64_t p0, int64_t p1,
+                                     const RowEnds<T> &re, CO coef, int mm)
+{
+    constexpr int NF = FacesOf<NS>::value;
+    T t[NS];
+#pragma unroll
+    for (int b = 0; b < NS; ++b) t[b] = 0;
+    const bool faces = re.s1 > re.s0 && re.s1 - re.s0 == p1 - p0 && k.nf == NF;   // uniform over the wave
+    T acc = 0;
+    if (faces) {
+        T uf[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) uf[f] = 0;
+        row_streams_faces<NS, NF, T, MODE>(k, cl, vl, fv, p0, p1, re.s0 - p0, mm, t, uf);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) acc += coef(b) * t[b];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc += k.coefF[mm * NF + f] * uf[f];
+        acc *= xs_out<MODE>(k);
+    } else {
+        row_streams<NS, T, MODE>(k, cl, vl, p0, p1, mm, t);
+#pragma unroll
+        for (int b = 0; b < NS; ++b) acc += coef(b) * t[b];
+        acc *= xs_out<MODE>(k);
+        if (re.s1 > re.s0) acc += spmv_surface<MODE>(k, re.s0, re.s1, mm);
+    }
+    return acc;
+}
+
 // Wave-per-row SpMV (used when the ordinates fill whole waves): each wave
 // owns one (row, 64-ordinate chunk).  The row index is wave-uniform, so the
 // row's column indices and stream values are read with scalar loads straight
-// into SGPRs (read-only kernel arguments, no vector broadcast needed) and
-// combined with the lane's own coefficients; the x gathers of eight nonzeros
-// are issued back to back so that their latencies overlap.
+// into SGPRs (read-only kernel arguments, no vector broadcast needed).  The
+// row is accumulated per stream, t_b = sum_p v_b[p] x[col p], and combined
+// with the lane's coefficients once at the end: NS FMAs per nonzero and
+// ordinate, with the x gathers of eight nonzeros issued back to back so that
+// their latencies overlap.  A surface row accumulates its faces' sums in the
+// same loop (row_sum).
 template <int NS, class T, int MODE>
 __global__ __launch_bounds__(512) void spmv_wave_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
                                                         const int32_t *__restrict__ col,
-                                                        const T *__restrict__ vals)
+                                                        const T *__restrict__ vals, const T *__restrict__ fv)
 {
     if (k.gate && *k.gate == 0) return;
     // Workgroups are dealt round-robin to the dies (XCDs), each with its own
@@ -247,62 +411,98 @@ __global__ __launch_bounds__(512) void spmv_wave_kernel(SpmvK<T> k, const int64_
     const int64_t i0 = (int64_t)lb * k.items_per_block;
     const int64_t i1 = i0 + k.items_per_block < nitems ? i0 + k.items_per_block : nitems;
     for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += (blockDim.x >> 6)) {
-        const int64_t iu = __builtin_amdgcn_readfirstlane((int)(item / nchunk));
+        const int64_t iu =
+            __builtin_amdgcn_readfirstlane((int)(nchunk == 1 ? item : item / nchunk));
         const int chunk = (int)(item - iu * nchunk);
         const int m = chunk * 64 + lane;
         const bool on = m < k.M;
         const int mm = on ? m : 0;
-        T c[NS];
-#pragma unroll
-        for (int b = 0; b < NS; ++b) c[b] = k.coef[mm * NS + b];
+        const RowEnds<T> re = row_ends(k, iu, mm);
         const int64_t p0 = row_off[iu], p1 = row_off[iu + 1];
-        T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        int64_t p = p0;
-        for (; p + 7 < p1; p += 8) {
-            int32_t jj[8];
-            T xx[8], aa[8];
+        // the coefficients (a few KB, cache resident) are read after the sums,
+        // so that they hold no registers during the row's loop
+        const T acc = row_sum<NS, T, MODE>(k, col, vals, fv, p0, p1, re, [&](int b) { return k.coef[mm * NS + b]; }, mm);
+        if (on) spmv_finish(k, iu, m, acc, re);
+    }
+}
+
+// LDS-staged sweep (at most 64 ordinates, so one item per row): a workgroup
+// of W waves owns a contiguous range of rows and walks it in rounds of W rows,
+// one row per wave.  The round's stream values and column indices (at most
+// 64 W nonzeros) are brought in by coalesced vector loads of the whole
+// workgroup and kept in LDS, two buffers deep: the loads of the next round
+// are in flight while the waves compute the current one from LDS.  Many more
+// bytes of the value streams are then in flight per CU than the scalar loads
+// of the wave kernel allow, which is what the sweep waits on once the streams
+// have left the caches.  A round with more nonzeros than the buffer reads
+// them from global memory instead.  Sums are formed in the same order as in
+// spmv_wave_kernel.
+template <int NS, class T, int MODE, int W>
+__global__ __launch_bounds__(64 * W) void spmv_lds_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
+                                                          const int32_t *__restrict__ col,
+                                                          const T *__restrict__ vals, const T *__restrict__ fv)
+{
+    constexpr int CAP = 64 * W;   // nonzeros per staged round
+    __shared__ T sv[2][CAP * NS];
+    __shared__ int32_t sc[2][CAP];
+    __shared__ T scoef[64 * NS];  // the lanes' coefficients, read once per row after its sums
+    if (k.gate && *k.gate == 0) return;
+    const int G = gridDim.x, X = k.nxcd;
+    const int per = G / X;
+    const int lb = (blockIdx.x % X) * per + blockIdx.x / X;
+    const int64_t i0 = (int64_t)lb * k.items_per_block;
+    const int64_t i1 = i0 + k.items_per_block < k.n ? i0 + k.items_per_block : k.n;
+    if (i0 >= i1) return;   // uniform over the workgroup
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool on = lane < k.M;
+    const int mm = on ? lane : 0;
+    for (int e = tid; e < 64 * NS; e += 64 * W) scoef[e] = e < k.M * NS ? k.coef[e] : (T)0;
+    // registers holding the next round on its way to LDS
+    T rv[NS];
+    int32_t rcol = 0;
+    int64_t q0 = row_off[i0];
+    int64_t r1 = i0 + W < i1 ? i0 + W : i1;
+    int64_t cnt = row_off[r1] - q0;
+    auto fetch = [&]() {
+        if (cnt > CAP || cnt <= 0) return;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) jj[u] = col[p + u];
+        for (int s = 0; s < NS; ++s) {
+            const int64_t e = tid + s * 64 * W;
+            rv[s] = vals[q0 * NS + (e < cnt * NS ? e : 0)];
+        }
+        rcol = col[q0 + (tid < cnt ? tid : 0)];
+    };
+    fetch();
+    int buf = 0;
+    for (int64_t r0 = i0; r0 < i1; r0 += W, buf ^= 1) {
+        const bool staged = cnt <= CAP;
+        if (staged) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xx[u] = xin<MODE>(k, jj[u], mm);
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                T a = 0;
-#pragma unroll
-                for (int b = 0; b < NS; ++b) a += c[b] * vals[(p + u) * NS + b];
-                aa[u] = a;
+            for (int s = 0; s < NS; ++s) {
+                const int e = tid + s * 64 * W;
+                if (e < cnt * NS) sv[buf][e] = rv[s];
             }
-            acc0 += aa[0] * xx[0] + aa[4] * xx[4];
-            acc1 += aa[1] * xx[1] + aa[5] * xx[5];
-            acc2 += aa[2] * xx[2] + aa[6] * xx[6];
-            acc3 += aa[3] * xx[3] + aa[7] * xx[7];
+            if (tid < cnt) sc[buf][tid] = rcol;
         }
-        for (; p + 3 < p1; p += 4) {
-            const int32_t j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
-            const T x0 = xin<MODE>(k, j0, mm), x1 = xin<MODE>(k, j1, mm), x2 = xin<MODE>(k, j2, mm),
-                    x3 = xin<MODE>(k, j3, mm);
-            T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-            for (int b = 0; b < NS; ++b) {
-                a0 += c[b] * vals[p * NS + b];
-                a1 += c[b] * vals[(p + 1) * NS + b];
-                a2 += c[b] * vals[(p + 2) * NS + b];
-                a3 += c[b] * vals[(p + 3) * NS + b];
-            }
-            acc0 += a0 * x0;
-            acc1 += a1 * x1;
-            acc2 += a2 * x2;
-            acc3 += a3 * x3;
+        const int64_t qc = q0, rend = r1;
+        // buffer `buf` was last read two rounds ago, before the previous barrier
+        __syncthreads();
+        if (r0 + W < i1) {
+            q0 = row_off[r0 + W];
+            r1 = r0 + 2 * W < i1 ? r0 + 2 * W : i1;
+            cnt = row_off[r1] - q0;
+            fetch();
         }
-        for (; p < p1; ++p) {
-            T a0 = 0;
-#pragma unroll
-            for (int b = 0; b < NS; ++b) a0 += c[b] * vals[p * NS + b];
-            acc0 += a0 * xin<MODE>(k, col[p], mm);
+        const int64_t iu = r0 + w;   // uniform over the wave
+        if (iu < rend) {
+            const RowEnds<T> re = row_ends(k, iu, mm);
+            const int64_t p0 = row_off[iu], p1 = row_off[iu + 1];
+            auto cf = [&](int b) { return scoef[mm * NS + b]; };
+            const T acc = staged ? row_sum<NS, T, MODE>(k, &sc[buf][0], &sv[buf][0], fv, p0 - qc, p1 - qc, re, cf, mm)
+                                 : row_sum<NS, T, MODE>(k, col, vals, fv, p0, p1, re, cf, mm);
+            if (on) spmv_finish(k, iu, lane, acc, re);
         }
-        T acc = (acc0 + acc1) + (acc2 + acc3);
-        if (k.soff) acc += spmv_surface<MODE>(k, iu, mm);
-        if (on) spmv_finish(k, iu, m, acc);
     }
 }
 
@@ -321,6 +521,7 @@ __global__ __launch_bounds__(512) void spmv_group_kernel(SpmvK<T> k)
 #pragma unroll
     for (int b = 0; b < NS; ++b) c[b] = k.coef[m * NS + b];
     for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < k.n; i += (int64_t)gridDim.x * rpb) {
+        const RowEnds<T> re = row_ends(k, i, m);
         const int64_t p0 = k.row_off[i], p1 = k.row_off[i + 1];
         T acc0 = 0, acc1 = 0;
         int64_t p = p0;
@@ -345,8 +546,8 @@ __global__ __launch_bounds__(512) void spmv_group_kernel(SpmvK<T> k)
             acc0 += a * xin<MODE>(k, k.col[p], m);
         }
         T acc = acc0 + acc1;
-        if (k.soff) acc += spmv_surface<MODE>(k, i, m);
-        spmv_finish(k, i, m, acc);
+        if (re.s1 > re.s0) acc += spmv_surface<MODE>(k, re.s0, re.s1, m);
+        spmv_finish(k, i, m, acc, re);
     }
 }
 
@@ -469,15 +670,27 @@ hipError_t launch_jacobi(Problem &P, hipStream_t s)
 }
 
 // ---- launch shapes of the sweep and their autotuning -------------------------
-// Wave kernel (M >= 48): `wpb` waves per workgroup, each wave sweeping `ipw`
-// (row, 64-ordinate chunk) items; with `xcd` = 8 workgroups are renumbered so
-// that every die walks one contiguous range of rows.  Group kernel (M < 48):
-// `threads` per workgroup (rows of M lanes).  The best shape per (rows,
-// ordinates, streams, value size) is measured once per process on the
+// Wave kernel (M >= 48), form 0: `wpb` waves per workgroup, each wave
+// sweeping `ipw` (row, 64-ordinate chunk) items; with `xcd` = 8 workgroups
+// are renumbered so that every die walks one contiguous range of rows.
+// LDS-staged kernel, form 1 (48 <= M <= 64, 6 or 10 streams): `wpb` = 4 or 8
+// waves, `rounds` rounds of one row per wave per workgroup.  Group kernel
+// (M < 48): `threads` per workgroup (rows of M lanes).  The best shape per
+// (rows, ordinates, streams, value size) is measured once per process on the
 // problem's own operator and kept in a table (mlpg_get_tuning).
 struct SpmvShape {
-    int wpb = 4, ipw = 1, xcd = 8, threads = 256;
+    int form = 0;
+    int wpb = 4, ipw = 1, rounds = 1, xcd = 8, threads = 256;
 };
+
+// Form 1 applies to one 64-ordinate chunk per row and the 2D/3D transport
+// operators; its two LDS buffers (64 W nonzeros of values and columns each)
+// stay within 64 KiB per workgroup.
+static bool lds_form_fits(int M, int ns, int wpb, int tbytes)
+{
+    return M >= 48 && M <= 64 && (ns == 6 || ns == 10) && (wpb == 4 || wpb == 8) &&
+           2 * 64 * wpb * (ns * tbytes + 4) <= 65536;
+}
 
 namespace {
 struct TuneEntry {
@@ -488,7 +701,10 @@ struct TuneEntry {
 };
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
-bool g_autotune = true;
+std::atomic<bool> g_autotune{true};
+// held while candidates are timed, so that threads serving several problems
+// tune one key once and never time their candidates against each other
+std::mutex g_tuning_mu;
 
 bool find_shape(int64_t n, int M, int ns, int tb, SpmvShape *out)
 {
@@ -499,6 +715,17 @@ bool find_shape(int64_t n, int M, int ns, int tb, SpmvShape *out)
             return true;
         }
     return false;
+}
+
+// inserts or replaces the entry of e's key (caller holds g_tune_mu)
+void put_entry(const TuneEntry &e)
+{
+    for (auto &o : g_tune)
+        if (o.n == e.n && o.M == e.M && o.ns == e.ns && o.tbytes == e.tbytes) {
+            o = e;
+            return;
+        }
+    g_tune.push_back(e);
 }
 }  // namespace
 
@@ -517,13 +744,15 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
     if (a.vout && !a.vsrc && (a.x_bcast || a.x2)) return hipErrorInvalidValue;
     if (a.surface && (!a.sval || !a.coefF)) return hipErrorInvalidValue;
     const bool wave = M >= 48;
+    const bool lds = sh.form == 1 && lds_form_fits(M, a.ns, sh.wpb, (int)sizeof(T));
     unsigned blocks;
     int threads;
     if (wave) {
-        // sh.wpb waves per workgroup, sh.ipw items per wave, grid a multiple of the xcd count
+        // sh.wpb waves per workgroup, each taking sh.ipw items (form 0) or one
+        // row in each of sh.rounds rounds (form 1); grid a multiple of the xcd count
         threads = 64 * sh.wpb;
         const int64_t items = P.n * ((M + 63) / 64);
-        const int64_t per_block = (int64_t)sh.wpb * sh.ipw;
+        const int64_t per_block = (int64_t)sh.wpb * (lds ? std::max(sh.rounds, 1) : sh.ipw);
         int64_t b = (items + per_block - 1) / per_block;
         b = ((b + sh.xcd - 1) / sh.xcd) * sh.xcd;
         if (b < sh.xcd) b = sh.xcd;
@@ -540,25 +769,34 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
     if (a.x2) mode = IN_X2;
     if (a.dinv) mode = IN_DINV;
     if ((a.x_bcast != 0) + (a.x2 != nullptr) + (a.dinv != nullptr) > 1) return hipErrorInvalidValue;
-#define MLPG_SPMV_M(NSV, MD)                                                      \
-    if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals); \
+#define MLPG_SPMV_L(NSV, MD)                                                                       \
+    if (sh.wpb == 4) spmv_lds_kernel<NSV, T, MD, 4><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals, k.sval); \
+    else spmv_lds_kernel<NSV, T, MD, 8><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals, k.sval)
+#define MLPG_SPMV_M(NSV, MD)                                                                       \
+    if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals, k.sval); \
     else spmv_group_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k)
-#define MLPG_SPMV(NSV)                                                            \
+#define MLPG_SPMV(NSV, KER)                                                       \
     switch (mode) {                                                               \
-    case IN_PLAIN: MLPG_SPMV_M(NSV, IN_PLAIN); break;                             \
-    case IN_DINV: MLPG_SPMV_M(NSV, IN_DINV); break;                               \
-    case IN_BCAST: MLPG_SPMV_M(NSV, IN_BCAST); break;                             \
-    default: MLPG_SPMV_M(NSV, IN_X2); break;                                      \
+    case IN_PLAIN: KER(NSV, IN_PLAIN); break;                                     \
+    case IN_DINV: KER(NSV, IN_DINV); break;                                       \
+    case IN_BCAST: KER(NSV, IN_BCAST); break;                                     \
+    default: KER(NSV, IN_X2); break;                                              \
     }
-    switch (a.ns) {
-    case 3: MLPG_SPMV(3); break;
-    case 4: MLPG_SPMV(4); break;
-    case 6: MLPG_SPMV(6); break;
-    case 10: MLPG_SPMV(10); break;
-    default: return hipErrorInvalidValue;
+    if (lds) {
+        if (a.ns == 6) { MLPG_SPMV(6, MLPG_SPMV_L); }
+        else { MLPG_SPMV(10, MLPG_SPMV_L); }
+    } else {
+        switch (a.ns) {
+        case 3: MLPG_SPMV(3, MLPG_SPMV_M); break;
+        case 4: MLPG_SPMV(4, MLPG_SPMV_M); break;
+        case 6: MLPG_SPMV(6, MLPG_SPMV_M); break;
+        case 10: MLPG_SPMV(10, MLPG_SPMV_M); break;
+        default: return hipErrorInvalidValue;
+        }
     }
 #undef MLPG_SPMV
 #undef MLPG_SPMV_M
+#undef MLPG_SPMV_L
     return hipGetLastError();
 }
 
@@ -570,16 +808,34 @@ hipError_t launch_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
     return launch_spmv_shape<T>(P, a, sh, s);
 }
 
+// Reads n4 x 32 bytes (a pass that evicts the caches before a timed launch);
+// the guarded store never happens for finite data and keeps the reads alive.
+__global__ void evict_kernel(const double4 *__restrict__ a, int64_t n4, double *sink)
+{
+    double acc = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n4; t += (int64_t)gridDim.x * blockDim.x) {
+        const double4 v = a[t];
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    if (acc == 1.0e308) sink[0] = acc;
+}
+
 // Times every candidate shape of the transport sweep as the inner solver
 // calls it (normalisation fused, per-ordinate column scale) on x -> y, both
 // [n][M] scratch vectors of the caller, and records the fastest.  Runs once
 // per (rows, ordinates, streams, value size) and process; never during a
-// graph capture (the caller tunes before the first solve).
+// graph capture (the caller tunes before the first solve).  Before each
+// timed launch the caller's scratch region `evict` (the Krylov basis) is read
+// once, as the Gram-Schmidt passes read it between two sweeps of the Arnoldi
+// loop, so that the candidates are compared with the stream values as far
+// out of the caches as the solver finds them.
 template <class T>
-hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
+hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, const void *evict, size_t evict_bytes, hipStream_t s)
 {
     SpmvShape cur;
-    if (!g_autotune || find_shape(P.n, P.n_ord, a.ns, (int)sizeof(T), &cur)) return hipSuccess;
+    if (!g_autotune.load() || find_shape(P.n, P.n_ord, a.ns, (int)sizeof(T), &cur)) return hipSuccess;
+    std::lock_guard<std::mutex> tuning(g_tuning_mu);
+    if (find_shape(P.n, P.n_ord, a.ns, (int)sizeof(T), &cur)) return hipSuccess;   // tuned meanwhile
     std::vector<SpmvShape> cand;
     if (P.n_ord >= 48) {
         for (int wpb : {2, 4, 8})
@@ -587,6 +843,13 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
                 for (int xcd : {8, 1}) {
                     SpmvShape c;
                     c.wpb = wpb; c.ipw = ipw; c.xcd = xcd;
+                    cand.push_back(c);
+                }
+        for (int wpb : {4, 8})
+            for (int rounds : {2, 4})
+                if (lds_form_fits(P.n_ord, a.ns, wpb, (int)sizeof(T))) {
+                    SpmvShape c;
+                    c.form = 1; c.wpb = wpb; c.rounds = rounds; c.xcd = 8;
                     cand.push_back(c);
                 }
     } else {
@@ -606,6 +869,11 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
         if ((e = launch_spmv_shape<T>(P, a, c, s)) != hipSuccess) break;   // warm-up
         float t = 1e30f;
         for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+            if (evict && evict_bytes >= 32) {
+                evict_kernel<<<2048, 256, 0, s>>>((const double4 *)evict, (int64_t)(evict_bytes / 32),
+                                                  (double *)(void *)a.y);
+                if ((e = hipGetLastError()) != hipSuccess) break;
+            }
             if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
             if ((e = launch_spmv_shape<T>(P, a, c, s)) != hipSuccess) break;
             if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
@@ -616,7 +884,7 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
         }
         if (e != hipSuccess) break;
         const SpmvShape d;
-        if (c.wpb == d.wpb && c.ipw == d.ipw && c.xcd == d.xcd && c.threads == d.threads) dflt = t;
+        if (c.form == d.form && c.wpb == d.wpb && c.ipw == d.ipw && c.xcd == d.xcd && c.threads == d.threads) dflt = t;
         if (t < best) {
             best = t;
             pick = c;
@@ -626,17 +894,17 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, hipStream_t s)
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune.push_back({P.n, P.n_ord, a.ns, (int)sizeof(T), pick, 1e3f * best, 1e3f * dflt});
+    put_entry({P.n, P.n_ord, a.ns, (int)sizeof(T), pick, 1e3f * best, 1e3f * dflt});
     return hipSuccess;
 }
-template hipError_t tune_spmv<double>(Problem &, const SpmvArgsT<double> &, hipStream_t);
-template hipError_t tune_spmv<float>(Problem &, const SpmvArgsT<float> &, hipStream_t);
+template hipError_t tune_spmv<double>(Problem &, const SpmvArgsT<double> &, const void *, size_t, hipStream_t);
+template hipError_t tune_spmv<float>(Problem &, const SpmvArgsT<float> &, const void *, size_t, hipStream_t);
 
 void set_autotune(int mode)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (mode == 2) g_tune.clear();
-    else g_autotune = mode != 0;
+    else g_autotune.store(mode != 0);
 }
 
 int get_tuning(int cap, mlpg_tune_entry *out)
@@ -645,18 +913,54 @@ int get_tuning(int cap, mlpg_tune_entry *out)
     const int cnt = (int)g_tune.size();
     for (int i = 0; i < cnt && i < cap; ++i) {
         const TuneEntry &e = g_tune[i];
+        const bool wave = e.M >= 48;
         out[i].n = e.n;
         out[i].n_ord = e.M;
         out[i].streams = e.ns;
         out[i].value_bytes = e.tbytes;
-        out[i].waves_per_block = e.M >= 48 ? e.shape.wpb : 0;
-        out[i].items_per_wave = e.M >= 48 ? e.shape.ipw : 0;
-        out[i].xcd_split = e.M >= 48 ? e.shape.xcd : 0;
-        out[i].threads = e.M >= 48 ? 64 * e.shape.wpb : e.shape.threads;
+        out[i].form = wave ? e.shape.form : 0;
+        out[i].waves_per_block = wave ? e.shape.wpb : 0;
+        out[i].items_per_wave = wave && e.shape.form == 0 ? e.shape.ipw : (wave ? 1 : 0);
+        out[i].rounds = wave && e.shape.form == 1 ? e.shape.rounds : (wave ? 1 : 0);
+        out[i].xcd_split = wave ? e.shape.xcd : 0;
+        out[i].threads = wave ? 64 * e.shape.wpb : e.shape.threads;
         out[i].us_best = e.us_best;
         out[i].us_default = e.us_default;
     }
     return cnt;
+}
+
+std::string set_tuning(const mlpg_tune_entry &t)
+{
+    if (t.n < 1 || t.n_ord < 1 || (t.value_bytes != 4 && t.value_bytes != 8)) return "bad n, n_ord or value_bytes";
+    if (t.streams != 3 && t.streams != 4 && t.streams != 6 && t.streams != 10) return "streams must be 3, 4, 6 or 10";
+    SpmvShape sh;
+    if (t.n_ord >= 48) {
+        if (t.xcd_split != 1 && t.xcd_split != 8) return "xcd_split must be 1 or 8";
+        sh.xcd = t.xcd_split;
+        sh.form = t.form;
+        if (t.form == 0) {
+            if (t.waves_per_block < 1 || t.waves_per_block > 8 || t.items_per_wave < 1 || t.items_per_wave > 64)
+                return "form 0 needs 1..8 waves per block and 1..64 items per wave";
+            sh.wpb = t.waves_per_block;
+            sh.ipw = t.items_per_wave;
+        } else if (t.form == 1) {
+            if (!lds_form_fits(t.n_ord, t.streams, t.waves_per_block, t.value_bytes) || t.rounds < 1 ||
+                t.rounds > 64)
+                return "form 1 needs 48..64 ordinates, 6 or 10 streams, 4 or 8 waves (4 for 10 FP64 streams) "
+                       "and 1..64 rounds";
+            sh.wpb = t.waves_per_block;
+            sh.rounds = t.rounds;
+        } else {
+            return "form must be 0 or 1";
+        }
+    } else {
+        if (t.threads < t.n_ord || t.threads > 512) return "threads must be in [n_ord, 512]";
+        sh.threads = t.threads;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    put_entry({t.n, t.n_ord, t.streams, t.value_bytes, sh, t.us_best, t.us_default});
+    return "";
 }
 
 template hipError_t launch_spmv<double>(Problem &, const SpmvArgsT<double> &, hipStream_t);

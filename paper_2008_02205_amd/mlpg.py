@@ -32,7 +32,7 @@ EXPORTS = ["mlpg_last_error", "mlpg_angular_quadrature", "mlpg_neighbors_count",
            "mlpg_material_fields", "mlpg_update_points", "mlpg_refined_quadrature",
            "mlpg_material_shells", "mlpg_apply_patch_precond", "mlpg_geometry_workspace_bytes",
            "mlpg_integrate_workspace_bytes", "mlpg_assemble_workspace_bytes", "mlpg_solve_workspace_bytes",
-           "mlpg_set_autotune", "mlpg_get_tuning", "mlpg_neighbors_static"]
+           "mlpg_set_autotune", "mlpg_get_tuning", "mlpg_set_tuning", "mlpg_neighbors_static"]
 
 
 class MlpgError(RuntimeError):
@@ -56,8 +56,8 @@ class SolveOpts(C.Structure):
 
 class TuneEntry(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_ord", C.c_int), ("streams", C.c_int), ("value_bytes", C.c_int),
-                ("waves_per_block", C.c_int), ("items_per_wave", C.c_int), ("xcd_split", C.c_int),
-                ("threads", C.c_int), ("us_best", C.c_float), ("us_default", C.c_float)]
+                ("form", C.c_int), ("waves_per_block", C.c_int), ("items_per_wave", C.c_int), ("rounds", C.c_int),
+                ("xcd_split", C.c_int), ("threads", C.c_int), ("us_best", C.c_float), ("us_default", C.c_float)]
 
 
 class SolveInfo(C.Structure):
@@ -123,6 +123,7 @@ def lib() -> C.CDLL:
         L.mlpg_set_progress.argtypes = [PROGRESS_FN, vp]
         L.mlpg_set_autotune.argtypes = [i32]
         L.mlpg_get_tuning.argtypes = [i32, C.POINTER(TuneEntry)]
+        L.mlpg_set_tuning.argtypes = [C.POINTER(TuneEntry)]
         for name in EXPORTS:
             if name not in ("mlpg_last_error", "mlpg_default_opts", "mlpg_destroy") and \
                     not name.endswith("_workspace_bytes"):
@@ -384,6 +385,15 @@ def mlpg_get_tuning() -> list:
     arr = (TuneEntry * max(cnt, 1))()
     lib().mlpg_get_tuning(cnt, arr)
     return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_} for i in range(cnt)]
+
+
+def mlpg_set_tuning(entry: dict):
+    """Inserts or replaces one launch-shape entry (a dict as returned by mlpg_get_tuning;
+    missing keys default to 0, except us_best and us_default)."""
+    e = TuneEntry()
+    for k, _ in TuneEntry._fields_:
+        setattr(e, k, entry.get(k, 0))
+    _check(lib().mlpg_set_tuning(C.byref(e)))
 
 
 def mlpg_default_opts() -> SolveOpts:

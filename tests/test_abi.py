@@ -96,3 +96,39 @@ def test_geometry_workspace_query_is_the_sum_of_its_buffers(lib, dim, n, nnz):
     assert got == sum(_aligned(b) for b in sizes)
     assert mlpg.mlpg_geometry_workspace_bytes(dim, n, nnz, hi, lo) == 0
     assert mlpg.mlpg_geometry_workspace_bytes(4, n, nnz, lo, hi) == 0
+
+
+def test_tuning_table_entries_round_trip_and_are_validated(lib):
+    """mlpg_set_tuning stores an entry under its key (replacing an older one) and
+    rejects shapes outside the documented ranges; host only."""
+    from paper_2008_02205_amd import mlpg
+    mlpg.mlpg_set_autotune(2)
+    try:
+        base = dict(n=777, n_ord=64, streams=6, value_bytes=8, xcd_split=8)
+        mlpg.mlpg_set_tuning(dict(base, form=0, waves_per_block=2, items_per_wave=2, us_best=1.5))
+        mlpg.mlpg_set_tuning(dict(base, form=1, waves_per_block=8, rounds=3, us_best=2.5))
+        t = [e for e in mlpg.mlpg_get_tuning() if e["n"] == 777]
+        assert len(t) == 1
+        t = t[0]
+        assert (t["form"], t["waves_per_block"], t["rounds"], t["threads"]) == (1, 8, 3, 512)
+        assert t["us_best"] == 2.5
+        mlpg.mlpg_set_tuning(dict(n=777, n_ord=16, streams=3, value_bytes=4, threads=256))
+        small = [e for e in mlpg.mlpg_get_tuning() if e["n_ord"] == 16]
+        assert small[0]["threads"] == 256 and small[0]["form"] == 0
+        bad = [dict(base, form=1, waves_per_block=2, rounds=2),           # form 1 needs 4 or 8 waves
+               dict(base, form=1, waves_per_block=4, rounds=0),           # rounds >= 1
+               dict(base, n_ord=96, form=1, waves_per_block=4, rounds=2),  # form 1 needs <= 64 ordinates
+               dict(base, streams=3, form=1, waves_per_block=4, rounds=2),
+               dict(base, form=2, waves_per_block=4),
+               dict(base, form=0, waves_per_block=16, items_per_wave=1),
+               dict(base, form=0, waves_per_block=4, items_per_wave=1, xcd_split=4),
+               dict(base, streams=5, form=0, waves_per_block=4, items_per_wave=1),
+               dict(n=777, n_ord=16, streams=3, value_bytes=4, threads=8),
+               dict(n=0, n_ord=64, streams=6, value_bytes=8, form=0, waves_per_block=4, items_per_wave=1,
+                    xcd_split=8)]
+        for b in bad:
+            with pytest.raises(mlpg.MlpgError):
+                mlpg.mlpg_set_tuning(b)
+        assert len([e for e in mlpg.mlpg_get_tuning() if e["n"] == 777]) == 2
+    finally:
+        mlpg.mlpg_set_autotune(2)
