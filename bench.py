@@ -469,7 +469,12 @@ def serving_record(k, slots, opts):
 
     specs = W.request_stream(k)
     t0 = time.perf_counter()
-    res = Server(slots=slots, opts=opts).run(specs, build, realtime=True, keep_fields=False)
+
+    def done(r, nd):
+        if nd % 25 == 0 or nd == k:
+            print(f"[serving] {nd}/{k} requests done, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+
+    res = Server(slots=slots, opts=opts).run(specs, build, realtime=True, keep_fields=False, on_done=done)
     el = time.perf_counter() - t0
     summ = latency_summary(res)
     its = sum(r.info["inner_iters"] * r_spec.side ** 2 for r, r_spec in zip(res, specs) if r.info)

@@ -43,6 +43,7 @@ hipError_t upload_rules(hipStream_t s)
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kThreads3 = 256;   // 3D: one quadrature point per thread, its RK correction kept in registers
 
 template <int ORD>
 struct Basis2 {
@@ -880,7 +881,7 @@ __global__ void cand_count3_kernel(int64_t n, const double *__restrict__ x, cons
 }
 
 template <int ORD, bool FIELDS>
-__global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
+__global__ __launch_bounds__(kThreads3) void integrate3d_kernel(Integ3Args g)
 {
     extern __shared__ double lds[];
     __shared__ int sA, sntet, snbt;
@@ -939,13 +940,24 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
     const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
     const int64_t nnz = g.nnz;
 
-    for (int a0 = 0; a0 < A; a0 += g.tile_rows) {
-        const int a1 = min(A, a0 + g.tile_rows);
-        const int TR = a1 - a0;
-        const int TT = TR * A;
-        for (int t = threadIdx.x; t < NB * TT; t += kThreads) gram[t] = 0.0;
-        __syncthreads();
-        for (int t = threadIdx.x; t < nq; t += kThreads) {
+    // The cell's quadrature points are taken blockDim.x at a time, one per
+    // thread (a 3D cell has a few hundred, so usually all at once).  Each
+    // thread computes its point's RK correction once and keeps it in registers
+    // for every tile of Gram rows below; a tile's rows that do not cover the
+    // point are skipped by their support test before any other work.
+    for (int q0 = 0; q0 < nq; q0 += blockDim.x) {
+        const int t = q0 + threadIdx.x;
+        bool valid = false;
+        double y[3] = {xc[0], xc[1], xc[2]};
+        double w = 0.0;
+        double C[B], dC[3][B];
+        int mat = 0;
+        double wf[kMaxMat];
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) C[k2] = dC[0][k2] = dC[1][k2] = dC[2][k2] = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 < kMaxMat; ++m2) wf[m2] = 0.0;
+        if (t < nq) {
             const int te = t / kTetRule, q = t - te * kTetRule;
             int f = 0;
             while (tet_pre[f + 1] <= te) f++;
@@ -959,123 +971,134 @@ __global__ __launch_bounds__(kThreads) void integrate3d_kernel(Integ3Args g)
             cr[1] = e2[2] * e3[0] - e2[0] * e3[2];
             cr[2] = e2[0] * e3[1] - e2[1] * e3[0];
             const double detJ = e1[0] * cr[0] + e1[1] * cr[1] + e1[2] * cr[2];
-            if (!(detJ > 0.0)) continue;
-            double y[3];
-            for (int d = 0; d < 3; ++d)
-                y[d] = xc[d] + e1[d] * c_tet_pts[q][0] + e2[d] * c_tet_pts[q][1] + e3[d] * c_tet_pts[q][2];
-            const double w = c_tet_w[q] * detJ;
-            double C[B], dC[3][B];
-            int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
-            if (o < 0) continue;
-            if (a0 == 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
-            const int mat = material_at3(y, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
-            double wf[kMaxMat];
-            if (FIELDS) material_weights<3>(y, mat, w, g.fields, wf);
-            // the lanes of a wave (neighbouring quadrature points) start the
-            // column walk at different columns, so that their LDS atomics
-            // never meet on one address (they would serialise)
-            const int bstart = (int)(threadIdx.x & 63) % A;
-            if constexpr (!FIELDS) {
-                // the tile rows' values at y once (registers), then every
-                // column's values once, added against all active rows
-                double ta[kTileRows3], td0[kTileRows3], td1[kTileRows3], td2[kTileRows3];
-                unsigned amask = 0;
-#pragma unroll
-                for (int al = 0; al < kTileRows3; ++al) {
-                    ta[al] = td0[al] = td1[al] = td2[al] = 0.0;
-                    double Na, dNa[3];
-                    if (a0 + al < a1 && rk_value3<ORD>(y, a0 + al, sx, sR, sV, hs, C, dC, &Na, dNa)) {
-                        ta[al] = Na; td0[al] = dNa[0]; td1[al] = dNa[1]; td2[al] = dNa[2];
-                        amask |= 1u << al;
-                    }
+            if (detJ > 0.0) {
+                for (int d = 0; d < 3; ++d)
+                    y[d] = xc[d] + e1[d] * c_tet_pts[q][0] + e2[d] * c_tet_pts[q][1] + e3[d] * c_tet_pts[q][2];
+                w = c_tet_w[q] * detJ;
+                const int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
+                if (o >= 0) {
+                    valid = true;
+                    if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+                    mat = material_at3(y, g.nreg, g.reg_lo, g.reg_hi, g.reg_mat);
+                    if (FIELDS) material_weights<3>(y, mat, w, g.fields, wf);
                 }
-                if (!amask) continue;
-                for (int bi = 0; bi < A; ++bi) {
-                    const int b = bstart + bi < A ? bstart + bi : bstart + bi - A;
-                    double Nb, dNb[3];
-                    if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
-                    const double wNb = w * Nb, wd0 = w * dNb[0], wd1 = w * dNb[1], wd2 = w * dNb[2];
+            }
+        }
+        for (int a0 = 0; a0 < A; a0 += g.tile_rows) {
+            const int a1 = min(A, a0 + g.tile_rows);
+            const int TR = a1 - a0;
+            const int TT = TR * A;
+            for (int t2 = threadIdx.x; t2 < NB * TT; t2 += blockDim.x) gram[t2] = 0.0;
+            __syncthreads();
+            if (valid) {
+                // the lanes of a wave (neighbouring quadrature points) start the
+                // column walk at different columns, so that their LDS atomics
+                // never meet on one address (they would serialise)
+                const int bstart = (int)(threadIdx.x & 63) % A;
+                if constexpr (!FIELDS) {
+                    // the tile rows' values at y once (registers), then every
+                    // column's values once, added against all active rows
+                    constexpr int TRR = kTileRows3;
+                    double ta[TRR], td0[TRR], td1[TRR], td2[TRR];
+                    unsigned amask = 0;
 #pragma unroll
-                    for (int al = 0; al < kTileRows3; ++al) {
-                        if (!((amask >> al) & 1u)) continue;
-                        double *gr = gram + al * A;
-                        atomicAdd(&gr[(4 * mat + 0) * TT + b], ta[al] * wNb);
-                        atomicAdd(&gr[(4 * mat + 1) * TT + b], td0[al] * wNb);
-                        atomicAdd(&gr[(4 * mat + 2) * TT + b], td1[al] * wNb);
-                        atomicAdd(&gr[(4 * mat + 3) * TT + b], td2[al] * wNb);
-                        atomicAdd(&gr[(4 * G + 0) * TT + b], td0[al] * wd0);
-                        atomicAdd(&gr[(4 * G + 1) * TT + b], td0[al] * wd1);
-                        atomicAdd(&gr[(4 * G + 2) * TT + b], td0[al] * wd2);
-                        atomicAdd(&gr[(4 * G + 3) * TT + b], td1[al] * wd1);
-                        atomicAdd(&gr[(4 * G + 4) * TT + b], td1[al] * wd2);
-                        atomicAdd(&gr[(4 * G + 5) * TT + b], td2[al] * wd2);
+                    for (int al = 0; al < TRR; ++al) {
+                        ta[al] = td0[al] = td1[al] = td2[al] = 0.0;
+                        double Na, dNa[3];
+                        if (a0 + al < a1 && rk_value3<ORD>(y, a0 + al, sx, sR, sV, hs, C, dC, &Na, dNa)) {
+                            ta[al] = Na; td0[al] = dNa[0]; td1[al] = dNa[1]; td2[al] = dNa[2];
+                            amask |= 1u << al;
+                        }
                     }
-                }
-            } else {
-                // with material fields (per-material weights per point) the
-                // rows are taken one at a time, each column re-evaluated
-                for (int a = a0; a < a1; ++a) {
-                    double Na, dNa[3];
-                    if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
-                    const double wa0 = w * dNa[0], wa1 = w * dNa[1], wa2 = w * dNa[2];
-                    double *gr = gram + (a - a0) * A;
+                    if (amask)
                     for (int bi = 0; bi < A; ++bi) {
                         const int b = bstart + bi < A ? bstart + bi : bstart + bi - A;
                         double Nb, dNb[3];
                         if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
+                        const double wNb = w * Nb, wd0 = w * dNb[0], wd1 = w * dNb[1], wd2 = w * dNb[2];
 #pragma unroll
-                        for (int m = 0; m < kMaxMat; ++m) {
-                            if (m >= G || wf[m] == 0.0) continue;
-                            atomicAdd(&gr[(4 * m + 0) * TT + b], wf[m] * Na * Nb);
-                            atomicAdd(&gr[(4 * m + 1) * TT + b], wf[m] * dNa[0] * Nb);
-                            atomicAdd(&gr[(4 * m + 2) * TT + b], wf[m] * dNa[1] * Nb);
-                            atomicAdd(&gr[(4 * m + 3) * TT + b], wf[m] * dNa[2] * Nb);
+                        for (int al = 0; al < TRR; ++al) {
+                            if (!((amask >> al) & 1u)) continue;
+                            double *gr = gram + al * A;
+                            atomicAdd(&gr[(4 * mat + 0) * TT + b], ta[al] * wNb);
+                            atomicAdd(&gr[(4 * mat + 1) * TT + b], td0[al] * wNb);
+                            atomicAdd(&gr[(4 * mat + 2) * TT + b], td1[al] * wNb);
+                            atomicAdd(&gr[(4 * mat + 3) * TT + b], td2[al] * wNb);
+                            atomicAdd(&gr[(4 * G + 0) * TT + b], td0[al] * wd0);
+                            atomicAdd(&gr[(4 * G + 1) * TT + b], td0[al] * wd1);
+                            atomicAdd(&gr[(4 * G + 2) * TT + b], td0[al] * wd2);
+                            atomicAdd(&gr[(4 * G + 3) * TT + b], td1[al] * wd1);
+                            atomicAdd(&gr[(4 * G + 4) * TT + b], td1[al] * wd2);
+                            atomicAdd(&gr[(4 * G + 5) * TT + b], td2[al] * wd2);
                         }
-                        atomicAdd(&gr[(4 * G + 0) * TT + b], wa0 * dNb[0]);
-                        atomicAdd(&gr[(4 * G + 1) * TT + b], wa0 * dNb[1]);
-                        atomicAdd(&gr[(4 * G + 2) * TT + b], wa0 * dNb[2]);
-                        atomicAdd(&gr[(4 * G + 3) * TT + b], wa1 * dNb[1]);
-                        atomicAdd(&gr[(4 * G + 4) * TT + b], wa1 * dNb[2]);
-                        atomicAdd(&gr[(4 * G + 5) * TT + b], wa2 * dNb[2]);
+                    }
+                } else {
+                    // with material fields (per-material weights per point) the
+                    // rows are taken one at a time, each column re-evaluated
+                    for (int a = a0; a < a1; ++a) {
+                        double Na, dNa[3];
+                        if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) continue;
+                        const double wa0 = w * dNa[0], wa1 = w * dNa[1], wa2 = w * dNa[2];
+                        double *gr = gram + (a - a0) * A;
+                        for (int bi = 0; bi < A; ++bi) {
+                            const int b = bstart + bi < A ? bstart + bi : bstart + bi - A;
+                            double Nb, dNb[3];
+                            if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb)) continue;
+#pragma unroll
+                            for (int m = 0; m < kMaxMat; ++m) {
+                                if (m >= G || wf[m] == 0.0) continue;
+                                atomicAdd(&gr[(4 * m + 0) * TT + b], wf[m] * Na * Nb);
+                                atomicAdd(&gr[(4 * m + 1) * TT + b], wf[m] * dNa[0] * Nb);
+                                atomicAdd(&gr[(4 * m + 2) * TT + b], wf[m] * dNa[1] * Nb);
+                                atomicAdd(&gr[(4 * m + 3) * TT + b], wf[m] * dNa[2] * Nb);
+                            }
+                            atomicAdd(&gr[(4 * G + 0) * TT + b], wa0 * dNb[0]);
+                            atomicAdd(&gr[(4 * G + 1) * TT + b], wa0 * dNb[1]);
+                            atomicAdd(&gr[(4 * G + 2) * TT + b], wa0 * dNb[2]);
+                            atomicAdd(&gr[(4 * G + 3) * TT + b], wa1 * dNb[1]);
+                            atomicAdd(&gr[(4 * G + 4) * TT + b], wa1 * dNb[2]);
+                            atomicAdd(&gr[(4 * G + 5) * TT + b], wa2 * dNb[2]);
+                        }
                     }
                 }
             }
+            __syncthreads();
+            // scatter: K^ab for a <= b from the tile, K^ba[j][i] = K^ab[i][j] as its transpose
+            const int kb = 4 * G;
+            for (int t2 = threadIdx.x; t2 < TT; t2 += blockDim.x) {
+                const int t = t2;
+                const int al = t / A, b = t - al * A;
+                const int a = a0 + al;
+                bool nz = false;
+                for (int q = 0; q < NB; ++q) nz |= (gram[q * TT + t] != 0.0);
+                if (!nz) continue;
+                const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+                if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+                for (int m = 0; m < G; ++m)
+                    for (int q = 0; q < 4; ++q) {
+                        double v = gram[(4 * m + q) * TT + t];
+                        if (v != 0.0) atomicAdd(&g.blocks[(int64_t)(4 * m + q) * nnz + pos], v);
+                    }
+                // tile order xx, xy, xz, yy, yz, zz -> block kb + 3 alpha + beta
+                const int ab[6] = {0, 1, 2, 4, 5, 8};
+                for (int q = 0; q < 6; ++q)
+                    atomicAdd(&g.blocks[(int64_t)(kb + ab[q]) * nnz + pos], gram[(4 * G + q) * TT + t]);
+                const int64_t pos_t = find_col(g.row_off, g.col, sidx[b], sidx[a]);
+                if (pos_t < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+                const int ba[3] = {3, 6, 7};          // yx, zx, zy
+                const int src[3] = {1, 2, 4};         // from xy, xz, yz
+                for (int q = 0; q < 3; ++q)
+                    atomicAdd(&g.blocks[(int64_t)(kb + ba[q]) * nnz + pos_t], gram[(4 * G + src[q]) * TT + t]);
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        // scatter: K^ab for a <= b from the tile, K^ba[j][i] = K^ab[i][j] as its transpose
-        const int kb = 4 * G;
-        for (int t = threadIdx.x; t < TT; t += kThreads) {
-            const int al = t / A, b = t - al * A;
-            const int a = a0 + al;
-            bool nz = false;
-            for (int q = 0; q < NB; ++q) nz |= (gram[q * TT + t] != 0.0);
-            if (!nz) continue;
-            const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
-            if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
-            for (int m = 0; m < G; ++m)
-                for (int q = 0; q < 4; ++q) {
-                    double v = gram[(4 * m + q) * TT + t];
-                    if (v != 0.0) atomicAdd(&g.blocks[(int64_t)(4 * m + q) * nnz + pos], v);
-                }
-            // tile order xx, xy, xz, yy, yz, zz -> block kb + 3 alpha + beta
-            const int ab[6] = {0, 1, 2, 4, 5, 8};
-            for (int q = 0; q < 6; ++q)
-                atomicAdd(&g.blocks[(int64_t)(kb + ab[q]) * nnz + pos], gram[(4 * G + q) * TT + t]);
-            const int64_t pos_t = find_col(g.row_off, g.col, sidx[b], sidx[a]);
-            if (pos_t < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
-            const int ba[3] = {3, 6, 7};          // yx, zx, zy
-            const int src[3] = {1, 2, 4};         // from xy, xz, yz
-            for (int q = 0; q < 3; ++q)
-                atomicAdd(&g.blocks[(int64_t)(kb + ba[q]) * nnz + pos_t], gram[(4 * G + src[q]) * TT + t]);
-        }
-        __syncthreads();
     }
 
     // boundary triangles on domain faces: 4-point rule, surface blocks and
     // the boundary point table used for the inflow term
     const int nbq = snbt * kTri3Rule;
     const int sb = 4 * G + 9;
-    for (int t = threadIdx.x; t < nbq; t += kThreads) {
+    for (int t = threadIdx.x; t < nbq; t += blockDim.x) {
         const int tr = t / kTri3Rule, q = t - tr * kTri3Rule;
         int f = 0;
         while (bnd_pre[f + 1] <= tr) f++;
@@ -1160,12 +1183,12 @@ hipError_t upload_rules3(hipStream_t s)
 
 template <int ORD, class Args>
 hipError_t launch_integ(void (*plain)(Args), void (*fields)(Args), bool use_fields, dim3 grid, size_t shmem,
-                        const Args &g, hipStream_t s)
+                        const Args &g, hipStream_t s, int threads = kThreads)
 {
     void (*k)(Args) = use_fields ? fields : plain;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     if (e != hipSuccess) return e;
-    k<<<grid, kThreads, shmem, s>>>(g);
+    k<<<grid, threads, shmem, s>>>(g);
     return hipGetLastError();
 }
 
@@ -1279,15 +1302,15 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
     dim3 grid((unsigned)P.n);
     switch (P.rk_order) {
     case 0:
-        e = launch_integ<0>(integrate3d_kernel<0, false>, integrate3d_kernel<0, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
+        e = launch_integ<0>(integrate3d_kernel<0, false>, integrate3d_kernel<0, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s, kThreads3);
         if (e != hipSuccess) return e;
         break;
     case 1:
-        e = launch_integ<1>(integrate3d_kernel<1, false>, integrate3d_kernel<1, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
+        e = launch_integ<1>(integrate3d_kernel<1, false>, integrate3d_kernel<1, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s, kThreads3);
         if (e != hipSuccess) return e;
         break;
     default:
-        e = launch_integ<2>(integrate3d_kernel<2, false>, integrate3d_kernel<2, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s);
+        e = launch_integ<2>(integrate3d_kernel<2, false>, integrate3d_kernel<2, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s, kThreads3);
         if (e != hipSuccess) return e;
         break;
     }

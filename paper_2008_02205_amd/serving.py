@@ -98,10 +98,13 @@ class Server:
                 P.close()
         return phi_h, pv_h, info
 
-    def run(self, specs: List, build: Callable, realtime: bool = True, keep_fields: bool = True) -> List[Result]:
+    def run(self, specs: List, build: Callable, realtime: bool = True, keep_fields: bool = True,
+            on_done: Optional[Callable] = None) -> List[Result]:
         """Serve ``specs`` (objects with rid, arrival, side and n_ord); ``build(spec)``
         returns (x, R, dx, omega, w, sigma_t, sigma_s, q).  With ``realtime``, requests
-        become visible at their arrival times; otherwise all are waiting at once."""
+        become visible at their arrival times; otherwise all are waiting at once.
+        ``on_done(result, n_done)`` is called (under the server's lock, from the worker
+        thread) as each request completes."""
         lock = threading.Condition()
         waiting: list = []
         state = {"bytes": 0, "running": 0}
@@ -134,6 +137,8 @@ class Server:
             res.done = time.perf_counter() - t0
             with lock:
                 results.append(res)
+                if on_done is not None:
+                    on_done(res, len(results))
                 state["bytes"] -= held[0]
                 state["running"] -= 1
                 free_streams.append(sidx)
