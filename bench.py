@@ -235,7 +235,8 @@ def main():
             "rel_l2_phi_point_vs_fp64": float(np.linalg.norm(pv2_np - pv_np) / np.linalg.norm(pv_np)),
             "roofline": roofline(prof2, counters=False)}
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
+        rec["cpu_baseline"], X, k = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
+        rec["detail"]["error_vs_oracle"] = oracle_error(w, x, R, dx, om, wq, psi0, X, k)
     if args.serving_sample:
         rec["detail"]["serving_sample"] = serving_record(args.serving_sample, args.slots, None)
     print(json.dumps(rec), flush=True)
@@ -554,7 +555,7 @@ def cpu_baseline(w, x, R, dx, om, wq, k, min_seconds=10.0):
     reps = 0
     t0 = time.perf_counter()
     while True:
-        _, i, _ = tr.inner_solve(F, 0, k)
+        X, i, _ = tr.inner_solve(F, 0, k)
         its += i
         reps += 1
         el = time.perf_counter() - t0
@@ -564,13 +565,39 @@ def cpu_baseline(w, x, R, dx, om, wq, k, min_seconds=10.0):
     t1 = time.perf_counter()
     _, i1, _ = tr.inner_solve(F, 0, 1)
     el1 = time.perf_counter() - t1
-    return {"value": x.shape[0] * its / el, "unit": "DOF*ord*iter/s", "cores": th, "kind": "oracle",
-            "cpu_model": cpu_model(),
-            "one_thread_value": x.shape[0] * i1 / el1,
-            "sample": f"first-flight inner GMRES solves (right-Jacobi GMRES(30) to 1e-13) of BE step 1 for "
-                      f"ordinates 0..{k - 1} of {om.shape[0]}, full {x.shape[0]}-point problem, x{reps}: "
-                      f"{its} Arnoldi steps in {el:.1f} s on {th} threads; one thread: ordinate 0 alone, "
-                      f"{i1} Arnoldi steps in {el1:.2f} s"}
+    rec = {"value": x.shape[0] * its / el, "unit": "DOF*ord*iter/s", "cores": th, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "one_thread_value": x.shape[0] * i1 / el1,
+           "sample": f"first-flight inner GMRES solves (right-Jacobi GMRES(30) to 1e-13) of BE step 1 for "
+                     f"ordinates 0..{k - 1} of {om.shape[0]}, full {x.shape[0]}-point problem, x{reps}: "
+                     f"{its} Arnoldi steps in {el:.1f} s on {th} threads; one thread: ordinate 0 alone, "
+                     f"{i1} Arnoldi steps in {el1:.2f} s"}
+    return rec, X, k
+
+
+def oracle_error(w, x, R, dx, om, wq, psi0, X, k):
+    """Relative L2 error of the GPU path against the oracle's solutions of the CPU
+    sample, X = L_m^-1 (T psi^0 + r) for ordinates 0..k-1: the first backward-Euler
+    step of the same problem without scattering (sigma_s = 0, which changes
+    neither L_m nor the right-hand side), where the step's Psi is exactly X."""
+    import torch
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    q = torch.from_numpy(np.ascontiguousarray(W.source_values(w, x, om, w.dt))).cuda()
+    tau = torch.full((x.shape[0],), dx, dtype=torch.float64, device="cuda")
+    out = {"sample": f"Psi of BE step 1 with sigma_s = 0 against the oracle's L_m^-1 F of the CPU sample, "
+                     f"ordinates 0..{k - 1}"}
+    ref = X[:, :k]
+    for name, prec in (("fp64", mlpg.MLPG_FP64), ("mixed", mlpg.MLPG_MIXED)):
+        P = GpuProblem(x, R, w.lo, w.hi)
+        P.integrate(w.rk_order)
+        P.assemble(om, wq, [w.sigma_t[0]], [0.0], w.inv_c_dt, tau, precision=prec)
+        P.set_state(psi0)
+        _, _, psi, _ = P.step(q, None, mlpg.mlpg_default_opts())
+        got = psi.cpu().numpy()[:, :k]
+        P.close()
+        out[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return out
 
 
 def cpu_model():

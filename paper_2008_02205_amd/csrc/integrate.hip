@@ -880,6 +880,130 @@ __global__ void cand_count3_kernel(int64_t n, const double *__restrict__ x, cons
     cnt[c] = k;
 }
 
+// Thread 0 of a cell's workgroup: the functions whose support can reach
+// cell c (the generator first, then the overlap neighbours within R_j + rho_c)
+// into the LDS arrays (A = -1 when more than g.amax), and the prefix counts
+// of the cell's fan tetrahedra and of its boundary triangles per face.
+__device__ void stage_cell3(const Integ3Args &g, int64_t c, const double (&xc)[3], double *sx, double *sR, double *sV,
+                            int32_t *sidx, int *sA, int *tet_pre, int *bnd_pre, int *sntet, int *snbt)
+{
+    const int amax = g.amax;
+    const int nfc = g.nf[c];
+    int A = 0;
+    double rc = g.rho[c];
+    sidx[0] = (int32_t)c; sx[0] = xc[0]; sx[1] = xc[1]; sx[2] = xc[2]; sR[0] = g.R[c]; sV[0] = g.V[c];
+    A = 1;
+    for (int64_t p = g.nb_off[c]; p < g.nb_off[c + 1]; ++p) {
+        int64_t j = g.nb_idx[p];
+        double d0 = g.x[3 * j] - xc[0], d1 = g.x[3 * j + 1] - xc[1], d2 = g.x[3 * j + 2] - xc[2];
+        double lim = g.R[j] + rc;
+        if (d0 * d0 + d1 * d1 + d2 * d2 < lim * lim) {
+            if (A >= amax) { A = -1; break; }
+            sidx[A] = (int32_t)j;
+            sx[3 * A] = g.x[3 * j]; sx[3 * A + 1] = g.x[3 * j + 1]; sx[3 * A + 2] = g.x[3 * j + 2];
+            sR[A] = g.R[j];
+            sV[A] = g.V[j];
+            A++;
+        }
+    }
+    if (A < 0) atomicAdd(&g.counters[kOverflow], 1ull);
+    *sA = A;
+    int nt = 0, nb = 0;
+    tet_pre[0] = 0;
+    bnd_pre[0] = 0;
+    for (int f = 0; f < nfc; ++f) {
+        int m = g.fnv[c * kFaceCap3 + f];
+        int tg = g.ftags[c * kFaceCap3 + f];
+        nt += m - 2;
+        if (tg <= -1 && tg >= -6) nb += m - 2;
+        tet_pre[f + 1] = nt;
+        bnd_pre[f + 1] = nb;
+    }
+    *sntet = nt;
+    *snbt = nb;
+}
+
+// The cell's boundary triangles on domain faces (4-point rule): the surface
+// blocks and the boundary point table of the inflow term; then the point
+// values at the generator, E[c, j] = N_j(x_c).  All threads of the workgroup.
+template <int ORD>
+__device__ void integ3_boundary(const Integ3Args &g, int64_t c, int A, const double *sx, const double *sR,
+                                const double *sV, const int32_t *sidx, const double (&xc)[3], double hs,
+                                const double *fvc, int snbt, const int *bnd_pre)
+{
+    constexpr int B = Basis3<ORD>::B;
+    const int G = g.G;
+    const int64_t nnz = g.nnz;
+    // boundary triangles on domain faces: 4-point rule, surface blocks and
+    // the boundary point table used for the inflow term
+    const int nbq = snbt * kTri3Rule;
+    const int sb = 4 * G + 9;
+    for (int t = threadIdx.x; t < nbq; t += blockDim.x) {
+        const int tr = t / kTri3Rule, q = t - tr * kTri3Rule;
+        int f = 0;
+        while (bnd_pre[f + 1] <= tr) f++;
+        const int k = 1 + tr - bnd_pre[f];
+        const int face = -1 - g.ftags[c * kFaceCap3 + f];
+        const double *A0 = fvc + (f * kFaceVerts3) * 3;
+        const double *B0 = fvc + (f * kFaceVerts3 + k) * 3;
+        const double *C0 = fvc + (f * kFaceVerts3 + k + 1) * 3;
+        double g1[3], g2[3], nn[3];
+        for (int d = 0; d < 3; ++d) { g1[d] = B0[d] - A0[d]; g2[d] = C0[d] - A0[d]; }
+        nn[0] = g1[1] * g2[2] - g1[2] * g2[1];
+        nn[1] = g1[2] * g2[0] - g1[0] * g2[2];
+        nn[2] = g1[0] * g2[1] - g1[1] * g2[0];
+        const double area2 = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        double y[3];
+        for (int d = 0; d < 3; ++d) y[d] = A0[d] + g1[d] * c_tri3_pts[q][0] + g2[d] * c_tri3_pts[q][1];
+        const double w = c_tri3_w[q] * area2;
+        const int64_t bq = g.bq_off[c] + t;
+        for (int d = 0; d < 3; ++d) g.bq_y[3 * bq + d] = y[d];
+        g.bq_face[bq] = face;
+        g.bq_w[bq] = w;
+        double C[B], dC[3][B];
+        int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
+        int na = 0;
+        if (o >= 0) {
+            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            for (int a = 0; a < A; ++a) {
+                double Na, d_[3];
+                if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
+                if (na < kBqAct3) {
+                    g.bq_act[bq * kBqAct3 + na] = sidx[a];
+                    g.bq_N[bq * kBqAct3 + na] = Na;
+                } else {
+                    atomicAdd(&g.counters[kOverflow], 1ull);
+                }
+                na++;
+                for (int b = 0; b < A; ++b) {
+                    double Nb, e_[3];
+                    if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, e_)) continue;
+                    const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+                    if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+                    atomicAdd(&g.blocks[(int64_t)(sb + face) * nnz + pos], w * Na * Nb);
+                }
+            }
+        }
+        g.bq_nact[bq] = na < kBqAct3 ? na : kBqAct3;
+    }
+
+    // point values at the generator: E[c, j] = N_j(x_c)
+    if (threadIdx.x == 0) {
+        double C[B], dC[3][B];
+        int o = rk_prepare3<ORD>(xc, A, sx, sR, sV, hs, C, dC);
+        if (o >= 0) {
+            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            for (int a = 0; a < A; ++a) {
+                double Na, d_[3];
+                if (!rk_value3<ORD>(xc, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
+                const int64_t pos = find_col(g.row_off, g.col, (int32_t)c, sidx[a]);
+                if (pos >= 0) g.E[pos] = Na;
+                else atomicAdd(&g.counters[kMissing], 1ull);
+            }
+        }
+    }
+}
+
 template <int ORD, bool FIELDS>
 __global__ __launch_bounds__(kThreads3) void integrate3d_kernel(Integ3Args g)
 {
@@ -897,41 +1021,7 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_kernel(Integ3Args g)
     const int64_t c = blockIdx.x;
     const double xc[3] = {g.x[3 * c], g.x[3 * c + 1], g.x[3 * c + 2]};
     const double hs = 0.5 * g.R[c];
-    const int nfc = g.nf[c];
-    if (threadIdx.x == 0) {
-        int A = 0;
-        double rc = g.rho[c];
-        sidx[0] = (int32_t)c; sx[0] = xc[0]; sx[1] = xc[1]; sx[2] = xc[2]; sR[0] = g.R[c]; sV[0] = g.V[c];
-        A = 1;
-        for (int64_t p = g.nb_off[c]; p < g.nb_off[c + 1]; ++p) {
-            int64_t j = g.nb_idx[p];
-            double d0 = g.x[3 * j] - xc[0], d1 = g.x[3 * j + 1] - xc[1], d2 = g.x[3 * j + 2] - xc[2];
-            double lim = g.R[j] + rc;
-            if (d0 * d0 + d1 * d1 + d2 * d2 < lim * lim) {
-                if (A >= amax) { A = -1; break; }
-                sidx[A] = (int32_t)j;
-                sx[3 * A] = g.x[3 * j]; sx[3 * A + 1] = g.x[3 * j + 1]; sx[3 * A + 2] = g.x[3 * j + 2];
-                sR[A] = g.R[j];
-                sV[A] = g.V[j];
-                A++;
-            }
-        }
-        if (A < 0) atomicAdd(&g.counters[kOverflow], 1ull);
-        sA = A;
-        int nt = 0, nb = 0;
-        tet_pre[0] = 0;
-        bnd_pre[0] = 0;
-        for (int f = 0; f < nfc; ++f) {
-            int m = g.fnv[c * kFaceCap3 + f];
-            int tg = g.ftags[c * kFaceCap3 + f];
-            nt += m - 2;
-            if (tg <= -1 && tg >= -6) nb += m - 2;
-            tet_pre[f + 1] = nt;
-            bnd_pre[f + 1] = nb;
-        }
-        sntet = nt;
-        snbt = nb;
-    }
+    if (threadIdx.x == 0) stage_cell3(g, c, xc, sx, sR, sV, sidx, &sA, tet_pre, bnd_pre, &sntet, &snbt);
     __syncthreads();
     const int A = sA;
     if (A <= 0) return;
@@ -1094,74 +1184,216 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_kernel(Integ3Args g)
         }
     }
 
-    // boundary triangles on domain faces: 4-point rule, surface blocks and
-    // the boundary point table used for the inflow term
-    const int nbq = snbt * kTri3Rule;
-    const int sb = 4 * G + 9;
-    for (int t = threadIdx.x; t < nbq; t += blockDim.x) {
-        const int tr = t / kTri3Rule, q = t - tr * kTri3Rule;
-        int f = 0;
-        while (bnd_pre[f + 1] <= tr) f++;
-        const int k = 1 + tr - bnd_pre[f];
-        const int face = -1 - g.ftags[c * kFaceCap3 + f];
-        const double *A0 = fvc + (f * kFaceVerts3) * 3;
-        const double *B0 = fvc + (f * kFaceVerts3 + k) * 3;
-        const double *C0 = fvc + (f * kFaceVerts3 + k + 1) * 3;
-        double g1[3], g2[3], nn[3];
-        for (int d = 0; d < 3; ++d) { g1[d] = B0[d] - A0[d]; g2[d] = C0[d] - A0[d]; }
-        nn[0] = g1[1] * g2[2] - g1[2] * g2[1];
-        nn[1] = g1[2] * g2[0] - g1[0] * g2[2];
-        nn[2] = g1[0] * g2[1] - g1[1] * g2[0];
-        const double area2 = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
-        double y[3];
-        for (int d = 0; d < 3; ++d) y[d] = A0[d] + g1[d] * c_tri3_pts[q][0] + g2[d] * c_tri3_pts[q][1];
-        const double w = c_tri3_w[q] * area2;
-        const int64_t bq = g.bq_off[c] + t;
-        for (int d = 0; d < 3; ++d) g.bq_y[3 * bq + d] = y[d];
-        g.bq_face[bq] = face;
-        g.bq_w[bq] = w;
-        double C[B], dC[3][B];
-        int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
-        int na = 0;
-        if (o >= 0) {
-            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
-            for (int a = 0; a < A; ++a) {
-                double Na, d_[3];
-                if (!rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
-                if (na < kBqAct3) {
-                    g.bq_act[bq * kBqAct3 + na] = sidx[a];
-                    g.bq_N[bq * kBqAct3 + na] = Na;
-                } else {
-                    atomicAdd(&g.counters[kOverflow], 1ull);
-                }
-                na++;
-                for (int b = 0; b < A; ++b) {
-                    double Nb, e_[3];
-                    if (!rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, e_)) continue;
-                    const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
-                    if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
-                    atomicAdd(&g.blocks[(int64_t)(sb + face) * nnz + pos], w * Na * Nb);
-                }
-            }
-        }
-        g.bq_nact[bq] = na < kBqAct3 ? na : kBqAct3;
-    }
+    integ3_boundary<ORD>(g, c, A, sx, sR, sV, sidx, xc, hs, fvc, snbt, bnd_pre);
+}
 
-    // point values at the generator: E[c, j] = N_j(x_c)
-    if (threadIdx.x == 0) {
-        double C[B], dC[3][B];
-        int o = rk_prepare3<ORD>(xc, A, sx, sR, sV, hs, C, dC);
-        if (o >= 0) {
-            if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
-            for (int a = 0; a < A; ++a) {
-                double Na, d_[3];
-                if (!rk_value3<ORD>(xc, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
-                const int64_t pos = find_col(g.row_off, g.col, (int32_t)c, sidx[a]);
-                if (pos >= 0) g.E[pos] = Na;
-                else atomicAdd(&g.counters[kMissing], 1ull);
+// 3D integration without LDS atomics, for one material without fields (the
+// Gram products then need no per-point material weights).  A cell's
+// quadrature points are taken up to `qcap` at a time; each point's RK
+// correction (y, w, C, dC) is computed once into LDS.  The Gram matrix is
+// then formed in tiles of kColRows rows: every lane owns one column b (one
+// candidate function), walks the points in order and accumulates the tile's
+// sums w N_a N_b, w dN_a N_b and w dN_a dN_b for its column in registers, with
+// the tile rows' values at a chunk of kRowChunk points staged in LDS by the
+// workgroup first.  Each (row, column) entry is then added once into the CSR
+// blocks.  The same sums as integrate3d_kernel in another order.
+constexpr int kColRows = 8;
+constexpr int kRowChunk = 32;
+
+template <int ORD>
+struct PointRec3 {
+    static constexpr int size = 4 + 4 * Basis3<ORD>::B;   // y, w, C, dC
+};
+
+template <int ORD>
+__global__ __launch_bounds__(kThreads3) void integrate3d_cols_kernel(Integ3Args g, int qcap)
+{
+    extern __shared__ double lds[];
+    __shared__ int sA, sntet, snbt;
+    __shared__ int tet_pre[kFaceCap3 + 1], bnd_pre[kFaceCap3 + 1];
+    constexpr int B = Basis3<ORD>::B;
+    constexpr int PR = PointRec3<ORD>::size;
+    constexpr int TR = kColRows;
+    const int amax = g.amax;
+    double *sx = lds;
+    double *sR = sx + 3 * amax;
+    double *sV = sR + amax;
+    int32_t *sidx = (int32_t *)(sV + amax);
+    double *pts = sV + amax + (amax + 1) / 2;    // [qcap][PR]
+    double *rv = pts + (size_t)qcap * PR;          // [kRowChunk][TR][4]
+    const int64_t c = blockIdx.x;
+    const double xc[3] = {g.x[3 * c], g.x[3 * c + 1], g.x[3 * c + 2]};
+    const double hs = 0.5 * g.R[c];
+    if (threadIdx.x == 0) stage_cell3(g, c, xc, sx, sR, sV, sidx, &sA, tet_pre, bnd_pre, &sntet, &snbt);
+    __syncthreads();
+    const int A = sA;
+    if (A <= 0) return;
+    const int nq = sntet * kTetRule;
+    const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
+    const int64_t nnz = g.nnz;
+
+    for (int p0 = 0; p0 < nq; p0 += qcap) {
+        const int np = min(qcap, nq - p0);
+        // the points' RK corrections, once per point (w = 0: no contribution)
+        for (int t = threadIdx.x; t < np; t += blockDim.x) {
+            const int te = (p0 + t) / kTetRule, q = (p0 + t) - te * kTetRule;
+            int f = 0;
+            while (tet_pre[f + 1] <= te) f++;
+            const int k = 1 + te - tet_pre[f];
+            const double *v0 = fvc + (f * kFaceVerts3) * 3;
+            const double *vk = fvc + (f * kFaceVerts3 + k) * 3;
+            const double *vk1 = fvc + (f * kFaceVerts3 + k + 1) * 3;
+            double e1[3], e2[3], e3[3], cr[3];
+            for (int d = 0; d < 3; ++d) { e1[d] = v0[d] - xc[d]; e2[d] = vk[d] - xc[d]; e3[d] = vk1[d] - xc[d]; }
+            cr[0] = e2[1] * e3[2] - e2[2] * e3[1];
+            cr[1] = e2[2] * e3[0] - e2[0] * e3[2];
+            cr[2] = e2[0] * e3[1] - e2[1] * e3[0];
+            const double detJ = e1[0] * cr[0] + e1[1] * cr[1] + e1[2] * cr[2];
+            double y[3] = {xc[0], xc[1], xc[2]};
+            double w = 0.0;
+            double C[B], dC[3][B];
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) C[k2] = dC[0][k2] = dC[1][k2] = dC[2][k2] = 0.0;
+            if (detJ > 0.0) {
+                for (int d = 0; d < 3; ++d)
+                    y[d] = xc[d] + e1[d] * c_tet_pts[q][0] + e2[d] * c_tet_pts[q][1] + e3[d] * c_tet_pts[q][2];
+                w = c_tet_w[q] * detJ;
+                const int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
+                if (o < 0) w = 0.0;
+                else if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+            }
+            double *pr = pts + (size_t)t * PR;
+            pr[0] = y[0]; pr[1] = y[1]; pr[2] = y[2]; pr[3] = w;
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) {
+                pr[4 + k2] = C[k2];
+                pr[4 + B + k2] = dC[0][k2];
+                pr[4 + 2 * B + k2] = dC[1][k2];
+                pr[4 + 3 * B + k2] = dC[2][k2];
             }
         }
+        __syncthreads();
+        for (int a0 = 0; a0 < A; a0 += TR) {
+            for (int b0 = 0; b0 < A; b0 += blockDim.x) {
+                const int b = b0 + threadIdx.x;
+                const bool bon = b < A;
+                double acc[TR][10];
+#pragma unroll
+                for (int al = 0; al < TR; ++al)
+#pragma unroll
+                    for (int u = 0; u < 10; ++u) acc[al][u] = 0.0;
+                for (int r0 = 0; r0 < np; r0 += kRowChunk) {
+                    const int nr = min(kRowChunk, np - r0);
+                    // the tile rows' values at the chunk's points (zero where a row is inactive)
+                    for (int t = threadIdx.x; t < kRowChunk * TR; t += blockDim.x) {
+                        const int ql = t / TR, al = t - ql * TR;
+                        double v4[4] = {0.0, 0.0, 0.0, 0.0};
+                        if (ql < nr && a0 + al < A) {
+                            const double *pr = pts + (size_t)(r0 + ql) * PR;
+                            if (pr[3] != 0.0) {
+                                const double y[3] = {pr[0], pr[1], pr[2]};
+                                double C[B], dC[3][B];
+#pragma unroll
+                                for (int k2 = 0; k2 < B; ++k2) {
+                                    C[k2] = pr[4 + k2];
+                                    dC[0][k2] = pr[4 + B + k2];
+                                    dC[1][k2] = pr[4 + 2 * B + k2];
+                                    dC[2][k2] = pr[4 + 3 * B + k2];
+                                }
+                                double Na, dNa[3];
+                                if (rk_value3<ORD>(y, a0 + al, sx, sR, sV, hs, C, dC, &Na, dNa)) {
+                                    v4[0] = Na; v4[1] = dNa[0]; v4[2] = dNa[1]; v4[3] = dNa[2];
+                                }
+                            }
+                        }
+                        double *o = rv + (size_t)t * 4;
+                        o[0] = v4[0]; o[1] = v4[1]; o[2] = v4[2]; o[3] = v4[3];
+                    }
+                    __syncthreads();
+                    for (int ql = 0; ql < nr; ++ql) {
+                        const double *pr = pts + (size_t)(r0 + ql) * PR;
+                        const double w = pr[3];
+                        if (w == 0.0) continue;   // uniform over the workgroup
+                        double Nb = 0.0, dNb[3] = {0.0, 0.0, 0.0};
+                        bool act = false;
+                        if (bon) {
+                            const double y[3] = {pr[0], pr[1], pr[2]};
+                            double C[B], dC[3][B];
+#pragma unroll
+                            for (int k2 = 0; k2 < B; ++k2) {
+                                C[k2] = pr[4 + k2];
+                                dC[0][k2] = pr[4 + B + k2];
+                                dC[1][k2] = pr[4 + 2 * B + k2];
+                                dC[2][k2] = pr[4 + 3 * B + k2];
+                            }
+                            act = rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb);
+                        }
+                        if (act) {
+                            const double wNb = w * Nb, wd0 = w * dNb[0], wd1 = w * dNb[1], wd2 = w * dNb[2];
+                            const double *r = rv + (size_t)ql * TR * 4;
+#pragma unroll
+                            for (int al = 0; al < TR; ++al) {
+                                const double Na = r[4 * al], d0 = r[4 * al + 1], d1 = r[4 * al + 2], d2 = r[4 * al + 3];
+                                acc[al][0] += Na * wNb;
+                                acc[al][1] += d0 * wNb;
+                                acc[al][2] += d1 * wNb;
+                                acc[al][3] += d2 * wNb;
+                                acc[al][4] += d0 * wd0;
+                                acc[al][5] += d0 * wd1;
+                                acc[al][6] += d0 * wd2;
+                                acc[al][7] += d1 * wd1;
+                                acc[al][8] += d1 * wd2;
+                                acc[al][9] += d2 * wd2;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+                // the tile's sums of column b into the CSR blocks: K^ab and, for
+                // the derivative blocks yx, zx, zy, K^ba as the transpose
+                if (bon) {
+#pragma unroll
+                    for (int al = 0; al < TR; ++al) {
+                        const int a = a0 + al;
+                        if (a >= A) continue;
+                        bool nz = false;
+#pragma unroll
+                        for (int u = 0; u < 10; ++u) nz |= acc[al][u] != 0.0;
+                        if (!nz) continue;
+                        const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+                        if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (acc[al][u] != 0.0) atomicAdd(&g.blocks[(int64_t)u * nnz + pos], acc[al][u]);
+                        const int ab[6] = {0, 1, 2, 4, 5, 8};
+#pragma unroll
+                        for (int u = 0; u < 6; ++u)
+                            atomicAdd(&g.blocks[(int64_t)(4 + ab[u]) * nnz + pos], acc[al][4 + u]);
+                        const int64_t pos_t = find_col(g.row_off, g.col, sidx[b], sidx[a]);
+                        if (pos_t < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
+                        const int ba[3] = {3, 6, 7};    // yx, zx, zy
+                        const int src[3] = {1, 2, 4};   // from xy, xz, yz
+#pragma unroll
+                        for (int u = 0; u < 3; ++u)
+                            atomicAdd(&g.blocks[(int64_t)(4 + ba[u]) * nnz + pos_t], acc[al][4 + src[u]]);
+                    }
+                }
+            }
+        }
+        __syncthreads();   // the next pass overwrites the point records
     }
+    integ3_boundary<ORD>(g, c, A, sx, sR, sV, sidx, xc, hs, fvc, snbt, bnd_pre);
+}
+
+// Quadrature points per cell (fan tetrahedra of the cell's faces times the rule).
+__global__ void cell_points3_kernel(int64_t n, const int32_t *__restrict__ nf, const int32_t *__restrict__ fnv,
+                                    int32_t *__restrict__ out)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    int nt = 0;
+    for (int f = 0; f < nf[c]; ++f) nt += fnv[c * kFaceCap3 + f] - 2;
+    out[c] = nt * kTetRule;
 }
 
 hipError_t upload_rules3(hipStream_t s)
@@ -1300,6 +1532,34 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
     g.fields = field_set(P);
     if ((e = upload_rules(s)) != hipSuccess) return e;
     dim3 grid((unsigned)P.n);
+    if (P.n_mat == 1 && !(P.n_fields > 0 || P.n_shells > 0)) {
+        // one material without fields: the column-accumulating kernel, with as
+        // many point records per pass as LDS holds beside the candidates
+        cell_points3_kernel<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.nf.p, P.fnv.p, P.tmp_cand.p);
+        e = hipMemcpyAsync(h.data(), P.tmp_cand.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        int nqmax = 1;
+        for (int32_t v : h) nqmax = v > nqmax ? v : nqmax;
+        const int B = P.rk_order == 0 ? 1 : (P.rk_order == 1 ? 4 : 10);
+        const int PR = 4 + 4 * B;
+        const size_t cand = sizeof(double) * (5 * amax + (amax + 1) / 2);
+        const size_t rows = sizeof(double) * kRowChunk * kColRows * 4;
+        const size_t stat = 2 * sizeof(int) * (kFaceCap3 + 1) + 64;
+        const size_t avail = (lds_max > 0 ? (size_t)lds_max : 65536);
+        if (avail > cand + rows + stat + sizeof(double) * PR) {
+            int qcap = (int)((avail - cand - rows - stat) / (sizeof(double) * PR));
+            if (qcap > nqmax) qcap = nqmax;
+            const size_t sh = cand + rows + sizeof(double) * (size_t)qcap * PR;
+            void (*k)(Integ3Args, int) = P.rk_order == 0 ? integrate3d_cols_kernel<0>
+                                       : (P.rk_order == 1 ? integrate3d_cols_kernel<1> : integrate3d_cols_kernel<2>);
+            if ((e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) !=
+                hipSuccess)
+                return e;
+            k<<<grid, kThreads3, sh, s>>>(g, qcap);
+            return hipGetLastError();
+        }
+    }
     switch (P.rk_order) {
     case 0:
         e = launch_integ<0>(integrate3d_kernel<0, false>, integrate3d_kernel<0, true>, P.n_fields > 0 || P.n_shells > 0, grid, shmem, g, s, kThreads3);
