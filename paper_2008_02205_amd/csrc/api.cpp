@@ -30,7 +30,7 @@ void Problem::release()
     dsa.release();
     poff.release(); boff.release(); pidx.release(); binv.release(); binv32.release();
     patches_ok = binv_ok = false;
-    tmp_flags.release(); tmp_cand.release(); tmp_bqc.release(); tmp_key.release(); tmp_s2.release();
+    tmp_flags.release(); tmp_cand.release(); gram_ws.release(); tmp_bqc.release(); tmp_key.release(); tmp_s2.release();
     tmp_npc.release(); tmp_off.release(); tmp_pbase.release(); tmp_scnt.release(); tmp_cnt.release();
     tmp_sing.release(); tmp_work.release();
     own_geo.release(); own_int.release(); own_asm.release(); own_slv.release();
@@ -696,6 +696,7 @@ size_t mlpg_integrate_workspace_bytes(mlpg_handle h, int rk_order)
     if (!h || h->stage < 1 || rk_order < 0 || rk_order > 2) return 0;
     Problem Q;   // sizes only
     Q.n = h->n; Q.nnz = h->nnz; Q.n_bq = h->n_bq; Q.bq_kmax = h->bq_kmax; Q.dim = h->dim; Q.n_mat = h->n_mat;
+    Q.n_fields = h->n_fields; Q.n_shells = h->n_shells;
     Arena A;
     layout_integrate(Q, A);
     return A.used;

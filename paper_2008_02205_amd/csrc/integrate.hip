@@ -1187,56 +1187,230 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_kernel(Integ3Args g)
     integ3_boundary<ORD>(g, c, A, sx, sR, sV, sidx, xc, hs, fvc, snbt, bnd_pre);
 }
 
-// 3D integration without LDS atomics, for one material without fields (the
-// Gram products then need no per-point material weights).  A cell's
-// quadrature points are taken up to `qcap` at a time; each point's RK
-// correction (y, w, C, dC) is computed once into LDS.  The Gram matrix is
-// then formed in tiles of kColRows rows: every lane owns one column b (one
-// candidate function), walks the points in order and accumulates the tile's
-// sums w N_a N_b, w dN_a N_b and w dN_a dN_b for its column in registers, with
-// the tile rows' values at a chunk of kRowChunk points staged in LDS by the
-// workgroup first.  Each (row, column) entry is then added once into the CSR
-// blocks.  The same sums as integrate3d_kernel in another order.
-constexpr int kColRows = 8;
-constexpr int kRowChunk = 32;
+// Quadrature points per cell (fan tetrahedra of the cell's faces times the
+// rule) and, when outb is given, boundary points per cell (the triangles of
+// its faces on the domain boundary times the boundary rule).
+__global__ void cell_points3_kernel(int64_t n, const int32_t *__restrict__ nf, const int32_t *__restrict__ fnv,
+                                    const int32_t *__restrict__ ftags, int32_t *__restrict__ out,
+                                    int32_t *__restrict__ outb)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    int nt = 0, nb = 0;
+    for (int f = 0; f < nf[c]; ++f) {
+        const int m = fnv[c * kFaceCap3 + f] - 2;
+        const int tg = ftags[c * kFaceCap3 + f];
+        nt += m;
+        if (tg <= -1 && tg >= -6) nb += m;
+    }
+    out[c] = nt * kTetRule;
+    if (outb) outb[c] = nb * kTri3Rule;
+}
 
-template <int ORD>
-struct PointRec3 {
-    static constexpr int size = 4 + 4 * Basis3<ORD>::B;   // y, w, C, dC
+// ---- 3D, one material without fields: Gram products on the matrix cores ----
+//
+// The volume blocks of a cell (Sec. 3.2, Alg. 1) are sums over the cell's
+// quadrature points q of w_q f_i(y_q) f_j(y_q), where i = 4a + u runs over
+// the candidate functions a and the values u of each (N_a, dN_a/dx, dN_a/dy,
+// dN_a/dz).  With the panel F[q][i] = sqrt(w_q) f_i(y_q) this is the
+// symmetric product G = F^T F: a dense (4A x Q)(Q x 4A) contraction per cell.
+// A first kernel writes the panels of a batch of cells (one point per thread,
+// its RK correction computed once); a second forms the upper triangle of G in
+// 64 x 64 tiles with FP64 MFMA (one tile per wave, accumulators in registers)
+// and adds every entry to its CSR block.  The quadrature weights are positive
+// (conical product rule, positive Jacobians), so sqrt(w) is real.
+
+struct GramArgs {
+    double *F;          // [slots][slot] panels, row stride ipad
+    int64_t slot;       // doubles per slot: the volume panel (rows x ipad), then the surface panel
+    int64_t soff;       // offset of the surface panel in a slot: [boundary points][amax]
+    int ipad;           // row stride: 4 amax rounded up to 64
+    int amax;
+    int32_t *meta;      // [slots][2]: A, quadrature points (A = 0: nothing to add)
+    int32_t *idx;       // [slots][amax]: global index of each candidate
 };
 
+// Boundary terms of a cell for the panel kernel (the same quantities as
+// integ3_boundary).  Every boundary point (one per thread) writes its row of
+// the boundary table and its weighted values sqrt(w) N_a into the surface
+// panel Sp; then, for each of the cell's faces on the domain boundary, the
+// workgroup forms the face's sums over its points for every pair of functions
+// nonzero there, and adds each sum to the face's surface block at (a, b) and
+// (b, a) -- one CSR lookup per pair and face rather than per pair and point.
+// The point values at the generator are spread over the candidates.
 template <int ORD>
-__global__ __launch_bounds__(kThreads3) void integrate3d_cols_kernel(Integ3Args g, int qcap)
+__device__ void integ3_boundary_panel(const Integ3Args &g, int64_t c, int A, const double *sx, const double *sR,
+                                      const double *sV, const int32_t *sidx, const double (&xc)[3], double hs,
+                                      const double *fvc, int snbt, const int *bnd_pre, double *Sp, int ss,
+                                      int32_t *sflag, int32_t *slist)
+{
+    constexpr int B = Basis3<ORD>::B;
+    __shared__ double sC[4 * B];
+    __shared__ int s_o, s_m;
+    const int64_t nnz = g.nnz;
+    const int nbq = snbt * kTri3Rule;
+    const int sb = 4 * g.G + 9;
+    for (int t = threadIdx.x; t < nbq; t += blockDim.x) {
+        const int tr = t / kTri3Rule, q = t - tr * kTri3Rule;
+        int f = 0;
+        while (bnd_pre[f + 1] <= tr) f++;
+        const int k = 1 + tr - bnd_pre[f];
+        const int face = -1 - g.ftags[c * kFaceCap3 + f];
+        const double *A0 = fvc + (f * kFaceVerts3) * 3;
+        const double *B0 = fvc + (f * kFaceVerts3 + k) * 3;
+        const double *C0 = fvc + (f * kFaceVerts3 + k + 1) * 3;
+        double g1[3], g2[3], nn[3];
+        for (int d = 0; d < 3; ++d) { g1[d] = B0[d] - A0[d]; g2[d] = C0[d] - A0[d]; }
+        nn[0] = g1[1] * g2[2] - g1[2] * g2[1];
+        nn[1] = g1[2] * g2[0] - g1[0] * g2[2];
+        nn[2] = g1[0] * g2[1] - g1[1] * g2[0];
+        const double area2 = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+        double y[3];
+        for (int d = 0; d < 3; ++d) y[d] = A0[d] + g1[d] * c_tri3_pts[q][0] + g2[d] * c_tri3_pts[q][1];
+        const double w = c_tri3_w[q] * area2;
+        const int64_t bq = g.bq_off[c] + t;
+        for (int d = 0; d < 3; ++d) g.bq_y[3 * bq + d] = y[d];
+        g.bq_face[bq] = face;
+        g.bq_w[bq] = w;
+        double C[B], dC[3][B];
+        const int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
+        const double sw = w > 0.0 ? sqrt(w) : 0.0;
+        double *srow = Sp + (int64_t)t * ss;
+        int na = 0;
+        if (o >= 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+        for (int a = 0; a < A; ++a) {
+            double Na, d_[3];
+            if (o < 0 || !rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, d_)) {
+                srow[a] = 0.0;
+                continue;
+            }
+            if (na < kBqAct3) {
+                g.bq_act[bq * kBqAct3 + na] = sidx[a];
+                g.bq_N[bq * kBqAct3 + na] = Na;
+            } else {
+                atomicAdd(&g.counters[kOverflow], 1ull);
+            }
+            na++;
+            srow[a] = sw * Na;
+        }
+        g.bq_nact[bq] = na < kBqAct3 ? na : kBqAct3;
+    }
+    if (threadIdx.x == 0) {
+        double C[B], dC[3][B];
+        const int o = rk_prepare3<ORD>(xc, A, sx, sR, sV, hs, C, dC);
+        if (o >= 0 && o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
+        s_o = o;
+        for (int k2 = 0; k2 < B; ++k2) {
+            sC[k2] = C[k2];
+            sC[B + k2] = dC[0][k2];
+            sC[2 * B + k2] = dC[1][k2];
+            sC[3 * B + k2] = dC[2][k2];
+        }
+    }
+    __syncthreads();   // the surface panel rows and the generator's correction
+    // point values at the generator: E[c, j] = N_j(x_c)
+    if (s_o >= 0) {
+        double C[B], dC[3][B];
+        for (int k2 = 0; k2 < B; ++k2) {
+            C[k2] = sC[k2];
+            dC[0][k2] = sC[B + k2];
+            dC[1][k2] = sC[2 * B + k2];
+            dC[2][k2] = sC[3 * B + k2];
+        }
+        for (int a = threadIdx.x; a < A; a += blockDim.x) {
+            double Na, d_[3];
+            if (!rk_value3<ORD>(xc, a, sx, sR, sV, hs, C, dC, &Na, d_)) continue;
+            const int64_t pos = find_col(g.row_off, g.col, (int32_t)c, sidx[a]);
+            if (pos >= 0) g.E[pos] = Na;
+            else atomicAdd(&g.counters[kMissing], 1ull);
+        }
+    }
+    const int nfc = g.nf[c];
+    for (int f = 0; f < nfc; ++f) {
+        if (bnd_pre[f + 1] == bnd_pre[f]) continue;   // not on the domain boundary
+        const int q0 = kTri3Rule * bnd_pre[f], q1 = kTri3Rule * bnd_pre[f + 1];
+        const int face = -1 - g.ftags[c * kFaceCap3 + f];
+        double *blk = g.blocks + (int64_t)(sb + face) * nnz;
+        for (int a = threadIdx.x; a < A; a += blockDim.x) {
+            bool nz = false;
+            for (int qq = q0; qq < q1; ++qq) nz = nz || Sp[(int64_t)qq * ss + a] != 0.0;
+            sflag[a] = nz ? 1 : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int m = 0;
+            for (int a = 0; a < A; ++a)
+                if (sflag[a]) slist[m++] = a;
+            s_m = m;
+        }
+        __syncthreads();
+        const int m = s_m;
+        for (int p = threadIdx.x; p < m * m; p += blockDim.x) {
+            const int i = p / m, j = p - i * m;
+            if (j < i) continue;
+            const int a = slist[i], b = slist[j];
+            double sum = 0.0;
+            for (int qq = q0; qq < q1; ++qq) sum += Sp[(int64_t)qq * ss + a] * Sp[(int64_t)qq * ss + b];
+            if (sum == 0.0) continue;
+            const int64_t pab = find_col(g.row_off, g.col, sidx[a], sidx[b]);
+            if (pab < 0) atomicAdd(&g.counters[kMissing], 1ull);
+            else atomicAdd(&blk[pab], sum);
+            if (a == b) continue;
+            const int64_t pba = find_col(g.row_off, g.col, sidx[b], sidx[a]);
+            if (pba < 0) atomicAdd(&g.counters[kMissing], 1ull);
+            else atomicAdd(&blk[pba], sum);
+        }
+        __syncthreads();   // the flags and the list are reused by the next face
+    }
+}
+
+constexpr int kGramSplit = 4;   // workgroups per cell in the product kernel
+
+// Panels of cells c0 + blockIdx.x: row q (q < nq rounded up to 4) holds
+// sqrt(w_q) (N_a, dN_a) for the candidates a < A at columns 4a..4a+3 and zeros
+// up to the last 64-column tile; rows past nq are zero.  Then the cell's
+// boundary terms and point values (integ3_boundary_panel).
+template <int ORD>
+__global__ __launch_bounds__(kThreads3) void integrate3d_panels_kernel(Integ3Args g, GramArgs q, int64_t c0)
 {
     extern __shared__ double lds[];
     __shared__ int sA, sntet, snbt;
     __shared__ int tet_pre[kFaceCap3 + 1], bnd_pre[kFaceCap3 + 1];
     constexpr int B = Basis3<ORD>::B;
-    constexpr int PR = PointRec3<ORD>::size;
-    constexpr int TR = kColRows;
     const int amax = g.amax;
     double *sx = lds;
     double *sR = sx + 3 * amax;
     double *sV = sR + amax;
     int32_t *sidx = (int32_t *)(sV + amax);
-    double *pts = sV + amax + (amax + 1) / 2;    // [qcap][PR]
-    double *rv = pts + (size_t)qcap * PR;          // [kRowChunk][TR][4]
-    const int64_t c = blockIdx.x;
+    int32_t *sflag = sidx + amax;
+    int32_t *slist = sflag + amax;
+    const int slot = blockIdx.x;
+    const int64_t c = c0 + slot;
     const double xc[3] = {g.x[3 * c], g.x[3 * c + 1], g.x[3 * c + 2]};
     const double hs = 0.5 * g.R[c];
     if (threadIdx.x == 0) stage_cell3(g, c, xc, sx, sR, sV, sidx, &sA, tet_pre, bnd_pre, &sntet, &snbt);
     __syncthreads();
     const int A = sA;
-    if (A <= 0) return;
+    int32_t *meta = q.meta + 2 * (int64_t)slot;
+    if (A <= 0) {
+        if (threadIdx.x == 0) { meta[0] = 0; meta[1] = 0; }
+        return;
+    }
     const int nq = sntet * kTetRule;
+    const int nq4 = (nq + 3) & ~3;
+    const int width = ((4 * A + 63) >> 6) << 6;
+    if (threadIdx.x == 0) { meta[0] = A; meta[1] = nq; }
+    for (int a = threadIdx.x; a < A; a += blockDim.x) q.idx[(int64_t)slot * amax + a] = sidx[a];
     const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
-    const int64_t nnz = g.nnz;
-
-    for (int p0 = 0; p0 < nq; p0 += qcap) {
-        const int np = min(qcap, nq - p0);
-        // the points' RK corrections, once per point (w = 0: no contribution)
-        for (int t = threadIdx.x; t < np; t += blockDim.x) {
-            const int te = (p0 + t) / kTetRule, q = (p0 + t) - te * kTetRule;
+    double *Fs = q.F + (int64_t)slot * q.slot;
+    for (int t = threadIdx.x; t < nq4; t += blockDim.x) {
+        double y[3] = {xc[0], xc[1], xc[2]};
+        double w = 0.0;
+        double C[B], dC[3][B];
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) C[k2] = dC[0][k2] = dC[1][k2] = dC[2][k2] = 0.0;
+        if (t < nq) {
+            const int te = t / kTetRule, qq = t - te * kTetRule;
             int f = 0;
             while (tet_pre[f + 1] <= te) f++;
             const int k = 1 + te - tet_pre[f];
@@ -1249,151 +1423,170 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_cols_kernel(Integ3Args 
             cr[1] = e2[2] * e3[0] - e2[0] * e3[2];
             cr[2] = e2[0] * e3[1] - e2[1] * e3[0];
             const double detJ = e1[0] * cr[0] + e1[1] * cr[1] + e1[2] * cr[2];
-            double y[3] = {xc[0], xc[1], xc[2]};
-            double w = 0.0;
-            double C[B], dC[3][B];
-#pragma unroll
-            for (int k2 = 0; k2 < B; ++k2) C[k2] = dC[0][k2] = dC[1][k2] = dC[2][k2] = 0.0;
             if (detJ > 0.0) {
                 for (int d = 0; d < 3; ++d)
-                    y[d] = xc[d] + e1[d] * c_tet_pts[q][0] + e2[d] * c_tet_pts[q][1] + e3[d] * c_tet_pts[q][2];
-                w = c_tet_w[q] * detJ;
+                    y[d] = xc[d] + e1[d] * c_tet_pts[qq][0] + e2[d] * c_tet_pts[qq][1] + e3[d] * c_tet_pts[qq][2];
+                w = c_tet_w[qq] * detJ;
                 const int o = rk_prepare3<ORD>(y, A, sx, sR, sV, hs, C, dC);
                 if (o < 0) w = 0.0;
                 else if (o < ORD) atomicAdd(&g.counters[kFallbacks], 1ull);
             }
-            double *pr = pts + (size_t)t * PR;
-            pr[0] = y[0]; pr[1] = y[1]; pr[2] = y[2]; pr[3] = w;
-#pragma unroll
-            for (int k2 = 0; k2 < B; ++k2) {
-                pr[4 + k2] = C[k2];
-                pr[4 + B + k2] = dC[0][k2];
-                pr[4 + 2 * B + k2] = dC[1][k2];
-                pr[4 + 3 * B + k2] = dC[2][k2];
-            }
         }
-        __syncthreads();
-        for (int a0 = 0; a0 < A; a0 += TR) {
-            for (int b0 = 0; b0 < A; b0 += blockDim.x) {
-                const int b = b0 + threadIdx.x;
-                const bool bon = b < A;
-                double acc[TR][10];
-#pragma unroll
-                for (int al = 0; al < TR; ++al)
-#pragma unroll
-                    for (int u = 0; u < 10; ++u) acc[al][u] = 0.0;
-                for (int r0 = 0; r0 < np; r0 += kRowChunk) {
-                    const int nr = min(kRowChunk, np - r0);
-                    // the tile rows' values at the chunk's points (zero where a row is inactive)
-                    for (int t = threadIdx.x; t < kRowChunk * TR; t += blockDim.x) {
-                        const int ql = t / TR, al = t - ql * TR;
-                        double v4[4] = {0.0, 0.0, 0.0, 0.0};
-                        if (ql < nr && a0 + al < A) {
-                            const double *pr = pts + (size_t)(r0 + ql) * PR;
-                            if (pr[3] != 0.0) {
-                                const double y[3] = {pr[0], pr[1], pr[2]};
-                                double C[B], dC[3][B];
-#pragma unroll
-                                for (int k2 = 0; k2 < B; ++k2) {
-                                    C[k2] = pr[4 + k2];
-                                    dC[0][k2] = pr[4 + B + k2];
-                                    dC[1][k2] = pr[4 + 2 * B + k2];
-                                    dC[2][k2] = pr[4 + 3 * B + k2];
-                                }
-                                double Na, dNa[3];
-                                if (rk_value3<ORD>(y, a0 + al, sx, sR, sV, hs, C, dC, &Na, dNa)) {
-                                    v4[0] = Na; v4[1] = dNa[0]; v4[2] = dNa[1]; v4[3] = dNa[2];
-                                }
-                            }
-                        }
-                        double *o = rv + (size_t)t * 4;
-                        o[0] = v4[0]; o[1] = v4[1]; o[2] = v4[2]; o[3] = v4[3];
-                    }
-                    __syncthreads();
-                    for (int ql = 0; ql < nr; ++ql) {
-                        const double *pr = pts + (size_t)(r0 + ql) * PR;
-                        const double w = pr[3];
-                        if (w == 0.0) continue;   // uniform over the workgroup
-                        double Nb = 0.0, dNb[3] = {0.0, 0.0, 0.0};
-                        bool act = false;
-                        if (bon) {
-                            const double y[3] = {pr[0], pr[1], pr[2]};
-                            double C[B], dC[3][B];
-#pragma unroll
-                            for (int k2 = 0; k2 < B; ++k2) {
-                                C[k2] = pr[4 + k2];
-                                dC[0][k2] = pr[4 + B + k2];
-                                dC[1][k2] = pr[4 + 2 * B + k2];
-                                dC[2][k2] = pr[4 + 3 * B + k2];
-                            }
-                            act = rk_value3<ORD>(y, b, sx, sR, sV, hs, C, dC, &Nb, dNb);
-                        }
-                        if (act) {
-                            const double wNb = w * Nb, wd0 = w * dNb[0], wd1 = w * dNb[1], wd2 = w * dNb[2];
-                            const double *r = rv + (size_t)ql * TR * 4;
-#pragma unroll
-                            for (int al = 0; al < TR; ++al) {
-                                const double Na = r[4 * al], d0 = r[4 * al + 1], d1 = r[4 * al + 2], d2 = r[4 * al + 3];
-                                acc[al][0] += Na * wNb;
-                                acc[al][1] += d0 * wNb;
-                                acc[al][2] += d1 * wNb;
-                                acc[al][3] += d2 * wNb;
-                                acc[al][4] += d0 * wd0;
-                                acc[al][5] += d0 * wd1;
-                                acc[al][6] += d0 * wd2;
-                                acc[al][7] += d1 * wd1;
-                                acc[al][8] += d1 * wd2;
-                                acc[al][9] += d2 * wd2;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-                // the tile's sums of column b into the CSR blocks: K^ab and, for
-                // the derivative blocks yx, zx, zy, K^ba as the transpose
-                if (bon) {
-#pragma unroll
-                    for (int al = 0; al < TR; ++al) {
-                        const int a = a0 + al;
-                        if (a >= A) continue;
-                        bool nz = false;
-#pragma unroll
-                        for (int u = 0; u < 10; ++u) nz |= acc[al][u] != 0.0;
-                        if (!nz) continue;
-                        const int64_t pos = find_col(g.row_off, g.col, sidx[a], sidx[b]);
-                        if (pos < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (acc[al][u] != 0.0) atomicAdd(&g.blocks[(int64_t)u * nnz + pos], acc[al][u]);
-                        const int ab[6] = {0, 1, 2, 4, 5, 8};
-#pragma unroll
-                        for (int u = 0; u < 6; ++u)
-                            atomicAdd(&g.blocks[(int64_t)(4 + ab[u]) * nnz + pos], acc[al][4 + u]);
-                        const int64_t pos_t = find_col(g.row_off, g.col, sidx[b], sidx[a]);
-                        if (pos_t < 0) { atomicAdd(&g.counters[kMissing], 1ull); continue; }
-                        const int ba[3] = {3, 6, 7};    // yx, zx, zy
-                        const int src[3] = {1, 2, 4};   // from xy, xz, yz
-#pragma unroll
-                        for (int u = 0; u < 3; ++u)
-                            atomicAdd(&g.blocks[(int64_t)(4 + ba[u]) * nnz + pos_t], acc[al][4 + src[u]]);
-                    }
-                }
+        const double sw = w > 0.0 ? sqrt(w) : 0.0;
+        double *row = Fs + (int64_t)t * q.ipad;
+        for (int a = 0; a < A; ++a) {
+            double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+            double Na, dNa[3];
+            if (sw > 0.0 && rk_value3<ORD>(y, a, sx, sR, sV, hs, C, dC, &Na, dNa)) {
+                v0 = sw * Na; v1 = sw * dNa[0]; v2 = sw * dNa[1]; v3 = sw * dNa[2];
             }
+            double2 *o = (double2 *)(row + 4 * a);
+            o[0] = make_double2(v0, v1);
+            o[1] = make_double2(v2, v3);
         }
-        __syncthreads();   // the next pass overwrites the point records
+        for (int i = 4 * A; i < width; i += 2) *(double2 *)(row + i) = make_double2(0.0, 0.0);
     }
-    integ3_boundary<ORD>(g, c, A, sx, sR, sV, sidx, xc, hs, fvc, snbt, bnd_pre);
+    integ3_boundary_panel<ORD>(g, c, A, sx, sR, sV, sidx, xc, hs, fvc, snbt, bnd_pre, Fs + q.soff, amax, sflag,
+                               slist);
 }
 
-// Quadrature points per cell (fan tetrahedra of the cell's faces times the rule).
-__global__ void cell_points3_kernel(int64_t n, const int32_t *__restrict__ nf, const int32_t *__restrict__ fnv,
-                                    int32_t *__restrict__ out)
+typedef double gram_acc_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    int nt = 0;
-    for (int f = 0; f < nf[c]; ++f) nt += fnv[c * kFaceCap3 + f] - 2;
-    out[c] = nt * kTetRule;
+    const int lo = __shfl((int)(uint32_t)(uint64_t)v, src);
+    const int hi = __shfl((int)(uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Block index of the entry (value u of row function, value v of column
+// function) at the row's CSR position: 0 for N N, u for dN_u N, and
+// 4 + 3(u-1) + (v-1) for dN_u dN_v (u, v = 1..3 for x, y, z).
+__device__ __forceinline__ int gram_block(int u, int v)
+{
+    return v == 0 ? u : 4 + 3 * (u - 1) + (v - 1);
+}
+
+// One 64 x 64 tile (I, J), I <= J, of a cell's G: 16 x 16 candidate pairs.
+// MFMA 16x16x4 (FP64): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of
+// the operands and D[l / 16 + 4 r][l % 16] in accumulator register r.
+template <bool DIAG>
+__device__ __forceinline__ void gram_tile(const double *__restrict__ Fs, int ipad, int nk, int I, int J, int lane,
+                                          gram_acc_t (&acc)[4][4])
+{
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = gram_acc_t{0.0, 0.0, 0.0, 0.0};
+    const double *pa = Fs + (int64_t)(lane >> 4) * ipad + I * 64 + (lane & 15);
+    const double *pb = Fs + (int64_t)(lane >> 4) * ipad + J * 64 + (lane & 15);
+    const int64_t step = 4 * (int64_t)ipad;
+    double av[4], bv[4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi) {
+        av[bi] = pa[bi * 16];
+        bv[bi] = DIAG ? 0.0 : pb[bi * 16];
+    }
+    for (int ks = 0; ks < nk; ++ks) {
+        double an[4], bn[4];
+        const bool more = ks + 1 < nk;
+        pa += step;
+        pb += step;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) {
+            an[bi] = more ? pa[bi * 16] : 0.0;
+            bn[bi] = (!DIAG && more) ? pb[bi * 16] : 0.0;
+        }
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                if (DIAG && bi > bj) continue;   // wholly below the diagonal
+                acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], DIAG ? av[bj] : bv[bj], acc[bi][bj],
+                                                                  0, 0, 0);
+            }
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) {
+            av[bi] = an[bi];
+            bv[bi] = bn[bi];
+        }
+    }
+}
+
+// Workgroups (cell slot, part): kGramSplit per slot, renumbered so that the
+// parts of one slot run on one XCD (blocks are dealt round-robin over the 8
+// XCDs) and share its L2.  Each wave takes the slot's tiles t = part * 4 +
+// wave, + 4 kGramSplit, ...: looks up the CSR positions of the tile's 256
+// candidate pairs both ways (8 per lane, kept in registers), forms the tile,
+// and adds each entry of the upper triangle to its block (twice when the
+// mirrored entry belongs to another block or position).
+__global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, const int64_t *__restrict__ row_off,
+                                                       const int32_t *__restrict__ col, double *blocks, int64_t nnz,
+                                                       unsigned long long *counters, int nslot)
+{
+    const int G8 = gridDim.x >> 3;
+    const int L = (blockIdx.x & 7) * G8 + (blockIdx.x >> 3);
+    const int slot = L / kGramSplit, part = L - slot * kGramSplit;
+    if (slot >= nslot) return;
+    const int A = q.meta[2 * slot], nq = q.meta[2 * slot + 1];
+    if (A <= 0 || nq <= 0) return;
+    const int T = (4 * A + 63) >> 6;
+    const int ntask = T * (T + 1) / 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nk = (nq + 3) >> 2;
+    const double *Fs = q.F + (int64_t)slot * q.slot;
+    const int32_t *gidx = q.idx + (int64_t)slot * q.amax;
+    for (int t = part * 4 + wave; t < ntask; t += 4 * kGramSplit) {
+        int I = 0, r = t;
+        while (r >= T - I) { r -= T - I; ++I; }
+        const int J = I + r;
+        // pair p = 16 a' + b' (a = 16 I + a', b = 16 J + b'): entries 0..255
+        // are pos(a, b), 256..511 pos(b, a); lane l holds entries l + 64 s
+        int64_t pos[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int p = (lane + 64 * s) & 255;
+            const int a = 16 * I + (p >> 4), b = 16 * J + (p & 15);
+            pos[s] = -1;
+            if (a < A && b < A)
+                pos[s] = s < 4 ? find_col(row_off, col, gidx[a], gidx[b]) : find_col(row_off, col, gidx[b], gidx[a]);
+        }
+        gram_acc_t acc[4][4];
+        if (I == J) gram_tile<true>(Fs, q.ipad, nk, I, J, lane, acc);
+        else gram_tile<false>(Fs, q.ipad, nk, I, J, lane, acc);
+        // lane l holds value u = l / 16 of row function a = 16 I + 4 bi + r and
+        // value v = l % 4 of column function b = 16 J + 4 bj + (l % 16) / 4;
+        // pair entry 16 (4 bi + r) + b' sits in pos[bi] (pos[4 + bi]) of lane
+        // 16 r + b'
+        const int u = lane >> 4, v = lane & 3, c4 = (lane & 15) >> 2;
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+                if (I == J && bi > bj) continue;   // uniform: wholly below the diagonal
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int src = 16 * r + 4 * bj + c4;
+                    const int64_t pab = shfl64(pos[bi], src), pba = shfl64(pos[4 + bi], src);
+                    const int a = 16 * I + 4 * bi + r, b = 16 * J + 4 * bj + c4;
+                    if (a >= A || b >= A) continue;
+                    const double val = acc[bi][bj][r];
+                    if (val == 0.0) continue;
+                    const int i = 4 * a + u, j = 4 * b + v;
+                    if (i > j) continue;   // the mirror entry (in this tile when I == J) adds it
+                    const bool fwd = i == j || u >= 1 || v == 0;
+                    const bool bwd = i != j && (v >= 1 || u == 0);
+                    if (fwd) {
+                        if (pab < 0) atomicAdd(&counters[kMissing], 1ull);
+                        else atomicAdd(&blocks[(int64_t)gram_block(u, v) * nnz + pab], val);
+                    }
+                    if (bwd) {
+                        if (pba < 0) atomicAdd(&counters[kMissing], 1ull);
+                        else atomicAdd(&blocks[(int64_t)gram_block(v, u) * nnz + pba], val);
+                    }
+                }
+            }
+    }
 }
 
 hipError_t upload_rules3(hipStream_t s)
@@ -1533,30 +1726,48 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
     if ((e = upload_rules(s)) != hipSuccess) return e;
     dim3 grid((unsigned)P.n);
     if (P.n_mat == 1 && !(P.n_fields > 0 || P.n_shells > 0)) {
-        // one material without fields: the column-accumulating kernel, with as
-        // many point records per pass as LDS holds beside the candidates
-        cell_points3_kernel<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.nf.p, P.fnv.p, P.tmp_cand.p);
+        // one material without fields: panels of as many cells as the
+        // workspace region holds, then their Gram products on the matrix cores
+        // (the atomic kernel below when not even one panel fits)
+        int32_t *nbq_cell = (int32_t *)P.tmp_scnt.p;   // free until the surface counts after integration
+        cell_points3_kernel<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.nf.p, P.fnv.p, P.ftags.p,
+                                                                          P.tmp_cand.p, nbq_cell);
+        std::vector<int32_t> hb(P.n);
         e = hipMemcpyAsync(h.data(), P.tmp_cand.p, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), nbq_cell, sizeof(int32_t) * P.n, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        int nqmax = 1;
+        int nqmax = 1, nbqmax = 0;
         for (int32_t v : h) nqmax = v > nqmax ? v : nqmax;
-        const int B = P.rk_order == 0 ? 1 : (P.rk_order == 1 ? 4 : 10);
-        const int PR = 4 + 4 * B;
-        const size_t cand = sizeof(double) * (5 * amax + (amax + 1) / 2);
-        const size_t rows = sizeof(double) * kRowChunk * kColRows * 4;
-        const size_t stat = 2 * sizeof(int) * (kFaceCap3 + 1) + 64;
-        const size_t avail = (lds_max > 0 ? (size_t)lds_max : 65536);
-        if (avail > cand + rows + stat + sizeof(double) * PR) {
-            int qcap = (int)((avail - cand - rows - stat) / (sizeof(double) * PR));
-            if (qcap > nqmax) qcap = nqmax;
-            const size_t sh = cand + rows + sizeof(double) * (size_t)qcap * PR;
-            void (*k)(Integ3Args, int) = P.rk_order == 0 ? integrate3d_cols_kernel<0>
-                                       : (P.rk_order == 1 ? integrate3d_cols_kernel<1> : integrate3d_cols_kernel<2>);
-            if ((e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh)) !=
-                hipSuccess)
-                return e;
-            k<<<grid, kThreads3, sh, s>>>(g, qcap);
+        for (int32_t v : hb) nbqmax = v > nbqmax ? v : nbqmax;
+        const int ipad = ((4 * amax + 63) / 64) * 64;
+        const int64_t rows = (nqmax + 3) & ~3;
+        const int64_t soff = rows * ipad;
+        const size_t panel = sizeof(double) * ((size_t)soff + (size_t)nbqmax * amax);
+        const size_t per = panel + sizeof(int32_t) * (2 + (size_t)amax);
+        const size_t region = P.gram_ws.count;
+        const int64_t nb = region > 1024 ? std::min<int64_t>(P.n, (int64_t)((region - 1024) / per)) : 0;
+        if (nb >= 1) {
+            GramArgs q;
+            char *base = P.gram_ws.p;
+            q.F = (double *)base;
+            q.slot = (int64_t)(panel / sizeof(double));
+            q.soff = soff;
+            q.ipad = ipad;
+            q.amax = amax;
+            q.meta = (int32_t *)(base + ((panel * nb + 255) & ~(size_t)255));
+            q.idx = q.meta + 2 * nb;
+            const size_t cand = sizeof(double) * (5 * amax + (amax + 1) / 2) + 2 * sizeof(int32_t) * amax;
+            void (*kp)(Integ3Args, GramArgs, int64_t) =
+                P.rk_order == 0 ? integrate3d_panels_kernel<0>
+                                : (P.rk_order == 1 ? integrate3d_panels_kernel<1> : integrate3d_panels_kernel<2>);
+            for (int64_t c0 = 0; c0 < P.n; c0 += nb) {
+                const int64_t nc = std::min<int64_t>(nb, P.n - c0);
+                kp<<<(unsigned)nc, kThreads3, cand, s>>>(g, q, c0);
+                const int64_t nblk = ((nc * kGramSplit + 7) / 8) * 8;
+                gram3_kernel<<<(unsigned)nblk, 256, 0, s>>>(q, g.row_off, g.col, g.blocks, g.nnz, g.counters,
+                                                            (int)nc);
+            }
             return hipGetLastError();
         }
     }

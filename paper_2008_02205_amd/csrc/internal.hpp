@@ -29,6 +29,13 @@ constexpr int kTri3Rule = kTri3N * kTri3N;
 constexpr int kBqAct3 = 128;       // active functions stored per boundary point (3D)
 constexpr int kCandMax3D = 512;    // functions possibly active on one 3D cell
 constexpr int kTileRows3 = 8;      // most Gram rows per 3D tile without fields (their values sit in registers)
+// 3D, one material without fields: the cells' weighted function values are
+// written to panels in the integration workspace, a batch of cells at a
+// time, and their Gram products formed on the matrix cores.  The region holds
+// up to kGramCells panels of the estimated size below (the batch shrinks
+// when a problem's panels are larger).
+constexpr int64_t kGramCells = 1024;
+constexpr size_t kGramPanelBytes = size_t(2) << 20;
 constexpr int kMaxRestart = 30;
 constexpr int kMaxFields = 8;    // smooth material fields per problem
 constexpr int kMaxMat = 8;       // materials per problem
@@ -311,6 +318,7 @@ struct Problem {
     int32_t reg_mat_h[64] = {};
     int64_t ncell = 0;                      // cells of the patch grid
     DevBuf<int32_t> tmp_flags, tmp_cand;
+    DevBuf<char> gram_ws;                   // 3D panels of weighted values (integration workspace)
     DevBuf<int64_t> tmp_bqc, tmp_key, tmp_s2, tmp_npc, tmp_off, tmp_pbase, tmp_scnt;
     DevBuf<unsigned long long> tmp_cnt, tmp_sing;
     DevBuf<double> tmp_work;

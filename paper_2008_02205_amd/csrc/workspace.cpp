@@ -56,7 +56,8 @@ void layout_geometry(Problem &P, Arena &A, int64_t nnz_nb)
 }
 
 // Blocks, point-value matrix, boundary quadrature (sized by the cells), the
-// surface-row offsets, and the candidate and surface counts.
+// surface-row offsets, the candidate and surface counts, and in 3D with one
+// material and no fields the Gram panels of a batch of cells.
 void layout_integrate(Problem &P, Arena &A)
 {
     const int64_t n = P.n, nnz = P.nnz;
@@ -73,6 +74,8 @@ void layout_integrate(Problem &P, Arena &A)
     A.take(P.surf_off, n + 1);
     A.take(P.tmp_cand, n);
     A.take(P.tmp_scnt, n);
+    const bool panels = P.dim == 3 && P.n_mat == 1 && P.n_fields == 0 && P.n_shells == 0;
+    A.take(P.gram_ws, panels ? (size_t)std::min<int64_t>(n, kGramCells) * kGramPanelBytes : 0);
 }
 
 // The state (Psi, Phi: first, so that a workspace reused with the same
