@@ -1222,12 +1222,14 @@ __global__ void cell_points3_kernel(int64_t n, const int32_t *__restrict__ nf, c
 
 struct GramArgs {
     double *F;          // [slots][slot] panels, row stride ipad
-    int64_t slot;       // doubles per slot: the volume panel (rows x ipad), then the surface panel
+    int64_t slot;       // doubles per slot: the volume panel (rows x ipad), the surface panel,
+                        // the position table, the row starts
     int64_t soff;       // offset of the surface panel in a slot: [boundary points][amax]
+    int64_t toff;       // offset of the position table: int32 [amax][amax], then int64 [amax]
     int ipad;           // row stride: 4 amax rounded up to 64
     int amax;
     int32_t *meta;      // [slots][2]: A, quadrature points (A = 0: nothing to add)
-    int32_t *idx;       // [slots][amax]: global index of each candidate
+    unsigned *queue;    // one task counter per XCD, 64 bytes apart (zeroed by the panel kernel)
 };
 
 // Boundary terms of a cell for the panel kernel (the same quantities as
@@ -1364,7 +1366,6 @@ __device__ void integ3_boundary_panel(const Integ3Args &g, int64_t c, int A, con
     }
 }
 
-constexpr int kGramSplit = 4;   // workgroups per cell in the product kernel
 
 // Panels of cells c0 + blockIdx.x: row q (q < nq rounded up to 4) holds
 // sqrt(w_q) (N_a, dN_a) for the candidates a < A at columns 4a..4a+3 and zeros
@@ -1400,9 +1401,36 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_panels_kernel(Integ3Arg
     const int nq4 = (nq + 3) & ~3;
     const int width = ((4 * A + 63) >> 6) << 6;
     if (threadIdx.x == 0) { meta[0] = A; meta[1] = nq; }
-    for (int a = threadIdx.x; a < A; a += blockDim.x) q.idx[(int64_t)slot * amax + a] = sidx[a];
+    if (blockIdx.x == 0 && threadIdx.x < 8) q.queue[16 * threadIdx.x] = 0u;
     const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
     double *Fs = q.F + (int64_t)slot * q.slot;
+    // CSR positions of every candidate pair, relative to the row start (-1:
+    // not in the pattern): each candidate's row merged with the candidates in
+    // global order (the overlap list is ascending; the generator, candidate
+    // 0, goes in at its place)
+    {
+        int32_t *rel = (int32_t *)(Fs + q.toff);
+        int64_t *rstart = (int64_t *)(Fs + q.toff + ((int64_t)amax * amax + 1) / 2);
+        int lo = 1, hi = A;   // first candidate after the generator in global order
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sidx[mid] < (int32_t)c) lo = mid + 1;
+            else hi = mid;
+        }
+        const int p0 = lo - 1;
+        for (int a = threadIdx.x; a < A; a += blockDim.x) {
+            const int64_t r0 = g.row_off[sidx[a]], r1 = g.row_off[sidx[a] + 1];
+            rstart[a] = r0;
+            int32_t *ra = rel + (int64_t)a * amax;
+            int64_t p = r0;
+            for (int k = 0; k < A; ++k) {
+                const int b = k < p0 ? k + 1 : (k == p0 ? 0 : k);
+                const int32_t j = sidx[b];
+                while (p < r1 && g.col[p] < j) ++p;
+                ra[b] = (p < r1 && g.col[p] == j) ? (int32_t)(p - r0) : -1;
+            }
+        }
+    }
     for (int t = threadIdx.x; t < nq4; t += blockDim.x) {
         double y[3] = {xc[0], xc[1], xc[2]};
         double w = 0.0;
@@ -1513,33 +1541,41 @@ __device__ __forceinline__ void gram_tile(const double *__restrict__ Fs, int ipa
     }
 }
 
-// Workgroups (cell slot, part): kGramSplit per slot, renumbered so that the
-// parts of one slot run on one XCD (blocks are dealt round-robin over the 8
-// XCDs) and share its L2.  Each wave takes the slot's tiles t = part * 4 +
-// wave, + 4 kGramSplit, ...: looks up the CSR positions of the tile's 256
-// candidate pairs both ways (8 per lane, kept in registers), forms the tile,
-// and adds each entry of the upper triangle to its block (twice when the
-// mirrored entry belongs to another block or position).
-__global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, const int64_t *__restrict__ row_off,
-                                                       const int32_t *__restrict__ col, double *blocks, int64_t nnz,
-                                                       unsigned long long *counters, int nslot)
+// Persistent workgroups, each serving the task queue of the XCD it runs on
+// (workgroups are dealt round-robin over the 8 XCDs): queue x holds the tiles
+// of the batch's slots x, x + 8, ..., slot by slot, so that the waves of one
+// XCD work on few cells at a time and find their panels in its L2.  A wave
+// takes the next tile (I, J), I <= J, reads the CSR positions of its 256
+// candidate pairs both ways from the slot's table (8 per lane, kept in
+// registers), forms the tile, and adds each entry of the upper triangle to its
+// block (twice when the mirrored entry belongs to another block or position).
+// Every wave leaves once its queue is drained.
+__global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, double *blocks, int64_t nnz,
+                                                       unsigned long long *counters, int nslot, int ntmax)
 {
-    const int G8 = gridDim.x >> 3;
-    const int L = (blockIdx.x & 7) * G8 + (blockIdx.x >> 3);
-    const int slot = L / kGramSplit, part = L - slot * kGramSplit;
-    if (slot >= nslot) return;
-    const int A = q.meta[2 * slot], nq = q.meta[2 * slot + 1];
-    if (A <= 0 || nq <= 0) return;
-    const int T = (4 * A + 63) >> 6;
-    const int ntask = T * (T + 1) / 2;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nk = (nq + 3) >> 2;
-    const double *Fs = q.F + (int64_t)slot * q.slot;
-    const int32_t *gidx = q.idx + (int64_t)slot * q.amax;
-    for (int t = part * 4 + wave; t < ntask; t += 4 * kGramSplit) {
-        int I = 0, r = t;
-        while (r >= T - I) { r -= T - I; ++I; }
-        const int J = I + r;
+    const int x = blockIdx.x & 7;
+    const int lane = threadIdx.x & 63;
+    const int nsx = nslot > x ? (nslot - x + 7) / 8 : 0;
+    const unsigned total = (unsigned)nsx * (unsigned)ntmax;
+    const int amax = q.amax;
+    for (;;) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(&q.queue[16 * x], 1u);
+        t = (unsigned)__shfl((int)t, 0);
+        if (t >= total) break;
+        const int slot = x + 8 * (int)(t / (unsigned)ntmax);
+        int rt = (int)(t % (unsigned)ntmax);
+        const int A = q.meta[2 * slot], nq = q.meta[2 * slot + 1];
+        if (A <= 0 || nq <= 0) continue;
+        const int T = (4 * A + 63) >> 6;
+        if (rt >= T * (T + 1) / 2) continue;
+        int I = 0;
+        while (rt >= T - I) { rt -= T - I; ++I; }
+        const int J = I + rt;
+        const int nk = (nq + 3) >> 2;
+        const double *Fs = q.F + (int64_t)slot * q.slot;
+        const int32_t *rel = (const int32_t *)(Fs + q.toff);
+        const int64_t *rstart = (const int64_t *)(Fs + q.toff + ((int64_t)amax * amax + 1) / 2);
         // pair p = 16 a' + b' (a = 16 I + a', b = 16 J + b'): entries 0..255
         // are pos(a, b), 256..511 pos(b, a); lane l holds entries l + 64 s
         int64_t pos[8];
@@ -1548,8 +1584,11 @@ __global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, const int64_t
             const int p = (lane + 64 * s) & 255;
             const int a = 16 * I + (p >> 4), b = 16 * J + (p & 15);
             pos[s] = -1;
-            if (a < A && b < A)
-                pos[s] = s < 4 ? find_col(row_off, col, gidx[a], gidx[b]) : find_col(row_off, col, gidx[b], gidx[a]);
+            if (a < A && b < A) {
+                const int ra = s < 4 ? a : b, rb = s < 4 ? b : a;
+                const int32_t o = rel[(int64_t)ra * amax + rb];
+                if (o >= 0) pos[s] = rstart[ra] + o;
+            }
         }
         gram_acc_t acc[4][4];
         if (I == J) gram_tile<true>(Fs, q.ipad, nk, I, J, lane, acc);
@@ -1743,20 +1782,28 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
         const int ipad = ((4 * amax + 63) / 64) * 64;
         const int64_t rows = (nqmax + 3) & ~3;
         const int64_t soff = rows * ipad;
-        const size_t panel = sizeof(double) * ((size_t)soff + (size_t)nbqmax * amax);
-        const size_t per = panel + sizeof(int32_t) * (2 + (size_t)amax);
+        const int64_t toff = soff + (int64_t)nbqmax * amax;
+        const size_t panel = sizeof(double) * ((size_t)toff + ((size_t)amax * amax + 1) / 2 + (size_t)amax);
+        const size_t per = panel + 2 * sizeof(int32_t);
         const size_t region = P.gram_ws.count;
-        const int64_t nb = region > 1024 ? std::min<int64_t>(P.n, (int64_t)((region - 1024) / per)) : 0;
+        const int64_t nb = region > 2048 ? std::min<int64_t>(P.n, (int64_t)((region - 2048) / per)) : 0;
         if (nb >= 1) {
             GramArgs q;
             char *base = P.gram_ws.p;
             q.F = (double *)base;
             q.slot = (int64_t)(panel / sizeof(double));
             q.soff = soff;
+            q.toff = toff;
             q.ipad = ipad;
             q.amax = amax;
-            q.meta = (int32_t *)(base + ((panel * nb + 255) & ~(size_t)255));
-            q.idx = q.meta + 2 * nb;
+            const size_t moff = (panel * nb + 255) & ~(size_t)255;
+            q.meta = (int32_t *)(base + moff);
+            q.queue = (unsigned *)(base + ((moff + 2 * sizeof(int32_t) * nb + 255) & ~(size_t)255));
+            int ncu = 0;
+            if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+            const int tmax = ipad / 64;
+            const int ntmax = tmax * (tmax + 1) / 2;
+            const unsigned gblocks = (unsigned)(((std::max(ncu, 8) * 2) + 7) / 8 * 8);
             const size_t cand = sizeof(double) * (5 * amax + (amax + 1) / 2) + 2 * sizeof(int32_t) * amax;
             void (*kp)(Integ3Args, GramArgs, int64_t) =
                 P.rk_order == 0 ? integrate3d_panels_kernel<0>
@@ -1764,9 +1811,7 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
             for (int64_t c0 = 0; c0 < P.n; c0 += nb) {
                 const int64_t nc = std::min<int64_t>(nb, P.n - c0);
                 kp<<<(unsigned)nc, kThreads3, cand, s>>>(g, q, c0);
-                const int64_t nblk = ((nc * kGramSplit + 7) / 8) * 8;
-                gram3_kernel<<<(unsigned)nblk, 256, 0, s>>>(q, g.row_off, g.col, g.blocks, g.nnz, g.counters,
-                                                            (int)nc);
+                gram3_kernel<<<gblocks, 256, 0, s>>>(q, g.blocks, g.nnz, g.counters, (int)nc, ntmax);
             }
             return hipGetLastError();
         }
