@@ -298,7 +298,11 @@ int mlpg_integrate(mlpg_handle h, int rk_order, void *workspace, size_t ws_bytes
 /* Bytes of the integration workspace of handle h (after mlpg_geometry and any
  * mlpg_material_fields / mlpg_material_shells, which set the material
  * count): the blocks, the point-value matrix, the boundary quadrature and the
- * surface-row offsets.  0 before mlpg_geometry or for an invalid order. */
+ * surface-row offsets; in 3D with one material and no fields or shells also
+ * a region for the cells' weighted-value panels, whose Gram products are
+ * formed on the matrix cores a batch of cells at a time (up to 1024 cells of
+ * 2 MiB estimated each; a problem with larger panels takes smaller batches).
+ * 0 before mlpg_geometry or for an invalid order. */
 size_t mlpg_integrate_workspace_bytes(mlpg_handle h, int rk_order);
 
 /* Pattern and blocks for parity checks.  row_off: device [n+1]; col: device
