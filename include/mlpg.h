@@ -514,6 +514,11 @@ int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
  *   48 <= n_ord <= 64 with 6 or 10 streams, form 1 (stream values staged
  *     through LDS by the workgroup, two rounds deep): 4 or 8 waves (4 only
  *     for 10 FP64 streams), 2 or 4 rounds of one row per wave, xcd_split 8;
+ *   n_ord > 64 with 6 or 10 streams, form 2 (as form 0 with 2 or 4 adjacent
+ *     ordinates per lane, so that an item is a row and 128 or 256 ordinates;
+ *     n_ord a multiple of the count, and the count only where it makes fewer
+ *     items than half of it: 96 and 128 ordinates take 2, 256 take 2 or 4):
+ *     2, 4 or 8 waves, 1 item per wave, xcd_split 8 or 1;
  *   n_ord < 48: 128, 256 or 512 threads per workgroup.
  * mlpg_set_autotune(0) keeps the built-in shape (form 0, 4 waves, 1 item,
  * split 8; 256 threads) for shapes not yet in the table, (1) measures again
@@ -524,15 +529,17 @@ int mlpg_profile_end(double *ms, int64_t *launches, double *bytes);
  * entry->(n, n_ord, streams, value_bytes) (host struct; us_best and
  * us_default are stored as given), so that a table saved from one process
  * can be loaded into the next, or a shape pinned; MLPG_ERR_ARG for a shape
- * outside the ranges above (form 1: 4 or 8 waves, 1..64 rounds; form 0: 1..8
- * waves, 1..64 items; xcd_split 1 or 8; threads in [n_ord, 512]).
+ * outside the ranges above (form 1: 4 or 8 waves, 1..64 rounds; forms 0 and
+ * 2: 1..8 waves, 1..64 items; form 2: 2 or 4 ordinates per lane; xcd_split 1
+ * or 8; threads in [n_ord, 512]).
  * Process-wide; the table is guarded by a lock.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int64_t n;
     int n_ord, streams, value_bytes;
-    int form;                    /* 0 or 1 as above (0 for n_ord < 48) */
+    int form;                    /* 0, 1 or 2 as above (0 for n_ord < 48) */
     int waves_per_block, items_per_wave, rounds, xcd_split, threads;
+    int ords_per_lane;           /* form 2: 2 or 4; otherwise 1 */
     float us_best, us_default;   /* measured duration of the chosen and of the built-in shape */
 } mlpg_tune_entry;
 int mlpg_set_autotune(int mode);

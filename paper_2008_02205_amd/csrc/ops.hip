@@ -426,6 +426,186 @@ __global__ __launch_bounds__(512) void spmv_wave_kernel(SpmvK<T> k, const int64_
     }
 }
 
+// V adjacent ordinates of one lane, loaded as one aligned vector.
+template <class T, int V>
+struct alignas(sizeof(T) * V) Pack {
+    T v[V];
+};
+
+// xraw for the V ordinates m0 .. m0 + V - 1 of column j (one vector load per
+// input array; m0 and M multiples of V, the arrays aligned to V elements).
+template <int MODE, class T, int V>
+__device__ __forceinline__ void xraw_vec(const SpmvK<T> &k, int64_t j, int m0, T (&out)[V])
+{
+    if (MODE == IN_BCAST) {
+        const T b = k.x[j];
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = b;
+        return;
+    }
+    const int64_t o = j * k.M + m0;
+    const Pack<T, V> a = *(const Pack<T, V> *)(k.x + o);
+    if (MODE == IN_X2) {
+        const Pack<T, V> b = *(const Pack<T, V> *)(k.x2 + o);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T xv = k.xs * a.v[v];
+            xv += b.v[v];
+            out[v] = xv;
+        }
+    } else if (MODE == IN_DINV) {
+        const Pack<T, V> d = *(const Pack<T, V> *)(k.dinv + o);
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = a.v[v] * d.v[v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) out[v] = a.v[v];
+    }
+}
+
+// row_sum for V ordinates of one lane: the same per-stream (and per-face)
+// sums over the row's nonzeros in the same order, combined with each
+// ordinate's coefficients in the same order, so every ordinate's result is
+// the one row_sum gives.  One x gather of V values per nonzero, and the
+// row's stream values and columns read once for V ordinates.
+template <int NS, class T, int MODE, int V>
+__device__ __forceinline__ void row_sum_vec(const SpmvK<T> &k, const int32_t *__restrict__ cl,
+                                            const T *__restrict__ vl, const T *__restrict__ fv, int64_t p0,
+                                            int64_t p1, int64_t s0, int64_t s1, int m0, T (&acc)[V])
+{
+    constexpr int NF = FacesOf<NS>::value;
+    T t[V][NS];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int b = 0; b < NS; ++b) t[v][b] = 0;
+    const bool faces = s1 > s0 && s1 - s0 == p1 - p0 && k.nf == NF;   // uniform over the wave
+    if (faces) {
+        T uf[V][NF];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) uf[v][f] = 0;
+        const int64_t fofs = s0 - p0;
+        int64_t p = p0;
+        for (; p + 7 < p1; p += 8) {
+            int32_t jj[8];
+            T xx[8][V];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) jj[u] = cl[p + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xraw_vec<MODE, T, V>(k, jj[u], m0, xx[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+#pragma unroll
+                for (int b = 0; b < NS; ++b)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) t[v][b] += vl[(p + u) * NS + b] * xx[u][v];
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) uf[v][f] += fv[(p + u + fofs) * NF + f] * xx[u][v];
+            }
+        }
+        for (; p < p1; ++p) {
+            T xv[V];
+            xraw_vec<MODE, T, V>(k, cl[p], m0, xv);
+#pragma unroll
+            for (int b = 0; b < NS; ++b)
+#pragma unroll
+                for (int v = 0; v < V; ++v) t[v][b] += vl[p * NS + b] * xv[v];
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int v = 0; v < V; ++v) uf[v][f] += fv[(p + fofs) * NF + f] * xv[v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T a = 0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) a += k.coef[(m0 + v) * NS + b] * t[v][b];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) a += k.coefF[(m0 + v) * NF + f] * uf[v][f];
+            a *= xs_out<MODE>(k);
+            acc[v] = a;
+        }
+    } else {
+        int64_t p = p0;
+        for (; p + 7 < p1; p += 8) {
+            int32_t jj[8];
+            T xx[8][V];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) jj[u] = cl[p + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xraw_vec<MODE, T, V>(k, jj[u], m0, xx[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int b = 0; b < NS; ++b)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) t[v][b] += vl[(p + u) * NS + b] * xx[u][v];
+        }
+        for (; p < p1; ++p) {
+            T xv[V];
+            xraw_vec<MODE, T, V>(k, cl[p], m0, xv);
+#pragma unroll
+            for (int b = 0; b < NS; ++b)
+#pragma unroll
+                for (int v = 0; v < V; ++v) t[v][b] += vl[p * NS + b] * xv[v];
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            T a = 0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) a += k.coef[(m0 + v) * NS + b] * t[v][b];
+            a *= xs_out<MODE>(k);
+            if (s1 > s0) a += spmv_surface<MODE>(k, s0, s1, m0 + v);
+            acc[v] = a;
+        }
+    }
+}
+
+// Wave-per-row SpMV with V adjacent ordinates per lane (form 2, more than 64
+// ordinates): an item is a row and 64 V ordinates, so that a row of 96 or 128
+// ordinates is one item (two of 64 in spmv_wave_kernel) and its stream values
+// and columns are read once; each nonzero's x gather is one vector load per
+// lane.  Same sums as spmv_wave_kernel, ordinate by ordinate.
+template <int NS, class T, int MODE, int V>
+__global__ __launch_bounds__(512) void spmv_vec_kernel(SpmvK<T> k, const int64_t *__restrict__ row_off,
+                                                       const int32_t *__restrict__ col,
+                                                       const T *__restrict__ vals, const T *__restrict__ fv)
+{
+    if (k.gate && *k.gate == 0) return;
+    const int G = gridDim.x, X = k.nxcd;
+    const int bx = blockIdx.x;
+    const int per = G / X;
+    const int lb = (bx % X) * per + bx / X;
+    const int lane = threadIdx.x & 63;
+    constexpr int CW = 64 * V;
+    const int nchunk = (k.M + CW - 1) / CW;
+    const int64_t nitems = k.n * nchunk;
+    const int64_t i0 = (int64_t)lb * k.items_per_block;
+    const int64_t i1 = i0 + k.items_per_block < nitems ? i0 + k.items_per_block : nitems;
+    for (int64_t item = i0 + (threadIdx.x >> 6); item < i1; item += (blockDim.x >> 6)) {
+        const int64_t iu =
+            __builtin_amdgcn_readfirstlane((int)(nchunk == 1 ? item : item / nchunk));
+        const int chunk = (int)(item - iu * nchunk);
+        const int m0 = chunk * CW + V * lane;
+        const bool on = m0 < k.M;   // M is a multiple of V: all V ordinates or none
+        const int mm0 = on ? m0 : 0;
+        RowEnds<T> re[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) re[v] = row_ends(k, iu, mm0 + v);
+        const int64_t p0 = row_off[iu], p1 = row_off[iu + 1];
+        T acc[V];
+        row_sum_vec<NS, T, MODE, V>(k, col, vals, fv, p0, p1, re[0].s0, re[0].s1, mm0, acc);
+        if (on) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) spmv_finish(k, iu, m0 + v, acc[v], re[v]);
+        }
+    }
+}
+
 // LDS-staged sweep (at most 64 ordinates, so one item per row): a workgroup
 // of W waves owns a contiguous range of rows and walks it in rounds of W rows,
 // one row per wave.  The round's stream values and column indices (at most
@@ -680,8 +860,18 @@ hipError_t launch_jacobi(Problem &P, hipStream_t s)
 // problem's own operator and kept in a table (mlpg_get_tuning).
 struct SpmvShape {
     int form = 0;
-    int wpb = 4, ipw = 1, rounds = 1, xcd = 8, threads = 256;
+    int wpb = 4, ipw = 1, rounds = 1, xcd = 8, threads = 256, vec = 1;
 };
+
+// Form 2 (V ordinates per lane) applies to the transport operators when it
+// makes fewer (row, ordinate) items than V/2 ordinates per lane would (form 0
+// for V = 2): a multiple of V ordinates, more than 64 (96 and 128: V = 2;
+// 256: V = 2 or 4).
+static bool vec_form_fits(int M, int ns, int V)
+{
+    return (V == 2 || V == 4) && (ns == 6 || ns == 10) && M > 64 && M % V == 0 &&
+           (M + 64 * V - 1) / (64 * V) < (M + 32 * V - 1) / (32 * V);
+}
 
 // Form 1 applies to one 64-ordinate chunk per row and the 2D/3D transport
 // operators; its two LDS buffers (64 W nonzeros of values and columns each)
@@ -745,13 +935,21 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
     if (a.surface && (!a.sval || !a.coefF)) return hipErrorInvalidValue;
     const bool wave = M >= 48;
     const bool lds = sh.form == 1 && lds_form_fits(M, a.ns, sh.wpb, (int)sizeof(T));
+    // form 2 loads V ordinates of an input row at once: the inputs must be
+    // aligned to V elements (the solver's vectors are), and isotropic inputs
+    // (one value per row) keep form 0
+    const size_t va = sizeof(T) * (size_t)sh.vec;
+    const bool vecf = sh.form == 2 && wave && vec_form_fits(M, a.ns, sh.vec) && !a.x_bcast &&
+                      (uintptr_t)a.x % va == 0 && (uintptr_t)a.x2 % va == 0 && (uintptr_t)a.dinv % va == 0;
     unsigned blocks;
     int threads;
     if (wave) {
-        // sh.wpb waves per workgroup, each taking sh.ipw items (form 0) or one
-        // row in each of sh.rounds rounds (form 1); grid a multiple of the xcd count
+        // sh.wpb waves per workgroup, each taking sh.ipw items (forms 0 and 2)
+        // or one row in each of sh.rounds rounds (form 1); grid a multiple of
+        // the xcd count
         threads = 64 * sh.wpb;
-        const int64_t items = P.n * ((M + 63) / 64);
+        const int cw = vecf ? 64 * sh.vec : 64;
+        const int64_t items = P.n * ((M + cw - 1) / cw);
         const int64_t per_block = (int64_t)sh.wpb * (lds ? std::max(sh.rounds, 1) : sh.ipw);
         int64_t b = (items + per_block - 1) / per_block;
         b = ((b + sh.xcd - 1) / sh.xcd) * sh.xcd;
@@ -775,6 +973,9 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
 #define MLPG_SPMV_M(NSV, MD)                                                                       \
     if (wave) spmv_wave_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals, k.sval); \
     else spmv_group_kernel<NSV, T, MD><<<blocks, threads, 0, s>>>(k)
+#define MLPG_SPMV_V(NSV, MD)                                                                       \
+    if (sh.vec == 2) spmv_vec_kernel<NSV, T, MD, 2><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals, k.sval); \
+    else spmv_vec_kernel<NSV, T, MD, 4><<<blocks, threads, 0, s>>>(k, k.row_off, k.col, k.vals, k.sval)
 #define MLPG_SPMV(NSV, KER)                                                       \
     switch (mode) {                                                               \
     case IN_PLAIN: KER(NSV, IN_PLAIN); break;                                     \
@@ -785,6 +986,16 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
     if (lds) {
         if (a.ns == 6) { MLPG_SPMV(6, MLPG_SPMV_L); }
         else { MLPG_SPMV(10, MLPG_SPMV_L); }
+    } else if (vecf) {
+#define MLPG_SPMV_VM(NSV)                                                          \
+        switch (mode) {                                                            \
+        case IN_PLAIN: MLPG_SPMV_V(NSV, IN_PLAIN); break;                          \
+        case IN_DINV: MLPG_SPMV_V(NSV, IN_DINV); break;                            \
+        default: MLPG_SPMV_V(NSV, IN_X2); break;                                   \
+        }
+        if (a.ns == 6) { MLPG_SPMV_VM(6); }
+        else { MLPG_SPMV_VM(10); }
+#undef MLPG_SPMV_VM
     } else {
         switch (a.ns) {
         case 3: MLPG_SPMV(3, MLPG_SPMV_M); break;
@@ -795,6 +1006,7 @@ static hipError_t launch_spmv_shape(Problem &P, const SpmvArgsT<T> &a, const Spm
         }
     }
 #undef MLPG_SPMV
+#undef MLPG_SPMV_V
 #undef MLPG_SPMV_M
 #undef MLPG_SPMV_L
     return hipGetLastError();
@@ -852,6 +1064,14 @@ hipError_t tune_spmv(Problem &P, const SpmvArgsT<T> &a, const void *evict, size_
                     c.form = 1; c.wpb = wpb; c.rounds = rounds; c.xcd = 8;
                     cand.push_back(c);
                 }
+        for (int V : {2, 4})
+            if (vec_form_fits(P.n_ord, a.ns, V))
+                for (int wpb : {2, 4, 8})
+                    for (int xcd : {8, 1}) {
+                        SpmvShape c;
+                        c.form = 2; c.vec = V; c.wpb = wpb; c.xcd = xcd;
+                        cand.push_back(c);
+                    }
     } else {
         for (int th : {128, 256, 512}) {
             SpmvShape c;
@@ -920,10 +1140,11 @@ int get_tuning(int cap, mlpg_tune_entry *out)
         out[i].value_bytes = e.tbytes;
         out[i].form = wave ? e.shape.form : 0;
         out[i].waves_per_block = wave ? e.shape.wpb : 0;
-        out[i].items_per_wave = wave && e.shape.form == 0 ? e.shape.ipw : (wave ? 1 : 0);
+        out[i].items_per_wave = wave && e.shape.form != 1 ? e.shape.ipw : (wave ? 1 : 0);
         out[i].rounds = wave && e.shape.form == 1 ? e.shape.rounds : (wave ? 1 : 0);
         out[i].xcd_split = wave ? e.shape.xcd : 0;
         out[i].threads = wave ? 64 * e.shape.wpb : e.shape.threads;
+        out[i].ords_per_lane = wave && e.shape.form == 2 ? e.shape.vec : 1;
         out[i].us_best = e.us_best;
         out[i].us_default = e.us_default;
     }
@@ -951,8 +1172,16 @@ std::string set_tuning(const mlpg_tune_entry &t)
                        "and 1..64 rounds";
             sh.wpb = t.waves_per_block;
             sh.rounds = t.rounds;
+        } else if (t.form == 2) {
+            if (!vec_form_fits(t.n_ord, t.streams, t.ords_per_lane) || t.waves_per_block < 1 ||
+                t.waves_per_block > 8 || t.items_per_wave < 1 || t.items_per_wave > 64)
+                return "form 2 needs 6 or 10 streams, 2 or 4 ordinates per lane dividing n_ord > 64 into fewer "
+                       "items than form 0, 1..8 waves per block and 1..64 items per wave";
+            sh.wpb = t.waves_per_block;
+            sh.ipw = t.items_per_wave;
+            sh.vec = t.ords_per_lane;
         } else {
-            return "form must be 0 or 1";
+            return "form must be 0, 1 or 2";
         }
     } else {
         if (t.threads < t.n_ord || t.threads > 512) return "threads must be in [n_ord, 512]";

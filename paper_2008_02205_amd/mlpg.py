@@ -57,7 +57,8 @@ class SolveOpts(C.Structure):
 class TuneEntry(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_ord", C.c_int), ("streams", C.c_int), ("value_bytes", C.c_int),
                 ("form", C.c_int), ("waves_per_block", C.c_int), ("items_per_wave", C.c_int), ("rounds", C.c_int),
-                ("xcd_split", C.c_int), ("threads", C.c_int), ("us_best", C.c_float), ("us_default", C.c_float)]
+                ("xcd_split", C.c_int), ("threads", C.c_int), ("ords_per_lane", C.c_int), ("us_best", C.c_float),
+                ("us_default", C.c_float)]
 
 
 class SolveInfo(C.Structure):

@@ -115,11 +115,22 @@ def test_tuning_table_entries_round_trip_and_are_validated(lib):
         mlpg.mlpg_set_tuning(dict(n=777, n_ord=16, streams=3, value_bytes=4, threads=256))
         small = [e for e in mlpg.mlpg_get_tuning() if e["n_ord"] == 16]
         assert small[0]["threads"] == 256 and small[0]["form"] == 0
+        wide = dict(n=777, n_ord=96, streams=10, value_bytes=8, xcd_split=1)
+        mlpg.mlpg_set_tuning(dict(wide, form=2, waves_per_block=4, items_per_wave=1, ords_per_lane=2))
+        t = [e for e in mlpg.mlpg_get_tuning() if e["n_ord"] == 96][0]
+        assert (t["form"], t["ords_per_lane"], t["waves_per_block"], t["xcd_split"]) == (2, 2, 4, 1)
+        mlpg.mlpg_set_tuning(t)   # an entry read back is accepted as it is
+        assert [e for e in mlpg.mlpg_get_tuning() if e["n_ord"] == 96] == [t]
         bad = [dict(base, form=1, waves_per_block=2, rounds=2),           # form 1 needs 4 or 8 waves
                dict(base, form=1, waves_per_block=4, rounds=0),           # rounds >= 1
                dict(base, n_ord=96, form=1, waves_per_block=4, rounds=2),  # form 1 needs <= 64 ordinates
                dict(base, streams=3, form=1, waves_per_block=4, rounds=2),
                dict(base, form=2, waves_per_block=4),
+               dict(base, form=2, waves_per_block=4, items_per_wave=1, ords_per_lane=2),   # 64 ordinates: no gain
+               dict(wide, form=2, waves_per_block=4, items_per_wave=1, ords_per_lane=4),   # 96 / 4 not fewer items
+               dict(wide, form=2, waves_per_block=4, items_per_wave=1, ords_per_lane=3),
+               dict(wide, streams=4, form=2, waves_per_block=4, items_per_wave=1, ords_per_lane=2),
+               dict(base, form=3, waves_per_block=4, items_per_wave=1),
                dict(base, form=0, waves_per_block=16, items_per_wave=1),
                dict(base, form=0, waves_per_block=4, items_per_wave=1, xcd_split=4),
                dict(base, streams=5, form=0, waves_per_block=4, items_per_wave=1),
@@ -129,6 +140,6 @@ def test_tuning_table_entries_round_trip_and_are_validated(lib):
         for b in bad:
             with pytest.raises(mlpg.MlpgError):
                 mlpg.mlpg_set_tuning(b)
-        assert len([e for e in mlpg.mlpg_get_tuning() if e["n"] == 777]) == 2
+        assert len([e for e in mlpg.mlpg_get_tuning() if e["n"] == 777]) == 3
     finally:
         mlpg.mlpg_set_autotune(2)
