@@ -217,7 +217,9 @@ def main():
                                           "GB_s": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                                       for k, v in prof.items()},
                    "rel_l1_phi_vs_manufactured": err},
-        "roofline": roofline(prof, counters=main_name == "fp64"),
+        "roofline": roofline(prof, shape=next((e for e in mlpg.mlpg_get_tuning()
+                                               if (e["n"], e["n_ord"], e["streams"], e["value_bytes"]) ==
+                                               (n, M, 6, 8)), None) if main_name == "fp64" else None),
         "cpu_baseline": None,
     }
     if "mixed" in runs and main_name != "mixed":
@@ -233,7 +235,7 @@ def main():
             "refinements_per_step": tot2["refinements"] / max(args.steps, 1),
             "fp64_completions_per_step": tot2["fp64_completions"] / max(args.steps, 1),
             "rel_l2_phi_point_vs_fp64": float(np.linalg.norm(pv2_np - pv_np) / np.linalg.norm(pv_np)),
-            "roofline": roofline(prof2, counters=False)}
+            "roofline": roofline(prof2)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"], X, k = cpu_baseline(w, x, R, dx, om, wq, args.cpu_ordinates)
         rec["detail"]["error_vs_oracle"] = oracle_error(w, x, R, dx, om, wq, psi0, X, k)
@@ -508,11 +510,13 @@ def serve(args):
     print(json.dumps(rec), flush=True)
 
 
-def roofline(prof, counters=True):
+def roofline(prof, shape=None):
     """Dominant kernel class of the profiled step against the HBM peak.
 
     achieved = algorithmic bytes per launch (each operand once; see the
-    per-class byte model in the library) / average launch duration."""
+    per-class byte model in the library) / average launch duration.  With
+    `shape` (the sweep's tuned launch shape), traffic is the counters' HBM
+    bytes per launch of the sweep in that shape."""
     name = max(prof, key=lambda k: prof[k]["ms"])
     v = prof[name]
     if v["launches"] == 0 or v["ms"] <= 0:
@@ -520,26 +524,39 @@ def roofline(prof, counters=True):
     avg_s = v["ms"] * 1e-3 / v["launches"]
     per_launch = v["bytes"] / v["launches"]
     achieved = per_launch / avg_s / 1e9
+    traffic, key = measured_traffic(shape) if shape and name == "spmv_L" else (None, None)
     return {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic() if counters and name == "spmv_L" else None,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "traffic_shape": key,
             "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": per_launch}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the operator sweep (FETCH_SIZE and WRITE_SIZE
-    scaled against a copy of known size), or None when the kernel source has
-    changed since the counters were taken."""
+def shape_key(e):
+    """The counters file's key of a launch-shape table entry."""
+    if e["form"] == 1:
+        return f"form=1 waves={e['waves_per_block']} rounds={e['rounds']} xcd={e['xcd_split']}"
+    if e["form"] == 2:
+        return (f"form=2 ords={e['ords_per_lane']} waves={e['waves_per_block']} items={e['items_per_wave']} "
+                f"xcd={e['xcd_split']}")
+    return f"form=0 waves={e['waves_per_block']} items={e['items_per_wave']} xcd={e['xcd_split']}"
+
+
+def measured_traffic(shape):
+    """HBM bytes per launch of the operator sweep in launch shape `shape` (FETCH_SIZE and WRITE_SIZE
+    scaled against a copy of known size) and the shape's key, or (None, key) when the kernel source has
+    changed since the counters were taken or the shape was not measured."""
     import hashlib
+    key = shape_key(shape)
     try:
         txt = open(COUNTERS).read()
         src = hashlib.sha256(open(SPMV_SOURCE, "rb").read()).hexdigest()
     except OSError:
-        return None
-    kv = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith(("source_sha256:",
-                                                                                   "traffic_bytes_per_launch:")))
+        return None, key
+    kv = dict(line.split(": ", 1) for line in txt.splitlines()
+              if line.startswith(("source_sha256:", "traffic_bytes_per_launch ")))
     if kv.get("source_sha256", "").strip() != src:
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+        return None, key
+    v = kv.get("traffic_bytes_per_launch " + key)
+    return (float(v) if v is not None else None), key
 
 
 def cpu_baseline(w, x, R, dx, om, wq, k, min_seconds=10.0):
