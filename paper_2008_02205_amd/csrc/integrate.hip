@@ -356,6 +356,34 @@ __global__ void cand_count_kernel(int64_t n, const double *__restrict__ x, const
     cnt[c] = k;
 }
 
+// Thread 0 of a cell's workgroup: the functions whose support can reach
+// cell c (the generator first, then the overlap neighbours within R_j +
+// rho_c) into the LDS arrays; A = -1 when more than g.amax.
+__device__ void stage_cell2(const IntegArgs &g, int64_t c, double xc0, double xc1, double *sx, double *sR,
+                            double *sV, int32_t *sidx, int *sA)
+{
+    const int amax = g.amax;
+    int A = 0;
+    double rc = g.rho[c];
+    sidx[A] = (int32_t)c; sx[0] = xc0; sx[1] = xc1; sR[0] = g.R[c]; sV[0] = g.V[c]; A = 1;
+    for (int64_t p = g.nb_off[c]; p < g.nb_off[c + 1]; ++p) {
+        int32_t j = g.nb_idx[p];
+        double d0 = g.x[2 * (int64_t)j] - xc0, d1 = g.x[2 * (int64_t)j + 1] - xc1;
+        double lim = g.R[j] + rc;
+        if (d0 * d0 + d1 * d1 < lim * lim) {
+            if (A >= amax) { A = -1; break; }
+            sidx[A] = j;
+            sx[2 * A] = g.x[2 * (int64_t)j];
+            sx[2 * A + 1] = g.x[2 * (int64_t)j + 1];
+            sR[A] = g.R[j];
+            sV[A] = g.V[j];
+            A++;
+        }
+    }
+    if (A < 0) atomicAdd(&g.counters[kOverflow], 1ull);
+    *sA = A;
+}
+
 template <int ORD, bool FIELDS>
 __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
 {
@@ -372,27 +400,7 @@ __global__ __launch_bounds__(kThreads) void integrate2d_kernel(IntegArgs g)
     const int64_t c = blockIdx.x;
     const double xc0 = g.x[2 * c], xc1 = g.x[2 * c + 1];
     const double hs = 0.5 * g.R[c];
-    if (threadIdx.x == 0) {
-        int A = 0;
-        double rc = g.rho[c];
-        sidx[A] = (int32_t)c; sx[0] = xc0; sx[1] = xc1; sR[0] = g.R[c]; sV[0] = g.V[c]; A = 1;
-        for (int64_t p = g.nb_off[c]; p < g.nb_off[c + 1]; ++p) {
-            int32_t j = g.nb_idx[p];
-            double d0 = g.x[2 * (int64_t)j] - xc0, d1 = g.x[2 * (int64_t)j + 1] - xc1;
-            double lim = g.R[j] + rc;
-            if (d0 * d0 + d1 * d1 < lim * lim) {
-                if (A >= amax) { A = -1; break; }
-                sidx[A] = j;
-                sx[2 * A] = g.x[2 * (int64_t)j];
-                sx[2 * A + 1] = g.x[2 * (int64_t)j + 1];
-                sR[A] = g.R[j];
-                sV[A] = g.V[j];
-                A++;
-            }
-        }
-        if (A < 0) atomicAdd(&g.counters[kOverflow], 1ull);
-        sA = A;
-    }
+    if (threadIdx.x == 0) stage_cell2(g, c, xc0, xc1, sx, sR, sV, sidx, &sA);
     __syncthreads();
     const int A = sA;
     if (A <= 0) return;
@@ -1232,6 +1240,37 @@ struct GramArgs {
     unsigned *queue;    // one task counter per XCD, 64 bytes apart (zeroed by the panel kernel)
 };
 
+// CSR positions of every pair of a cell's candidates, relative to the row
+// start (-1: not in the pattern), into tab [amax][amax] (int32), then the row
+// starts (int64 [amax]): each candidate's row merged with the candidates in
+// global order (the overlap list is ascending; the generator, candidate 0,
+// goes in at its place).  All threads of the workgroup.
+__device__ void gram_positions(const int64_t *__restrict__ row_off, const int32_t *__restrict__ col,
+                               const int32_t *sidx, int A, int64_t c, int amax, double *tab)
+{
+    int32_t *rel = (int32_t *)tab;
+    int64_t *rstart = (int64_t *)(tab + ((int64_t)amax * amax + 1) / 2);
+    int lo = 1, hi = A;   // first candidate after the generator in global order
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sidx[mid] < (int32_t)c) lo = mid + 1;
+        else hi = mid;
+    }
+    const int p0 = lo - 1;
+    for (int a = threadIdx.x; a < A; a += blockDim.x) {
+        const int64_t r0 = row_off[sidx[a]], r1 = row_off[sidx[a] + 1];
+        rstart[a] = r0;
+        int32_t *ra = rel + (int64_t)a * amax;
+        int64_t p = r0;
+        for (int k = 0; k < A; ++k) {
+            const int b = k < p0 ? k + 1 : (k == p0 ? 0 : k);
+            const int32_t j = sidx[b];
+            while (p < r1 && col[p] < j) ++p;
+            ra[b] = (p < r1 && col[p] == j) ? (int32_t)(p - r0) : -1;
+        }
+    }
+}
+
 // Boundary terms of a cell for the panel kernel (the same quantities as
 // integ3_boundary).  Every boundary point (one per thread) writes its row of
 // the boundary table and its weighted values sqrt(w) N_a into the surface
@@ -1404,33 +1443,7 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_panels_kernel(Integ3Arg
     if (blockIdx.x == 0 && threadIdx.x < 8) q.queue[16 * threadIdx.x] = 0u;
     const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
     double *Fs = q.F + (int64_t)slot * q.slot;
-    // CSR positions of every candidate pair, relative to the row start (-1:
-    // not in the pattern): each candidate's row merged with the candidates in
-    // global order (the overlap list is ascending; the generator, candidate
-    // 0, goes in at its place)
-    {
-        int32_t *rel = (int32_t *)(Fs + q.toff);
-        int64_t *rstart = (int64_t *)(Fs + q.toff + ((int64_t)amax * amax + 1) / 2);
-        int lo = 1, hi = A;   // first candidate after the generator in global order
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sidx[mid] < (int32_t)c) lo = mid + 1;
-            else hi = mid;
-        }
-        const int p0 = lo - 1;
-        for (int a = threadIdx.x; a < A; a += blockDim.x) {
-            const int64_t r0 = g.row_off[sidx[a]], r1 = g.row_off[sidx[a] + 1];
-            rstart[a] = r0;
-            int32_t *ra = rel + (int64_t)a * amax;
-            int64_t p = r0;
-            for (int k = 0; k < A; ++k) {
-                const int b = k < p0 ? k + 1 : (k == p0 ? 0 : k);
-                const int32_t j = sidx[b];
-                while (p < r1 && g.col[p] < j) ++p;
-                ra[b] = (p < r1 && g.col[p] == j) ? (int32_t)(p - r0) : -1;
-            }
-        }
-    }
+    gram_positions(g.row_off, g.col, sidx, A, c, amax, Fs + q.toff);
     for (int t = threadIdx.x; t < nq4; t += blockDim.x) {
         double y[3] = {xc[0], xc[1], xc[2]};
         double w = 0.0;
@@ -1488,11 +1501,13 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src)
 }
 
 // Block index of the entry (value u of row function, value v of column
-// function) at the row's CSR position: 0 for N N, u for dN_u N, and
-// 4 + 3(u-1) + (v-1) for dN_u dN_v (u, v = 1..3 for x, y, z).
+// function) at the row's CSR position (one material): 0 for N N, u for
+// dN_u N, and 1 + DIM + DIM (u-1) + (v-1) for dN_u dN_v (u, v = 1..DIM for
+// x, y, z).
+template <int DIM>
 __device__ __forceinline__ int gram_block(int u, int v)
 {
-    return v == 0 ? u : 4 + 3 * (u - 1) + (v - 1);
+    return v == 0 ? u : 1 + DIM + DIM * (u - 1) + (v - 1);
 }
 
 // One 64 x 64 tile (I, J), I <= J, of a cell's G: 16 x 16 candidate pairs.
@@ -1550,8 +1565,9 @@ __device__ __forceinline__ void gram_tile(const double *__restrict__ Fs, int ipa
 // registers), forms the tile, and adds each entry of the upper triangle to its
 // block (twice when the mirrored entry belongs to another block or position).
 // Every wave leaves once its queue is drained.
-__global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, double *blocks, int64_t nnz,
-                                                       unsigned long long *counters, int nslot, int ntmax)
+template <int DIM>
+__device__ __forceinline__ void gram_products(const GramArgs &q, double *blocks, int64_t nnz,
+                                              unsigned long long *counters, int nslot, int ntmax)
 {
     const int x = blockIdx.x & 7;
     const int lane = threadIdx.x & 63;
@@ -1617,15 +1633,21 @@ __global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, double *block
                     const bool bwd = i != j && (v >= 1 || u == 0);
                     if (fwd) {
                         if (pab < 0) atomicAdd(&counters[kMissing], 1ull);
-                        else atomicAdd(&blocks[(int64_t)gram_block(u, v) * nnz + pab], val);
+                        else atomicAdd(&blocks[(int64_t)gram_block<DIM>(u, v) * nnz + pab], val);
                     }
                     if (bwd) {
                         if (pba < 0) atomicAdd(&counters[kMissing], 1ull);
-                        else atomicAdd(&blocks[(int64_t)gram_block(v, u) * nnz + pba], val);
+                        else atomicAdd(&blocks[(int64_t)gram_block<DIM>(v, u) * nnz + pba], val);
                     }
                 }
             }
     }
+}
+
+__global__ __launch_bounds__(256, 2) void gram3_kernel(GramArgs q, double *blocks, int64_t nnz,
+                                                       unsigned long long *counters, int nslot, int ntmax)
+{
+    gram_products<3>(q, blocks, nnz, counters, nslot, ntmax);
 }
 
 hipError_t upload_rules3(hipStream_t s)
@@ -1668,6 +1690,35 @@ static FieldSet field_set(const Problem &P)
         F.shell_mat[r] = P.shell_mat[r];
     }
     return F;
+}
+
+// The Gram panel region of the integration workspace carved for a batch of
+// cells: per slot the volume panel (quadrature points rounded up to 4 rows of
+// 4 amax values rounded up to 64), the surface panel [boundary points][amax],
+// the position table; then the slots' metadata and the product kernel's
+// queue counters.  *nb = cells per batch (0: not even one slot fits).
+static hipError_t gram_layout(Problem &P, int amax, int nqmax, int nbqmax, GramArgs *q, int64_t *nb)
+{
+    const int ipad = ((4 * amax + 63) / 64) * 64;
+    const int64_t rows = (nqmax + 3) & ~3;
+    const int64_t soff = rows * ipad;
+    const int64_t toff = soff + (int64_t)nbqmax * amax;
+    const size_t panel = sizeof(double) * ((size_t)toff + ((size_t)amax * amax + 1) / 2 + (size_t)amax);
+    const size_t per = panel + 2 * sizeof(int32_t);
+    const size_t region = P.gram_ws.count;
+    *nb = region > 2048 ? std::min<int64_t>(P.n, (int64_t)((region - 2048) / per)) : 0;
+    if (*nb < 1) return hipSuccess;
+    char *base = P.gram_ws.p;
+    q->F = (double *)base;
+    q->slot = (int64_t)(panel / sizeof(double));
+    q->soff = soff;
+    q->toff = toff;
+    q->ipad = ipad;
+    q->amax = amax;
+    const size_t moff = (panel * *nb + 255) & ~(size_t)255;
+    q->meta = (int32_t *)(base + moff);
+    q->queue = (unsigned *)(base + ((moff + 2 * sizeof(int32_t) * *nb + 255) & ~(size_t)255));
+    return hipSuccess;
 }
 
 hipError_t launch_integrate2d(Problem &P, hipStream_t s)
@@ -1779,29 +1830,13 @@ hipError_t launch_integrate3d(Problem &P, hipStream_t s)
         int nqmax = 1, nbqmax = 0;
         for (int32_t v : h) nqmax = v > nqmax ? v : nqmax;
         for (int32_t v : hb) nbqmax = v > nbqmax ? v : nbqmax;
-        const int ipad = ((4 * amax + 63) / 64) * 64;
-        const int64_t rows = (nqmax + 3) & ~3;
-        const int64_t soff = rows * ipad;
-        const int64_t toff = soff + (int64_t)nbqmax * amax;
-        const size_t panel = sizeof(double) * ((size_t)toff + ((size_t)amax * amax + 1) / 2 + (size_t)amax);
-        const size_t per = panel + 2 * sizeof(int32_t);
-        const size_t region = P.gram_ws.count;
-        const int64_t nb = region > 2048 ? std::min<int64_t>(P.n, (int64_t)((region - 2048) / per)) : 0;
+        GramArgs q;
+        int64_t nb = 0;
+        if ((e = gram_layout(P, amax, nqmax, nbqmax, &q, &nb)) != hipSuccess) return e;
         if (nb >= 1) {
-            GramArgs q;
-            char *base = P.gram_ws.p;
-            q.F = (double *)base;
-            q.slot = (int64_t)(panel / sizeof(double));
-            q.soff = soff;
-            q.toff = toff;
-            q.ipad = ipad;
-            q.amax = amax;
-            const size_t moff = (panel * nb + 255) & ~(size_t)255;
-            q.meta = (int32_t *)(base + moff);
-            q.queue = (unsigned *)(base + ((moff + 2 * sizeof(int32_t) * nb + 255) & ~(size_t)255));
             int ncu = 0;
             if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-            const int tmax = ipad / 64;
+            const int tmax = q.ipad / 64;
             const int ntmax = tmax * (tmax + 1) / 2;
             const unsigned gblocks = (unsigned)(((std::max(ncu, 8) * 2) + 7) / 8 * 8);
             const size_t cand = sizeof(double) * (5 * amax + (amax + 1) / 2) + 2 * sizeof(int32_t) * amax;
