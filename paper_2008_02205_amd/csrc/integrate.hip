@@ -1432,6 +1432,8 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_panels_kernel(Integ3Arg
     __syncthreads();
     const int A = sA;
     int32_t *meta = q.meta + 2 * (int64_t)slot;
+    // the product kernel's task counters start at zero for every batch
+    if (blockIdx.x == 0 && threadIdx.x < 8) q.queue[16 * threadIdx.x] = 0u;
     if (A <= 0) {
         if (threadIdx.x == 0) { meta[0] = 0; meta[1] = 0; }
         return;
@@ -1440,7 +1442,6 @@ __global__ __launch_bounds__(kThreads3) void integrate3d_panels_kernel(Integ3Arg
     const int nq4 = (nq + 3) & ~3;
     const int width = ((4 * A + 63) >> 6) << 6;
     if (threadIdx.x == 0) { meta[0] = A; meta[1] = nq; }
-    if (blockIdx.x == 0 && threadIdx.x < 8) q.queue[16 * threadIdx.x] = 0u;
     const double *fvc = g.fverts + c * kFaceCap3 * kFaceVerts3 * 3;
     double *Fs = q.F + (int64_t)slot * q.slot;
     gram_positions(g.row_off, g.col, sidx, A, c, amax, Fs + q.toff);
