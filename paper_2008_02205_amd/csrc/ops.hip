@@ -467,13 +467,21 @@ __device__ __forceinline__ void xraw_vec(const SpmvK<T> &k, int64_t j, int m0, T
 // sums over the row's nonzeros in the same order, combined with each
 // ordinate's coefficients in the same order, so every ordinate's result is
 // the one row_sum gives.  One x gather of V values per nonzero, and the
-// row's stream values and columns read once for V ordinates.
+// row's stream values and columns read once for V ordinates.  The gathers
+// of VB nonzeros are issued together (VecBatch: 4 where the accumulators of
+// 10 FP64 streams for 2 ordinates would otherwise cost a wave per SIMD).
+template <int NS, class T, int V>
+struct VecBatch {
+    static constexpr int value = (NS == 10 && V == 2 && sizeof(T) == 8) ? 4 : 8;
+};
+
 template <int NS, class T, int MODE, int V>
 __device__ __forceinline__ void row_sum_vec(const SpmvK<T> &k, const int32_t *__restrict__ cl,
                                             const T *__restrict__ vl, const T *__restrict__ fv, int64_t p0,
                                             int64_t p1, int64_t s0, int64_t s1, int m0, T (&acc)[V])
 {
     constexpr int NF = FacesOf<NS>::value;
+    constexpr int VB = VecBatch<NS, T, V>::value;
     T t[V][NS];
 #pragma unroll
     for (int v = 0; v < V; ++v)
@@ -488,15 +496,15 @@ __device__ __forceinline__ void row_sum_vec(const SpmvK<T> &k, const int32_t *__
             for (int f = 0; f < NF; ++f) uf[v][f] = 0;
         const int64_t fofs = s0 - p0;
         int64_t p = p0;
-        for (; p + 7 < p1; p += 8) {
-            int32_t jj[8];
-            T xx[8][V];
+        for (; p + VB - 1 < p1; p += VB) {
+            int32_t jj[VB];
+            T xx[VB][V];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) jj[u] = cl[p + u];
+            for (int u = 0; u < VB; ++u) jj[u] = cl[p + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xraw_vec<MODE, T, V>(k, jj[u], m0, xx[u]);
+            for (int u = 0; u < VB; ++u) xraw_vec<MODE, T, V>(k, jj[u], m0, xx[u]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < VB; ++u) {
 #pragma unroll
                 for (int b = 0; b < NS; ++b)
 #pragma unroll
@@ -531,15 +539,15 @@ __device__ __forceinline__ void row_sum_vec(const SpmvK<T> &k, const int32_t *__
         }
     } else {
         int64_t p = p0;
-        for (; p + 7 < p1; p += 8) {
-            int32_t jj[8];
-            T xx[8][V];
+        for (; p + VB - 1 < p1; p += VB) {
+            int32_t jj[VB];
+            T xx[VB][V];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) jj[u] = cl[p + u];
+            for (int u = 0; u < VB; ++u) jj[u] = cl[p + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xraw_vec<MODE, T, V>(k, jj[u], m0, xx[u]);
+            for (int u = 0; u < VB; ++u) xraw_vec<MODE, T, V>(k, jj[u], m0, xx[u]);
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < VB; ++u)
 #pragma unroll
                 for (int b = 0; b < NS; ++b)
 #pragma unroll
