@@ -78,3 +78,70 @@ def test_asteroid_solve_matches_oracle(precision):
     print(f"phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} ordinates {om_g.shape[0]}", flush=True)
     assert max(e) <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
     P.close()
+
+
+# The graded point set of Sec. 5.4 (quadtree leaves at the paper's spacing, per-point radii and SUPG
+# lengths), coarsened so that the oracle finishes in seconds.
+
+def test_graded_stages_match_oracle():
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    a = W.asteroid(0.1)
+    x, R, L = W.asteroid_graded_points(a, 4.0)
+    shells, st, ss = W.asteroid_materials(a)
+    print(f"[case] graded asteroid stages n={x.shape[0]}", flush=True)
+    g = oracle.geometry(x, R, a.lo, a.hi)
+    it = oracle.integrate(g, 1, n_mat=2, shells=shells)
+    P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
+    assert np.array_equal(_cpu(P.nbr_off), g.nb_off)
+    assert np.array_equal(_cpu(P.nbr_idx), g.nb_idx)
+    V = _cpu(mlpg.mlpg_get_volumes(P.h, P.n))
+    assert np.abs(V - g.V).max() <= 1e-13 * g.V.max()
+    info = P.integrate(1)
+    assert info["missing_pairs"] == 0 and info["fallback_qps"] == it.fallbacks
+    row_off, col = mlpg.mlpg_get_pattern(P.h, P.n, info["nnz"])
+    assert np.array_equal(_cpu(row_off), g.row_off) and np.array_equal(_cpu(col), g.col)
+    blocks, E = mlpg.mlpg_get_blocks(P.h, info["n_blocks"], info["nnz"])
+    blocks, E = _cpu(blocks), _cpu(E)
+    for b, name in enumerate(oracle.block_names(2, 2)):
+        ref = it.blocks[b]
+        assert np.abs(blocks[b] - ref).max() <= 1e-12 * np.abs(ref).max(), name
+    assert np.abs(E - it.E).max() <= 1e-12 * np.abs(it.E).max()
+    P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graded_asteroid_step_matches_oracle(precision):
+    """One backward-Euler step from zero radiation, long enough to cross the domain (Sec. 5.4), on the
+    graded points at ten times the paper's spacing.  The shell's cross section is scaled down by the
+    same factor, so that a point spacing in the shell is as many mean free paths thick as in the
+    full-size problem (the shell is then 2 instead of 20 mean free paths thick)."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    coarsen = 10.0
+    base = W.asteroid(0.1)
+    a = dataclasses.replace(base, sigma_shell=base.sigma_shell / coarsen)
+    x, R, L = W.asteroid_graded_points(a, coarsen)
+    shells, st, ss = W.asteroid_materials(a)
+    a0 = W.asteroid_step_inv_c_dt(a)
+    print(f"[case] graded asteroid step n={x.shape[0]} {precision}", flush=True)
+    om_o, w_o = oracle.refined_quadrature(0, 6, a.src, (0.0, 0.0), a.radius)
+    om_g, w_g = mlpg.mlpg_refined_quadrature(0, 6, a.src, (0.0, 0.0), a.radius)
+    g = oracle.geometry(x, R, a.lo, a.hi)
+    it = oracle.integrate(g, 1, n_mat=2, shells=shells)
+    tr = oracle.Transport(it, om_o, w_o, st, ss, a0, L, opts=oracle.SolveOpts(max_in=20000))
+    psi_o, phi_o, info_o = tr.step(None, W.asteroid_source(a, x, om_o.shape[0]))
+    assert info_o["inner_res_max"] <= 1e-12
+    P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
+    P.integrate(1)
+    P.assemble(om_g, w_g, list(st), list(ss), a0, torch.from_numpy(L).cuda(),
+               precision=mlpg.MLPG_FP64 if precision == "fp64" else mlpg.MLPG_MIXED)
+    q = torch.from_numpy(np.ascontiguousarray(W.asteroid_source(a, x, om_g.shape[0]))).cuda()
+    opts = mlpg.mlpg_default_opts()
+    opts.max_inner = 20000
+    phi, pv, psi, info = P.step(q, None, opts)
+    assert info["converged"] == 1
+    e = (rel_l2(_cpu(phi), phi_o), rel_l2(_cpu(pv), tr.point_values(phi_o)), rel_l2(_cpu(psi), psi_o))
+    print(f"phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} ordinates {om_g.shape[0]}", flush=True)
+    assert max(e) <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
+    P.close()

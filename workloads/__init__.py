@@ -8,7 +8,10 @@ workload.  Both the oracle and the HIP path receive exactly these arrays.
 
 Point placement follows the paper's Results section: a uniform lattice
 whose points are perturbed by up to 0.2 times the spacing in each
-dimension, independently per point and dimension.
+dimension, independently per point and dimension.  The asteroid problem
+(Sec. 5.4) grades its spacing with the distance to the shell and to the
+source; its points are the jittered leaves of a quadtree refined to that
+spacing.
 """
 from __future__ import annotations
 
@@ -360,12 +363,14 @@ def chord_in_circle(src: np.ndarray, xe: np.ndarray, radius: float) -> np.ndarra
     return np.where(ok, (s1 - s0) * np.sqrt(l2), 0.0)
 
 
-def asteroid_optical_depth(a: Asteroid, x: np.ndarray) -> np.ndarray:
-    """omega = integral of sigma_a from the source centre to each point (straight ray)."""
+def asteroid_optical_depth(a: Asteroid, x: np.ndarray, extra: float = 0.0) -> np.ndarray:
+    """omega = integral of sigma_a from the source centre to each point (straight ray), with a
+    uniform absorption ``extra`` added everywhere (a backward-Euler step from zero radiation adds
+    1/(c dt) to sigma_a)."""
     src = np.asarray(a.src, dtype=np.float64)
     r = np.sqrt(np.sum((x - src[None, :]) ** 2, axis=1))
     in_shell = chord_in_circle(src, x, a.radius) - chord_in_circle(src, x, a.radius - a.thickness)
-    return a.sigma_back * (r - in_shell) + a.sigma_shell * in_shell
+    return a.sigma_back * (r - in_shell) + a.sigma_shell * in_shell + extra * r
 
 
 def asteroid_phi_paper(a: Asteroid, x: np.ndarray) -> np.ndarray:
@@ -377,12 +382,14 @@ def asteroid_phi_paper(a: Asteroid, x: np.ndarray) -> np.ndarray:
     return (np.exp(-om) - om * e1) / r
 
 
-def asteroid_phi_ordinates(a: Asteroid, x: np.ndarray, xi: np.ndarray, wp: np.ndarray) -> np.ndarray:
+def asteroid_phi_ordinates(a: Asteroid, x: np.ndarray, xi: np.ndarray, wp: np.ndarray,
+                           extra: float = 0.0) -> np.ndarray:
     """Scalar flux of a line source of the asteroid's strength seen through polar levels with cosines
     xi and weights wp (folded: 2 wp each) and a continuum of azimuths: along the in-plane ray of length
-    r the path is r / sin(theta), so phi = S / (4 pi r) sum_p 2 wp_p exp(-omega / st_p) / st_p."""
+    r the path is r / sin(theta), so phi = S / (4 pi r) sum_p 2 wp_p exp(-omega / st_p) / st_p, with
+    the optical depth omega of ``asteroid_optical_depth`` (``extra`` as there)."""
     r = np.sqrt(np.sum((x - np.asarray(a.src)[None, :]) ** 2, axis=1))
-    om = asteroid_optical_depth(a, x)
+    om = asteroid_optical_depth(a, x, extra)
     st = np.sqrt(1.0 - np.asarray(xi) ** 2)
     tot = sum(2.0 * w * np.exp(-om / t) / t for w, t in zip(wp, st))
     return a.strength / (4.0 * np.pi * r) * tot
@@ -393,6 +400,111 @@ def asteroid_points(a: Asteroid, spacing: float, seed: int = SEED_BASE + 9, jitt
     counts = [max(2, int(round((h - l) / spacing))) for l, h in zip(a.lo, a.hi)]
     x, dx = jittered_lattice(counts, a.lo, a.hi, jitter, seed)
     return x, np.full(x.shape[0], 2.0 * dx), dx
+
+
+def asteroid_spacing(a: Asteroid, x: np.ndarray, coarsen: float = 1.0) -> np.ndarray:
+    """Target point spacing h(x) of Sec. 5.4, in the paper's units times the workload's scale s:
+    0.2 s on the shell's inner surface, 0.1 s on its outer surface (linear across the shell), 0.1 s at
+    the source, 1.0 s halfway (35 s) between the source and the asteroid.  Away from the shell and from
+    the source h grows linearly with the distance, from those surface values to 1.0 s at 35 s, and
+    is capped at 1.0 s; inside the shell's inner radius it grows inward at the same rate.  h is the
+    smaller of the shell's and the source's ramps, times ``coarsen``."""
+    s = a.radius / 35.0
+    slope = 0.9 / 35.0
+    r = np.sqrt(np.sum(x * x, axis=1))
+    R, t = a.radius, a.thickness
+    h_out = 0.1 * s + slope * np.maximum(r - R, 0.0)
+    h_shell = 0.1 * s + 0.1 * s * (R - r) / t
+    h_in = 0.2 * s + slope * np.maximum(R - t - r, 0.0)
+    h = np.where(r >= R, h_out, np.where(r >= R - t, h_shell, h_in))
+    d_src = np.sqrt(np.sum((x - np.asarray(a.src)[None, :]) ** 2, axis=1))
+    h = np.minimum(h, 0.1 * s + slope * d_src)
+    return coarsen * np.minimum(h, 1.0 * s)
+
+
+def morton_order(x: np.ndarray, lo: Sequence[float], hi: Sequence[float], bits: int = 16) -> np.ndarray:
+    """Permutation that sorts 2D points along the Z (Morton) curve of a 2^bits grid over the box."""
+    lo = np.asarray(lo, dtype=np.float64)
+    ext = np.asarray(hi, dtype=np.float64) - lo
+    q = np.clip(((x - lo[None, :]) / ext[None, :] * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+    key = np.zeros(x.shape[0], dtype=np.int64)
+    for b in range(bits):
+        key |= ((q[:, 0] >> b) & 1) << (2 * b)
+        key |= ((q[:, 1] >> b) & 1) << (2 * b + 1)
+    return np.argsort(key, kind="stable")
+
+
+def asteroid_graded_points(a: Asteroid, coarsen: float = 1.0, seed: int = SEED_BASE + 10, jitter: float = 0.2):
+    """Points at the graded spacing of Sec. 5.4 (``asteroid_spacing``): the leaves of a quadtree over
+    the domain, split while a leaf's size exceeds sqrt(2) h at its centre (so each leaf is within a
+    factor sqrt(2) of h there), one point per leaf at its centre moved by U[-jitter, jitter] times the
+    leaf's sides, in Morton order of the leaves.  Root cells are the near-square cells of the
+    coarsest spacing, ceil(extent / hmax) per axis.  A leaf on the domain's edge is also split while
+    a leaf touching its inner face (the face opposite that edge) is finer: with the support radius
+    R = 2 L of every point (L = sqrt(area), the leaf size and local spacing), a coarse edge row beside
+    a finer row inside would leave the edge covered by the supports of one row of points only, where
+    the linear RK moment matrix is nearly singular.  Returns (x, R, L); the SUPG length is L."""
+    lo = np.asarray(a.lo, dtype=np.float64)
+    hi = np.asarray(a.hi, dtype=np.float64)
+    ext = hi - lo
+    hmax = coarsen * a.radius / 35.0
+    nroot = np.maximum(1, np.ceil(ext / hmax - 1e-9).astype(np.int64))
+    root = ext / nroot
+    ii, jj = np.meshgrid(np.arange(nroot[0]), np.arange(nroot[1]), indexing="ij")
+    corner = lo[None, :] + np.stack([ii.ravel(), jj.ravel()], axis=1) * root[None, :]
+    sz = np.repeat(root[None, :], corner.shape[0], axis=0)
+
+    def children(c, s):
+        h = 0.5 * s
+        return (np.concatenate([c, c + h * [1.0, 0.0], c + h * [0.0, 1.0], c + h]), np.tile(h, (4, 1)))
+
+    c_l, s_l = [], []
+    while corner.shape[0]:
+        L = np.sqrt(sz[:, 0] * sz[:, 1])
+        split = L > math.sqrt(2.0) * asteroid_spacing(a, corner + 0.5 * sz, coarsen)
+        c_l.append(corner[~split])
+        s_l.append(sz[~split])
+        corner, sz = children(corner[split], sz[split])
+    corner, sz = np.concatenate(c_l), np.concatenate(s_l)
+    tol = 1e-9 * float(ext.max())
+    from scipy.spatial import cKDTree
+    while True:
+        cen = corner + 0.5 * sz
+        L = np.sqrt(sz[:, 0] * sz[:, 1])
+        at_lo = corner - lo[None, :] < tol
+        at_hi = hi[None, :] - (corner + sz) < tol
+        edge = np.nonzero(np.any(at_lo | at_hi, axis=1))[0]
+        # leaves touching an edge leaf: centres within (s_i + s_j) / 2 along both axes, which for
+        # touching leaves of at most twice the size is within 1.5 leaf diagonals
+        near = cKDTree(cen).query_ball_point(cen[edge], 1.5 * 1.01 * np.sqrt(np.sum(sz[edge] ** 2, axis=1)))
+        split = np.zeros(corner.shape[0], dtype=bool)
+        for i, js in zip(edge, near):
+            js = np.asarray(js, dtype=np.int64)
+            gap = np.abs(cen[js] - cen[i]) - 0.5 * (sz[js] + sz[i])
+            js = js[np.all(gap <= tol, axis=1) & (L[js] < L[i] * (1.0 - 1e-9))]
+            for ax in range(2):
+                d = cen[js, ax] - cen[i, ax]
+                inner = (d > 0.0) if at_lo[i, ax] else (d < 0.0) if at_hi[i, ax] else np.zeros(js.size, bool)
+                # across the inner face: the centres are (s_i + s_j) / 2 apart along this axis
+                inner &= np.abs(np.abs(d) - 0.5 * (sz[js, ax] + sz[i, ax])) <= tol
+                split[i] |= bool(inner.any())
+        if not split.any():
+            break
+        c2, s2 = children(corner[split], sz[split])
+        corner, sz = np.concatenate([corner[~split], c2]), np.concatenate([sz[~split], s2])
+    cen = corner + 0.5 * sz
+    order = morton_order(cen, lo, hi)
+    cen, sz = cen[order], sz[order]
+    L = np.sqrt(sz[:, 0] * sz[:, 1])
+    g = rng(seed).uniform(-jitter, jitter, size=cen.shape)
+    x = np.ascontiguousarray(cen + g * sz, dtype=np.float64)
+    return x, 2.0 * L, L
+
+
+def asteroid_step_inv_c_dt(a: Asteroid) -> float:
+    """1/(c dt) of the asteroid's single backward-Euler step (Sec. 5.4: one step long enough for the
+    radiation to cross the domain): c dt is 100 times the domain's diagonal."""
+    return 1.0 / (100.0 * float(np.linalg.norm(np.subtract(a.hi, a.lo))))
 
 
 def asteroid_materials(a: Asteroid):
