@@ -61,16 +61,18 @@ def parse():
                          "with the relative error against the exact scalar flux; 8: workload 2 with points "
                          "that move every step (geometry, integration and assembly inside the time loop); 9: the asteroid of "
                          "Sec. 5.4 at one tenth of its lengths (shell materials, Alg. 2 refined quadrature, the "
-                         "paper's graded point spacing coarsened --scale times, default 2, one large time step)")
+                         "paper's graded point spacing coarsened --scale times, default 1, one large time step)")
     ap.add_argument("--be-steps", type=int, default=None, help="backward-Euler steps per repetition (workloads 3/4)")
     ap.add_argument("--max-outer", type=int, default=None,
                     help="outer-iteration cap per solve in the --workload mode (the record states convergence)")
     ap.add_argument("--max-inner", type=int, default=None, help="inner-iteration cap per solve (--workload mode)")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="inner GMRES restart length, 1-60 (--workload mode; default 30, 60 for workload 9)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay the inner solves' restart cycles from captured HIP graphs (default: one by one)")
     ap.add_argument("--precond", choices=["jacobi", "patch"], default=None,
                     help="right preconditioner of the inner solves: point Jacobi (the default) or patch block "
-                         "Jacobi (the default of workload 9, whose graded points stall point-Jacobi GMRES(30))")
+                         "Jacobi (the default of workload 9)")
     ap.add_argument("--accel", action="store_true",
                     help="workload and serving modes: diffusion-synthetic acceleration of the outer iteration")
     ap.add_argument("--probe", action="store_true",
@@ -318,6 +320,8 @@ def other_workload(args):
             opts.accel = mlpg.MLPG_ACCEL_DSA
         if args.max_outer:
             opts.max_outer = args.max_outer
+        if args.restart:
+            opts.restart_inner = args.restart
         if args.max_inner:
             opts.max_inner = args.max_inner
         err = None
@@ -387,14 +391,14 @@ def other_workload(args):
 
 
 ASTEROID_MAX_INNER = 20000
-ASTEROID_COARSEN = 2.0
+ASTEROID_RESTART = 60
 
 
 def asteroid_workload(args):
     """Sec. 5.4 asteroid at one tenth of the paper's lengths: an absorbing shell (20 mean free paths)
     lit by a small source through the Alg. 2 refined quadrature (goal 2048 ordinates), on points at
-    twice the paper's graded spacing (0.1-1.0 in its units; ``--scale k`` coarsens it k times instead,
-    1 is the paper's own), one backward-Euler step from zero radiation long enough to cross the domain.  The error is taken where
+    the paper's graded spacing (0.1-1.0 in its units; ``--scale k`` coarsens it k times), one
+    backward-Euler step from zero radiation long enough to cross the domain.  The error is taken where
     the refined ordinates resolve the flux (the lit cone in front of the asteroid), weighted by the
     points' shares of the area, against the exact line-source flux for the same polar levels with the
     step's 1/(c dt) added to the absorption."""
@@ -402,9 +406,7 @@ def asteroid_workload(args):
     from paper_2008_02205_amd import mlpg
     from paper_2008_02205_amd.problem import GpuProblem
     a = W.asteroid(0.1)
-    # at the paper's own spacing (132,684 points) some ordinates' inner GMRES(30) solves do not reach
-    # 1e-13 within 20,000 steps with either preconditioner built here; at twice it every one converges
-    coarsen = float(args.scale) if args.scale else ASTEROID_COARSEN
+    coarsen = float(args.scale) if args.scale else 1.0
     x, R, L = W.asteroid_graded_points(a, coarsen)
     shells, st, ss = W.asteroid_materials(a)
     a0 = W.asteroid_step_inv_c_dt(a)
@@ -432,11 +434,13 @@ def asteroid_workload(args):
         t3 = sync_time()
         opts = mlpg.mlpg_default_opts()
         opts.precond = mlpg.MLPG_PRECOND_JACOBI if args.precond == "jacobi" else mlpg.MLPG_PRECOND_PATCH
-        # on the graded points point-Jacobi GMRES(30) stalls near a relative residual of 0.5 on some
-        # ordinates of the oblique polar level (the shell is 20 mean free paths thick, 1-2.5 per point
-        # spacing along the plane and twice that along those ordinates), so the patch preconditioner is
-        # this workload's default; the cap stays above the library's 3,000 for --precond jacobi
+        # on the graded points restarted GMRES(30) stalls near a relative residual of 0.5 on some
+        # ordinates of the oblique polar level (with point Jacobi at twice the paper's spacing, with
+        # the patch preconditioner too at its own); GMRES(60) with the patch preconditioner converges
+        # every ordinate, so these are this workload's defaults (the cap stays above the library's
+        # 3,000 steps for the other settings)
         opts.max_inner = args.max_inner or ASTEROID_MAX_INNER
+        opts.restart_inner = args.restart or ASTEROID_RESTART
         if args.accel:
             opts.accel = mlpg.MLPG_ACCEL_DSA
         _, pv, _, inf = mlpg.mlpg_solve(P.h, q, None, opts, want_psi=False, raise_on_error=False,
@@ -474,7 +478,7 @@ def asteroid_workload(args):
            "config": {"workload": f"asteroid (lengths x0.1, graded spacing x{coarsen:g}): {n} points, {M} refined "
                                   f"ordinates, one backward-Euler step (c dt = {1.0 / a0:.0f})",
                       "points": n, "ordinates": M, "dim": 2, "accel": "dsa" if args.accel else "none",
-                      "precond": args.precond or "patch"},
+                      "precond": args.precond or "patch", "restart": args.restart or ASTEROID_RESTART},
            "detail": out}
     print(json.dumps(rec), flush=True)
 

@@ -377,8 +377,10 @@ typedef struct {
     double tol_outer;     /* outer relative residual (default 1e-12; MLPG_MIXED stops at 1e-10 at the
                              tightest: its inner solves make the outer operator linear only to about
                              tol_inner / (1 - c)) */
-    int restart_inner;    /* GMRES restart length, <= 30 (default 30) */
-    int restart_outer;    /* <= 30 (default 30) */
+    int restart_inner;    /* GMRES restart length, <= 60 (default 30); above 30 each Gram-Schmidt pass
+                             runs in two chunks over the basis and the solve workspace holds two more
+                             FP64 fields of the inner systems' shape (same sums, bit for bit) */
+    int restart_outer;    /* <= 60 (default 30) */
     int max_inner;        /* Arnoldi steps per ordinate per solve (default 3000) */
     int max_outer;        /* (default 500) */
     int check_every;      /* Arnoldi steps queued ahead of the host convergence check (default 3) */

@@ -246,7 +246,7 @@ int dsa_apply(Problem &P, SolveCounters &c, const double *v, double *out, hipStr
     double rm = 0.0;
     bool conv = true;
     int rc = gmres_batched<double>(P, P.dsa, op_dsa, false, nullptr, P.dsa_dinv.p, P.dsa_r.p, P.dsa_x.p, P.n, 1,
-                                   1e-12, kMaxRestart, 20000, 1, true, s, &c.accel_its, &sweeps, &rm, &conv,
+                                   1e-12, kDsaRestart, 20000, 1, true, s, &c.accel_its, &sweeps, &rm, &conv,
                                    nullptr, true);
     if (rc) return rc;
     if (!conv) {
@@ -913,7 +913,7 @@ static int check_opts(const mlpg_solve_opts &o, const char *who)
     MLPG_CHECK(o.tol_inner > 0 && o.tol_outer > 0, MLPG_ERR_ARG, w + ": tolerances must be positive");
     MLPG_CHECK(o.restart_inner >= 1 && o.restart_inner <= kMaxRestart && o.restart_outer >= 1 &&
                    o.restart_outer <= kMaxRestart,
-               MLPG_ERR_ARG, w + ": restart lengths must be in [1, 30]");
+               MLPG_ERR_ARG, w + ": restart lengths must be in [1, 60]");
     MLPG_CHECK(o.max_inner >= 1 && o.max_outer >= 0 && o.check_every >= 1 && o.max_refine >= 0, MLPG_ERR_ARG,
                w + ": iteration limits must be positive");
     MLPG_CHECK(P_ok_lo(o), MLPG_ERR_ARG, w + ": tol_inner_lo must be in (0, 1)");

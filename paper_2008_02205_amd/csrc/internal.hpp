@@ -36,7 +36,10 @@ constexpr int kTileRows3 = 8;      // most Gram rows per 3D tile without fields 
 // when a problem's panels are larger).
 constexpr int64_t kGramCells = 1024;
 constexpr size_t kGramPanelBytes = size_t(2) << 20;
-constexpr int kMaxRestart = 30;
+constexpr int kMaxRestart = 60;   // longest GMRES restart cycle
+constexpr int kChunkRestart = 30; // basis vectors a streaming pass holds in registers; longer cycles run
+                                  // their passes in two chunks
+constexpr int kDsaRestart = 30;   // restart of the diffusion solves of the synthetic acceleration
 constexpr int kMaxFields = 8;    // smooth material fields per problem
 constexpr int kMaxMat = 8;       // materials per problem
 constexpr double kMixedOuterFloor = 1e-10;   // tightest outer tolerance of the mixed path
@@ -181,6 +184,7 @@ struct KrylovT {
     DevBuf<T> z;             // [n][nb] dinv .* w, the next operator input
     DevBuf<T> r;             // [n][nb]
     DevBuf<double> vscale;   // [nb] 1/h_{j+1,j} of the newest column (0 once a system stops)
+    DevBuf<double> pu, pw;   // [n][nb] FP64 partial u and w between the chunks of pass B (k > 30 only)
     DevBuf<double> part;     // [nblk][2k+2][nb] block partial sums
     DevBuf<double> h1, h2;   // [2k+2][nb] reduced projections, pass-B coefficients
     DevBuf<double> H;        // [nb][k+1][k] rotated Hessenberg (upper triangular part used)

@@ -32,12 +32,12 @@ constexpr int kThreads = 256;       // small kernels
 constexpr int kMaxThreads = 512;    // streaming passes (2 waves per SIMD: ~190 VGPRs fit)
 constexpr int kPartBlocks = 256;    // workgroups (and partial sums) of a streaming pass
 constexpr int kRowsPerThread = 4;
-constexpr int KP = kMaxRestart + 1;   // register capacity for the Hessenberg column
+constexpr int KP = kChunkRestart + 1;   // register capacity for the Hessenberg column (32-lane kernels)
+constexpr int KPL = kMaxRestart + 1;    // the same for cycles longer than kChunkRestart (64-lane kernels)
 constexpr int kRows = 2 * kMaxRestart + 2;   // partial-sum rows: a, b, u.w, u.u
+constexpr int kChunk = kChunkRestart;   // basis vectors per chunk of a streaming pass
 constexpr int QC = 8;                 // partial sums reduced per LDS round
 constexpr int kSlots = 8;
-constexpr int kGroup = 32;            // threads per system in the small kernel
-constexpr int kGroupsPerBlock = kThreads / kGroup;
 
 constexpr int kRedThreads = 1024;   // partial-sum reductions: every strand's loads in flight at once
 
@@ -57,9 +57,9 @@ inline int pow2_floor(int v)
 
 // Reduce acc[q] (q < NQ) over the rpb row groups of the block into
 // part[blockIdx][q][m], QC values at a time through a fixed-shape LDS tree.
-template <int NQ>
+template <int NQ, class RowOf>
 __device__ __forceinline__ void block_reduce_store(const double (&acc)[NQ], int rpb, int rl, int m, int nb,
-                                                   double *red, double *part)
+                                                   double *red, double *part, RowOf row)
 {
 #pragma unroll
     for (int q0 = 0; q0 < NQ; q0 += QC) {
@@ -77,11 +77,20 @@ __device__ __forceinline__ void block_reduce_store(const double (&acc)[NQ], int 
         }
         if (rl == 0) {
 #pragma unroll
-            for (int qq = 0; qq < QC; ++qq)
-                if (q0 + qq < NQ) part[((int64_t)blockIdx.x * kRows + q0 + qq) * nb + m] = red[qq * nb + m];
+            for (int qq = 0; qq < QC; ++qq) {
+                const int r = q0 + qq < NQ ? row(q0 + qq) : -1;   // a negative row is not stored
+                if (r >= 0) part[((int64_t)blockIdx.x * kRows + r) * nb + m] = red[qq * nb + m];
+            }
         }
         __syncthreads();
     }
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_reduce_store(const double (&acc)[NQ], int rpb, int rl, int m, int nb,
+                                                   double *red, double *part)
+{
+    block_reduce_store<NQ>(acc, rpb, rl, m, nb, red, part, [](int q) { return q; });
 }
 
 // part[b][0][m] = the block's share of ||x_m||^2 (FP64 whatever T is).
@@ -188,6 +197,123 @@ __global__ __launch_bounds__(kMaxThreads) void pass_b_kernel(int64_t n, int nb, 
         acc[0] += (double)wt * (double)wt;
     }
     block_reduce_store<1>(acc, rpb, rl, m, nb, red, part);
+}
+
+// Pass A of a step with more than kChunk basis vectors (a cycle longer than
+// kChunk), one chunk of at most kChunk of them per launch: the partial sums
+// a_q (and b_q) for q in [q0, q0 + nc) and, with TAIL, the u.w and u.u rows,
+// in the row layout pass_a_kernel has for NQ = nq.  Every sum runs over the
+// same rows in the same order as in one pass, so the chunks change no bit.
+template <class T, bool HW, bool TAIL>
+__global__ __launch_bounds__(kMaxThreads) void pass_a_chunk_kernel(int64_t n, int nb, const T *__restrict__ V,
+                                                                   int64_t vstride, const T *__restrict__ u,
+                                                                   const T *__restrict__ w,
+                                                                   double *__restrict__ part,
+                                                                   const int *__restrict__ gate, int q0, int nc,
+                                                                   int nq)
+{
+    extern __shared__ double red[];
+    if (gate && *gate == 0) return;
+    const int rpb = blockDim.x / nb;
+    const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
+    constexpr int NV = HW ? 2 * kChunk : kChunk;
+    constexpr int NA = NV + (TAIL ? (HW ? 2 : 1) : 0);
+    double acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
+        const int64_t o = i * nb + m;
+        T v[kChunk];
+        const double uv = (double)u[o];
+        const double wv = HW ? (double)w[o] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) v[q] = q < nc ? V[(q0 + q) * vstride + o] : (T)0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            acc[q] += (double)v[q] * uv;
+            if (HW) acc[kChunk + q] += (double)v[q] * wv;
+        }
+        if (TAIL) {
+            if (HW) {
+                acc[NV] += uv * wv;
+                acc[NV + 1] += uv * uv;
+            } else {
+                acc[NV] += uv * uv;
+            }
+        }
+    }
+    block_reduce_store<NA>(acc, rpb, rl, m, nb, red, part, [=](int x) {
+        if (x < kChunk) return x < nc ? q0 + x : -1;                      // a_q
+        if (HW && x < 2 * kChunk) return x - kChunk < nc ? nq + q0 + x - kChunk : -1;   // b_q
+        return x == NV ? (HW ? 2 * nq : nq) : 2 * nq + 1;                 // u.w (or u.u), u.u
+    });
+}
+
+// Pass B of a step with more than kChunk basis vectors in two launches.  The
+// first (FIRST) takes q in [0, kChunk): u - sum a_q V_q and w - s u -
+// sum g_q V_q, kept in FP64 in pu and pw; the second takes q in
+// [kChunk, nq) from there in the same order, then scales, writes u, w and z
+// and the partial sums of ||w||^2.  The sums are those of pass_b_kernel
+// term by term (the FP64 intermediate is exact), so no bit changes.
+template <class T, bool FIRST>
+__global__ __launch_bounds__(kMaxThreads) void pass_b_chunk_kernel(int64_t n, int nb, const T *__restrict__ V,
+                                                                   int64_t vstride, T *__restrict__ u,
+                                                                   T *__restrict__ w, const double *__restrict__ c,
+                                                                   const T *__restrict__ dinv, T *__restrict__ z,
+                                                                   double *__restrict__ part,
+                                                                   const int *__restrict__ gate,
+                                                                   double *__restrict__ pu, double *__restrict__ pw,
+                                                                   int nq)
+{
+    extern __shared__ double red[];
+    if (gate && *gate == 0) return;
+    const int rpb = blockDim.x / nb;
+    const int rl = threadIdx.x / nb, m = threadIdx.x - rl * nb;
+    const int q0 = FIRST ? 0 : kChunk;
+    const int nc = FIRST ? kChunk : nq - kChunk;
+    double ca[kChunk], cg[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+        ca[q] = q < nc ? c[(q0 + q) * nb + m] : 0.0;
+        cg[q] = q < nc ? c[(nq + q0 + q) * nb + m] : 0.0;
+    }
+    const double cs = c[(2 * nq) * nb + m], ir = c[(2 * nq + 1) * nb + m];
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * rpb + rl; i < n; i += (int64_t)gridDim.x * rpb) {
+        const int64_t o = i * nb + m;
+        T v[kChunk];
+        double vj, wj;
+        if (FIRST) {
+            const double uv = (double)u[o];
+            vj = uv;
+            wj = (double)w[o] - cs * uv;
+        } else {
+            vj = pu[o];
+            wj = pw[o];
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) v[q] = q < nc ? V[(q0 + q) * vstride + o] : (T)0;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+            if (q < nc) {
+                vj -= ca[q] * (double)v[q];
+                wj -= cg[q] * (double)v[q];
+            }
+        }
+        if (FIRST) {
+            pu[o] = vj;
+            pw[o] = wj;
+        } else {
+            const T vt = (T)(vj * ir), wt = (T)(wj * ir);
+            u[o] = vt;
+            w[o] = wt;
+            if (z) z[o] = dinv ? dinv[o] * wt : wt;
+            acc[0] += (double)wt * (double)wt;
+        }
+    }
+    if (!FIRST) block_reduce_store<1>(acc, rpb, rl, m, nb, red, part);
 }
 
 // out[q][m] = sum_b part[b][q][m]: one workgroup per q; threads split the
@@ -301,7 +427,8 @@ __global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, con
     }
 }
 
-// The small part of step j, kGroup threads per system (thread q owns row q).
+// The small part of step j, G threads per system (thread q owns row q; G = 32
+// and KPT = 31 for cycles of up to 30 steps, G = 64 and KPT = 61 beyond).
 // From pass A: rho = sqrt(u.u - |a|^2); the previous column of the
 // unrotated Hessenberg Ht is corrected with beta (the norm pass B gave the
 // previous vector) and a, then rotated by the earlier Givens rotations into
@@ -318,6 +445,7 @@ __global__ __launch_bounds__(kThreads) void cycle_init_kernel(int nb, int k, con
 // kAfterPre (coefficients only; column j-1 was corrected by kPre).
 enum { kStep = 0, kEnd = 1, kPre = 2, kAfterPre = 3 };
 
+template <int G, int KPT>
 __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, int k, int j, const double *__restrict__ P,
                                                               const double *__restrict__ betap,
                                                               double *__restrict__ Ht, double *__restrict__ R,
@@ -332,9 +460,11 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
                                                               int *__restrict__ nact_out,
                                                               int *__restrict__ nact_clear)
 {
-    __shared__ double sa[kGroupsPerBlock][KP + 1], scol[kGroupsPerBlock][KP + 1];
-    __shared__ double scs[kGroupsPerBlock][KP + 1], ssn[kGroupsPerBlock][KP + 1];
-    __shared__ int sstill[kGroupsPerBlock];
+    // rows of a system's staging arrays: every lane's row q (< G) and rows up to KPT
+    constexpr int SW = G > KPT + 1 ? G : KPT + 1;
+    __shared__ double sa[(kThreads / G)][SW], scol[(kThreads / G)][SW];
+    __shared__ double scs[(kThreads / G)][SW], ssn[(kThreads / G)][SW];
+    __shared__ int sstill[(kThreads / G)];
     if (blockIdx.x == 0 && threadIdx.x == 0 && nact_clear) nact_clear[0] = 0;
     // No early return on the gate: a gated step has no active system, and
     // every effect below then reduces to clearing the stopped systems'
@@ -342,8 +472,8 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     (void)gate;
     const bool FINAL = mode == kEnd || mode == kPre;     // no coefficients
     const bool correct = mode != kAfterPre && j >= 1;   // correct and test column j-1
-    const int grp = threadIdx.x / kGroup, q = threadIdx.x % kGroup;
-    const int m = blockIdx.x * kGroupsPerBlock + grp;
+    const int grp = threadIdx.x / G, q = threadIdx.x % G;
+    const int m = blockIdx.x * (kThreads / G) + grp;
     const int mc = m < nb ? m : 0;
     double *Hm = Ht + (int64_t)mc * (k + 1) * k;
     // Every load of the kernel is issued here, before any of them is used:
@@ -364,9 +494,9 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     const double csq = (correct && q < j - 1) ? cs[mc * k + q] : 0.0;
     const double snq = (correct && q < j - 1) ? sn[mc * k + q] : 0.0;
     // row q of Ht left of column j-1 (not written by this kernel), for t
-    double hv[KP];
+    double hv[KPT];
 #pragma unroll
-    for (int p = 0; p < KP; ++p) hv[p] = (!FINAL && q <= j && p + 1 >= q && p < j - 1) ? Hm[q * k + p] : 0.0;
+    for (int p = 0; p < KPT; ++p) hv[p] = (!FINAL && q <= j && p + 1 >= q && p < j - 1) ? Hm[q * k + p] : 0.0;
     // the serial part's scalars (thread 0 of each system)
     double g_prev = 0.0, fn = 0.0, tl = tol0;
     int it0 = 0;
@@ -384,9 +514,9 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
         d = 0.0;
     }
     double aa = a * a, ab = a * b;
-    for (int o = kGroup / 2; o > 0; o >>= 1) {
-        aa += __shfl_xor(aa, o, kGroup);
-        ab += __shfl_xor(ab, o, kGroup);
+    for (int o = G / 2; o > 0; o >>= 1) {
+        aa += __shfl_xor(aa, o, G);
+        ab += __shfl_xor(ab, o, G);
     }
     const double rho2 = d - aa;
     const double rho = rho2 > 0.0 ? sqrt(rho2) : 0.0;
@@ -416,11 +546,11 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
         } else if (act && correct) {
             double *Rm = R + (int64_t)m * (k + 1) * k;
             double *cm = cs + m * k, *sm = sn + m * k, *gm = g + m * (k + 1);
-            double col[KP + 1];
+            double col[KPT + 1];
 #pragma unroll
-            for (int r = 0; r <= KP; ++r) col[r] = (r <= j) ? scol[grp][r] : 0.0;
+            for (int r = 0; r <= KPT; ++r) col[r] = (r <= j) ? scol[grp][r] : 0.0;
 #pragma unroll
-            for (int r = 0; r < KP - 1; ++r) {
+            for (int r = 0; r < KPT - 1; ++r) {
                 if (r < j - 1) {
                     const double cr = scs[grp][r], sr = ssn[grp][r];
                     const double x0 = col[r], x1 = col[r + 1];
@@ -430,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
             }
             double aj = 0.0, hn = 0.0;
 #pragma unroll
-            for (int r = 0; r <= KP; ++r) {
+            for (int r = 0; r <= KPT; ++r) {
                 if (r == j - 1) aj = col[r];
                 if (r == j) hn = col[r];
             }
@@ -438,7 +568,7 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
             const double cj = den == 0.0 ? 1.0 : aj / den;
             const double sj = den == 0.0 ? 0.0 : hn / den;
 #pragma unroll
-            for (int r = 0; r < KP; ++r) {
+            for (int r = 0; r < KPT; ++r) {
                 if (r < j - 1) Rm[r * k + (j - 1)] = col[r];
                 if (r == j - 1) Rm[r * k + (j - 1)] = den;
             }
@@ -463,7 +593,7 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     if (FINAL || m >= nb) return;
     const int rows = 2 * j + 2;
     if (!sstill[grp]) {
-        for (int r = q; r < rows; r += kGroup) coef[r * nb + m] = 0.0;
+        for (int r = q; r < rows; r += G) coef[r * nb + m] = 0.0;
         return;
     }
     // t_q = sum_{p = max(q-1, 0)}^{j-1} a_p Ht[q][p] for q <= j (column j-1
@@ -471,10 +601,10 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     double t = 0.0;
     if (q <= j && j >= 1) {
 #pragma unroll
-        for (int p = 0; p < KP; ++p) t += sa[grp][p] * hv[p];
+        for (int p = 0; p < KPT; ++p) t += sa[grp][p] * hv[p];
         t += sa[grp][j - 1] * scol[grp][q];
     }
-    const double tj = __shfl(t, j < kGroup ? j : 0, kGroup);
+    const double tj = __shfl(t, j < G ? j : 0, G);
     const double vw = (c - ab) / rho;
     const double hjj = (vw - tj) / rho;
     const double sc = tj / rho + hjj;
@@ -513,27 +643,28 @@ __global__ void init_v0_kernel(int64_t n, int nb, const T *__restrict__ r, const
 }
 
 // Least squares: back substitution R y = g over the jend columns.
+template <int G, int KPT>
 __global__ __launch_bounds__(kThreads) void lsq_kernel(int nb, int k, const double *__restrict__ H,
                                                        const double *__restrict__ g,
                                                        const int *__restrict__ jend, double *__restrict__ y)
 {
-    // One kGroup-lane group per system: lane r holds row r of R (loaded at
+    // One G-lane group per system: lane r holds row r of R (loaded at
     // once, no dependent round trips) and its running right-hand side; step
     // q divides on lane q and broadcasts y_q to the rows above it.
-    const int grp = threadIdx.x / kGroup, r = threadIdx.x % kGroup;
-    const int m = blockIdx.x * kGroupsPerBlock + grp;
+    const int grp = threadIdx.x / G, r = threadIdx.x % G;
+    const int m = blockIdx.x * (kThreads / G) + grp;
     const int mc = m < nb ? m : 0;
     const double *Hm = H + (int64_t)mc * (k + 1) * k;
-    const int je = jend[mc];   // <= k < KP, the same on every lane of the group
-    double h[KP];
+    const int je = jend[mc];   // <= k < KPT, the same on every lane of the group
+    double h[KPT];
 #pragma unroll
-    for (int p = 0; p < KP; ++p) h[p] = (r < je && p >= r && p < je) ? Hm[r * k + p] : 0.0;
+    for (int p = 0; p < KPT; ++p) h[p] = (r < je && p >= r && p < je) ? Hm[r * k + p] : 0.0;
     double s = r < je ? g[mc * (k + 1) + r] : 0.0;
     double yr = 0.0;
 #pragma unroll
-    for (int q = KP - 1; q >= 0; --q) {
+    for (int q = KPT - 1; q >= 0; --q) {
         if (q < je) {
-            const double yq = __shfl(s / h[q], q, kGroup);   // lane q: R[q][q]
+            const double yq = __shfl(s / h[q], q, G);   // lane q: R[q][q]
             if (r == q) yr = yq;
             if (r < q) s -= h[q] * yq;                      // lane r: R[r][q]
         }
@@ -645,7 +776,21 @@ hipError_t pass_a(KrylovT<T> &K, int j, const T *w, const int *gate, hipStream_t
     const int rows = hw ? 2 * j + 2 : j + 1;
     const T *u = K.V.p + (int64_t)j * K.vs;
     int id = prof_start(hw ? 1 : 3, pass_bytes(K, j + (hw ? 2 : 1), rows, L.blocks), s);
-    switch (j) {
+    if (j > kChunk) {
+        // V_0..V_29 with the u.w and u.u rows, then V_30..V_{j-1}
+        if (hw) {
+            pass_a_chunk_kernel<T, true, true><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, w,
+                                                                                   K.part.p, gate, 0, kChunk, j);
+            pass_a_chunk_kernel<T, true, false><<<L.blocks, L.threads, L.shmem, s>>>(
+                K.n, K.nb, K.V.p, K.vs, u, w, K.part.p, gate, kChunk, j - kChunk, j);
+        } else {
+            pass_a_chunk_kernel<T, false, true><<<L.blocks, L.threads, L.shmem, s>>>(
+                K.n, K.nb, K.V.p, K.vs, u, nullptr, K.part.p, gate, 0, kChunk, j);
+            pass_a_chunk_kernel<T, false, false><<<L.blocks, L.threads, L.shmem, s>>>(
+                K.n, K.nb, K.V.p, K.vs, u, nullptr, K.part.p, gate, kChunk, j - kChunk, j);
+        }
+    }
+    switch (j > kChunk ? -1 : j) {
 #define MLPG_PA_CASE(Q)                                                                                          \
     case Q:                                                                                                       \
         if (hw)                                                                                                   \
@@ -669,12 +814,19 @@ template <class T>
 hipError_t pass_b(KrylovT<T> &K, int j, T *w, const T *dinv, T *z, const int *gate, int *host_slot, hipStream_t s)
 {
     if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
+    if (j > kChunk && !(K.pu.p && K.pw.p)) return hipErrorInvalidValue;
     Launch L = vec_launch(K.n, K.nb);
     T *u = K.V.p + (int64_t)j * K.vs;
     // V_0..V_{j-1}, u and w read; u and w written; dinv read and z written
     const double nvec = j + 4 + (z ? (dinv ? 2 : 1) : 0);
     int id = prof_start(2, pass_bytes(K, nvec, 1, L.blocks), s);
-    switch (j) {
+    if (j > kChunk) {
+        pass_b_chunk_kernel<T, true><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, w, K.h2.p, dinv,
+                                                                         z, K.part.p, gate, K.pu.p, K.pw.p, j);
+        pass_b_chunk_kernel<T, false><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, w, K.h2.p,
+                                                                          dinv, z, K.part.p, gate, K.pu.p, K.pw.p, j);
+    }
+    switch (j > kChunk ? -1 : j) {
 #define MLPG_PB_CASE(Q)                                                                                      \
     case Q:                                                                                                   \
         pass_b_kernel<T, Q><<<L.blocks, L.threads, L.shmem, s>>>(K.n, K.nb, K.V.p, K.vs, u, w, K.h2.p, dinv, \
@@ -723,6 +875,10 @@ void KrylovT<T>::carve(Arena &A, int64_t n_, int nb_, int k_)
     A.take(its, nb);
     A.take(jend, nb);
     A.take(nactive, 3);
+    if (k > kChunk) {
+        A.take(pu, (size_t)n * nb);
+        A.take(pw, (size_t)n * nb);
+    }
 }
 
 template <class T>
@@ -766,6 +922,7 @@ void KrylovT<T>::release()
     V.release(); w.release(); w2.release(); z.release(); r.release(); part.release(); h1.release(); h2.release(); H.release();
     Ht.release(); cs.release(); sn.release(); g.release(); y.release(); vscale.release(); fnorm.release(); beta.release();
     resid.release(); active.release(); done.release(); its.release(); jend.release(); nactive.release();
+    pu.release(); pw.release();
     if (nactive_host) {
         (void)hipHostFree(nactive_host);
         for (int i = 0; i < kSlots; ++i)
@@ -787,7 +944,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(!(pp && dinv), MLPG_ERR_ARG, "batched GMRES: one right preconditioner at a time");
-    MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 30]");
+    MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 60]");
     MLPG_CHECK(K.V.p && K.n == n && K.nb == nb && K.k >= restart, MLPG_ERR_WORKSPACE,
                "batched GMRES: the solve workspace was laid out for another shape");
     MLPG_HIP(K.host_init());
@@ -796,7 +953,20 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
     const int k = restart;
     const int64_t cnt = n * nb;
     const int nbt = ((nb + 63) / 64) * 64;
-    const unsigned small_blocks = (unsigned)((nb + kGroupsPerBlock - 1) / kGroupsPerBlock);
+    // the per-system kernels: 32 lanes per system for cycles of up to 30 steps, 64 beyond
+    const bool longc = k > kChunk;
+    const int groups = kThreads / (longc ? 64 : 32);
+    const unsigned small_blocks = (unsigned)((nb + groups - 1) / groups);
+    auto small = [&](int mode, int j, const int *gate, int *nout, int *nclear, hipStream_t st) {
+        if (longc)
+            step_small_kernel<64, KPL><<<small_blocks, kThreads, 0, st>>>(
+                mode, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
+                max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nout, nclear);
+        else
+            step_small_kernel<32, KP><<<small_blocks, kThreads, 0, st>>>(
+                mode, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
+                max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nout, nclear);
+    };
     // the outer operator (each application a full set of inner solves) is
     // tested before it is applied; a cheap unfused operator is not
     const bool precheck = !fused && !cheap_op;
@@ -841,9 +1011,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             const bool pre = precheck && j >= 1;
             if (pre) {
                 MLPG_HIP(pass_a<T>(K, j, nullptr, gate, s));
-                step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
-                    kPre, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
-                    max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nullptr, nullptr);
+                small(kPre, j, gate, nullptr, nullptr, s);
                 std::vector<int> act(nb);
                 MLPG_HIP(hipMemcpyAsync(act.data(), K.active.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
                 MLPG_HIP(hipStreamSynchronize(s));
@@ -874,10 +1042,7 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             int rc = op(P, c, s, ctx);
             if (rc) return rc;
             MLPG_HIP(pass_a<T>(K, j, wcur, gate, s));
-            step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
-                pre ? kAfterPre : kStep, nb, k, j, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p,
-                K.fnorm.p, tol, tolv, max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nnext,
-                nact + ((j + 2) % 3));
+            small(pre ? kAfterPre : kStep, j, gate, nnext, nact + ((j + 2) % 3), s);
             const int slot = (int)(sw % kSlots);
             MLPG_HIP(pass_b<T>(K, j, wcur, dinv, (fused && !pp) ? K.z.p : nullptr, nnext, K.nactive_hdev + slot, s));
             // the next operator input M^-1 w_j (normalised inside the next sweep)
@@ -903,11 +1068,12 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             // end of the cycle: the last column's delayed correction
             const int *gate = nact + (k % 3);
             MLPG_HIP(pass_a<T>(K, k, nullptr, gate, s));
-            step_small_kernel<<<small_blocks, kThreads, 0, s>>>(
-                kEnd, nb, k, k, K.h1.p, K.beta.p, K.Ht.p, K.H.p, K.cs.p, K.sn.p, K.g.p, K.fnorm.p, tol, tolv,
-                max_its, K.active.p, K.its.p, K.jend.p, K.resid.p, K.h2.p, gate, nact + ((k + 1) % 3), nullptr);
+            small(kEnd, k, gate, nact + ((k + 1) % 3), nullptr, s);
         }
-        lsq_kernel<<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
+        if (longc)
+            lsq_kernel<64, KPL><<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
+        else
+            lsq_kernel<32, KP><<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
         if (pp) {
             // x += M^-1 (V y)
             vy_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, K.z.p);

@@ -141,7 +141,7 @@ void layout_solve(Problem &P, Arena &A, const mlpg_solve_opts &o)
         A.take(P.tolv, M);
     }
     if (o.accel == MLPG_ACCEL_DSA) {
-        P.dsa.carve(A, n, 1, kMaxRestart);
+        P.dsa.carve(A, n, 1, kDsaRestart);
         A.take(P.dsa_r, n);
         A.take(P.dsa_x, n);
         A.take(P.dsa_t, n);
