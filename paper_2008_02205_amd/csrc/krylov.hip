@@ -199,6 +199,21 @@ __global__ __launch_bounds__(kMaxThreads) void pass_b_kernel(int64_t n, int nb, 
     block_reduce_store<1>(acc, rpb, rl, m, nb, red, part);
 }
 
+// Slot q of a chunk of nc basis vectors from q0 (the chunk passes' loads; a
+// slot past the chunk is not used).  FP64 values load under the slot's
+// branch; FP32 values are converted to FP64 at their use, and under a branch
+// the compiler moves that conversion, and the wait for the load, into the
+// branch, one load at a time; so FP32 slots load unconditionally, those past
+// the chunk from its last vector again (an L1 hit).  The FP64 chunks keep
+// the branch because the rereads cost them about a fifth of a second chunk's
+// time at 132,684 x 240.
+template <class T>
+__device__ __forceinline__ T chunk_load(const T *__restrict__ V, int64_t vstride, int64_t o, int q0, int q, int nc)
+{
+    if (sizeof(T) == sizeof(double)) return q < nc ? V[(q0 + q) * vstride + o] : (T)0;
+    return V[(q0 + (q < nc ? q : nc - 1)) * vstride + o];
+}
+
 // Pass A of a step with more than kChunk basis vectors (a cycle longer than
 // kChunk), one chunk of at most kChunk of them per launch: the partial sums
 // a_q (and b_q) for q in [q0, q0 + nc) and, with TAIL, the u.w and u.u rows,
@@ -227,7 +242,7 @@ __global__ __launch_bounds__(kMaxThreads) void pass_a_chunk_kernel(int64_t n, in
         const double uv = (double)u[o];
         const double wv = HW ? (double)w[o] : 0.0;
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q) v[q] = q < nc ? V[(q0 + q) * vstride + o] : (T)0;
+        for (int q = 0; q < kChunk; ++q) v[q] = chunk_load(V, vstride, o, q0, q, nc);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) {
@@ -275,8 +290,14 @@ __global__ __launch_bounds__(kMaxThreads) void pass_b_chunk_kernel(int64_t n, in
     double ca[kChunk], cg[kChunk];
 #pragma unroll
     for (int q = 0; q < kChunk; ++q) {
-        ca[q] = q < nc ? c[(q0 + q) * nb + m] : 0.0;
-        cg[q] = q < nc ? c[(nq + q0 + q) * nb + m] : 0.0;
+        const int qi = q0 + (q < nc ? q : nc - 1);   // unconditional loads, then zeros past the chunk
+        ca[q] = c[qi * nb + m];
+        cg[q] = c[(nq + qi) * nb + m];
+    }
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+        ca[q] = q < nc ? ca[q] : 0.0;
+        cg[q] = q < nc ? cg[q] : 0.0;
     }
     const double cs = c[(2 * nq) * nb + m], ir = c[(2 * nq + 1) * nb + m];
     double acc[1] = {0.0};
@@ -293,7 +314,7 @@ __global__ __launch_bounds__(kMaxThreads) void pass_b_chunk_kernel(int64_t n, in
             wj = pw[o];
         }
 #pragma unroll
-        for (int q = 0; q < kChunk; ++q) v[q] = q < nc ? V[(q0 + q) * vstride + o] : (T)0;
+        for (int q = 0; q < kChunk; ++q) v[q] = chunk_load(V, vstride, o, q0, q, nc);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < kChunk; ++q) {

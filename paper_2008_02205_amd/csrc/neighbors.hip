@@ -3,12 +3,13 @@
 //
 // The points' bounding box is cut into a uniform grid of cells of side at
 // least 2 max_i R_i, so that two overlapping points sit in the same or in
-// adjacent cells.  Points are binned (counts, exclusive scan, scatter, each
-// cell sorted by index); every point then tests the points of the 3^dim
-// cells around its own.  The count pass writes the list lengths, the fill
-// pass writes each list and sorts it (Shell sort with the gaps 701, 301,
-// 132, 57, 23, 10, 4, 1 of Ciura, 2001), so the lists come out in increasing
-// j exactly as a brute-force search over all pairs would draw them.
+// adjacent cells.  Points are binned (counts, exclusive scan, scatter; the
+// order inside a cell is whatever the scatter's atomics give); every point
+// then tests the points of the 3^dim cells around its own.  The count pass
+// writes the list lengths, which do not depend on that order; the fill pass
+// writes each list and sorts it (Shell sort with the gaps 701, 301, 132, 57,
+// 23, 10, 4, 1 of Ciura, 2001), so the lists come out in increasing j exactly
+// as a brute-force search over all pairs would draw them.
 //
 // Scratch (NbScratch): the bounding box, each point's cell, each cell's
 // count and start, and the points in cell order.
@@ -136,22 +137,6 @@ __global__ void nb_scatter_kernel(int64_t n, const int32_t *__restrict__ cell, c
     pts[off[c] + k] = (int32_t)i;
 }
 
-__global__ void nb_cell_sort_kernel(int64_t m, const int64_t *__restrict__ off, int32_t *__restrict__ pts)
-{
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= m) return;
-    const int64_t a = off[c], b = off[c + 1];
-    for (int64_t p = a + 1; p < b; ++p) {
-        const int32_t v = pts[p];
-        int64_t q = p - 1;
-        while (q >= a && pts[q] > v) {
-            pts[q + 1] = pts[q];
-            --q;
-        }
-        pts[q + 1] = v;
-    }
-}
-
 // MODE 0: counts[i] = number of neighbours; MODE 1: the neighbours into
 // idx[off[i] ..] (cell order), then sorted.
 template <int MODE>
@@ -262,7 +247,6 @@ hipError_t nb_bin(int dim, int64_t n, const double *x, const double *R, const Nb
     nb_scan_kernel<<<1, 1024, 0, s>>>(sc.cnt, sc.coff, m);
     zero_u32_kernel<<<grid_of(m, 256), 256, 0, s>>>(sc.cnt, m);
     nb_scatter_kernel<<<grid_of(n, 256), 256, 0, s>>>(n, sc.cell, sc.coff, sc.cnt, sc.pts);
-    nb_cell_sort_kernel<<<grid_of(m, 256), 256, 0, s>>>(m, sc.coff, sc.pts);
     *g_out = g;
     return hipGetLastError();
 }
