@@ -2,7 +2,8 @@
 two chunks over the basis and the per-system kernels use 64 lanes, against the oracle's GMRES of the
 same restart length.  The case is the asteroid's single backward-Euler step on its graded points at
 ten times the paper's spacing (point-Jacobi inner solves of about 370 steps per ordinate, so every
-cycle but the last runs its full length)."""
+cycle but the last runs its full length), and a thick scattering problem whose outer GMRES runs cycles
+of 45 steps."""
 import dataclasses
 
 import numpy as np
@@ -99,4 +100,38 @@ def test_restart_bounds_and_workspace(_case):
     opts.restart_outer = 61
     with pytest.raises(mlpg.MlpgError, match=r"restart lengths must be in \[1, 60\]"):
         P.step(q, None, opts)
+    P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_long_outer_and_inner_cycles_thick_scattering(precision):
+    """A thick scattering problem (sigma_t = 50, c = 0.99 on a 12 x 12 lattice, 8 ordinates) whose outer
+    GMRES needs more than 30 steps, with outer and inner cycles of 45: the outer iteration's long cycles
+    run the chunked passes with one system and the check of each column before the next operator."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    n, sig_t, c, M = 12, 50.0, 0.99, 8
+    print(f"[case] long outer cycles {precision}", flush=True)
+    x, dx = W.jittered_lattice((n, n), (0, 0), (1, 1), 0.2, 5)
+    R = np.full(x.shape[0], 2 * dx)
+    g = oracle.geometry(x, R, (0, 0), (1, 1))
+    it = oracle.integrate(g, 1)
+    om_o, w_o = oracle.angular_quadrature(2, M)
+    tr = oracle.Transport(it, om_o, w_o, [sig_t], [c * sig_t], 0.0, dx,
+                          opts=oracle.SolveOpts(restart_in=45, restart_out=45))
+    psi_o, phi_o, info_o = tr.step(None, np.ones((g.n, M)))
+    om_g, w_g = mlpg.mlpg_angular_quadrature(2, M)
+    P = GpuProblem(x, R, (0, 0), (1, 1))
+    P.integrate(1)
+    P.assemble(om_g, w_g, [sig_t], [c * sig_t], 0.0, dx,
+               precision=mlpg.MLPG_FP64 if precision == "fp64" else mlpg.MLPG_MIXED)
+    opts = mlpg.mlpg_default_opts()
+    opts.restart_inner = 45
+    opts.restart_outer = 45
+    phi, pv, psi, info = P.step(torch.ones((g.n, M), dtype=torch.float64, device="cuda"), None, opts)
+    assert info["converged"] == 1
+    assert info["outer_iters"] > 30     # at least one outer cycle ran past 30 steps
+    e = (rel_l2(_cpu(phi), phi_o), rel_l2(_cpu(psi), psi_o))
+    print(f"phi {e[0]:.2e} psi {e[1]:.2e} outer {info['outer_iters']} (oracle {info_o['outer_iters']})", flush=True)
+    assert max(e) <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
     P.close()
