@@ -58,7 +58,7 @@ def _gpu_problem(case, precision):
     return P, q
 
 
-@pytest.mark.parametrize("restart", [45, 60])
+@pytest.mark.parametrize("restart", [31, 45, 60])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_long_restart_step_matches_oracle(_case, restart, precision):
     from paper_2008_02205_amd import mlpg
