@@ -301,7 +301,8 @@ struct Problem {
     DevBuf<double> mr, rn2, fn2, tolv;
     // diffusion-synthetic acceleration of the outer iteration: C, Ms on the
     // pattern, 1/diag(C), and the diffusion solve's workspace
-    DevBuf<double> dsaC, dsaMs, dsa_dinv, dsa_r, dsa_x, dsa_t;
+    DevBuf<double> dsaC, dsaMs, dsa_dinv, dsa_r, dsa_x;
+    DevBuf<double> dsa_Z;   // [restart_outer][n] the outer iteration's preconditioned vectors
     Krylov dsa;
     // patch block-Jacobi preconditioner (mlpg_solve_opts.precond): patches of
     // the current positions, block inverses of the current operators
@@ -465,13 +466,25 @@ using OpCall = OpCallT<double>;
 template <class T>
 using OpFnT = int (*)(Problem &P, const OpCallT<T> &c, hipStream_t s, void *ctx);
 using OpFn = OpFnT<double>;
+// A variable right preconditioner (flexible GMRES): z_j = M_j^-1 v_j is
+// computed by `apply` before each operator application and kept in Z (slot j
+// at Z + j * zs, k slots); the iterate is updated with Z y, so the residual
+// stays that of the unpreconditioned system whatever M_j does.
+template <class T>
+struct FlexPrecT {
+    int (*apply)(Problem &P, const T *v, T *z, hipStream_t s, void *ctx) = nullptr;
+    void *ctx = nullptr;
+    T *Z = nullptr;
+    int64_t zs = 0;
+};
 template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged,
                   const double *tolv = nullptr, bool cheap_op = false,   // optional per-system relative tolerance (device [nb])
                   const PatchPrecT<T> *pp = nullptr,    // patch block-Jacobi instead of dinv (dinv must be null)
-                  bool graphs = false);                 // replay restart cycles from captured HIP graphs
+                  bool graphs = false,                  // replay restart cycles from captured HIP graphs
+                  const FlexPrecT<T> *fx = nullptr);    // flexible right preconditioner (unfused operator only)
 // out[m] = sum_i x[i][m]^2 for the nb systems of K's shape
 hipError_t batched_norm2(KrylovT<double> &K, const double *x, double *out, hipStream_t s);
 

@@ -961,10 +961,12 @@ template <class T>
 int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx, const T *dinv, const T *f, T *x,
                   int64_t n, int nb, double tol, int restart, int max_its, int lag, bool x_zero, hipStream_t s,
                   int64_t *its_sum, int64_t *sweeps, double *res_max, bool *converged, const double *tolv,
-                  bool cheap_op, const PatchPrecT<T> *pp, bool graphs)
+                  bool cheap_op, const PatchPrecT<T> *pp, bool graphs, const FlexPrecT<T> *fx)
 {
     MLPG_CHECK(nb >= 1 && nb <= kThreads, MLPG_ERR_ARG, "batched GMRES: system count must be in [1, 256]");
     MLPG_CHECK(!(pp && dinv), MLPG_ERR_ARG, "batched GMRES: one right preconditioner at a time");
+    MLPG_CHECK(!fx || (!pp && !dinv && !fused && fx->apply && fx->Z && fx->zs >= n * nb), MLPG_ERR_ARG,
+               "batched GMRES: a flexible preconditioner needs an unfused operator and no other preconditioner");
     MLPG_CHECK(restart >= 1 && restart <= kMaxRestart, MLPG_ERR_ARG, "GMRES restart must be in [1, 60]");
     MLPG_CHECK(K.V.p && K.n == n && K.nb == nb && K.k >= restart, MLPG_ERR_WORKSPACE,
                "batched GMRES: the solve workspace was laid out for another shape");
@@ -1043,7 +1045,13 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             OpCallT<T> c;
             c.dinv = dinv;
             c.gate = gate;
-            if (j == 0 || !fused) {
+            if (fx) {
+                // z_j = M_j^-1 v_j, kept for the update of x
+                T *zj = fx->Z + (int64_t)j * fx->zs;
+                int rcp = fx->apply(P, K.V.p + (int64_t)j * K.vs, zj, s, fx->ctx);
+                if (rcp) return rcp;
+                c.in = zj;
+            } else if (j == 0 || !fused) {
                 c.in = K.V.p + (int64_t)j * K.vs;
                 if (pp) {
                     // the operator's input is M^-1 v_j
@@ -1095,7 +1103,10 @@ int gmres_batched(Problem &P, KrylovT<T> &K, OpFnT<T> op, bool fused, void *ctx,
             lsq_kernel<64, KPL><<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
         else
             lsq_kernel<32, KP><<<small_blocks, kThreads, 0, s>>>(nb, k, K.H.p, K.g.p, K.jend.p, K.y.p);
-        if (pp) {
+        if (fx) {
+            // x += Z y (the preconditioned vectors themselves)
+            x_update_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, fx->Z, fx->zs, K.y.p, K.jend.p, nullptr, x);
+        } else if (pp) {
             // x += M^-1 (V y)
             vy_kernel<T><<<grid_of(cnt), kThreads, 0, s>>>(n, nb, jc, K.V.p, K.vs, K.y.p, K.jend.p, K.z.p);
             MLPG_HIP(launch_patch_apply<T>(*pp, nb, K.z.p, x, true, nullptr, s));
@@ -1189,10 +1200,10 @@ template struct KrylovT<float>;
 template int gmres_batched<double>(Problem &, KrylovT<double> &, OpFnT<double>, bool, void *, const double *,
                                    const double *, double *, int64_t, int, double, int, int, int, bool, hipStream_t,
                                    int64_t *, int64_t *, double *, bool *, const double *, bool,
-                                   const PatchPrecT<double> *, bool);
+                                   const PatchPrecT<double> *, bool, const FlexPrecT<double> *);
 template int gmres_batched<float>(Problem &, KrylovT<float> &, OpFnT<float>, bool, void *, const float *,
                                   const float *, float *, int64_t, int, double, int, int, int, bool, hipStream_t,
                                   int64_t *, int64_t *, double *, bool *, const double *, bool,
-                                  const PatchPrecT<float> *, bool);
+                                  const PatchPrecT<float> *, bool, const FlexPrecT<float> *);
 
 }  // namespace mlpg

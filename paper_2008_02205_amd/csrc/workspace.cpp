@@ -144,7 +144,7 @@ void layout_solve(Problem &P, Arena &A, const mlpg_solve_opts &o)
         P.dsa.carve(A, n, 1, kDsaRestart);
         A.take(P.dsa_r, n);
         A.take(P.dsa_x, n);
-        A.take(P.dsa_t, n);
+        A.take(P.dsa_Z, (size_t)o.restart_outer * n);
     }
     if (o.precond == MLPG_PRECOND_PATCH) {
         const size_t cnt = (size_t)P.nbsq * M;
