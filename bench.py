@@ -392,7 +392,6 @@ def other_workload(args):
     print(json.dumps(rec), flush=True)
 
 
-ASTEROID_MAX_INNER = 20000
 ASTEROID_RESTART = 60
 
 
@@ -439,9 +438,10 @@ def asteroid_workload(args):
         # on the graded points restarted GMRES(30) stalls near a relative residual of 0.5 on some
         # ordinates of the oblique polar level (with point Jacobi at twice the paper's spacing, with
         # the patch preconditioner too at its own); GMRES(60) with the patch preconditioner converges
-        # every ordinate, so these are this workload's defaults (the cap stays above the library's
-        # 3,000 steps for the other settings)
-        opts.max_inner = args.max_inner or ASTEROID_MAX_INNER
+        # every ordinate within the library's default cap of 3,000 steps, so these are this
+        # workload's defaults
+        if args.max_inner:
+            opts.max_inner = args.max_inner
         opts.restart_inner = args.restart or ASTEROID_RESTART
         if args.accel:
             opts.accel = mlpg.MLPG_ACCEL_DSA
