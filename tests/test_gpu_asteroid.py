@@ -145,3 +145,42 @@ def test_graded_asteroid_step_matches_oracle(precision):
     print(f"phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} ordinates {om_g.shape[0]}", flush=True)
     assert max(e) <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
     P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graded_asteroid_workload_settings_match_oracle(precision):
+    """The asteroid workload's solver settings (patch block-Jacobi inner preconditioner, GMRES(60)) on
+    the graded points at four times the paper's spacing (8,458 points, 44 refined ordinates, the
+    shell's cross section divided by four as in the ten-times case), against the oracle with the same
+    preconditioner and restart length."""
+    from paper_2008_02205_amd import mlpg
+    from paper_2008_02205_amd.problem import GpuProblem
+    coarsen = 4.0
+    base = W.asteroid(0.1)
+    a = dataclasses.replace(base, sigma_shell=base.sigma_shell / coarsen)
+    x, R, L = W.asteroid_graded_points(a, coarsen)
+    shells, st, ss = W.asteroid_materials(a)
+    a0 = W.asteroid_step_inv_c_dt(a)
+    print(f"[case] graded asteroid workload settings n={x.shape[0]} {precision}", flush=True)
+    om_o, w_o = oracle.refined_quadrature(0, 5, a.src, (0.0, 0.0), a.radius)
+    om_g, w_g = mlpg.mlpg_refined_quadrature(0, 5, a.src, (0.0, 0.0), a.radius)
+    g = oracle.geometry(x, R, a.lo, a.hi)
+    it = oracle.integrate(g, 1, n_mat=2, shells=shells)
+    tr = oracle.Transport(it, om_o, w_o, st, ss, a0, L, opts=oracle.SolveOpts(restart_in=60, precond="patch"))
+    psi_o, phi_o, info_o = tr.step(None, W.asteroid_source(a, x, om_o.shape[0]))
+    assert info_o["inner_res_max"] <= 1e-12
+    P = GpuProblem(x, R, a.lo, a.hi, shells=shells)
+    P.integrate(1)
+    P.assemble(om_g, w_g, list(st), list(ss), a0, torch.from_numpy(L).cuda(),
+               precision=mlpg.MLPG_FP64 if precision == "fp64" else mlpg.MLPG_MIXED)
+    q = torch.from_numpy(np.ascontiguousarray(W.asteroid_source(a, x, om_g.shape[0]))).cuda()
+    opts = mlpg.mlpg_default_opts()
+    opts.precond = mlpg.MLPG_PRECOND_PATCH
+    opts.restart_inner = 60
+    phi, pv, psi, info = P.step(q, None, opts)
+    assert info["converged"] == 1
+    e = (rel_l2(_cpu(phi), phi_o), rel_l2(_cpu(pv), tr.point_values(phi_o)), rel_l2(_cpu(psi), psi_o))
+    print(f"phi {e[0]:.2e} point {e[1]:.2e} psi {e[2]:.2e} steps {info['inner_iters']} (oracle "
+          f"{info_o['inner_iters']})", flush=True)
+    assert max(e) <= (FP64_TOL if precision == "fp64" else MIXED_TOL)
+    P.close()
