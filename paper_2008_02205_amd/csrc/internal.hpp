@@ -188,7 +188,7 @@ struct KrylovT {
     DevBuf<double> part;     // [nblk][2k+2][nb] block partial sums
     DevBuf<double> h1, h2;   // [2k+2][nb] reduced projections, pass-B coefficients
     DevBuf<double> H;        // [nb][k+1][k] rotated Hessenberg (upper triangular part used)
-    DevBuf<double> Ht;       // [nb][k+1][k] unrotated Hessenberg
+    DevBuf<double> Ht;       // [nb][k][k+1] unrotated Hessenberg, by columns
     DevBuf<double> cs, sn;   // [nb][k]
     DevBuf<double> g;        // [nb][k+1]
     DevBuf<double> y;        // [k][nb]

@@ -496,7 +496,10 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     const int grp = threadIdx.x / G, q = threadIdx.x % G;
     const int m = blockIdx.x * (kThreads / G) + grp;
     const int mc = m < nb ? m : 0;
+    // Ht is stored by columns ((k + 1) rows each), so that lane q's reads and
+    // writes of row q in one column are contiguous across the lanes
     double *Hm = Ht + (int64_t)mc * (k + 1) * k;
+    auto HT = [&](int r, int c) -> double & { return Hm[(int64_t)c * (k + 1) + r]; };
     // Every load of the kernel is issued here, before any of them is used:
     // the previous kernels wrote these values (partly from other dies), so
     // each dependent round trip would cost a full memory latency.
@@ -511,13 +514,13 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     }
     const double bp = correct ? betap[mc] : 0.0;
     // column j-1: corrected below (q < j), or read as corrected by kPre
-    const double hprev = (j >= 1 && q <= j && (mode == kAfterPre || q < j)) ? Hm[q * k + (j - 1)] : 0.0;
+    const double hprev = (j >= 1 && q <= j && (mode == kAfterPre || q < j)) ? HT(q, j - 1) : 0.0;
     const double csq = (correct && q < j - 1) ? cs[mc * k + q] : 0.0;
     const double snq = (correct && q < j - 1) ? sn[mc * k + q] : 0.0;
     // row q of Ht left of column j-1 (not written by this kernel), for t
     double hv[KPT];
 #pragma unroll
-    for (int p = 0; p < KPT; ++p) hv[p] = (!FINAL && q <= j && p + 1 >= q && p < j - 1) ? Hm[q * k + p] : 0.0;
+    for (int p = 0; p < KPT; ++p) hv[p] = (!FINAL && q <= j && p + 1 >= q && p < j - 1) ? HT(q, p) : 0.0;
     // the serial part's scalars (thread 0 of each system)
     double g_prev = 0.0, fn = 0.0, tl = tol0;
     int it0 = 0;
@@ -551,11 +554,11 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     if (act && correct) {
         if (q < j) {
             const double v = hprev + bp * a;
-            Hm[q * k + (j - 1)] = v;
+            HT(q, j - 1) = v;
             scol[grp][q] = v;
         } else if (q == j) {
             const double v = bp * rho;
-            Hm[j * k + (j - 1)] = v;
+            HT(j, j - 1) = v;
             scol[grp][q] = v;
         }
     }
@@ -629,8 +632,8 @@ __global__ __launch_bounds__(kThreads) void step_small_kernel(int mode, int nb, 
     const double vw = (c - ab) / rho;
     const double hjj = (vw - tj) / rho;
     const double sc = tj / rho + hjj;
-    if (q < j) Hm[q * k + j] = (b - t) / rho;
-    if (q == j) Hm[j * k + j] = hjj;
+    if (q < j) HT(q, j) = (b - t) / rho;
+    if (q == j) HT(j, j) = hjj;
     if (q < j) {
         coef[q * nb + m] = a;
         coef[(j + q) * nb + m] = b - sc * a;
