@@ -439,7 +439,7 @@ int mlpg_apply_patch_precond(mlpg_handle h, const double *X, double *Y, int64_t 
  * vacuum terms on the domain faces); sigma_a,g = sigma_t,g - sigma_s,g +
  * 1/(c dt), and sigma_t,i is point i's mass-weighted mean of sigma_t,g +
  * 1/(c dt).  C x = r is solved by GMRES(30) with point Jacobi to a relative
- * residual of 1e-8 (at most 2,000 steps).  The outer iteration is then
+ * residual of 1e-4 (at most 2,000 steps).  The outer iteration is then
  * flexible GMRES: it keeps every P^-1 v_j and updates Phi with them, so its
  * residual is that of the unaccelerated system whatever the accuracy of the
  * diffusion solve; the converged Phi is the same as without acceleration, and

@@ -244,7 +244,7 @@ int op_dsa(Problem &P, const OpCall &c, hipStream_t s, void *)
 // need not be exact nor the same linear map at every step: the outer
 // residual is that of the unaccelerated system, and its converged Phi is the
 // unaccelerated solution.
-constexpr double kDsaTol = 1e-8;
+constexpr double kDsaTol = 1e-4;
 constexpr int kDsaMaxIts = 2000;
 
 int dsa_apply(Problem &P, SolveCounters &c, const double *v, double *out, hipStream_t s)
